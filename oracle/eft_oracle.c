@@ -1,0 +1,1331 @@
+/*
+ * eft_oracle.c -- plain FP64 CPU reference of one time step of the fully
+ * Eulerian phase-field FSI method (Mao & Jaiman, arXiv 2402.10348).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle the HIP path is checked
+ * against.  Only the tests, the smoke check and the CPU-baseline leg of the
+ * bench load it.  It shares no code, header, table or helper with the HIP
+ * library; the two only see the same seeded inputs.
+ *
+ * Everything is written as the paper states it, element by element and
+ * quadrature point by quadrature point, without blocking or fusion:
+ *   - generalized-alpha in first-order form              Sec. 2.1.2, eqs. (3)-(7)
+ *   - phase interpolation of rho, mu, body force, stress Sec. 2.1.1
+ *   - stabilized Petrov-Galerkin momentum/mass form      eq. (PG_NS) and the tau_m, tau_c formula
+ *   - Newtonian stress                                   Sec. 2.2 (fluid stress)
+ *   - left Cauchy-Green stress mu_L (B - I)              Sec. 2.3.1
+ *   - elastic Jacobian dB/dv                             eq. (Bext) and Appendix B
+ *   - time-dependent mobility with L2 projection         eqs. (tdm-num) and the RMS formula, Appendix A
+ *   - Lagrange multiplier beta                           Sec. 2.2.1 (text after eq. Allen-Cahn)
+ *   - Allen-Cahn semi-discrete form with SUPG            eq. (PPV_AC) and tau_phi
+ *   - B transport with recovery term and SUPG            eq. (semiCGT) and tau_B
+ *   - partitioned NS -> phi -> B iteration, stop rule    Sec. 2.4 (eqs. LS_NS, LS_AC, LS_MC)
+ * Readings of silent or garbled points are marked READING in the comments.
+ *
+ * Parity pins: see tests/test_oracle_*.py.  Function "orc_band" (the grid-cell
+ * transport band) defines a restriction that the paper does not state; its
+ * definition is pinned by brute-force checks only.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ types */
+
+typedef struct {
+    int dim, n_nodes, n_elems;
+    const double *xyz;          /* [N][dim]                               */
+    const int *conn;            /* [E][dim+1], positive orientation       */
+    int grid[3];                /* structured cell counts (band grid)     */
+    int n_dir;
+    const int *dir_node;        /* [n_dir]                                */
+    const uint8_t *dir_mask;    /* bit k<dim: velocity k, bit dim: p      */
+    const double *dir_val;      /* [n_dir][dim+1]                         */
+    int n_phase;
+    const int *kind;            /* 0 fluid, 1 solid                       */
+    const int *transported;     /* 0 = background complement              */
+    const double *rho, *mu, *muL;
+    double g[3];
+    double dt, rho_inf, eps, eta, C_I, di_cut, nl_rtol;
+    int nl_max, nl_fixed;
+    double lin_rtol;
+    int restart, lin_maxit;
+    double band_flat;
+    int band_cell, band_halo;
+} orc_problem;
+
+typedef struct {
+    double *vp;      /* [N][dim+1] */
+    double *vdot;    /* [N][dim]   */
+    double *phi;     /* [n_ind][N] */
+    double *phidot;  /* [n_ind][N] */
+    double *B;       /* [n_s][N][nv] */
+    double *Bdot;    /* [n_s][N][nv] */
+} orc_state;
+
+typedef struct {
+    int nl_iters, converged, lin_iters_total, lin_failures;
+    int n_blocks;
+    double block_ratio[66];
+    double gamma[64], beta[64];
+} orc_step_info;
+
+/* ---------------------------------------------------------- small helpers */
+
+static int nvoigt(int dim) { return dim == 3 ? 6 : 3; }
+
+/* Voigt order [11,22,33,12,23,13] (3D) and [11,22,12] (2D), Sec. 2.5 remark */
+static void voigt_pair(int dim, int c, int *i, int *j)
+{
+    static const int p3[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {1, 2}, {0, 2}};
+    static const int p2[3][2] = {{0, 0}, {1, 1}, {0, 1}};
+    if (dim == 3) { *i = p3[c][0]; *j = p3[c][1]; }
+    else          { *i = p2[c][0]; *j = p2[c][1]; }
+}
+
+static void voigt_to_full(int dim, const double *v, double M[3][3])
+{
+    memset(M, 0, 9 * sizeof(double));
+    for (int c = 0; c < nvoigt(dim); ++c) {
+        int i, j;
+        voigt_pair(dim, c, &i, &j);
+        M[i][j] = v[c];
+        M[j][i] = v[c];
+    }
+}
+
+/* generalized-alpha constants, eq. for alpha, alpha_m, varsigma */
+typedef struct { double alpha, alpha_m, vs, dt, ct, kappa; } galpha;
+
+static galpha galpha_of(double rho_inf, double dt)
+{
+    galpha ga;
+    ga.alpha = 1.0 / (1.0 + rho_inf);
+    ga.alpha_m = 0.5 * (3.0 - rho_inf) / (1.0 + rho_inf);
+    ga.vs = 0.5 + ga.alpha_m - ga.alpha;
+    ga.dt = dt;
+    ga.ct = ga.alpha_m / (ga.vs * dt);              /* d(rate at n+alpha_m)/d(x^{n+1}) */
+    ga.kappa = ga.alpha * ga.vs * dt / ga.alpha_m;  /* factor of dB/dv in eq. (Bext)   */
+    return ga;
+}
+
+/* Value at n+alpha and rate at n+alpha_m of one dof, from x^n, xdot^n and the
+ * current iterate x^{n+1}.  The rate at n+1 follows from the update formula
+ * x^{n+1} = x^n + dt xdot^n + dt varsigma (xdot^{n+1} - xdot^n). */
+static void level_values(const galpha *ga, double xn, double xdn, double xnp1, double *xa, double *xdam)
+{
+    double xdnp1 = xdn + (xnp1 - xn - ga->dt * xdn) / (ga->vs * ga->dt);
+    *xdam = xdn + ga->alpha_m * (xdnp1 - xdn);
+    *xa = xn + ga->alpha * (xnp1 - xn);
+}
+
+static double rate_at_np1(const galpha *ga, double xn, double xdn, double xnp1)
+{
+    return xdn + (xnp1 - xn - ga->dt * xdn) / (ga->vs * ga->dt);
+}
+
+/* degree-2 simplex rules (READING: the paper names no rule).
+ * Triangle: 3 points at barycentric (2/3,1/6,1/6) and permutations.
+ * Tetrahedron: 4 points (a,b,b,b), a=(5+3 sqrt5)/20, b=(5-sqrt5)/20.
+ * 1D (segment, used by the projection pin): 2-point Gauss.
+ * Returns the number of points; w is the weight as a fraction of |e|. */
+static int quad_rule(int dim, double bary[4][4], double *w)
+{
+    memset(bary, 0, 16 * sizeof(double));
+    if (dim == 1) {
+        double s = 0.5 / sqrt(3.0);
+        bary[0][0] = 0.5 + s; bary[0][1] = 0.5 - s;
+        bary[1][0] = 0.5 - s; bary[1][1] = 0.5 + s;
+        *w = 0.5;
+        return 2;
+    }
+    if (dim == 2) {
+        for (int q = 0; q < 3; ++q)
+            for (int a = 0; a < 3; ++a) bary[q][a] = (a == q) ? 2.0 / 3.0 : 1.0 / 6.0;
+        *w = 1.0 / 3.0;
+        return 3;
+    }
+    double a = (5.0 + 3.0 * sqrt(5.0)) / 20.0, b = (5.0 - sqrt(5.0)) / 20.0;
+    for (int q = 0; q < 4; ++q)
+        for (int k = 0; k < 4; ++k) bary[q][k] = (k == q) ? a : b;
+    *w = 0.25;
+    return 4;
+}
+
+/* Geometry of a P1 simplex.  Jm[i][k] = dx_i/dxi_k on the unit right simplex,
+ * dN[a][i] = dN_a/dx_i, G = J^-T J^-1 (contravariant metric, READING: unit
+ * right simplex without correction).  Returns the measure |e|. */
+static double simplex_geometry(int dim, const double X[4][3], double dN[4][3], double G[3][3])
+{
+    double Jm[3][3] = {{0}}, Ji[3][3] = {{0}}, det;
+    for (int i = 0; i < dim; ++i)
+        for (int k = 0; k < dim; ++k) Jm[i][k] = X[k + 1][i] - X[0][i];
+    if (dim == 1) {
+        det = Jm[0][0];
+        Ji[0][0] = 1.0 / det;
+    } else if (dim == 2) {
+        det = Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0];
+        Ji[0][0] = Jm[1][1] / det;  Ji[0][1] = -Jm[0][1] / det;
+        Ji[1][0] = -Jm[1][0] / det; Ji[1][1] = Jm[0][0] / det;
+    } else {
+        det = Jm[0][0] * (Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1])
+            - Jm[0][1] * (Jm[1][0] * Jm[2][2] - Jm[1][2] * Jm[2][0])
+            + Jm[0][2] * (Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0]);
+        Ji[0][0] = (Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1]) / det;
+        Ji[0][1] = (Jm[0][2] * Jm[2][1] - Jm[0][1] * Jm[2][2]) / det;
+        Ji[0][2] = (Jm[0][1] * Jm[1][2] - Jm[0][2] * Jm[1][1]) / det;
+        Ji[1][0] = (Jm[1][2] * Jm[2][0] - Jm[1][0] * Jm[2][2]) / det;
+        Ji[1][1] = (Jm[0][0] * Jm[2][2] - Jm[0][2] * Jm[2][0]) / det;
+        Ji[1][2] = (Jm[0][2] * Jm[1][0] - Jm[0][0] * Jm[1][2]) / det;
+        Ji[2][0] = (Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0]) / det;
+        Ji[2][1] = (Jm[0][1] * Jm[2][0] - Jm[0][0] * Jm[2][1]) / det;
+        Ji[2][2] = (Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0]) / det;
+    }
+    /* Ji[k][i] = dxi_k/dx_i */
+    memset(dN, 0, 12 * sizeof(double));
+    for (int i = 0; i < dim; ++i) {
+        double s = 0.0;
+        for (int k = 0; k < dim; ++k) {
+            dN[k + 1][i] = Ji[k][i];
+            s += Ji[k][i];
+        }
+        dN[0][i] = -s;
+    }
+    memset(G, 0, 9 * sizeof(double));
+    for (int i = 0; i < dim; ++i)
+        for (int j = 0; j < dim; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < dim; ++k) s += Ji[k][i] * Ji[k][j];
+            G[i][j] = s;
+        }
+    double fact = dim == 1 ? 1.0 : (dim == 2 ? 2.0 : 6.0);
+    return fabs(det) / fact;
+}
+
+static void element_coords(const orc_problem *P, int e, int nodes[4], double X[4][3])
+{
+    int nn = P->dim + 1;
+    memset(X, 0, 12 * sizeof(double));
+    for (int a = 0; a < nn; ++a) {
+        nodes[a] = P->conn[(size_t)e * nn + a];
+        for (int i = 0; i < P->dim; ++i) X[a][i] = P->xyz[(size_t)nodes[a] * P->dim + i];
+    }
+}
+
+/* --------------------------------------------------- sparsity (node graph) */
+
+/* Node graph: column set of row p = nodes sharing an element with p
+ * (including p), sorted ascending.  Two calls: count, then fill. */
+int orc_graph_nnz(const orc_problem *P)
+{
+    int N = P->n_nodes, nn = P->dim + 1;
+    int cap = 64, *buf = malloc(sizeof(int) * cap), total = 0;
+    /* node -> element incidence */
+    int *cnt = calloc(N + 1, sizeof(int));
+    for (int e = 0; e < P->n_elems; ++e)
+        for (int a = 0; a < nn; ++a) cnt[P->conn[(size_t)e * nn + a] + 1]++;
+    for (int p = 0; p < N; ++p) cnt[p + 1] += cnt[p];
+    int *inc = malloc(sizeof(int) * (size_t)cnt[N]), *fill = calloc(N, sizeof(int));
+    for (int e = 0; e < P->n_elems; ++e)
+        for (int a = 0; a < nn; ++a) {
+            int p = P->conn[(size_t)e * nn + a];
+            inc[cnt[p] + fill[p]++] = e;
+        }
+    for (int p = 0; p < N; ++p) {
+        int m = 0;
+        for (int t = cnt[p]; t < cnt[p + 1]; ++t)
+            for (int a = 0; a < nn; ++a) {
+                int q = P->conn[(size_t)inc[t] * nn + a], dup = 0;
+                for (int s = 0; s < m; ++s) if (buf[s] == q) { dup = 1; break; }
+                if (!dup) {
+                    if (m == cap) { cap *= 2; buf = realloc(buf, sizeof(int) * cap); }
+                    buf[m++] = q;
+                }
+            }
+        total += m;
+    }
+    free(buf); free(cnt); free(inc); free(fill);
+    return total;
+}
+
+static int cmp_int(const void *a, const void *b)
+{
+    int x = *(const int *)a, y = *(const int *)b;
+    return (x > y) - (x < y);
+}
+
+void orc_graph(const orc_problem *P, int *rowptr, int *col)
+{
+    int N = P->n_nodes, nn = P->dim + 1;
+    int *cnt = calloc(N + 1, sizeof(int));
+    for (int e = 0; e < P->n_elems; ++e)
+        for (int a = 0; a < nn; ++a) cnt[P->conn[(size_t)e * nn + a] + 1]++;
+    for (int p = 0; p < N; ++p) cnt[p + 1] += cnt[p];
+    int *inc = malloc(sizeof(int) * (size_t)cnt[N]), *fill = calloc(N, sizeof(int));
+    for (int e = 0; e < P->n_elems; ++e)
+        for (int a = 0; a < nn; ++a) {
+            int p = P->conn[(size_t)e * nn + a];
+            inc[cnt[p] + fill[p]++] = e;
+        }
+    rowptr[0] = 0;
+    for (int p = 0; p < N; ++p) {
+        int m = rowptr[p];
+        for (int t = cnt[p]; t < cnt[p + 1]; ++t)
+            for (int a = 0; a < nn; ++a) {
+                int q = P->conn[(size_t)inc[t] * nn + a], dup = 0;
+                for (int s = rowptr[p]; s < m; ++s) if (col[s] == q) { dup = 1; break; }
+                if (!dup) col[m++] = q;
+            }
+        qsort(col + rowptr[p], m - rowptr[p], sizeof(int), cmp_int);
+        rowptr[p + 1] = m;
+    }
+    free(cnt); free(inc); free(fill);
+}
+
+static int find_col(const int *rowptr, const int *col, int r, int c)
+{
+    for (int k = rowptr[r]; k < rowptr[r + 1]; ++k)
+        if (col[k] == c) return k;
+    return -1;
+}
+
+/* ------------------------------------------------------- phase bookkeeping */
+
+static int count_indicators(const orc_problem *P)
+{
+    int n = 0;
+    for (int ph = 0; ph < P->n_phase; ++ph) n += P->transported[ph] ? 1 : 0;
+    return n;
+}
+
+static int count_solids(const orc_problem *P)
+{
+    int n = 0;
+    for (int ph = 0; ph < P->n_phase; ++ph) n += P->kind[ph] == 1 ? 1 : 0;
+    return n;
+}
+
+/* indicator index of phase ph (order of transported phases), -1 if background */
+static int indicator_of(const orc_problem *P, int ph)
+{
+    if (!P->transported[ph]) return -1;
+    int k = 0;
+    for (int q = 0; q < ph; ++q) k += P->transported[q] ? 1 : 0;
+    return k;
+}
+
+/* phase index of solid s */
+static int phase_of_solid(const orc_problem *P, int s)
+{
+    int k = 0;
+    for (int ph = 0; ph < P->n_phase; ++ph)
+        if (P->kind[ph] == 1) { if (k == s) return ph; ++k; }
+    return -1;
+}
+
+static double clamp01(double x) { return x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x); }
+
+/* Nodal phase fractions (Sec. 2.1.1, alpha = (1+phi)/2).
+ * READING: clamp to [0,1] at nodes; the one non-transported phase takes the
+ * complement max(0, 1 - sum of the others).  rho and mu are the phase-weighted
+ * sums of the dynamic properties (READING: mu, not nu). */
+static void nodal_properties(const orc_problem *P, const double *phi_a, double *afrac /*[n_phase][N]*/,
+                             double *rho, double *mu)
+{
+    int N = P->n_nodes;
+    for (int p = 0; p < N; ++p) {
+        double sum = 0.0;
+        int bg = -1;
+        for (int ph = 0; ph < P->n_phase; ++ph) {
+            int k = indicator_of(P, ph);
+            if (k < 0) { bg = ph; continue; }
+            double a = clamp01(0.5 * (1.0 + phi_a[(size_t)k * N + p]));
+            afrac[(size_t)ph * N + p] = a;
+            sum += a;
+        }
+        if (bg >= 0) afrac[(size_t)bg * N + p] = sum < 1.0 ? 1.0 - sum : 0.0;
+        double r = 0.0, m = 0.0;
+        for (int ph = 0; ph < P->n_phase; ++ph) {
+            r += afrac[(size_t)ph * N + p] * P->rho[ph];
+            m += afrac[(size_t)ph * N + p] * P->mu[ph];
+        }
+        rho[p] = r;
+        mu[p] = m;
+    }
+}
+
+/* ------------------------------------------------ momentum / mass element */
+
+/* One element of eq. (PG_NS) at time level n+alpha (pressure at n+1):
+ * residual re[a][dof] and tangent Ke[a][b][dof_a][dof_b] with respect to the
+ * iterate (v, p)^{n+1}.  dofs 0..dim-1 velocity, dim pressure.
+ *
+ * READINGS: R_m = rho(a + L v - g) + grad p (viscous divergence vanishes for
+ * P1; the divergence of the elastic stress is dropped).  R_c = div v.  The
+ * tangent freezes tau_m, tau_c, the SUPG weight v.grad N_a, rho, mu, phi and B
+ * except through dB/dv of eq. (Bext); Galerkin convection is linearized fully.
+ * The elastic tangent uses varsigma (the appendix's gamma) and no stray
+ * derivative on B22. */
+static void ns_element(int dim, const galpha *ga, double C_I, const double g[3],
+                       const double X[4][3], const double v[4][3], const double (*vref)[3],
+                       const double acc[4][3],
+                       const double p[4], const double rho[4], const double mu[4],
+                       int n_s, const double *as /*[n_s][4]*/, const double *Bv /*[n_s][4][6]*/,
+                       const double *muL /*[n_s]*/,
+                       double re[4][4], double Ke[4][4][4][4])
+{
+    /* vref: linearization point of the frozen quantities (tau_m, tau_c and the
+     * SUPG weight); NULL means the iterate itself.  Only the finite-difference
+     * pins pass a separate point. */
+    if (!vref) vref = v;
+    int nn = dim + 1, nv = nvoigt(dim);
+    double dN[4][3], G[3][3], bary[4][4], wf;
+    double vol = simplex_geometry(dim, X, dN, G);
+    int nq = quad_rule(dim, bary, &wf);
+    double GG = 0.0, trG = 0.0;
+    for (int i = 0; i < dim; ++i) {
+        trG += G[i][i];
+        for (int j = 0; j < dim; ++j) GG += G[i][j] * G[i][j];
+    }
+    double L[3][3] = {{0}}, gp[3] = {0};
+    for (int i = 0; i < dim; ++i)
+        for (int j = 0; j < dim; ++j)
+            for (int b = 0; b < nn; ++b) L[i][j] += v[b][i] * dN[b][j];
+    for (int j = 0; j < dim; ++j)
+        for (int b = 0; b < nn; ++b) gp[j] += p[b] * dN[b][j];
+    double divv = 0.0;
+    for (int i = 0; i < dim; ++i) divv += L[i][i];
+
+    memset(re, 0, 16 * sizeof(double));
+    memset(Ke, 0, 256 * sizeof(double));
+
+    for (int q = 0; q < nq; ++q) {
+        const double *N = bary[q];
+        double w = vol * wf;
+        double rq = 0.0, mq = 0.0, pq = 0.0, vq[3] = {0}, wq[3] = {0}, aq[3] = {0};
+        for (int b = 0; b < nn; ++b) {
+            rq += N[b] * rho[b];
+            mq += N[b] * mu[b];
+            pq += N[b] * p[b];
+            for (int i = 0; i < dim; ++i) {
+                vq[i] += N[b] * v[b][i];
+                wq[i] += N[b] * vref[b][i];
+                aq[i] += N[b] * acc[b][i];
+            }
+        }
+        double Lv[3] = {0}, vGv = 0.0;
+        for (int i = 0; i < dim; ++i)
+            for (int j = 0; j < dim; ++j) {
+                Lv[i] += L[i][j] * vq[j];
+                vGv += wq[i] * G[i][j] * wq[j];
+            }
+        double Rm[3];
+        for (int i = 0; i < dim; ++i) Rm[i] = rq * (aq[i] + Lv[i] - g[i]) + gp[i];
+        double nu = mq / rq;
+        double tau_m = 1.0 / sqrt(4.0 / (ga->dt * ga->dt) + vGv + C_I * nu * nu * GG);
+        double tau_c = 1.0 / (trG * tau_m);
+
+        /* stress at the point: -p I + mu (L + L^T) + sum_s alpha_s muL_s (B_s - I) */
+        double sig[3][3];
+        for (int i = 0; i < dim; ++i)
+            for (int j = 0; j < dim; ++j) sig[i][j] = (i == j ? -pq : 0.0) + mq * (L[i][j] + L[j][i]);
+        double Bq[64][3][3], dB[64][3][3][3], aS[64];
+        for (int s = 0; s < n_s; ++s) {
+            double a_s = 0.0, bq[6] = {0};
+            for (int b = 0; b < nn; ++b) {
+                a_s += N[b] * as[s * 4 + b];
+                for (int c = 0; c < nv; ++c) bq[c] += N[b] * Bv[(s * 4 + b) * 6 + c];
+            }
+            aS[s] = a_s;
+            voigt_to_full(dim, bq, Bq[s]);
+            for (int k = 0; k < dim; ++k) {
+                double gk[6] = {0};
+                for (int b = 0; b < nn; ++b)
+                    for (int c = 0; c < nv; ++c) gk[c] += dN[b][k] * Bv[(s * 4 + b) * 6 + c];
+                voigt_to_full(dim, gk, dB[s][k]);
+            }
+            for (int i = 0; i < dim; ++i)
+                for (int j = 0; j < dim; ++j)
+                    sig[i][j] += a_s * muL[s] * (Bq[s][i][j] - (i == j ? 1.0 : 0.0));
+        }
+
+        double u[4];   /* SUPG weight v.grad N_a (frozen) */
+        for (int a = 0; a < nn; ++a) {
+            u[a] = 0.0;
+            for (int j = 0; j < dim; ++j) u[a] += wq[j] * dN[a][j];
+        }
+        /* residual */
+        for (int a = 0; a < nn; ++a) {
+            for (int i = 0; i < dim; ++i) {
+                double sd = 0.0;
+                for (int j = 0; j < dim; ++j) sd += sig[i][j] * dN[a][j];
+                re[a][i] += w * (N[a] * rq * (aq[i] + Lv[i] - g[i]) + sd
+                                 + tau_m * u[a] * Rm[i] + tau_c * rq * dN[a][i] * divv);
+            }
+            double gR = 0.0;
+            for (int j = 0; j < dim; ++j) gR += dN[a][j] * Rm[j];
+            re[a][dim] += w * (N[a] * divv + (tau_m / rq) * gR);
+        }
+        /* tangent */
+        double al = ga->alpha, ct = ga->ct;
+        for (int a = 0; a < nn; ++a)
+            for (int b = 0; b < nn; ++b) {
+                double gab = 0.0;
+                for (int j = 0; j < dim; ++j) gab += dN[a][j] * dN[b][j];
+                for (int i = 0; i < dim; ++i)
+                    for (int k = 0; k < dim; ++k) {
+                        double dik = (i == k) ? 1.0 : 0.0;
+                        double val = rq * (N[a] + tau_m * u[a]) * (ct * N[b] * dik + al * (dik * u[b] + L[i][k] * N[b]))
+                                   + al * mq * (dik * gab + dN[a][k] * dN[b][i])
+                                   + al * tau_c * rq * dN[a][i] * dN[b][k];
+                        for (int s = 0; s < n_s; ++s) {
+                            double c = al * ga->kappa * aS[s] * muL[s];
+                            double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+                            for (int j = 0; j < dim; ++j) t1 += dB[s][k][i][j] * dN[a][j];
+                            t1 *= -N[b];
+                            if (i == k)
+                                for (int j = 0; j < dim; ++j)
+                                    for (int l = 0; l < dim; ++l) t2 += dN[a][j] * Bq[s][j][l] * dN[b][l];
+                            for (int l = 0; l < dim; ++l) t3 += Bq[s][i][l] * dN[b][l];
+                            t3 *= dN[a][k];
+                            val += c * (t1 + t2 + t3);
+                        }
+                        Ke[a][b][i][k] += w * val;
+                    }
+                for (int i = 0; i < dim; ++i)
+                    Ke[a][b][i][dim] += w * (-dN[a][i] * N[b] + tau_m * u[a] * dN[b][i]);
+                for (int k = 0; k < dim; ++k) {
+                    double aL = 0.0;
+                    for (int j = 0; j < dim; ++j) aL += dN[a][j] * L[j][k];
+                    Ke[a][b][dim][k] += w * (al * N[a] * dN[b][k]
+                                             + tau_m * (dN[a][k] * (ct * N[b] + al * u[b]) + al * aL * N[b]));
+                }
+                Ke[a][b][dim][dim] += w * (tau_m / rq) * gab;
+            }
+    }
+}
+
+/* Nodal n+alpha values and n+alpha_m rates of every field from the level-n
+ * state and the iterate. */
+typedef struct {
+    double *v_a, *acc, *p;     /* [N][dim], [N][dim], [N] */
+    double *phi_a, *phid_am;   /* [n_ind][N]              */
+    double *B_a, *Bd_am;       /* [n_s][N][nv]            */
+} level_fields;
+
+static void level_fields_alloc(const orc_problem *P, level_fields *F)
+{
+    size_t N = P->n_nodes, d = P->dim, ni = count_indicators(P), ns = count_solids(P), nv = nvoigt(P->dim);
+    F->v_a = malloc(sizeof(double) * N * d);
+    F->acc = malloc(sizeof(double) * N * d);
+    F->p = malloc(sizeof(double) * N);
+    F->phi_a = malloc(sizeof(double) * (N * ni + 1));
+    F->phid_am = malloc(sizeof(double) * (N * ni + 1));
+    F->B_a = malloc(sizeof(double) * (N * ns * nv + 1));
+    F->Bd_am = malloc(sizeof(double) * (N * ns * nv + 1));
+}
+
+static void level_fields_free(level_fields *F)
+{
+    free(F->v_a); free(F->acc); free(F->p); free(F->phi_a); free(F->phid_am); free(F->B_a); free(F->Bd_am);
+}
+
+static void level_fields_eval(const orc_problem *P, const galpha *ga, const orc_state *lvl,
+                              const double *it_vp, const double *it_phi, const double *it_B, level_fields *F)
+{
+    int N = P->n_nodes, d = P->dim, ni = count_indicators(P), ns = count_solids(P), nv = nvoigt(d);
+    for (int p = 0; p < N; ++p) {
+        for (int i = 0; i < d; ++i)
+            level_values(ga, lvl->vp[(size_t)p * (d + 1) + i], lvl->vdot[(size_t)p * d + i],
+                         it_vp[(size_t)p * (d + 1) + i], &F->v_a[(size_t)p * d + i], &F->acc[(size_t)p * d + i]);
+        F->p[p] = it_vp[(size_t)p * (d + 1) + d];   /* pressure at n+1 */
+    }
+    for (size_t t = 0; t < (size_t)ni * N; ++t)
+        level_values(ga, lvl->phi[t], lvl->phidot[t], it_phi[t], &F->phi_a[t], &F->phid_am[t]);
+    for (size_t t = 0; t < (size_t)ns * N * nv; ++t)
+        level_values(ga, lvl->B[t], lvl->Bdot[t], it_B[t], &F->B_a[t], &F->Bd_am[t]);
+}
+
+/* Global residual R [N][dim+1] and BSR Jacobian Jval [nnz][(dim+1)^2]
+ * (row-major blocks) of the momentum/mass system, before boundary rows. */
+void orc_ns_assemble(const orc_problem *P, const orc_state *lvl, const double *it_vp, const double *it_phi,
+                     const double *it_B, const int *rowptr, const int *col, double *R, double *Jval)
+{
+    int N = P->n_nodes, d = P->dim, nn = d + 1, bs = d + 1, ns = count_solids(P), nv = nvoigt(d);
+    galpha ga = galpha_of(P->rho_inf, P->dt);
+    level_fields F;
+    level_fields_alloc(P, &F);
+    level_fields_eval(P, &ga, lvl, it_vp, it_phi, it_B, &F);
+    double *af = malloc(sizeof(double) * (size_t)P->n_phase * N), *rho = malloc(sizeof(double) * N),
+           *mu = malloc(sizeof(double) * N);
+    nodal_properties(P, F.phi_a, af, rho, mu);
+    double *muL = malloc(sizeof(double) * (ns + 1));
+    for (int s = 0; s < ns; ++s) muL[s] = P->muL[phase_of_solid(P, s)];
+
+    memset(R, 0, sizeof(double) * (size_t)N * bs);
+    memset(Jval, 0, sizeof(double) * (size_t)rowptr[N] * bs * bs);
+    double *as = malloc(sizeof(double) * 4 * (ns + 1)), *Bv = malloc(sizeof(double) * 24 * (ns + 1));
+    for (int e = 0; e < P->n_elems; ++e) {
+        int nodes[4];
+        double X[4][3], v[4][3] = {{0}}, acc[4][3] = {{0}}, p[4], r4[4], m4[4], re[4][4], Ke[4][4][4][4];
+        element_coords(P, e, nodes, X);
+        for (int a = 0; a < nn; ++a) {
+            int n = nodes[a];
+            for (int i = 0; i < d; ++i) {
+                v[a][i] = F.v_a[(size_t)n * d + i];
+                acc[a][i] = F.acc[(size_t)n * d + i];
+            }
+            p[a] = F.p[n];
+            r4[a] = rho[n];
+            m4[a] = mu[n];
+            for (int s = 0; s < ns; ++s) {
+                as[s * 4 + a] = af[(size_t)phase_of_solid(P, s) * N + n];
+                for (int c = 0; c < nv; ++c) Bv[(s * 4 + a) * 6 + c] = F.B_a[((size_t)s * N + n) * nv + c];
+            }
+        }
+        ns_element(d, &ga, P->C_I, P->g, X, v, NULL, acc, p, r4, m4, ns, as, Bv, muL, re, Ke);
+        for (int a = 0; a < nn; ++a) {
+            for (int i = 0; i < bs; ++i) R[(size_t)nodes[a] * bs + i] += re[a][i];
+            for (int b = 0; b < nn; ++b) {
+                int k = find_col(rowptr, col, nodes[a], nodes[b]);
+                for (int i = 0; i < bs; ++i)
+                    for (int j = 0; j < bs; ++j) Jval[((size_t)k * bs + i) * bs + j] += Ke[a][b][i][j];
+            }
+        }
+    }
+    free(as); free(Bv); free(af); free(rho); free(mu); free(muL);
+    level_fields_free(&F);
+}
+
+/* Dirichlet rows: residual 0, Jacobian row = unit row (the iterate already
+ * holds the boundary value). */
+void orc_ns_apply_bc(const orc_problem *P, const int *rowptr, const int *col, double *R, double *Jval)
+{
+    int bs = P->dim + 1;
+    for (int t = 0; t < P->n_dir; ++t) {
+        int n = P->dir_node[t];
+        for (int i = 0; i < bs; ++i) {
+            if (!((P->dir_mask[t] >> i) & 1)) continue;
+            R[(size_t)n * bs + i] = 0.0;
+            for (int k = rowptr[n]; k < rowptr[n + 1]; ++k)
+                for (int j = 0; j < bs; ++j)
+                    Jval[((size_t)k * bs + i) * bs + j] = (col[k] == n && j == i) ? 1.0 : 0.0;
+        }
+    }
+}
+
+/* ------------------------------------------------------- sparse algebra */
+
+void orc_spmv(int bs, int n, const int *rowptr, const int *col, const double *val, const double *x, double *y)
+{
+    for (int r = 0; r < n; ++r)
+        for (int i = 0; i < bs; ++i) {
+            double s = 0.0;
+            for (int k = rowptr[r]; k < rowptr[r + 1]; ++k)
+                for (int j = 0; j < bs; ++j) s += val[((size_t)k * bs + i) * bs + j] * x[(size_t)col[k] * bs + j];
+            y[(size_t)r * bs + i] = s;
+        }
+}
+
+static double dot(size_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (size_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* LU with partial pivoting of one bs x bs block (in place), piv[bs]. */
+static void block_lu(int bs, double *A, int *piv)
+{
+    for (int k = 0; k < bs; ++k) {
+        int pr = k;
+        for (int i = k + 1; i < bs; ++i) if (fabs(A[i * bs + k]) > fabs(A[pr * bs + k])) pr = i;
+        piv[k] = pr;
+        if (pr != k)
+            for (int j = 0; j < bs; ++j) { double t = A[k * bs + j]; A[k * bs + j] = A[pr * bs + j]; A[pr * bs + j] = t; }
+        for (int i = k + 1; i < bs; ++i) {
+            A[i * bs + k] /= A[k * bs + k];
+            for (int j = k + 1; j < bs; ++j) A[i * bs + j] -= A[i * bs + k] * A[k * bs + j];
+        }
+    }
+}
+
+static void block_lu_solve(int bs, const double *LU, const int *piv, double *x)
+{
+    for (int k = 0; k < bs; ++k)
+        if (piv[k] != k) { double t = x[k]; x[k] = x[piv[k]]; x[piv[k]] = t; }
+    for (int i = 0; i < bs; ++i)
+        for (int j = 0; j < i; ++j) x[i] -= LU[i * bs + j] * x[j];
+    for (int i = bs - 1; i >= 0; --i) {
+        for (int j = i + 1; j < bs; ++j) x[i] -= LU[i * bs + j] * x[j];
+        x[i] /= LU[i * bs + i];
+    }
+}
+
+/* Right-preconditioned FGMRES(m) with modified Gram-Schmidt and point-block
+ * Jacobi (LU of each diagonal node block).  x0 = 0.  Stops when the true
+ * residual satisfies ||b - A x|| <= rtol ||b||.  Returns 0 if converged. */
+int orc_fgmres(int bs, int n, const int *rowptr, const int *col, const double *val, const double *b, double *x,
+               int m, int maxit, double rtol, int *iters_out, double *relres_out)
+{
+    size_t nd = (size_t)n * bs;
+    double *LU = malloc(sizeof(double) * (size_t)n * bs * bs);
+    int *piv = malloc(sizeof(int) * (size_t)n * bs);
+    for (int r = 0; r < n; ++r) {
+        int k = find_col(rowptr, col, r, r);
+        memcpy(LU + (size_t)r * bs * bs, val + (size_t)k * bs * bs, sizeof(double) * bs * bs);
+        block_lu(bs, LU + (size_t)r * bs * bs, piv + (size_t)r * bs);
+    }
+    double *V = malloc(sizeof(double) * nd * (m + 1)), *Z = malloc(sizeof(double) * nd * m);
+    double *H = calloc((size_t)(m + 1) * m, sizeof(double)), *cs = malloc(sizeof(double) * m),
+           *sn = malloc(sizeof(double) * m), *gv = malloc(sizeof(double) * (m + 1)), *y = malloc(sizeof(double) * m);
+    double *r = malloc(sizeof(double) * nd);
+    memset(x, 0, sizeof(double) * nd);
+    double bnorm = sqrt(dot(nd, b, b));
+    int total = 0, status = 1;
+    double relres = 0.0;
+    if (bnorm == 0.0) {
+        status = 0;
+        goto done;
+    }
+    for (;;) {
+        orc_spmv(bs, n, rowptr, col, val, x, r);
+        for (size_t i = 0; i < nd; ++i) r[i] = b[i] - r[i];
+        double beta = sqrt(dot(nd, r, r));
+        relres = beta / bnorm;
+        if (beta <= rtol * bnorm) { status = 0; break; }
+        if (total >= maxit) break;
+        for (size_t i = 0; i < nd; ++i) V[i] = r[i] / beta;
+        memset(gv, 0, sizeof(double) * (m + 1));
+        gv[0] = beta;
+        int jj = 0;
+        for (int j = 0; j < m; ++j) {
+            double *zj = Z + (size_t)j * nd, *w = V + (size_t)(j + 1) * nd;
+            memcpy(zj, V + (size_t)j * nd, sizeof(double) * nd);
+            for (int rr = 0; rr < n; ++rr) block_lu_solve(bs, LU + (size_t)rr * bs * bs, piv + (size_t)rr * bs, zj + (size_t)rr * bs);
+            orc_spmv(bs, n, rowptr, col, val, zj, w);
+            for (int i = 0; i <= j; ++i) {
+                double h = dot(nd, w, V + (size_t)i * nd);
+                H[i * m + j] = h;
+                for (size_t t = 0; t < nd; ++t) w[t] -= h * V[(size_t)i * nd + t];
+            }
+            double hn = sqrt(dot(nd, w, w));
+            H[(j + 1) * m + j] = hn;
+            if (hn != 0.0)
+                for (size_t t = 0; t < nd; ++t) w[t] /= hn;
+            for (int i = 0; i < j; ++i) {
+                double a = H[i * m + j], c = H[(i + 1) * m + j];
+                H[i * m + j] = cs[i] * a + sn[i] * c;
+                H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+            }
+            double a = H[j * m + j], c = H[(j + 1) * m + j], den = sqrt(a * a + c * c);
+            cs[j] = den == 0.0 ? 1.0 : a / den;
+            sn[j] = den == 0.0 ? 0.0 : c / den;
+            H[j * m + j] = cs[j] * a + sn[j] * c;
+            H[(j + 1) * m + j] = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            ++total;
+            jj = j + 1;
+            if (fabs(gv[j + 1]) <= rtol * bnorm || total >= maxit || hn == 0.0) break;
+        }
+        for (int i = jj - 1; i >= 0; --i) {
+            double s = gv[i];
+            for (int k = i + 1; k < jj; ++k) s -= H[i * m + k] * y[k];
+            y[i] = s / H[i * m + i];
+        }
+        for (int i = 0; i < jj; ++i)
+            for (size_t t = 0; t < nd; ++t) x[t] += y[i] * Z[(size_t)i * nd + t];
+    }
+done:
+    if (iters_out) *iters_out = total;
+    if (relres_out) *relres_out = relres;
+    free(LU); free(piv); free(V); free(Z); free(H); free(cs); free(sn); free(gv); free(y); free(r);
+    return status;
+}
+
+/* ------------------------------------------------------- L2 projection */
+
+/* Appendix A / eq. (tdm-num): nodal value = sum_e int N_p f / sum_e int N_p,
+ * with f given at the quadrature points of the degree-2 rule (2-point Gauss
+ * on segments).  fq [E][nq].  out[p] = 0 where no element touches p. */
+void orc_l2_project(int dim, int n_nodes, int n_elems, const double *xyz, const int *conn,
+                    const double *fq, double *out)
+{
+    int nn = dim + 1;
+    double bary[4][4], wf;
+    int nq = quad_rule(dim, bary, &wf);
+    double *num = calloc(n_nodes, sizeof(double)), *den = calloc(n_nodes, sizeof(double));
+    for (int e = 0; e < n_elems; ++e) {
+        double X[4][3] = {{0}}, dN[4][3], G[3][3];
+        for (int a = 0; a < nn; ++a)
+            for (int i = 0; i < dim; ++i) X[a][i] = xyz[(size_t)conn[(size_t)e * nn + a] * dim + i];
+        double vol = simplex_geometry(dim, X, dN, G);
+        for (int q = 0; q < nq; ++q)
+            for (int a = 0; a < nn; ++a) {
+                int pn = conn[(size_t)e * nn + a];
+                num[pn] += vol * wf * bary[q][a] * fq[(size_t)e * nq + q];
+                den[pn] += vol * wf * bary[q][a];
+            }
+    }
+    for (int p = 0; p < n_nodes; ++p) out[p] = den[p] > 0.0 ? num[p] / den[p] : 0.0;
+    free(num); free(den);
+}
+
+/* ------------------------------------------------ time-dependent mobility */
+
+/* gamma = (1/eta) RMS over nodes with |phi_p| <= di_cut of the absolute L2
+ * projection of (grad phi)^T grad v (grad phi) / |grad phi|^2 (eq. tdm-num and
+ * the discrete mobility formula).  READING: the quotient is 0 where grad phi
+ * vanishes; gamma = 0 when no node lies in the diffuse region. */
+double orc_mobility(const orc_problem *P, const double *v_a /*[N][dim]*/, const double *phi_a /*[N]*/)
+{
+    int d = P->dim, nn = d + 1, N = P->n_nodes;
+    double bary[4][4], wf;
+    int nq = quad_rule(d, bary, &wf);
+    double *fq = malloc(sizeof(double) * (size_t)P->n_elems * nq), *Q = malloc(sizeof(double) * N);
+    for (int e = 0; e < P->n_elems; ++e) {
+        int nodes[4];
+        double X[4][3], dN[4][3], G[3][3];
+        element_coords(P, e, nodes, X);
+        simplex_geometry(d, X, dN, G);
+        double gphi[3] = {0}, L[3][3] = {{0}};
+        for (int a = 0; a < nn; ++a)
+            for (int j = 0; j < d; ++j) {
+                gphi[j] += phi_a[nodes[a]] * dN[a][j];
+                for (int i = 0; i < d; ++i) L[i][j] += v_a[(size_t)nodes[a] * d + i] * dN[a][j];
+            }
+        double g2 = 0.0, gLg = 0.0;
+        for (int i = 0; i < d; ++i) {
+            g2 += gphi[i] * gphi[i];
+            for (int j = 0; j < d; ++j) gLg += gphi[i] * L[i][j] * gphi[j];
+        }
+        double qe = g2 > 0.0 ? gLg / g2 : 0.0;
+        for (int q = 0; q < nq; ++q) fq[(size_t)e * nq + q] = qe;
+    }
+    orc_l2_project(d, N, P->n_elems, P->xyz, P->conn, fq, Q);
+    double sum = 0.0;
+    long cnt = 0;
+    for (int p = 0; p < N; ++p)
+        if (fabs(phi_a[p]) <= P->di_cut) {
+            sum += Q[p] * Q[p];
+            ++cnt;
+        }
+    free(fq); free(Q);
+    return cnt ? sqrt(sum / (double)cnt) / P->eta : 0.0;
+}
+
+/* ------------------------------------------------------------ the band */
+
+/* Grid-cell band of one indicator (READING: the paper uses grid cells only to
+ * initialize; restricting transport to them is this implementation's choice).
+ * Grid cell size = band_cell mesh cells per axis; an element lies in the grid
+ * cell of its centroid; a cell is seeded when one of its elements has a node
+ * with |phi^n| < 1 - band_flat; the band is the seeded cells dilated by
+ * band_halo cell layers (26-neighbourhood).  Band elements are the elements
+ * of band cells; a band node is "free" when no non-band element touches it.
+ * Outputs: band_elem [E] (0/1), free_node [N] (0/1). */
+void orc_band(const orc_problem *P, const double *phi_n, uint8_t *band_elem, uint8_t *free_node)
+{
+    int d = P->dim, nn = d + 1, N = P->n_nodes, E = P->n_elems;
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int i = 0; i < d; ++i) { lo[i] = 1e300; hi[i] = -1e300; }
+    for (int p = 0; p < N; ++p)
+        for (int i = 0; i < d; ++i) {
+            double x = P->xyz[(size_t)p * d + i];
+            if (x < lo[i]) lo[i] = x;
+            if (x > hi[i]) hi[i] = x;
+        }
+    int ng[3] = {1, 1, 1};
+    double hg[3] = {1, 1, 1};
+    for (int i = 0; i < d; ++i) {
+        ng[i] = (P->grid[i] + P->band_cell - 1) / P->band_cell;
+        hg[i] = P->band_cell * (hi[i] - lo[i]) / P->grid[i];
+    }
+    size_t ncell = (size_t)ng[0] * ng[1] * ng[2];
+    uint8_t *seed = calloc(ncell, 1), *active = calloc(ncell, 1);
+    int *cell_of = malloc(sizeof(int) * (size_t)E);
+    for (int e = 0; e < E; ++e) {
+        double c[3] = {0, 0, 0};
+        int iface = 0, ci[3] = {0, 0, 0};
+        for (int a = 0; a < nn; ++a) {
+            int pn = P->conn[(size_t)e * nn + a];
+            for (int i = 0; i < d; ++i) c[i] += P->xyz[(size_t)pn * d + i] / nn;
+            if (fabs(phi_n[pn]) < 1.0 - P->band_flat) iface = 1;
+        }
+        for (int i = 0; i < d; ++i) {
+            int k = (int)floor((c[i] - lo[i]) / hg[i]);
+            ci[i] = k < 0 ? 0 : (k >= ng[i] ? ng[i] - 1 : k);
+        }
+        cell_of[e] = ci[0] + ng[0] * (ci[1] + ng[1] * ci[2]);
+        if (iface) seed[cell_of[e]] = 1;
+    }
+    int H = P->band_halo;
+    for (int k = 0; k < ng[2]; ++k)
+        for (int j = 0; j < ng[1]; ++j)
+            for (int i = 0; i < ng[0]; ++i) {
+                if (!seed[i + ng[0] * (j + ng[1] * k)]) continue;
+                for (int dk = -H; dk <= H; ++dk)
+                    for (int dj = -H; dj <= H; ++dj)
+                        for (int di = -H; di <= H; ++di) {
+                            int ii = i + di, jj = j + dj, kk = k + dk;
+                            if (ii < 0 || jj < 0 || kk < 0 || ii >= ng[0] || jj >= ng[1] || kk >= ng[2]) continue;
+                            active[ii + ng[0] * (jj + ng[1] * kk)] = 1;
+                        }
+            }
+    uint8_t *in_band = calloc(N, 1), *touch_out = calloc(N, 1);
+    for (int e = 0; e < E; ++e) {
+        band_elem[e] = active[cell_of[e]];
+        for (int a = 0; a < nn; ++a) {
+            int pn = P->conn[(size_t)e * nn + a];
+            if (band_elem[e]) in_band[pn] = 1;
+            else touch_out[pn] = 1;
+        }
+    }
+    for (int p = 0; p < N; ++p) free_node[p] = in_band[p] && !touch_out[p];
+    free(seed); free(active); free(cell_of); free(in_band); free(touch_out);
+}
+
+/* ------------------------------------------------------------ Allen-Cahn */
+
+/* F'(phi) = phi^3 - phi, sqrt(F) = |phi^2 - 1|/2 with F = (phi^2-1)^2/4 */
+static double Fprime(double f) { return f * f * f - f; }
+static double sqrtF(double f) { return 0.5 * fabs(f * f - 1.0); }
+
+/* beta = int F'(phi) / int sqrt(F(phi)) (Sec. 2.2.1), integrals over the band
+ * elements with the degree-2 rule.  READING: beta = 0 if the denominator is 0. */
+double orc_beta(const orc_problem *P, const double *phi_a, const uint8_t *band_elem)
+{
+    int d = P->dim, nn = d + 1;
+    double bary[4][4], wf, num = 0.0, den = 0.0;
+    int nq = quad_rule(d, bary, &wf);
+    for (int e = 0; e < P->n_elems; ++e) {
+        if (band_elem && !band_elem[e]) continue;
+        int nodes[4];
+        double X[4][3], dN[4][3], G[3][3];
+        element_coords(P, e, nodes, X);
+        double vol = simplex_geometry(d, X, dN, G);
+        for (int q = 0; q < nq; ++q) {
+            double f = 0.0;
+            for (int a = 0; a < nn; ++a) f += bary[q][a] * phi_a[nodes[a]];
+            num += vol * wf * Fprime(f);
+            den += vol * wf * sqrtF(f);
+        }
+    }
+    return den > 0.0 ? num / den : 0.0;
+}
+
+/* One element of eq. (PPV_AC).  READINGS: k_hat = eps^2; s_hat and f_hat are
+ * the Newton linearization of F' - beta sqrt(F) (the positivity-preserving
+ * coefficients of the cited work are not available), so the Galerkin reaction
+ * is F'(phi) - beta sqrt(F(phi)) and s_hat = 3 phi^2 - 1 - beta phi sgn(phi^2-1);
+ * tau_phi carries gamma on its diffusion and reaction terms.  The tangent
+ * freezes gamma, beta and tau_phi. */
+static void ac_element(int dim, const galpha *ga, double eps, double gamma, double beta,
+                       const double X[4][3], const double v[4][3], const double phi[4], const double *phiref,
+                       const double phid[4], double re[4], double Ke[4][4])
+{
+    /* phiref: linearization point of the frozen tau_phi; NULL = phi itself */
+    if (!phiref) phiref = phi;
+    int nn = dim + 1;
+    double dN[4][3], G[3][3], bary[4][4], wf;
+    double vol = simplex_geometry(dim, X, dN, G);
+    int nq = quad_rule(dim, bary, &wf);
+    double GG = 0.0;
+    for (int i = 0; i < dim; ++i)
+        for (int j = 0; j < dim; ++j) GG += G[i][j] * G[i][j];
+    double gphi[3] = {0};
+    for (int a = 0; a < nn; ++a)
+        for (int j = 0; j < dim; ++j) gphi[j] += phi[a] * dN[a][j];
+    double k_hat = eps * eps;
+    memset(re, 0, 4 * sizeof(double));
+    memset(Ke, 0, 16 * sizeof(double));
+    for (int q = 0; q < nq; ++q) {
+        const double *N = bary[q];
+        double w = vol * wf, fq = 0.0, fr = 0.0, fdq = 0.0, vq[3] = {0};
+        for (int b = 0; b < nn; ++b) {
+            fq += N[b] * phi[b];
+            fr += N[b] * phiref[b];
+            fdq += N[b] * phid[b];
+            for (int i = 0; i < dim; ++i) vq[i] += N[b] * v[b][i];
+        }
+        double vg = 0.0, vGv = 0.0;
+        for (int i = 0; i < dim; ++i) {
+            vg += vq[i] * gphi[i];
+            for (int j = 0; j < dim; ++j) vGv += vq[i] * G[i][j] * vq[j];
+        }
+        double f2m1 = fq * fq - 1.0;
+        double sgn = (f2m1 > 0.0) - (f2m1 < 0.0);
+        double react = Fprime(fq) - beta * sqrtF(fq);
+        double s_hat = 3.0 * fq * fq - 1.0 - beta * fq * sgn;
+        double fr2m1 = fr * fr - 1.0;
+        double s_ref = 3.0 * fr * fr - 1.0 - beta * fr * ((fr2m1 > 0.0) - (fr2m1 < 0.0));
+        double Rphi = fdq + vg + gamma * react;
+        double tau = 1.0 / sqrt(4.0 / (ga->dt * ga->dt) + vGv + 9.0 * (gamma * k_hat) * (gamma * k_hat) * GG
+                                + (gamma * s_ref) * (gamma * s_ref));
+        double u[4];
+        for (int a = 0; a < nn; ++a) {
+            u[a] = 0.0;
+            for (int j = 0; j < dim; ++j) u[a] += vq[j] * dN[a][j];
+        }
+        for (int a = 0; a < nn; ++a) {
+            double gg = 0.0;
+            for (int j = 0; j < dim; ++j) gg += dN[a][j] * gphi[j];
+            re[a] += w * (N[a] * (fdq + vg) + gamma * (k_hat * gg + N[a] * react) + tau * u[a] * Rphi);
+            for (int b = 0; b < nn; ++b) {
+                double gab = 0.0;
+                for (int j = 0; j < dim; ++j) gab += dN[a][j] * dN[b][j];
+                double lin = ga->ct * N[b] + ga->alpha * u[b];
+                Ke[a][b] += w * (N[a] * lin + ga->alpha * gamma * (k_hat * gab + N[a] * s_hat * N[b])
+                                 + tau * u[a] * (lin + ga->alpha * gamma * s_hat * N[b]));
+            }
+        }
+    }
+}
+
+/* Allen-Cahn residual [N] and Jacobian [nnz] (1x1 blocks) of one indicator
+ * over the band elements; non-free rows become unit rows with residual 0. */
+void orc_ac_assemble(const orc_problem *P, const double *v_a, const double *phi_a, const double *phid_am,
+                     double gamma, double beta, const uint8_t *band_elem, const uint8_t *free_node,
+                     const int *rowptr, const int *col, double *R, double *Jval)
+{
+    int d = P->dim, nn = d + 1, N = P->n_nodes;
+    galpha ga = galpha_of(P->rho_inf, P->dt);
+    memset(R, 0, sizeof(double) * N);
+    memset(Jval, 0, sizeof(double) * rowptr[N]);
+    for (int e = 0; e < P->n_elems; ++e) {
+        if (!band_elem[e]) continue;
+        int nodes[4];
+        double X[4][3], v[4][3] = {{0}}, f[4], fd[4], re[4], Ke[4][4];
+        element_coords(P, e, nodes, X);
+        for (int a = 0; a < nn; ++a) {
+            for (int i = 0; i < d; ++i) v[a][i] = v_a[(size_t)nodes[a] * d + i];
+            f[a] = phi_a[nodes[a]];
+            fd[a] = phid_am[nodes[a]];
+        }
+        ac_element(d, &ga, P->eps, gamma, beta, X, v, f, NULL, fd, re, Ke);
+        for (int a = 0; a < nn; ++a) {
+            R[nodes[a]] += re[a];
+            for (int b = 0; b < nn; ++b) Jval[find_col(rowptr, col, nodes[a], nodes[b])] += Ke[a][b];
+        }
+    }
+    for (int p = 0; p < N; ++p) {
+        if (free_node[p]) continue;
+        R[p] = 0.0;
+        for (int k = rowptr[p]; k < rowptr[p + 1]; ++k) Jval[k] = col[k] == p ? 1.0 : 0.0;
+    }
+}
+
+/* ---------------------------------------------------- left Cauchy-Green B */
+
+/* One element of eq. (semiCGT) for one solid, unknowns in Voigt order.
+ * T = Bdot + (v.grad)B - L B - B L^T,  R_B = alpha T + (1 - alpha)(B - I),
+ * residual row (ij) = int (N_a + tau_B v.grad N_a) R_B,ij.
+ * READINGS: alpha is evaluated pointwise (interpolated nodal fraction) and
+ * tau_B = ((2/dt)^2 + v.Gv)^(-1/2).  R_B is linear in B so the tangent is exact. */
+static void b_element(int dim, const galpha *ga, const double X[4][3], const double v[4][3], const double afr[4],
+                      const double *Bv /*[4][nv]*/, const double *Bd /*[4][nv]*/, double re[4][6],
+                      double Ke[4][4][6][6])
+{
+    int nn = dim + 1, nv = nvoigt(dim);
+    double dN[4][3], G[3][3], bary[4][4], wf;
+    double vol = simplex_geometry(dim, X, dN, G);
+    int nq = quad_rule(dim, bary, &wf);
+    double L[3][3] = {{0}};
+    for (int i = 0; i < dim; ++i)
+        for (int j = 0; j < dim; ++j)
+            for (int b = 0; b < nn; ++b) L[i][j] += v[b][i] * dN[b][j];
+    double dB[3][3][3];
+    for (int k = 0; k < dim; ++k) {
+        double gk[6] = {0};
+        for (int b = 0; b < nn; ++b)
+            for (int c = 0; c < nv; ++c) gk[c] += dN[b][k] * Bv[b * nv + c];
+        voigt_to_full(dim, gk, dB[k]);
+    }
+    memset(re, 0, 24 * sizeof(double));
+    memset(Ke, 0, 576 * sizeof(double));
+    /* L E + E L^T for each symmetric unit direction E of Voigt component c */
+    double LE[6][3][3];
+    for (int c = 0; c < nv; ++c) {
+        double E[3][3] = {{0}};
+        int k, l;
+        voigt_pair(dim, c, &k, &l);
+        E[k][l] = 1.0;
+        E[l][k] = 1.0;
+        for (int i = 0; i < dim; ++i)
+            for (int j = 0; j < dim; ++j) {
+                double s = 0.0;
+                for (int m = 0; m < dim; ++m) s += L[i][m] * E[m][j] + E[i][m] * L[j][m];
+                LE[c][i][j] = s;
+            }
+    }
+    for (int q = 0; q < nq; ++q) {
+        const double *N = bary[q];
+        double w = vol * wf, vq[3] = {0}, aq = 0.0, bq[6] = {0}, bdq[6] = {0};
+        for (int b = 0; b < nn; ++b) {
+            aq += N[b] * afr[b];
+            for (int i = 0; i < dim; ++i) vq[i] += N[b] * v[b][i];
+            for (int c = 0; c < nv; ++c) {
+                bq[c] += N[b] * Bv[b * nv + c];
+                bdq[c] += N[b] * Bd[b * nv + c];
+            }
+        }
+        double Bq[3][3], Bdq[3][3];
+        voigt_to_full(dim, bq, Bq);
+        voigt_to_full(dim, bdq, Bdq);
+        double vGv = 0.0;
+        for (int i = 0; i < dim; ++i)
+            for (int j = 0; j < dim; ++j) vGv += vq[i] * G[i][j] * vq[j];
+        double tau = 1.0 / sqrt(4.0 / (ga->dt * ga->dt) + vGv);
+        double RB[3][3];
+        for (int i = 0; i < dim; ++i)
+            for (int j = 0; j < dim; ++j) {
+                double conv = 0.0, LB = 0.0, BL = 0.0;
+                for (int k = 0; k < dim; ++k) {
+                    conv += vq[k] * dB[k][i][j];
+                    LB += L[i][k] * Bq[k][j];
+                    BL += Bq[i][k] * L[j][k];
+                }
+                double T = Bdq[i][j] + conv - LB - BL;
+                RB[i][j] = aq * T + (1.0 - aq) * (Bq[i][j] - (i == j ? 1.0 : 0.0));
+            }
+        double u[4];
+        for (int a = 0; a < nn; ++a) {
+            u[a] = 0.0;
+            for (int j = 0; j < dim; ++j) u[a] += vq[j] * dN[a][j];
+        }
+        for (int a = 0; a < nn; ++a) {
+            double wa = w * (N[a] + tau * u[a]);
+            for (int c = 0; c < nv; ++c) {
+                int i, j;
+                voigt_pair(dim, c, &i, &j);
+                re[a][c] += wa * RB[i][j];
+            }
+            for (int b = 0; b < nn; ++b) {
+                double diag = aq * (ga->ct * N[b] + ga->alpha * u[b]) + (1.0 - aq) * ga->alpha * N[b];
+                for (int c = 0; c < nv; ++c) {
+                    int i, j;
+                    voigt_pair(dim, c, &i, &j);
+                    for (int cc = 0; cc < nv; ++cc) {
+                        double val = (c == cc ? diag : 0.0) - aq * ga->alpha * N[b] * LE[cc][i][j];
+                        Ke[a][b][c][cc] += wa * val;
+                    }
+                }
+            }
+        }
+    }
+}
+
+/* B residual [N][nv] and BSR Jacobian [nnz][nv*nv] of one solid over the band
+ * elements of its indicator; non-free rows become unit rows, residual 0. */
+void orc_b_assemble(const orc_problem *P, const double *v_a, const double *afrac /*[N]*/, const double *B_a,
+                    const double *Bd_am, const uint8_t *band_elem, const uint8_t *free_node,
+                    const int *rowptr, const int *col, double *R, double *Jval)
+{
+    int d = P->dim, nn = d + 1, N = P->n_nodes, nv = nvoigt(d);
+    galpha ga = galpha_of(P->rho_inf, P->dt);
+    memset(R, 0, sizeof(double) * (size_t)N * nv);
+    memset(Jval, 0, sizeof(double) * (size_t)rowptr[N] * nv * nv);
+    for (int e = 0; e < P->n_elems; ++e) {
+        if (!band_elem[e]) continue;
+        int nodes[4];
+        double X[4][3], v[4][3] = {{0}}, af[4], Bv[24], Bd[24], re[4][6], Ke[4][4][6][6];
+        element_coords(P, e, nodes, X);
+        for (int a = 0; a < nn; ++a) {
+            for (int i = 0; i < d; ++i) v[a][i] = v_a[(size_t)nodes[a] * d + i];
+            af[a] = afrac[nodes[a]];
+            for (int c = 0; c < nv; ++c) {
+                Bv[a * nv + c] = B_a[(size_t)nodes[a] * nv + c];
+                Bd[a * nv + c] = Bd_am[(size_t)nodes[a] * nv + c];
+            }
+        }
+        b_element(d, &ga, X, v, af, Bv, Bd, re, Ke);
+        for (int a = 0; a < nn; ++a) {
+            for (int c = 0; c < nv; ++c) R[(size_t)nodes[a] * nv + c] += re[a][c];
+            for (int b = 0; b < nn; ++b) {
+                int k = find_col(rowptr, col, nodes[a], nodes[b]);
+                for (int c = 0; c < nv; ++c)
+                    for (int cc = 0; cc < nv; ++cc) Jval[((size_t)k * nv + c) * nv + cc] += Ke[a][b][c][cc];
+            }
+        }
+    }
+    for (int p = 0; p < N; ++p) {
+        if (free_node[p]) continue;
+        for (int c = 0; c < nv; ++c) {
+            R[(size_t)p * nv + c] = 0.0;
+            for (int k = rowptr[p]; k < rowptr[p + 1]; ++k)
+                for (int cc = 0; cc < nv; ++cc)
+                    Jval[((size_t)k * nv + c) * nv + cc] = (col[k] == p && c == cc) ? 1.0 : 0.0;
+        }
+    }
+}
+
+/* --------------------------------------------------------- one time step */
+
+static double norm2(size_t n, const double *a) { return sqrt(dot(n, a, a)); }
+
+/* One time step (Sec. 2.4): predictor x^{n+1} = x^n with boundary values;
+ * bands from phi^n; nonlinear iterations NS -> every indicator (gamma, beta,
+ * one Allen-Cahn solve) -> every solid (one B solve with the new phi); stop when
+ * every block's ||dx||/||x|| < nl_rtol or after nl_max iterations (exactly
+ * nl_fixed iterations when nl_fixed > 0); corrector stores the rates at n+1.
+ * READING: one linear solve per block per iteration, gamma and beta lagged,
+ * block norms are vector 2-norms with [v,p] as one block.
+ * The state is advanced in place.  Returns 0, or 1 if a linear solve failed. */
+int orc_step(const orc_problem *P, orc_state *S, orc_step_info *info)
+{
+    int N = P->n_nodes, d = P->dim, bs = d + 1, ni = count_indicators(P), ns = count_solids(P), nv = nvoigt(d);
+    galpha ga = galpha_of(P->rho_inf, P->dt);
+    size_t nvp = (size_t)N * bs, nphi = (size_t)N * ni, nB = (size_t)N * ns * nv;
+    orc_state lvl;
+    lvl.vp = malloc(sizeof(double) * nvp); memcpy(lvl.vp, S->vp, sizeof(double) * nvp);
+    lvl.vdot = malloc(sizeof(double) * N * d); memcpy(lvl.vdot, S->vdot, sizeof(double) * N * d);
+    lvl.phi = malloc(sizeof(double) * (nphi + 1)); memcpy(lvl.phi, S->phi, sizeof(double) * nphi);
+    lvl.phidot = malloc(sizeof(double) * (nphi + 1)); memcpy(lvl.phidot, S->phidot, sizeof(double) * nphi);
+    lvl.B = malloc(sizeof(double) * (nB + 1)); memcpy(lvl.B, S->B, sizeof(double) * nB);
+    lvl.Bdot = malloc(sizeof(double) * (nB + 1)); memcpy(lvl.Bdot, S->Bdot, sizeof(double) * nB);
+    /* predictor: the iterate lives in S->vp, S->phi, S->B */
+    for (int t = 0; t < P->n_dir; ++t)
+        for (int i = 0; i < bs; ++i)
+            if ((P->dir_mask[t] >> i) & 1) S->vp[(size_t)P->dir_node[t] * bs + i] = P->dir_val[(size_t)t * bs + i];
+
+    int nnz = orc_graph_nnz(P);
+    int *rowptr = malloc(sizeof(int) * (N + 1)), *col = malloc(sizeof(int) * nnz);
+    orc_graph(P, rowptr, col);
+    int maxbs = bs > nv ? bs : nv;
+    double *R = malloc(sizeof(double) * (size_t)N * maxbs), *J = malloc(sizeof(double) * (size_t)nnz * maxbs * maxbs);
+    double *dx = malloc(sizeof(double) * (size_t)N * maxbs);
+    uint8_t *band = malloc((size_t)P->n_elems * (ni + 1)), *fre = malloc((size_t)N * (ni + 1));
+    for (int k = 0; k < ni; ++k) orc_band(P, lvl.phi + (size_t)k * N, band + (size_t)k * P->n_elems, fre + (size_t)k * N);
+    level_fields F;
+    level_fields_alloc(P, &F);
+    double *af = malloc(sizeof(double) * (size_t)P->n_phase * N), *rho = malloc(sizeof(double) * N),
+           *mu = malloc(sizeof(double) * N);
+
+    int nblocks = 1 + ni + ns, status = 0, lin_total = 0, lin_fail = 0, converged = 0, it;
+    int nl_lim = P->nl_fixed > 0 ? P->nl_fixed : P->nl_max;
+    double ratio[66] = {0};
+    for (it = 1; it <= nl_lim; ++it) {
+        int li;
+        double rr;
+        /* momentum / mass block, eq. (LS_NS) */
+        orc_ns_assemble(P, &lvl, S->vp, S->phi, S->B, rowptr, col, R, J);
+        orc_ns_apply_bc(P, rowptr, col, R, J);
+        for (size_t t = 0; t < nvp; ++t) R[t] = -R[t];
+        if (orc_fgmres(bs, N, rowptr, col, J, R, dx, P->restart, P->lin_maxit, P->lin_rtol, &li, &rr)) { status = 1; ++lin_fail; }
+        lin_total += li;
+        for (size_t t = 0; t < nvp; ++t) S->vp[t] += dx[t];
+        ratio[0] = norm2(nvp, dx) / fmax(norm2(nvp, S->vp), 1e-300);
+        level_fields_eval(P, &ga, &lvl, S->vp, S->phi, S->B, &F);
+        /* order parameters, eq. (LS_AC) */
+        for (int k = 0; k < ni; ++k) {
+            const double *fa = F.phi_a + (size_t)k * N;
+            double gam = orc_mobility(P, F.v_a, fa);
+            double bet = orc_beta(P, fa, band + (size_t)k * P->n_elems);
+            info->gamma[k] = gam;
+            info->beta[k] = bet;
+            orc_ac_assemble(P, F.v_a, fa, F.phid_am + (size_t)k * N, gam, bet, band + (size_t)k * P->n_elems,
+                            fre + (size_t)k * N, rowptr, col, R, J);
+            for (int p = 0; p < N; ++p) R[p] = -R[p];
+            if (orc_fgmres(1, N, rowptr, col, J, R, dx, P->restart, P->lin_maxit, P->lin_rtol, &li, &rr)) { status = 1; ++lin_fail; }
+            lin_total += li;
+            for (int p = 0; p < N; ++p) S->phi[(size_t)k * N + p] += dx[p];
+            ratio[1 + k] = norm2(N, dx) / fmax(norm2(N, S->phi + (size_t)k * N), 1e-300);
+        }
+        /* left Cauchy-Green tensors, eq. (LS_MC), with the new phi */
+        level_fields_eval(P, &ga, &lvl, S->vp, S->phi, S->B, &F);
+        nodal_properties(P, F.phi_a, af, rho, mu);
+        for (int s = 0; s < ns; ++s) {
+            int ph = phase_of_solid(P, s), k = indicator_of(P, ph);
+            orc_b_assemble(P, F.v_a, af + (size_t)ph * N, F.B_a + (size_t)s * N * nv, F.Bd_am + (size_t)s * N * nv,
+                           band + (size_t)k * P->n_elems, fre + (size_t)k * N, rowptr, col, R, J);
+            for (size_t t = 0; t < (size_t)N * nv; ++t) R[t] = -R[t];
+            if (orc_fgmres(nv, N, rowptr, col, J, R, dx, P->restart, P->lin_maxit, P->lin_rtol, &li, &rr)) { status = 1; ++lin_fail; }
+            lin_total += li;
+            for (size_t t = 0; t < (size_t)N * nv; ++t) S->B[(size_t)s * N * nv + t] += dx[t];
+            ratio[1 + ni + s] = norm2((size_t)N * nv, dx) / fmax(norm2((size_t)N * nv, S->B + (size_t)s * N * nv), 1e-300);
+        }
+        if (P->nl_fixed <= 0) {
+            int ok = 1;
+            for (int b = 0; b < nblocks; ++b) ok &= ratio[b] < P->nl_rtol;
+            if (ok) { converged = 1; break; }
+        }
+    }
+    if (P->nl_fixed > 0) { converged = 1; it = P->nl_fixed; }
+    else if (!converged) it = P->nl_max;
+    /* corrector: rates at n+1 */
+    for (int p = 0; p < N; ++p)
+        for (int i = 0; i < d; ++i)
+            S->vdot[(size_t)p * d + i] = rate_at_np1(&ga, lvl.vp[(size_t)p * bs + i], lvl.vdot[(size_t)p * d + i],
+                                                     S->vp[(size_t)p * bs + i]);
+    for (size_t t = 0; t < nphi; ++t) S->phidot[t] = rate_at_np1(&ga, lvl.phi[t], lvl.phidot[t], S->phi[t]);
+    for (size_t t = 0; t < nB; ++t) S->Bdot[t] = rate_at_np1(&ga, lvl.B[t], lvl.Bdot[t], S->B[t]);
+
+    info->nl_iters = it;
+    info->converged = converged;
+    info->lin_iters_total = lin_total;
+    info->lin_failures = lin_fail;
+    info->n_blocks = nblocks;
+    for (int b = 0; b < nblocks && b < 66; ++b) info->block_ratio[b] = ratio[b];
+
+    level_fields_free(&F);
+    free(af); free(rho); free(mu);
+    free(lvl.vp); free(lvl.vdot); free(lvl.phi); free(lvl.phidot); free(lvl.B); free(lvl.Bdot);
+    free(rowptr); free(col); free(R); free(J); free(dx); free(band); free(fre);
+    return status;
+}
+
+/* ------------------------------------------------ exported element probes */
+
+/* Level values, nodal properties and element kernels exposed for the
+ * finite-difference and closed-form pins. */
+void orc_level_values(double rho_inf, double dt, int n, const double *xn, const double *xdn, const double *xnp1,
+                      double *xa, double *xdam)
+{
+    galpha ga = galpha_of(rho_inf, dt);
+    for (int i = 0; i < n; ++i) level_values(&ga, xn[i], xdn[i], xnp1[i], &xa[i], &xdam[i]);
+}
+
+void orc_galpha(double rho_inf, double dt, double *out /*[5]: alpha, alpha_m, varsigma, ct, kappa*/)
+{
+    galpha ga = galpha_of(rho_inf, dt);
+    out[0] = ga.alpha; out[1] = ga.alpha_m; out[2] = ga.vs; out[3] = ga.ct; out[4] = ga.kappa;
+}
+
+void orc_nodal_properties(const orc_problem *P, const double *phi_a, double *afrac, double *rho, double *mu)
+{
+    nodal_properties(P, phi_a, afrac, rho, mu);
+}
+
+void orc_ns_element(int dim, double rho_inf, double dt, double C_I, const double *g, const double *X,
+                    const double *v, const double *vref, const double *acc, const double *p, const double *rho, const double *mu,
+                    int n_s, const double *as, const double *Bv, const double *muL, double *re, double *Ke)
+{
+    galpha ga = galpha_of(rho_inf, dt);
+    ns_element(dim, &ga, C_I, g, (const double(*)[3])X, (const double(*)[3])v, (const double(*)[3])vref,
+               (const double(*)[3])acc, p, rho, mu,
+               n_s, as, Bv, muL, (double(*)[4])re, (double(*)[4][4][4])Ke);
+}
+
+void orc_ac_element(int dim, double rho_inf, double dt, double eps, double gamma, double beta, const double *X,
+                    const double *v, const double *phi, const double *phiref, const double *phid, double *re,
+                    double *Ke)
+{
+    galpha ga = galpha_of(rho_inf, dt);
+    ac_element(dim, &ga, eps, gamma, beta, (const double(*)[3])X, (const double(*)[3])v, phi, phiref, phid, re,
+               (double(*)[4])Ke);
+}
+
+void orc_b_element(int dim, double rho_inf, double dt, const double *X, const double *v, const double *afr,
+                   const double *Bv, const double *Bd, double *re, double *Ke)
+{
+    galpha ga = galpha_of(rho_inf, dt);
+    b_element(dim, &ga, (const double(*)[3])X, (const double(*)[3])v, afr, Bv, Bd, (double(*)[6])re,
+              (double(*)[4][6][6])Ke);
+}
+
+double orc_simplex_geometry(int dim, const double *X, double *dN, double *G)
+{
+    return simplex_geometry(dim, (const double(*)[3])X, (double(*)[3])dN, (double(*)[3])G);
+}
