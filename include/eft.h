@@ -1,0 +1,209 @@
+/*
+ * eft.h -- C ABI of the MI355X hot path of the fully Eulerian phase-field
+ * fluid-structure method of Mao & Jaiman (arXiv 2402.10348): one partitioned
+ * nonlinear iteration of a time step, i.e.
+ *   (a) assembly of the unified, phase-interpolated momentum/mass residual and
+ *       Jacobian (eq. PG_NS, tau_m/tau_c, Newtonian and left-Cauchy-Green
+ *       stress, elastic tangent of eq. Bext / Appendix B),
+ *   (b) the sparse Krylov solve of eq. LS_NS (BSR SpMV + FGMRES),
+ *   (c) the Allen-Cahn order-parameter transport of every indicator
+ *       (eqs. Allen-Cahn, tdm-num, PPV_AC) and the B-tensor transport of every
+ *       solid (eq. semiCGT), restricted to a grid-cell band around each
+ *       interface, with the stop rule of Sec. 2.4.
+ *
+ * Conventions
+ *   - Plain C types only.  Mesh, material and parameter arguments of
+ *     eft_create are HOST pointers and are copied.  Every field, vector and
+ *     matrix array argument of the other calls is a DEVICE pointer (HIP device
+ *     memory, FP64 unless stated) owned by the caller; the library never frees
+ *     caller memory.
+ *   - Dimension d is 2 (triangles) or 3 (tetrahedra).  Nodal blocks are
+ *     interleaved: vp is [N][d+1] = (v_0..v_{d-1}, p) per node.
+ *   - Symmetric tensors use the Voigt order [11,22,33,12,23,13] (d = 3) or
+ *     [11,22,12] (d = 2), Sec. 2.5 remark; nv = 6 or 3.
+ *   - All work is enqueued on the HIP stream given to eft_create; calls that
+ *     return host-visible results (info structs, status) synchronize it.
+ *   - A context is not thread-safe; one stream per context.
+ *   - The return code is the only error channel; eft_last_error gives text.
+ */
+#ifndef EFT_H
+#define EFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EFT_OK = 0,
+    EFT_EINVAL = 1,          /* bad argument (null, size, unsupported value)       */
+    EFT_ENOMEM = 2,          /* device or host allocation failed                   */
+    EFT_EDEVICE = 3,         /* a HIP call failed                                  */
+    EFT_ENOTCONV = 4,        /* Krylov solve hit its iteration cap (best iterate
+                                returned, info filled)                             */
+    EFT_EBREAKDOWN = 5,      /* Krylov breakdown on a singular system              */
+    EFT_ENAN = 6,            /* NaN/Inf met; fields keep the last good iterate     */
+    EFT_EBAND_OVERFLOW = 7,  /* max|v| dt exceeds the band halo width              */
+    EFT_EUNSUPPORTED = 8     /* valid request the library does not implement       */
+} eft_status;
+
+typedef struct eft_ctx eft_ctx;        /* opaque; owns every internal buffer */
+typedef struct eft_matrix eft_matrix;  /* opaque BSR matrix owned by a ctx   */
+
+/* Fixed Eulerian mesh of P1 simplices (Sec. 2.1.2), HOST arrays. */
+typedef struct {
+    int32_t dim;                 /* 2 or 3                                         */
+    int64_t n_nodes, n_elems;
+    const double *xyz;           /* [n_nodes][dim]                                 */
+    const int32_t *conn;         /* [n_elems][dim+1], positive orientation         */
+    int64_t n_dir;               /* Dirichlet nodes of the momentum/mass block     */
+    const int32_t *dir_node;     /* [n_dir]                                        */
+    const uint8_t *dir_mask;     /* [n_dir]: bit k<dim velocity k, bit dim pressure */
+    const double *dir_val;       /* [n_dir][dim+1] prescribed values               */
+    int32_t grid[3];             /* structured cell counts of the box (band grid)  */
+} eft_mesh;
+
+/* One phase (Sec. 2.1.1): fluid (Newtonian, Sec. 2.2) or Neo-Hookean solid
+ * (Sec. 2.3).  Exactly the transported phases carry an order parameter; at
+ * most one non-transported phase fills the complement. */
+typedef struct {
+    int32_t kind;                /* 0 fluid, 1 solid                               */
+    int32_t transported;         /* 1: own order parameter; 0: background          */
+    double rho, mu, mu_L;        /* density, dynamic viscosity, shear modulus      */
+} eft_phase;
+
+typedef struct {
+    int32_t n_phases;            /* <= 65 (at most 64 order parameters)            */
+    const eft_phase *phase;      /* HOST [n_phases]                                */
+    double g[3];                 /* gravity; body force rho g                      */
+} eft_materials;
+
+typedef struct {
+    double dt;                   /* time step                                      */
+    double rho_inf;              /* generalized-alpha spectral radius (paper: 0)   */
+    double eps;                  /* interface thickness parameter                  */
+    double eta;                  /* mobility regularization eta                    */
+    double C_I;                  /* inverse-estimate constant in tau_m             */
+    double di_cut;               /* diffuse-interface cut |phi| <= 0.9             */
+    double nl_rtol;              /* stop rule ||dx||/||x|| (paper: 5e-4)           */
+    int32_t nl_max;              /* nonlinear iteration cap (paper: 20)            */
+    int32_t nl_fixed;            /* >0: run exactly this many iterations           */
+    double lin_rtol;             /* FGMRES relative residual target                */
+    int32_t restart;             /* FGMRES restart length m (<= 512)               */
+    int32_t lin_maxit;           /* FGMRES iteration cap per solve                 */
+    int32_t precond;             /* 0 point-block Jacobi                           */
+    int32_t precision;           /* 0 FP64; 1 FP32 Jacobian values + FP64 rest     */
+    double band_flat;            /* band seed: |phi^n| < 1 - band_flat             */
+    int32_t band_cell;           /* mesh cells per grid cell and axis              */
+    int32_t band_halo;           /* grid-cell layers added around the seeds        */
+} eft_params;
+
+/* State at time level n (Sec. 2.1.2): values and rates.  DEVICE arrays. */
+typedef struct {
+    double *vp;                  /* [N][d+1]                                       */
+    double *vdot;                /* [N][d]                                         */
+    double *phi;                 /* [n_ind][N]                                     */
+    double *phidot;              /* [n_ind][N]                                     */
+    double *B;                   /* [n_s][N][nv]                                   */
+    double *Bdot;                /* [n_s][N][nv]                                   */
+    double t;
+    int64_t step;
+} eft_state;
+
+/* Current nonlinear iterate x^{n+1,(k)}.  DEVICE arrays, shapes as above. */
+typedef struct {
+    double *vp;
+    double *phi;
+    double *B;
+} eft_iterate;
+
+typedef struct {
+    int32_t iters;               /* Krylov iterations                              */
+    int32_t restarts;            /* completed restart cycles                       */
+    int32_t converged;           /* 1 if ||b - A x|| <= lin_rtol ||b||             */
+    int32_t fallback_used;       /* reserved (0)                                   */
+    double rel_res0;             /* ||b - A x0|| / ||b|| (x0 = 0: 1)               */
+    double rel_res;              /* final true relative residual                   */
+} eft_solve_info;
+
+typedef struct {
+    int32_t n_ind, n_solid;
+    double gamma[64];            /* mobility per indicator                         */
+    double beta[64];             /* Lagrange multiplier per indicator              */
+    int64_t band_nodes[64];      /* band size per indicator                        */
+    int64_t band_elems[64];
+    int32_t lin_iters[128];      /* per indicator, then per solid                  */
+    double ratio[128];           /* ||dx||/||x|| per indicator, then per solid     */
+} eft_transport_info;
+
+typedef struct {
+    int32_t nl_iters;            /* nonlinear iterations taken                     */
+    int32_t converged;           /* stop rule met (or nl_fixed reached)            */
+    int32_t lin_iters_total;     /* Krylov iterations over all blocks              */
+    int32_t n_blocks;            /* 1 + n_ind + n_s                                */
+    double block_ratio[129];     /* last ||dx||/||x|| per block: [v,p], phi_i, B_s */
+    double t_assemble, t_solve, t_transport;   /* seconds (host clock)            */
+} eft_step_info;
+
+/* Create a context: copies the mesh to the device, builds the node graph
+ * (BSR pattern of eq. LS_NS) and every workspace.  hip_stream may be NULL
+ * (default stream).  EFT_EINVAL on inconsistent sizes or orientation. */
+eft_status eft_create(const eft_mesh *mesh, const eft_materials *mat, const eft_params *par,
+                      void *hip_stream, eft_ctx **out);
+eft_status eft_destroy(eft_ctx *ctx);
+const char *eft_last_error(const eft_ctx *ctx);
+
+/* Replace the solver parameters (dt, tolerances, band definition ...). */
+eft_status eft_set_params(eft_ctx *ctx, const eft_params *par);
+
+/* The context-owned Jacobian of the momentum/mass block (bs = d+1). */
+eft_status eft_ns_matrix(eft_ctx *ctx, eft_matrix **out);
+eft_status eft_matrix_shape(const eft_matrix *A, int64_t *n_rows, int64_t *nnzb, int32_t *bs);
+/* Copy pattern and FP64 values (FP32 values are widened) into caller DEVICE
+ * buffers: rowptr [n_rows+1], col [nnzb], val [nnzb][bs][bs] row-major. */
+eft_status eft_matrix_export(eft_ctx *ctx, const eft_matrix *A, int32_t *rowptr, int32_t *col, double *val);
+
+/* (a) Momentum/mass residual R [N][d+1] (FP64) and Jacobian J of eq. (PG_NS)
+ * at the iterate, with the elastic tangent of eq. (Bext), Dirichlet rows
+ * replaced by unit rows and zero residual.  J may be NULL (residual only). */
+eft_status eft_assemble(eft_ctx *ctx, const eft_state *level_n, const eft_iterate *it, double *R,
+                        eft_matrix *J);
+
+/* (b) y = A x for a context matrix; x, y [n_rows][bs]. */
+eft_status eft_spmv(eft_ctx *ctx, const eft_matrix *A, const double *x, double *y);
+
+/* (b) Solve A x = b with right-preconditioned FGMRES(restart), x0 = 0,
+ * point-block Jacobi; classical Gram-Schmidt with reorthogonalization in FP64.
+ * x is output only.  EFT_ENOTCONV if lin_maxit is reached (x = best iterate). */
+eft_status eft_fgmres(eft_ctx *ctx, const eft_matrix *A, const double *b, double *x, eft_solve_info *info);
+
+/* (c) Build the transport band of every indicator from phi^n (grid cells of
+ * band_cell mesh cells seeded by |phi^n| < 1 - band_flat, dilated by band_halo
+ * layers; nodes touched by a non-band element keep their value). */
+eft_status eft_bands_build(eft_ctx *ctx, const eft_state *level_n);
+
+/* Export the band of indicator k: band_elem [E] and free_node [N] as 0/1
+ * bytes, DEVICE buffers (test hook). */
+eft_status eft_band_export(eft_ctx *ctx, int32_t k, uint8_t *band_elem, uint8_t *free_node);
+
+/* (c) One transport pass of the partitioned iteration (eqs. LS_AC, LS_MC):
+ * for every indicator the mobility gamma (eq. tdm-num, RMS over |phi| <= 0.9),
+ * beta, one Allen-Cahn solve on its band; then for every solid one B solve on
+ * the band of its indicator with the updated phi.  Updates it->phi and it->B
+ * in place.  Requires eft_bands_build for the current level. */
+eft_status eft_transport_solids(eft_ctx *ctx, const eft_state *level_n, eft_iterate *it,
+                                eft_transport_info *info);
+
+/* One time step (Sec. 2.4): predictor, bands, nonlinear iterations
+ * NS -> indicators -> solids until every block satisfies ||dx||/||x|| <
+ * nl_rtol or nl_max (exactly nl_fixed when > 0), corrector.  Advances *st in
+ * place (t += dt, step += 1).  A non-converged nonlinear loop still returns
+ * EFT_OK with info->converged = 0 (the paper continues after 20 iterations). */
+eft_status eft_step(eft_ctx *ctx, eft_state *st, double dt, eft_step_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EFT_H */

@@ -1,0 +1,182 @@
+// Internal declarations of the HIP library behind include/eft.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "eft.h"
+
+#define EFT_MAX_IND 64
+#define EFT_MAX_PHASE 65
+#define EFT_MAX_SOLID 64
+#define EFT_MAX_RESTART 512
+
+// ------------------------------------------------------------ matrices ----
+
+// BSR matrix with row-major bs x bs blocks.  Values live in val (FP64) or,
+// for the reduced-precision Jacobian, in val32 (FP32).
+struct eft_matrix {
+    int32_t bs = 0;
+    int64_t n = 0, nnzb = 0;
+    int32_t *rowptr = nullptr, *col = nullptr, *diag = nullptr;  // device
+    double *val = nullptr;
+    float *val32 = nullptr;
+    bool fp32 = false;
+};
+
+// FGMRES workspace for vectors of length nd = n*bs and restart m.
+struct KrylovWs {
+    int64_t cap_nd = 0;
+    int32_t cap_m = 0;
+    int64_t cap_n = 0;
+    int32_t cap_bs = 0;
+    double *V = nullptr;        // [m+1][nd]
+    double *Z = nullptr;        // [m][nd]
+    double *w = nullptr;        // [nd]
+    double *r = nullptr;        // [nd]
+    double *Dinv = nullptr;     // [n][bs*bs]
+    double *part = nullptr;     // reduction partials
+    double *small = nullptr;    // device scalars: H, cs, sn, g, y, h, norms
+    int32_t *flag = nullptr;    // [4]: active, j_done, breakdown, nan
+    int32_t nblk = 0;           // blocks of the reduction kernels
+};
+
+// Compact system on the band of one indicator.
+struct Band {
+    int64_t n = 0, ne = 0, nnz = 0;            // band nodes, band elements, pattern size
+    int64_t cap_n = 0, cap_ne = 0, cap_nnz = 0;
+    int32_t *node = nullptr;                   // [n] global id of band node
+    int32_t *elem = nullptr;                   // [ne] global id of band element
+    int32_t *epos = nullptr;                   // [ne][nn*nn] position in band pattern
+    int32_t *bconn_ = nullptr;                 // [ne][nn] band-local node ids
+    uint8_t *fre = nullptr;                    // [n] 1 if the node is solved for
+    int32_t *rowptr = nullptr, *col = nullptr, *diag = nullptr;
+    int64_t cap[8] = {0, 0, 0, 0, 0, 0, 0, 0}; // allocation sizes in bytes
+};
+
+struct eft_ctx {
+    hipStream_t stream = nullptr;
+    std::string err;
+    int dim = 0, nn = 0, bs = 0, nv = 0;
+    int64_t N = 0, E = 0;
+    // materials
+    int n_phase = 0, n_ind = 0, n_s = 0, bg = -1;
+    std::vector<eft_phase> phase;
+    std::vector<int> ind_phase;     // phase of indicator k
+    std::vector<int> solid_phase;   // phase of solid s
+    std::vector<int> solid_ind;     // indicator of solid s
+    double g[3] = {0, 0, 0};
+    eft_params par{};
+    // device mesh
+    double *xyz = nullptr;
+    int32_t *conn = nullptr;
+    int32_t *epos = nullptr;        // [E][nn*nn] position of (a,b) in the NS pattern
+    int32_t *cell_of = nullptr;     // [E] band grid cell of each element
+    int64_t n_dir = 0;
+    int32_t *dir_node = nullptr;
+    uint8_t *dir_mask = nullptr;
+    double *dir_val = nullptr;
+    double *phase_tab = nullptr;    // [5][EFT_MAX_PHASE]: kind, transported, rho, mu, mu_L
+    int32_t *ind_of_phase = nullptr;   // [n_phase] indicator index or -1
+    // band grid
+    int ng[3] = {1, 1, 1};
+    // momentum/mass matrix and node fields
+    eft_matrix J;
+    double *va = nullptr, *acc = nullptr;      // [N][d]
+    double *rho = nullptr, *mu = nullptr;      // [N]
+    double *as = nullptr;                      // [n_s][N]
+    double *Ba = nullptr;                      // [n_s][N][nv]
+    double *R = nullptr, *dx = nullptr;        // [N][max(bs,nv)]
+    // level-n copies used by eft_step
+    double *l_vp = nullptr, *l_vdot = nullptr, *l_phi = nullptr, *l_phidot = nullptr, *l_B = nullptr,
+           *l_Bdot = nullptr;
+    // transport
+    std::vector<Band> band;                    // per indicator
+    bool bands_valid = false;
+    uint8_t *seed = nullptr, *active = nullptr;  // [n_cells]
+    uint8_t *nin = nullptr, *nout = nullptr;     // [N]
+    uint8_t *ein = nullptr;                      // [E]
+    int32_t *g2b = nullptr;                      // [N] global -> band id
+    int32_t *gpos2b = nullptr;                   // [nnzb] global pattern pos -> band pos
+    int32_t *scan_tmp = nullptr;                 // scan workspace
+    int64_t scan_cap = 0;
+    double *bR = nullptr, *bX = nullptr;         // band system rhs / solution [cap][nv]
+    double *bval = nullptr;                      // band matrix values [cap_nnz][nv*nv]
+    int64_t bcap_n = 0, bcap_nnz = 0;
+    double *tnum = nullptr, *tden = nullptr;     // mobility projection sums [cap_n]
+    // reductions and host mirror
+    double *red = nullptr;                       // partial sums
+    double *dscal = nullptr;                     // device scalars
+    double *hscal = nullptr;                     // pinned host scalars
+    int32_t nred = 0;
+    KrylovWs kw;
+};
+
+// ------------------------------------------------------------- helpers ----
+
+#define EFT_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);               \
+            return EFT_EDEVICE;                                                         \
+        }                                                                               \
+    } while (0)
+
+#define EFT_TRY(expr)                      \
+    do {                                   \
+        eft_status s_ = (expr);            \
+        if (s_ != EFT_OK) return s_;       \
+    } while (0)
+
+static inline int eft_grid(int64_t n, int block) { return (int)((n + block - 1) / block); }
+
+// generalized-alpha constants (Sec. 2.1.2)
+struct GA {
+    double alpha, alpha_m, vs, dt, ct, kappa;
+};
+static inline GA ga_of(double rho_inf, double dt)
+{
+    GA g;
+    g.alpha = 1.0 / (1.0 + rho_inf);
+    g.alpha_m = 0.5 * (3.0 - rho_inf) / (1.0 + rho_inf);
+    g.vs = 0.5 + g.alpha_m - g.alpha;
+    g.dt = dt;
+    g.ct = g.alpha_m / (g.vs * dt);
+    g.kappa = g.alpha * g.vs * dt / g.alpha_m;
+    return g;
+}
+
+// ------------------------------------------------- kernels (launchers) ----
+
+// k_assemble.hip
+eft_status eft_props(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it);
+eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_matrix *J);
+eft_status eft_fill(eft_ctx *ctx, double *p, int64_t n, double v);
+eft_status eft_fill32(eft_ctx *ctx, float *p, int64_t n, float v);
+eft_status eft_fill_u8(eft_ctx *ctx, uint8_t *p, int64_t n);
+
+// k_sparse.hip
+eft_status eft_spmv_dev(eft_ctx *ctx, const eft_matrix *A, const double *x, double *y);
+eft_status eft_bj_setup(eft_ctx *ctx, const eft_matrix *A, double *Dinv);
+eft_status eft_bj_apply(eft_ctx *ctx, int bs, int64_t n, const double *Dinv, const double *x, double *z,
+                        const int32_t *active);
+eft_status eft_spmv_flag(eft_ctx *ctx, const eft_matrix *A, const double *x, double *y, const int32_t *active);
+
+// k_krylov.hip
+eft_status eft_krylov_reserve(eft_ctx *ctx, int64_t n, int bs, int m);
+eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, double *x, eft_solve_info *info);
+eft_status eft_norm2(eft_ctx *ctx, const double *x, int64_t n, double *out_host);
+eft_status eft_dot_dev(eft_ctx *ctx, const double *x, const double *y, int64_t n, double *out_dev);
+
+// k_transport.hip
+eft_status eft_bands_build_dev(eft_ctx *ctx, const double *phi_n);
+eft_status eft_transport_dev(eft_ctx *ctx, const eft_state *lvl, eft_iterate *it, eft_transport_info *info);
+
+// abi helpers
+eft_status eft_reserve_band_sys(eft_ctx *ctx, int64_t n, int64_t nnz);

@@ -1,0 +1,415 @@
+// Right-preconditioned FGMRES(m) with classical Gram-Schmidt and a second,
+// conditional orthogonalization pass ("twice is enough": the pass runs only
+// when the first one removed more than half of ||w||^2), FP64 throughout.
+//
+// Every kernel of an iteration reads a device flag and returns at once after
+// convergence, so the host enqueues iterations in chunks and reads the status
+// once per chunk; Hessenberg, Givens rotations and the triangular solve run in
+// single-thread device kernels.  Dot products reduce deterministically: each
+// block writes a partial, a second kernel sums the partials in a fixed order.
+#include "dev_common.h"
+#include "eft_internal.h"
+
+namespace {
+
+constexpr int RB = 256;   // reduction block size
+constexpr int KC = 8;     // vectors per multi-dot block
+
+// layout of KrylovWs::small (doubles) for restart m
+struct Small {
+    int m;
+    __host__ __device__ int64_t H() const { return 0; }                        // [(m+1)][m]
+    __host__ __device__ int64_t cs() const { return (int64_t)(m + 1) * m; }    // [m]
+    __host__ __device__ int64_t sn() const { return cs() + m; }                // [m]
+    __host__ __device__ int64_t g() const { return sn() + m; }                 // [m+1]
+    __host__ __device__ int64_t y() const { return g() + m + 1; }              // [m]
+    __host__ __device__ int64_t h() const { return y() + m; }                  // [m+2] dots, then ||w||^2
+    __host__ __device__ int64_t h2() const { return h() + m + 2; }             // [m+2]
+    __host__ __device__ int64_t sc() const { return h2() + m + 2; }            // [8] scalars
+    __host__ __device__ int64_t size() const { return sc() + 8; }
+};
+// scalars: sc+0 ||w'||^2 (after pass 1), sc+1 ||w''||^2, sc+2 tol_abs, sc+3 beta
+// flags: 0 active, 1 columns done in this cycle, 2 breakdown, 3 second-pass gate
+
+// dots of w with V[0..nvec-1] (and w.w as index nvec when with_ww): partials
+__global__ __launch_bounds__(RB) void k_mdot(const double *__restrict__ V, int64_t nd, int nvec, int with_ww,
+                                             const double *__restrict__ w, double *__restrict__ part, int nblk,
+                                             const int32_t *flag, int gated)
+{
+    __shared__ double lds[RB / 64];
+    if (flag[0] == 0 || (gated && flag[3] == 0)) return;
+    const int k0 = blockIdx.y * KC;
+    const int ntot = nvec + with_ww;
+    double acc[KC];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) acc[kk] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < nd; i += (int64_t)nblk * RB) {
+        const double wi = w[i];
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            const int k = k0 + kk;
+            if (k < nvec) acc[kk] += V[(int64_t)k * nd + i] * wi;
+            else if (k == nvec && with_ww) acc[kk] += wi * wi;
+        }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        const double s = block_sum<RB>(acc[kk], lds);
+        const int k = k0 + kk;
+        if (threadIdx.x == 0 && k < ntot) part[(int64_t)k * nblk + blockIdx.x] = s;
+    }
+}
+
+// out[k] = sum of part[k][*], grid = number of sums
+__global__ __launch_bounds__(RB) void k_sum_parts(const double *__restrict__ part, int nblk, double *__restrict__ out,
+                                                  const int32_t *flag, int gated)
+{
+    __shared__ double lds[RB / 64];
+    if (flag && (flag[0] == 0 || (gated && flag[3] == 0))) return;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += RB) s += part[(int64_t)blockIdx.x * nblk + b];
+    s = block_sum<RB>(s, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// w -= sum_k c[k] V[k] (sign = -1) or x += sum_k c[k] V[k] (sign = +1);
+// partial sums of the squared result when part != nullptr
+__global__ __launch_bounds__(RB) void k_maxpy(const double *__restrict__ V, int64_t nd, int nvec,
+                                              const double *__restrict__ c, double sign, double *__restrict__ w,
+                                              double *__restrict__ part, int nblk, const int32_t *flag, int gated)
+{
+    __shared__ double cl[EFT_MAX_RESTART + 2];
+    __shared__ double lds[RB / 64];
+    if (flag && (flag[0] == 0 || (gated && flag[3] == 0))) return;
+    for (int k = threadIdx.x; k < nvec; k += RB) cl[k] = sign * c[k];
+    __syncthreads();
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < nd; i += (int64_t)nblk * RB) {
+        double s = w[i];
+        for (int k = 0; k < nvec; ++k) s += cl[k] * V[(int64_t)k * nd + i];
+        w[i] = s;
+        acc += s * s;
+    }
+    if (part) {
+        const double t = block_sum<RB>(acc, lds);
+        if (threadIdx.x == 0) part[blockIdx.x] = t;
+    }
+}
+
+// After pass 1: store the dots as Hessenberg column j, decide on pass 2.
+__global__ void k_after_pass1(double *small, int m, int j, int32_t *flag)
+{
+    if (flag[0] == 0) return;
+    Small L{m};
+    double *H = small + L.H(), *h = small + L.h();
+    for (int i = 0; i <= j; ++i) H[(int64_t)i * m + j] = h[i];
+    const double ww = h[j + 1], nw = small[L.sc() + 0];
+    flag[3] = (nw < 0.5 * ww) ? 1 : 0;
+    if (!flag[3]) H[(int64_t)(j + 1) * m + j] = sqrt(nw);
+}
+
+__global__ void k_after_pass2(double *small, int m, int j, int32_t *flag)
+{
+    if (flag[0] == 0 || flag[3] == 0) return;
+    Small L{m};
+    double *H = small + L.H(), *h2 = small + L.h2();
+    for (int i = 0; i <= j; ++i) H[(int64_t)i * m + j] += h2[i];
+    H[(int64_t)(j + 1) * m + j] = sqrt(small[L.sc() + 1]);
+}
+
+// Givens update of column j, residual estimate, convergence / breakdown.
+__global__ void k_givens(double *small, int m, int j, int32_t *flag)
+{
+    if (flag[0] == 0) return;
+    Small L{m};
+    double *H = small + L.H(), *cs = small + L.cs(), *sn = small + L.sn(), *g = small + L.g();
+    for (int i = 0; i < j; ++i) {
+        const double a = H[(int64_t)i * m + j], b = H[(int64_t)(i + 1) * m + j];
+        H[(int64_t)i * m + j] = cs[i] * a + sn[i] * b;
+        H[(int64_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = H[(int64_t)j * m + j], b = H[(int64_t)(j + 1) * m + j];
+    const double hn = b;
+    const double den = sqrt(a * a + b * b);
+    cs[j] = den == 0.0 ? 1.0 : a / den;
+    sn[j] = den == 0.0 ? 0.0 : b / den;
+    H[(int64_t)j * m + j] = cs[j] * a + sn[j] * b;
+    H[(int64_t)(j + 1) * m + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    flag[1] = j + 1;
+    const double tol = small[L.sc() + 2];
+    if (!(fabs(g[j + 1]) > tol)) flag[0] = 0;  // converged (or NaN)
+    if (hn == 0.0) {
+        flag[0] = 0;
+        flag[2] = 1;
+    }
+    if (j + 1 >= m) flag[0] = 0;
+}
+
+// v_{j+1} = w / H[j+1][j]
+__global__ __launch_bounds__(RB) void k_normalize(const double *__restrict__ w, double *__restrict__ v, int64_t nd,
+                                                  const double *small, int m, int j, const int32_t *flag)
+{
+    if (flag[0] == 0) return;
+    Small L{m};
+    const double inv = 1.0 / small[L.H() + (int64_t)(j + 1) * m + j];
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < nd; i += (int64_t)gridDim.x * RB) v[i] = w[i] * inv;
+}
+
+// y = H^-1 g (upper triangular, jj columns)
+__global__ void k_trisolve(double *small, int m, const int32_t *flag)
+{
+    Small L{m};
+    const int jj = flag[1];
+    double *H = small + L.H(), *g = small + L.g(), *y = small + L.y();
+    for (int i = jj - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int k = i + 1; k < jj; ++k) s -= H[(int64_t)i * m + k] * y[k];
+        y[i] = s / H[(int64_t)i * m + i];
+    }
+}
+
+// start of a cycle: v0 = r / beta, g = (beta, 0, ...), flags
+__global__ __launch_bounds__(RB) void k_start_cycle(const double *__restrict__ r, double *__restrict__ v0, int64_t nd,
+                                                    double *small, int m, double beta, double tol, int32_t *flag)
+{
+    Small L{m};
+    const double inv = 1.0 / beta;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < nd; i += (int64_t)gridDim.x * RB) v0[i] = r[i] * inv;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double *g = small + L.g();
+        for (int i = 0; i <= m; ++i) g[i] = 0.0;
+        g[0] = beta;
+        small[L.sc() + 2] = tol;
+        flag[0] = 1;
+        flag[1] = 0;
+        flag[2] = 0;
+        flag[3] = 0;
+    }
+}
+
+// r = b - r
+__global__ __launch_bounds__(RB) void k_bmr(const double *__restrict__ b, double *__restrict__ r, int64_t nd)
+{
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < nd; i += (int64_t)gridDim.x * RB) r[i] = b[i] - r[i];
+}
+
+__global__ __launch_bounds__(RB) void k_norm_part(const double *__restrict__ x, int64_t nd, double *part, int nblk)
+{
+    __shared__ double lds[RB / 64];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < nd; i += (int64_t)nblk * RB) acc += x[i] * x[i];
+    acc = block_sum<RB>(acc, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(RB) void k_dot_part(const double *__restrict__ x, const double *__restrict__ y,
+                                                 int64_t nd, double *part, int nblk)
+{
+    __shared__ double lds[RB / 64];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < nd; i += (int64_t)nblk * RB) acc += x[i] * y[i];
+    acc = block_sum<RB>(acc, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+int nblk_for(int64_t nd) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (nd + RB - 1) / RB)); }
+int stream_grid(int64_t nd) { return (int)std::max<int64_t>(1, std::min<int64_t>(8192, (nd + RB - 1) / RB)); }
+
+}  // namespace
+
+eft_status eft_krylov_reserve(eft_ctx *ctx, int64_t n, int bs, int m)
+{
+    KrylovWs &K = ctx->kw;
+    const int64_t nd = n * bs;
+    if (m > EFT_MAX_RESTART) {
+        ctx->err = "restart above 512";
+        return EFT_EINVAL;
+    }
+    if (nd <= K.cap_nd && m <= K.cap_m && n <= K.cap_n && bs * bs * n <= K.cap_bs * K.cap_bs * K.cap_n) return EFT_OK;
+    const int64_t cnd = std::max(nd, K.cap_nd);
+    const int cm = std::max(m, K.cap_m);
+    const int64_t cn = std::max(n, K.cap_n);
+    const int cbs = std::max(bs, K.cap_bs);
+    auto fr = [](void *p) {
+        if (p) (void)hipFree(p);
+    };
+    fr(K.V); fr(K.Z); fr(K.w); fr(K.r); fr(K.Dinv); fr(K.part); fr(K.small); fr(K.flag);
+    K = KrylovWs{};
+    Small L{cm};
+    const int nblk = nblk_for(cnd);
+    if (hipMalloc(&K.V, sizeof(double) * cnd * (cm + 1)) != hipSuccess ||
+        hipMalloc(&K.Z, sizeof(double) * cnd * cm) != hipSuccess || hipMalloc(&K.w, sizeof(double) * cnd) != hipSuccess ||
+        hipMalloc(&K.r, sizeof(double) * cnd) != hipSuccess ||
+        hipMalloc(&K.Dinv, sizeof(double) * cn * cbs * cbs) != hipSuccess ||
+        hipMalloc(&K.part, sizeof(double) * (int64_t)nblk * (cm + 2)) != hipSuccess ||
+        hipMalloc(&K.small, sizeof(double) * L.size()) != hipSuccess ||
+        hipMalloc(&K.flag, sizeof(int32_t) * 8) != hipSuccess) {
+        ctx->err = "out of device memory for the Krylov workspace";
+        return EFT_ENOMEM;
+    }
+    K.cap_nd = cnd;
+    K.cap_m = cm;
+    K.cap_n = cn;
+    K.cap_bs = cbs;
+    K.nblk = nblk;
+    return EFT_OK;
+}
+
+static eft_status sum_to_host(eft_ctx *ctx, const double *part, int nblk, int count, double *host)
+{
+    hipLaunchKernelGGL(k_sum_parts, dim3(count), dim3(RB), 0, ctx->stream, part, nblk, ctx->dscal,
+                       (const int32_t *)nullptr, 0);
+    EFT_HIP(hipGetLastError());
+    EFT_HIP(hipMemcpyAsync(ctx->hscal, ctx->dscal, sizeof(double) * count, hipMemcpyDeviceToHost, ctx->stream));
+    EFT_HIP(hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < count; ++i) host[i] = ctx->hscal[i];
+    return EFT_OK;
+}
+
+eft_status eft_norm2(eft_ctx *ctx, const double *x, int64_t n, double *out_host)
+{
+    if (n == 0) {
+        *out_host = 0.0;
+        return EFT_OK;
+    }
+    const int nblk = nblk_for(n);
+    hipLaunchKernelGGL(k_norm_part, dim3(nblk), dim3(RB), 0, ctx->stream, x, n, ctx->red, nblk);
+    EFT_HIP(hipGetLastError());
+    double s;
+    EFT_TRY(sum_to_host(ctx, ctx->red, nblk, 1, &s));
+    *out_host = sqrt(s);
+    return EFT_OK;
+}
+
+eft_status eft_dot_dev(eft_ctx *ctx, const double *x, const double *y, int64_t n, double *out_dev)
+{
+    const int nblk = nblk_for(n);
+    hipLaunchKernelGGL(k_dot_part, dim3(nblk), dim3(RB), 0, ctx->stream, x, y, n, ctx->red, nblk);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(RB), 0, ctx->stream, ctx->red, nblk, out_dev,
+                       (const int32_t *)nullptr, 0);
+    EFT_HIP(hipGetLastError());
+    return EFT_OK;
+}
+
+// Solve A x = b (x0 = 0).  The preconditioner is the point-block Jacobi of A.
+eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, double *x, eft_solve_info *info)
+{
+    const int bs = A->bs;
+    const int64_t n = A->n, nd = n * bs;
+    const int m = std::max(1, std::min(ctx->par.restart, EFT_MAX_RESTART));
+    eft_solve_info inf{};
+    inf.rel_res0 = 1.0;
+    EFT_TRY(eft_krylov_reserve(ctx, n, bs, m));
+    KrylovWs &K = ctx->kw;
+    Small L{m};
+    const int nblk = nblk_for(nd), sg = stream_grid(nd);
+    EFT_TRY(eft_fill(ctx, x, nd, 0.0));
+    double bnorm;
+    EFT_TRY(eft_norm2(ctx, b, nd, &bnorm));
+    if (!std::isfinite(bnorm)) {
+        ctx->err = "non-finite right-hand side";
+        return EFT_ENAN;
+    }
+    if (bnorm == 0.0) {
+        inf.converged = 1;
+        inf.rel_res = 0.0;
+        if (info) *info = inf;
+        return EFT_OK;
+    }
+    EFT_TRY(eft_bj_setup(ctx, A, K.Dinv));
+    const double tol = ctx->par.lin_rtol * bnorm;
+    const int maxit = std::max(1, ctx->par.lin_maxit);
+    const int chunk = 8;
+    int total = 0;
+    double *small = K.small;
+    eft_status st = EFT_ENOTCONV;
+    // first residual: r = b
+    EFT_HIP(hipMemcpyAsync(K.r, b, sizeof(double) * nd, hipMemcpyDeviceToDevice, ctx->stream));
+    double beta = bnorm;
+    for (;;) {
+        const double rel = beta / bnorm;
+        inf.rel_res = rel;
+        if (!std::isfinite(beta)) {
+            ctx->err = "NaN in the Krylov solve";
+            st = EFT_ENAN;
+            break;
+        }
+        if (beta <= tol) {
+            st = EFT_OK;
+            inf.converged = 1;
+            break;
+        }
+        if (total >= maxit) break;
+        const int mc = std::min(m, maxit - total);
+        hipLaunchKernelGGL(k_start_cycle, dim3(sg), dim3(RB), 0, ctx->stream, K.r, K.V, nd, small, m, beta, tol,
+                           K.flag);
+        int jdone = 0;
+        for (int j0 = 0; j0 < mc; j0 += chunk) {
+            for (int j = j0; j < std::min(mc, j0 + chunk); ++j) {
+                double *vj = K.V + (int64_t)j * nd, *zj = K.Z + (int64_t)j * nd;
+                EFT_TRY(eft_bj_apply(ctx, bs, n, K.Dinv, vj, zj, K.flag));
+                EFT_TRY(eft_spmv_flag(ctx, A, zj, K.w, K.flag));
+                // pass 1: dots with V[0..j] and ||w||^2
+                dim3 g1(nblk, (j + 2 + KC - 1) / KC);
+                hipLaunchKernelGGL(k_mdot, g1, dim3(RB), 0, ctx->stream, K.V, nd, j + 1, 1, K.w, K.part, nblk,
+                                   K.flag, 0);
+                hipLaunchKernelGGL(k_sum_parts, dim3(j + 2), dim3(RB), 0, ctx->stream, K.part, nblk, small + L.h(),
+                                   K.flag, 0);
+                hipLaunchKernelGGL(k_maxpy, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, j + 1, small + L.h(), -1.0,
+                                   K.w, K.part, nblk, K.flag, 0);
+                hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, small + L.sc(),
+                                   K.flag, 0);
+                hipLaunchKernelGGL(k_after_pass1, dim3(1), dim3(1), 0, ctx->stream, small, m, j, K.flag);
+                // pass 2 (gated)
+                dim3 g2(nblk, (j + 1 + KC - 1) / KC);
+                hipLaunchKernelGGL(k_mdot, g2, dim3(RB), 0, ctx->stream, K.V, nd, j + 1, 0, K.w, K.part, nblk, K.flag,
+                                   1);
+                hipLaunchKernelGGL(k_sum_parts, dim3(j + 1), dim3(RB), 0, ctx->stream, K.part, nblk, small + L.h2(),
+                                   K.flag, 1);
+                hipLaunchKernelGGL(k_maxpy, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, j + 1, small + L.h2(),
+                                   -1.0, K.w, K.part, nblk, K.flag, 1);
+                hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, small + L.sc() + 1,
+                                   K.flag, 1);
+                hipLaunchKernelGGL(k_after_pass2, dim3(1), dim3(1), 0, ctx->stream, small, m, j, K.flag);
+                hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, ctx->stream, small, m, j, K.flag);
+                hipLaunchKernelGGL(k_normalize, dim3(sg), dim3(RB), 0, ctx->stream, K.w, K.V + (int64_t)(j + 1) * nd,
+                                   nd, small, m, j, K.flag);
+            }
+            EFT_HIP(hipGetLastError());
+            EFT_HIP(hipMemcpyAsync(ctx->hscal, K.flag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, ctx->stream));
+            EFT_HIP(hipStreamSynchronize(ctx->stream));
+            const int32_t *hf = (const int32_t *)ctx->hscal;
+            jdone = hf[1];
+            if (hf[0] == 0) break;
+        }
+        // x += Z y
+        hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(1), 0, ctx->stream, small, m, K.flag);
+        hipLaunchKernelGGL(k_maxpy, dim3(nblk), dim3(RB), 0, ctx->stream, K.Z, nd, jdone, small + L.y(), 1.0, x,
+                           (double *)nullptr, nblk, (const int32_t *)nullptr, 0);
+        EFT_HIP(hipGetLastError());
+        total += jdone;
+        inf.restarts += 1;
+        // true residual
+        EFT_TRY(eft_spmv_dev(ctx, A, x, K.r));
+        hipLaunchKernelGGL(k_bmr, dim3(sg), dim3(RB), 0, ctx->stream, b, K.r, nd);
+        EFT_HIP(hipGetLastError());
+        EFT_TRY(eft_norm2(ctx, K.r, nd, &beta));
+        if (jdone == 0) {  // no progress possible
+            inf.rel_res = beta / bnorm;
+            if (beta <= tol) {
+                st = EFT_OK;
+                inf.converged = 1;
+            } else {
+                st = EFT_EBREAKDOWN;
+                ctx->err = "FGMRES made no progress";
+            }
+            break;
+        }
+    }
+    inf.iters = total;
+    if (info) *info = inf;
+    if (st == EFT_ENOTCONV) ctx->err = "FGMRES reached lin_maxit";
+    return st;
+}

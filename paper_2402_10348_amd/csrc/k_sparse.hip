@@ -1,0 +1,210 @@
+// Sparse kernels of the Krylov solve (eq. LS_NS and the band systems):
+// BSR sparse matrix-vector product and point-block Jacobi.
+//
+// SpMV layout: one 64-wide wavefront per block row.  The wavefront reads
+// floor(64 / bs^2) whole blocks per step, one value per lane, so every load
+// instruction covers contiguous 128 B (bs = 4, FP64) runs of the value array;
+// x entries are gathered per block column.  bs = 1 uses 16 lanes per row.
+#include "dev_common.h"
+#include "eft_internal.h"
+
+template <typename TV> __device__ __forceinline__ double ld(const TV *p) { return (double)*p; }
+
+// bs = 4: shuffle reduction over the 4 columns and the 4 block slots.
+template <typename TV>
+__global__ __launch_bounds__(256) void k_spmv4(int64_t n, const int32_t *__restrict__ rowptr,
+                                               const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                               const double *__restrict__ x, double *__restrict__ y,
+                                               const int32_t *active)
+{
+    if (active && *active == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (row >= n) return;
+    const int slot = lane >> 4, e = lane & 15, c = e & 3;
+    const int k0 = rowptr[row], k1 = rowptr[row + 1];
+    double acc = 0.0;
+    for (int k = k0 + slot; k < k1; k += 4) acc += ld(val + (int64_t)k * 16 + e) * x[(int64_t)col[k] * 4 + c];
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    acc += __shfl_xor(acc, 16, 64);
+    acc += __shfl_xor(acc, 32, 64);
+    if (slot == 0 && c == 0) y[row * 4 + (e >> 2)] = acc;
+}
+
+// general bs in 2..8: LDS reduction per wavefront.
+template <typename TV>
+__global__ __launch_bounds__(256) void k_spmvb(int64_t n, int bs, const int32_t *__restrict__ rowptr,
+                                               const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                               const double *__restrict__ x, double *__restrict__ y,
+                                               const int32_t *active)
+{
+    __shared__ double lds[256];
+    if (active && *active == 0) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int b2 = bs * bs, slots = 64 / b2;
+    const int slot = lane / b2, e = lane - slot * b2, c = e % bs;
+    double acc = 0.0;
+    if (row < n && slot < slots) {
+        const int k0 = rowptr[row], k1 = rowptr[row + 1];
+        for (int k = k0 + slot; k < k1; k += slots) acc += ld(val + (int64_t)k * b2 + e) * x[(int64_t)col[k] * bs + c];
+    }
+    lds[threadIdx.x] = acc;
+    __syncthreads();
+    if (row < n && lane < bs) {
+        double s = 0.0;
+        for (int sl = 0; sl < slots; ++sl)
+            for (int cc = 0; cc < bs; ++cc) s += lds[wv * 64 + sl * b2 + lane * bs + cc];
+        y[row * bs + lane] = s;
+    }
+}
+
+// bs = 1: 16 lanes per row.
+template <typename TV>
+__global__ __launch_bounds__(256) void k_spmv1(int64_t n, const int32_t *__restrict__ rowptr,
+                                               const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                               const double *__restrict__ x, double *__restrict__ y,
+                                               const int32_t *active)
+{
+    if (active && *active == 0) return;
+    const int sub = threadIdx.x & 15;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    double acc = 0.0;
+    if (row < n) {
+        const int k0 = rowptr[row], k1 = rowptr[row + 1];
+        for (int k = k0 + sub; k < k1; k += 16) acc += ld(val + k) * x[col[k]];
+    }
+    acc += __shfl_xor(acc, 1, 16);
+    acc += __shfl_xor(acc, 2, 16);
+    acc += __shfl_xor(acc, 4, 16);
+    acc += __shfl_xor(acc, 8, 16);
+    if (row < n && sub == 0) y[row] = acc;
+}
+
+template <typename TV>
+static void spmv_launch(eft_ctx *ctx, int64_t n, int bs, const int32_t *rowptr, const int32_t *col, const TV *val,
+                        const double *x, double *y, const int32_t *active)
+{
+    if (bs == 1) {
+        hipLaunchKernelGGL(k_spmv1<TV>, dim3(eft_grid(n, 16)), dim3(256), 0, ctx->stream, n, rowptr, col, val, x, y,
+                           active);
+    } else if (bs == 4) {
+        hipLaunchKernelGGL(k_spmv4<TV>, dim3(eft_grid(n, 4)), dim3(256), 0, ctx->stream, n, rowptr, col, val, x, y,
+                           active);
+    } else {
+        hipLaunchKernelGGL(k_spmvb<TV>, dim3(eft_grid(n, 4)), dim3(256), 0, ctx->stream, n, bs, rowptr, col, val, x,
+                           y, active);
+    }
+}
+
+eft_status eft_spmv_flag(eft_ctx *ctx, const eft_matrix *A, const double *x, double *y, const int32_t *active)
+{
+    if (A->n == 0) return EFT_OK;
+    if (A->fp32)
+        spmv_launch<float>(ctx, A->n, A->bs, A->rowptr, A->col, A->val32, x, y, active);
+    else
+        spmv_launch<double>(ctx, A->n, A->bs, A->rowptr, A->col, A->val, x, y, active);
+    EFT_HIP(hipGetLastError());
+    return EFT_OK;
+}
+
+eft_status eft_spmv_dev(eft_ctx *ctx, const eft_matrix *A, const double *x, double *y)
+{
+    return eft_spmv_flag(ctx, A, x, y, nullptr);
+}
+
+// -------------------------------------------------- point-block Jacobi ----
+
+// Inverse of each diagonal block by Gauss-Jordan elimination with partial
+// pivoting.  A block with a zero pivot gets the identity (no scaling).
+template <typename TV>
+__global__ __launch_bounds__(256) void k_bj_setup(int64_t n, int bs, const int32_t *__restrict__ diag,
+                                                  const TV *__restrict__ val, double *__restrict__ Dinv)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double A[8][8], I[8][8];
+    const int b2 = bs * bs;
+    const TV *blk = val + (int64_t)diag[r] * b2;
+    for (int i = 0; i < bs; ++i)
+        for (int j = 0; j < bs; ++j) {
+            A[i][j] = (double)blk[i * bs + j];
+            I[i][j] = (i == j) ? 1.0 : 0.0;
+        }
+    bool ok = true;
+    for (int k = 0; k < bs && ok; ++k) {
+        int pr = k;
+        for (int i = k + 1; i < bs; ++i)
+            if (fabs(A[i][k]) > fabs(A[pr][k])) pr = i;
+        if (A[pr][k] == 0.0) {
+            ok = false;
+            break;
+        }
+        if (pr != k)
+            for (int j = 0; j < bs; ++j) {
+                double t = A[k][j]; A[k][j] = A[pr][j]; A[pr][j] = t;
+                t = I[k][j]; I[k][j] = I[pr][j]; I[pr][j] = t;
+            }
+        const double inv = 1.0 / A[k][k];
+        for (int j = 0; j < bs; ++j) {
+            A[k][j] *= inv;
+            I[k][j] *= inv;
+        }
+        for (int i = 0; i < bs; ++i) {
+            if (i == k) continue;
+            const double f = A[i][k];
+            if (f == 0.0) continue;
+            for (int j = 0; j < bs; ++j) {
+                A[i][j] -= f * A[k][j];
+                I[i][j] -= f * I[k][j];
+            }
+        }
+    }
+    double *out = Dinv + r * b2;
+    for (int i = 0; i < bs; ++i)
+        for (int j = 0; j < bs; ++j) out[i * bs + j] = ok ? I[i][j] : (i == j ? 1.0 : 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_bj_apply(int64_t nd, int bs, const double *__restrict__ Dinv,
+                                                  const double *__restrict__ x, double *__restrict__ z,
+                                                  const int32_t *active)
+{
+    if (active && *active == 0) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nd) return;
+    const int64_t r = t / bs;
+    const int i = (int)(t - r * bs);
+    const double *D = Dinv + r * bs * bs + i * bs;
+    const double *xr = x + r * bs;
+    double s = 0.0;
+    for (int c = 0; c < bs; ++c) s += D[c] * xr[c];
+    z[t] = s;
+}
+
+eft_status eft_bj_setup(eft_ctx *ctx, const eft_matrix *A, double *Dinv)
+{
+    if (A->n == 0) return EFT_OK;
+    if (A->bs > 8) {
+        ctx->err = "block size above 8";
+        return EFT_EINVAL;
+    }
+    if (A->fp32)
+        hipLaunchKernelGGL(k_bj_setup<float>, dim3(eft_grid(A->n, 256)), dim3(256), 0, ctx->stream, A->n, A->bs,
+                           A->diag, A->val32, Dinv);
+    else
+        hipLaunchKernelGGL(k_bj_setup<double>, dim3(eft_grid(A->n, 256)), dim3(256), 0, ctx->stream, A->n, A->bs,
+                           A->diag, A->val, Dinv);
+    EFT_HIP(hipGetLastError());
+    return EFT_OK;
+}
+
+eft_status eft_bj_apply(eft_ctx *ctx, int bs, int64_t n, const double *Dinv, const double *x, double *z,
+                        const int32_t *active)
+{
+    const int64_t nd = n * bs;
+    if (nd == 0) return EFT_OK;
+    hipLaunchKernelGGL(k_bj_apply, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, nd, bs, Dinv, x, z, active);
+    EFT_HIP(hipGetLastError());
+    return EFT_OK;
+}

@@ -1,0 +1,972 @@
+// Order-parameter and left-Cauchy-Green transport restricted to the grid-cell
+// band of every indicator:
+//   band build   grid cells (Sec. 3.1 grid-cell method) seeded where
+//                |phi^n| < 1 - band_flat, dilated by band_halo cell layers;
+//                band nodes/elements compacted, band pattern carved out of the
+//                global node graph;
+//   mobility     eq. (tdm-num): element quotient (grad phi)^T grad v
+//                (grad phi) / |grad phi|^2, L2 projection to nodes (Appendix A),
+//                RMS over |phi| <= di_cut, divided by eta;
+//   beta         int F'(phi) / int sqrt(F(phi)) over the band (Sec. 2.2.1);
+//   Allen-Cahn   eq. (PPV_AC) residual and tangent, SUPG with tau_phi;
+//   B            eq. (semiCGT) residual and tangent, SUPG with tau_B;
+// each band system is solved with the same FGMRES as the momentum block.
+#include <algorithm>
+
+#include "dev_common.h"
+#include "eft_internal.h"
+
+namespace {
+
+constexpr int SB = 1024;     // scan block
+constexpr int ST = 4;        // items per thread
+constexpr int TILE = SB * ST;
+
+__device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t *lds, int32_t *total)
+{
+    const int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+    for (int off = 1; off < SB; off <<= 1) {
+        int32_t a = t >= off ? lds[t - off] : 0;
+        __syncthreads();
+        lds[t] += a;
+        __syncthreads();
+    }
+    int32_t incl = lds[t];
+    *total = lds[SB - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+template <typename TI>
+__global__ __launch_bounds__(SB) void k_scan_count(const TI *in, int64_t n, int32_t *bsum)
+{
+    __shared__ int32_t lds[SB];
+    const int64_t base = (int64_t)blockIdx.x * TILE + threadIdx.x * ST;
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < ST; ++k)
+        if (base + k < n) s += (int32_t)in[base + k];
+    int32_t tot;
+    block_excl_scan(s, lds, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SB) void k_scan_blocks(int32_t *bsum, int nb, int32_t *total)
+{
+    __shared__ int32_t lds[SB];
+    int32_t carry = 0;
+    for (int c = 0; c < nb; c += SB) {
+        const int i = c + threadIdx.x;
+        const int32_t v = i < nb ? bsum[i] : 0;
+        int32_t tot;
+        const int32_t ex = block_excl_scan(v, lds, &tot);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+// Exclusive offsets out[i] (optional), compacted indices idx[] of nonzero
+// entries (optional, for flags), map[i] = position or -1 (optional).
+template <typename TI>
+__global__ __launch_bounds__(SB) void k_scan_write(const TI *in, int64_t n, const int32_t *bsum,
+                                                   int32_t *out, int32_t *idx, int32_t *map)
+{
+    __shared__ int32_t lds[SB];
+    const int64_t base = (int64_t)blockIdx.x * TILE + threadIdx.x * ST;
+    int32_t v[ST], s = 0;
+#pragma unroll
+    for (int k = 0; k < ST; ++k) {
+        v[k] = base + k < n ? (int32_t)in[base + k] : 0;
+        s += v[k];
+    }
+    int32_t tot;
+    int32_t pos = block_excl_scan(s, lds, &tot) + bsum[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < ST; ++k) {
+        const int64_t i = base + k;
+        if (i < n) {
+            if (out) out[i] = pos;
+            if (idx && v[k]) idx[pos] = (int32_t)i;
+            if (map) map[i] = v[k] ? pos : -1;
+        }
+        pos += v[k];
+    }
+}
+
+// ---------------------------------------------------------------- band ----
+
+template <int D>
+__global__ __launch_bounds__(256) void k_seed(int64_t E, const int32_t *conn, const int32_t *cell_of,
+                                              const double *phi, double thr, uint8_t *seed)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    bool iface = false;
+#pragma unroll
+    for (int a = 0; a < D + 1; ++a) iface |= fabs(phi[conn[e * (D + 1) + a]]) < thr;
+    if (iface) seed[cell_of[e]] = 1;
+}
+
+__global__ __launch_bounds__(256) void k_dilate(int nx, int ny, int nz, int H, const uint8_t *seed, uint8_t *active)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ncell = (int64_t)nx * ny * nz;
+    if (c >= ncell) return;
+    const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((int64_t)nx * ny));
+    uint8_t act = 0;
+    for (int dk = -H; dk <= H && !act; ++dk)
+        for (int dj = -H; dj <= H && !act; ++dj)
+            for (int di = -H; di <= H; ++di) {
+                const int ii = i + di, jj = j + dj, kk = k + dk;
+                if (ii < 0 || jj < 0 || kk < 0 || ii >= nx || jj >= ny || kk >= nz) continue;
+                if (seed[ii + (int64_t)nx * (jj + (int64_t)ny * kk)]) {
+                    act = 1;
+                    break;
+                }
+            }
+    active[c] = act;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_mark(int64_t E, const int32_t *conn, const int32_t *cell_of,
+                                              const uint8_t *active, uint8_t *ein, uint8_t *nin, uint8_t *nout)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const uint8_t inb = active[cell_of[e]];
+    ein[e] = inb;
+#pragma unroll
+    for (int a = 0; a < D + 1; ++a) {
+        const int p = conn[e * (D + 1) + a];
+        if (inb) nin[p] = 1;
+        else nout[p] = 1;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_band_free(int64_t n, const int32_t *node, const uint8_t *nout, uint8_t *fre)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    fre[r] = nout[node[r]] ? 0 : 1;
+}
+
+__global__ __launch_bounds__(256) void k_band_rowcount(int64_t n, const int32_t *node, const int32_t *grow,
+                                                       const int32_t *gcol, const int32_t *g2b, int32_t *cnt)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int g = node[r];
+    int c = 0;
+    for (int k = grow[g]; k < grow[g + 1]; ++k) c += g2b[gcol[k]] >= 0 ? 1 : 0;
+    cnt[r] = c;
+}
+
+__global__ __launch_bounds__(256) void k_band_fill(int64_t n, const int32_t *node, const int32_t *grow,
+                                                   const int32_t *gcol, const int32_t *g2b, const int32_t *rowptr,
+                                                   int32_t *col, int32_t *diag, int32_t *gpos2b)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int g = node[r];
+    int pos = rowptr[r];
+    for (int k = grow[g]; k < grow[g + 1]; ++k) {
+        const int b = g2b[gcol[k]];
+        if (b < 0) continue;
+        col[pos] = b;
+        if (b == r) diag[r] = pos;
+        gpos2b[k] = pos;
+        ++pos;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_band_epos(int64_t ne, const int32_t *elem, const int32_t *conn,
+                                                   const int32_t *epos, const int32_t *gpos2b, const int32_t *g2b,
+                                                   int32_t *bepos, int32_t *bconn)
+{
+    const int64_t be = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (be >= ne) return;
+    constexpr int NN = D + 1;
+    const int64_t e = elem[be];
+#pragma unroll
+    for (int a = 0; a < NN; ++a) bconn[be * NN + a] = g2b[conn[e * NN + a]];
+#pragma unroll
+    for (int t = 0; t < NN * NN; ++t) bepos[be * NN * NN + t] = gpos2b[epos[e * NN * NN + t]];
+}
+
+// ------------------------------------------------------------ mobility ----
+
+template <int D>
+__global__ __launch_bounds__(256) void k_mob_elem(int64_t ne, const int32_t *elem, const int32_t *bconn,
+                                                  const int32_t *conn, const double *xyz, const double *va,
+                                                  const double *lphi, const double *iphi, double alpha, double *num,
+                                                  double *den)
+{
+    const int64_t be = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (be >= ne) return;
+    constexpr int NN = D + 1;
+    const int64_t e = elem[be];
+    double X[NN][D], v[NN][D], f[NN];
+#pragma unroll
+    for (int a = 0; a < NN; ++a) {
+        const int64_t g = conn[e * NN + a];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            X[a][i] = xyz[g * D + i];
+            v[a][i] = va[g * D + i];
+        }
+        f[a] = lphi[g] + alpha * (iphi[g] - lphi[g]);
+    }
+    double dN[NN][D], G[D][D];
+    const double vol = simplex_geom<D>(X, dN, G);
+    double gf[D], L[D][D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < NN; ++a) s += f[a] * dN[a][j];
+        gf[j] = s;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double t = 0.0;
+#pragma unroll
+            for (int a = 0; a < NN; ++a) t += v[a][i] * dN[a][j];
+            L[i][j] = t;
+        }
+    }
+    double g2 = 0.0, gLg = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        g2 += gf[i] * gf[i];
+#pragma unroll
+        for (int j = 0; j < D; ++j) gLg += gf[i] * L[i][j] * gf[j];
+    }
+    const double q = g2 > 0.0 ? gLg / g2 : 0.0;
+    // int_e N_p with the degree-2 rule
+    const double share = vol * Rule<D>::WF * (Rule<D>::QA + (Rule<D>::NQ - 1) * Rule<D>::QB);
+#pragma unroll
+    for (int a = 0; a < NN; ++a) {
+        const int l = bconn[be * NN + a];
+        unsafeAtomicAdd(num + l, q * share);
+        unsafeAtomicAdd(den + l, share);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mob_node(int64_t n, const int32_t *node, const double *lphi,
+                                                  const double *iphi, double alpha, double cut, const double *num,
+                                                  const double *den, double *part)
+{
+    __shared__ double lds[4];
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0, c = 0.0;
+    if (r < n) {
+        const int g = node[r];
+        const double f = lphi[g] + alpha * (iphi[g] - lphi[g]);
+        if (fabs(f) <= cut) {
+            const double Q = fabs(den[r] > 0.0 ? num[r] / den[r] : 0.0);
+            s = Q * Q;
+            c = 1.0;
+        }
+    }
+    s = block_sum<256>(s, lds);
+    c = block_sum<256>(c, lds);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s;
+        part[2 * blockIdx.x + 1] = c;
+    }
+}
+
+// --------------------------------------------------------------- beta -----
+
+template <int D>
+__global__ __launch_bounds__(256) void k_beta_elem(int64_t ne, const int32_t *elem, const int32_t *conn,
+                                                   const double *xyz, const double *lphi, const double *iphi,
+                                                   double alpha, double *part)
+{
+    __shared__ double lds[4];
+    const int64_t be = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int NN = D + 1, NQ = Rule<D>::NQ;
+    double sn = 0.0, sd = 0.0;
+    if (be < ne) {
+        const int64_t e = elem[be];
+        double X[NN][D], f[NN];
+#pragma unroll
+        for (int a = 0; a < NN; ++a) {
+            const int64_t g = conn[e * NN + a];
+#pragma unroll
+            for (int i = 0; i < D; ++i) X[a][i] = xyz[g * D + i];
+            f[a] = lphi[g] + alpha * (iphi[g] - lphi[g]);
+        }
+        double dN[NN][D], G[D][D];
+        const double w = simplex_geom<D>(X, dN, G) * Rule<D>::WF;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            double fq = 0.0;
+#pragma unroll
+            for (int a = 0; a < NN; ++a) fq += shape_at<D>(q, a) * f[a];
+            sn += w * (fq * fq * fq - fq);
+            sd += w * 0.5 * fabs(fq * fq - 1.0);
+        }
+    }
+    sn = block_sum<256>(sn, lds);
+    sd = block_sum<256>(sd, lds);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sn;
+        part[2 * blockIdx.x + 1] = sd;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sum2(const double *part, int nb, double *out)
+{
+    __shared__ double lds[4];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) {
+        a += part[2 * i];
+        b += part[2 * i + 1];
+    }
+    a = block_sum<256>(a, lds);
+    b = block_sum<256>(b, lds);
+    if (threadIdx.x == 0) {
+        out[0] = a;
+        out[1] = b;
+    }
+}
+
+// ---------------------------------------------------------- Allen-Cahn ----
+
+struct TrArgs {
+    int64_t ne;
+    const int32_t *elem, *bconn, *bepos, *conn;
+    const double *xyz, *va;
+    const double *lx, *ldx, *ix;  // level value, level rate, iterate of the transported field
+    double alpha, alpha_m, vs, dt, ct;
+    double *R, *J;
+};
+
+template <int D>
+__global__ __launch_bounds__(128) void k_ac_elem(TrArgs a, double eps, const double *gb /* gamma, beta */)
+{
+    const int64_t be = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (be >= a.ne) return;
+    constexpr int NN = D + 1, NQ = Rule<D>::NQ;
+    const double gamma = gb[0], beta = gb[1];
+    const int64_t e = a.elem[be];
+    double X[NN][D], v[NN][D], f[NN], fd[NN];
+#pragma unroll
+    for (int b = 0; b < NN; ++b) {
+        const int64_t g = a.conn[e * NN + b];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            X[b][i] = a.xyz[g * D + i];
+            v[b][i] = a.va[g * D + i];
+        }
+        const double xn = a.lx[g], xd = a.ldx[g], x1 = a.ix[g];
+        const double xd1 = xd + (x1 - xn - a.dt * xd) / (a.vs * a.dt);
+        fd[b] = xd + a.alpha_m * (xd1 - xd);
+        f[b] = xn + a.alpha * (x1 - xn);
+    }
+    double dN[NN][D], G[D][D];
+    const double vol = simplex_geom<D>(X, dN, G);
+    double GG = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) GG += G[i][j] * G[i][j];
+    double gf[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b < NN; ++b) s += f[b] * dN[b][j];
+        gf[j] = s;
+    }
+    const double kh = eps * eps, w = vol * Rule<D>::WF, al = a.alpha, ct = a.ct;
+    const double gk9 = 9.0 * (gamma * kh) * (gamma * kh) * GG, i4 = 4.0 / (a.dt * a.dt);
+    double re[NN], K[NN][NN];
+#pragma unroll
+    for (int b = 0; b < NN; ++b) {
+        re[b] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NN; ++c) K[b][c] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double fq = 0.0, fdq = 0.0, vq[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) vq[i] = 0.0;
+#pragma unroll
+        for (int b = 0; b < NN; ++b) {
+            const double Nb = shape_at<D>(q, b);
+            fq += Nb * f[b];
+            fdq += Nb * fd[b];
+#pragma unroll
+            for (int i = 0; i < D; ++i) vq[i] += Nb * v[b][i];
+        }
+        double vg = 0.0, vGv = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            vg += vq[i] * gf[i];
+#pragma unroll
+            for (int j = 0; j < D; ++j) vGv += vq[i] * G[i][j] * vq[j];
+        }
+        const double f2m1 = fq * fq - 1.0;
+        const double sgn = (f2m1 > 0.0) - (f2m1 < 0.0);
+        const double react = fq * fq * fq - fq - beta * 0.5 * fabs(f2m1);
+        const double sh = 3.0 * fq * fq - 1.0 - beta * fq * sgn;
+        const double Rphi = fdq + vg + gamma * react;
+        const double tau = 1.0 / sqrt(i4 + vGv + gk9 + (gamma * sh) * (gamma * sh));
+        double u[NN];
+#pragma unroll
+        for (int b = 0; b < NN; ++b) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) s += vq[j] * dN[b][j];
+            u[b] = s;
+        }
+#pragma unroll
+        for (int ia = 0; ia < NN; ++ia) {
+            const double Na = shape_at<D>(q, ia);
+            double gg = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) gg += dN[ia][j] * gf[j];
+            re[ia] += w * (Na * (fdq + vg) + gamma * (kh * gg + Na * react) + tau * u[ia] * Rphi);
+#pragma unroll
+            for (int ib = 0; ib < NN; ++ib) {
+                const double Nb = shape_at<D>(q, ib);
+                double gab = 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) gab += dN[ia][j] * dN[ib][j];
+                const double lin = ct * Nb + al * u[ib];
+                K[ia][ib] += w * (Na * lin + al * gamma * (kh * gab + Na * sh * Nb) + tau * u[ia] * (lin + al * gamma * sh * Nb));
+            }
+        }
+    }
+    const int32_t *ep = a.bepos + be * NN * NN;
+#pragma unroll
+    for (int ia = 0; ia < NN; ++ia) {
+        unsafeAtomicAdd(a.R + a.bconn[be * NN + ia], re[ia]);
+#pragma unroll
+        for (int ib = 0; ib < NN; ++ib) unsafeAtomicAdd(a.J + ep[ia * NN + ib], K[ia][ib]);
+    }
+}
+
+// ------------------------------------------------------------------- B ----
+
+template <int D>
+__global__ __launch_bounds__(128) void k_b_elem(TrArgs a, const double *afr /*[N]*/)
+{
+    const int64_t be = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (be >= a.ne) return;
+    constexpr int NN = D + 1, NQ = Rule<D>::NQ, NVv = NV<D>::v;
+    const int64_t e = a.elem[be];
+    double X[NN][D], v[NN][D], am[NN], Bn[NN][NVv], Bd[NN][NVv];
+#pragma unroll
+    for (int b = 0; b < NN; ++b) {
+        const int64_t g = a.conn[e * NN + b];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            X[b][i] = a.xyz[g * D + i];
+            v[b][i] = a.va[g * D + i];
+        }
+        am[b] = afr[g];
+#pragma unroll
+        for (int c = 0; c < NVv; ++c) {
+            const double xn = a.lx[g * NVv + c], xd = a.ldx[g * NVv + c], x1 = a.ix[g * NVv + c];
+            const double xd1 = xd + (x1 - xn - a.dt * xd) / (a.vs * a.dt);
+            Bd[b][c] = xd + a.alpha_m * (xd1 - xd);
+            Bn[b][c] = xn + a.alpha * (x1 - xn);
+        }
+    }
+    double dN[NN][D], G[D][D];
+    const double vol = simplex_geom<D>(X, dN, G);
+    double L[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int b = 0; b < NN; ++b) s += v[b][i] * dN[b][j];
+            L[i][j] = s;
+        }
+    double gB[D][D][D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double gk[NVv];
+#pragma unroll
+        for (int c = 0; c < NVv; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int b = 0; b < NN; ++b) s += dN[b][k] * Bn[b][c];
+            gk[c] = s;
+        }
+        vfull<D>(gk, gB[k]);
+    }
+    const double w = vol * Rule<D>::WF, al = a.alpha, ct = a.ct, i4 = 4.0 / (a.dt * a.dt);
+    double re[NN][NVv], W[NN][NQ], U[NN][NQ], AQ[NQ];
+#pragma unroll
+    for (int b = 0; b < NN; ++b)
+#pragma unroll
+        for (int c = 0; c < NVv; ++c) re[b][c] = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double vq[D], aq = 0.0, bq[NVv], bdq[NVv];
+#pragma unroll
+        for (int i = 0; i < D; ++i) vq[i] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NVv; ++c) bq[c] = bdq[c] = 0.0;
+#pragma unroll
+        for (int b = 0; b < NN; ++b) {
+            const double Nb = shape_at<D>(q, b);
+            aq += Nb * am[b];
+#pragma unroll
+            for (int i = 0; i < D; ++i) vq[i] += Nb * v[b][i];
+#pragma unroll
+            for (int c = 0; c < NVv; ++c) {
+                bq[c] += Nb * Bn[b][c];
+                bdq[c] += Nb * Bd[b][c];
+            }
+        }
+        double Bq[D][D], Bdq[D][D];
+        vfull<D>(bq, Bq);
+        vfull<D>(bdq, Bdq);
+        double vGv = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) vGv += vq[i] * G[i][j] * vq[j];
+        const double tau = 1.0 / sqrt(i4 + vGv);
+        double RB[NVv];
+#pragma unroll
+        for (int c = 0; c < NVv; ++c) {
+            int i, j;
+            vpair<D>(c, i, j);
+            double conv = 0.0, LB = 0.0, BL = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                conv += vq[k] * gB[k][i][j];
+                LB += L[i][k] * Bq[k][j];
+                BL += Bq[i][k] * L[j][k];
+            }
+            RB[c] = aq * (Bdq[i][j] + conv - LB - BL) + (1.0 - aq) * (Bq[i][j] - (i == j ? 1.0 : 0.0));
+        }
+#pragma unroll
+        for (int ia = 0; ia < NN; ++ia) {
+            double u = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) u += vq[j] * dN[ia][j];
+            U[ia][q] = u;
+            W[ia][q] = w * (shape_at<D>(q, ia) + tau * u);
+#pragma unroll
+            for (int c = 0; c < NVv; ++c) re[ia][c] += W[ia][q] * RB[c];
+        }
+        AQ[q] = aq;
+    }
+    // LE[c][cc] = (L E_cc + E_cc L^T)_{ij(c)} with E_cc the symmetric unit direction
+    double LE[NVv][NVv];
+#pragma unroll
+    for (int cc = 0; cc < NVv; ++cc) {
+        int k, l;
+        vpair<D>(cc, k, l);
+#pragma unroll
+        for (int c = 0; c < NVv; ++c) {
+            int i, j;
+            vpair<D>(c, i, j);
+            // (L E)_ij = L_ik' E_k'j with E_kl = E_lk = 1
+            double s = 0.0;
+            if (l == j) s += L[i][k];
+            if (k == j && k != l) s += L[i][l];
+            if (l == i) s += L[j][k];
+            if (k == i && k != l) s += L[j][l];
+            LE[c][cc] = s;
+        }
+    }
+    const int32_t *ep = a.bepos + be * NN * NN;
+#pragma unroll
+    for (int ia = 0; ia < NN; ++ia) {
+        const int64_t l = a.bconn[be * NN + ia];
+#pragma unroll
+        for (int c = 0; c < NVv; ++c) unsafeAtomicAdd(a.R + l * NVv + c, re[ia][c]);
+#pragma unroll
+        for (int ib = 0; ib < NN; ++ib) {
+            double S1 = 0.0, S2 = 0.0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const double Nb = shape_at<D>(q, ib);
+                S1 += W[ia][q] * (AQ[q] * (ct * Nb + al * U[ib][q]) + (1.0 - AQ[q]) * al * Nb);
+                S2 += W[ia][q] * AQ[q] * Nb;
+            }
+            S2 *= al;
+            double *blk = a.J + (int64_t)ep[ia * NN + ib] * NVv * NVv;
+#pragma unroll
+            for (int c = 0; c < NVv; ++c)
+#pragma unroll
+                for (int cc = 0; cc < NVv; ++cc) {
+                    const double val = (c == cc ? S1 : 0.0) - S2 * LE[c][cc];
+                    if (val != 0.0) unsafeAtomicAdd(blk + c * NVv + cc, val);
+                }
+        }
+    }
+}
+
+// Rows of nodes that keep their value: residual 0, unit row.
+__global__ __launch_bounds__(256) void k_band_bc(int64_t n, int bs, const uint8_t *fre, const int32_t *rowptr,
+                                                 const int32_t *col, double *R, double *J)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n || fre[r]) return;
+    for (int i = 0; i < bs; ++i) {
+        R[r * bs + i] = 0.0;
+        for (int k = rowptr[r]; k < rowptr[r + 1]; ++k)
+            for (int j = 0; j < bs; ++j) J[((int64_t)k * bs + i) * bs + j] = (col[k] == r && i == j) ? 1.0 : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_negate(double *x, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = -x[i];
+}
+
+// x[node[r]*bs + c] += dx[r*bs + c]
+__global__ __launch_bounds__(256) void k_band_update(int64_t n, int bs, const int32_t *node, const double *dx,
+                                                     double *x)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * bs) return;
+    const int64_t r = t / bs;
+    const int c = (int)(t - r * bs);
+    x[(int64_t)node[r] * bs + c] += dx[t];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- host side --
+
+template <typename TI>
+static eft_status scan_compact(eft_ctx *ctx, const TI *in, int64_t n, int32_t *out, int32_t *idx, int32_t *map,
+                               int64_t *count)
+{
+    const int nb = (int)std::max<int64_t>(1, (n + TILE - 1) / TILE);
+    if (ctx->scan_cap < nb + 1) {
+        if (ctx->scan_tmp) (void)hipFree(ctx->scan_tmp);
+        ctx->scan_cap = 0;
+        if (hipMalloc(&ctx->scan_tmp, sizeof(int32_t) * (nb + 1)) != hipSuccess) {
+            ctx->err = "out of device memory (scan)";
+            return EFT_ENOMEM;
+        }
+        ctx->scan_cap = nb + 1;
+    }
+    int32_t *bsum = ctx->scan_tmp;
+    hipLaunchKernelGGL(k_scan_count<TI>, dim3(nb), dim3(SB), 0, ctx->stream, in, n, bsum);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SB), 0, ctx->stream, bsum, nb, bsum + nb);
+    hipLaunchKernelGGL(k_scan_write<TI>, dim3(nb), dim3(SB), 0, ctx->stream, in, n, bsum, out, idx, map);
+    EFT_HIP(hipGetLastError());
+    int32_t tot = 0;
+    EFT_HIP(hipMemcpyAsync(ctx->hscal, bsum + nb, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    EFT_HIP(hipStreamSynchronize(ctx->stream));
+    tot = *(int32_t *)ctx->hscal;
+    *count = tot;
+    return EFT_OK;
+}
+
+static eft_status grow(eft_ctx *ctx, void **p, int64_t bytes, int64_t *cap_bytes)
+{
+    if (bytes <= *cap_bytes) return EFT_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap_bytes = 0;
+    const int64_t want = std::max<int64_t>(bytes + bytes / 4, 1024);
+    if (hipMalloc(p, want) != hipSuccess) {
+        ctx->err = "out of device memory (band)";
+        return EFT_ENOMEM;
+    }
+    *cap_bytes = want;
+    return EFT_OK;
+}
+
+eft_status eft_reserve_band_sys(eft_ctx *ctx, int64_t n, int64_t nnz)
+{
+    const int nv = std::max(ctx->nv, 1);
+    if (n > ctx->bcap_n) {
+        if (ctx->bR) (void)hipFree(ctx->bR);
+        if (ctx->bX) (void)hipFree(ctx->bX);
+        if (ctx->tnum) (void)hipFree(ctx->tnum);
+        if (ctx->tden) (void)hipFree(ctx->tden);
+        const int64_t c = n + n / 4 + 64;
+        if (hipMalloc(&ctx->bR, sizeof(double) * c * nv) != hipSuccess ||
+            hipMalloc(&ctx->bX, sizeof(double) * c * nv) != hipSuccess ||
+            hipMalloc(&ctx->tnum, sizeof(double) * c) != hipSuccess ||
+            hipMalloc(&ctx->tden, sizeof(double) * c) != hipSuccess) {
+            ctx->err = "out of device memory (band system)";
+            return EFT_ENOMEM;
+        }
+        ctx->bcap_n = c;
+    }
+    if (nnz > ctx->bcap_nnz) {
+        if (ctx->bval) (void)hipFree(ctx->bval);
+        const int64_t c = nnz + nnz / 4 + 64;
+        if (hipMalloc(&ctx->bval, sizeof(double) * c * nv * nv) != hipSuccess) {
+            ctx->err = "out of device memory (band matrix)";
+            return EFT_ENOMEM;
+        }
+        ctx->bcap_nnz = c;
+    }
+    return EFT_OK;
+}
+
+eft_status eft_bands_build_dev(eft_ctx *ctx, const double *phi_n)
+{
+    const int D = ctx->dim, NN = D + 1;
+    const int64_t N = ctx->N, E = ctx->E;
+    const int64_t ncell = (int64_t)ctx->ng[0] * ctx->ng[1] * ctx->ng[2];
+    ctx->band.resize(ctx->n_ind);
+    const double thr = 1.0 - ctx->par.band_flat;
+    int64_t max_n = 0, max_nnz = 0;
+    for (int k = 0; k < ctx->n_ind; ++k) {
+        const double *phi = phi_n + (int64_t)k * N;
+        Band &B = ctx->band[k];
+        EFT_TRY(eft_fill_u8(ctx, ctx->seed, ncell));
+        EFT_TRY(eft_fill_u8(ctx, ctx->nin, N));
+        EFT_TRY(eft_fill_u8(ctx, ctx->nout, N));
+        if (D == 2)
+            hipLaunchKernelGGL(k_seed<2>, dim3(eft_grid(E, 256)), dim3(256), 0, ctx->stream, E, ctx->conn, ctx->cell_of,
+                               phi, thr, ctx->seed);
+        else
+            hipLaunchKernelGGL(k_seed<3>, dim3(eft_grid(E, 256)), dim3(256), 0, ctx->stream, E, ctx->conn, ctx->cell_of,
+                               phi, thr, ctx->seed);
+        hipLaunchKernelGGL(k_dilate, dim3(eft_grid(ncell, 256)), dim3(256), 0, ctx->stream, ctx->ng[0], ctx->ng[1],
+                           ctx->ng[2], ctx->par.band_halo, ctx->seed, ctx->active);
+        if (D == 2)
+            hipLaunchKernelGGL(k_mark<2>, dim3(eft_grid(E, 256)), dim3(256), 0, ctx->stream, E, ctx->conn, ctx->cell_of,
+                               ctx->active, ctx->ein, ctx->nin, ctx->nout);
+        else
+            hipLaunchKernelGGL(k_mark<3>, dim3(eft_grid(E, 256)), dim3(256), 0, ctx->stream, E, ctx->conn, ctx->cell_of,
+                               ctx->active, ctx->ein, ctx->nin, ctx->nout);
+        EFT_HIP(hipGetLastError());
+        // element list
+        int64_t ne = 0, n = 0;
+        int64_t *caps = B.cap;
+        // element and node lists are sized for the worst case (all of the mesh)
+        EFT_TRY(grow(ctx, (void **)&B.elem, sizeof(int32_t) * E, &caps[0]));
+        EFT_TRY(scan_compact<uint8_t>(ctx, ctx->ein, E, nullptr, B.elem, nullptr, &ne));
+        EFT_TRY(grow(ctx, (void **)&B.node, sizeof(int32_t) * N, &caps[1]));
+        EFT_TRY(scan_compact<uint8_t>(ctx, ctx->nin, N, nullptr, B.node, ctx->g2b, &n));
+        B.n = n;
+        B.ne = ne;
+        EFT_TRY(grow(ctx, (void **)&B.fre, std::max<int64_t>(n, 1), &caps[2]));
+        EFT_TRY(grow(ctx, (void **)&B.rowptr, sizeof(int32_t) * (n + 1), &caps[3]));
+        EFT_TRY(grow(ctx, (void **)&B.diag, sizeof(int32_t) * std::max<int64_t>(n, 1), &caps[4]));
+        if (n > 0) {
+            hipLaunchKernelGGL(k_band_free, dim3(eft_grid(n, 256)), dim3(256), 0, ctx->stream, n, B.node, ctx->nout,
+                               B.fre);
+            hipLaunchKernelGGL(k_band_rowcount, dim3(eft_grid(n, 256)), dim3(256), 0, ctx->stream, n, B.node,
+                               ctx->J.rowptr, ctx->J.col, ctx->g2b, B.rowptr);
+            EFT_HIP(hipGetLastError());
+        }
+        int64_t nnz = 0;
+        // exclusive scan of the row counts, in place (rowptr[n] = total)
+        EFT_TRY(scan_compact<int32_t>(ctx, B.rowptr, n, B.rowptr, nullptr, nullptr, &nnz));
+        int32_t nnz32 = (int32_t)nnz;
+        EFT_HIP(hipMemcpyAsync(B.rowptr + n, &nnz32, sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+        EFT_HIP(hipStreamSynchronize(ctx->stream));
+        B.nnz = nnz;
+        EFT_TRY(grow(ctx, (void **)&B.col, sizeof(int32_t) * std::max<int64_t>(nnz, 1), &caps[5]));
+        EFT_TRY(grow(ctx, (void **)&B.epos, sizeof(int32_t) * std::max<int64_t>(ne, 1) * NN * NN, &caps[6]));
+        EFT_TRY(grow(ctx, (void **)&B.bconn_, sizeof(int32_t) * std::max<int64_t>(ne, 1) * NN, &caps[7]));
+        if (n > 0) {
+            hipLaunchKernelGGL(k_band_fill, dim3(eft_grid(n, 256)), dim3(256), 0, ctx->stream, n, B.node, ctx->J.rowptr,
+                               ctx->J.col, ctx->g2b, B.rowptr, B.col, B.diag, ctx->gpos2b);
+        }
+        if (ne > 0) {
+            if (D == 2)
+                hipLaunchKernelGGL(k_band_epos<2>, dim3(eft_grid(ne, 256)), dim3(256), 0, ctx->stream, ne, B.elem,
+                                   ctx->conn, ctx->epos, ctx->gpos2b, ctx->g2b, B.epos, B.bconn_);
+            else
+                hipLaunchKernelGGL(k_band_epos<3>, dim3(eft_grid(ne, 256)), dim3(256), 0, ctx->stream, ne, B.elem,
+                                   ctx->conn, ctx->epos, ctx->gpos2b, ctx->g2b, B.epos, B.bconn_);
+        }
+        EFT_HIP(hipGetLastError());
+        max_n = std::max(max_n, n);
+        max_nnz = std::max(max_nnz, nnz);
+    }
+    EFT_TRY(eft_reserve_band_sys(ctx, max_n, max_nnz));
+    EFT_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->bands_valid = true;
+    return EFT_OK;
+}
+
+static eft_status band_solve(eft_ctx *ctx, const Band &B, int bs, double *x_global, double *ratio_num,
+                             eft_solve_info *si)
+{
+    // residual -> rhs
+    const int64_t nd = B.n * bs;
+    hipLaunchKernelGGL(k_band_bc, dim3(eft_grid(B.n, 256)), dim3(256), 0, ctx->stream, B.n, bs, B.fre, B.rowptr, B.col,
+                       ctx->bR, ctx->bval);
+    hipLaunchKernelGGL(k_negate, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, ctx->bR, nd);
+    EFT_HIP(hipGetLastError());
+    eft_matrix A;
+    A.bs = bs;
+    A.n = B.n;
+    A.nnzb = B.nnz;
+    A.rowptr = B.rowptr;
+    A.col = B.col;
+    A.diag = B.diag;
+    A.val = ctx->bval;
+    eft_status st = eft_fgmres_dev(ctx, &A, ctx->bR, ctx->bX, si);
+    if (st != EFT_OK && st != EFT_ENOTCONV) return st;
+    hipLaunchKernelGGL(k_band_update, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, B.n, bs, B.node, ctx->bX,
+                       x_global);
+    EFT_HIP(hipGetLastError());
+    EFT_TRY(eft_norm2(ctx, ctx->bX, nd, ratio_num));
+    return st;
+}
+
+eft_status eft_transport_dev(eft_ctx *ctx, const eft_state *lvl, eft_iterate *it, eft_transport_info *info)
+{
+    if (!ctx->bands_valid) {
+        ctx->err = "eft_bands_build must run before the transport";
+        return EFT_EINVAL;
+    }
+    const int D = ctx->dim, NN = D + 1, nv = ctx->nv;
+    const int64_t N = ctx->N;
+    GA ga = ga_of(ctx->par.rho_inf, ctx->par.dt);
+    eft_transport_info inf{};
+    inf.n_ind = ctx->n_ind;
+    inf.n_solid = ctx->n_s;
+    eft_status worst = EFT_OK;
+    EFT_TRY(eft_props(ctx, lvl, it));
+    for (int k = 0; k < ctx->n_ind; ++k) {
+        const Band &B = ctx->band[k];
+        inf.band_nodes[k] = B.n;
+        inf.band_elems[k] = B.ne;
+        const double *lphi = lvl->phi + (int64_t)k * N, *iphi = it->phi + (int64_t)k * N;
+        double gb[2] = {0.0, 0.0};
+        if (B.ne > 0) {
+            // mobility
+            EFT_TRY(eft_fill(ctx, ctx->tnum, B.n, 0.0));
+            EFT_TRY(eft_fill(ctx, ctx->tden, B.n, 0.0));
+            if (D == 2)
+                hipLaunchKernelGGL(k_mob_elem<2>, dim3(eft_grid(B.ne, 256)), dim3(256), 0, ctx->stream, B.ne, B.elem,
+                                   B.bconn_, ctx->conn, ctx->xyz, ctx->va, lphi, iphi, ga.alpha, ctx->tnum, ctx->tden);
+            else
+                hipLaunchKernelGGL(k_mob_elem<3>, dim3(eft_grid(B.ne, 256)), dim3(256), 0, ctx->stream, B.ne, B.elem,
+                                   B.bconn_, ctx->conn, ctx->xyz, ctx->va, lphi, iphi, ga.alpha, ctx->tnum, ctx->tden);
+            const int nbn = eft_grid(B.n, 256);
+            hipLaunchKernelGGL(k_mob_node, dim3(nbn), dim3(256), 0, ctx->stream, B.n, B.node, lphi, iphi, ga.alpha,
+                               ctx->par.di_cut, ctx->tnum, ctx->tden, ctx->red);
+            hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, ctx->stream, ctx->red, nbn, ctx->dscal);
+            // beta
+            const int nbe = eft_grid(B.ne, 256);
+            if (D == 2)
+                hipLaunchKernelGGL(k_beta_elem<2>, dim3(nbe), dim3(256), 0, ctx->stream, B.ne, B.elem, ctx->conn,
+                                   ctx->xyz, lphi, iphi, ga.alpha, ctx->red + 2 * (int64_t)nbn);
+            else
+                hipLaunchKernelGGL(k_beta_elem<3>, dim3(nbe), dim3(256), 0, ctx->stream, B.ne, B.elem, ctx->conn,
+                                   ctx->xyz, lphi, iphi, ga.alpha, ctx->red + 2 * (int64_t)nbn);
+            hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, ctx->stream, ctx->red + 2 * (int64_t)nbn, nbe,
+                               ctx->dscal + 2);
+            EFT_HIP(hipGetLastError());
+            EFT_HIP(hipMemcpyAsync(ctx->hscal, ctx->dscal, sizeof(double) * 4, hipMemcpyDeviceToHost, ctx->stream));
+            EFT_HIP(hipStreamSynchronize(ctx->stream));
+            const double S = ctx->hscal[0], cnt = ctx->hscal[1], bnum = ctx->hscal[2], bden = ctx->hscal[3];
+            gb[0] = cnt > 0.0 ? sqrt(S / cnt) / ctx->par.eta : 0.0;
+            gb[1] = bden > 0.0 ? bnum / bden : 0.0;
+        }
+        inf.gamma[k] = gb[0];
+        inf.beta[k] = gb[1];
+        if (B.n == 0) continue;
+        ctx->hscal[8] = gb[0];
+        ctx->hscal[9] = gb[1];
+        EFT_HIP(hipMemcpyAsync(ctx->dscal + 4, ctx->hscal + 8, sizeof(double) * 2, hipMemcpyHostToDevice, ctx->stream));
+        EFT_TRY(eft_fill(ctx, ctx->bR, B.n, 0.0));
+        EFT_TRY(eft_fill(ctx, ctx->bval, B.nnz, 0.0));
+        TrArgs a;
+        a.ne = B.ne;
+        a.elem = B.elem;
+        a.bconn = B.bconn_;
+        a.bepos = B.epos;
+        a.conn = ctx->conn;
+        a.xyz = ctx->xyz;
+        a.va = ctx->va;
+        a.lx = lphi;
+        a.ldx = lvl->phidot + (int64_t)k * N;
+        a.ix = iphi;
+        a.alpha = ga.alpha;
+        a.alpha_m = ga.alpha_m;
+        a.vs = ga.vs;
+        a.dt = ga.dt;
+        a.ct = ga.ct;
+        a.R = ctx->bR;
+        a.J = ctx->bval;
+        if (B.ne > 0) {
+            if (D == 2)
+                hipLaunchKernelGGL(k_ac_elem<2>, dim3(eft_grid(B.ne, 128)), dim3(128), 0, ctx->stream, a, ctx->par.eps,
+                                   ctx->dscal + 4);
+            else
+                hipLaunchKernelGGL(k_ac_elem<3>, dim3(eft_grid(B.ne, 128)), dim3(128), 0, ctx->stream, a, ctx->par.eps,
+                                   ctx->dscal + 4);
+            EFT_HIP(hipGetLastError());
+        }
+        eft_solve_info si{};
+        double dn = 0.0;
+        eft_status st = band_solve(ctx, B, 1, it->phi + (int64_t)k * N, &dn, &si);
+        if (st != EFT_OK && st != EFT_ENOTCONV) return st;
+        if (st == EFT_ENOTCONV) worst = st;
+        inf.lin_iters[k] = si.iters;
+        double xn;
+        EFT_TRY(eft_norm2(ctx, it->phi + (int64_t)k * N, N, &xn));
+        inf.ratio[k] = dn / std::max(xn, 1e-300);
+    }
+    if (ctx->n_s > 0) {
+        EFT_TRY(eft_props(ctx, lvl, it));   // solid fractions from the new phi
+        for (int s = 0; s < ctx->n_s; ++s) {
+            const Band &B = ctx->band[ctx->solid_ind[s]];
+            if (B.n == 0) continue;
+            EFT_TRY(eft_fill(ctx, ctx->bR, B.n * nv, 0.0));
+            EFT_TRY(eft_fill(ctx, ctx->bval, B.nnz * nv * nv, 0.0));
+            TrArgs a;
+            a.ne = B.ne;
+            a.elem = B.elem;
+            a.bconn = B.bconn_;
+            a.bepos = B.epos;
+            a.conn = ctx->conn;
+            a.xyz = ctx->xyz;
+            a.va = ctx->va;
+            a.lx = lvl->B + (int64_t)s * N * nv;
+            a.ldx = lvl->Bdot + (int64_t)s * N * nv;
+            a.ix = it->B + (int64_t)s * N * nv;
+            a.alpha = ga.alpha;
+            a.alpha_m = ga.alpha_m;
+            a.vs = ga.vs;
+            a.dt = ga.dt;
+            a.ct = ga.ct;
+            a.R = ctx->bR;
+            a.J = ctx->bval;
+            if (B.ne > 0) {
+                if (D == 2)
+                    hipLaunchKernelGGL(k_b_elem<2>, dim3(eft_grid(B.ne, 128)), dim3(128), 0, ctx->stream, a,
+                                       ctx->as + (int64_t)s * N);
+                else
+                    hipLaunchKernelGGL(k_b_elem<3>, dim3(eft_grid(B.ne, 128)), dim3(128), 0, ctx->stream, a,
+                                       ctx->as + (int64_t)s * N);
+                EFT_HIP(hipGetLastError());
+            }
+            eft_solve_info si{};
+            double dn = 0.0;
+            eft_status st = band_solve(ctx, B, nv, it->B + (int64_t)s * N * nv, &dn, &si);
+            if (st != EFT_OK && st != EFT_ENOTCONV) return st;
+            if (st == EFT_ENOTCONV) worst = st;
+            inf.lin_iters[ctx->n_ind + s] = si.iters;
+            double xn;
+            EFT_TRY(eft_norm2(ctx, it->B + (int64_t)s * N * nv, N * nv, &xn));
+            inf.ratio[ctx->n_ind + s] = dn / std::max(xn, 1e-300);
+        }
+    }
+    (void)NN;
+    if (info) *info = inf;
+    return worst;
+}

@@ -1,0 +1,290 @@
+"""Python binding of include/eft.h (ctypes; argument marshalling only).
+
+Device memory and streams come from PyTorch (ROCm build): every field or
+vector is a contiguous float64 torch tensor on the GPU; the HIP library does
+all of the work.  Importing this module loads ``_libeft.so`` and raises if it
+is missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_libeft.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN, ENAN, EBAND_OVERFLOW, EUNSUPPORTED = range(9)
+STATUS = {0: "EFT_OK", 1: "EFT_EINVAL", 2: "EFT_ENOMEM", 3: "EFT_EDEVICE", 4: "EFT_ENOTCONV",
+          5: "EFT_EBREAKDOWN", 6: "EFT_ENAN", 7: "EFT_EBAND_OVERFLOW", 8: "EFT_EUNSUPPORTED"}
+
+vp_ = C.c_void_p
+dp = C.POINTER(C.c_double)
+
+
+class Mesh(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_nodes", C.c_int64), ("n_elems", C.c_int64),
+                ("xyz", vp_), ("conn", vp_), ("n_dir", C.c_int64), ("dir_node", vp_), ("dir_mask", vp_),
+                ("dir_val", vp_), ("grid", C.c_int32 * 3)]
+
+
+class Phase(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("transported", C.c_int32), ("rho", C.c_double), ("mu", C.c_double),
+                ("mu_L", C.c_double)]
+
+
+class Materials(C.Structure):
+    _fields_ = [("n_phases", C.c_int32), ("phase", vp_), ("g", C.c_double * 3)]
+
+
+class Params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("rho_inf", C.c_double), ("eps", C.c_double), ("eta", C.c_double),
+                ("C_I", C.c_double), ("di_cut", C.c_double), ("nl_rtol", C.c_double),
+                ("nl_max", C.c_int32), ("nl_fixed", C.c_int32), ("lin_rtol", C.c_double),
+                ("restart", C.c_int32), ("lin_maxit", C.c_int32), ("precond", C.c_int32),
+                ("precision", C.c_int32), ("band_flat", C.c_double), ("band_cell", C.c_int32),
+                ("band_halo", C.c_int32)]
+
+
+class State(C.Structure):
+    _fields_ = [("vp", vp_), ("vdot", vp_), ("phi", vp_), ("phidot", vp_), ("B", vp_), ("Bdot", vp_),
+                ("t", C.c_double), ("step", C.c_int64)]
+
+
+class Iterate(C.Structure):
+    _fields_ = [("vp", vp_), ("phi", vp_), ("B", vp_)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
+                ("fallback_used", C.c_int32), ("rel_res0", C.c_double), ("rel_res", C.c_double)]
+
+
+class TransportInfo(C.Structure):
+    _fields_ = [("n_ind", C.c_int32), ("n_solid", C.c_int32), ("gamma", C.c_double * 64),
+                ("beta", C.c_double * 64), ("band_nodes", C.c_int64 * 64), ("band_elems", C.c_int64 * 64),
+                ("lin_iters", C.c_int32 * 128), ("ratio", C.c_double * 128)]
+
+
+class StepInfo(C.Structure):
+    _fields_ = [("nl_iters", C.c_int32), ("converged", C.c_int32), ("lin_iters_total", C.c_int32),
+                ("n_blocks", C.c_int32), ("block_ratio", C.c_double * 129), ("t_assemble", C.c_double),
+                ("t_solve", C.c_double), ("t_transport", C.c_double)]
+
+
+EXPORTS = ["eft_create", "eft_destroy", "eft_last_error", "eft_set_params", "eft_ns_matrix", "eft_matrix_shape",
+           "eft_matrix_export", "eft_assemble", "eft_spmv", "eft_fgmres", "eft_bands_build", "eft_band_export",
+           "eft_transport_solids", "eft_step"]
+
+_lib = None
+
+
+def load():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is missing: run `python -m paper_2402_10348_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    for name in EXPORTS:
+        getattr(L, name).restype = C.c_int
+    L.eft_last_error.restype = C.c_char_p
+    L.eft_create.argtypes = [C.POINTER(Mesh), C.POINTER(Materials), C.POINTER(Params), vp_, C.POINTER(vp_)]
+    _lib = L
+    return L
+
+
+class EftError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def params_struct(p, **over):
+    vals = dict(dt=p.dt, rho_inf=p.rho_inf, eps=p.eps, eta=p.eta, C_I=p.C_I, di_cut=p.di_cut, nl_rtol=p.nl_rtol,
+                nl_max=p.nl_max, nl_fixed=p.nl_fixed, lin_rtol=p.lin_rtol, restart=p.restart,
+                lin_maxit=p.lin_maxit, precond=p.precond, precision=p.precision, band_flat=p.band_flat,
+                band_cell=p.band_cell, band_halo=p.band_halo)
+    vals.update(over)
+    P = Params()
+    for k, v in vals.items():
+        setattr(P, k, v)
+    return P
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One eft_ctx: a mesh, materials and parameters on the current GPU."""
+
+    def __init__(self, prob, stream=None, **overrides):
+        import torch
+        self.torch = torch
+        self.L = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the HIP library needs a device")
+        self.dev = torch.device("cuda", torch.cuda.current_device())
+        self.dim = prob.dim
+        self.N = prob.n_nodes
+        self.E = prob.n_elems
+        self.bs = self.dim + 1
+        self.nv = 6 if self.dim == 3 else 3
+        self.n_ind = prob.n_ind
+        self.n_s = prob.n_solid
+        self._keep = dict(
+            xyz=np.ascontiguousarray(prob.xyz, dtype=np.float64),
+            conn=np.ascontiguousarray(prob.conn, dtype=np.int32),
+            dir_node=np.ascontiguousarray(prob.dir_node, dtype=np.int32),
+            dir_mask=np.ascontiguousarray(prob.dir_mask, dtype=np.uint8),
+            dir_val=np.ascontiguousarray(prob.dir_val, dtype=np.float64))
+        k = self._keep
+        M = Mesh()
+        M.dim, M.n_nodes, M.n_elems = self.dim, self.N, self.E
+        M.xyz, M.conn = k["xyz"].ctypes.data, k["conn"].ctypes.data
+        M.n_dir = k["dir_node"].shape[0]
+        M.dir_node, M.dir_mask, M.dir_val = k["dir_node"].ctypes.data, k["dir_mask"].ctypes.data, k["dir_val"].ctypes.data
+        for i in range(3):
+            M.grid[i] = int(prob.grid[i])
+        ph = (Phase * len(prob.phases))()
+        for i, p in enumerate(prob.phases):
+            ph[i].kind, ph[i].transported, ph[i].rho, ph[i].mu, ph[i].mu_L = p.kind, p.transported, p.rho, p.mu, p.mu_L
+        mat = Materials()
+        mat.n_phases = len(prob.phases)
+        mat.phase = C.cast(ph, vp_)
+        for i in range(3):
+            mat.g[i] = float(prob.g[i])
+        self.params = params_struct(prob.params, **overrides)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.dev).cuda_stream
+        self.stream = stream
+        self.ctx = vp_()
+        st = self.L.eft_create(C.byref(M), C.byref(mat), C.byref(self.params), vp_(stream), C.byref(self.ctx))
+        if st != OK:
+            msg = self.L.eft_last_error(self.ctx).decode() if self.ctx else ""
+            if self.ctx:
+                self.L.eft_destroy(self.ctx)
+            self.ctx = None
+            raise EftError(st, msg)
+        self.J = vp_()
+        self._check(self.L.eft_ns_matrix(self.ctx, C.byref(self.J)))
+
+    # -------------------------------------------------------------- helpers
+    def _check(self, st, allow=()):
+        if st != OK and st not in allow:
+            raise EftError(st, self.L.eft_last_error(self.ctx).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.torch.cuda.synchronize()
+            self.L.eft_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tensor(self, a, dtype=None):
+        t = self.torch
+        return t.as_tensor(np.ascontiguousarray(a), device=self.dev, dtype=dtype or t.float64).contiguous()
+
+    def device_state(self, st):
+        """Dict of numpy arrays (vp, vdot, phi, phidot, B, Bdot) -> device tensors."""
+        return {k: self.tensor(st[k]) for k in ("vp", "vdot", "phi", "phidot", "B", "Bdot") if k in st}
+
+    def _state(self, d, t=0.0, step=0):
+        S = State()
+        for k in ("vp", "vdot", "phi", "phidot", "B", "Bdot"):
+            v = d.get(k)
+            setattr(S, k, _ptr(v) if v is not None and v.numel() else None)
+        S.t, S.step = t, step
+        return S
+
+    def _iterate(self, d):
+        I = Iterate()
+        for k in ("vp", "phi", "B"):
+            v = d.get(k)
+            setattr(I, k, _ptr(v) if v is not None and v.numel() else None)
+        return I
+
+    def set_params(self, **over):
+        p = self.params
+        for k, v in over.items():
+            setattr(p, k, v)
+        self._check(self.L.eft_set_params(self.ctx, C.byref(p)))
+
+    # ------------------------------------------------------------- the ABI
+    def assemble(self, lvl, it, with_J=True):
+        """Residual [N][d+1] (and the context Jacobian) at the iterate."""
+        R = self.torch.empty((self.N, self.bs), dtype=self.torch.float64, device=self.dev)
+        S, I = self._state(lvl), self._iterate(it)
+        self._check(self.L.eft_assemble(self.ctx, C.byref(S), C.byref(I), _ptr(R), self.J if with_J else None))
+        return R
+
+    def matrix_shape(self):
+        n, nnz, bs = C.c_int64(), C.c_int64(), C.c_int32()
+        self._check(self.L.eft_matrix_shape(self.J, C.byref(n), C.byref(nnz), C.byref(bs)))
+        return n.value, nnz.value, bs.value
+
+    def matrix(self):
+        """(rowptr, col, val[nnzb][bs][bs]) of the momentum Jacobian as device tensors."""
+        t = self.torch
+        n, nnz, bs = self.matrix_shape()
+        rowptr = t.empty(n + 1, dtype=t.int32, device=self.dev)
+        col = t.empty(nnz, dtype=t.int32, device=self.dev)
+        val = t.empty((nnz, bs, bs), dtype=t.float64, device=self.dev)
+        self._check(self.L.eft_matrix_export(self.ctx, self.J, _ptr(rowptr), _ptr(col), _ptr(val)))
+        return rowptr, col, val
+
+    def spmv(self, x, y=None):
+        if y is None:
+            y = self.torch.empty_like(x)
+        self._check(self.L.eft_spmv(self.ctx, self.J, _ptr(x), _ptr(y)))
+        return y
+
+    def fgmres(self, b, x=None):
+        if x is None:
+            x = self.torch.empty_like(b)
+        info = SolveInfo()
+        st = self._check(self.L.eft_fgmres(self.ctx, self.J, _ptr(b), _ptr(x), C.byref(info)), allow=(ENOTCONV,))
+        return x, dict(status=st, iters=info.iters, restarts=info.restarts, converged=info.converged,
+                       rel_res=info.rel_res)
+
+    def bands_build(self, lvl):
+        self._check(self.L.eft_bands_build(self.ctx, C.byref(self._state(lvl))))
+
+    def band_export(self, k):
+        t = self.torch
+        be = t.empty(self.E, dtype=t.uint8, device=self.dev)
+        fr = t.empty(self.N, dtype=t.uint8, device=self.dev)
+        self._check(self.L.eft_band_export(self.ctx, k, _ptr(be), _ptr(fr)))
+        return be, fr
+
+    def transport(self, lvl, it):
+        info = TransportInfo()
+        S, I = self._state(lvl), self._iterate(it)
+        st = self._check(self.L.eft_transport_solids(self.ctx, C.byref(S), C.byref(I), C.byref(info)),
+                         allow=(ENOTCONV,))
+        ni, ns = info.n_ind, info.n_solid
+        return dict(status=st, gamma=list(info.gamma[:ni]), beta=list(info.beta[:ni]),
+                    band_nodes=list(info.band_nodes[:ni]), band_elems=list(info.band_elems[:ni]),
+                    lin_iters=list(info.lin_iters[:ni + ns]), ratio=list(info.ratio[:ni + ns]))
+
+    def step(self, st, t=0.0, step=0, dt=0.0):
+        """Advance the device state dict in place by one time step."""
+        S = self._state(st, t, step)
+        info = StepInfo()
+        self._check(self.L.eft_step(self.ctx, C.byref(S), C.c_double(dt), C.byref(info)))
+        nb = info.n_blocks
+        return dict(nl_iters=info.nl_iters, converged=info.converged, lin_iters_total=info.lin_iters_total,
+                    block_ratio=list(info.block_ratio[:nb]), t_assemble=info.t_assemble, t_solve=info.t_solve,
+                    t_transport=info.t_transport, t=S.t, step=S.step)

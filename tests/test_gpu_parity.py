@@ -1,0 +1,290 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Every case prints its name, seed and size before touching the GPU.  FP64
+tolerances: assembly, SpMV, band and element-level quantities 1e-12 relative
+(only the summation order differs); fields after Krylov solves 1e-10
+relative with both sides solving to lin_rtol = 1e-13.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2402_10348_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def ctx_for(prob, **over):
+    from paper_2402_10348_amd.eft import Context
+    return Context(prob, **over)
+
+
+def relmax(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def relnorm(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+CASES = {
+    "disk2d_32": lambda: W.cavity_disk_2d(n=32),
+    "sphere3d_6": lambda: W.cavity_sphere_3d(n=6),
+    "falling3d_5": lambda: W.falling_sphere_3d(n=5),
+}
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("seed", [1, 2])
+def test_assembly_matches_oracle(torch_cuda, name, seed):
+    prob = CASES[name]()
+    say(f"[assembly] case={name} seed={seed} N={prob.n_nodes} E={prob.n_elems}")
+    lvl, it = W.perturbed_state(prob, seed=seed)
+    c = O.Case(prob)
+    R0, J0 = c.ns_assemble(lvl, it)
+    rowptr0, col0 = c.graph()
+    ctx = ctx_for(prob)
+    R = ctx.assemble(ctx.device_state(lvl), ctx.device_state(it))
+    rowptr, col, val = ctx.matrix()
+    assert np.array_equal(to_np(rowptr), rowptr0) and np.array_equal(to_np(col), col0)
+    assert relmax(to_np(R), R0) < 1e-12
+    assert relmax(to_np(val), J0) < 1e-12
+    # residual only (no Jacobian) gives the same residual
+    R2 = ctx.assemble(ctx.device_state(lvl), ctx.device_state(it), with_J=False)
+    assert relmax(to_np(R2), R0) < 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["disk2d_32", "sphere3d_6"])
+def test_spmv_and_fgmres_match_oracle(torch_cuda, name):
+    torch = torch_cuda
+    prob = CASES[name]()
+    say(f"[spmv/fgmres] case={name} N={prob.n_nodes}")
+    lvl, it = W.perturbed_state(prob, seed=3)
+    c = O.Case(prob)
+    R0, J0 = c.ns_assemble(lvl, it)
+    ctx = ctx_for(prob, lin_rtol=1e-12, restart=200, lin_maxit=20000)
+    R = ctx.assemble(ctx.device_state(lvl), ctx.device_state(it))
+    rng = np.random.Generator(np.random.PCG64(4))
+    x = rng.standard_normal(R0.shape)
+    y = ctx.spmv(ctx.tensor(x))
+    assert relmax(to_np(y), c.spmv(J0, x)) < 1e-12
+    b = -R
+    xs, info = ctx.fgmres(b)
+    say(f"  fgmres iters={info['iters']} rel_res={info['rel_res']:.3e}")
+    assert info["converged"] == 1 and info["rel_res"] <= 1e-12
+    # true residual with the GPU SpMV
+    r = b - ctx.spmv(xs)
+    assert float(torch.linalg.norm(r) / torch.linalg.norm(b)) <= 1.0001e-12
+    import scipy.sparse as sp
+    rowptr, col = c.graph()
+    bs = prob.dim + 1
+    A = sp.bsr_matrix((J0, col, rowptr), shape=(c.N * bs, c.N * bs)).tocsc()
+    import scipy.sparse.linalg as spl
+    xd = spl.spsolve(A, -R0.ravel()).reshape(R0.shape)
+    assert relnorm(to_np(xs), xd) < 1e-8
+    ctx.close()
+
+
+def test_fgmres_zero_rhs_and_restart_edge(torch_cuda):
+    torch = torch_cuda
+    prob = W.cavity_disk_2d(n=8)
+    say("[fgmres edge] zero rhs, restart 1")
+    lvl, it = W.perturbed_state(prob, seed=5)
+    ctx = ctx_for(prob, restart=1, lin_rtol=1e-6, lin_maxit=200)
+    R = ctx.assemble(ctx.device_state(lvl), ctx.device_state(it))
+    x, info = ctx.fgmres(torch.zeros_like(R))
+    assert info["converged"] == 1 and float(x.abs().max()) == 0.0
+    x, info = ctx.fgmres(-R)
+    assert info["iters"] <= 200
+    if info["converged"]:
+        assert info["rel_res"] <= 1e-6
+    else:
+        assert info["status"] == 4
+    ctx.close()
+
+
+@pytest.mark.parametrize("dim,n,cell,halo", [(2, 48, 4, 1), (2, 40, 3, 2), (3, 16, 2, 1), (3, 12, 4, 1)])
+def test_band_matches_oracle(torch_cuda, dim, n, cell, halo):
+    prob = W.cavity_disk_2d(n=n) if dim == 2 else W.cavity_sphere_3d(n=n)
+    say(f"[band] dim={dim} n={n} cell={cell} halo={halo}")
+    c = O.Case(prob, band_cell=cell, band_halo=halo)
+    be0, fr0 = c.band(prob.phi[0])
+    ctx = ctx_for(prob, band_cell=cell, band_halo=halo)
+    st = ctx.device_state(prob.state_copy())
+    ctx.bands_build(st)
+    be, fr = ctx.band_export(0)
+    assert np.array_equal(to_np(be), be0) and np.array_equal(to_np(fr), fr0)
+    ctx.close()
+
+
+def test_band_empty_and_full(torch_cuda):
+    """phi = +-1 everywhere: no band, transport leaves phi and B alone;
+    band_flat = 2: every cell is a seed and the whole mesh is the band."""
+    prob = W.cavity_disk_2d(n=16)
+    say("[band edge] empty / full")
+    prob.phi[:] = -1.0
+    ctx = ctx_for(prob)
+    st = ctx.device_state(prob.state_copy())
+    ctx.bands_build(st)
+    be, fr = ctx.band_export(0)
+    assert int(be.sum()) == 0 and int(fr.sum()) == 0
+    it = {k: st[k].clone() for k in ("vp", "phi", "B")}
+    info = ctx.transport(st, it)
+    assert info["band_nodes"] == [0]
+    assert np.array_equal(to_np(it["phi"]), prob.phi) and np.array_equal(to_np(it["B"]), prob.B)
+    ctx.close()
+    ctx = ctx_for(prob, band_flat=2.0)
+    ctx.bands_build(st)
+    be, fr = ctx.band_export(0)
+    assert int(be.sum()) == prob.n_elems and int(fr.sum()) == prob.n_nodes
+    ctx.close()
+
+
+def oracle_transport(c, prob, lvl, it, rtol):
+    """One transport pass with the oracle's functions (same order as the
+    partitioned iteration): every indicator, then every solid."""
+    dim, N = prob.dim, prob.n_nodes
+    dt, ri = prob.params.dt, prob.params.rho_inf
+    va, _ = O.level_values(ri, dt, lvl["vp"][:, :dim], lvl["vdot"], it["vp"][:, :dim])
+    phi = it["phi"].copy()
+    B = it["B"].copy()
+    gam, bet = [], []
+    n_ind = phi.shape[0]
+    bands = [c.band(lvl["phi"][k]) for k in range(n_ind)]
+    for k in range(n_ind):
+        fa, fd = O.level_values(ri, dt, lvl["phi"][k], lvl["phidot"][k], phi[k])
+        g = c.mobility(va, fa)
+        b = c.beta(fa, bands[k][0])
+        gam.append(g)
+        bet.append(b)
+        R, J = c.ac_assemble(va, fa, fd, g, b, bands[k][0], bands[k][1])
+        dx, info = c.fgmres(J, -R, rtol=rtol, restart=200, maxit=20000)
+        phi[k] += dx
+    fa_all, _ = O.level_values(ri, dt, lvl["phi"], lvl["phidot"], phi)
+    af, _, _ = c.nodal_properties(fa_all)
+    s = 0
+    for ph_i, ph in enumerate(prob.phases):
+        if ph.kind != 1:
+            continue
+        k = sum(1 for p in prob.phases[:ph_i] if p.transported)
+        Ba, Bd = O.level_values(ri, dt, lvl["B"][s], lvl["Bdot"][s], B[s])
+        R, J = c.b_assemble(va, af[ph_i], Ba, Bd, bands[k][0], bands[k][1])
+        dx, info = c.fgmres(J, -R.ravel(), rtol=rtol, restart=200, maxit=20000)
+        B[s] += dx.reshape(B[s].shape)
+        s += 1
+    return phi, B, gam, bet
+
+
+@pytest.mark.parametrize("name", ["disk2d_32", "sphere3d_6", "falling3d_5"])
+def test_transport_matches_oracle(torch_cuda, name):
+    prob = CASES[name]()
+    say(f"[transport] case={name}")
+    lvl, it = W.perturbed_state(prob, seed=11, amp_phi=0.02, amp_B=0.02)
+    # keep phi^n flat far from the interfaces so that the band is a strict subset
+    lvl["phi"] = np.where(np.abs(prob.phi) >= 1.0, prob.phi, lvl["phi"])
+    it["phi"] = np.where(np.abs(prob.phi) >= 1.0, prob.phi, it["phi"])
+    c = O.Case(prob, lin_rtol=1e-13, restart=200)
+    phi0, B0, g0, b0 = oracle_transport(c, prob, lvl, it, 1e-13)
+    ctx = ctx_for(prob, lin_rtol=1e-13, restart=200, lin_maxit=20000)
+    L = ctx.device_state(lvl)
+    I = {k: ctx.tensor(it[k]) for k in ("vp", "phi", "B")}
+    ctx.bands_build(L)
+    info = ctx.transport(L, I)
+    say(f"  gamma={info['gamma']} beta={info['beta']} band_nodes={info['band_nodes']} iters={info['lin_iters']}")
+    for k in range(prob.n_ind):
+        assert abs(info["gamma"][k] - g0[k]) <= 1e-12 * max(abs(g0[k]), 1e-300)
+        assert abs(info["beta"][k] - b0[k]) <= 1e-12 * max(abs(b0[k]), 1e-14)
+    assert relnorm(to_np(I["phi"]) - lvl["phi"], phi0 - lvl["phi"]) < 1e-9
+    assert relnorm(to_np(I["phi"]), phi0) < 1e-12
+    assert relnorm(to_np(I["B"]), B0) < 1e-12
+    ctx.close()
+
+
+def _run_steps(prob, nsteps, **over):
+    c = O.Case(prob, **over)
+    st0 = prob.state_copy()
+    infos0 = [c.step(st0) for _ in range(nsteps)]
+    ctx = ctx_for(prob, **over)
+    st = ctx.device_state(prob.state_copy())
+    infos = [ctx.step(st) for _ in range(nsteps)]
+    return st0, infos0, {k: to_np(v) for k, v in st.items()}, infos
+
+
+@pytest.mark.parametrize("name,nsteps,over", [
+    ("disk2d_32", 2, dict(nl_fixed=3)),
+    ("sphere3d_6", 2, dict(nl_fixed=0, nl_max=6)),
+    ("falling3d_5", 1, dict(nl_fixed=2)),
+])
+def test_step_matches_oracle(torch_cuda, name, nsteps, over):
+    prob = CASES[name]()
+    say(f"[step] case={name} steps={nsteps} {over}")
+    over = dict(over, lin_rtol=1e-13, restart=200, lin_maxit=40000)
+    st0, infos0, st, infos = _run_steps(prob, nsteps, **over)
+    say(f"  oracle nl={[i['nl_iters'] for i in infos0]} gpu nl={[i['nl_iters'] for i in infos]}")
+    assert [i["nl_iters"] for i in infos] == [i["nl_iters"] for i in infos0]
+    for k in ("vp", "vdot", "phi", "phidot", "B", "Bdot"):
+        if st0[k].size == 0:
+            continue
+        e = relnorm(st[k], st0[k])
+        say(f"  {k}: rel {e:.2e}")
+        assert e < 1e-10, k
+
+
+def test_rest_state_on_gpu(torch_cuda):
+    prob = W.cavity_sphere_3d(n=6)
+    say("[rest] sphere3d_6 no lid")
+    prob.dir_val[:] = 0.0
+    prob.vp[:] = 0.0
+    ctx = ctx_for(prob, nl_fixed=2)
+    st = ctx.device_state(prob.state_copy())
+    ctx.step(st)
+    assert float(st["vp"].abs().max()) < 1e-13
+    assert float((st["phi"] - ctx.tensor(prob.phi)).abs().max()) < 1e-13
+    ctx.close()
+
+
+def test_full_size_cavity_step(torch_cuda):
+    """The 64^3 cavity (1.57M tets) in the bench configuration: one step, the
+    residual at the new state against the oracle's assembly at full size, and
+    the final linear solve's true residual."""
+    torch = torch_cuda
+    prob = W.cavity_sphere_3d(n=64)
+    say(f"[full size] 64^3 N={prob.n_nodes} E={prob.n_elems}")
+    ctx = ctx_for(prob)
+    st = ctx.device_state(prob.state_copy())
+    info = ctx.step(st)
+    say(f"  nl={info['nl_iters']} lin={info['lin_iters_total']} ratios={info['block_ratio']}")
+    assert info["converged"] == 1
+    hst = {k: to_np(v) for k, v in st.items()}
+    lvl = prob.state_copy()
+    R = ctx.assemble(ctx.device_state(lvl), {k: st[k] for k in ("vp", "phi", "B")})
+    c = O.Case(prob)
+    R0, J0 = c.ns_assemble(lvl, hst)
+    assert relmax(to_np(R), R0) < 1e-11
+    x, si = ctx.fgmres(-R)
+    r = -R - ctx.spmv(x)
+    assert float(torch.linalg.norm(r) / torch.linalg.norm(R)) <= prob.params.lin_rtol * 1.0001
+    ctx.close()
