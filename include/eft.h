@@ -187,6 +187,18 @@ eft_status eft_bands_build(eft_ctx *ctx, const eft_state *level_n);
  * bytes, DEVICE buffers (test hook). */
 eft_status eft_band_export(eft_ctx *ctx, int32_t k, uint8_t *band_elem, uint8_t *free_node);
 
+/* Assemble one band system at the iterate and copy it out (test hook):
+ * kind 0 = Allen-Cahn system of indicator `index` (with its gamma and beta),
+ * kind 1 = B system of solid `index`.  Rows of kept nodes are unit rows with
+ * zero residual.  Call once with null buffers to get n (band nodes) and nnz
+ * (pattern size); then node [n] (global ids), rowptr [n+1], col [nnz]
+ * (band-local ids), R [n][bs] and J [nnz][bs][bs] (bs = 1 or nv) are DEVICE
+ * buffers; gamma_beta [2] is a HOST buffer (kind 0).  Requires
+ * eft_bands_build. */
+eft_status eft_band_system(eft_ctx *ctx, const eft_state *level_n, const eft_iterate *it, int32_t kind,
+                           int32_t index, int64_t *n, int64_t *nnz, int32_t *node, int32_t *rowptr, int32_t *col,
+                           double *R, double *J, double *gamma_beta);
+
 /* (c) One transport pass of the partitioned iteration (eqs. LS_AC, LS_MC):
  * for every indicator the mobility gamma (eq. tdm-num, RMS over |phi| <= 0.9),
  * beta, one Allen-Cahn solve on its band; then for every solid one B solve on

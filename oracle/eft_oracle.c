@@ -955,12 +955,17 @@ static void ac_element(int dim, const galpha *ga, double eps, double gamma, doub
             vg += vq[i] * gphi[i];
             for (int j = 0; j < dim; ++j) vGv += vq[i] * G[i][j] * vq[j];
         }
+        /* READING: sqrt(F) has a kink at |phi| = 1 where the derivative of
+         * |phi^2 - 1| is undefined; within 1e-12 of it the sign is taken as 0
+         * (midpoint of the one-sided derivatives), so that flat regions, whose
+         * quadrature values equal +-1 only up to rounding, get one definite s_hat. */
         double f2m1 = fq * fq - 1.0;
-        double sgn = (f2m1 > 0.0) - (f2m1 < 0.0);
+        double sgn = fabs(f2m1) <= 1e-12 ? 0.0 : (double)((f2m1 > 0.0) - (f2m1 < 0.0));
         double react = Fprime(fq) - beta * sqrtF(fq);
         double s_hat = 3.0 * fq * fq - 1.0 - beta * fq * sgn;
         double fr2m1 = fr * fr - 1.0;
-        double s_ref = 3.0 * fr * fr - 1.0 - beta * fr * ((fr2m1 > 0.0) - (fr2m1 < 0.0));
+        double sref_sgn = fabs(fr2m1) <= 1e-12 ? 0.0 : (double)((fr2m1 > 0.0) - (fr2m1 < 0.0));
+        double s_ref = 3.0 * fr * fr - 1.0 - beta * fr * sref_sgn;
         double Rphi = fdq + vg + gamma * react;
         double tau = 1.0 / sqrt(4.0 / (ga->dt * ga->dt) + vGv + 9.0 * (gamma * k_hat) * (gamma * k_hat) * GG
                                 + (gamma * s_ref) * (gamma * s_ref));

@@ -505,6 +505,16 @@ eft_status eft_band_export(eft_ctx *ctx, int32_t k, uint8_t *band_elem, uint8_t 
     return EFT_OK;
 }
 
+eft_status eft_band_system(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, int32_t kind, int32_t index,
+                           int64_t *n, int64_t *nnz, int32_t *node, int32_t *rowptr, int32_t *col, double *R,
+                           double *J, double *gamma_beta)
+{
+    if (!ctx || !lvl || !it) return EFT_EINVAL;
+    if (ctx->n_ind == 0 || !lvl->phi || !lvl->phidot || !it->phi || (kind == 1 && (!lvl->B || !lvl->Bdot || !it->B)))
+        return EFT_EINVAL;
+    return eft_band_system_dev(ctx, lvl, it, kind, index, n, nnz, node, rowptr, col, R, J, gamma_beta);
+}
+
 eft_status eft_transport_solids(eft_ctx *ctx, const eft_state *lvl, eft_iterate *it, eft_transport_info *info)
 {
     if (!ctx || !lvl || !it) return EFT_EINVAL;

@@ -177,6 +177,9 @@ eft_status eft_dot_dev(eft_ctx *ctx, const double *x, const double *y, int64_t n
 // k_transport.hip
 eft_status eft_bands_build_dev(eft_ctx *ctx, const double *phi_n);
 eft_status eft_transport_dev(eft_ctx *ctx, const eft_state *lvl, eft_iterate *it, eft_transport_info *info);
+eft_status eft_band_system_dev(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, int kind, int index,
+                               int64_t *n, int64_t *nnz, int32_t *node, int32_t *rowptr, int32_t *col, double *R,
+                               double *J, double *gamma_beta);
 
 // abi helpers
 eft_status eft_reserve_band_sys(eft_ctx *ctx, int64_t n, int64_t nnz);

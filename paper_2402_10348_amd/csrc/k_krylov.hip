@@ -28,7 +28,8 @@ struct Small {
     __host__ __device__ int64_t sc() const { return h2() + m + 2; }            // [8] scalars
     __host__ __device__ int64_t size() const { return sc() + 8; }
 };
-// scalars: sc+0 ||w'||^2 (after pass 1), sc+1 ||w''||^2, sc+2 tol_abs, sc+3 beta
+// scalars: sc+0 ||w'||^2 (after pass 1), sc+1 ||w''||^2, sc+2 tol_abs, sc+3 beta,
+// sc+4 H[j+1][j] before the rotation
 // flags: 0 active, 1 columns done in this cycle, 2 breakdown, 3 second-pass gate
 
 // dots of w with V[0..nvec-1] (and w.w as index nvec when with_ww): partials
@@ -130,6 +131,7 @@ __global__ void k_givens(double *small, int m, int j, int32_t *flag)
     }
     const double a = H[(int64_t)j * m + j], b = H[(int64_t)(j + 1) * m + j];
     const double hn = b;
+    small[L.sc() + 4] = hn;   // ||w||, kept for the normalization of v_{j+1}
     const double den = sqrt(a * a + b * b);
     cs[j] = den == 0.0 ? 1.0 : a / den;
     sn[j] = den == 0.0 ? 0.0 : b / den;
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(RB) void k_normalize(const double *__restrict__ w, 
 {
     if (flag[0] == 0) return;
     Small L{m};
-    const double inv = 1.0 / small[L.H() + (int64_t)(j + 1) * m + j];
+    const double inv = 1.0 / small[L.sc() + 4];
     for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < nd; i += (int64_t)gridDim.x * RB) v[i] = w[i] * inv;
 }
 

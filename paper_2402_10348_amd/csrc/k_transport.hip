@@ -412,8 +412,10 @@ __global__ __launch_bounds__(128) void k_ac_elem(TrArgs a, double eps, const dou
 #pragma unroll
             for (int j = 0; j < D; ++j) vGv += vq[i] * G[i][j] * vq[j];
         }
+        // derivative of |phi^2 - 1| at the kink |phi| = 1 taken as 0 within
+        // 1e-12 (flat regions interpolate to +-1 only up to rounding)
         const double f2m1 = fq * fq - 1.0;
-        const double sgn = (f2m1 > 0.0) - (f2m1 < 0.0);
+        const double sgn = fabs(f2m1) <= 1e-12 ? 0.0 : (f2m1 > 0.0 ? 1.0 : -1.0);
         const double react = fq * fq * fq - fq - beta * 0.5 * fabs(f2m1);
         const double sh = 3.0 * fq * fq - 1.0 - beta * fq * sgn;
         const double Rphi = fdq + vg + gamma * react;
@@ -802,10 +804,8 @@ eft_status eft_bands_build_dev(eft_ctx *ctx, const double *phi_n)
 static eft_status band_solve(eft_ctx *ctx, const Band &B, int bs, double *x_global, double *ratio_num,
                              eft_solve_info *si)
 {
-    // residual -> rhs
+    // the band system (unit rows already in place) -> rhs = -R
     const int64_t nd = B.n * bs;
-    hipLaunchKernelGGL(k_band_bc, dim3(eft_grid(B.n, 256)), dim3(256), 0, ctx->stream, B.n, bs, B.fre, B.rowptr, B.col,
-                       ctx->bR, ctx->bval);
     hipLaunchKernelGGL(k_negate, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, ctx->bR, nd);
     EFT_HIP(hipGetLastError());
     eft_matrix A;
@@ -825,15 +825,132 @@ static eft_status band_solve(eft_ctx *ctx, const Band &B, int bs, double *x_glob
     return st;
 }
 
+// gamma and beta of indicator k at the iterate (host values; also left in
+// dscal[4..5] for the element kernel)
+static eft_status mobility_beta(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, int k, double gb[2])
+{
+    const int D = ctx->dim;
+    const int64_t N = ctx->N;
+    const Band &B = ctx->band[k];
+    GA ga = ga_of(ctx->par.rho_inf, ctx->par.dt);
+    const double *lphi = lvl->phi + (int64_t)k * N, *iphi = it->phi + (int64_t)k * N;
+    gb[0] = gb[1] = 0.0;
+    if (B.ne > 0) {
+        EFT_TRY(eft_fill(ctx, ctx->tnum, B.n, 0.0));
+        EFT_TRY(eft_fill(ctx, ctx->tden, B.n, 0.0));
+        if (D == 2)
+            hipLaunchKernelGGL(k_mob_elem<2>, dim3(eft_grid(B.ne, 256)), dim3(256), 0, ctx->stream, B.ne, B.elem,
+                               B.bconn_, ctx->conn, ctx->xyz, ctx->va, lphi, iphi, ga.alpha, ctx->tnum, ctx->tden);
+        else
+            hipLaunchKernelGGL(k_mob_elem<3>, dim3(eft_grid(B.ne, 256)), dim3(256), 0, ctx->stream, B.ne, B.elem,
+                               B.bconn_, ctx->conn, ctx->xyz, ctx->va, lphi, iphi, ga.alpha, ctx->tnum, ctx->tden);
+        const int nbn = eft_grid(B.n, 256);
+        hipLaunchKernelGGL(k_mob_node, dim3(nbn), dim3(256), 0, ctx->stream, B.n, B.node, lphi, iphi, ga.alpha,
+                           ctx->par.di_cut, ctx->tnum, ctx->tden, ctx->red);
+        hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, ctx->stream, ctx->red, nbn, ctx->dscal);
+        const int nbe = eft_grid(B.ne, 256);
+        if (D == 2)
+            hipLaunchKernelGGL(k_beta_elem<2>, dim3(nbe), dim3(256), 0, ctx->stream, B.ne, B.elem, ctx->conn, ctx->xyz,
+                               lphi, iphi, ga.alpha, ctx->red + 2 * (int64_t)nbn);
+        else
+            hipLaunchKernelGGL(k_beta_elem<3>, dim3(nbe), dim3(256), 0, ctx->stream, B.ne, B.elem, ctx->conn, ctx->xyz,
+                               lphi, iphi, ga.alpha, ctx->red + 2 * (int64_t)nbn);
+        hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, ctx->stream, ctx->red + 2 * (int64_t)nbn, nbe, ctx->dscal + 2);
+        EFT_HIP(hipGetLastError());
+        EFT_HIP(hipMemcpyAsync(ctx->hscal, ctx->dscal, sizeof(double) * 4, hipMemcpyDeviceToHost, ctx->stream));
+        EFT_HIP(hipStreamSynchronize(ctx->stream));
+        const double S = ctx->hscal[0], cnt = ctx->hscal[1], bnum = ctx->hscal[2], bden = ctx->hscal[3];
+        gb[0] = cnt > 0.0 ? sqrt(S / cnt) / ctx->par.eta : 0.0;
+        gb[1] = bden > 0.0 ? bnum / bden : 0.0;
+    }
+    ctx->hscal[8] = gb[0];
+    ctx->hscal[9] = gb[1];
+    EFT_HIP(hipMemcpyAsync(ctx->dscal + 4, ctx->hscal + 8, sizeof(double) * 2, hipMemcpyHostToDevice, ctx->stream));
+    EFT_HIP(hipStreamSynchronize(ctx->stream));
+    return EFT_OK;
+}
+
+static TrArgs tr_args(eft_ctx *ctx, const Band &B, const double *lx, const double *ldx, const double *ix)
+{
+    GA ga = ga_of(ctx->par.rho_inf, ctx->par.dt);
+    TrArgs a;
+    a.ne = B.ne;
+    a.elem = B.elem;
+    a.bconn = B.bconn_;
+    a.bepos = B.epos;
+    a.conn = ctx->conn;
+    a.xyz = ctx->xyz;
+    a.va = ctx->va;
+    a.lx = lx;
+    a.ldx = ldx;
+    a.ix = ix;
+    a.alpha = ga.alpha;
+    a.alpha_m = ga.alpha_m;
+    a.vs = ga.vs;
+    a.dt = ga.dt;
+    a.ct = ga.ct;
+    a.R = ctx->bR;
+    a.J = ctx->bval;
+    return a;
+}
+
+// Allen-Cahn system of indicator k on its band (unit rows for kept nodes);
+// gamma, beta must be in dscal[4..5]
+static eft_status assemble_ac(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, int k)
+{
+    const int64_t N = ctx->N;
+    const Band &B = ctx->band[k];
+    EFT_TRY(eft_fill(ctx, ctx->bR, B.n, 0.0));
+    EFT_TRY(eft_fill(ctx, ctx->bval, B.nnz, 0.0));
+    TrArgs a = tr_args(ctx, B, lvl->phi + (int64_t)k * N, lvl->phidot + (int64_t)k * N, it->phi + (int64_t)k * N);
+    if (B.ne > 0) {
+        if (ctx->dim == 2)
+            hipLaunchKernelGGL(k_ac_elem<2>, dim3(eft_grid(B.ne, 128)), dim3(128), 0, ctx->stream, a, ctx->par.eps,
+                               ctx->dscal + 4);
+        else
+            hipLaunchKernelGGL(k_ac_elem<3>, dim3(eft_grid(B.ne, 128)), dim3(128), 0, ctx->stream, a, ctx->par.eps,
+                               ctx->dscal + 4);
+    }
+    if (B.n > 0)
+        hipLaunchKernelGGL(k_band_bc, dim3(eft_grid(B.n, 256)), dim3(256), 0, ctx->stream, B.n, 1, B.fre, B.rowptr,
+                           B.col, ctx->bR, ctx->bval);
+    EFT_HIP(hipGetLastError());
+    return EFT_OK;
+}
+
+// B system of solid s on the band of its indicator; the solid fractions in
+// ctx->as must come from the current order parameters
+static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, int s)
+{
+    const int64_t N = ctx->N;
+    const int nv = ctx->nv;
+    const Band &B = ctx->band[ctx->solid_ind[s]];
+    EFT_TRY(eft_fill(ctx, ctx->bR, B.n * nv, 0.0));
+    EFT_TRY(eft_fill(ctx, ctx->bval, B.nnz * nv * nv, 0.0));
+    TrArgs a = tr_args(ctx, B, lvl->B + (int64_t)s * N * nv, lvl->Bdot + (int64_t)s * N * nv, it->B + (int64_t)s * N * nv);
+    if (B.ne > 0) {
+        if (ctx->dim == 2)
+            hipLaunchKernelGGL(k_b_elem<2>, dim3(eft_grid(B.ne, 128)), dim3(128), 0, ctx->stream, a,
+                               ctx->as + (int64_t)s * N);
+        else
+            hipLaunchKernelGGL(k_b_elem<3>, dim3(eft_grid(B.ne, 128)), dim3(128), 0, ctx->stream, a,
+                               ctx->as + (int64_t)s * N);
+    }
+    if (B.n > 0)
+        hipLaunchKernelGGL(k_band_bc, dim3(eft_grid(B.n, 256)), dim3(256), 0, ctx->stream, B.n, nv, B.fre, B.rowptr,
+                           B.col, ctx->bR, ctx->bval);
+    EFT_HIP(hipGetLastError());
+    return EFT_OK;
+}
+
 eft_status eft_transport_dev(eft_ctx *ctx, const eft_state *lvl, eft_iterate *it, eft_transport_info *info)
 {
     if (!ctx->bands_valid) {
         ctx->err = "eft_bands_build must run before the transport";
         return EFT_EINVAL;
     }
-    const int D = ctx->dim, NN = D + 1, nv = ctx->nv;
+    const int nv = ctx->nv;
     const int64_t N = ctx->N;
-    GA ga = ga_of(ctx->par.rho_inf, ctx->par.dt);
     eft_transport_info inf{};
     inf.n_ind = ctx->n_ind;
     inf.n_solid = ctx->n_s;
@@ -843,74 +960,12 @@ eft_status eft_transport_dev(eft_ctx *ctx, const eft_state *lvl, eft_iterate *it
         const Band &B = ctx->band[k];
         inf.band_nodes[k] = B.n;
         inf.band_elems[k] = B.ne;
-        const double *lphi = lvl->phi + (int64_t)k * N, *iphi = it->phi + (int64_t)k * N;
-        double gb[2] = {0.0, 0.0};
-        if (B.ne > 0) {
-            // mobility
-            EFT_TRY(eft_fill(ctx, ctx->tnum, B.n, 0.0));
-            EFT_TRY(eft_fill(ctx, ctx->tden, B.n, 0.0));
-            if (D == 2)
-                hipLaunchKernelGGL(k_mob_elem<2>, dim3(eft_grid(B.ne, 256)), dim3(256), 0, ctx->stream, B.ne, B.elem,
-                                   B.bconn_, ctx->conn, ctx->xyz, ctx->va, lphi, iphi, ga.alpha, ctx->tnum, ctx->tden);
-            else
-                hipLaunchKernelGGL(k_mob_elem<3>, dim3(eft_grid(B.ne, 256)), dim3(256), 0, ctx->stream, B.ne, B.elem,
-                                   B.bconn_, ctx->conn, ctx->xyz, ctx->va, lphi, iphi, ga.alpha, ctx->tnum, ctx->tden);
-            const int nbn = eft_grid(B.n, 256);
-            hipLaunchKernelGGL(k_mob_node, dim3(nbn), dim3(256), 0, ctx->stream, B.n, B.node, lphi, iphi, ga.alpha,
-                               ctx->par.di_cut, ctx->tnum, ctx->tden, ctx->red);
-            hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, ctx->stream, ctx->red, nbn, ctx->dscal);
-            // beta
-            const int nbe = eft_grid(B.ne, 256);
-            if (D == 2)
-                hipLaunchKernelGGL(k_beta_elem<2>, dim3(nbe), dim3(256), 0, ctx->stream, B.ne, B.elem, ctx->conn,
-                                   ctx->xyz, lphi, iphi, ga.alpha, ctx->red + 2 * (int64_t)nbn);
-            else
-                hipLaunchKernelGGL(k_beta_elem<3>, dim3(nbe), dim3(256), 0, ctx->stream, B.ne, B.elem, ctx->conn,
-                                   ctx->xyz, lphi, iphi, ga.alpha, ctx->red + 2 * (int64_t)nbn);
-            hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, ctx->stream, ctx->red + 2 * (int64_t)nbn, nbe,
-                               ctx->dscal + 2);
-            EFT_HIP(hipGetLastError());
-            EFT_HIP(hipMemcpyAsync(ctx->hscal, ctx->dscal, sizeof(double) * 4, hipMemcpyDeviceToHost, ctx->stream));
-            EFT_HIP(hipStreamSynchronize(ctx->stream));
-            const double S = ctx->hscal[0], cnt = ctx->hscal[1], bnum = ctx->hscal[2], bden = ctx->hscal[3];
-            gb[0] = cnt > 0.0 ? sqrt(S / cnt) / ctx->par.eta : 0.0;
-            gb[1] = bden > 0.0 ? bnum / bden : 0.0;
-        }
+        double gb[2];
+        EFT_TRY(mobility_beta(ctx, lvl, it, k, gb));
         inf.gamma[k] = gb[0];
         inf.beta[k] = gb[1];
         if (B.n == 0) continue;
-        ctx->hscal[8] = gb[0];
-        ctx->hscal[9] = gb[1];
-        EFT_HIP(hipMemcpyAsync(ctx->dscal + 4, ctx->hscal + 8, sizeof(double) * 2, hipMemcpyHostToDevice, ctx->stream));
-        EFT_TRY(eft_fill(ctx, ctx->bR, B.n, 0.0));
-        EFT_TRY(eft_fill(ctx, ctx->bval, B.nnz, 0.0));
-        TrArgs a;
-        a.ne = B.ne;
-        a.elem = B.elem;
-        a.bconn = B.bconn_;
-        a.bepos = B.epos;
-        a.conn = ctx->conn;
-        a.xyz = ctx->xyz;
-        a.va = ctx->va;
-        a.lx = lphi;
-        a.ldx = lvl->phidot + (int64_t)k * N;
-        a.ix = iphi;
-        a.alpha = ga.alpha;
-        a.alpha_m = ga.alpha_m;
-        a.vs = ga.vs;
-        a.dt = ga.dt;
-        a.ct = ga.ct;
-        a.R = ctx->bR;
-        a.J = ctx->bval;
-        if (B.ne > 0) {
-            if (D == 2)
-                hipLaunchKernelGGL(k_ac_elem<2>, dim3(eft_grid(B.ne, 128)), dim3(128), 0, ctx->stream, a, ctx->par.eps,
-                                   ctx->dscal + 4);
-            else
-                hipLaunchKernelGGL(k_ac_elem<3>, dim3(eft_grid(B.ne, 128)), dim3(128), 0, ctx->stream, a, ctx->par.eps,
-                                   ctx->dscal + 4);
-            EFT_HIP(hipGetLastError());
-        }
+        EFT_TRY(assemble_ac(ctx, lvl, it, k));
         eft_solve_info si{};
         double dn = 0.0;
         eft_status st = band_solve(ctx, B, 1, it->phi + (int64_t)k * N, &dn, &si);
@@ -926,35 +981,7 @@ eft_status eft_transport_dev(eft_ctx *ctx, const eft_state *lvl, eft_iterate *it
         for (int s = 0; s < ctx->n_s; ++s) {
             const Band &B = ctx->band[ctx->solid_ind[s]];
             if (B.n == 0) continue;
-            EFT_TRY(eft_fill(ctx, ctx->bR, B.n * nv, 0.0));
-            EFT_TRY(eft_fill(ctx, ctx->bval, B.nnz * nv * nv, 0.0));
-            TrArgs a;
-            a.ne = B.ne;
-            a.elem = B.elem;
-            a.bconn = B.bconn_;
-            a.bepos = B.epos;
-            a.conn = ctx->conn;
-            a.xyz = ctx->xyz;
-            a.va = ctx->va;
-            a.lx = lvl->B + (int64_t)s * N * nv;
-            a.ldx = lvl->Bdot + (int64_t)s * N * nv;
-            a.ix = it->B + (int64_t)s * N * nv;
-            a.alpha = ga.alpha;
-            a.alpha_m = ga.alpha_m;
-            a.vs = ga.vs;
-            a.dt = ga.dt;
-            a.ct = ga.ct;
-            a.R = ctx->bR;
-            a.J = ctx->bval;
-            if (B.ne > 0) {
-                if (D == 2)
-                    hipLaunchKernelGGL(k_b_elem<2>, dim3(eft_grid(B.ne, 128)), dim3(128), 0, ctx->stream, a,
-                                       ctx->as + (int64_t)s * N);
-                else
-                    hipLaunchKernelGGL(k_b_elem<3>, dim3(eft_grid(B.ne, 128)), dim3(128), 0, ctx->stream, a,
-                                       ctx->as + (int64_t)s * N);
-                EFT_HIP(hipGetLastError());
-            }
+            EFT_TRY(assemble_b(ctx, lvl, it, s));
             eft_solve_info si{};
             double dn = 0.0;
             eft_status st = band_solve(ctx, B, nv, it->B + (int64_t)s * N * nv, &dn, &si);
@@ -966,7 +993,46 @@ eft_status eft_transport_dev(eft_ctx *ctx, const eft_state *lvl, eft_iterate *it
             inf.ratio[ctx->n_ind + s] = dn / std::max(xn, 1e-300);
         }
     }
-    (void)NN;
     if (info) *info = inf;
     return worst;
+}
+
+// Assemble one band system at the iterate and copy it out (test hook).
+eft_status eft_band_system_dev(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, int kind, int index,
+                               int64_t *n, int64_t *nnz, int32_t *node, int32_t *rowptr, int32_t *col, double *R,
+                               double *J, double *gamma_beta)
+{
+    if (!ctx->bands_valid) {
+        ctx->err = "eft_bands_build must run first";
+        return EFT_EINVAL;
+    }
+    if ((kind == 0 && (index < 0 || index >= ctx->n_ind)) || (kind == 1 && (index < 0 || index >= ctx->n_s)) ||
+        (kind != 0 && kind != 1)) {
+        ctx->err = "band system: bad kind/index";
+        return EFT_EINVAL;
+    }
+    const int bs = kind == 0 ? 1 : ctx->nv;
+    const Band &B = ctx->band[kind == 0 ? index : ctx->solid_ind[index]];
+    if (n) *n = B.n;
+    if (nnz) *nnz = B.nnz;
+    if (!node && !rowptr && !col && !R && !J) return EFT_OK;
+    EFT_TRY(eft_props(ctx, lvl, it));
+    double gb[2] = {0.0, 0.0};
+    if (kind == 0) {
+        EFT_TRY(mobility_beta(ctx, lvl, it, index, gb));
+        EFT_TRY(assemble_ac(ctx, lvl, it, index));
+    } else {
+        EFT_TRY(assemble_b(ctx, lvl, it, index));
+    }
+    if (gamma_beta) {
+        gamma_beta[0] = gb[0];
+        gamma_beta[1] = gb[1];
+    }
+    if (node) EFT_HIP(hipMemcpyAsync(node, B.node, sizeof(int32_t) * B.n, hipMemcpyDeviceToDevice, ctx->stream));
+    if (rowptr) EFT_HIP(hipMemcpyAsync(rowptr, B.rowptr, sizeof(int32_t) * (B.n + 1), hipMemcpyDeviceToDevice, ctx->stream));
+    if (col) EFT_HIP(hipMemcpyAsync(col, B.col, sizeof(int32_t) * B.nnz, hipMemcpyDeviceToDevice, ctx->stream));
+    if (R) EFT_HIP(hipMemcpyAsync(R, ctx->bR, sizeof(double) * B.n * bs, hipMemcpyDeviceToDevice, ctx->stream));
+    if (J) EFT_HIP(hipMemcpyAsync(J, ctx->bval, sizeof(double) * B.nnz * bs * bs, hipMemcpyDeviceToDevice, ctx->stream));
+    EFT_HIP(hipStreamSynchronize(ctx->stream));
+    return EFT_OK;
 }

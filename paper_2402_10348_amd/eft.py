@@ -75,7 +75,7 @@ class StepInfo(C.Structure):
 
 EXPORTS = ["eft_create", "eft_destroy", "eft_last_error", "eft_set_params", "eft_ns_matrix", "eft_matrix_shape",
            "eft_matrix_export", "eft_assemble", "eft_spmv", "eft_fgmres", "eft_bands_build", "eft_band_export",
-           "eft_transport_solids", "eft_step"]
+           "eft_band_system", "eft_transport_solids", "eft_step"]
 
 _lib = None
 
@@ -268,6 +268,27 @@ class Context:
         fr = t.empty(self.N, dtype=t.uint8, device=self.dev)
         self._check(self.L.eft_band_export(self.ctx, k, _ptr(be), _ptr(fr)))
         return be, fr
+
+    def band_system(self, lvl, it, kind, index):
+        """Assembled band system (test hook): dict with node, rowptr, col, R, J
+        (device tensors) and gamma, beta for kind 0 (Allen-Cahn)."""
+        t = self.torch
+        S, I = self._state(lvl), self._iterate(it)
+        n, nnz = C.c_int64(), C.c_int64()
+        self._check(self.L.eft_band_system(self.ctx, C.byref(S), C.byref(I), kind, index, C.byref(n), C.byref(nnz),
+                                           None, None, None, None, None, None))
+        bs = 1 if kind == 0 else self.nv
+        n, nnz = n.value, nnz.value
+        node = t.empty(max(n, 1), dtype=t.int32, device=self.dev)
+        rowptr = t.empty(n + 1, dtype=t.int32, device=self.dev)
+        col = t.empty(max(nnz, 1), dtype=t.int32, device=self.dev)
+        R = t.empty((max(n, 1), bs), dtype=t.float64, device=self.dev)
+        J = t.empty((max(nnz, 1), bs, bs), dtype=t.float64, device=self.dev)
+        gb = (C.c_double * 2)()
+        self._check(self.L.eft_band_system(self.ctx, C.byref(S), C.byref(I), kind, index, C.byref(C.c_int64(n)),
+                                           C.byref(C.c_int64(nnz)), _ptr(node), _ptr(rowptr), _ptr(col), _ptr(R),
+                                           _ptr(J), gb))
+        return dict(node=node[:n], rowptr=rowptr, col=col[:nnz], R=R[:n], J=J[:nnz], gamma=gb[0], beta=gb[1])
 
     def transport(self, lvl, it):
         info = TransportInfo()
