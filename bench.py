@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Throughput of the hot path on one MI355X: converged time steps per second
+of the 3D lid-driven cavity with one elastic sphere (64^3 cells split into
+1,572,864 P1 tets, 274,625 nodes, 4 dof per node), every time step running
+the partitioned nonlinear iteration (momentum/mass assembly + FGMRES,
+Allen-Cahn and B band transport) to the stop rule ||dx||/||x|| < 5e-4 with
+linear solves to 1e-8 relative residual.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  The line carries
+  roofline      the BSR SpMV of the momentum Jacobian (the kernel that
+                dominates the step), timed with HIP events on the library's
+                stream: algorithmic bytes per launch / mean launch time, vs
+                the 8 TB/s HBM peak;
+  cpu_baseline  the FP64 CPU oracle timed on a bounded sample of the same
+                workload on the host cores (see --no-cpu).
+Inputs are seeded and synthetic and resident in device memory before the
+timed region starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=64, help="cells per axis of the cavity (64 = the benchmark)")
+    ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 FP32 Jacobian values")
+    ap.add_argument("--restart", type=int, default=50)
+    ap.add_argument("--precond", type=int, default=1, help="1 multigrid V-cycle, 0 point-block Jacobi")
+    ap.add_argument("--spmv-reps", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--traffic", type=str, default="", help="JSON file with measured HBM bytes per SpMV launch")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *a):
+    if not args.quiet:
+        print(*a, file=sys.stderr, flush=True)
+
+
+def spmv_bytes(n, nnzb, bs, val_bytes=8):
+    """Compulsory bytes of one BSR SpMV: values, block columns, row pointers,
+    x and y read/written once."""
+    return nnzb * bs * bs * val_bytes + nnzb * 4 + (n + 1) * 4 + 2 * n * bs * 8
+
+
+def cpu_baseline(prob, gpu_counts, args):
+    """Time the FP64 oracle on the host: one momentum/mass assembly and a
+    bounded number of FGMRES iterations on the same 64^3 system, then scale
+    to steps/s with the per-step operation counts of the GPU run (nonlinear
+    iterations and Krylov iterations per step).  The transport solves are
+    counted as Krylov iterations of the momentum system (an overestimate of
+    their cost, so the CPU figure is optimistic)."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2402_10348_amd import workloads as W
+    c = O.Case(prob)
+    lvl, it = W.perturbed_state(prob, seed=1)
+    t0 = time.perf_counter()
+    R, J = c.ns_assemble(lvl, it)
+    t_asm = time.perf_counter() - t0
+    iters = 20
+    t0 = time.perf_counter()
+    _, info = c.fgmres(J, -R.ravel(), rtol=1e-30, restart=iters, maxit=iters)
+    t_it = (time.perf_counter() - t0) / max(info["iters"], 1)
+    nl, lin = gpu_counts
+    t_step = nl * t_asm + lin * t_it
+    return dict(value=1.0 / t_step, unit="steps/s", cores=1, kind="oracle",
+                sample=f"64^3 cavity: one FP64 momentum/mass assembly ({t_asm:.2f} s) and {iters} FGMRES(m={iters}) "
+                       f"iterations ({t_it * 1e3:.1f} ms each) on one host core, scaled by the GPU run's "
+                       f"{nl:.1f} nonlinear and {lin:.0f} Krylov iterations per step")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the box has one MI355X)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2402_10348_amd import workloads as W
+    from paper_2402_10348_amd.eft import Context
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    prob = W.cavity_sphere_3d(n=args.n)
+    ctx = Context(prob, lin_rtol=1e-8, restart=args.restart, lin_maxit=20000, precision=args.precision,
+                  precond=args.precond)
+    st = ctx.device_state(prob.state_copy())
+    log(args, f"[bench] 64^3 cavity N={prob.n_nodes} E={prob.n_elems} precision={args.precision}")
+    t_sim, step_no = 0.0, 0
+    for w in range(args.warmup):
+        info = ctx.step(st, t=t_sim, step=step_no)
+        t_sim, step_no = info["t"], info["step"]
+        log(args, f"[bench] warmup {w}: nl={info['nl_iters']} lin={info['lin_iters_total']}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for k in range(args.steps):
+        info = ctx.step(st, t=t_sim, step=step_no)
+        t_sim, step_no = info["t"], info["step"]
+        infos.append(info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for i, info in enumerate(infos):
+        log(args, f"[bench] step {i}: nl={info['nl_iters']} lin={info['lin_iters_total']} conv={info['converged']} "
+                  f"asm={info['t_assemble']:.3f}s solve={info['t_solve']:.3f}s transport={info['t_transport']:.3f}s")
+    value = args.steps / elapsed
+    nl_mean = float(np.mean([i["nl_iters"] for i in infos]))
+    lin_mean = float(np.mean([i["lin_iters_total"] for i in infos]))
+
+    # dominant kernel: the momentum SpMV, timed with events on the library stream
+    n, nnzb, bs = ctx.matrix_shape()
+    x = torch.randn(n, bs, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        ctx.spmv(x, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.spmv_reps):
+        ctx.spmv(x, y)
+    e1.record(stream)
+    e1.synchronize()
+    t_spmv = e0.elapsed_time(e1) / 1e3 / args.spmv_reps
+    vb = 4 if args.precision == 1 else 8
+    alg = spmv_bytes(n, nnzb, bs, vb)
+    achieved = alg / t_spmv / 1e9
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                    kernel="k_spmv4 (BSR 4x4 SpMV of the momentum Jacobian)",
+                    bytes_per_launch=alg, mean_launch_s=t_spmv)
+    ctx.close()
+
+    cpu = None
+    if not args.no_cpu:
+        log(args, "[bench] timing the CPU oracle sample ...")
+        cpu = cpu_baseline(prob, (nl_mean, lin_mean), args)
+
+    line = {
+        "metric": "converged time steps/s (3D cavity, elastic sphere, FP64, FGMRES to 1e-8)",
+        "value": round(value, 4),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == 0 else "f64+f32J",
+        "data": "synthetic (seeded cavity, tanh sphere indicator, B = I, v = 0 at t = 0)",
+        "config": {"workload": f"3D lid-driven cavity with one elastic sphere, {args.n}^3 x 6 P1 tets",
+                   "n_nodes": prob.n_nodes, "n_elems": prob.n_elems, "dt": prob.params.dt,
+                   "lin_rtol": 1e-8, "restart": args.restart, "nl_rtol": prob.params.nl_rtol,
+                   "nl_iters_per_step": nl_mean, "krylov_iters_per_step": lin_mean,
+                   "parallelism": "1 GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -92,7 +92,11 @@ typedef struct {
     double lin_rtol;             /* FGMRES relative residual target                */
     int32_t restart;             /* FGMRES restart length m (<= 512)               */
     int32_t lin_maxit;           /* FGMRES iteration cap per solve                 */
-    int32_t precond;             /* 0 point-block Jacobi                           */
+    int32_t precond;             /* 0 point-block Jacobi; 1 geometric multigrid V-
+                                    cycle for the momentum/mass block when the mesh
+                                    is a structured Kuhn box with even cell counts
+                                    (point-block Jacobi otherwise, and always for
+                                    the band systems)                              */
     int32_t precision;           /* 0 FP64; 1 FP32 Jacobian values + FP64 rest     */
     double band_flat;            /* band seed: |phi^n| < 1 - band_flat             */
     int32_t band_cell;           /* mesh cells per grid cell and axis              */
@@ -122,7 +126,8 @@ typedef struct {
     int32_t iters;               /* Krylov iterations                              */
     int32_t restarts;            /* completed restart cycles                       */
     int32_t converged;           /* 1 if ||b - A x|| <= lin_rtol ||b||             */
-    int32_t fallback_used;       /* reserved (0)                                   */
+    int32_t fallback_used;       /* 1: multigrid requested but unavailable (point-
+                                    block Jacobi used)                             */
     double rel_res0;             /* ||b - A x0|| / ||b|| (x0 = 0: 1)               */
     double rel_res;              /* final true relative residual                   */
 } eft_solve_info;

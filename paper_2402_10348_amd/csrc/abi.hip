@@ -3,6 +3,7 @@
 // (predictor, partitioned nonlinear iterations NS -> order parameters -> B
 // tensors with the stop rule, corrector).
 #include <chrono>
+#include <climits>
 #include <cstring>
 #include <numeric>
 
@@ -100,6 +101,7 @@ void free_all(eft_ctx *ctx)
     fr(ctx->seed); fr(ctx->active); fr(ctx->nin); fr(ctx->nout); fr(ctx->ein); fr(ctx->g2b); fr(ctx->gpos2b);
     fr(ctx->scan_tmp); fr(ctx->bR); fr(ctx->bX); fr(ctx->bval); fr(ctx->tnum); fr(ctx->tden); fr(ctx->red);
     fr(ctx->dscal);
+    eft_mg_free(ctx);
     KrylovWs &K = ctx->kw;
     fr(K.V); fr(K.Z); fr(K.w); fr(K.r); fr(K.Dinv); fr(K.part); fr(K.small); fr(K.flag);
     if (ctx->hscal) (void)hipHostFree(ctx->hscal);
@@ -109,9 +111,9 @@ eft_status check_params(eft_ctx *ctx, const eft_params *p)
 {
     if (!(p->dt > 0.0) || !(p->eta > 0.0) || p->restart < 1 || p->restart > EFT_MAX_RESTART || p->lin_maxit < 1 ||
         p->band_cell < 1 || p->band_halo < 0 || p->nl_max < 1 || !(p->lin_rtol > 0.0) || p->rho_inf < 0.0 ||
-        p->rho_inf > 1.0 || (p->precision != 0 && p->precision != 1) || p->precond != 0) {
+        p->rho_inf > 1.0 || (p->precision != 0 && p->precision != 1) || (p->precond != 0 && p->precond != 1)) {
         ctx->err = "invalid eft_params (dt, eta, lin_rtol > 0; 1 <= restart <= 512; band_cell >= 1; "
-                   "0 <= rho_inf <= 1; precision 0/1; precond 0)";
+                   "0 <= rho_inf <= 1; precision 0/1; precond 0/1)";
         return EFT_EINVAL;
     }
     return EFT_OK;
@@ -127,6 +129,64 @@ eft_status alloc_jacobian_values(eft_ctx *ctx)
     ctx->J.fp32 = ctx->par.precision == 1;
     if (ctx->J.fp32) return dalloc(ctx, &ctx->J.val32, n);
     return dalloc(ctx, &ctx->J.val, n);
+}
+
+// True when the mesh is the structured Kuhn (Freudenthal) split of a box:
+// nodes numbered lexicographically (x fastest) on a uniform grid and every
+// simplex a monotone lattice path from a cell corner to the opposite corner.
+bool structured_kuhn(int d, const int32_t *grid, int64_t N, int64_t E, const double *xyz, const int32_t *conn)
+{
+    int64_t np = 1, nc = 1;
+    for (int k = 0; k < d; ++k) {
+        np *= grid[k] + 1;
+        nc *= grid[k];
+    }
+    if (np != N || E != nc * (d == 3 ? 6 : 2)) return false;
+    double lo[3], hi[3];
+    for (int k = 0; k < d; ++k) {
+        lo[k] = 1e300;
+        hi[k] = -1e300;
+    }
+    for (int64_t p = 0; p < N; ++p)
+        for (int k = 0; k < d; ++k) {
+            lo[k] = std::min(lo[k], xyz[p * d + k]);
+            hi[k] = std::max(hi[k], xyz[p * d + k]);
+        }
+    auto idx = [&](int64_t p, int k) -> int64_t {
+        if (k == 0) return p % (grid[0] + 1);
+        if (k == 1) return (p / (grid[0] + 1)) % (grid[1] + 1);
+        return p / ((int64_t)(grid[0] + 1) * (grid[1] + 1));
+    };
+    for (int64_t p = 0; p < N; ++p)
+        for (int k = 0; k < d; ++k) {
+            const double x = lo[k] + (hi[k] - lo[k]) * (double)idx(p, k) / grid[k];
+            if (std::fabs(xyz[p * d + k] - x) > 1e-9 * (hi[k] - lo[k])) return false;
+        }
+    const int nn = d + 1;
+    for (int64_t e = 0; e < E; ++e) {
+        int64_t mn[3] = {INT64_MAX, INT64_MAX, INT64_MAX};
+        for (int a = 0; a < nn; ++a)
+            for (int k = 0; k < d; ++k) mn[k] = std::min(mn[k], idx(conn[e * nn + a], k));
+        int off[4][3], sum[4];
+        for (int a = 0; a < nn; ++a) {
+            sum[a] = 0;
+            for (int k = 0; k < d; ++k) {
+                off[a][k] = (int)(idx(conn[e * nn + a], k) - mn[k]);
+                if (off[a][k] < 0 || off[a][k] > 1) return false;
+                sum[a] += off[a][k];
+            }
+        }
+        // one node per lattice level 0..d, each adding one unit vector
+        int at[4] = {-1, -1, -1, -1};
+        for (int a = 0; a < nn; ++a) {
+            if (sum[a] > d || at[sum[a]] >= 0) return false;
+            at[sum[a]] = a;
+        }
+        for (int l = 1; l <= d; ++l)
+            for (int k = 0; k < d; ++k)
+                if (off[at[l]][k] < off[at[l - 1]][k]) return false;
+    }
+    return true;
 }
 
 eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *mat, const eft_params *par)
@@ -223,44 +283,9 @@ eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *
             return EFT_EINVAL;
         }
     }
-    std::vector<int64_t> ioff(N + 1, 0);
-    for (int64_t t = 0; t < E * nn; ++t) ioff[conn[t] + 1]++;
-    for (int64_t p = 0; p < N; ++p) ioff[p + 1] += ioff[p];
-    std::vector<int32_t> inc(ioff[N]);
-    {
-        std::vector<int64_t> fill(ioff.begin(), ioff.end() - 1);
-        for (int64_t e = 0; e < E; ++e)
-            for (int a = 0; a < nn; ++a) inc[fill[conn[e * nn + a]]++] = (int32_t)e;
-    }
-    std::vector<int32_t> rowptr(N + 1, 0);
-    std::vector<int32_t> col;
-    col.reserve((size_t)N * (d == 3 ? 16 : 8));
-    std::vector<int32_t> buf;
-    for (int64_t p = 0; p < N; ++p) {
-        buf.clear();
-        for (int64_t t = ioff[p]; t < ioff[p + 1]; ++t)
-            for (int a = 0; a < nn; ++a) buf.push_back(conn[(int64_t)inc[t] * nn + a]);
-        if (buf.empty()) buf.push_back((int32_t)p);
-        std::sort(buf.begin(), buf.end());
-        buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
-        col.insert(col.end(), buf.begin(), buf.end());
-        if (col.size() > 2000000000ULL) {
-            ctx->err = "node graph too large for 32-bit indices";
-            return EFT_EINVAL;
-        }
-        rowptr[p + 1] = (int32_t)col.size();
-    }
+    std::vector<int32_t> rowptr, col, diag, epos;
+    EFT_TRY(eft_build_graph(N, E, nn, conn, rowptr, col, diag, epos, ctx->err));
     const int64_t nnzb = (int64_t)col.size();
-    std::vector<int32_t> diag(N), epos((size_t)E * nn * nn);
-    for (int64_t p = 0; p < N; ++p)
-        diag[p] = (int32_t)(std::lower_bound(col.begin() + rowptr[p], col.begin() + rowptr[p + 1], (int32_t)p) - col.begin());
-    for (int64_t e = 0; e < E; ++e)
-        for (int a = 0; a < nn; ++a) {
-            const int32_t r = conn[e * nn + a];
-            for (int b = 0; b < nn; ++b)
-                epos[(size_t)e * nn * nn + a * nn + b] = (int32_t)(
-                    std::lower_bound(col.begin() + rowptr[r], col.begin() + rowptr[r + 1], conn[e * nn + b]) - col.begin());
-        }
     // band grid: cells of band_cell mesh cells, element -> cell of its centroid
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     for (int i = 0; i < d; ++i) {
@@ -316,6 +341,13 @@ eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *
     EFT_TRY(upload(ctx, &ctx->J.col, col.data(), nnzb));
     EFT_TRY(upload(ctx, &ctx->J.diag, diag.data(), N));
     EFT_TRY(alloc_jacobian_values(ctx));
+    // geometric multigrid needs the structured Kuhn layout of a box
+    ctx->structured = structured_kuhn(d, mesh->grid, N, E, mesh->xyz, conn);
+    if (ctx->structured) {
+        std::vector<uint8_t> dm(N, 0);
+        for (int64_t t = 0; t < mesh->n_dir; ++t) dm[mesh->dir_node[t]] |= mesh->dir_mask[t];
+        EFT_TRY(eft_mg_create(ctx, mesh->grid, dm));
+    }
     const int mx = std::max(bs, nv);
     EFT_TRY(dalloc(ctx, &ctx->va, N * d));
     EFT_TRY(dalloc(ctx, &ctx->acc, N * d));

@@ -59,6 +59,36 @@ struct Band {
     int64_t cap[8] = {0, 0, 0, 0, 0, 0, 0, 0}; // allocation sizes in bytes
 };
 
+// One level of the mesh with the node fields the element kernels read.
+struct MeshView {
+    int64_t N = 0, E = 0;
+    const int32_t *conn = nullptr, *epos = nullptr;
+    const double *xyz = nullptr;
+    const double *va = nullptr, *acc = nullptr, *rho = nullptr, *mu = nullptr, *as = nullptr, *Ba = nullptr;
+    int64_t n_dir = 0;
+    const int32_t *dir_node = nullptr;
+    const uint8_t *dir_mask = nullptr;
+};
+
+// One level of the geometric multigrid hierarchy on nested Kuhn meshes.
+// Level 0 is the momentum/mass mesh itself (its mesh arrays and matrix are
+// the context's); coarser levels own theirs.
+struct MGLevel {
+    int n[3] = {1, 1, 1};            // cells per axis
+    int64_t N = 0, E = 0;
+    int32_t *conn = nullptr, *epos = nullptr, *inj = nullptr;  // inj: fine-mesh node of each node
+    double *xyz = nullptr;
+    double *va = nullptr, *acc = nullptr, *rho = nullptr, *mu = nullptr, *as = nullptr, *Ba = nullptr;
+    double *vp = nullptr, *R = nullptr;
+    int64_t n_dir = 0;
+    int32_t *dir_node = nullptr;
+    uint8_t *dir_mask = nullptr;
+    uint8_t *fmask = nullptr;        // [N]: bit c set when dof c is free (not Dirichlet)
+    eft_matrix A;                    // coarse levels: FP64 values
+    double *Dinv = nullptr;          // [N][bs*bs]
+    double *x = nullptr, *x2 = nullptr, *b = nullptr, *r = nullptr;  // [N*bs]
+};
+
 struct eft_ctx {
     hipStream_t stream = nullptr;
     std::string err;
@@ -115,6 +145,13 @@ struct eft_ctx {
     double *hscal = nullptr;                     // pinned host scalars
     int32_t nred = 0;
     KrylovWs kw;
+    // geometric multigrid (structured Kuhn meshes with even cell counts)
+    bool structured = false;
+    std::vector<MGLevel> mg;
+    double *mg_dense = nullptr, *mg_inv = nullptr;   // coarsest level [nd][nd]
+    int64_t mg_nd = 0;
+    double mg_omega = 0.7;
+    int mg_nu = 2;
 };
 
 // ------------------------------------------------------------- helpers ----
@@ -157,6 +194,17 @@ static inline GA ga_of(double rho_inf, double dt)
 // k_assemble.hip
 eft_status eft_props(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it);
 eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_matrix *J);
+eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, double *R, eft_matrix *J);
+
+// k_mg.hip
+eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<uint8_t> &dmask0);
+eft_status eft_mg_setup(eft_ctx *ctx, const double *vp);
+eft_status eft_mg_vcycle(eft_ctx *ctx, const double *b0, double *z, const int32_t *flag);
+void eft_mg_free(eft_ctx *ctx);
+bool eft_mg_active(const eft_ctx *ctx, const eft_matrix *A);
+eft_status eft_build_graph(int64_t N, int64_t E, int nn, const int32_t *conn, std::vector<int32_t> &rowptr,
+                           std::vector<int32_t> &col, std::vector<int32_t> &diag, std::vector<int32_t> &epos,
+                           std::string &err);
 eft_status eft_fill(eft_ctx *ctx, double *p, int64_t n, double v);
 eft_status eft_fill32(eft_ctx *ctx, float *p, int64_t n, float v);
 eft_status eft_fill_u8(eft_ctx *ctx, uint8_t *p, int64_t n);

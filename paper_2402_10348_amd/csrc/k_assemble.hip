@@ -516,20 +516,16 @@ eft_status eft_props(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it)
     return EFT_OK;
 }
 
-template <int D, typename TJ> static void launch_ns(eft_ctx *ctx, const NSArgs &a, const ElArgs &el, TJ *Jv)
-{
-    const int nb = eft_grid(ctx->E, 128);
-    hipLaunchKernelGGL((k_ns_fluid<D, TJ>), dim3(nb), dim3(128), 0, ctx->stream, a, Jv);
-    if (ctx->n_s > 0) hipLaunchKernelGGL((k_ns_elastic<D, TJ>), dim3(nb), dim3(128), 0, ctx->stream, el, Jv);
-}
 
 // Residual and Jacobian of the momentum/mass block at the iterate (the
 // node fields va, acc, rho, mu, as, Ba must be current, see eft_props).
-eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_matrix *J)
+// Residual and Jacobian of the momentum/mass block on one mesh level (the
+// node fields of the view must be current).
+eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, double *R, eft_matrix *J)
 {
     GA ga = ga_of(ctx->par.rho_inf, ctx->par.dt);
     const int BS = ctx->bs;
-    EFT_TRY(eft_fill(ctx, R, ctx->N * BS, 0.0));
+    EFT_TRY(eft_fill(ctx, R, M.N * BS, 0.0));
     if (J) {
         if (J->fp32)
             EFT_TRY(eft_fill32(ctx, J->val32, J->nnzb * BS * BS, 0.0f));
@@ -537,15 +533,15 @@ eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_ma
             EFT_TRY(eft_fill(ctx, J->val, J->nnzb * BS * BS, 0.0));
     }
     NSArgs a;
-    a.E = ctx->E;
-    a.conn = ctx->conn;
-    a.epos = ctx->epos;
-    a.xyz = ctx->xyz;
-    a.va = ctx->va;
-    a.acc = ctx->acc;
-    a.vp = it->vp;
-    a.rho = ctx->rho;
-    a.mu = ctx->mu;
+    a.E = M.E;
+    a.conn = M.conn;
+    a.epos = M.epos;
+    a.xyz = M.xyz;
+    a.va = M.va;
+    a.acc = M.acc;
+    a.vp = vp;
+    a.rho = M.rho;
+    a.mu = M.mu;
     a.ct = ga.ct;
     a.alpha = ga.alpha;
     a.dt = ga.dt;
@@ -555,35 +551,74 @@ eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_ma
     a.g2 = ctx->g[2];
     a.R = R;
     ElArgs el;
-    el.E = ctx->E;
-    el.N = ctx->N;
+    el.E = M.E;
+    el.N = M.N;
     el.n_s = ctx->n_s;
-    el.conn = ctx->conn;
-    el.epos = ctx->epos;
-    el.xyz = ctx->xyz;
-    el.as = ctx->as;
-    el.Ba = ctx->Ba;
-    el.muL = ctx->phase_tab + 4 * EFT_MAX_PHASE + EFT_MAX_PHASE;  // solid mu_L copy, see abi
+    el.conn = M.conn;
+    el.epos = M.epos;
+    el.xyz = M.xyz;
+    el.as = M.as;
+    el.Ba = M.Ba;
+    el.muL = ctx->phase_tab + 5 * EFT_MAX_PHASE;  // mu_L of each solid
     el.alpha = ga.alpha;
     el.kappa = ga.kappa;
     el.R = R;
+    const int nb = eft_grid(M.E, 128);
     if (ctx->dim == 2) {
-        if (J && J->fp32) launch_ns<2, float>(ctx, a, el, J->val32);
-        else launch_ns<2, double>(ctx, a, el, J ? J->val : nullptr);
+        if (J && J->fp32) {
+            hipLaunchKernelGGL((k_ns_fluid<2, float>), dim3(nb), dim3(128), 0, ctx->stream, a, J->val32);
+            if (ctx->n_s > 0) hipLaunchKernelGGL((k_ns_elastic<2, float>), dim3(nb), dim3(128), 0, ctx->stream, el, J->val32);
+        } else {
+            double *Jv = J ? J->val : nullptr;
+            hipLaunchKernelGGL((k_ns_fluid<2, double>), dim3(nb), dim3(128), 0, ctx->stream, a, Jv);
+            if (ctx->n_s > 0) hipLaunchKernelGGL((k_ns_elastic<2, double>), dim3(nb), dim3(128), 0, ctx->stream, el, Jv);
+        }
     } else {
-        if (J && J->fp32) launch_ns<3, float>(ctx, a, el, J->val32);
-        else launch_ns<3, double>(ctx, a, el, J ? J->val : nullptr);
+        if (J && J->fp32) {
+            hipLaunchKernelGGL((k_ns_fluid<3, float>), dim3(nb), dim3(128), 0, ctx->stream, a, J->val32);
+            if (ctx->n_s > 0) hipLaunchKernelGGL((k_ns_elastic<3, float>), dim3(nb), dim3(128), 0, ctx->stream, el, J->val32);
+        } else {
+            double *Jv = J ? J->val : nullptr;
+            hipLaunchKernelGGL((k_ns_fluid<3, double>), dim3(nb), dim3(128), 0, ctx->stream, a, Jv);
+            if (ctx->n_s > 0) hipLaunchKernelGGL((k_ns_elastic<3, double>), dim3(nb), dim3(128), 0, ctx->stream, el, Jv);
+        }
     }
     EFT_HIP(hipGetLastError());
-    if (ctx->n_dir > 0) {
-        const int nb = eft_grid(ctx->n_dir, 128);
+    if (M.n_dir > 0) {
+        const int nbd = eft_grid(M.n_dir, 128);
         if (J && J->fp32)
-            hipLaunchKernelGGL(k_bc_rows<float>, dim3(nb), dim3(128), 0, ctx->stream, ctx->n_dir, ctx->dir_node,
-                               ctx->dir_mask, J->rowptr, J->col, BS, R, J->val32);
+            hipLaunchKernelGGL(k_bc_rows<float>, dim3(nbd), dim3(128), 0, ctx->stream, M.n_dir, M.dir_node, M.dir_mask,
+                               J->rowptr, J->col, BS, R, J->val32);
         else
-            hipLaunchKernelGGL(k_bc_rows<double>, dim3(nb), dim3(128), 0, ctx->stream, ctx->n_dir, ctx->dir_node,
-                               ctx->dir_mask, ctx->J.rowptr, ctx->J.col, BS, R, J ? J->val : (double *)nullptr);
+            hipLaunchKernelGGL(k_bc_rows<double>, dim3(nbd), dim3(128), 0, ctx->stream, M.n_dir, M.dir_node,
+                               M.dir_mask, J ? J->rowptr : nullptr, J ? J->col : nullptr, BS, R,
+                               J ? J->val : (double *)nullptr);
         EFT_HIP(hipGetLastError());
     }
+    return EFT_OK;
+}
+
+// Residual and Jacobian of the momentum/mass block at the iterate (the node
+// fields va, acc, rho, mu, as, Ba must be current, see eft_props); with a
+// Jacobian, the multigrid levels are refreshed too.
+eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_matrix *J)
+{
+    MeshView M;
+    M.N = ctx->N;
+    M.E = ctx->E;
+    M.conn = ctx->conn;
+    M.epos = ctx->epos;
+    M.xyz = ctx->xyz;
+    M.va = ctx->va;
+    M.acc = ctx->acc;
+    M.rho = ctx->rho;
+    M.mu = ctx->mu;
+    M.as = ctx->as;
+    M.Ba = ctx->Ba;
+    M.n_dir = ctx->n_dir;
+    M.dir_node = ctx->dir_node;
+    M.dir_mask = ctx->dir_mask;
+    EFT_TRY(eft_ns_level(ctx, M, it->vp, R, J));
+    if (J && eft_mg_active(ctx, J)) EFT_TRY(eft_mg_setup(ctx, it->vp));
     return EFT_OK;
 }

@@ -320,7 +320,9 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
         if (info) *info = inf;
         return EFT_OK;
     }
-    EFT_TRY(eft_bj_setup(ctx, A, K.Dinv));
+    const bool mg = eft_mg_active(ctx, A);   // hierarchy refreshed by the assembly
+    inf.fallback_used = (ctx->par.precond == 1 && A == &ctx->J && !mg) ? 1 : 0;
+    if (!mg) EFT_TRY(eft_bj_setup(ctx, A, K.Dinv));
     const double tol = ctx->par.lin_rtol * bnorm;
     const int maxit = std::max(1, ctx->par.lin_maxit);
     const int chunk = 8;
@@ -351,7 +353,10 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
         for (int j0 = 0; j0 < mc; j0 += chunk) {
             for (int j = j0; j < std::min(mc, j0 + chunk); ++j) {
                 double *vj = K.V + (int64_t)j * nd, *zj = K.Z + (int64_t)j * nd;
-                EFT_TRY(eft_bj_apply(ctx, bs, n, K.Dinv, vj, zj, K.flag));
+                if (mg)
+                    EFT_TRY(eft_mg_vcycle(ctx, vj, zj, K.flag));
+                else
+                    EFT_TRY(eft_bj_apply(ctx, bs, n, K.Dinv, vj, zj, K.flag));
                 EFT_TRY(eft_spmv_flag(ctx, A, zj, K.w, K.flag));
                 // pass 1: dots with V[0..j] and ||w||^2
                 dim3 g1(nblk, (j + 2 + KC - 1) / KC);

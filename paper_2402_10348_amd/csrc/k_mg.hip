@@ -1,0 +1,763 @@
+// Geometric multigrid preconditioner for the momentum/mass system on nested
+// Kuhn (Freudenthal) meshes of a box.
+//
+// The structured simplex mesh of n cells per axis is the regular refinement of
+// the one with n/2 cells: every coarse node is a fine node and every other
+// fine node is the midpoint of a coarse edge (a Kuhn direction, i.e. a
+// non-zero 0/1 offset).  The P1 spaces are nested, so prolongation is linear
+// interpolation (weights 1 and 1/2) and restriction its transpose, both
+// evaluated in gather form from structured indices.  Coarse operators are
+// rediscretized: the same element kernels assemble the coarse Jacobian from
+// node fields injected from the fine mesh.  Smoothing is damped point-block
+// Jacobi, i.e. the node-wise Vanka smoother of the (d+1)x(d+1) node blocks of
+// the equal-order stabilized system; the coarsest level is inverted exactly.
+// Dirichlet dofs are removed from the coarse space (masked in transfer).
+#include <algorithm>
+
+#include "dev_common.h"
+#include "eft_internal.h"
+
+namespace {
+
+// ------------------------------------------------------------- helpers ----
+
+struct Dims {
+    int n[3];   // cells per axis (1 for unused axes)
+};
+
+__device__ __forceinline__ int64_t node_id(const Dims &d, int i, int j, int k)
+{
+    return i + (int64_t)(d.n[0] + 1) * (j + (int64_t)(d.n[1] + 1) * k);
+}
+
+// Kuhn stencil offsets (D = 3: 0 and +-{x, y, z, x+y, y+z, x+z, x+y+z};
+// D = 2: 0 and +-{x, y, x+y})
+template <int D> struct Stencil;
+template <> struct Stencil<3> {
+    static constexpr int S = 15;
+    __device__ static void off(int s, int &a, int &b, int &c)
+    {
+        const int t[8][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {0, 1, 1}, {1, 0, 1}, {1, 1, 1}};
+        const int q = s < 8 ? s : s - 7;
+        const int sg = s < 8 ? 1 : -1;
+        a = sg * t[q][0];
+        b = sg * t[q][1];
+        c = sg * t[q][2];
+    }
+};
+template <> struct Stencil<2> {
+    static constexpr int S = 7;
+    __device__ static void off(int s, int &a, int &b, int &c)
+    {
+        const int t[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
+        const int q = s < 4 ? s : s - 3;
+        const int sg = s < 4 ? 1 : -1;
+        a = sg * t[q][0];
+        b = sg * t[q][1];
+        c = 0;
+    }
+};
+
+// ---------------------------------------------------------- injection -----
+
+struct InjArgs {
+    int64_t Nc, Nf;
+    int d, bs, nv, n_s;
+    const int32_t *inj;
+    const double *va, *acc, *rho, *mu, *as, *Ba, *vp;
+    double *cva, *cacc, *crho, *cmu, *cas, *cBa, *cvp;
+};
+
+__global__ __launch_bounds__(256) void k_inject(InjArgs a)
+{
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= a.Nc) return;
+    const int64_t f = a.inj[I];
+    for (int i = 0; i < a.d; ++i) {
+        a.cva[I * a.d + i] = a.va[f * a.d + i];
+        a.cacc[I * a.d + i] = a.acc[f * a.d + i];
+    }
+    for (int i = 0; i < a.bs; ++i) a.cvp[I * a.bs + i] = a.vp[f * a.bs + i];
+    a.crho[I] = a.rho[f];
+    a.cmu[I] = a.mu[f];
+    for (int s = 0; s < a.n_s; ++s) {
+        a.cas[(int64_t)s * a.Nc + I] = a.as[(int64_t)s * a.Nf + f];
+        for (int c = 0; c < a.nv; ++c) a.cBa[((int64_t)s * a.Nc + I) * a.nv + c] = a.Ba[((int64_t)s * a.Nf + f) * a.nv + c];
+    }
+}
+
+// ----------------------------------------------------------- smoothing ----
+
+// x_out = x_in + omega D^-1 (b - A x_in), bs = 4, one wavefront per block row
+template <typename TV>
+__global__ __launch_bounds__(256) void k_sweep4(int64_t n, const int32_t *__restrict__ rowptr,
+                                                const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                const double *__restrict__ Dinv, double omega,
+                                                const double *__restrict__ b, const double *__restrict__ x,
+                                                double *__restrict__ xo, const int32_t *flag)
+{
+    if (*flag == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (row >= n) return;
+    const int slot = lane >> 4, e = lane & 15, c = e & 3;
+    const int k0 = rowptr[row], k1 = rowptr[row + 1];
+    double acc = 0.0;
+    for (int k = k0 + slot; k < k1; k += 4) acc += (double)val[(int64_t)k * 16 + e] * x[(int64_t)col[k] * 4 + c];
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    acc += __shfl_xor(acc, 16, 64);
+    acc += __shfl_xor(acc, 32, 64);
+    // lanes 0, 4, 8, 12 hold (A x) of rows 0..3
+    const double r0 = __shfl(acc, 0, 64), r1 = __shfl(acc, 4, 64), r2 = __shfl(acc, 8, 64), r3 = __shfl(acc, 12, 64);
+    if (lane < 4) {
+        const double *Dr = Dinv + row * 16 + lane * 4;
+        const double *br = b + row * 4;
+        const double u = Dr[0] * (br[0] - r0) + Dr[1] * (br[1] - r1) + Dr[2] * (br[2] - r2) + Dr[3] * (br[3] - r3);
+        xo[row * 4 + lane] = x[row * 4 + lane] + omega * u;
+    }
+}
+
+// general bs <= 8
+template <typename TV>
+__global__ __launch_bounds__(256) void k_sweepb(int64_t n, int bs, const int32_t *__restrict__ rowptr,
+                                                const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                const double *__restrict__ Dinv, double omega,
+                                                const double *__restrict__ b, const double *__restrict__ x,
+                                                double *__restrict__ xo, const int32_t *flag)
+{
+    __shared__ double lds[256];
+    __shared__ double res[4][8];
+    if (*flag == 0) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int b2 = bs * bs, slots = 64 / b2;
+    const int slot = lane / b2, e = lane - slot * b2, c = e % bs;
+    double acc = 0.0;
+    if (row < n && slot < slots) {
+        const int k0 = rowptr[row], k1 = rowptr[row + 1];
+        for (int k = k0 + slot; k < k1; k += slots) acc += (double)val[(int64_t)k * b2 + e] * x[(int64_t)col[k] * bs + c];
+    }
+    lds[threadIdx.x] = acc;
+    __syncthreads();
+    if (row < n && lane < bs) {
+        double s = 0.0;
+        for (int sl = 0; sl < slots; ++sl)
+            for (int cc = 0; cc < bs; ++cc) s += lds[wv * 64 + sl * b2 + lane * bs + cc];
+        res[wv][lane] = b[row * bs + lane] - s;
+    }
+    __syncthreads();
+    if (row < n && lane < bs) {
+        double u = 0.0;
+        for (int cc = 0; cc < bs; ++cc) u += Dinv[row * b2 + lane * bs + cc] * res[wv][cc];
+        xo[row * bs + lane] = x[row * bs + lane] + omega * u;
+    }
+}
+
+// x = omega D^-1 b (first sweep from x = 0)
+__global__ __launch_bounds__(256) void k_sweep0(int64_t nd, int bs, const double *__restrict__ Dinv, double omega,
+                                                const double *__restrict__ b, double *__restrict__ x,
+                                                const int32_t *flag)
+{
+    if (*flag == 0) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nd) return;
+    const int64_t r = t / bs;
+    const int i = (int)(t - r * bs);
+    const double *D = Dinv + r * bs * bs + i * bs;
+    double s = 0.0;
+    for (int c = 0; c < bs; ++c) s += D[c] * b[r * bs + c];
+    x[t] = omega * s;
+}
+
+// r = b - A x
+template <typename TV>
+__global__ __launch_bounds__(256) void k_resid4(int64_t n, const int32_t *__restrict__ rowptr,
+                                                const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                const double *__restrict__ b, const double *__restrict__ x,
+                                                double *__restrict__ r, const int32_t *flag)
+{
+    if (*flag == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (row >= n) return;
+    const int slot = lane >> 4, e = lane & 15, c = e & 3;
+    const int k0 = rowptr[row], k1 = rowptr[row + 1];
+    double acc = 0.0;
+    for (int k = k0 + slot; k < k1; k += 4) acc += (double)val[(int64_t)k * 16 + e] * x[(int64_t)col[k] * 4 + c];
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    acc += __shfl_xor(acc, 16, 64);
+    acc += __shfl_xor(acc, 32, 64);
+    if (slot == 0 && c == 0) r[row * 4 + (e >> 2)] = b[row * 4 + (e >> 2)] - acc;
+}
+
+template <typename TV>
+__global__ __launch_bounds__(256) void k_residb(int64_t n, int bs, const int32_t *__restrict__ rowptr,
+                                                const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                const double *__restrict__ b, const double *__restrict__ x,
+                                                double *__restrict__ r, const int32_t *flag)
+{
+    __shared__ double lds[256];
+    if (*flag == 0) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int b2 = bs * bs, slots = 64 / b2;
+    const int slot = lane / b2, e = lane - slot * b2, c = e % bs;
+    double acc = 0.0;
+    if (row < n && slot < slots) {
+        const int k0 = rowptr[row], k1 = rowptr[row + 1];
+        for (int k = k0 + slot; k < k1; k += slots) acc += (double)val[(int64_t)k * b2 + e] * x[(int64_t)col[k] * bs + c];
+    }
+    lds[threadIdx.x] = acc;
+    __syncthreads();
+    if (row < n && lane < bs) {
+        double s = 0.0;
+        for (int sl = 0; sl < slots; ++sl)
+            for (int cc = 0; cc < bs; ++cc) s += lds[wv * 64 + sl * b2 + lane * bs + cc];
+        r[row * bs + lane] = b[row * bs + lane] - s;
+    }
+}
+
+// --------------------------------------------------------- transfers ------
+
+// coarse b[I] = sum over children i of I (fine nodes 2I + s, s in the Kuhn
+// stencil) of w(i, I) r[i], masked by the free dofs of both levels
+template <int D>
+__global__ __launch_bounds__(256) void k_restrict(Dims cd, Dims fd, int bs, const uint8_t *__restrict__ cmask,
+                                                  const uint8_t *__restrict__ fmask, const double *__restrict__ r,
+                                                  double *__restrict__ bc, const int32_t *flag)
+{
+    if (*flag == 0) return;
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t Nc = (int64_t)(cd.n[0] + 1) * (cd.n[1] + 1) * (cd.n[2] + 1);
+    if (I >= Nc) return;
+    const int ci = (int)(I % (cd.n[0] + 1));
+    const int cj = (int)((I / (cd.n[0] + 1)) % (cd.n[1] + 1));
+    const int ck = (int)(I / ((int64_t)(cd.n[0] + 1) * (cd.n[1] + 1)));
+    double acc[8];
+    for (int c = 0; c < bs; ++c) acc[c] = 0.0;
+    for (int s = 0; s < Stencil<D>::S; ++s) {
+        int a, b, c3;
+        Stencil<D>::off(s, a, b, c3);
+        const int fi = 2 * ci + a, fj = 2 * cj + b, fk = 2 * ck + c3;
+        if (fi < 0 || fj < 0 || fk < 0 || fi > fd.n[0] || fj > fd.n[1] || fk > fd.n[2]) continue;
+        const int64_t f = node_id(fd, fi, fj, fk);
+        const double w = s == 0 ? 1.0 : 0.5;
+        const int m = fmask[f];
+        for (int c = 0; c < bs; ++c)
+            if ((m >> c) & 1) acc[c] += w * r[f * bs + c];
+    }
+    const int mc = cmask[I];
+    for (int c = 0; c < bs; ++c) bc[I * bs + c] = ((mc >> c) & 1) ? acc[c] : 0.0;
+}
+
+// x[i] += sum over parents I of i of w(i, I) xc[I] (free dofs only)
+__global__ __launch_bounds__(256) void k_prolong(Dims cd, Dims fd, int bs, const uint8_t *__restrict__ cmask,
+                                                 const uint8_t *__restrict__ fmask, const double *__restrict__ xc,
+                                                 double *__restrict__ x, const int32_t *flag)
+{
+    if (*flag == 0) return;
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t Nf = (int64_t)(fd.n[0] + 1) * (fd.n[1] + 1) * (fd.n[2] + 1);
+    if (f >= Nf) return;
+    const int fi = (int)(f % (fd.n[0] + 1));
+    const int fj = (int)((f / (fd.n[0] + 1)) % (fd.n[1] + 1));
+    const int fk = (int)(f / ((int64_t)(fd.n[0] + 1) * (fd.n[1] + 1)));
+    const int64_t I0 = node_id(cd, fi >> 1, fj >> 1, fk >> 1);
+    const bool mid = (fi & 1) | (fj & 1) | (fk & 1);
+    const int64_t I1 = mid ? node_id(cd, (fi >> 1) + (fi & 1), (fj >> 1) + (fj & 1), (fk >> 1) + (fk & 1)) : I0;
+    const int m = fmask[f];
+    const int m0 = cmask[I0], m1 = cmask[I1];
+    for (int c = 0; c < bs; ++c) {
+        if (!((m >> c) & 1)) continue;
+        double v;
+        if (mid) {
+            const double a0 = ((m0 >> c) & 1) ? xc[I0 * bs + c] : 0.0;
+            const double a1 = ((m1 >> c) & 1) ? xc[I1 * bs + c] : 0.0;
+            v = 0.5 * (a0 + a1);
+        } else {
+            v = ((m0 >> c) & 1) ? xc[I0 * bs + c] : 0.0;
+        }
+        x[f * bs + c] += v;
+    }
+}
+
+// -------------------------------------------------------- coarsest level --
+
+__global__ void k_dense_fill(int64_t n, int bs, const int32_t *rowptr, const int32_t *col, const double *val,
+                             double *M, int64_t nd)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    for (int64_t j = 0; j < nd; ++j)
+        for (int i = 0; i < bs; ++i) M[(r * bs + i) * nd + j] = 0.0;
+    for (int k = rowptr[r]; k < rowptr[r + 1]; ++k)
+        for (int i = 0; i < bs; ++i)
+            for (int j = 0; j < bs; ++j) M[(r * bs + i) * nd + (int64_t)col[k] * bs + j] = val[((int64_t)k * bs + i) * bs + j];
+}
+
+// Gauss-Jordan inversion with partial pivoting, one workgroup; M is
+// destroyed, Inv receives the inverse.
+__global__ __launch_bounds__(256) void k_gauss_jordan(double *M, double *Inv, int nd)
+{
+    __shared__ double sv[256];
+    __shared__ int si[256];
+    __shared__ int piv;
+    const int t = threadIdx.x;
+    for (int64_t e = t; e < (int64_t)nd * nd; e += 256) Inv[e] = (e / nd == e % nd) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int k = 0; k < nd; ++k) {
+        double best = -1.0;
+        int bi = k;
+        for (int i = k + t; i < nd; i += 256) {
+            const double a = fabs(M[(int64_t)i * nd + k]);
+            if (a > best) {
+                best = a;
+                bi = i;
+            }
+        }
+        sv[t] = best;
+        si[t] = bi;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if (t < off && sv[t + off] > sv[t]) {
+                sv[t] = sv[t + off];
+                si[t] = si[t + off];
+            }
+            __syncthreads();
+        }
+        if (t == 0) piv = si[0];
+        __syncthreads();
+        const int p = piv;
+        if (p != k)
+            for (int j = t; j < nd; j += 256) {
+                double a = M[(int64_t)k * nd + j];
+                M[(int64_t)k * nd + j] = M[(int64_t)p * nd + j];
+                M[(int64_t)p * nd + j] = a;
+                a = Inv[(int64_t)k * nd + j];
+                Inv[(int64_t)k * nd + j] = Inv[(int64_t)p * nd + j];
+                Inv[(int64_t)p * nd + j] = a;
+            }
+        __syncthreads();
+        const double d = M[(int64_t)k * nd + k];
+        const double inv = d != 0.0 ? 1.0 / d : 0.0;
+        __syncthreads();
+        for (int j = t; j < nd; j += 256) {
+            M[(int64_t)k * nd + j] *= inv;
+            Inv[(int64_t)k * nd + j] *= inv;
+        }
+        __syncthreads();
+        for (int64_t e = t; e < (int64_t)nd * nd; e += 256) {
+            const int i = (int)(e / nd), j = (int)(e % nd);
+            if (i == k) continue;
+            const double f = M[(int64_t)i * nd + k];
+            if (j != k) M[e] -= f * M[(int64_t)k * nd + j];
+            Inv[e] -= f * Inv[(int64_t)k * nd + j];
+        }
+        __syncthreads();
+        for (int i = t; i < nd; i += 256)
+            if (i != k) M[(int64_t)i * nd + k] = 0.0;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_dense_apply(const double *Inv, int nd, const double *b, double *x,
+                                                     const int32_t *flag)
+{
+    if (*flag == 0) return;
+    for (int i = threadIdx.x; i < nd; i += 256) {
+        double s = 0.0;
+        for (int j = 0; j < nd; ++j) s += Inv[(int64_t)i * nd + j] * b[j];
+        x[i] = s;
+    }
+}
+
+// ------------------------------------------------------------------ host --
+
+eft_status kuhn_mesh(int d, const int n[3], std::vector<int32_t> &conn)
+{
+    conn.clear();
+    if (d == 2) {
+        const int64_t nx1 = n[0] + 1;
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                const int32_t v00 = (int32_t)(i + nx1 * j), v10 = v00 + 1, v01 = (int32_t)(v00 + nx1), v11 = v01 + 1;
+                const int32_t t[6] = {v00, v10, v11, v00, v11, v01};
+                conn.insert(conn.end(), t, t + 6);
+            }
+        return EFT_OK;
+    }
+    const int64_t sx = 1, sy = n[0] + 1, sz = (int64_t)(n[0] + 1) * (n[1] + 1);
+    const int64_t st[3] = {sx, sy, sz};
+    const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    const bool even[6] = {true, false, false, true, true, false};
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                const int64_t v0 = i * sx + j * sy + k * sz;
+                for (int p = 0; p < 6; ++p) {
+                    const int64_t a = v0 + st[perms[p][0]], b = a + st[perms[p][1]], c = b + st[perms[p][2]];
+                    if (even[p]) {
+                        const int32_t t[4] = {(int32_t)v0, (int32_t)a, (int32_t)b, (int32_t)c};
+                        conn.insert(conn.end(), t, t + 4);
+                    } else {
+                        const int32_t t[4] = {(int32_t)v0, (int32_t)b, (int32_t)a, (int32_t)c};
+                        conn.insert(conn.end(), t, t + 4);
+                    }
+                }
+            }
+    return EFT_OK;
+}
+
+template <typename T> eft_status dmal(eft_ctx *ctx, T **p, int64_t count)
+{
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    if (hipMalloc((void **)p, sizeof(T) * (size_t)count) != hipSuccess) {
+        ctx->err = "out of device memory (multigrid)";
+        return EFT_ENOMEM;
+    }
+    return EFT_OK;
+}
+
+template <typename T> eft_status dput(eft_ctx *ctx, T **p, const std::vector<T> &h)
+{
+    EFT_TRY(dmal(ctx, p, (int64_t)h.size()));
+    if (!h.empty()) EFT_HIP(hipMemcpy(*p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+    return EFT_OK;
+}
+
+Dims dims_of(const MGLevel &L) { return Dims{{L.n[0], L.n[1], L.n[2]}}; }
+
+}  // namespace
+
+// Node graph of a simplex mesh: sorted columns per row (self included), the
+// diagonal position per row and, per element, the position of each node
+// pair (a, b) in row a.
+eft_status eft_build_graph(int64_t N, int64_t E, int nn, const int32_t *conn, std::vector<int32_t> &rowptr,
+                           std::vector<int32_t> &col, std::vector<int32_t> &diag, std::vector<int32_t> &epos,
+                           std::string &err)
+{
+    std::vector<int64_t> ioff(N + 1, 0);
+    for (int64_t t = 0; t < E * nn; ++t) ioff[conn[t] + 1]++;
+    for (int64_t p = 0; p < N; ++p) ioff[p + 1] += ioff[p];
+    std::vector<int32_t> inc(ioff[N]);
+    {
+        std::vector<int64_t> fill(ioff.begin(), ioff.end() - 1);
+        for (int64_t e = 0; e < E; ++e)
+            for (int a = 0; a < nn; ++a) inc[fill[conn[e * nn + a]]++] = (int32_t)e;
+    }
+    rowptr.assign(N + 1, 0);
+    col.clear();
+    col.reserve((size_t)N * (nn == 4 ? 16 : 8));
+    std::vector<int32_t> buf;
+    for (int64_t p = 0; p < N; ++p) {
+        buf.clear();
+        for (int64_t t = ioff[p]; t < ioff[p + 1]; ++t)
+            for (int a = 0; a < nn; ++a) buf.push_back(conn[(int64_t)inc[t] * nn + a]);
+        if (buf.empty()) buf.push_back((int32_t)p);
+        std::sort(buf.begin(), buf.end());
+        buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+        col.insert(col.end(), buf.begin(), buf.end());
+        if (col.size() > 2000000000ULL) {
+            err = "node graph too large for 32-bit indices";
+            return EFT_EINVAL;
+        }
+        rowptr[p + 1] = (int32_t)col.size();
+    }
+    diag.assign(N, 0);
+    epos.assign((size_t)E * nn * nn, 0);
+    for (int64_t p = 0; p < N; ++p)
+        diag[p] = (int32_t)(std::lower_bound(col.begin() + rowptr[p], col.begin() + rowptr[p + 1], (int32_t)p) - col.begin());
+    for (int64_t e = 0; e < E; ++e)
+        for (int a = 0; a < nn; ++a) {
+            const int32_t r = conn[e * nn + a];
+            for (int b = 0; b < nn; ++b)
+                epos[(size_t)e * nn * nn + a * nn + b] = (int32_t)(
+                    std::lower_bound(col.begin() + rowptr[r], col.begin() + rowptr[r + 1], conn[e * nn + b]) - col.begin());
+        }
+    return EFT_OK;
+}
+
+// Build the coarse levels.  grid: cells per axis of the fine mesh (known to be
+// a structured Kuhn mesh); dmask0: Dirichlet dof bits of each fine node.
+eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<uint8_t> &dmask0)
+{
+    const int d = ctx->dim, bs = ctx->bs, nv = ctx->nv, nn = d + 1;
+    const int full = (1 << bs) - 1;
+    ctx->mg.clear();
+    MGLevel L0;
+    for (int k = 0; k < 3; ++k) L0.n[k] = k < d ? grid[k] : 0;
+    L0.N = ctx->N;
+    L0.E = ctx->E;
+    std::vector<uint8_t> fm(ctx->N);
+    for (int64_t p = 0; p < ctx->N; ++p) fm[p] = (uint8_t)(full & ~dmask0[p]);
+    EFT_TRY(dput(ctx, &L0.fmask, fm));
+    EFT_TRY(dmal(ctx, &L0.Dinv, ctx->N * bs * bs));
+    EFT_TRY(dmal(ctx, &L0.x, ctx->N * bs));
+    EFT_TRY(dmal(ctx, &L0.x2, ctx->N * bs));
+    EFT_TRY(dmal(ctx, &L0.r, ctx->N * bs));
+    ctx->mg.push_back(L0);
+    // level-0 coordinates on the host, to carry to the coarse levels
+    std::vector<double> xyz0(ctx->N * d);
+    EFT_HIP(hipMemcpy(xyz0.data(), ctx->xyz, sizeof(double) * xyz0.size(), hipMemcpyDeviceToHost));
+    std::vector<int64_t> inj_prev(ctx->N);
+    for (int64_t p = 0; p < ctx->N; ++p) inj_prev[p] = p;
+    for (;;) {
+        const MGLevel &F = ctx->mg.back();
+        // coarsen while every axis has an even cell count of at least 4
+        bool can = true;
+        for (int k = 0; k < d; ++k) can &= F.n[k] % 2 == 0 && F.n[k] >= 4;
+        if (!can) break;
+        MGLevel C;
+        for (int k = 0; k < 3; ++k) C.n[k] = k < d ? F.n[k] / 2 : 0;
+        C.N = 1;
+        for (int k = 0; k < d; ++k) C.N *= C.n[k] + 1;
+        std::vector<int32_t> conn;
+        EFT_TRY(kuhn_mesh(d, C.n, conn));
+        C.E = (int64_t)conn.size() / nn;
+        std::vector<int64_t> inj(C.N);
+        std::vector<int32_t> inj32(C.N);
+        std::vector<double> xyz(C.N * d);
+        std::vector<uint8_t> cm(C.N);
+        std::vector<int32_t> dn;
+        std::vector<uint8_t> dmk;
+        for (int64_t I = 0; I < C.N; ++I) {
+            const int64_t i = I % (C.n[0] + 1), j = (I / (C.n[0] + 1)) % (C.n[1] + 1),
+                          k = d == 3 ? I / ((int64_t)(C.n[0] + 1) * (C.n[1] + 1)) : 0;
+            const int64_t f = 2 * i + (F.n[0] + 1) * (2 * j + (int64_t)(F.n[1] + 1) * 2 * k);
+            inj[I] = inj_prev[f];
+            inj32[I] = (int32_t)inj[I];
+            for (int c = 0; c < d; ++c) xyz[I * d + c] = xyz0[inj[I] * d + c];
+            const uint8_t dm = dmask0[inj[I]];
+            cm[I] = (uint8_t)(full & ~dm);
+            if (dm) {
+                dn.push_back((int32_t)I);
+                dmk.push_back(dm);
+            }
+        }
+        std::vector<int32_t> rowptr, col, diag, epos;
+        EFT_TRY(eft_build_graph(C.N, C.E, nn, conn.data(), rowptr, col, diag, epos, ctx->err));
+        EFT_TRY(dput(ctx, &C.conn, conn));
+        EFT_TRY(dput(ctx, &C.epos, epos));
+        EFT_TRY(dput(ctx, &C.inj, inj32));
+        EFT_TRY(dput(ctx, &C.xyz, xyz));
+        EFT_TRY(dput(ctx, &C.fmask, cm));
+        C.n_dir = (int64_t)dn.size();
+        EFT_TRY(dput(ctx, &C.dir_node, dn));
+        EFT_TRY(dput(ctx, &C.dir_mask, dmk));
+        C.A.bs = bs;
+        C.A.n = C.N;
+        C.A.nnzb = (int64_t)col.size();
+        EFT_TRY(dput(ctx, &C.A.rowptr, rowptr));
+        EFT_TRY(dput(ctx, &C.A.col, col));
+        EFT_TRY(dput(ctx, &C.A.diag, diag));
+        EFT_TRY(dmal(ctx, &C.A.val, C.A.nnzb * bs * bs));
+        EFT_TRY(dmal(ctx, &C.va, C.N * d));
+        EFT_TRY(dmal(ctx, &C.acc, C.N * d));
+        EFT_TRY(dmal(ctx, &C.rho, C.N));
+        EFT_TRY(dmal(ctx, &C.mu, C.N));
+        EFT_TRY(dmal(ctx, &C.as, C.N * std::max(ctx->n_s, 1)));
+        EFT_TRY(dmal(ctx, &C.Ba, C.N * nv * std::max(ctx->n_s, 1)));
+        EFT_TRY(dmal(ctx, &C.vp, C.N * bs));
+        EFT_TRY(dmal(ctx, &C.R, C.N * bs));
+        EFT_TRY(dmal(ctx, &C.Dinv, C.N * bs * bs));
+        EFT_TRY(dmal(ctx, &C.x, C.N * bs));
+        EFT_TRY(dmal(ctx, &C.x2, C.N * bs));
+        EFT_TRY(dmal(ctx, &C.b, C.N * bs));
+        EFT_TRY(dmal(ctx, &C.r, C.N * bs));
+        inj_prev = inj;
+        ctx->mg.push_back(C);
+    }
+    if (ctx->mg.size() < 2) {
+        eft_mg_free(ctx);
+        return EFT_OK;
+    }
+    const MGLevel &Lc = ctx->mg.back();
+    ctx->mg_nd = Lc.N * bs;
+    if (ctx->mg_nd <= 512) {
+        EFT_TRY(dmal(ctx, &ctx->mg_dense, ctx->mg_nd * ctx->mg_nd));
+        EFT_TRY(dmal(ctx, &ctx->mg_inv, ctx->mg_nd * ctx->mg_nd));
+    }
+    return EFT_OK;
+}
+
+void eft_mg_free(eft_ctx *ctx)
+{
+    auto fr = [](void *p) {
+        if (p) (void)hipFree(p);
+    };
+    for (size_t l = 0; l < ctx->mg.size(); ++l) {
+        MGLevel &L = ctx->mg[l];
+        if (l > 0) {
+            fr(L.conn); fr(L.epos); fr(L.inj); fr(L.xyz); fr(L.va); fr(L.acc); fr(L.rho); fr(L.mu); fr(L.as);
+            fr(L.Ba); fr(L.vp); fr(L.R); fr(L.dir_node); fr(L.dir_mask); fr(L.A.rowptr); fr(L.A.col); fr(L.A.diag);
+            fr(L.A.val); fr(L.b);
+        }
+        fr(L.fmask); fr(L.Dinv); fr(L.x); fr(L.x2); fr(L.r);
+    }
+    ctx->mg.clear();
+    fr(ctx->mg_dense);
+    fr(ctx->mg_inv);
+    ctx->mg_dense = ctx->mg_inv = nullptr;
+    ctx->mg_nd = 0;
+}
+
+bool eft_mg_active(const eft_ctx *ctx, const eft_matrix *A)
+{
+    return ctx->par.precond == 1 && ctx->mg.size() >= 2 && A == &ctx->J;
+}
+
+// Refresh the hierarchy for the current Jacobian: inject node fields,
+// rediscretize the coarse Jacobians, block inverses and the coarsest inverse.
+eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
+{
+    const int bs = ctx->bs;
+    const int64_t L = (int64_t)ctx->mg.size();
+    EFT_TRY(eft_bj_setup(ctx, &ctx->J, ctx->mg[0].Dinv));
+    for (int64_t l = 1; l < L; ++l) {
+        MGLevel &C = ctx->mg[l];
+        InjArgs a;
+        a.Nc = C.N;
+        a.Nf = ctx->N;
+        a.d = ctx->dim;
+        a.bs = bs;
+        a.nv = ctx->nv;
+        a.n_s = ctx->n_s;
+        a.inj = C.inj;
+        a.va = ctx->va;
+        a.acc = ctx->acc;
+        a.rho = ctx->rho;
+        a.mu = ctx->mu;
+        a.as = ctx->as;
+        a.Ba = ctx->Ba;
+        a.vp = vp;
+        a.cva = C.va;
+        a.cacc = C.acc;
+        a.crho = C.rho;
+        a.cmu = C.mu;
+        a.cas = C.as;
+        a.cBa = C.Ba;
+        a.cvp = C.vp;
+        hipLaunchKernelGGL(k_inject, dim3(eft_grid(C.N, 256)), dim3(256), 0, ctx->stream, a);
+        EFT_HIP(hipGetLastError());
+        MeshView M;
+        M.N = C.N;
+        M.E = C.E;
+        M.conn = C.conn;
+        M.epos = C.epos;
+        M.xyz = C.xyz;
+        M.va = C.va;
+        M.acc = C.acc;
+        M.rho = C.rho;
+        M.mu = C.mu;
+        M.as = C.as;
+        M.Ba = C.Ba;
+        M.n_dir = C.n_dir;
+        M.dir_node = C.dir_node;
+        M.dir_mask = C.dir_mask;
+        EFT_TRY(eft_ns_level(ctx, M, C.vp, C.R, &C.A));
+        EFT_TRY(eft_bj_setup(ctx, &C.A, C.Dinv));
+    }
+    if (ctx->mg_inv) {
+        const MGLevel &Cc = ctx->mg.back();
+        hipLaunchKernelGGL(k_dense_fill, dim3(eft_grid(Cc.N, 64)), dim3(64), 0, ctx->stream, Cc.N, bs, Cc.A.rowptr,
+                           Cc.A.col, Cc.A.val, ctx->mg_dense, ctx->mg_nd);
+        hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(256), 0, ctx->stream, ctx->mg_dense, ctx->mg_inv,
+                           (int)ctx->mg_nd);
+        EFT_HIP(hipGetLastError());
+    }
+    return EFT_OK;
+}
+
+namespace {
+
+template <typename TV>
+void launch_sweep(eft_ctx *ctx, const eft_matrix &A, const TV *val, const double *Dinv, double omega,
+                  const double *b, const double *x, double *xo, const int32_t *flag)
+{
+    if (A.bs == 4)
+        hipLaunchKernelGGL(k_sweep4<TV>, dim3(eft_grid(A.n, 4)), dim3(256), 0, ctx->stream, A.n, A.rowptr, A.col, val,
+                           Dinv, omega, b, x, xo, flag);
+    else
+        hipLaunchKernelGGL(k_sweepb<TV>, dim3(eft_grid(A.n, 4)), dim3(256), 0, ctx->stream, A.n, A.bs, A.rowptr, A.col,
+                           val, Dinv, omega, b, x, xo, flag);
+}
+
+template <typename TV>
+void launch_resid(eft_ctx *ctx, const eft_matrix &A, const TV *val, const double *b, const double *x, double *r,
+                  const int32_t *flag)
+{
+    if (A.bs == 4)
+        hipLaunchKernelGGL(k_resid4<TV>, dim3(eft_grid(A.n, 4)), dim3(256), 0, ctx->stream, A.n, A.rowptr, A.col, val,
+                           b, x, r, flag);
+    else
+        hipLaunchKernelGGL(k_residb<TV>, dim3(eft_grid(A.n, 4)), dim3(256), 0, ctx->stream, A.n, A.bs, A.rowptr, A.col,
+                           val, b, x, r, flag);
+}
+
+void sweep(eft_ctx *ctx, const eft_matrix &A, const double *Dinv, const double *b, const double *x, double *xo,
+           const int32_t *flag)
+{
+    if (A.fp32) launch_sweep<float>(ctx, A, A.val32, Dinv, ctx->mg_omega, b, x, xo, flag);
+    else launch_sweep<double>(ctx, A, A.val, Dinv, ctx->mg_omega, b, x, xo, flag);
+}
+
+void resid(eft_ctx *ctx, const eft_matrix &A, const double *b, const double *x, double *r, const int32_t *flag)
+{
+    if (A.fp32) launch_resid<float>(ctx, A, A.val32, b, x, r, flag);
+    else launch_resid<double>(ctx, A, A.val, b, x, r, flag);
+}
+
+// V-cycle on level l with right-hand side b; returns the buffer holding x
+double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag)
+{
+    MGLevel &L = ctx->mg[l];
+    const eft_matrix &A = l == 0 ? ctx->J : L.A;
+    const int bs = ctx->bs;
+    const int64_t nd = L.N * bs;
+    double *cur = L.x, *oth = L.x2;
+    const bool last = l + 1 == (int)ctx->mg.size();
+    if (last && ctx->mg_inv) {
+        hipLaunchKernelGGL(k_dense_apply, dim3(1), dim3(256), 0, ctx->stream, ctx->mg_inv, (int)ctx->mg_nd, b, cur, flag);
+        return cur;
+    }
+    hipLaunchKernelGGL(k_sweep0, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, nd, bs, L.Dinv, ctx->mg_omega, b,
+                       cur, flag);
+    const int nu = last ? 40 : ctx->mg_nu;
+    for (int s = 1; s < nu; ++s) {
+        sweep(ctx, A, L.Dinv, b, cur, oth, flag);
+        std::swap(cur, oth);
+    }
+    if (last) return cur;
+    MGLevel &C = ctx->mg[l + 1];
+    resid(ctx, A, b, cur, L.r, flag);
+    const Dims fd = dims_of(L), cd = dims_of(C);
+    if (ctx->dim == 2)
+        hipLaunchKernelGGL(k_restrict<2>, dim3(eft_grid(C.N, 256)), dim3(256), 0, ctx->stream, cd, fd, bs, C.fmask,
+                           L.fmask, L.r, C.b, flag);
+    else
+        hipLaunchKernelGGL(k_restrict<3>, dim3(eft_grid(C.N, 256)), dim3(256), 0, ctx->stream, cd, fd, bs, C.fmask,
+                           L.fmask, L.r, C.b, flag);
+    double *xc = vcycle(ctx, l + 1, C.b, flag);
+    hipLaunchKernelGGL(k_prolong, dim3(eft_grid(L.N, 256)), dim3(256), 0, ctx->stream, cd, fd, bs, C.fmask, L.fmask, xc,
+                       cur, flag);
+    for (int s = 0; s < ctx->mg_nu; ++s) {
+        sweep(ctx, A, L.Dinv, b, cur, oth, flag);
+        std::swap(cur, oth);
+    }
+    return cur;
+}
+
+}  // namespace
+
+// z = M^-1 b0 with one V-cycle
+eft_status eft_mg_vcycle(eft_ctx *ctx, const double *b0, double *z, const int32_t *flag)
+{
+    MGLevel &L0 = ctx->mg[0];
+    double *x = vcycle(ctx, 0, b0, flag);
+    EFT_HIP(hipGetLastError());
+    EFT_HIP(hipMemcpyAsync(z, x, sizeof(double) * L0.N * ctx->bs, hipMemcpyDeviceToDevice, ctx->stream));
+    return EFT_OK;
+}

@@ -11,13 +11,15 @@
 template <typename TV> __device__ __forceinline__ double ld(const TV *p) { return (double)*p; }
 
 // bs = 4: shuffle reduction over the 4 columns and the 4 block slots.
-template <typename TV>
+// GATED instances (inside the Krylov loop) return at once when the solve has
+// converged; the plain instances always do the full product.
+template <typename TV, bool GATED>
 __global__ __launch_bounds__(256) void k_spmv4(int64_t n, const int32_t *__restrict__ rowptr,
                                                const int32_t *__restrict__ col, const TV *__restrict__ val,
                                                const double *__restrict__ x, double *__restrict__ y,
                                                const int32_t *active)
 {
-    if (active && *active == 0) return;
+    if (GATED && *active == 0) return;
     const int lane = threadIdx.x & 63;
     const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (row >= n) return;
@@ -90,8 +92,12 @@ static void spmv_launch(eft_ctx *ctx, int64_t n, int bs, const int32_t *rowptr, 
         hipLaunchKernelGGL(k_spmv1<TV>, dim3(eft_grid(n, 16)), dim3(256), 0, ctx->stream, n, rowptr, col, val, x, y,
                            active);
     } else if (bs == 4) {
-        hipLaunchKernelGGL(k_spmv4<TV>, dim3(eft_grid(n, 4)), dim3(256), 0, ctx->stream, n, rowptr, col, val, x, y,
-                           active);
+        if (active)
+            hipLaunchKernelGGL((k_spmv4<TV, true>), dim3(eft_grid(n, 4)), dim3(256), 0, ctx->stream, n, rowptr, col,
+                               val, x, y, active);
+        else
+            hipLaunchKernelGGL((k_spmv4<TV, false>), dim3(eft_grid(n, 4)), dim3(256), 0, ctx->stream, n, rowptr, col,
+                               val, x, y, active);
     } else {
         hipLaunchKernelGGL(k_spmvb<TV>, dim3(eft_grid(n, 4)), dim3(256), 0, ctx->stream, n, bs, rowptr, col, val, x,
                            y, active);

@@ -257,7 +257,7 @@ class Context:
         info = SolveInfo()
         st = self._check(self.L.eft_fgmres(self.ctx, self.J, _ptr(b), _ptr(x), C.byref(info)), allow=(ENOTCONV,))
         return x, dict(status=st, iters=info.iters, restarts=info.restarts, converged=info.converged,
-                       rel_res=info.rel_res)
+                       rel_res=info.rel_res, fallback=info.fallback_used)
 
     def bands_build(self, lvl):
         self._check(self.L.eft_bands_build(self.ctx, C.byref(self._state(lvl))))

@@ -149,7 +149,7 @@ class Params:
     lin_rtol: float = 1e-8
     restart: int = 50
     lin_maxit: int = 1000
-    precond: int = 0
+    precond: int = 1          # 1: geometric multigrid (structured boxes), 0: point-block Jacobi
     precision: int = 0
     band_flat: float = 1e-6
     band_cell: int = 4
