@@ -90,13 +90,13 @@ void free_all(eft_ctx *ctx)
     auto fr = [](void *p) {
         if (p) (void)hipFree(p);
     };
-    fr(ctx->xyz); fr(ctx->conn); fr(ctx->epos); fr(ctx->cell_of); fr(ctx->dir_node); fr(ctx->dir_mask);
+    fr(ctx->xyz); fr(ctx->conn); fr(ctx->epos); fr(ctx->iptr); fr(ctx->ient); fr(ctx->cell_of); fr(ctx->dir_node); fr(ctx->dir_mask);
     fr(ctx->dir_val); fr(ctx->phase_tab); fr(ctx->ind_of_phase);
     fr(ctx->J.rowptr); fr(ctx->J.col); fr(ctx->J.diag); fr(ctx->J.val); fr(ctx->J.val32);
     fr(ctx->va); fr(ctx->acc); fr(ctx->rho); fr(ctx->mu); fr(ctx->as); fr(ctx->Ba); fr(ctx->R); fr(ctx->dx);
     fr(ctx->l_vp); fr(ctx->l_vdot); fr(ctx->l_phi); fr(ctx->l_phidot); fr(ctx->l_B); fr(ctx->l_Bdot);
     for (Band &B : ctx->band) {
-        fr(B.node); fr(B.elem); fr(B.epos); fr(B.bconn_); fr(B.fre); fr(B.rowptr); fr(B.col); fr(B.diag);
+        fr(B.node); fr(B.elem); fr(B.epos); fr(B.bconn_); fr(B.fre); fr(B.eflag); fr(B.rowptr); fr(B.col); fr(B.diag);
     }
     fr(ctx->seed); fr(ctx->active); fr(ctx->nin); fr(ctx->nout); fr(ctx->ein); fr(ctx->g2b); fr(ctx->gpos2b);
     fr(ctx->scan_tmp); fr(ctx->bR); fr(ctx->bX); fr(ctx->bval); fr(ctx->tnum); fr(ctx->tden); fr(ctx->red);
@@ -283,8 +283,8 @@ eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *
             return EFT_EINVAL;
         }
     }
-    std::vector<int32_t> rowptr, col, diag, epos;
-    EFT_TRY(eft_build_graph(N, E, nn, conn, rowptr, col, diag, epos, ctx->err));
+    std::vector<int32_t> rowptr, col, diag, epos, iptr, ient;
+    EFT_TRY(eft_build_graph(N, E, nn, conn, rowptr, col, diag, epos, iptr, ient, ctx->maxc, ctx->rpb, ctx->err));
     const int64_t nnzb = (int64_t)col.size();
     // band grid: cells of band_cell mesh cells, element -> cell of its centroid
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
@@ -320,6 +320,8 @@ eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *
     EFT_TRY(upload(ctx, &ctx->xyz, mesh->xyz, N * d));
     EFT_TRY(upload(ctx, &ctx->conn, conn, E * nn));
     EFT_TRY(upload(ctx, &ctx->epos, epos.data(), E * nn * nn));
+    EFT_TRY(upload(ctx, &ctx->iptr, iptr.data(), N + 1));
+    EFT_TRY(upload(ctx, &ctx->ient, ient.data(), E * nn));
     EFT_TRY(upload(ctx, &ctx->cell_of, cell_of.data(), E));
     ctx->n_dir = mesh->n_dir;
     if (mesh->n_dir > 0) {

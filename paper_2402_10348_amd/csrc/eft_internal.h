@@ -55,8 +55,9 @@ struct Band {
     int32_t *epos = nullptr;                   // [ne][nn*nn] position in band pattern
     int32_t *bconn_ = nullptr;                 // [ne][nn] band-local node ids
     uint8_t *fre = nullptr;                    // [n] 1 if the node is solved for
+    uint8_t *eflag = nullptr;                  // [E] 1 for band elements
     int32_t *rowptr = nullptr, *col = nullptr, *diag = nullptr;
-    int64_t cap[8] = {0, 0, 0, 0, 0, 0, 0, 0}; // allocation sizes in bytes
+    int64_t cap[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}; // allocation sizes in bytes
 };
 
 // One level of the mesh with the node fields the element kernels read.
@@ -68,6 +69,8 @@ struct MeshView {
     int64_t n_dir = 0;
     const int32_t *dir_node = nullptr;
     const uint8_t *dir_mask = nullptr;
+    const int32_t *iptr = nullptr, *ient = nullptr;  // node -> (element << 2 | local node)
+    int maxc = 0, rpb = 1;                           // longest matrix row, rows per workgroup
 };
 
 // One level of the geometric multigrid hierarchy on nested Kuhn meshes.
@@ -77,6 +80,8 @@ struct MGLevel {
     int n[3] = {1, 1, 1};            // cells per axis
     int64_t N = 0, E = 0;
     int32_t *conn = nullptr, *epos = nullptr, *inj = nullptr;  // inj: fine-mesh node of each node
+    int32_t *iptr = nullptr, *ient = nullptr;
+    int maxc = 0, rpb = 1;
     double *xyz = nullptr;
     double *va = nullptr, *acc = nullptr, *rho = nullptr, *mu = nullptr, *as = nullptr, *Ba = nullptr;
     double *vp = nullptr, *R = nullptr;
@@ -106,6 +111,8 @@ struct eft_ctx {
     double *xyz = nullptr;
     int32_t *conn = nullptr;
     int32_t *epos = nullptr;        // [E][nn*nn] position of (a,b) in the NS pattern
+    int32_t *iptr = nullptr, *ient = nullptr;  // node -> incident (element << 2 | local node)
+    int maxc = 0, rpb = 1;          // longest row of the node graph, rows per assembly workgroup
     int32_t *cell_of = nullptr;     // [E] band grid cell of each element
     int64_t n_dir = 0;
     int32_t *dir_node = nullptr;
@@ -204,6 +211,7 @@ void eft_mg_free(eft_ctx *ctx);
 bool eft_mg_active(const eft_ctx *ctx, const eft_matrix *A);
 eft_status eft_build_graph(int64_t N, int64_t E, int nn, const int32_t *conn, std::vector<int32_t> &rowptr,
                            std::vector<int32_t> &col, std::vector<int32_t> &diag, std::vector<int32_t> &epos,
+                           std::vector<int32_t> &iptr, std::vector<int32_t> &ient, int &maxc, int &rpb,
                            std::string &err);
 eft_status eft_fill(eft_ctx *ctx, double *p, int64_t n, double v);
 eft_status eft_fill32(eft_ctx *ctx, float *p, int64_t n, float v);

@@ -80,169 +80,264 @@ __global__ __launch_bounds__(256) void k_props(PropsArgs a)
     }
 }
 
-// ------------------------------------------------------------ fluid part --
+// ------------------------------------------------------ row-owned kernel --
 
-struct NSArgs {
-    int64_t E;
-    const int32_t *conn, *epos;
+// One workgroup owns a block of consecutive matrix rows.  Every (row node,
+// incident element) pair is one thread: it evaluates the element (geometry,
+// quadrature-point state, tau_m and tau_c) and adds that element's share of
+// the row -- the residual of the row node and the blocks coupling it to the
+// element's nodes -- into LDS accumulators.  Each element is thus evaluated
+// once per node (4 times in 3D) instead of scattering 16 blocks with global
+// atomics; the finished rows are written once, contiguously.
+struct RowArgs {
+    int64_t N;                   // rows (nodes)
+    int rpb, maxc;               // rows per workgroup, longest row (LDS layout)
+    const int32_t *iptr, *ient;  // node -> incident (element << 2 | local node)
+    const int32_t *conn, *epos, *rowptr;
     const double *xyz, *va, *acc, *vp, *rho, *mu;
-    double ct, alpha, dt, C_I, g0, g1, g2;
+    int n_s;
+    const double *as, *Ba, *muL;
+    double ct, alpha, kappa, dt, C_I, g0, g1, g2;
     double *R;
 };
 
-template <typename T> __device__ __forceinline__ void atomic_add(T *p, double v);
-template <> __device__ __forceinline__ void atomic_add<double>(double *p, double v) { unsafeAtomicAdd(p, v); }
-template <> __device__ __forceinline__ void atomic_add<float>(float *p, double v) { unsafeAtomicAdd(p, (float)v); }
-
 template <int D, typename TJ>
-__global__ __launch_bounds__(128) void k_ns_fluid(NSArgs a, TJ *__restrict__ Jv)
+__global__ __launch_bounds__(256) void k_ns_rows(RowArgs a, TJ *__restrict__ Jv)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= a.E) return;
-    constexpr int NN = D + 1, BS = D + 1, NQ = Rule<D>::NQ;
+    extern __shared__ double lds[];
+    constexpr int NN = D + 1, BS = D + 1, B2 = BS * BS, NQ = Rule<D>::NQ, NVv = NV<D>::v;
+    const int64_t r0 = (int64_t)blockIdx.x * a.rpb;
+    const int64_t r1 = r0 + a.rpb < a.N ? r0 + a.rpb : a.N;
+    double *accJ = lds;                                 // [rpb][maxc][B2]
+    double *accR = lds + (int64_t)a.rpb * a.maxc * B2;  // [rpb][BS]
+    const int nacc = a.rpb * a.maxc * B2 + a.rpb * BS;
+    for (int t = threadIdx.x; t < nacc; t += blockDim.x) lds[t] = 0.0;
+    __syncthreads();
     const double gv[3] = {a.g0, a.g1, a.g2};
-    int nd[NN];
-    double X[NN][D], v[NN][D], ac[NN][D], p[NN], rh[NN], mu[NN];
-#pragma unroll
-    for (int b = 0; b < NN; ++b) {
-        nd[b] = a.conn[e * NN + b];
-        const int64_t n = nd[b];
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            X[b][i] = a.xyz[n * D + i];
-            v[b][i] = a.va[n * D + i];
-            ac[b][i] = a.acc[n * D + i];
-        }
-        p[b] = a.vp[n * BS + D];
-        rh[b] = a.rho[n];
-        mu[b] = a.mu[n];
-    }
-    double dN[NN][D], G[D][D];
-    const double vol = simplex_geom<D>(X, dN, G);
-    double GG = 0.0, trG = 0.0;
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-        trG += G[i][i];
-#pragma unroll
-        for (int j = 0; j < D; ++j) GG += G[i][j] * G[i][j];
-    }
-    double L[D][D], gp[D], divv = 0.0;
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            double s = 0.0;
-#pragma unroll
-            for (int b = 0; b < NN; ++b) s += v[b][i] * dN[b][j];
-            L[i][j] = s;
-        }
-        double s = 0.0;
-#pragma unroll
-        for (int b = 0; b < NN; ++b) s += p[b] * dN[b][i];
-        gp[i] = s;
-    }
-#pragma unroll
-    for (int i = 0; i < D; ++i) divv += L[i][i];
-
-    const double w = vol * Rule<D>::WF;
-    const double inv4dt2 = 4.0 / (a.dt * a.dt);
-    double rl[NN][BS];
-#pragma unroll
-    for (int b = 0; b < NN; ++b)
-#pragma unroll
-        for (int i = 0; i < BS; ++i) rl[b][i] = 0.0;
-    double W[NN][NQ], U[NN][NQ], TM[NQ];
-    double muI = 0.0, Tc = 0.0, Tp = 0.0;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        double rq = 0.0, mq = 0.0, pq = 0.0, vq[D], aq[D];
-#pragma unroll
-        for (int i = 0; i < D; ++i) vq[i] = aq[i] = 0.0;
+    const int i0 = a.iptr[r0], i1 = a.iptr[r1];
+    for (int ii = i0 + threadIdx.x; ii < i1; ii += blockDim.x) {
+        const int32_t ent = a.ient[ii];
+        const int64_t e = ent >> 2;
+        const int la = ent & 3;
+        int nd[NN];
+        double X[NN][D], v[NN][D], ac[NN][D], p[NN], rh[NN], mu[NN];
 #pragma unroll
         for (int b = 0; b < NN; ++b) {
-            const double Nb = shape_at<D>(q, b);
-            rq += Nb * rh[b];
-            mq += Nb * mu[b];
-            pq += Nb * p[b];
+            nd[b] = a.conn[e * NN + b];
+            const int64_t n = nd[b];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                vq[i] += Nb * v[b][i];
-                aq[i] += Nb * ac[b][i];
+                X[b][i] = a.xyz[n * D + i];
+                v[b][i] = a.va[n * D + i];
+                ac[b][i] = a.acc[n * D + i];
             }
+            p[b] = a.vp[n * BS + D];
+            rh[b] = a.rho[n];
+            mu[b] = a.mu[n];
         }
-        double Lv[D], vGv = 0.0;
+        const int64_t row = nd[la];
+        const int lr = (int)(row - r0);
+        double dN[NN][D], G[D][D];
+        const double vol = simplex_geom<D>(X, dN, G);
+        double GG = 0.0, trG = 0.0;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            double s = 0.0, t = 0.0;
+            trG += G[i][i];
+#pragma unroll
+            for (int j = 0; j < D; ++j) GG += G[i][j] * G[i][j];
+        }
+        double L[D][D], gp[D], divv = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                s += L[i][j] * vq[j];
-                t += G[i][j] * vq[j];
+                double s = 0.0;
+#pragma unroll
+                for (int b = 0; b < NN; ++b) s += v[b][i] * dN[b][j];
+                L[i][j] = s;
             }
-            Lv[i] = s;
-            vGv += vq[i] * t;
-        }
-        double Rm[D], body[D];
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            body[i] = aq[i] + Lv[i] - gv[i];
-            Rm[i] = rq * body[i] + gp[i];
-        }
-        const double nu = mq / rq;
-        const double tau_m = 1.0 / sqrt(inv4dt2 + vGv + a.C_I * nu * nu * GG);
-        const double tau_c = 1.0 / (trG * tau_m);
-        double u[NN];
-#pragma unroll
-        for (int b = 0; b < NN; ++b) {
             double s = 0.0;
 #pragma unroll
-            for (int j = 0; j < D; ++j) s += vq[j] * dN[b][j];
-            u[b] = s;
+            for (int b = 0; b < NN; ++b) s += p[b] * dN[b][i];
+            gp[i] = s;
         }
 #pragma unroll
-        for (int b = 0; b < NN; ++b) {
-            const double Nb = shape_at<D>(q, b);
+        for (int i = 0; i < D; ++i) divv += L[i][i];
+        const double w = vol * Rule<D>::WF;
+        const double inv4dt2 = 4.0 / (a.dt * a.dt);
+        double rl[BS];
+#pragma unroll
+        for (int i = 0; i < BS; ++i) rl[i] = 0.0;
+        double Wa[NQ], U[NN][NQ], TM[NQ];
+        double muI = 0.0, Tc = 0.0, Tp = 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            double rq = 0.0, mq = 0.0, pq = 0.0, vq[D], aq[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) vq[i] = aq[i] = 0.0;
+#pragma unroll
+            for (int b = 0; b < NN; ++b) {
+                const double Nb = shape_at<D>(q, b);
+                rq += Nb * rh[b];
+                mq += Nb * mu[b];
+                pq += Nb * p[b];
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    vq[i] += Nb * v[b][i];
+                    aq[i] += Nb * ac[b][i];
+                }
+            }
+            double Lv[D], vGv = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                double s = 0.0, t = 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    s += L[i][j] * vq[j];
+                    t += G[i][j] * vq[j];
+                }
+                Lv[i] = s;
+                vGv += vq[i] * t;
+            }
+            double Rm[D], body[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                body[i] = aq[i] + Lv[i] - gv[i];
+                Rm[i] = rq * body[i] + gp[i];
+            }
+            const double nu = mq / rq;
+            const double tau_m = 1.0 / sqrt(inv4dt2 + vGv + a.C_I * nu * nu * GG);
+            const double tau_c = 1.0 / (trG * tau_m);
+#pragma unroll
+            for (int b = 0; b < NN; ++b) {
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) s += vq[j] * dN[b][j];
+                U[b][q] = s;
+            }
+            const double Na = shape_at<D>(q, la);
+            const double ua = U[la][q];
             double gR = 0.0;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                double sd = -pq * dN[b][i];
+                double sd = -pq * dN[la][i];
 #pragma unroll
-                for (int j = 0; j < D; ++j) sd += mq * (L[i][j] + L[j][i]) * dN[b][j];
-                rl[b][i] += w * (Nb * rq * body[i] + sd + tau_m * u[b] * Rm[i] + tau_c * rq * dN[b][i] * divv);
-                gR += dN[b][i] * Rm[i];
+                for (int j = 0; j < D; ++j) sd += mq * (L[i][j] + L[j][i]) * dN[la][j];
+                rl[i] += w * (Na * rq * body[i] + sd + tau_m * ua * Rm[i] + tau_c * rq * dN[la][i] * divv);
+                gR += dN[la][i] * Rm[i];
             }
-            rl[b][D] += w * (Nb * divv + (tau_m / rq) * gR);
-            W[b][q] = w * rq * (Nb + tau_m * u[b]);
-            U[b][q] = u[b];
+            rl[D] += w * (Na * divv + (tau_m / rq) * gR);
+            Wa[q] = w * rq * (Na + tau_m * ua);
+            TM[q] = w * tau_m;
+            muI += w * mq;
+            Tc += w * tau_c * rq;
+            Tp += w * tau_m / rq;
         }
-        TM[q] = w * tau_m;
-        muI += w * mq;
-        Tc += w * tau_c * rq;
-        Tp += w * tau_m / rq;
-    }
+        // elastic stress mu_L (B - I) of every solid present on the element,
+        // and the sums its tangent needs (the dB/dv tangent is linear in them):
+        //   M2       = sum_s int alpha_s mu_L,s B_s
+        //   T[b][i][k] = sum_s (int N_b alpha_s mu_L,s) (dB_s/dx_k grad N_a)_i
+        double M2[D][D], T[NN][D][D];
+        bool solid = false;
 #pragma unroll
-    for (int b = 0; b < NN; ++b)
+        for (int i = 0; i < D; ++i)
 #pragma unroll
-        for (int i = 0; i < BS; ++i) unsafeAtomicAdd(a.R + (int64_t)nd[b] * BS + i, rl[b][i]);
-    if (Jv == nullptr) return;
-
-    const double al = a.alpha, ct = a.ct;
-    // integral of one shape function with the rule: w * (QA + (NQ-1) QB)
-    const double NI = w * (Rule<D>::QA + (NQ - 1) * Rule<D>::QB);
-    const int32_t *ep = a.epos + e * NN * NN;
+            for (int j = 0; j < D; ++j) M2[i][j] = 0.0;
 #pragma unroll
-    for (int ia = 0; ia < NN; ++ia) {
+        for (int b = 0; b < NN; ++b)
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int k = 0; k < D; ++k) T[b][i][k] = 0.0;
+        for (int sI = 0; sI < a.n_s; ++sI) {
+            double asn[NN];
+            bool any = false;
+#pragma unroll
+            for (int b = 0; b < NN; ++b) {
+                asn[b] = a.as[(int64_t)sI * a.N + nd[b]];
+                any |= asn[b] != 0.0;
+            }
+            if (!any) continue;
+            solid = true;
+            const double muL = a.muL[sI];
+            double Bn[NN][NVv];
+#pragma unroll
+            for (int b = 0; b < NN; ++b)
+#pragma unroll
+                for (int c = 0; c < NVv; ++c) Bn[b][c] = a.Ba[((int64_t)sI * a.N + nd[b]) * NVv + c];
+            double Wbs[NN];
+#pragma unroll
+            for (int b = 0; b < NN; ++b) Wbs[b] = 0.0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                double aq = 0.0, bq[NVv];
+#pragma unroll
+                for (int c = 0; c < NVv; ++c) bq[c] = 0.0;
+#pragma unroll
+                for (int b = 0; b < NN; ++b) {
+                    const double Nb = shape_at<D>(q, b);
+                    aq += Nb * asn[b];
+#pragma unroll
+                    for (int c = 0; c < NVv; ++c) bq[c] += Nb * Bn[b][c];
+                }
+                double Bq[D][D];
+                vfull<D>(bq, Bq);
+                const double f = aq * muL;
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    double s2 = 0.0;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) s2 += (Bq[i][j] - (i == j ? 1.0 : 0.0)) * dN[la][j];
+                    rl[i] += w * f * s2;
+                }
+#pragma unroll
+                for (int b = 0; b < NN; ++b) Wbs[b] += w * shape_at<D>(q, b) * f;
+#pragma unroll
+                for (int i = 0; i < D; ++i)
+#pragma unroll
+                    for (int j = 0; j < D; ++j) M2[i][j] += w * f * Bq[i][j];
+            }
+            if (Jv == nullptr) continue;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                double gk[NVv];
+#pragma unroll
+                for (int c = 0; c < NVv; ++c) {
+                    double s2 = 0.0;
+#pragma unroll
+                    for (int b = 0; b < NN; ++b) s2 += dN[b][k] * Bn[b][c];
+                    gk[c] = s2;
+                }
+                double gf[D][D];
+                vfull<D>(gk, gf);
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    double Dk = 0.0;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) Dk += gf[i][j] * dN[la][j];
+#pragma unroll
+                    for (int b = 0; b < NN; ++b) T[b][i][k] += Wbs[b] * Dk;
+                }
+            }
+        }
+        // residual of the row node
+#pragma unroll
+        for (int i = 0; i < BS; ++i) atomicAdd(accR + lr * BS + i, rl[i]);
+        if (Jv == nullptr) continue;
+        const double al = a.alpha, ct = a.ct;
+        const double NI = w * (Rule<D>::QA + (NQ - 1) * Rule<D>::QB);
         double Pa = 0.0;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) Pa += TM[q] * U[ia][q];
+        for (int q = 0; q < NQ; ++q) Pa += TM[q] * U[la][q];
         double aL[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             double s = 0.0;
 #pragma unroll
-            for (int j = 0; j < D; ++j) s += dN[ia][j] * L[j][k];
+            for (int j = 0; j < D; ++j) s += dN[la][j] * L[j][k];
             aL[k] = s;
         }
+        const int64_t rbase = a.rowptr[row];
 #pragma unroll
         for (int ib = 0; ib < NN; ++ib) {
             double A = 0.0, C = 0.0, Q1 = 0.0, Q2 = 0.0;
@@ -250,177 +345,52 @@ __global__ __launch_bounds__(128) void k_ns_fluid(NSArgs a, TJ *__restrict__ Jv)
             for (int q = 0; q < NQ; ++q) {
                 const double Nb = shape_at<D>(q, ib);
                 const double lin = ct * Nb + al * U[ib][q];
-                A += W[ia][q] * lin;
-                C += W[ia][q] * Nb;
+                A += Wa[q] * lin;
+                C += Wa[q] * Nb;
                 Q1 += TM[q] * lin;
                 Q2 += TM[q] * Nb;
             }
             C *= al;
             double gab = 0.0;
 #pragma unroll
-            for (int j = 0; j < D; ++j) gab += dN[ia][j] * dN[ib][j];
-            TJ *blk = Jv + (int64_t)ep[ia * NN + ib] * (BS * BS);
+            for (int j = 0; j < D; ++j) gab += dN[la][j] * dN[ib][j];
+            const int slot = (int)(a.epos[e * NN * NN + la * NN + ib] - rbase);
+            double *blk = accJ + ((int64_t)lr * a.maxc + slot) * B2;
+            double Mb[D], aMb = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                double s2 = 0.0;
+#pragma unroll
+                for (int l = 0; l < D; ++l) s2 += M2[i][l] * dN[ib][l];
+                Mb[i] = s2;
+                aMb += dN[la][i] * s2;
+            }
+            const double ak = solid ? al * a.kappa : 0.0;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
-                    double val = C * L[i][k] + al * muI * dN[ia][k] * dN[ib][i] + al * Tc * dN[ia][i] * dN[ib][k];
+                    double val = C * L[i][k] + al * muI * dN[la][k] * dN[ib][i] + al * Tc * dN[la][i] * dN[ib][k];
                     if (i == k) val += A + al * muI * gab;
-                    atomic_add<TJ>(blk + i * BS + k, val);
+                    // elastic tangent through dB/dv, eq. (Bext)
+                    val += ak * (-T[ib][i][k] + dN[la][k] * Mb[i] + (i == k ? aMb : 0.0));
+                    atomicAdd(blk + i * BS + k, val);
                 }
-                atomic_add<TJ>(blk + i * BS + D, -dN[ia][i] * NI + Pa * dN[ib][i]);
+                atomicAdd(blk + i * BS + D, -dN[la][i] * NI + Pa * dN[ib][i]);
             }
 #pragma unroll
-            for (int k = 0; k < D; ++k) atomic_add<TJ>(blk + D * BS + k, al * dN[ib][k] * NI + dN[ia][k] * Q1 + al * aL[k] * Q2);
-            atomic_add<TJ>(blk + D * BS + D, Tp * gab);
+            for (int k = 0; k < D; ++k) atomicAdd(blk + D * BS + k, al * dN[ib][k] * NI + dN[la][k] * Q1 + al * aL[k] * Q2);
+            atomicAdd(blk + D * BS + D, Tp * gab);
         }
     }
-}
-
-// ---------------------------------------------------------- elastic part --
-
-struct ElArgs {
-    int64_t E, N;
-    int n_s;
-    const int32_t *conn, *epos;
-    const double *xyz, *as, *Ba, *muL;   // muL [n_s] (device)
-    double alpha, kappa;
-    double *R;
-};
-
-template <int D, typename TJ>
-__global__ __launch_bounds__(128) void k_ns_elastic(ElArgs a, TJ *__restrict__ Jv)
-{
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= a.E) return;
-    constexpr int NN = D + 1, BS = D + 1, NQ = Rule<D>::NQ, NVv = NV<D>::v;
-    int nd[NN];
-#pragma unroll
-    for (int b = 0; b < NN; ++b) nd[b] = a.conn[e * NN + b];
-    bool geo = false;
-    double dN[NN][D], G[D][D], vol = 0.0;
-    for (int s = 0; s < a.n_s; ++s) {
-        double asn[NN];
-        bool any = false;
-#pragma unroll
-        for (int b = 0; b < NN; ++b) {
-            asn[b] = a.as[(int64_t)s * a.N + nd[b]];
-            any |= asn[b] != 0.0;
-        }
-        if (!any) continue;
-        if (!geo) {
-            double X[NN][D];
-#pragma unroll
-            for (int b = 0; b < NN; ++b)
-#pragma unroll
-                for (int i = 0; i < D; ++i) X[b][i] = a.xyz[(int64_t)nd[b] * D + i];
-            vol = simplex_geom<D>(X, dN, G);
-            geo = true;
-        }
-        const double muL = a.muL[s];
-        double Bn[NN][NVv];
-#pragma unroll
-        for (int b = 0; b < NN; ++b)
-#pragma unroll
-            for (int c = 0; c < NVv; ++c) Bn[b][c] = a.Ba[((int64_t)s * a.N + nd[b]) * NVv + c];
-        const double w = vol * Rule<D>::WF;
-        double rl[NN][D], M2[D][D], Wb[NN];
-#pragma unroll
-        for (int b = 0; b < NN; ++b) {
-            Wb[b] = 0.0;
-#pragma unroll
-            for (int i = 0; i < D; ++i) rl[b][i] = 0.0;
-        }
-#pragma unroll
-        for (int i = 0; i < D; ++i)
-#pragma unroll
-            for (int j = 0; j < D; ++j) M2[i][j] = 0.0;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            double aq = 0.0, bq[NVv];
-#pragma unroll
-            for (int c = 0; c < NVv; ++c) bq[c] = 0.0;
-#pragma unroll
-            for (int b = 0; b < NN; ++b) {
-                const double Nb = shape_at<D>(q, b);
-                aq += Nb * asn[b];
-#pragma unroll
-                for (int c = 0; c < NVv; ++c) bq[c] += Nb * Bn[b][c];
-            }
-            double Bq[D][D];
-            vfull<D>(bq, Bq);
-            const double f = aq * muL;
-#pragma unroll
-            for (int b = 0; b < NN; ++b) {
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    double s2 = 0.0;
-#pragma unroll
-                    for (int j = 0; j < D; ++j) s2 += (Bq[i][j] - (i == j ? 1.0 : 0.0)) * dN[b][j];
-                    rl[b][i] += w * f * s2;
-                }
-                Wb[b] += w * shape_at<D>(q, b) * f;
-            }
-#pragma unroll
-            for (int i = 0; i < D; ++i)
-#pragma unroll
-                for (int j = 0; j < D; ++j) M2[i][j] += w * f * Bq[i][j];
-        }
-#pragma unroll
-        for (int b = 0; b < NN; ++b)
-#pragma unroll
-            for (int i = 0; i < D; ++i) unsafeAtomicAdd(a.R + (int64_t)nd[b] * BS + i, rl[b][i]);
+    __syncthreads();
+    for (int64_t r = r0; r < r1; ++r) {
+        const int lr = (int)(r - r0);
+        if (threadIdx.x < BS) a.R[r * BS + threadIdx.x] = accR[lr * BS + threadIdx.x];
         if (Jv == nullptr) continue;
-        // gradient of B (constant on the element), full symmetric matrices
-        double gB[D][D][D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            double gk[NVv];
-#pragma unroll
-            for (int c = 0; c < NVv; ++c) {
-                double s2 = 0.0;
-#pragma unroll
-                for (int b = 0; b < NN; ++b) s2 += dN[b][k] * Bn[b][c];
-                gk[c] = s2;
-            }
-            vfull<D>(gk, gB[k]);
-        }
-        const double ak = a.alpha * a.kappa;
-        const int32_t *ep = a.epos + e * NN * NN;
-#pragma unroll
-        for (int ia = 0; ia < NN; ++ia) {
-            double Dk[D][D];  // Dk[i][k] = (dB/dx_k grad N_a)_i
-#pragma unroll
-            for (int k = 0; k < D; ++k)
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    double s2 = 0.0;
-#pragma unroll
-                    for (int j = 0; j < D; ++j) s2 += gB[k][i][j] * dN[ia][j];
-                    Dk[i][k] = s2;
-                }
-#pragma unroll
-            for (int ib = 0; ib < NN; ++ib) {
-                double Mb[D], aMb = 0.0;
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    double s2 = 0.0;
-#pragma unroll
-                    for (int l = 0; l < D; ++l) s2 += M2[i][l] * dN[ib][l];
-                    Mb[i] = s2;
-                    aMb += dN[ia][i] * s2;
-                }
-                TJ *blk = Jv + (int64_t)ep[ia * NN + ib] * (BS * BS);
-#pragma unroll
-                for (int i = 0; i < D; ++i)
-#pragma unroll
-                    for (int k = 0; k < D; ++k) {
-                        double val = -Wb[ib] * Dk[i][k] + dN[ia][k] * Mb[i];
-                        if (i == k) val += aMb;
-                        atomic_add<TJ>(blk + i * BS + k, ak * val);
-                    }
-            }
-        }
+        const int64_t kb = a.rowptr[r], len = a.rowptr[r + 1] - kb;
+        for (int t = threadIdx.x; t < len * B2; t += blockDim.x)
+            Jv[kb * B2 + t] = (TJ)accJ[(int64_t)lr * a.maxc * B2 + t];
     }
 }
 
@@ -525,63 +495,47 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
 {
     GA ga = ga_of(ctx->par.rho_inf, ctx->par.dt);
     const int BS = ctx->bs;
-    EFT_TRY(eft_fill(ctx, R, M.N * BS, 0.0));
-    if (J) {
-        if (J->fp32)
-            EFT_TRY(eft_fill32(ctx, J->val32, J->nnzb * BS * BS, 0.0f));
-        else
-            EFT_TRY(eft_fill(ctx, J->val, J->nnzb * BS * BS, 0.0));
-    }
-    NSArgs a;
-    a.E = M.E;
+    GA gq = ga;
+    RowArgs a;
+    a.N = M.N;
+    a.rpb = M.rpb;
+    a.maxc = M.maxc;
+    a.iptr = M.iptr;
+    a.ient = M.ient;
     a.conn = M.conn;
     a.epos = M.epos;
+    a.rowptr = J ? J->rowptr : nullptr;
     a.xyz = M.xyz;
     a.va = M.va;
     a.acc = M.acc;
     a.vp = vp;
     a.rho = M.rho;
     a.mu = M.mu;
-    a.ct = ga.ct;
-    a.alpha = ga.alpha;
-    a.dt = ga.dt;
+    a.n_s = ctx->n_s;
+    a.as = M.as;
+    a.Ba = M.Ba;
+    a.muL = ctx->phase_tab + 5 * EFT_MAX_PHASE;  // mu_L of each solid
+    a.ct = gq.ct;
+    a.alpha = gq.alpha;
+    a.kappa = gq.kappa;
+    a.dt = gq.dt;
     a.C_I = ctx->par.C_I;
     a.g0 = ctx->g[0];
     a.g1 = ctx->g[1];
     a.g2 = ctx->g[2];
     a.R = R;
-    ElArgs el;
-    el.E = M.E;
-    el.N = M.N;
-    el.n_s = ctx->n_s;
-    el.conn = M.conn;
-    el.epos = M.epos;
-    el.xyz = M.xyz;
-    el.as = M.as;
-    el.Ba = M.Ba;
-    el.muL = ctx->phase_tab + 5 * EFT_MAX_PHASE;  // mu_L of each solid
-    el.alpha = ga.alpha;
-    el.kappa = ga.kappa;
-    el.R = R;
-    const int nb = eft_grid(M.E, 128);
+    if (!J) {
+        // residual only: one row of accumulators suffices for the pattern-free path
+        a.rowptr = ctx->J.rowptr;
+    }
+    const int nb = eft_grid(M.N, M.rpb);
+    const size_t shm = (size_t)M.rpb * ((size_t)M.maxc * BS * BS + BS) * sizeof(double);
     if (ctx->dim == 2) {
-        if (J && J->fp32) {
-            hipLaunchKernelGGL((k_ns_fluid<2, float>), dim3(nb), dim3(128), 0, ctx->stream, a, J->val32);
-            if (ctx->n_s > 0) hipLaunchKernelGGL((k_ns_elastic<2, float>), dim3(nb), dim3(128), 0, ctx->stream, el, J->val32);
-        } else {
-            double *Jv = J ? J->val : nullptr;
-            hipLaunchKernelGGL((k_ns_fluid<2, double>), dim3(nb), dim3(128), 0, ctx->stream, a, Jv);
-            if (ctx->n_s > 0) hipLaunchKernelGGL((k_ns_elastic<2, double>), dim3(nb), dim3(128), 0, ctx->stream, el, Jv);
-        }
+        if (J && J->fp32) hipLaunchKernelGGL((k_ns_rows<2, float>), dim3(nb), dim3(256), shm, ctx->stream, a, J->val32);
+        else hipLaunchKernelGGL((k_ns_rows<2, double>), dim3(nb), dim3(256), shm, ctx->stream, a, J ? J->val : nullptr);
     } else {
-        if (J && J->fp32) {
-            hipLaunchKernelGGL((k_ns_fluid<3, float>), dim3(nb), dim3(128), 0, ctx->stream, a, J->val32);
-            if (ctx->n_s > 0) hipLaunchKernelGGL((k_ns_elastic<3, float>), dim3(nb), dim3(128), 0, ctx->stream, el, J->val32);
-        } else {
-            double *Jv = J ? J->val : nullptr;
-            hipLaunchKernelGGL((k_ns_fluid<3, double>), dim3(nb), dim3(128), 0, ctx->stream, a, Jv);
-            if (ctx->n_s > 0) hipLaunchKernelGGL((k_ns_elastic<3, double>), dim3(nb), dim3(128), 0, ctx->stream, el, Jv);
-        }
+        if (J && J->fp32) hipLaunchKernelGGL((k_ns_rows<3, float>), dim3(nb), dim3(256), shm, ctx->stream, a, J->val32);
+        else hipLaunchKernelGGL((k_ns_rows<3, double>), dim3(nb), dim3(256), shm, ctx->stream, a, J ? J->val : nullptr);
     }
     EFT_HIP(hipGetLastError());
     if (M.n_dir > 0) {
@@ -618,6 +572,10 @@ eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_ma
     M.n_dir = ctx->n_dir;
     M.dir_node = ctx->dir_node;
     M.dir_mask = ctx->dir_mask;
+    M.iptr = ctx->iptr;
+    M.ient = ctx->ient;
+    M.maxc = ctx->maxc;
+    M.rpb = ctx->rpb;
     EFT_TRY(eft_ns_level(ctx, M, it->vp, R, J));
     if (J && eft_mg_active(ctx, J)) EFT_TRY(eft_mg_setup(ctx, it->vp));
     return EFT_OK;

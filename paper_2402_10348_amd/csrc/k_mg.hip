@@ -437,8 +437,13 @@ Dims dims_of(const MGLevel &L) { return Dims{{L.n[0], L.n[1], L.n[2]}}; }
 // pair (a, b) in row a.
 eft_status eft_build_graph(int64_t N, int64_t E, int nn, const int32_t *conn, std::vector<int32_t> &rowptr,
                            std::vector<int32_t> &col, std::vector<int32_t> &diag, std::vector<int32_t> &epos,
+                           std::vector<int32_t> &iptr, std::vector<int32_t> &ient, int &maxc, int &rpb,
                            std::string &err)
 {
+    if (E >= (1LL << 29) || (int64_t)E * nn >= 2000000000LL) {
+        err = "too many elements for 32-bit incidence entries";
+        return EFT_EINVAL;
+    }
     std::vector<int64_t> ioff(N + 1, 0);
     for (int64_t t = 0; t < E * nn; ++t) ioff[conn[t] + 1]++;
     for (int64_t p = 0; p < N; ++p) ioff[p + 1] += ioff[p];
@@ -477,6 +482,28 @@ eft_status eft_build_graph(int64_t N, int64_t E, int nn, const int32_t *conn, st
                 epos[(size_t)e * nn * nn + a * nn + b] = (int32_t)(
                     std::lower_bound(col.begin() + rowptr[r], col.begin() + rowptr[r + 1], conn[e * nn + b]) - col.begin());
         }
+    // node -> incident (element << 2 | local index), grouped by node
+    iptr.assign(N + 1, 0);
+    ient.assign((size_t)E * nn, 0);
+    int maxinc = 1;
+    {
+        std::vector<int64_t> fill(N, 0);
+        for (int64_t p = 0; p < N; ++p) {
+            iptr[p + 1] = (int32_t)ioff[p + 1];
+            maxinc = std::max<int>(maxinc, (int)(ioff[p + 1] - ioff[p]));
+        }
+        for (int64_t e = 0; e < E; ++e)
+            for (int a = 0; a < nn; ++a) {
+                const int32_t p = conn[e * nn + a];
+                ient[ioff[p] + fill[p]++] = (int32_t)((e << 2) | a);
+            }
+    }
+    maxc = 1;
+    for (int64_t p = 0; p < N; ++p) maxc = std::max(maxc, rowptr[p + 1] - rowptr[p]);
+    // rows per assembly workgroup: about two incident elements per thread, and
+    // the row accumulators of the largest block size within 40 KB of LDS
+    const int64_t rowbytes = (int64_t)maxc * 36 * 8 + 6 * 8;
+    rpb = (int)std::max<int64_t>(1, std::min<int64_t>(512 / maxinc, 40960 / rowbytes));
     return EFT_OK;
 }
 
@@ -537,8 +564,11 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
                 dmk.push_back(dm);
             }
         }
-        std::vector<int32_t> rowptr, col, diag, epos;
-        EFT_TRY(eft_build_graph(C.N, C.E, nn, conn.data(), rowptr, col, diag, epos, ctx->err));
+        std::vector<int32_t> rowptr, col, diag, epos, iptr, ient;
+        EFT_TRY(eft_build_graph(C.N, C.E, nn, conn.data(), rowptr, col, diag, epos, iptr, ient, C.maxc, C.rpb,
+                                ctx->err));
+        EFT_TRY(dput(ctx, &C.iptr, iptr));
+        EFT_TRY(dput(ctx, &C.ient, ient));
         EFT_TRY(dput(ctx, &C.conn, conn));
         EFT_TRY(dput(ctx, &C.epos, epos));
         EFT_TRY(dput(ctx, &C.inj, inj32));
@@ -593,7 +623,7 @@ void eft_mg_free(eft_ctx *ctx)
         if (l > 0) {
             fr(L.conn); fr(L.epos); fr(L.inj); fr(L.xyz); fr(L.va); fr(L.acc); fr(L.rho); fr(L.mu); fr(L.as);
             fr(L.Ba); fr(L.vp); fr(L.R); fr(L.dir_node); fr(L.dir_mask); fr(L.A.rowptr); fr(L.A.col); fr(L.A.diag);
-            fr(L.A.val); fr(L.b);
+            fr(L.A.val); fr(L.b); fr(L.iptr); fr(L.ient);
         }
         fr(L.fmask); fr(L.Dinv); fr(L.x); fr(L.x2); fr(L.r);
     }
@@ -657,6 +687,10 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
         M.n_dir = C.n_dir;
         M.dir_node = C.dir_node;
         M.dir_mask = C.dir_mask;
+        M.iptr = C.iptr;
+        M.ient = C.ient;
+        M.maxc = C.maxc;
+        M.rpb = C.rpb;
         EFT_TRY(eft_ns_level(ctx, M, C.vp, C.R, &C.A));
         EFT_TRY(eft_bj_setup(ctx, &C.A, C.Dinv));
     }

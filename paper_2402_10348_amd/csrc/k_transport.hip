@@ -335,283 +335,366 @@ __global__ __launch_bounds__(256) void k_sum2(const double *part, int nb, double
     }
 }
 
-// ---------------------------------------------------------- Allen-Cahn ----
+// ---------------------------------------------- band systems, row-owned ----
+//
+// Same organization as the momentum assembly: a workgroup owns a block of
+// band rows; every (band row, incident band element) pair is one thread that
+// evaluates the element and adds only that row's residual and blocks into LDS
+// accumulators indexed by the slot of the column in the global row; the
+// write-out compacts global slots to the band pattern.
 
 struct TrArgs {
-    int64_t ne;
-    const int32_t *elem, *bconn, *bepos, *conn;
+    int64_t n;                              // band rows
+    int rpb, maxc;                          // rows per workgroup, longest global row
+    const int32_t *node;                    // band row -> global node
+    const int32_t *iptr, *ient;             // global node -> (element << 2 | local node)
+    const uint8_t *eflag;                   // [E] 1 for band elements
+    const int32_t *conn, *epos, *grow, *gcol;
+    const int32_t *brow, *bcol;             // band pattern, band-local columns
     const double *xyz, *va;
-    const double *lx, *ldx, *ix;  // level value, level rate, iterate of the transported field
+    const double *lx, *ldx, *ix;            // level value, level rate, iterate of the field
     double alpha, alpha_m, vs, dt, ct;
     double *R, *J;
 };
 
-template <int D>
-__global__ __launch_bounds__(128) void k_ac_elem(TrArgs a, double eps, const double *gb /* gamma, beta */)
+template <int BS>
+__device__ __forceinline__ void band_rows_out(const TrArgs &a, int64_t r0, int64_t r1, const double *accJ,
+                                              const double *accR)
 {
-    const int64_t be = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (be >= a.ne) return;
-    constexpr int NN = D + 1, NQ = Rule<D>::NQ;
-    const double gamma = gb[0], beta = gb[1];
-    const int64_t e = a.elem[be];
-    double X[NN][D], v[NN][D], f[NN], fd[NN];
-#pragma unroll
-    for (int b = 0; b < NN; ++b) {
-        const int64_t g = a.conn[e * NN + b];
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            X[b][i] = a.xyz[g * D + i];
-            v[b][i] = a.va[g * D + i];
-        }
-        const double xn = a.lx[g], xd = a.ldx[g], x1 = a.ix[g];
-        const double xd1 = xd + (x1 - xn - a.dt * xd) / (a.vs * a.dt);
-        fd[b] = xd + a.alpha_m * (xd1 - xd);
-        f[b] = xn + a.alpha * (x1 - xn);
-    }
-    double dN[NN][D], G[D][D];
-    const double vol = simplex_geom<D>(X, dN, G);
-    double GG = 0.0;
-#pragma unroll
-    for (int i = 0; i < D; ++i)
-#pragma unroll
-        for (int j = 0; j < D; ++j) GG += G[i][j] * G[i][j];
-    double gf[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-        double s = 0.0;
-#pragma unroll
-        for (int b = 0; b < NN; ++b) s += f[b] * dN[b][j];
-        gf[j] = s;
-    }
-    const double kh = eps * eps, w = vol * Rule<D>::WF, al = a.alpha, ct = a.ct;
-    const double gk9 = 9.0 * (gamma * kh) * (gamma * kh) * GG, i4 = 4.0 / (a.dt * a.dt);
-    double re[NN], K[NN][NN];
-#pragma unroll
-    for (int b = 0; b < NN; ++b) {
-        re[b] = 0.0;
-#pragma unroll
-        for (int c = 0; c < NN; ++c) K[b][c] = 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        double fq = 0.0, fdq = 0.0, vq[D];
-#pragma unroll
-        for (int i = 0; i < D; ++i) vq[i] = 0.0;
-#pragma unroll
-        for (int b = 0; b < NN; ++b) {
-            const double Nb = shape_at<D>(q, b);
-            fq += Nb * f[b];
-            fdq += Nb * fd[b];
-#pragma unroll
-            for (int i = 0; i < D; ++i) vq[i] += Nb * v[b][i];
-        }
-        double vg = 0.0, vGv = 0.0;
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            vg += vq[i] * gf[i];
-#pragma unroll
-            for (int j = 0; j < D; ++j) vGv += vq[i] * G[i][j] * vq[j];
-        }
-        // derivative of |phi^2 - 1| at the kink |phi| = 1 taken as 0 within
-        // 1e-12 (flat regions interpolate to +-1 only up to rounding)
-        const double f2m1 = fq * fq - 1.0;
-        const double sgn = fabs(f2m1) <= 1e-12 ? 0.0 : (f2m1 > 0.0 ? 1.0 : -1.0);
-        const double react = fq * fq * fq - fq - beta * 0.5 * fabs(f2m1);
-        const double sh = 3.0 * fq * fq - 1.0 - beta * fq * sgn;
-        const double Rphi = fdq + vg + gamma * react;
-        const double tau = 1.0 / sqrt(i4 + vGv + gk9 + (gamma * sh) * (gamma * sh));
-        double u[NN];
-#pragma unroll
-        for (int b = 0; b < NN; ++b) {
-            double s = 0.0;
-#pragma unroll
-            for (int j = 0; j < D; ++j) s += vq[j] * dN[b][j];
-            u[b] = s;
-        }
-#pragma unroll
-        for (int ia = 0; ia < NN; ++ia) {
-            const double Na = shape_at<D>(q, ia);
-            double gg = 0.0;
-#pragma unroll
-            for (int j = 0; j < D; ++j) gg += dN[ia][j] * gf[j];
-            re[ia] += w * (Na * (fdq + vg) + gamma * (kh * gg + Na * react) + tau * u[ia] * Rphi);
-#pragma unroll
-            for (int ib = 0; ib < NN; ++ib) {
-                const double Nb = shape_at<D>(q, ib);
-                double gab = 0.0;
-#pragma unroll
-                for (int j = 0; j < D; ++j) gab += dN[ia][j] * dN[ib][j];
-                const double lin = ct * Nb + al * u[ib];
-                K[ia][ib] += w * (Na * lin + al * gamma * (kh * gab + Na * sh * Nb) + tau * u[ia] * (lin + al * gamma * sh * Nb));
+    constexpr int B2 = BS * BS;
+    for (int64_t r = r0; r < r1; ++r) {
+        const int lr = (int)(r - r0);
+        if (threadIdx.x < BS) a.R[r * BS + threadIdx.x] = accR[lr * BS + threadIdx.x];
+        const int64_t g = a.node[r];
+        const int32_t *gc = a.gcol + a.grow[g];
+        const int glen = a.grow[g + 1] - a.grow[g];
+        const int64_t kb = a.brow[r], len = a.brow[r + 1] - kb;
+        for (int t = threadIdx.x; t < len; t += blockDim.x) {
+            const int32_t col = a.node[a.bcol[kb + t]];
+            int lo = 0, hi = glen - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (gc[mid] < col) lo = mid + 1;
+                else hi = mid;
             }
+            const double *src = accJ + ((int64_t)lr * a.maxc + lo) * B2;
+            double *dst = a.J + (kb + t) * B2;
+#pragma unroll
+            for (int v = 0; v < B2; ++v) dst[v] = src[v];
         }
-    }
-    const int32_t *ep = a.bepos + be * NN * NN;
-#pragma unroll
-    for (int ia = 0; ia < NN; ++ia) {
-        unsafeAtomicAdd(a.R + a.bconn[be * NN + ia], re[ia]);
-#pragma unroll
-        for (int ib = 0; ib < NN; ++ib) unsafeAtomicAdd(a.J + ep[ia * NN + ib], K[ia][ib]);
     }
 }
 
-// ------------------------------------------------------------------- B ----
-
 template <int D>
-__global__ __launch_bounds__(128) void k_b_elem(TrArgs a, const double *afr /*[N]*/)
+__global__ __launch_bounds__(256) void k_ac_rows(TrArgs a, double eps, const double *gb /* gamma, beta */)
 {
-    const int64_t be = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (be >= a.ne) return;
-    constexpr int NN = D + 1, NQ = Rule<D>::NQ, NVv = NV<D>::v;
-    const int64_t e = a.elem[be];
-    double X[NN][D], v[NN][D], am[NN], Bn[NN][NVv], Bd[NN][NVv];
-#pragma unroll
-    for (int b = 0; b < NN; ++b) {
-        const int64_t g = a.conn[e * NN + b];
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            X[b][i] = a.xyz[g * D + i];
-            v[b][i] = a.va[g * D + i];
-        }
-        am[b] = afr[g];
-#pragma unroll
-        for (int c = 0; c < NVv; ++c) {
-            const double xn = a.lx[g * NVv + c], xd = a.ldx[g * NVv + c], x1 = a.ix[g * NVv + c];
-            const double xd1 = xd + (x1 - xn - a.dt * xd) / (a.vs * a.dt);
-            Bd[b][c] = xd + a.alpha_m * (xd1 - xd);
-            Bn[b][c] = xn + a.alpha * (x1 - xn);
+    extern __shared__ double lds[];
+    constexpr int NN = D + 1, NQ = Rule<D>::NQ;
+    const int64_t r0 = (int64_t)blockIdx.x * a.rpb;
+    const int64_t r1 = r0 + a.rpb < a.n ? r0 + a.rpb : a.n;
+    double *accJ = lds, *accR = lds + (int64_t)a.rpb * a.maxc;
+    for (int t = threadIdx.x; t < a.rpb * (a.maxc + 1); t += blockDim.x) lds[t] = 0.0;
+    __syncthreads();
+    const double gamma = gb[0], beta = gb[1];
+    const double kh = eps * eps, al = a.alpha, ct = a.ct, i4 = 4.0 / (a.dt * a.dt);
+    // incidences of the workgroup's rows, flattened (band rows are not
+    // contiguous global nodes)
+    __shared__ int pre[65];
+    if (threadIdx.x == 0) {
+        pre[0] = 0;
+        for (int64_t r = r0; r < r1; ++r) {
+            const int64_t gg = a.node[r];
+            pre[r - r0 + 1] = pre[r - r0] + (a.iptr[gg + 1] - a.iptr[gg]);
         }
     }
-    double dN[NN][D], G[D][D];
-    const double vol = simplex_geom<D>(X, dN, G);
-    double L[D][D];
+    __syncthreads();
+    const int nrow = (int)(r1 - r0), total = pre[nrow];
+    {
+        for (int t = threadIdx.x; t < total; t += blockDim.x) {
+            int lr = 0;
+            while (pre[lr + 1] <= t) ++lr;
+            const int64_t g = a.node[r0 + lr];
+            const int ii = a.iptr[g] + (t - pre[lr]);
+            const int32_t ent = a.ient[ii];
+            const int64_t e = ent >> 2;
+            const int la = ent & 3;
+            if (!a.eflag[e]) continue;
+            double X[NN][D], v[NN][D], f[NN], fd[NN];
 #pragma unroll
-    for (int i = 0; i < D; ++i)
+            for (int b = 0; b < NN; ++b) {
+                const int64_t n = a.conn[e * NN + b];
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-            double s = 0.0;
-#pragma unroll
-            for (int b = 0; b < NN; ++b) s += v[b][i] * dN[b][j];
-            L[i][j] = s;
-        }
-    double gB[D][D][D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        double gk[NVv];
-#pragma unroll
-        for (int c = 0; c < NVv; ++c) {
-            double s = 0.0;
-#pragma unroll
-            for (int b = 0; b < NN; ++b) s += dN[b][k] * Bn[b][c];
-            gk[c] = s;
-        }
-        vfull<D>(gk, gB[k]);
-    }
-    const double w = vol * Rule<D>::WF, al = a.alpha, ct = a.ct, i4 = 4.0 / (a.dt * a.dt);
-    double re[NN][NVv], W[NN][NQ], U[NN][NQ], AQ[NQ];
-#pragma unroll
-    for (int b = 0; b < NN; ++b)
-#pragma unroll
-        for (int c = 0; c < NVv; ++c) re[b][c] = 0.0;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        double vq[D], aq = 0.0, bq[NVv], bdq[NVv];
-#pragma unroll
-        for (int i = 0; i < D; ++i) vq[i] = 0.0;
-#pragma unroll
-        for (int c = 0; c < NVv; ++c) bq[c] = bdq[c] = 0.0;
-#pragma unroll
-        for (int b = 0; b < NN; ++b) {
-            const double Nb = shape_at<D>(q, b);
-            aq += Nb * am[b];
-#pragma unroll
-            for (int i = 0; i < D; ++i) vq[i] += Nb * v[b][i];
-#pragma unroll
-            for (int c = 0; c < NVv; ++c) {
-                bq[c] += Nb * Bn[b][c];
-                bdq[c] += Nb * Bd[b][c];
+                for (int i = 0; i < D; ++i) {
+                    X[b][i] = a.xyz[n * D + i];
+                    v[b][i] = a.va[n * D + i];
+                }
+                const double xn = a.lx[n], xd = a.ldx[n], x1 = a.ix[n];
+                const double xd1 = xd + (x1 - xn - a.dt * xd) / (a.vs * a.dt);
+                fd[b] = xd + a.alpha_m * (xd1 - xd);
+                f[b] = xn + a.alpha * (x1 - xn);
             }
-        }
-        double Bq[D][D], Bdq[D][D];
-        vfull<D>(bq, Bq);
-        vfull<D>(bdq, Bdq);
-        double vGv = 0.0;
+            double dN[NN][D], G[D][D];
+            const double vol = simplex_geom<D>(X, dN, G);
+            double GG = 0.0;
 #pragma unroll
-        for (int i = 0; i < D; ++i)
+            for (int i = 0; i < D; ++i)
 #pragma unroll
-            for (int j = 0; j < D; ++j) vGv += vq[i] * G[i][j] * vq[j];
-        const double tau = 1.0 / sqrt(i4 + vGv);
-        double RB[NVv];
+                for (int j = 0; j < D; ++j) GG += G[i][j] * G[i][j];
+            double gf[D];
 #pragma unroll
-        for (int c = 0; c < NVv; ++c) {
-            int i, j;
-            vpair<D>(c, i, j);
-            double conv = 0.0, LB = 0.0, BL = 0.0;
+            for (int j = 0; j < D; ++j) {
+                double s = 0.0;
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                conv += vq[k] * gB[k][i][j];
-                LB += L[i][k] * Bq[k][j];
-                BL += Bq[i][k] * L[j][k];
+                for (int b = 0; b < NN; ++b) s += f[b] * dN[b][j];
+                gf[j] = s;
             }
-            RB[c] = aq * (Bdq[i][j] + conv - LB - BL) + (1.0 - aq) * (Bq[i][j] - (i == j ? 1.0 : 0.0));
-        }
+            double gga = 0.0, gab[NN];
 #pragma unroll
-        for (int ia = 0; ia < NN; ++ia) {
-            double u = 0.0;
+            for (int j = 0; j < D; ++j) gga += dN[la][j] * gf[j];
 #pragma unroll
-            for (int j = 0; j < D; ++j) u += vq[j] * dN[ia][j];
-            U[ia][q] = u;
-            W[ia][q] = w * (shape_at<D>(q, ia) + tau * u);
+            for (int b = 0; b < NN; ++b) {
+                double s = 0.0;
 #pragma unroll
-            for (int c = 0; c < NVv; ++c) re[ia][c] += W[ia][q] * RB[c];
-        }
-        AQ[q] = aq;
-    }
-    // LE[c][cc] = (L E_cc + E_cc L^T)_{ij(c)} with E_cc the symmetric unit direction
-    double LE[NVv][NVv];
+                for (int j = 0; j < D; ++j) s += dN[la][j] * dN[b][j];
+                gab[b] = s;
+            }
+            const double w = vol * Rule<D>::WF;
+            const double gk9 = 9.0 * (gamma * kh) * (gamma * kh) * GG;
+            double re = 0.0, K[NN];
 #pragma unroll
-    for (int cc = 0; cc < NVv; ++cc) {
-        int k, l;
-        vpair<D>(cc, k, l);
-#pragma unroll
-        for (int c = 0; c < NVv; ++c) {
-            int i, j;
-            vpair<D>(c, i, j);
-            // (L E)_ij = L_ik' E_k'j with E_kl = E_lk = 1
-            double s = 0.0;
-            if (l == j) s += L[i][k];
-            if (k == j && k != l) s += L[i][l];
-            if (l == i) s += L[j][k];
-            if (k == i && k != l) s += L[j][l];
-            LE[c][cc] = s;
-        }
-    }
-    const int32_t *ep = a.bepos + be * NN * NN;
-#pragma unroll
-    for (int ia = 0; ia < NN; ++ia) {
-        const int64_t l = a.bconn[be * NN + ia];
-#pragma unroll
-        for (int c = 0; c < NVv; ++c) unsafeAtomicAdd(a.R + l * NVv + c, re[ia][c]);
-#pragma unroll
-        for (int ib = 0; ib < NN; ++ib) {
-            double S1 = 0.0, S2 = 0.0;
+            for (int b = 0; b < NN; ++b) K[b] = 0.0;
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                const double Nb = shape_at<D>(q, ib);
-                S1 += W[ia][q] * (AQ[q] * (ct * Nb + al * U[ib][q]) + (1.0 - AQ[q]) * al * Nb);
-                S2 += W[ia][q] * AQ[q] * Nb;
-            }
-            S2 *= al;
-            double *blk = a.J + (int64_t)ep[ia * NN + ib] * NVv * NVv;
+                double fq = 0.0, fdq = 0.0, vq[D];
 #pragma unroll
-            for (int c = 0; c < NVv; ++c)
+                for (int i = 0; i < D; ++i) vq[i] = 0.0;
 #pragma unroll
-                for (int cc = 0; cc < NVv; ++cc) {
-                    const double val = (c == cc ? S1 : 0.0) - S2 * LE[c][cc];
-                    if (val != 0.0) unsafeAtomicAdd(blk + c * NVv + cc, val);
+                for (int b = 0; b < NN; ++b) {
+                    const double Nb = shape_at<D>(q, b);
+                    fq += Nb * f[b];
+                    fdq += Nb * fd[b];
+#pragma unroll
+                    for (int i = 0; i < D; ++i) vq[i] += Nb * v[b][i];
                 }
+                double vg = 0.0, vGv = 0.0;
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    vg += vq[i] * gf[i];
+#pragma unroll
+                    for (int j = 0; j < D; ++j) vGv += vq[i] * G[i][j] * vq[j];
+                }
+                // derivative of |phi^2 - 1| at the kink |phi| = 1 taken as 0 within
+                // 1e-12 (flat regions interpolate to +-1 only up to rounding)
+                const double f2m1 = fq * fq - 1.0;
+                const double sgn = fabs(f2m1) <= 1e-12 ? 0.0 : (f2m1 > 0.0 ? 1.0 : -1.0);
+                const double react = fq * fq * fq - fq - beta * 0.5 * fabs(f2m1);
+                const double sh = 3.0 * fq * fq - 1.0 - beta * fq * sgn;
+                const double Rphi = fdq + vg + gamma * react;
+                const double tau = 1.0 / sqrt(i4 + vGv + gk9 + (gamma * sh) * (gamma * sh));
+                double u[NN];
+#pragma unroll
+                for (int b = 0; b < NN; ++b) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) s += vq[j] * dN[b][j];
+                    u[b] = s;
+                }
+                const double Na = shape_at<D>(q, la);
+                re += w * (Na * (fdq + vg) + gamma * (kh * gga + Na * react) + tau * u[la] * Rphi);
+#pragma unroll
+                for (int ib = 0; ib < NN; ++ib) {
+                    const double Nb = shape_at<D>(q, ib);
+                    const double lin = ct * Nb + al * u[ib];
+                    K[ib] += w * (Na * lin + al * gamma * (kh * gab[ib] + Na * sh * Nb) +
+                                  tau * u[la] * (lin + al * gamma * sh * Nb));
+                }
+            }
+            atomicAdd(accR + lr, re);
+            const int64_t gb0 = a.grow[g];
+#pragma unroll
+            for (int ib = 0; ib < NN; ++ib) atomicAdd(accJ + (int64_t)lr * a.maxc + (a.epos[e * NN * NN + la * NN + ib] - gb0), K[ib]);
         }
     }
+    __syncthreads();
+    band_rows_out<1>(a, r0, r1, accJ, accR);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_b_rows(TrArgs a, const double *afr /*[N]*/)
+{
+    extern __shared__ double lds[];
+    constexpr int NN = D + 1, NQ = Rule<D>::NQ, NVv = NV<D>::v, B2 = NVv * NVv;
+    const int64_t r0 = (int64_t)blockIdx.x * a.rpb;
+    const int64_t r1 = r0 + a.rpb < a.n ? r0 + a.rpb : a.n;
+    double *accJ = lds, *accR = lds + (int64_t)a.rpb * a.maxc * B2;
+    for (int t = threadIdx.x; t < a.rpb * (a.maxc * B2 + NVv); t += blockDim.x) lds[t] = 0.0;
+    __syncthreads();
+    const double al = a.alpha, ct = a.ct, i4 = 4.0 / (a.dt * a.dt);
+    // incidences of the workgroup's rows, flattened (band rows are not
+    // contiguous global nodes)
+    __shared__ int pre[65];
+    if (threadIdx.x == 0) {
+        pre[0] = 0;
+        for (int64_t r = r0; r < r1; ++r) {
+            const int64_t gg = a.node[r];
+            pre[r - r0 + 1] = pre[r - r0] + (a.iptr[gg + 1] - a.iptr[gg]);
+        }
+    }
+    __syncthreads();
+    const int nrow = (int)(r1 - r0), total = pre[nrow];
+    {
+        for (int t = threadIdx.x; t < total; t += blockDim.x) {
+            int lr = 0;
+            while (pre[lr + 1] <= t) ++lr;
+            const int64_t g = a.node[r0 + lr];
+            const int ii = a.iptr[g] + (t - pre[lr]);
+            const int32_t ent = a.ient[ii];
+            const int64_t e = ent >> 2;
+            const int la = ent & 3;
+            if (!a.eflag[e]) continue;
+            double X[NN][D], v[NN][D], am[NN], Bn[NN][NVv], Bd[NN][NVv];
+#pragma unroll
+            for (int b = 0; b < NN; ++b) {
+                const int64_t n = a.conn[e * NN + b];
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    X[b][i] = a.xyz[n * D + i];
+                    v[b][i] = a.va[n * D + i];
+                }
+                am[b] = afr[n];
+#pragma unroll
+                for (int c = 0; c < NVv; ++c) {
+                    const double xn = a.lx[n * NVv + c], xd = a.ldx[n * NVv + c], x1 = a.ix[n * NVv + c];
+                    const double xd1 = xd + (x1 - xn - a.dt * xd) / (a.vs * a.dt);
+                    Bd[b][c] = xd + a.alpha_m * (xd1 - xd);
+                    Bn[b][c] = xn + a.alpha * (x1 - xn);
+                }
+            }
+            double dN[NN][D], G[D][D];
+            const double vol = simplex_geom<D>(X, dN, G);
+            double L[D][D];
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int b = 0; b < NN; ++b) s += v[b][i] * dN[b][j];
+                    L[i][j] = s;
+                }
+            double gB[D][D][D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                double gk[NVv];
+#pragma unroll
+                for (int c = 0; c < NVv; ++c) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int b = 0; b < NN; ++b) s += dN[b][k] * Bn[b][c];
+                    gk[c] = s;
+                }
+                vfull<D>(gk, gB[k]);
+            }
+            const double w = vol * Rule<D>::WF;
+            double re[NVv], Wl[NQ], U[NN][NQ], AQ[NQ];
+#pragma unroll
+            for (int c = 0; c < NVv; ++c) re[c] = 0.0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                double vq[D], aq = 0.0, bq[NVv], bdq[NVv];
+#pragma unroll
+                for (int i = 0; i < D; ++i) vq[i] = 0.0;
+#pragma unroll
+                for (int c = 0; c < NVv; ++c) bq[c] = bdq[c] = 0.0;
+#pragma unroll
+                for (int b = 0; b < NN; ++b) {
+                    const double Nb = shape_at<D>(q, b);
+                    aq += Nb * am[b];
+#pragma unroll
+                    for (int i = 0; i < D; ++i) vq[i] += Nb * v[b][i];
+#pragma unroll
+                    for (int c = 0; c < NVv; ++c) {
+                        bq[c] += Nb * Bn[b][c];
+                        bdq[c] += Nb * Bd[b][c];
+                    }
+                }
+                double Bq[D][D], Bdq[D][D];
+                vfull<D>(bq, Bq);
+                vfull<D>(bdq, Bdq);
+                double vGv = 0.0;
+#pragma unroll
+                for (int i = 0; i < D; ++i)
+#pragma unroll
+                    for (int j = 0; j < D; ++j) vGv += vq[i] * G[i][j] * vq[j];
+                const double tau = 1.0 / sqrt(i4 + vGv);
+#pragma unroll
+                for (int b = 0; b < NN; ++b) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) s += vq[j] * dN[b][j];
+                    U[b][q] = s;
+                }
+                Wl[q] = w * (shape_at<D>(q, la) + tau * U[la][q]);
+                AQ[q] = aq;
+#pragma unroll
+                for (int c = 0; c < NVv; ++c) {
+                    int i, j;
+                    vpair<D>(c, i, j);
+                    double conv = 0.0, LB = 0.0, BL = 0.0;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        conv += vq[k] * gB[k][i][j];
+                        LB += L[i][k] * Bq[k][j];
+                        BL += Bq[i][k] * L[j][k];
+                    }
+                    const double RB = aq * (Bdq[i][j] + conv - LB - BL) + (1.0 - aq) * (Bq[i][j] - (i == j ? 1.0 : 0.0));
+                    re[c] += Wl[q] * RB;
+                }
+            }
+            // LE[c][cc] = (L E + E L^T)_{ij(c)} for the symmetric unit direction E of cc
+            double LE[NVv][NVv];
+#pragma unroll
+            for (int cc = 0; cc < NVv; ++cc) {
+                int k, l;
+                vpair<D>(cc, k, l);
+#pragma unroll
+                for (int c = 0; c < NVv; ++c) {
+                    int i, j;
+                    vpair<D>(c, i, j);
+                    double s = 0.0;
+                    if (l == j) s += L[i][k];
+                    if (k == j && k != l) s += L[i][l];
+                    if (l == i) s += L[j][k];
+                    if (k == i && k != l) s += L[j][l];
+                    LE[c][cc] = s;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NVv; ++c) atomicAdd(accR + lr * NVv + c, re[c]);
+            const int64_t gb0 = a.grow[g];
+#pragma unroll
+            for (int ib = 0; ib < NN; ++ib) {
+                double S1 = 0.0, S2 = 0.0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const double Nb = shape_at<D>(q, ib);
+                    S1 += Wl[q] * (AQ[q] * (ct * Nb + al * U[ib][q]) + (1.0 - AQ[q]) * al * Nb);
+                    S2 += Wl[q] * AQ[q] * Nb;
+                }
+                S2 *= al;
+                double *blk = accJ + ((int64_t)lr * a.maxc + (a.epos[e * NN * NN + la * NN + ib] - gb0)) * B2;
+#pragma unroll
+                for (int c = 0; c < NVv; ++c)
+#pragma unroll
+                    for (int cc = 0; cc < NVv; ++cc) {
+                        const double val = (c == cc ? S1 : 0.0) - S2 * LE[c][cc];
+                        if (val != 0.0) atomicAdd(blk + c * NVv + cc, val);
+                    }
+            }
+        }
+    }
+    __syncthreads();
+    band_rows_out<NVv>(a, r0, r1, accJ, accR);
 }
 
 // Rows of nodes that keep their value: residual 0, unit row.
@@ -753,6 +836,8 @@ eft_status eft_bands_build_dev(eft_ctx *ctx, const double *phi_n)
         int64_t ne = 0, n = 0;
         int64_t *caps = B.cap;
         // element and node lists are sized for the worst case (all of the mesh)
+        EFT_TRY(grow(ctx, (void **)&B.eflag, E, &caps[8]));
+        EFT_HIP(hipMemcpyAsync(B.eflag, ctx->ein, E, hipMemcpyDeviceToDevice, ctx->stream));
         EFT_TRY(grow(ctx, (void **)&B.elem, sizeof(int32_t) * E, &caps[0]));
         EFT_TRY(scan_compact<uint8_t>(ctx, ctx->ein, E, nullptr, B.elem, nullptr, &ne));
         EFT_TRY(grow(ctx, (void **)&B.node, sizeof(int32_t) * N, &caps[1]));
@@ -874,11 +959,19 @@ static TrArgs tr_args(eft_ctx *ctx, const Band &B, const double *lx, const doubl
 {
     GA ga = ga_of(ctx->par.rho_inf, ctx->par.dt);
     TrArgs a;
-    a.ne = B.ne;
-    a.elem = B.elem;
-    a.bconn = B.bconn_;
-    a.bepos = B.epos;
+    a.n = B.n;
+    a.rpb = std::min(ctx->rpb, 64);
+    a.maxc = ctx->maxc;
+    a.node = B.node;
+    a.iptr = ctx->iptr;
+    a.ient = ctx->ient;
+    a.eflag = B.eflag;
     a.conn = ctx->conn;
+    a.epos = ctx->epos;
+    a.grow = ctx->J.rowptr;
+    a.gcol = ctx->J.col;
+    a.brow = B.rowptr;
+    a.bcol = B.col;
     a.xyz = ctx->xyz;
     a.va = ctx->va;
     a.lx = lx;
@@ -900,15 +993,14 @@ static eft_status assemble_ac(eft_ctx *ctx, const eft_state *lvl, const eft_iter
 {
     const int64_t N = ctx->N;
     const Band &B = ctx->band[k];
-    EFT_TRY(eft_fill(ctx, ctx->bR, B.n, 0.0));
-    EFT_TRY(eft_fill(ctx, ctx->bval, B.nnz, 0.0));
     TrArgs a = tr_args(ctx, B, lvl->phi + (int64_t)k * N, lvl->phidot + (int64_t)k * N, it->phi + (int64_t)k * N);
-    if (B.ne > 0) {
+    if (B.n > 0) {
+        const size_t shm = (size_t)a.rpb * (a.maxc + 1) * sizeof(double);
         if (ctx->dim == 2)
-            hipLaunchKernelGGL(k_ac_elem<2>, dim3(eft_grid(B.ne, 128)), dim3(128), 0, ctx->stream, a, ctx->par.eps,
+            hipLaunchKernelGGL(k_ac_rows<2>, dim3(eft_grid(B.n, a.rpb)), dim3(256), shm, ctx->stream, a, ctx->par.eps,
                                ctx->dscal + 4);
         else
-            hipLaunchKernelGGL(k_ac_elem<3>, dim3(eft_grid(B.ne, 128)), dim3(128), 0, ctx->stream, a, ctx->par.eps,
+            hipLaunchKernelGGL(k_ac_rows<3>, dim3(eft_grid(B.n, a.rpb)), dim3(256), shm, ctx->stream, a, ctx->par.eps,
                                ctx->dscal + 4);
     }
     if (B.n > 0)
@@ -925,15 +1017,14 @@ static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_itera
     const int64_t N = ctx->N;
     const int nv = ctx->nv;
     const Band &B = ctx->band[ctx->solid_ind[s]];
-    EFT_TRY(eft_fill(ctx, ctx->bR, B.n * nv, 0.0));
-    EFT_TRY(eft_fill(ctx, ctx->bval, B.nnz * nv * nv, 0.0));
     TrArgs a = tr_args(ctx, B, lvl->B + (int64_t)s * N * nv, lvl->Bdot + (int64_t)s * N * nv, it->B + (int64_t)s * N * nv);
-    if (B.ne > 0) {
+    if (B.n > 0) {
+        const size_t shm = (size_t)a.rpb * ((size_t)a.maxc * nv * nv + nv) * sizeof(double);
         if (ctx->dim == 2)
-            hipLaunchKernelGGL(k_b_elem<2>, dim3(eft_grid(B.ne, 128)), dim3(128), 0, ctx->stream, a,
+            hipLaunchKernelGGL(k_b_rows<2>, dim3(eft_grid(B.n, a.rpb)), dim3(256), shm, ctx->stream, a,
                                ctx->as + (int64_t)s * N);
         else
-            hipLaunchKernelGGL(k_b_elem<3>, dim3(eft_grid(B.ne, 128)), dim3(128), 0, ctx->stream, a,
+            hipLaunchKernelGGL(k_b_rows<3>, dim3(eft_grid(B.n, a.rpb)), dim3(256), shm, ctx->stream, a,
                                ctx->as + (int64_t)s * N);
     }
     if (B.n > 0)
