@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 FP32 Jacobian values")
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--precond", type=int, default=1, help="1 multigrid V-cycle, 0 point-block Jacobi")
+    ap.add_argument("--mg-nu", type=int, default=2)
+    ap.add_argument("--mg-omega", type=float, default=0.7)
     ap.add_argument("--spmv-reps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--traffic", type=str, default="", help="JSON file with measured HBM bytes per SpMV launch")
@@ -104,7 +106,7 @@ def main():
     torch.cuda.set_device(0)
     prob = W.cavity_sphere_3d(n=args.n)
     ctx = Context(prob, lin_rtol=1e-8, restart=args.restart, lin_maxit=20000, precision=args.precision,
-                  precond=args.precond)
+                  precond=args.precond, mg_nu=args.mg_nu, mg_omega=args.mg_omega)
     st = ctx.device_state(prob.state_copy())
     log(args, f"[bench] 64^3 cavity N={prob.n_nodes} E={prob.n_elems} precision={args.precision}")
     t_sim, step_no = 0.0, 0

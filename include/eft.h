@@ -101,6 +101,9 @@ typedef struct {
     double band_flat;            /* band seed: |phi^n| < 1 - band_flat             */
     int32_t band_cell;           /* mesh cells per grid cell and axis              */
     int32_t band_halo;           /* grid-cell layers added around the seeds        */
+    int32_t mg_nu;               /* multigrid: smoothing sweeps before and after
+                                    the coarse correction (1..8)                   */
+    double mg_omega;             /* multigrid: damping of the block-Jacobi sweeps  */
 } eft_params;
 
 /* State at time level n (Sec. 2.1.2): values and rates.  DEVICE arrays. */

@@ -89,7 +89,7 @@ struct MGLevel {
     int32_t *dir_node = nullptr;
     uint8_t *dir_mask = nullptr;
     uint8_t *fmask = nullptr;        // [N]: bit c set when dof c is free (not Dirichlet)
-    eft_matrix A;                    // coarse levels: FP64 values
+    eft_matrix A;                    // FP32 values (level 0: FP32 copy of the Jacobian)
     double *Dinv = nullptr;          // [N][bs*bs]
     double *x = nullptr, *x2 = nullptr, *b = nullptr, *r = nullptr;  // [N*bs]
 };
@@ -155,10 +155,9 @@ struct eft_ctx {
     // geometric multigrid (structured Kuhn meshes with even cell counts)
     bool structured = false;
     std::vector<MGLevel> mg;
-    double *mg_dense = nullptr, *mg_inv = nullptr;   // coarsest level [nd][nd]
+    double *mg_dense = nullptr, *mg_inv = nullptr;   // coarsest level [nd][nd] over its free dofs
+    int32_t *mg_fidx = nullptr, *mg_free = nullptr;  // dof -> free index, free index -> dof
     int64_t mg_nd = 0;
-    double mg_omega = 0.7;
-    int mg_nu = 2;
 };
 
 // ------------------------------------------------------------- helpers ----

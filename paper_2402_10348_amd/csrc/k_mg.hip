@@ -285,16 +285,24 @@ __global__ __launch_bounds__(256) void k_prolong(Dims cd, Dims fd, int bs, const
 
 // -------------------------------------------------------- coarsest level --
 
-__global__ void k_dense_fill(int64_t n, int bs, const int32_t *rowptr, const int32_t *col, const double *val,
-                             double *M, int64_t nd)
+// Dense matrix of the coarsest level restricted to its free dofs: fidx maps a
+// dof to its free index (-1 for Dirichlet dofs, whose rows are unit rows).
+template <typename TV>
+__global__ void k_dense_fill(int64_t n, int bs, const int32_t *rowptr, const int32_t *col, const TV *val,
+                             const int32_t *fidx, double *M, int64_t nd)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    for (int64_t j = 0; j < nd; ++j)
-        for (int i = 0; i < bs; ++i) M[(r * bs + i) * nd + j] = 0.0;
-    for (int k = rowptr[r]; k < rowptr[r + 1]; ++k)
-        for (int i = 0; i < bs; ++i)
-            for (int j = 0; j < bs; ++j) M[(r * bs + i) * nd + (int64_t)col[k] * bs + j] = val[((int64_t)k * bs + i) * bs + j];
+    for (int i = 0; i < bs; ++i) {
+        const int fi = fidx[r * bs + i];
+        if (fi < 0) continue;
+        for (int64_t j = 0; j < nd; ++j) M[fi * nd + j] = 0.0;
+        for (int k = rowptr[r]; k < rowptr[r + 1]; ++k)
+            for (int j = 0; j < bs; ++j) {
+                const int fj = fidx[(int64_t)col[k] * bs + j];
+                if (fj >= 0) M[fi * nd + fj] = (double)val[((int64_t)k * bs + i) * bs + j];
+            }
+    }
 }
 
 // Gauss-Jordan inversion with partial pivoting, one workgroup; M is
@@ -362,15 +370,26 @@ __global__ __launch_bounds__(256) void k_gauss_jordan(double *M, double *Inv, in
     }
 }
 
-__global__ __launch_bounds__(256) void k_dense_apply(const double *Inv, int nd, const double *b, double *x,
-                                                     const int32_t *flag)
+// x = A^-1 b on the coarsest level: free dofs from the dense inverse, the
+// Dirichlet dofs zero
+__global__ __launch_bounds__(256) void k_dense_apply(const double *Inv, int nd, const int32_t *free_dof, int64_t ndof,
+                                                     const double *b, double *x, const int32_t *flag)
 {
     if (*flag == 0) return;
+    for (int64_t i = threadIdx.x; i < ndof; i += 256) x[i] = 0.0;
+    __syncthreads();
     for (int i = threadIdx.x; i < nd; i += 256) {
         double s = 0.0;
-        for (int j = 0; j < nd; ++j) s += Inv[(int64_t)i * nd + j] * b[j];
-        x[i] = s;
+        for (int j = 0; j < nd; ++j) s += Inv[(int64_t)i * nd + j] * b[free_dof[j]];
+        x[free_dof[i]] = s;
     }
+}
+
+// FP32 copy of a matrix's values (multigrid works on FP32 matrices)
+__global__ void k_to_f32(const double *a, float *b, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
 }
 
 // ------------------------------------------------------------------ host --
@@ -604,9 +623,39 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
         eft_mg_free(ctx);
         return EFT_OK;
     }
+    // the smoother and the transfers work on FP32 copies of the matrices (the
+    // preconditioner only shapes the Krylov space; FGMRES keeps FP64)
+    MGLevel &F0 = ctx->mg[0];
+    F0.A.bs = bs;
+    F0.A.n = ctx->N;
+    F0.A.nnzb = ctx->J.nnzb;
+    F0.A.rowptr = ctx->J.rowptr;
+    F0.A.col = ctx->J.col;
+    F0.A.diag = ctx->J.diag;
+    F0.A.fp32 = true;
+    EFT_TRY(dmal(ctx, &F0.A.val32, ctx->J.nnzb * bs * bs));
+    for (size_t l = 1; l < ctx->mg.size(); ++l) {
+        MGLevel &C = ctx->mg[l];
+        (void)hipFree(C.A.val);
+        C.A.val = nullptr;
+        C.A.fp32 = true;
+        EFT_TRY(dmal(ctx, &C.A.val32, C.A.nnzb * bs * bs));
+    }
+    // coarsest level: dense inverse over its free dofs
     const MGLevel &Lc = ctx->mg.back();
-    ctx->mg_nd = Lc.N * bs;
-    if (ctx->mg_nd <= 512) {
+    std::vector<uint8_t> cmh(Lc.N);
+    EFT_HIP(hipMemcpy(cmh.data(), Lc.fmask, Lc.N, hipMemcpyDeviceToHost));
+    std::vector<int32_t> fidx(Lc.N * bs, -1), fdof;
+    for (int64_t I = 0; I < Lc.N; ++I)
+        for (int c = 0; c < bs; ++c)
+            if ((cmh[I] >> c) & 1) {
+                fidx[I * bs + c] = (int32_t)fdof.size();
+                fdof.push_back((int32_t)(I * bs + c));
+            }
+    ctx->mg_nd = (int64_t)fdof.size();
+    if (ctx->mg_nd > 0 && ctx->mg_nd <= 512) {
+        EFT_TRY(dput(ctx, &ctx->mg_fidx, fidx));
+        EFT_TRY(dput(ctx, &ctx->mg_free, fdof));
         EFT_TRY(dmal(ctx, &ctx->mg_dense, ctx->mg_nd * ctx->mg_nd));
         EFT_TRY(dmal(ctx, &ctx->mg_inv, ctx->mg_nd * ctx->mg_nd));
     }
@@ -625,11 +674,14 @@ void eft_mg_free(eft_ctx *ctx)
             fr(L.Ba); fr(L.vp); fr(L.R); fr(L.dir_node); fr(L.dir_mask); fr(L.A.rowptr); fr(L.A.col); fr(L.A.diag);
             fr(L.A.val); fr(L.b); fr(L.iptr); fr(L.ient);
         }
-        fr(L.fmask); fr(L.Dinv); fr(L.x); fr(L.x2); fr(L.r);
+        fr(L.fmask); fr(L.Dinv); fr(L.x); fr(L.x2); fr(L.r); fr(L.A.val32);
     }
     ctx->mg.clear();
     fr(ctx->mg_dense);
     fr(ctx->mg_inv);
+    fr(ctx->mg_fidx);
+    fr(ctx->mg_free);
+    ctx->mg_fidx = ctx->mg_free = nullptr;
     ctx->mg_dense = ctx->mg_inv = nullptr;
     ctx->mg_nd = 0;
 }
@@ -645,7 +697,17 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
 {
     const int bs = ctx->bs;
     const int64_t L = (int64_t)ctx->mg.size();
-    EFT_TRY(eft_bj_setup(ctx, &ctx->J, ctx->mg[0].Dinv));
+    MGLevel &F0 = ctx->mg[0];
+    if (ctx->J.fp32) {
+        EFT_HIP(hipMemcpyAsync(F0.A.val32, ctx->J.val32, sizeof(float) * ctx->J.nnzb * bs * bs,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    } else {
+        const int64_t nv = ctx->J.nnzb * bs * bs;
+        hipLaunchKernelGGL(k_to_f32, dim3((int)std::min<int64_t>(8192, (nv + 255) / 256)), dim3(256), 0, ctx->stream,
+                           ctx->J.val, F0.A.val32, nv);
+        EFT_HIP(hipGetLastError());
+    }
+    EFT_TRY(eft_bj_setup(ctx, &F0.A, F0.Dinv));
     for (int64_t l = 1; l < L; ++l) {
         MGLevel &C = ctx->mg[l];
         InjArgs a;
@@ -696,8 +758,8 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
     }
     if (ctx->mg_inv) {
         const MGLevel &Cc = ctx->mg.back();
-        hipLaunchKernelGGL(k_dense_fill, dim3(eft_grid(Cc.N, 64)), dim3(64), 0, ctx->stream, Cc.N, bs, Cc.A.rowptr,
-                           Cc.A.col, Cc.A.val, ctx->mg_dense, ctx->mg_nd);
+        hipLaunchKernelGGL(k_dense_fill<float>, dim3(eft_grid(Cc.N, 64)), dim3(64), 0, ctx->stream, Cc.N, bs,
+                           Cc.A.rowptr, Cc.A.col, Cc.A.val32, ctx->mg_fidx, ctx->mg_dense, ctx->mg_nd);
         hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(256), 0, ctx->stream, ctx->mg_dense, ctx->mg_inv,
                            (int)ctx->mg_nd);
         EFT_HIP(hipGetLastError());
@@ -734,8 +796,8 @@ void launch_resid(eft_ctx *ctx, const eft_matrix &A, const TV *val, const double
 void sweep(eft_ctx *ctx, const eft_matrix &A, const double *Dinv, const double *b, const double *x, double *xo,
            const int32_t *flag)
 {
-    if (A.fp32) launch_sweep<float>(ctx, A, A.val32, Dinv, ctx->mg_omega, b, x, xo, flag);
-    else launch_sweep<double>(ctx, A, A.val, Dinv, ctx->mg_omega, b, x, xo, flag);
+    if (A.fp32) launch_sweep<float>(ctx, A, A.val32, Dinv, ctx->par.mg_omega, b, x, xo, flag);
+    else launch_sweep<double>(ctx, A, A.val, Dinv, ctx->par.mg_omega, b, x, xo, flag);
 }
 
 void resid(eft_ctx *ctx, const eft_matrix &A, const double *b, const double *x, double *r, const int32_t *flag)
@@ -748,18 +810,19 @@ void resid(eft_ctx *ctx, const eft_matrix &A, const double *b, const double *x, 
 double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag)
 {
     MGLevel &L = ctx->mg[l];
-    const eft_matrix &A = l == 0 ? ctx->J : L.A;
+    const eft_matrix &A = L.A;
     const int bs = ctx->bs;
     const int64_t nd = L.N * bs;
     double *cur = L.x, *oth = L.x2;
     const bool last = l + 1 == (int)ctx->mg.size();
     if (last && ctx->mg_inv) {
-        hipLaunchKernelGGL(k_dense_apply, dim3(1), dim3(256), 0, ctx->stream, ctx->mg_inv, (int)ctx->mg_nd, b, cur, flag);
+        hipLaunchKernelGGL(k_dense_apply, dim3(1), dim3(256), 0, ctx->stream, ctx->mg_inv, (int)ctx->mg_nd,
+                           ctx->mg_free, nd, b, cur, flag);
         return cur;
     }
-    hipLaunchKernelGGL(k_sweep0, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, nd, bs, L.Dinv, ctx->mg_omega, b,
+    hipLaunchKernelGGL(k_sweep0, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, nd, bs, L.Dinv, ctx->par.mg_omega, b,
                        cur, flag);
-    const int nu = last ? 40 : ctx->mg_nu;
+    const int nu = last ? 40 : ctx->par.mg_nu;
     for (int s = 1; s < nu; ++s) {
         sweep(ctx, A, L.Dinv, b, cur, oth, flag);
         std::swap(cur, oth);
@@ -777,7 +840,7 @@ double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag)
     double *xc = vcycle(ctx, l + 1, C.b, flag);
     hipLaunchKernelGGL(k_prolong, dim3(eft_grid(L.N, 256)), dim3(256), 0, ctx->stream, cd, fd, bs, C.fmask, L.fmask, xc,
                        cur, flag);
-    for (int s = 0; s < ctx->mg_nu; ++s) {
+    for (int s = 0; s < ctx->par.mg_nu; ++s) {
         sweep(ctx, A, L.Dinv, b, cur, oth, flag);
         std::swap(cur, oth);
     }

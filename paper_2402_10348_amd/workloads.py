@@ -154,6 +154,8 @@ class Params:
     band_flat: float = 1e-6
     band_cell: int = 4
     band_halo: int = 1
+    mg_nu: int = 2
+    mg_omega: float = 0.7
 
 
 @dataclass

@@ -47,7 +47,7 @@ def test_struct_layouts_match_header():
     from paper_2402_10348_amd import eft
     assert ctypes.sizeof(eft.Phase) == 32
     assert ctypes.sizeof(eft.Materials) == 40
-    assert ctypes.sizeof(eft.Params) == 8 * 7 + 4 * 2 + 8 + 4 * 4 + 8 + 4 * 2
+    assert ctypes.sizeof(eft.Params) == 8 * 7 + 4 * 2 + 8 + 4 * 4 + 8 + 4 * 2 + 4 + 4 + 8
     assert ctypes.sizeof(eft.State) == 8 * 8
     assert ctypes.sizeof(eft.StepInfo) == 16 + 8 * 129 + 24
     assert ctypes.sizeof(eft.TransportInfo) == 8 + 8 * 64 * 4 + 4 * 128 + 8 * 128
