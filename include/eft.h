@@ -152,6 +152,7 @@ typedef struct {
     int32_t n_blocks;            /* 1 + n_ind + n_s                                */
     double block_ratio[129];     /* last ||dx||/||x|| per block: [v,p], phi_i, B_s */
     double t_assemble, t_solve, t_transport;   /* seconds (host clock)            */
+    int32_t lin_iters_block[129];/* Krylov iterations per block over the step      */
 } eft_step_info;
 
 /* Create a context: copies the mesh to the device, builds the node graph

@@ -616,6 +616,7 @@ eft_status eft_step(eft_ctx *ctx, eft_state *st, double dt, eft_step_info *info)
         eft_solve_info si{};
         eft_status ls = eft_fgmres_dev(ctx, &ctx->J, ctx->R, ctx->dx, &si);
         inf.lin_iters_total += si.iters;
+        inf.lin_iters_block[0] += si.iters;
         if (ls == EFT_ENAN || ls == EFT_EDEVICE || ls == EFT_ENOMEM) {
             restore();
             return ls;
@@ -643,6 +644,7 @@ eft_status eft_step(eft_ctx *ctx, eft_state *st, double dt, eft_step_info *info)
             for (int b = 0; b < ctx->n_ind + ctx->n_s; ++b) {
                 inf.block_ratio[1 + b] = ti.ratio[b];
                 inf.lin_iters_total += ti.lin_iters[b];
+                inf.lin_iters_block[1 + b] += ti.lin_iters[b];
                 if (!std::isfinite(ti.ratio[b])) {
                     restore();
                     ctx->err = "NaN in the transport update";

@@ -70,7 +70,7 @@ class TransportInfo(C.Structure):
 class StepInfo(C.Structure):
     _fields_ = [("nl_iters", C.c_int32), ("converged", C.c_int32), ("lin_iters_total", C.c_int32),
                 ("n_blocks", C.c_int32), ("block_ratio", C.c_double * 129), ("t_assemble", C.c_double),
-                ("t_solve", C.c_double), ("t_transport", C.c_double)]
+                ("t_solve", C.c_double), ("t_transport", C.c_double), ("lin_iters_block", C.c_int32 * 129)]
 
 
 EXPORTS = ["eft_create", "eft_destroy", "eft_last_error", "eft_set_params", "eft_ns_matrix", "eft_matrix_shape",
@@ -308,4 +308,5 @@ class Context:
         nb = info.n_blocks
         return dict(nl_iters=info.nl_iters, converged=info.converged, lin_iters_total=info.lin_iters_total,
                     block_ratio=list(info.block_ratio[:nb]), t_assemble=info.t_assemble, t_solve=info.t_solve,
-                    t_transport=info.t_transport, t=S.t, step=S.step)
+                    t_transport=info.t_transport, t=S.t, step=S.step,
+                    lin_iters_block=list(info.lin_iters_block[:nb]))

@@ -41,16 +41,37 @@ def test_binding_lists_every_export():
     assert sorted(eft.EXPORTS) == declared()
 
 
-def test_struct_layouts_match_header():
-    """Sizes of the ABI structs computed by ctypes follow the C layout rules
-    the header implies (x86-64 LP64)."""
+PAIRS = [("Mesh", "eft_mesh"), ("Phase", "eft_phase"), ("Materials", "eft_materials"), ("Params", "eft_params"),
+         ("State", "eft_state"), ("Iterate", "eft_iterate"), ("SolveInfo", "eft_solve_info"),
+         ("TransportInfo", "eft_transport_info"), ("StepInfo", "eft_step_info")]
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes struct of the binding has the size and field offsets that
+    a C compiler gives the header's struct of the same role."""
+    import shutil
+    import subprocess
     from paper_2402_10348_amd import eft
-    assert ctypes.sizeof(eft.Phase) == 32
-    assert ctypes.sizeof(eft.Materials) == 40
-    assert ctypes.sizeof(eft.Params) == 8 * 7 + 4 * 2 + 8 + 4 * 4 + 8 + 4 * 2 + 4 + 4 + 8
-    assert ctypes.sizeof(eft.State) == 8 * 8
-    assert ctypes.sizeof(eft.StepInfo) == 16 + 8 * 129 + 24
-    assert ctypes.sizeof(eft.TransportInfo) == 8 + 8 * 64 * 4 + 4 * 128 + 8 * 128
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "eft.h"', 'int main(void) {']
+    for py, c in PAIRS:
+        lines.append(f'printf("{py} size %zu\\n", sizeof({c}));')
+        for f in getattr(eft, py)._fields_:
+            lines.append(f'printf("{py} {f[0]} %zu\\n", offsetof({c}, {f[0]}));')
+    lines += ["return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for py, _ in PAIRS:
+        cls = getattr(eft, py)
+        assert got[(py, "size")] == ctypes.sizeof(cls), py
+        for f in cls._fields_:
+            assert got[(py, f[0])] == getattr(cls, f[0]).offset, (py, f[0])
 
 
 def test_null_arguments_are_rejected(lib):
