@@ -9,10 +9,12 @@ linear solves to 1e-8 relative residual.
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
 Prints one JSON line.  The line carries
-  roofline      the BSR SpMV of the momentum Jacobian (the kernel that
-                dominates the step), timed with HIP events on the library's
-                stream: algorithmic bytes per launch / mean launch time, vs
-                the 8 TB/s HBM peak;
+  roofline      the fine-level multigrid smoother sweep (the kernel with the
+                largest share of the step), every launch in the timed steps
+                bracketed by HIP events on the library's stream: algorithmic
+                bytes / summed launch time, vs the 8 TB/s HBM peak; traffic
+                is the rocprofv3-measured HBM bytes per launch when the
+                kernel's sources match the ones profiled;
   cpu_baseline  the FP64 CPU oracle timed on a bounded sample of the same
                 workload on the host cores (see --no-cpu).
 Inputs are seeded and synthetic and resident in device memory before the
@@ -44,9 +46,12 @@ def parse():
     ap.add_argument("--precond", type=int, default=1, help="1 multigrid V-cycle, 0 point-block Jacobi")
     ap.add_argument("--mg-nu", type=int, default=2)
     ap.add_argument("--mg-omega", type=float, default=0.7)
-    ap.add_argument("--spmv-reps", type=int, default=50)
+    ap.add_argument("--kernel-role", type=int, default=1,
+                    help="kernel timed with HIP events over the timed steps: 1 fine-level smoother sweep, "
+                         "2 momentum SpMV in FGMRES, 0 none")
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="MiB copied by a plain device copy before the timed steps (HBM counter calibration)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--traffic", type=str, default="", help="JSON file with measured HBM bytes per SpMV launch")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -56,10 +61,52 @@ def log(args, *a):
         print(*a, file=sys.stderr, flush=True)
 
 
-def spmv_bytes(n, nnzb, bs, val_bytes=8):
-    """Compulsory bytes of one BSR SpMV: values, block columns, row pointers,
-    x and y read/written once."""
-    return nnzb * bs * bs * val_bytes + nnzb * 4 + (n + 1) * 4 + 2 * n * bs * 8
+KERNEL_NAME = {1: "k_sweep_rows<4, float> (fine-level multigrid smoother sweep, FP32 copy of the 4x4-block "
+                  "momentum Jacobian)",
+               2: "k_spmv_rows<4, double, true> (FP64 SpMV of the 4x4-block momentum Jacobian in FGMRES)"}
+
+# HBM bytes per launch of the fine-level sweep from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE counters, with the hash of the kernel's sources when they were
+# taken: a changed kernel has no measured traffic.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_rows_cavity64_hbm_traffic.md")
+TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2402_10348_amd", "csrc", f) for f in ("bsr_rows.h", "k_mg.hip")]
+
+
+def sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            kv[k.strip()] = v.strip().strip("`")
+    if kv.get("sources_sha256") != sources_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def calib_copy(torch, mib):
+    """A plain device-to-device copy of known size (mib MiB read, mib MiB
+    written), three times: the reference dispatches for scaling the HBM
+    counters of a profiled run."""
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def cpu_baseline(prob, counts, args):
@@ -157,12 +204,16 @@ def main():
     ctx = Context(prob, lin_rtol=1e-8, restart=args.restart, lin_maxit=20000, precision=args.precision,
                   precond=args.precond, mg_nu=args.mg_nu, mg_omega=args.mg_omega)
     st = ctx.device_state(prob.state_copy())
-    log(args, f"[bench] 64^3 cavity N={prob.n_nodes} E={prob.n_elems} precision={args.precision}")
+    log(args, f"[bench] {args.n}^3 cavity N={prob.n_nodes} E={prob.n_elems} precision={args.precision}")
     t_sim, step_no = 0.0, 0
     for w in range(args.warmup):
         info = ctx.step(st, t=t_sim, step=step_no)
         t_sim, step_no = info["t"], info["step"]
         log(args, f"[bench] warmup {w}: nl={info['nl_iters']} lin={info['lin_iters_total']}")
+    if args.calib_copy:
+        calib_copy(torch, args.calib_copy)
+    if args.kernel_role:
+        ctx.time_kernel(args.kernel_role)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
@@ -180,32 +231,16 @@ def main():
     lin_mean = float(np.mean([i["lin_iters_total"] for i in infos]))
     kblk = [float(v) for v in np.mean([i["lin_iters_block"] for i in infos], axis=0)]
 
-    # dominant kernel: the momentum SpMV, timed with events on the library stream
-    n, nnzb, bs = ctx.matrix_shape()
-    x = torch.randn(n, bs, dtype=torch.float64, device="cuda")
-    y = torch.empty_like(x)
-    stream = torch.cuda.current_stream()
-    for _ in range(3):
-        ctx.spmv(x, y)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.spmv_reps):
-        ctx.spmv(x, y)
-    e1.record(stream)
-    e1.synchronize()
-    t_spmv = e0.elapsed_time(e1) / 1e3 / args.spmv_reps
-    vb = 4 if args.precision == 1 else 8
-    alg = spmv_bytes(n, nnzb, bs, vb)
-    achieved = alg / t_spmv / 1e9
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get("bytes_per_launch")
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    kernel="k_spmv4 (BSR 4x4 SpMV of the momentum Jacobian)",
-                    bytes_per_launch=alg, mean_launch_s=t_spmv)
+    kt = ctx.kernel_time() if args.kernel_role else None
     ctx.close()
-
+    roofline = None
+    if kt and kt["launches"] > 0 and kt["seconds"] > 0:
+        achieved = kt["bytes"] / kt["seconds"] / 1e9
+        roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
+                        kernel=KERNEL_NAME[args.kernel_role], launches=kt["launches"], active_launches=kt["active"],
+                        bytes_per_launch=round(kt["bytes"] / kt["launches"]),
+                        mean_launch_s=kt["seconds"] / kt["launches"])
     cpu = None
     if not args.no_cpu:
         log(args, "[bench] timing the CPU oracle sample ...")

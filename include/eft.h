@@ -155,6 +155,16 @@ typedef struct {
     int32_t lin_iters_block[129];/* Krylov iterations per block over the step      */
 } eft_step_info;
 
+typedef struct {
+    int64_t launches;            /* timed launches of the kernel role              */
+    int64_t active;              /* of these, launches that did work (launches of
+                                    Krylov columns past convergence return at once) */
+    double seconds;              /* summed HIP-event durations                     */
+    double bytes;                /* summed algorithmic bytes (matrix values, column
+                                    indices, row pointers, every vector entry read
+                                    or written once)                               */
+} eft_kernel_time;
+
 /* Create a context: copies the mesh to the device, builds the node graph
  * (BSR pattern of eq. LS_NS) and every workspace.  hip_stream may be NULL
  * (default stream).  EFT_EINVAL on inconsistent sizes or orientation. */
@@ -222,6 +232,18 @@ eft_status eft_transport_solids(eft_ctx *ctx, const eft_state *level_n, eft_iter
  * place (t += dt, step += 1).  A non-converged nonlinear loop still returns
  * EFT_OK with info->converged = 0 (the paper continues after 20 iterations). */
 eft_status eft_step(eft_ctx *ctx, eft_state *st, double dt, eft_step_info *info);
+
+/* Measurement hook, not part of the method: time every launch of one kernel
+ * role with a pair of HIP events on the context's stream.  role 0 = off,
+ * 1 = fine-level multigrid smoother sweep (x + omega D^-1 (b - A x) with the
+ * FP32 copy of the momentum Jacobian), 2 = SpMV of the momentum Jacobian
+ * inside FGMRES.  Resets the counters; two event records per timed launch
+ * are added to the stream.  EFT_EINVAL for an unknown role. */
+eft_status eft_time_kernel(eft_ctx *ctx, int32_t role);
+
+/* Counters of the role set by eft_time_kernel since it was called
+ * (synchronizes the context's stream).  *out is a HOST struct. */
+eft_status eft_kernel_time_read(eft_ctx *ctx, eft_kernel_time *out);
 
 #ifdef __cplusplus
 }

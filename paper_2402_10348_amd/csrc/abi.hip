@@ -105,6 +105,8 @@ void free_all(eft_ctx *ctx)
     KrylovWs &K = ctx->kw;
     fr(K.V); fr(K.Z); fr(K.w); fr(K.r); fr(K.Dinv); fr(K.part); fr(K.small); fr(K.flag);
     if (ctx->hscal) (void)hipHostFree(ctx->hscal);
+    for (hipEvent_t e : ctx->kt.ev) (void)hipEventDestroy(e);
+    ctx->kt.ev.clear();
 }
 
 eft_status check_params(eft_ctx *ctx, const eft_params *p)
@@ -396,6 +398,60 @@ double now_s()
 
 // --------------------------------------------------------------- the ABI --
 
+// ------------------------------------------------------- kernel timing ----
+
+int64_t eft_kt_begin(eft_ctx *ctx, int role)
+{
+    KTimer &T = ctx->kt;
+    if (T.role == EFT_KT_OFF || T.role != role) return -1;
+    const size_t need = 2 * (size_t)(T.pend + 1);
+    while (T.ev.size() < need) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        T.ev.push_back(e);
+    }
+    if (hipEventRecord(T.ev[2 * T.pend], ctx->stream) != hipSuccess) return -1;
+    return T.pend;
+}
+
+void eft_kt_end(eft_ctx *ctx, int64_t slot, double bytes)
+{
+    KTimer &T = ctx->kt;
+    if (slot < 0 || slot != T.pend) return;
+    if (hipEventRecord(T.ev[2 * slot + 1], ctx->stream) != hipSuccess) return;
+    T.pbytes.resize(T.pend + 1);
+    T.ptag.resize(T.pend + 1);
+    T.pbytes[slot] = bytes;
+    T.ptag[slot] = T.tag;
+    T.pend += 1;
+}
+
+void eft_kt_void_from(eft_ctx *ctx, int tag0)
+{
+    KTimer &T = ctx->kt;
+    for (int64_t i = 0; i < T.pend; ++i)
+        if (T.ptag[i] >= tag0) T.pbytes[i] = -1.0;
+}
+
+eft_status eft_kt_harvest(eft_ctx *ctx)
+{
+    KTimer &T = ctx->kt;
+    if (T.pend == 0) return EFT_OK;
+    EFT_HIP(hipEventSynchronize(T.ev[2 * T.pend - 1]));
+    for (int64_t i = 0; i < T.pend; ++i) {
+        float ms = 0.0f;
+        EFT_HIP(hipEventElapsedTime(&ms, T.ev[2 * i], T.ev[2 * i + 1]));
+        T.seconds += 1e-3 * ms;
+        T.launches += 1;
+        if (T.pbytes[i] >= 0.0) {
+            T.active += 1;
+            T.bytes += T.pbytes[i];
+        }
+    }
+    T.pend = 0;
+    return EFT_OK;
+}
+
 extern "C" {
 
 eft_status eft_create(const eft_mesh *mesh, const eft_materials *mat, const eft_params *par, void *hip_stream,
@@ -561,6 +617,33 @@ eft_status eft_transport_solids(eft_ctx *ctx, const eft_state *lvl, eft_iterate 
     eft_status st = eft_transport_dev(ctx, lvl, it, info);
     EFT_HIP(hipStreamSynchronize(ctx->stream));
     return st;
+}
+
+eft_status eft_time_kernel(eft_ctx *ctx, int32_t role)
+{
+    if (!ctx) return EFT_EINVAL;
+    if (role < EFT_KT_OFF || role > EFT_KT_SPMV) {
+        ctx->err = "eft_time_kernel: role must be 0, 1 or 2";
+        return EFT_EINVAL;
+    }
+    EFT_TRY(eft_kt_harvest(ctx));
+    KTimer &T = ctx->kt;
+    T.role = role;
+    T.tag = -1;
+    T.launches = T.active = 0;
+    T.seconds = T.bytes = 0.0;
+    return EFT_OK;
+}
+
+eft_status eft_kernel_time_read(eft_ctx *ctx, eft_kernel_time *out)
+{
+    if (!ctx || !out) return EFT_EINVAL;
+    EFT_TRY(eft_kt_harvest(ctx));
+    out->launches = ctx->kt.launches;
+    out->active = ctx->kt.active;
+    out->seconds = ctx->kt.seconds;
+    out->bytes = ctx->kt.bytes;
+    return EFT_OK;
 }
 
 eft_status eft_step(eft_ctx *ctx, eft_state *st, double dt, eft_step_info *info)

@@ -1,0 +1,153 @@
+// Block-row products of a BSR matrix with square bs x bs blocks, shared by
+// the Krylov SpMV and the multigrid smoother/residual kernels.
+//
+// One 64-wide wavefront owns R consecutive block rows.  Lane l = bs*j + r
+// (j < 64/bs) holds scalar row r of block k0 + j (+ 64/bs, + 2*64/bs, ... for
+// long rows) of each of them: it loads that row's bs contiguous values with
+// vector loads, gathers the bs entries of x under the block's column and
+// accumulates the dot product.  A whole block row of the 3D momentum matrix
+// (<= 15 blocks of 4x4) is then a single pass whose value loads cover one
+// contiguous run of the value array, and the R rows' passes are issued
+// together, so every load of a wavefront is in flight at once; partial sums
+// over j are combined with a shuffle tree over strides bs, 2 bs, 4 bs, ...
+//
+// Blocks are stored row-major (value (i, c) of block k at k*bs*bs + i*bs + c)
+// and the value array starts 256-byte aligned.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+typedef double eft_d2 __attribute__((ext_vector_type(2)));
+typedef float eft_f2 __attribute__((ext_vector_type(2)));
+typedef float eft_f4 __attribute__((ext_vector_type(4)));
+
+// One load, plain or non-temporal (streamed: not kept in the caches).
+template <bool NT, typename T> __device__ __forceinline__ T ld_hint(const T *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+// bs consecutive values starting at p, with the widest aligned vector loads
+// the offset allows.
+template <int BS, typename T, bool NT> struct RowLoad;
+
+template <int BS, bool NT> struct RowLoad<BS, double, NT> {
+    static __device__ __forceinline__ void get(const double *p, double (&v)[BS])
+    {
+        if constexpr (BS % 2 == 0) {
+#pragma unroll
+            for (int q = 0; q < BS / 2; ++q) {
+                const eft_d2 t = ld_hint<NT>(reinterpret_cast<const eft_d2 *>(p) + q);
+                v[2 * q] = t.x;
+                v[2 * q + 1] = t.y;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < BS; ++q) v[q] = ld_hint<NT>(p + q);
+        }
+    }
+};
+
+template <int BS, bool NT> struct RowLoad<BS, float, NT> {
+    static __device__ __forceinline__ void get(const float *p, double (&v)[BS])
+    {
+        if constexpr (BS % 4 == 0) {
+#pragma unroll
+            for (int q = 0; q < BS / 4; ++q) {
+                const eft_f4 t = ld_hint<NT>(reinterpret_cast<const eft_f4 *>(p) + q);
+                v[4 * q] = t.x;
+                v[4 * q + 1] = t.y;
+                v[4 * q + 2] = t.z;
+                v[4 * q + 3] = t.w;
+            }
+        } else if constexpr (BS % 2 == 0) {
+#pragma unroll
+            for (int q = 0; q < BS / 2; ++q) {
+                const eft_f2 t = ld_hint<NT>(reinterpret_cast<const eft_f2 *>(p) + q);
+                v[2 * q] = t.x;
+                v[2 * q + 1] = t.y;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < BS; ++q) v[q] = ld_hint<NT>(p + q);
+        }
+    }
+};
+
+// bs entries of x under block column c (cached loads: x is re-read by every
+// row that couples to c).
+template <int BS> __device__ __forceinline__ void x_get(const double *__restrict__ x, int64_t c, double (&v)[BS])
+{
+    const double *p = x + c * BS;
+    if constexpr (BS % 2 == 0) {
+#pragma unroll
+        for (int q = 0; q < BS / 2; ++q) {
+            const eft_d2 t = reinterpret_cast<const eft_d2 *>(p)[q];
+            v[2 * q] = t.x;
+            v[2 * q + 1] = t.y;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < BS; ++q) v[q] = p[q];
+    }
+}
+
+// (A x) of the block rows row[0..R-1] (rows >= n contribute nothing): the
+// result for scalar row r of row[q] ends in acc[q] of lane r (lanes
+// 0..bs-1); other lanes hold partial sums.  The first pass of every row is
+// unrolled across the R rows so that all their loads are in flight together.
+template <int BS, typename TV, int R, bool NT>
+__device__ __forceinline__ void bsr_rows_dot(const int64_t (&row)[R], int64_t n, const int32_t *__restrict__ rowptr,
+                                             const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                             const double *__restrict__ x, int lane, double (&acc)[R])
+{
+    constexpr int J = 64 / BS;
+    const int j = lane / BS, r = lane - j * BS;
+    int k0[R], k1[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        k0[q] = row[q] < n ? rowptr[row[q]] : 0;
+        k1[q] = row[q] < n ? rowptr[row[q] + 1] : 0;
+        acc[q] = 0.0;
+    }
+    if (j < J) {
+        double v[R][BS], xv[R][BS];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int k = k0[q] + j;
+            const bool ok = k < k1[q];
+            const int c = ok ? col[k] : 0;
+            if (ok) {
+                RowLoad<BS, TV, NT>::get(val + (int64_t)k * (BS * BS) + r * BS, v[q]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < BS; ++e) v[q][e] = 0.0;
+            }
+            x_get<BS>(x, c, xv[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+            for (int e = 0; e < BS; ++e) acc[q] += v[q][e] * xv[q][e];
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            for (int k = k0[q] + j + J; k < k1[q]; k += J) {
+                const int c = col[k];
+                double vv[BS], xx[BS];
+                RowLoad<BS, TV, NT>::get(val + (int64_t)k * (BS * BS) + r * BS, vv);
+                x_get<BS>(x, c, xx);
+#pragma unroll
+                for (int e = 0; e < BS; ++e) acc[q] += vv[e] * xx[e];
+            }
+    }
+#pragma unroll
+    for (int s = 1; s < J; s <<= 1)
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const double o = __shfl_down(acc[q], s * BS, 64);
+            if (j + s < J) acc[q] += o;
+        }
+}

@@ -94,6 +94,23 @@ struct MGLevel {
     double *x = nullptr, *x2 = nullptr, *b = nullptr, *r = nullptr;  // [N*bs]
 };
 
+// Optional HIP-event timing of one kernel role (a measurement hook): each
+// launch of that role is bracketed by two events on the context's stream and
+// carries its algorithmic bytes.  Launches inside a Krylov chunk are tagged
+// with their column; columns the solve never reached ran gated off and are
+// counted with zero bytes.
+enum { EFT_KT_OFF = 0, EFT_KT_SMOOTH = 1, EFT_KT_SPMV = 2 };
+struct KTimer {
+    int role = EFT_KT_OFF;
+    int tag = -1;                   // Krylov column being enqueued (-1: none)
+    std::vector<hipEvent_t> ev;     // event pool, two per pending launch
+    std::vector<double> pbytes;     // bytes of each pending launch
+    std::vector<int> ptag;          // tag of each pending launch
+    int64_t pend = 0;
+    int64_t launches = 0, active = 0;
+    double seconds = 0.0, bytes = 0.0;
+};
+
 struct eft_ctx {
     hipStream_t stream = nullptr;
     std::string err;
@@ -107,6 +124,7 @@ struct eft_ctx {
     std::vector<int> solid_ind;     // indicator of solid s
     double g[3] = {0, 0, 0};
     eft_params par{};
+    KTimer kt;
     // device mesh
     double *xyz = nullptr;
     int32_t *conn = nullptr;
@@ -238,3 +256,9 @@ eft_status eft_band_system_dev(eft_ctx *ctx, const eft_state *lvl, const eft_ite
 
 // abi helpers
 eft_status eft_reserve_band_sys(eft_ctx *ctx, int64_t n, int64_t nnz);
+
+// kernel timing hook (abi.hip)
+int64_t eft_kt_begin(eft_ctx *ctx, int role);
+void eft_kt_end(eft_ctx *ctx, int64_t slot, double bytes);
+void eft_kt_void_from(eft_ctx *ctx, int tag0);
+eft_status eft_kt_harvest(eft_ctx *ctx);

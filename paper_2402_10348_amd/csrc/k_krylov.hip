@@ -29,7 +29,7 @@ struct Small {
     __host__ __device__ int64_t size() const { return sc() + 8; }
 };
 // scalars: sc+0 ||w'||^2 (after pass 1), sc+1 ||w''||^2, sc+2 tol_abs, sc+3 beta,
-// sc+4 H[j+1][j] before the rotation
+// sc+4 H[j+1][j] before the rotation, sc+5 |g[j+1]| (residual estimate)
 // flags: 0 active, 1 columns done in this cycle, 2 breakdown, 3 second-pass gate
 
 // dots of w with V[0..nvec-1] (and w.w as index nvec when with_ww): partials
@@ -139,6 +139,7 @@ __global__ void k_givens(double *small, int m, int j, int32_t *flag)
     H[(int64_t)(j + 1) * m + j] = 0.0;
     g[j + 1] = -sn[j] * g[j];
     g[j] = cs[j] * g[j];
+    small[L.sc() + 5] = fabs(g[j + 1]);   // residual estimate after column j
     flag[1] = j + 1;
     const double tol = small[L.sc() + 2];
     if (!(fabs(g[j + 1]) > tol)) flag[0] = 0;  // converged (or NaN)
@@ -296,6 +297,14 @@ eft_status eft_dot_dev(eft_ctx *ctx, const double *x, const double *y, int64_t n
 }
 
 // Solve A x = b (x0 = 0).  The preconditioner is the point-block Jacobi of A.
+// Algorithmic bytes of one SpMV: values, column indices, row pointers, x
+// read and y written once.
+static double spmv_bytes(const eft_matrix *A)
+{
+    const double vb = A->fp32 ? 4.0 : 8.0, b2 = (double)A->bs * A->bs;
+    return (double)A->nnzb * (b2 * vb + 4.0) + (double)(A->n + 1) * 4.0 + 2.0 * A->n * A->bs * 8.0;
+}
+
 eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, double *x, eft_solve_info *info)
 {
     const int bs = A->bs;
@@ -325,7 +334,7 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
     if (!mg) EFT_TRY(eft_bj_setup(ctx, A, K.Dinv));
     const double tol = ctx->par.lin_rtol * bnorm;
     const int maxit = std::max(1, ctx->par.lin_maxit);
-    const int chunk = 8;
+    int chunk = 8;   // columns enqueued between two reads of the solver state
     int total = 0;
     double *small = K.small;
     eft_status st = EFT_ENOTCONV;
@@ -350,14 +359,20 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
         hipLaunchKernelGGL(k_start_cycle, dim3(sg), dim3(RB), 0, ctx->stream, K.r, K.V, nd, small, m, beta, tol,
                            K.flag);
         int jdone = 0;
-        for (int j0 = 0; j0 < mc; j0 += chunk) {
-            for (int j = j0; j < std::min(mc, j0 + chunk); ++j) {
+        double est_prev = beta;
+        int j_prev = 0;
+        for (int j0 = 0, j1 = 0; j0 < mc; j0 = j1) {
+            j1 = std::min(mc, j0 + chunk);
+            for (int j = j0; j < j1; ++j) {
                 double *vj = K.V + (int64_t)j * nd, *zj = K.Z + (int64_t)j * nd;
+                ctx->kt.tag = j;
                 if (mg)
                     EFT_TRY(eft_mg_vcycle(ctx, vj, zj, K.flag));
                 else
                     EFT_TRY(eft_bj_apply(ctx, bs, n, K.Dinv, vj, zj, K.flag));
+                const int64_t slot = A == &ctx->J ? eft_kt_begin(ctx, EFT_KT_SPMV) : -1;
                 EFT_TRY(eft_spmv_flag(ctx, A, zj, K.w, K.flag));
+                eft_kt_end(ctx, slot, spmv_bytes(A));
                 // pass 1: dots with V[0..j] and ||w||^2
                 dim3 g1(nblk, (j + 2 + KC - 1) / KC);
                 hipLaunchKernelGGL(k_mdot, g1, dim3(RB), 0, ctx->stream, K.V, nd, j + 1, 1, K.w, K.part, nblk,
@@ -385,11 +400,33 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
                                    nd, small, m, j, K.flag);
             }
             EFT_HIP(hipGetLastError());
+            ctx->kt.tag = -1;
             EFT_HIP(hipMemcpyAsync(ctx->hscal, K.flag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, ctx->stream));
+            EFT_HIP(hipMemcpyAsync(ctx->hscal + 2, small + L.sc() + 5, sizeof(double), hipMemcpyDeviceToHost,
+                                   ctx->stream));
             EFT_HIP(hipStreamSynchronize(ctx->stream));
             const int32_t *hf = (const int32_t *)ctx->hscal;
             jdone = hf[1];
+            eft_kt_void_from(ctx, jdone);
+            EFT_TRY(eft_kt_harvest(ctx));
             if (hf[0] == 0) break;
+            // next chunk: half the columns still needed at the faster of two
+            // convergence rates, the cycle's mean and the last chunk's (at
+            // least 1, at most 16).  GMRES convergence is irregular; columns
+            // enqueued past convergence still cost their (gated) launches,
+            // while a shorter chunk costs one more read of the state, so the
+            // prediction is taken short.
+            const double est = ctx->hscal[2];
+            chunk = 8;
+            if (est > 0.0 && est < beta && jdone > 0) {
+                double rate = std::log(est / beta) / (double)jdone;
+                if (est < est_prev && jdone > j_prev)
+                    rate = std::min(rate, std::log(est / est_prev) / (double)(jdone - j_prev));
+                const double need = std::log(tol / est) / rate;
+                if (std::isfinite(need)) chunk = (int)std::min(16.0, std::max(1.0, std::ceil(0.5 * need)));
+            }
+            est_prev = est;
+            j_prev = jdone;
         }
         // x += Z y
         hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(1), 0, ctx->stream, small, m, K.flag);

@@ -14,6 +14,7 @@
 // Dirichlet dofs are removed from the coarse space (masked in transfer).
 #include <algorithm>
 
+#include "bsr_rows.h"
 #include "dev_common.h"
 #include "eft_internal.h"
 
@@ -89,33 +90,34 @@ __global__ __launch_bounds__(256) void k_inject(InjArgs a)
 // ----------------------------------------------------------- smoothing ----
 
 // x_out = x_in + omega D^-1 (b - A x_in), bs = 4, one wavefront per block row
-template <typename TV>
-__global__ __launch_bounds__(256) void k_sweep4(int64_t n, const int32_t *__restrict__ rowptr,
-                                                const int32_t *__restrict__ col, const TV *__restrict__ val,
-                                                const double *__restrict__ Dinv, double omega,
-                                                const double *__restrict__ b, const double *__restrict__ x,
-                                                double *__restrict__ xo, const int32_t *flag)
+// x_out = x + omega D^-1 (b - A x) for bs in {3, 4}: one wavefront per
+// block row (bsr_rows.h) with streamed value loads; lanes 0..bs-1 finish the
+// row.  (Two rows per wavefront, which helps the plain product, measured
+// slower here.)
+template <int BS, typename TV>
+__global__ __launch_bounds__(256) void k_sweep_rows(int64_t n, const int32_t *__restrict__ rowptr,
+                                                    const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                    const double *__restrict__ Dinv, double omega,
+                                                    const double *__restrict__ b, const double *__restrict__ x,
+                                                    double *__restrict__ xo, const int32_t *flag)
 {
     if (*flag == 0) return;
+    const int64_t row[1] = {(int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)};
+    if (row[0] >= n) return;
     const int lane = threadIdx.x & 63;
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (row >= n) return;
-    const int slot = lane >> 4, e = lane & 15, c = e & 3;
-    const int k0 = rowptr[row], k1 = rowptr[row + 1];
-    double acc = 0.0;
-    for (int k = k0 + slot; k < k1; k += 4) acc += (double)val[(int64_t)k * 16 + e] * x[(int64_t)col[k] * 4 + c];
-    acc += __shfl_xor(acc, 1, 64);
-    acc += __shfl_xor(acc, 2, 64);
-    acc += __shfl_xor(acc, 16, 64);
-    acc += __shfl_xor(acc, 32, 64);
-    // lanes 0, 4, 8, 12 hold (A x) of rows 0..3
-    const double r0 = __shfl(acc, 0, 64), r1 = __shfl(acc, 4, 64), r2 = __shfl(acc, 8, 64), r3 = __shfl(acc, 12, 64);
-    if (lane < 4) {
-        const double *Dr = Dinv + row * 16 + lane * 4;
-        const double *br = b + row * 4;
-        const double u = Dr[0] * (br[0] - r0) + Dr[1] * (br[1] - r1) + Dr[2] * (br[2] - r2) + Dr[3] * (br[3] - r3);
-        xo[row * 4 + lane] = x[row * 4 + lane] + omega * u;
-    }
+    // row data of the update, loaded ahead of the product (lanes >= bs read
+    // row 0 of the block: in bounds, unused)
+    const int rl = lane < BS ? lane : 0;
+    const double br = b[row[0] * BS + rl], xr = x[row[0] * BS + rl];
+    double d[BS];
+    x_get<BS>(Dinv, row[0] * BS + rl, d);
+    double ax[1];
+    bsr_rows_dot<BS, TV, 1, true>(row, n, rowptr, col, val, x, lane, ax);
+    const double res = br - ax[0];
+    double u = 0.0;
+#pragma unroll
+    for (int c = 0; c < BS; ++c) u += d[c] * __shfl(res, c, 64);
+    if (lane < BS) xo[row[0] * BS + lane] = xr + omega * u;
 }
 
 // general bs <= 8
@@ -171,25 +173,30 @@ __global__ __launch_bounds__(256) void k_sweep0(int64_t nd, int bs, const double
 }
 
 // r = b - A x
-template <typename TV>
-__global__ __launch_bounds__(256) void k_resid4(int64_t n, const int32_t *__restrict__ rowptr,
-                                                const int32_t *__restrict__ col, const TV *__restrict__ val,
-                                                const double *__restrict__ b, const double *__restrict__ x,
-                                                double *__restrict__ r, const int32_t *flag)
+// r = b - A x, RESID_R block rows per wavefront (as the plain product)
+constexpr int RESID_R = 2;
+
+template <int BS, typename TV>
+__global__ __launch_bounds__(256) void k_resid_rows(int64_t n, const int32_t *__restrict__ rowptr,
+                                                    const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                    const double *__restrict__ b, const double *__restrict__ x,
+                                                    double *__restrict__ r, const int32_t *flag)
 {
     if (*flag == 0) return;
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    int64_t row[RESID_R];
+#pragma unroll
+    for (int q = 0; q < RESID_R; ++q) row[q] = w * RESID_R + q;
+    if (row[0] >= n) return;
     const int lane = threadIdx.x & 63;
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (row >= n) return;
-    const int slot = lane >> 4, e = lane & 15, c = e & 3;
-    const int k0 = rowptr[row], k1 = rowptr[row + 1];
-    double acc = 0.0;
-    for (int k = k0 + slot; k < k1; k += 4) acc += (double)val[(int64_t)k * 16 + e] * x[(int64_t)col[k] * 4 + c];
-    acc += __shfl_xor(acc, 1, 64);
-    acc += __shfl_xor(acc, 2, 64);
-    acc += __shfl_xor(acc, 16, 64);
-    acc += __shfl_xor(acc, 32, 64);
-    if (slot == 0 && c == 0) r[row * 4 + (e >> 2)] = b[row * 4 + (e >> 2)] - acc;
+    const int rl = lane < BS ? lane : 0;
+    double br[RESID_R], ax[RESID_R];
+#pragma unroll
+    for (int q = 0; q < RESID_R; ++q) br[q] = b[(row[q] < n ? row[q] : row[0]) * BS + rl];
+    bsr_rows_dot<BS, TV, RESID_R, false>(row, n, rowptr, col, val, x, lane, ax);
+#pragma unroll
+    for (int q = 0; q < RESID_R; ++q)
+        if (lane < BS && row[q] < n) r[row[q] * BS + lane] = br[q] - ax[q];
 }
 
 template <typename TV>
@@ -623,8 +630,10 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
         eft_mg_free(ctx);
         return EFT_OK;
     }
-    // the smoother and the transfers work on FP32 copies of the matrices (the
-    // preconditioner only shapes the Krylov space; FGMRES keeps FP64)
+    // the fine-level smoother works on an FP32 copy of the Jacobian (the
+    // preconditioner only shapes the Krylov space; FGMRES keeps FP64), which
+    // halves the bytes of the most expensive kernel of the cycle.  The coarse
+    // levels (1/8 of the rows per level) keep FP64 values.
     MGLevel &F0 = ctx->mg[0];
     F0.A.bs = bs;
     F0.A.n = ctx->N;
@@ -634,13 +643,6 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
     F0.A.diag = ctx->J.diag;
     F0.A.fp32 = true;
     EFT_TRY(dmal(ctx, &F0.A.val32, ctx->J.nnzb * bs * bs));
-    for (size_t l = 1; l < ctx->mg.size(); ++l) {
-        MGLevel &C = ctx->mg[l];
-        (void)hipFree(C.A.val);
-        C.A.val = nullptr;
-        C.A.fp32 = true;
-        EFT_TRY(dmal(ctx, &C.A.val32, C.A.nnzb * bs * bs));
-    }
     // coarsest level: dense inverse over its free dofs
     const MGLevel &Lc = ctx->mg.back();
     std::vector<uint8_t> cmh(Lc.N);
@@ -758,8 +760,8 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
     }
     if (ctx->mg_inv) {
         const MGLevel &Cc = ctx->mg.back();
-        hipLaunchKernelGGL(k_dense_fill<float>, dim3(eft_grid(Cc.N, 64)), dim3(64), 0, ctx->stream, Cc.N, bs,
-                           Cc.A.rowptr, Cc.A.col, Cc.A.val32, ctx->mg_fidx, ctx->mg_dense, ctx->mg_nd);
+        hipLaunchKernelGGL(k_dense_fill<double>, dim3(eft_grid(Cc.N, 64)), dim3(64), 0, ctx->stream, Cc.N, bs,
+                           Cc.A.rowptr, Cc.A.col, Cc.A.val, ctx->mg_fidx, ctx->mg_dense, ctx->mg_nd);
         hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(256), 0, ctx->stream, ctx->mg_dense, ctx->mg_inv,
                            (int)ctx->mg_nd);
         EFT_HIP(hipGetLastError());
@@ -773,24 +775,29 @@ template <typename TV>
 void launch_sweep(eft_ctx *ctx, const eft_matrix &A, const TV *val, const double *Dinv, double omega,
                   const double *b, const double *x, double *xo, const int32_t *flag)
 {
-    if (A.bs == 4)
-        hipLaunchKernelGGL(k_sweep4<TV>, dim3(eft_grid(A.n, 4)), dim3(256), 0, ctx->stream, A.n, A.rowptr, A.col, val,
-                           Dinv, omega, b, x, xo, flag);
+    const dim3 g(eft_grid(A.n, 4)), t(256);
+    if (A.bs == 3)
+        hipLaunchKernelGGL((k_sweep_rows<3, TV>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, Dinv, omega, b, x,
+                           xo, flag);
+    else if (A.bs == 4)
+        hipLaunchKernelGGL((k_sweep_rows<4, TV>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, Dinv, omega, b, x,
+                           xo, flag);
     else
-        hipLaunchKernelGGL(k_sweepb<TV>, dim3(eft_grid(A.n, 4)), dim3(256), 0, ctx->stream, A.n, A.bs, A.rowptr, A.col,
-                           val, Dinv, omega, b, x, xo, flag);
+        hipLaunchKernelGGL(k_sweepb<TV>, g, t, 0, ctx->stream, A.n, A.bs, A.rowptr, A.col, val, Dinv, omega, b, x, xo,
+                           flag);
 }
 
 template <typename TV>
 void launch_resid(eft_ctx *ctx, const eft_matrix &A, const TV *val, const double *b, const double *x, double *r,
                   const int32_t *flag)
 {
-    if (A.bs == 4)
-        hipLaunchKernelGGL(k_resid4<TV>, dim3(eft_grid(A.n, 4)), dim3(256), 0, ctx->stream, A.n, A.rowptr, A.col, val,
-                           b, x, r, flag);
+    const dim3 g(eft_grid(A.n, 4 * RESID_R)), g1(eft_grid(A.n, 4)), t(256);
+    if (A.bs == 3)
+        hipLaunchKernelGGL((k_resid_rows<3, TV>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, b, x, r, flag);
+    else if (A.bs == 4)
+        hipLaunchKernelGGL((k_resid_rows<4, TV>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, b, x, r, flag);
     else
-        hipLaunchKernelGGL(k_residb<TV>, dim3(eft_grid(A.n, 4)), dim3(256), 0, ctx->stream, A.n, A.bs, A.rowptr, A.col,
-                           val, b, x, r, flag);
+        hipLaunchKernelGGL(k_residb<TV>, g1, t, 0, ctx->stream, A.n, A.bs, A.rowptr, A.col, val, b, x, r, flag);
 }
 
 void sweep(eft_ctx *ctx, const eft_matrix &A, const double *Dinv, const double *b, const double *x, double *xo,
@@ -798,6 +805,23 @@ void sweep(eft_ctx *ctx, const eft_matrix &A, const double *Dinv, const double *
 {
     if (A.fp32) launch_sweep<float>(ctx, A, A.val32, Dinv, ctx->par.mg_omega, b, x, xo, flag);
     else launch_sweep<double>(ctx, A, A.val, Dinv, ctx->par.mg_omega, b, x, xo, flag);
+}
+
+// Algorithmic bytes of one sweep: values, column indices and row pointers
+// once, the block inverses, b and x read and x_out written once.
+double sweep_bytes(const eft_matrix &A)
+{
+    const double vb = A.fp32 ? 4.0 : 8.0, b2 = (double)A.bs * A.bs;
+    return (double)A.nnzb * (b2 * vb + 4.0) + (double)(A.n + 1) * 4.0 + (double)A.n * (b2 * 8.0 + 3.0 * A.bs * 8.0);
+}
+
+// fine-level sweeps carry the kernel-timing hook
+void timed_sweep(eft_ctx *ctx, int l, const eft_matrix &A, const double *Dinv, const double *b, const double *x,
+                 double *xo, const int32_t *flag)
+{
+    const int64_t slot = l == 0 ? eft_kt_begin(ctx, EFT_KT_SMOOTH) : -1;
+    sweep(ctx, A, Dinv, b, x, xo, flag);
+    eft_kt_end(ctx, slot, sweep_bytes(A));
 }
 
 void resid(eft_ctx *ctx, const eft_matrix &A, const double *b, const double *x, double *r, const int32_t *flag)
@@ -824,7 +848,7 @@ double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag)
                        cur, flag);
     const int nu = last ? 40 : ctx->par.mg_nu;
     for (int s = 1; s < nu; ++s) {
-        sweep(ctx, A, L.Dinv, b, cur, oth, flag);
+        timed_sweep(ctx, l, A, L.Dinv, b, cur, oth, flag);
         std::swap(cur, oth);
     }
     if (last) return cur;
@@ -841,7 +865,7 @@ double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag)
     hipLaunchKernelGGL(k_prolong, dim3(eft_grid(L.N, 256)), dim3(256), 0, ctx->stream, cd, fd, bs, C.fmask, L.fmask, xc,
                        cur, flag);
     for (int s = 0; s < ctx->par.mg_nu; ++s) {
-        sweep(ctx, A, L.Dinv, b, cur, oth, flag);
+        timed_sweep(ctx, l, A, L.Dinv, b, cur, oth, flag);
         std::swap(cur, oth);
     }
     return cur;

@@ -1,37 +1,40 @@
 // Sparse kernels of the Krylov solve (eq. LS_NS and the band systems):
 // BSR sparse matrix-vector product and point-block Jacobi.
 //
-// SpMV layout: one 64-wide wavefront per block row.  The wavefront reads
-// floor(64 / bs^2) whole blocks per step, one value per lane, so every load
-// instruction covers contiguous 128 B (bs = 4, FP64) runs of the value array;
-// x entries are gathered per block column.  bs = 1 uses 16 lanes per row.
+// SpMV layout for bs = 3, 4, 6 (the momentum/mass system in 2D and 3D and
+// the 3D B system): one wavefront per block row, one lane per scalar row of
+// a block (bsr_rows.h).  Other bs: one value per lane, LDS reduction.  bs = 1
+// uses 16 lanes per row.
+#include "bsr_rows.h"
 #include "dev_common.h"
 #include "eft_internal.h"
 
 template <typename TV> __device__ __forceinline__ double ld(const TV *p) { return (double)*p; }
 
-// bs = 4: shuffle reduction over the 4 columns and the 4 block slots.
-// GATED instances (inside the Krylov loop) return at once when the solve has
-// converged; the plain instances always do the full product.
-template <typename TV, bool GATED>
-__global__ __launch_bounds__(256) void k_spmv4(int64_t n, const int32_t *__restrict__ rowptr,
-                                               const int32_t *__restrict__ col, const TV *__restrict__ val,
-                                               const double *__restrict__ x, double *__restrict__ y,
-                                               const int32_t *active)
+// bs in {3, 4, 6}: SPMV_R block rows per wavefront, cached value loads
+// (measured fastest on the 64^3 momentum matrix).  GATED instances (inside
+// the Krylov loop) return at once when the solve has converged; the plain
+// instances always do the product.
+constexpr int SPMV_R = 2;
+
+template <int BS, typename TV, bool GATED>
+__global__ __launch_bounds__(256) void k_spmv_rows(int64_t n, const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                   const double *__restrict__ x, double *__restrict__ y,
+                                                   const int32_t *active)
 {
     if (GATED && *active == 0) return;
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    int64_t row[SPMV_R];
+#pragma unroll
+    for (int q = 0; q < SPMV_R; ++q) row[q] = w * SPMV_R + q;
+    if (row[0] >= n) return;
     const int lane = threadIdx.x & 63;
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (row >= n) return;
-    const int slot = lane >> 4, e = lane & 15, c = e & 3;
-    const int k0 = rowptr[row], k1 = rowptr[row + 1];
-    double acc = 0.0;
-    for (int k = k0 + slot; k < k1; k += 4) acc += ld(val + (int64_t)k * 16 + e) * x[(int64_t)col[k] * 4 + c];
-    acc += __shfl_xor(acc, 1, 64);
-    acc += __shfl_xor(acc, 2, 64);
-    acc += __shfl_xor(acc, 16, 64);
-    acc += __shfl_xor(acc, 32, 64);
-    if (slot == 0 && c == 0) y[row * 4 + (e >> 2)] = acc;
+    double acc[SPMV_R];
+    bsr_rows_dot<BS, TV, SPMV_R, false>(row, n, rowptr, col, val, x, lane, acc);
+#pragma unroll
+    for (int q = 0; q < SPMV_R; ++q)
+        if (lane < BS && row[q] < n) y[row[q] * BS + lane] = acc[q];
 }
 
 // general bs in 2..8: LDS reduction per wavefront.
@@ -84,24 +87,34 @@ __global__ __launch_bounds__(256) void k_spmv1(int64_t n, const int32_t *__restr
     if (row < n && sub == 0) y[row] = acc;
 }
 
+template <int BS, typename TV>
+static void spmv_rows_launch(eft_ctx *ctx, int64_t n, const int32_t *rowptr, const int32_t *col, const TV *val,
+                             const double *x, double *y, const int32_t *active)
+{
+    if (active)
+        hipLaunchKernelGGL((k_spmv_rows<BS, TV, true>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream, n,
+                           rowptr, col, val, x, y, active);
+    else
+        hipLaunchKernelGGL((k_spmv_rows<BS, TV, false>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream, n,
+                           rowptr, col, val, x, y, active);
+}
+
 template <typename TV>
 static void spmv_launch(eft_ctx *ctx, int64_t n, int bs, const int32_t *rowptr, const int32_t *col, const TV *val,
                         const double *x, double *y, const int32_t *active)
 {
-    if (bs == 1) {
+    if (bs == 1)
         hipLaunchKernelGGL(k_spmv1<TV>, dim3(eft_grid(n, 16)), dim3(256), 0, ctx->stream, n, rowptr, col, val, x, y,
                            active);
-    } else if (bs == 4) {
-        if (active)
-            hipLaunchKernelGGL((k_spmv4<TV, true>), dim3(eft_grid(n, 4)), dim3(256), 0, ctx->stream, n, rowptr, col,
-                               val, x, y, active);
-        else
-            hipLaunchKernelGGL((k_spmv4<TV, false>), dim3(eft_grid(n, 4)), dim3(256), 0, ctx->stream, n, rowptr, col,
-                               val, x, y, active);
-    } else {
+    else if (bs == 3)
+        spmv_rows_launch<3, TV>(ctx, n, rowptr, col, val, x, y, active);
+    else if (bs == 4)
+        spmv_rows_launch<4, TV>(ctx, n, rowptr, col, val, x, y, active);
+    else if (bs == 6)
+        spmv_rows_launch<6, TV>(ctx, n, rowptr, col, val, x, y, active);
+    else
         hipLaunchKernelGGL(k_spmvb<TV>, dim3(eft_grid(n, 4)), dim3(256), 0, ctx->stream, n, bs, rowptr, col, val, x,
                            y, active);
-    }
 }
 
 eft_status eft_spmv_flag(eft_ctx *ctx, const eft_matrix *A, const double *x, double *y, const int32_t *active)

@@ -73,9 +73,14 @@ class StepInfo(C.Structure):
                 ("t_solve", C.c_double), ("t_transport", C.c_double), ("lin_iters_block", C.c_int32 * 129)]
 
 
+class KernelTime(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("active", C.c_int64), ("seconds", C.c_double), ("bytes", C.c_double)]
+
+
 EXPORTS = ["eft_create", "eft_destroy", "eft_last_error", "eft_set_params", "eft_ns_matrix", "eft_matrix_shape",
            "eft_matrix_export", "eft_assemble", "eft_spmv", "eft_fgmres", "eft_bands_build", "eft_band_export",
-           "eft_band_system", "eft_transport_solids", "eft_step"]
+           "eft_band_system", "eft_transport_solids", "eft_step", "eft_time_kernel",
+           "eft_kernel_time_read"]
 
 _lib = None
 
@@ -221,6 +226,16 @@ class Context:
         for k, v in over.items():
             setattr(p, k, v)
         self._check(self.L.eft_set_params(self.ctx, C.byref(p)))
+
+    def time_kernel(self, role):
+        """Start HIP-event timing of one kernel role (0 off, 1 fine-level
+        smoother sweep, 2 momentum SpMV inside FGMRES); resets the counters."""
+        self._check(self.L.eft_time_kernel(self.ctx, C.c_int32(role)))
+
+    def kernel_time(self):
+        out = KernelTime()
+        self._check(self.L.eft_kernel_time_read(self.ctx, C.byref(out)))
+        return dict(launches=out.launches, active=out.active, seconds=out.seconds, bytes=out.bytes)
 
     # ------------------------------------------------------------- the ABI
     def assemble(self, lvl, it, with_J=True):

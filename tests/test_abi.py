@@ -80,3 +80,7 @@ def test_null_arguments_are_rejected(lib):
     assert lib.eft_create(None, None, None, None, ctypes.byref(out)) == 1   # EFT_EINVAL
     lib.eft_destroy.restype = ctypes.c_int
     assert lib.eft_destroy(None) == 1
+    lib.eft_time_kernel.restype = ctypes.c_int
+    assert lib.eft_time_kernel(None, 1) == 1
+    lib.eft_kernel_time_read.restype = ctypes.c_int
+    assert lib.eft_kernel_time_read(None, None) == 1

@@ -132,6 +132,34 @@ def test_multigrid_preconditioner_same_solution(torch_cuda, name, n):
     assert res[1][1] * 3 < res[0][1]
 
 
+def test_kernel_timer_counts(torch_cuda):
+    """The HIP-event timing hook sees every launch of the timed kernel role
+    in a solve: one SpMV and 2 nu - 1 fine-level sweeps per Krylov
+    iteration that did work, each with the algorithmic bytes of its shape."""
+    prob = W.cavity_sphere_3d(n=16)
+    say("[timer] sphere3d n=16")
+    lvl, it = W.perturbed_state(prob, seed=5)
+    ctx = ctx_for(prob, lin_rtol=1e-10)
+    R = ctx.assemble(ctx.device_state(lvl), ctx.device_state(it))
+    n, nnzb, bs = ctx.matrix_shape()
+    nu = prob.params.mg_nu
+    sweep_b = nnzb * (bs * bs * 4 + 4) + (n + 1) * 4 + n * (bs * bs * 8 + 3 * bs * 8)
+    spmv_b = nnzb * (bs * bs * 8 + 4) + (n + 1) * 4 + 2 * n * bs * 8
+    for role, per_it, nbytes in ((1, 2 * nu - 1, sweep_b), (2, 1, spmv_b)):
+        ctx.time_kernel(role)
+        x, info = ctx.fgmres(-R)
+        kt = ctx.kernel_time()
+        say(f"  role={role} iters={info['iters']} {kt}")
+        assert info["converged"] == 1
+        assert kt["active"] == info["iters"] * per_it
+        assert kt["launches"] >= kt["active"] and kt["seconds"] > 0.0
+        assert kt["bytes"] == pytest.approx(kt["active"] * nbytes, rel=1e-12)
+    ctx.time_kernel(0)
+    ctx.fgmres(-R)
+    assert ctx.kernel_time()["launches"] == 0
+    ctx.close()
+
+
 def test_fgmres_zero_rhs_and_restart_edge(torch_cuda):
     torch = torch_cuda
     prob = W.cavity_disk_2d(n=8)
