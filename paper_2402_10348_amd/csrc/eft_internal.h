@@ -90,7 +90,8 @@ struct MGLevel {
     uint8_t *dir_mask = nullptr;
     uint8_t *fmask = nullptr;        // [N]: bit c set when dof c is free (not Dirichlet)
     eft_matrix A;                    // FP32 values (level 0: FP32 copy of the Jacobian)
-    double *Dinv = nullptr;          // [N][bs*bs]
+    double *Dinv = nullptr;          // [N][bs*bs] (levels with FP64 values)
+    float *Dinv32 = nullptr;         // [N][bs*bs] (the level with FP32 values)
     double *x = nullptr, *x2 = nullptr, *b = nullptr, *r = nullptr;  // [N*bs]
 };
 
@@ -237,6 +238,7 @@ eft_status eft_fill_u8(eft_ctx *ctx, uint8_t *p, int64_t n);
 // k_sparse.hip
 eft_status eft_spmv_dev(eft_ctx *ctx, const eft_matrix *A, const double *x, double *y);
 eft_status eft_bj_setup(eft_ctx *ctx, const eft_matrix *A, double *Dinv);
+eft_status eft_bj_setup32(eft_ctx *ctx, const eft_matrix *A, float *Dinv);
 eft_status eft_bj_apply(eft_ctx *ctx, int bs, int64_t n, const double *Dinv, const double *x, double *z,
                         const int32_t *active);
 eft_status eft_spmv_flag(eft_ctx *ctx, const eft_matrix *A, const double *x, double *y, const int32_t *active);

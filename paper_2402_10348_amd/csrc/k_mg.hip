@@ -90,41 +90,52 @@ __global__ __launch_bounds__(256) void k_inject(InjArgs a)
 // ----------------------------------------------------------- smoothing ----
 
 // x_out = x_in + omega D^-1 (b - A x_in), bs = 4, one wavefront per block row
-// x_out = x + omega D^-1 (b - A x) for bs in {3, 4}: one wavefront per
-// block row (bsr_rows.h) with streamed value loads; lanes 0..bs-1 finish the
-// row.  (Two rows per wavefront, which helps the plain product, measured
-// slower here.)
+// x_out = x + omega D^-1 (b - A x) for bs in {3, 4}: SWEEP_R block rows per
+// wavefront (bsr_rows.h) with streamed value loads; lanes 0..bs-1 finish the
+// rows.  The block inverses D^-1 have the type of the matrix values.
+constexpr int SWEEP_R = 2;
+
 template <int BS, typename TV>
 __global__ __launch_bounds__(256) void k_sweep_rows(int64_t n, const int32_t *__restrict__ rowptr,
                                                     const int32_t *__restrict__ col, const TV *__restrict__ val,
-                                                    const double *__restrict__ Dinv, double omega,
+                                                    const TV *__restrict__ Dinv, double omega,
                                                     const double *__restrict__ b, const double *__restrict__ x,
                                                     double *__restrict__ xo, const int32_t *flag)
 {
     if (*flag == 0) return;
-    const int64_t row[1] = {(int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)};
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    int64_t row[SWEEP_R];
+#pragma unroll
+    for (int q = 0; q < SWEEP_R; ++q) row[q] = w * SWEEP_R + q;
     if (row[0] >= n) return;
     const int lane = threadIdx.x & 63;
-    // row data of the update, loaded ahead of the product (lanes >= bs read
-    // row 0 of the block: in bounds, unused)
+    // row data of the update, loaded ahead of the product (lanes >= bs, and
+    // rows past n, read the first row of the wavefront: in bounds, unused)
     const int rl = lane < BS ? lane : 0;
-    const double br = b[row[0] * BS + rl], xr = x[row[0] * BS + rl];
-    double d[BS];
-    x_get<BS>(Dinv, row[0] * BS + rl, d);
-    double ax[1];
-    bsr_rows_dot<BS, TV, 1, true>(row, n, rowptr, col, val, x, lane, ax);
-    const double res = br - ax[0];
-    double u = 0.0;
+    double br[SWEEP_R], xr[SWEEP_R], d[SWEEP_R][BS], ax[SWEEP_R];
 #pragma unroll
-    for (int c = 0; c < BS; ++c) u += d[c] * __shfl(res, c, 64);
-    if (lane < BS) xo[row[0] * BS + lane] = xr + omega * u;
+    for (int q = 0; q < SWEEP_R; ++q) {
+        const int64_t rr = row[q] < n ? row[q] : row[0];
+        br[q] = b[rr * BS + rl];
+        xr[q] = x[rr * BS + rl];
+        RowLoad<BS, TV, false>::get(Dinv + (rr * BS + rl) * BS, d[q]);
+    }
+    bsr_rows_dot<BS, TV, SWEEP_R, true>(row, n, rowptr, col, val, x, lane, ax);
+#pragma unroll
+    for (int q = 0; q < SWEEP_R; ++q) {
+        const double res = br[q] - ax[q];
+        double u = 0.0;
+#pragma unroll
+        for (int c = 0; c < BS; ++c) u += d[q][c] * __shfl(res, c, 64);
+        if (lane < BS && row[q] < n) xo[row[q] * BS + lane] = xr[q] + omega * u;
+    }
 }
 
 // general bs <= 8
 template <typename TV>
 __global__ __launch_bounds__(256) void k_sweepb(int64_t n, int bs, const int32_t *__restrict__ rowptr,
                                                 const int32_t *__restrict__ col, const TV *__restrict__ val,
-                                                const double *__restrict__ Dinv, double omega,
+                                                const TV *__restrict__ Dinv, double omega,
                                                 const double *__restrict__ b, const double *__restrict__ x,
                                                 double *__restrict__ xo, const int32_t *flag)
 {
@@ -151,13 +162,14 @@ __global__ __launch_bounds__(256) void k_sweepb(int64_t n, int bs, const int32_t
     __syncthreads();
     if (row < n && lane < bs) {
         double u = 0.0;
-        for (int cc = 0; cc < bs; ++cc) u += Dinv[row * b2 + lane * bs + cc] * res[wv][cc];
+        for (int cc = 0; cc < bs; ++cc) u += (double)Dinv[row * b2 + lane * bs + cc] * res[wv][cc];
         xo[row * bs + lane] = x[row * bs + lane] + omega * u;
     }
 }
 
 // x = omega D^-1 b (first sweep from x = 0)
-__global__ __launch_bounds__(256) void k_sweep0(int64_t nd, int bs, const double *__restrict__ Dinv, double omega,
+template <typename TD>
+__global__ __launch_bounds__(256) void k_sweep0(int64_t nd, int bs, const TD *__restrict__ Dinv, double omega,
                                                 const double *__restrict__ b, double *__restrict__ x,
                                                 const int32_t *flag)
 {
@@ -166,13 +178,12 @@ __global__ __launch_bounds__(256) void k_sweep0(int64_t nd, int bs, const double
     if (t >= nd) return;
     const int64_t r = t / bs;
     const int i = (int)(t - r * bs);
-    const double *D = Dinv + r * bs * bs + i * bs;
+    const TD *D = Dinv + r * bs * bs + i * bs;
     double s = 0.0;
-    for (int c = 0; c < bs; ++c) s += D[c] * b[r * bs + c];
+    for (int c = 0; c < bs; ++c) s += (double)D[c] * b[r * bs + c];
     x[t] = omega * s;
 }
 
-// r = b - A x
 // r = b - A x, RESID_R block rows per wavefront (as the plain product)
 constexpr int RESID_R = 2;
 
@@ -547,7 +558,7 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
     std::vector<uint8_t> fm(ctx->N);
     for (int64_t p = 0; p < ctx->N; ++p) fm[p] = (uint8_t)(full & ~dmask0[p]);
     EFT_TRY(dput(ctx, &L0.fmask, fm));
-    EFT_TRY(dmal(ctx, &L0.Dinv, ctx->N * bs * bs));
+    EFT_TRY(dmal(ctx, &L0.Dinv32, ctx->N * bs * bs));
     EFT_TRY(dmal(ctx, &L0.x, ctx->N * bs));
     EFT_TRY(dmal(ctx, &L0.x2, ctx->N * bs));
     EFT_TRY(dmal(ctx, &L0.r, ctx->N * bs));
@@ -676,7 +687,7 @@ void eft_mg_free(eft_ctx *ctx)
             fr(L.Ba); fr(L.vp); fr(L.R); fr(L.dir_node); fr(L.dir_mask); fr(L.A.rowptr); fr(L.A.col); fr(L.A.diag);
             fr(L.A.val); fr(L.b); fr(L.iptr); fr(L.ient);
         }
-        fr(L.fmask); fr(L.Dinv); fr(L.x); fr(L.x2); fr(L.r); fr(L.A.val32);
+        fr(L.fmask); fr(L.Dinv); fr(L.Dinv32); fr(L.x); fr(L.x2); fr(L.r); fr(L.A.val32);
     }
     ctx->mg.clear();
     fr(ctx->mg_dense);
@@ -709,7 +720,7 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
                            ctx->J.val, F0.A.val32, nv);
         EFT_HIP(hipGetLastError());
     }
-    EFT_TRY(eft_bj_setup(ctx, &F0.A, F0.Dinv));
+    EFT_TRY(eft_bj_setup32(ctx, &F0.A, F0.Dinv32));
     for (int64_t l = 1; l < L; ++l) {
         MGLevel &C = ctx->mg[l];
         InjArgs a;
@@ -772,10 +783,10 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
 namespace {
 
 template <typename TV>
-void launch_sweep(eft_ctx *ctx, const eft_matrix &A, const TV *val, const double *Dinv, double omega,
-                  const double *b, const double *x, double *xo, const int32_t *flag)
+void launch_sweep(eft_ctx *ctx, const eft_matrix &A, const TV *val, const TV *Dinv, double omega, const double *b,
+                  const double *x, double *xo, const int32_t *flag)
 {
-    const dim3 g(eft_grid(A.n, 4)), t(256);
+    const dim3 g(eft_grid(A.n, 4 * SWEEP_R)), g1(eft_grid(A.n, 4)), t(256);
     if (A.bs == 3)
         hipLaunchKernelGGL((k_sweep_rows<3, TV>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, Dinv, omega, b, x,
                            xo, flag);
@@ -783,7 +794,7 @@ void launch_sweep(eft_ctx *ctx, const eft_matrix &A, const TV *val, const double
         hipLaunchKernelGGL((k_sweep_rows<4, TV>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, Dinv, omega, b, x,
                            xo, flag);
     else
-        hipLaunchKernelGGL(k_sweepb<TV>, g, t, 0, ctx->stream, A.n, A.bs, A.rowptr, A.col, val, Dinv, omega, b, x, xo,
+        hipLaunchKernelGGL(k_sweepb<TV>, g1, t, 0, ctx->stream, A.n, A.bs, A.rowptr, A.col, val, Dinv, omega, b, x, xo,
                            flag);
 }
 
@@ -800,11 +811,22 @@ void launch_resid(eft_ctx *ctx, const eft_matrix &A, const TV *val, const double
         hipLaunchKernelGGL(k_residb<TV>, g1, t, 0, ctx->stream, A.n, A.bs, A.rowptr, A.col, val, b, x, r, flag);
 }
 
-void sweep(eft_ctx *ctx, const eft_matrix &A, const double *Dinv, const double *b, const double *x, double *xo,
-           const int32_t *flag)
+void sweep(eft_ctx *ctx, const MGLevel &L, const double *b, const double *x, double *xo, const int32_t *flag)
 {
-    if (A.fp32) launch_sweep<float>(ctx, A, A.val32, Dinv, ctx->par.mg_omega, b, x, xo, flag);
-    else launch_sweep<double>(ctx, A, A.val, Dinv, ctx->par.mg_omega, b, x, xo, flag);
+    if (L.A.fp32) launch_sweep<float>(ctx, L.A, L.A.val32, L.Dinv32, ctx->par.mg_omega, b, x, xo, flag);
+    else launch_sweep<double>(ctx, L.A, L.A.val, L.Dinv, ctx->par.mg_omega, b, x, xo, flag);
+}
+
+// first sweep from x = 0
+void sweep0(eft_ctx *ctx, const MGLevel &L, const double *b, double *x, const int32_t *flag)
+{
+    const int64_t nd = L.N * ctx->bs;
+    if (L.A.fp32)
+        hipLaunchKernelGGL(k_sweep0<float>, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, nd, ctx->bs, L.Dinv32,
+                           ctx->par.mg_omega, b, x, flag);
+    else
+        hipLaunchKernelGGL(k_sweep0<double>, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, nd, ctx->bs, L.Dinv,
+                           ctx->par.mg_omega, b, x, flag);
 }
 
 // Algorithmic bytes of one sweep: values, column indices and row pointers
@@ -812,16 +834,16 @@ void sweep(eft_ctx *ctx, const eft_matrix &A, const double *Dinv, const double *
 double sweep_bytes(const eft_matrix &A)
 {
     const double vb = A.fp32 ? 4.0 : 8.0, b2 = (double)A.bs * A.bs;
-    return (double)A.nnzb * (b2 * vb + 4.0) + (double)(A.n + 1) * 4.0 + (double)A.n * (b2 * 8.0 + 3.0 * A.bs * 8.0);
+    return (double)A.nnzb * (b2 * vb + 4.0) + (double)(A.n + 1) * 4.0 + (double)A.n * (b2 * vb + 3.0 * A.bs * 8.0);
 }
 
 // fine-level sweeps carry the kernel-timing hook
-void timed_sweep(eft_ctx *ctx, int l, const eft_matrix &A, const double *Dinv, const double *b, const double *x,
-                 double *xo, const int32_t *flag)
+void timed_sweep(eft_ctx *ctx, int l, const MGLevel &L, const double *b, const double *x, double *xo,
+                 const int32_t *flag)
 {
     const int64_t slot = l == 0 ? eft_kt_begin(ctx, EFT_KT_SMOOTH) : -1;
-    sweep(ctx, A, Dinv, b, x, xo, flag);
-    eft_kt_end(ctx, slot, sweep_bytes(A));
+    sweep(ctx, L, b, x, xo, flag);
+    eft_kt_end(ctx, slot, sweep_bytes(L.A));
 }
 
 void resid(eft_ctx *ctx, const eft_matrix &A, const double *b, const double *x, double *r, const int32_t *flag)
@@ -831,7 +853,8 @@ void resid(eft_ctx *ctx, const eft_matrix &A, const double *b, const double *x, 
 }
 
 // V-cycle on level l with right-hand side b; returns the buffer holding x
-double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag)
+// (out, when given, receives the last post-smoothing sweep)
+double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag, double *out = nullptr)
 {
     MGLevel &L = ctx->mg[l];
     const eft_matrix &A = L.A;
@@ -844,11 +867,10 @@ double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag)
                            ctx->mg_free, nd, b, cur, flag);
         return cur;
     }
-    hipLaunchKernelGGL(k_sweep0, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, nd, bs, L.Dinv, ctx->par.mg_omega, b,
-                       cur, flag);
+    sweep0(ctx, L, b, cur, flag);
     const int nu = last ? 40 : ctx->par.mg_nu;
     for (int s = 1; s < nu; ++s) {
-        timed_sweep(ctx, l, A, L.Dinv, b, cur, oth, flag);
+        timed_sweep(ctx, l, L, b, cur, oth, flag);
         std::swap(cur, oth);
     }
     if (last) return cur;
@@ -865,8 +887,10 @@ double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag)
     hipLaunchKernelGGL(k_prolong, dim3(eft_grid(L.N, 256)), dim3(256), 0, ctx->stream, cd, fd, bs, C.fmask, L.fmask, xc,
                        cur, flag);
     for (int s = 0; s < ctx->par.mg_nu; ++s) {
-        timed_sweep(ctx, l, A, L.Dinv, b, cur, oth, flag);
-        std::swap(cur, oth);
+        double *dst = (out && s + 1 == ctx->par.mg_nu) ? out : oth;
+        timed_sweep(ctx, l, L, b, cur, dst, flag);
+        oth = cur;
+        cur = dst;
     }
     return cur;
 }
@@ -877,8 +901,9 @@ double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag)
 eft_status eft_mg_vcycle(eft_ctx *ctx, const double *b0, double *z, const int32_t *flag)
 {
     MGLevel &L0 = ctx->mg[0];
-    double *x = vcycle(ctx, 0, b0, flag);
+    double *x = vcycle(ctx, 0, b0, flag, z);
     EFT_HIP(hipGetLastError());
-    EFT_HIP(hipMemcpyAsync(z, x, sizeof(double) * L0.N * ctx->bs, hipMemcpyDeviceToDevice, ctx->stream));
+    if (x != z)
+        EFT_HIP(hipMemcpyAsync(z, x, sizeof(double) * L0.N * ctx->bs, hipMemcpyDeviceToDevice, ctx->stream));
     return EFT_OK;
 }

@@ -137,9 +137,9 @@ eft_status eft_spmv_dev(eft_ctx *ctx, const eft_matrix *A, const double *x, doub
 
 // Inverse of each diagonal block by Gauss-Jordan elimination with partial
 // pivoting.  A block with a zero pivot gets the identity (no scaling).
-template <typename TV>
+template <typename TV, typename TD>
 __global__ __launch_bounds__(256) void k_bj_setup(int64_t n, int bs, const int32_t *__restrict__ diag,
-                                                  const TV *__restrict__ val, double *__restrict__ Dinv)
+                                                  const TV *__restrict__ val, TD *__restrict__ Dinv)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
@@ -180,9 +180,9 @@ __global__ __launch_bounds__(256) void k_bj_setup(int64_t n, int bs, const int32
             }
         }
     }
-    double *out = Dinv + r * b2;
+    TD *out = Dinv + r * b2;
     for (int i = 0; i < bs; ++i)
-        for (int j = 0; j < bs; ++j) out[i * bs + j] = ok ? I[i][j] : (i == j ? 1.0 : 0.0);
+        for (int j = 0; j < bs; ++j) out[i * bs + j] = (TD)(ok ? I[i][j] : (i == j ? 1.0 : 0.0));
 }
 
 __global__ __launch_bounds__(256) void k_bj_apply(int64_t nd, int bs, const double *__restrict__ Dinv,
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) void k_bj_apply(int64_t nd, int bs, const doub
     z[t] = s;
 }
 
-eft_status eft_bj_setup(eft_ctx *ctx, const eft_matrix *A, double *Dinv)
+template <typename TD> static eft_status bj_setup(eft_ctx *ctx, const eft_matrix *A, TD *Dinv)
 {
     if (A->n == 0) return EFT_OK;
     if (A->bs > 8) {
@@ -209,13 +209,23 @@ eft_status eft_bj_setup(eft_ctx *ctx, const eft_matrix *A, double *Dinv)
         return EFT_EINVAL;
     }
     if (A->fp32)
-        hipLaunchKernelGGL(k_bj_setup<float>, dim3(eft_grid(A->n, 256)), dim3(256), 0, ctx->stream, A->n, A->bs,
-                           A->diag, A->val32, Dinv);
+        hipLaunchKernelGGL((k_bj_setup<float, TD>), dim3(eft_grid(A->n, 256)), dim3(256), 0, ctx->stream, A->n,
+                           A->bs, A->diag, A->val32, Dinv);
     else
-        hipLaunchKernelGGL(k_bj_setup<double>, dim3(eft_grid(A->n, 256)), dim3(256), 0, ctx->stream, A->n, A->bs,
-                           A->diag, A->val, Dinv);
+        hipLaunchKernelGGL((k_bj_setup<double, TD>), dim3(eft_grid(A->n, 256)), dim3(256), 0, ctx->stream, A->n,
+                           A->bs, A->diag, A->val, Dinv);
     EFT_HIP(hipGetLastError());
     return EFT_OK;
+}
+
+eft_status eft_bj_setup(eft_ctx *ctx, const eft_matrix *A, double *Dinv)
+{
+    return bj_setup<double>(ctx, A, Dinv);
+}
+
+eft_status eft_bj_setup32(eft_ctx *ctx, const eft_matrix *A, float *Dinv)
+{
+    return bj_setup<float>(ctx, A, Dinv);
 }
 
 eft_status eft_bj_apply(eft_ctx *ctx, int bs, int64_t n, const double *Dinv, const double *x, double *z,

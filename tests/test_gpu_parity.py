@@ -143,7 +143,7 @@ def test_kernel_timer_counts(torch_cuda):
     R = ctx.assemble(ctx.device_state(lvl), ctx.device_state(it))
     n, nnzb, bs = ctx.matrix_shape()
     nu = prob.params.mg_nu
-    sweep_b = nnzb * (bs * bs * 4 + 4) + (n + 1) * 4 + n * (bs * bs * 8 + 3 * bs * 8)
+    sweep_b = nnzb * (bs * bs * 4 + 4) + (n + 1) * 4 + n * (bs * bs * 4 + 3 * bs * 8)
     spmv_b = nnzb * (bs * bs * 8 + 4) + (n + 1) * 4 + 2 * n * bs * 8
     for role, per_it, nbytes in ((1, 2 * nu - 1, sweep_b), (2, 1, spmv_b)):
         ctx.time_kernel(role)
