@@ -47,8 +47,10 @@ def parse():
     ap.add_argument("--mg-nu", type=int, default=2)
     ap.add_argument("--mg-omega", type=float, default=0.7)
     ap.add_argument("--kernel-role", type=int, default=1,
-                    help="kernel timed with HIP events over the timed steps: 1 fine-level smoother sweep, "
-                         "2 momentum SpMV in FGMRES, 0 none")
+                    help="kernel of the roofline object: 1 fine-level smoother sweep, 2 momentum SpMV in FGMRES, "
+                         "3 assembly (all three are timed with HIP events over the timed steps); 0 no timing")
+    ap.add_argument("--no-mixed", dest="mixed", action="store_false",
+                    help="skip the mixed-precision (FP32 Jacobian) run of the same steps")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB copied by a plain device copy before the timed steps (HBM counter calibration)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -63,7 +65,36 @@ def log(args, *a):
 
 KERNEL_NAME = {1: "k_sweep_rows<4, float> (fine-level multigrid smoother sweep, FP32 copy of the 4x4-block "
                   "momentum Jacobian)",
-               2: "k_spmv_rows<4, double, true> (FP64 SpMV of the 4x4-block momentum Jacobian in FGMRES)"}
+               2: "k_spmv_rows<4, double, true> (FP64 SpMV of the 4x4-block momentum Jacobian in FGMRES)",
+               3: "k_ns_rows<3, double> (momentum/mass residual and Jacobian assembly, bytes: J and R written "
+                  "once, connectivity and node fields read once)"}
+
+
+def run_mixed(args, prob, torch):
+    """The same steps with the mixed path: the momentum Jacobian assembled,
+    stored and applied in FP32 inside the FP64 Newton/Krylov iteration."""
+    from paper_2402_10348_amd.eft import Context
+    ctx = Context(prob, lin_rtol=1e-8, restart=args.restart, lin_maxit=20000, precision=1, precond=args.precond,
+                  mg_nu=args.mg_nu, mg_omega=args.mg_omega)
+    st = ctx.device_state(prob.state_copy())
+    t_sim, step_no = 0.0, 0
+    for _ in range(args.warmup):
+        info = ctx.step(st, t=t_sim, step=step_no)
+        t_sim, step_no = info["t"], info["step"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for _ in range(args.steps):
+        info = ctx.step(st, t=t_sim, step=step_no)
+        t_sim, step_no = info["t"], info["step"]
+        its.append(info)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.close()
+    return dict(value=round(args.steps / el, 4), unit="steps/s", ms_per_step=round(1e3 * el / args.steps, 2),
+                dtype="f64 residual/Krylov, f32 Jacobian",
+                nl_iters_per_step=sum(i["nl_iters"] for i in its) / len(its),
+                krylov_iters_per_step=sum(i["lin_iters_total"] for i in its) / len(its))
 
 # HBM bytes per launch of the fine-level sweep from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE counters, with the hash of the kernel's sources when they were
@@ -213,7 +244,7 @@ def main():
     if args.calib_copy:
         calib_copy(torch, args.calib_copy)
     if args.kernel_role:
-        ctx.time_kernel(args.kernel_role)
+        ctx.time_kernel(1, 2, 3)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
@@ -231,16 +262,25 @@ def main():
     lin_mean = float(np.mean([i["lin_iters_total"] for i in infos]))
     kblk = [float(v) for v in np.mean([i["lin_iters_block"] for i in infos], axis=0)]
 
-    kt = ctx.kernel_time() if args.kernel_role else None
+    kts = {r: ctx.kernel_time(r) for r in (1, 2, 3)} if args.kernel_role else {}
     ctx.close()
-    roofline = None
-    if kt and kt["launches"] > 0 and kt["seconds"] > 0:
+
+    def hbm(role, traffic=None):
+        kt = kts.get(role)
+        if not kt or kt["launches"] == 0 or kt["seconds"] <= 0:
+            return None
         achieved = kt["bytes"] / kt["seconds"] / 1e9
-        roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
-                        kernel=KERNEL_NAME[args.kernel_role], launches=kt["launches"], active_launches=kt["active"],
-                        bytes_per_launch=round(kt["bytes"] / kt["launches"]),
-                        mean_launch_s=kt["seconds"] / kt["launches"])
+        return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=KERNEL_NAME[role],
+                    launches=kt["launches"], active_launches=kt["active"],
+                    bytes_per_launch=round(kt["bytes"] / kt["launches"]), mean_launch_s=kt["seconds"] / kt["launches"])
+
+    roofline = hbm(args.kernel_role, measured_traffic() if args.kernel_role == 1 else None) if args.kernel_role else None
+    others = {name: hbm(r) for name, r in (("spmv", 2), ("assembly", 3)) if args.kernel_role and r != args.kernel_role}
+
+    mixed = None
+    if args.mixed:
+        mixed = run_mixed(args, prob, torch)
     cpu = None
     if not args.no_cpu:
         log(args, "[bench] timing the CPU oracle sample ...")
@@ -267,6 +307,8 @@ def main():
                    "parallelism": "1 GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "kernels": others,
+        "mixed_precision": mixed,
     }
     print(json.dumps(line), flush=True)
 

@@ -160,9 +160,10 @@ typedef struct {
     int64_t active;              /* of these, launches that did work (launches of
                                     Krylov columns past convergence return at once) */
     double seconds;              /* summed HIP-event durations                     */
-    double bytes;                /* summed algorithmic bytes (matrix values, column
-                                    indices, row pointers, every vector entry read
-                                    or written once)                               */
+    double bytes;                /* summed algorithmic bytes: every unique byte the
+                                    kernel must read or write, once (matrix values,
+                                    indices, vectors; for the assembly J, R, the
+                                    connectivity and the node fields it reads)     */
 } eft_kernel_time;
 
 /* Create a context: copies the mesh to the device, builds the node graph
@@ -233,17 +234,19 @@ eft_status eft_transport_solids(eft_ctx *ctx, const eft_state *level_n, eft_iter
  * EFT_OK with info->converged = 0 (the paper continues after 20 iterations). */
 eft_status eft_step(eft_ctx *ctx, eft_state *st, double dt, eft_step_info *info);
 
-/* Measurement hook, not part of the method: time every launch of one kernel
- * role with a pair of HIP events on the context's stream.  role 0 = off,
- * 1 = fine-level multigrid smoother sweep (x + omega D^-1 (b - A x) with the
- * FP32 copy of the momentum Jacobian), 2 = SpMV of the momentum Jacobian
- * inside FGMRES.  Resets the counters; two event records per timed launch
- * are added to the stream.  EFT_EINVAL for an unknown role. */
-eft_status eft_time_kernel(eft_ctx *ctx, int32_t role);
+/* Measurement hook, not part of the method: time every launch of the kernel
+ * roles set in role_mask with a pair of HIP events on the context's stream.
+ * Bit 1 = fine-level multigrid smoother sweep (x + omega D^-1 (b - A x) with
+ * the FP32 copy of the momentum Jacobian), bit 2 = SpMV of the momentum
+ * Jacobian inside FGMRES, bit 3 = momentum/mass assembly on the mesh (not the
+ * coarse levels).  0 turns timing off.  Resets the counters; two event records
+ * per timed launch are added to the stream.  EFT_EINVAL for other bits. */
+eft_status eft_time_kernel(eft_ctx *ctx, int32_t role_mask);
 
-/* Counters of the role set by eft_time_kernel since it was called
- * (synchronizes the context's stream).  *out is a HOST struct. */
-eft_status eft_kernel_time_read(eft_ctx *ctx, eft_kernel_time *out);
+/* Counters of one role (1, 2 or 3, as the bits above) since eft_time_kernel
+ * (synchronizes the context's stream).  *out is a HOST struct.  EFT_EINVAL
+ * for another role. */
+eft_status eft_kernel_time_read(eft_ctx *ctx, int32_t role, eft_kernel_time *out);
 
 #ifdef __cplusplus
 }

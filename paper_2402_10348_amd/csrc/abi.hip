@@ -403,7 +403,7 @@ double now_s()
 int64_t eft_kt_begin(eft_ctx *ctx, int role)
 {
     KTimer &T = ctx->kt;
-    if (T.role == EFT_KT_OFF || T.role != role) return -1;
+    if (!((T.mask >> role) & 1u)) return -1;
     const size_t need = 2 * (size_t)(T.pend + 1);
     while (T.ev.size() < need) {
         hipEvent_t e;
@@ -414,15 +414,17 @@ int64_t eft_kt_begin(eft_ctx *ctx, int role)
     return T.pend;
 }
 
-void eft_kt_end(eft_ctx *ctx, int64_t slot, double bytes)
+void eft_kt_end(eft_ctx *ctx, int64_t slot, double bytes, int role)
 {
     KTimer &T = ctx->kt;
     if (slot < 0 || slot != T.pend) return;
     if (hipEventRecord(T.ev[2 * slot + 1], ctx->stream) != hipSuccess) return;
     T.pbytes.resize(T.pend + 1);
     T.ptag.resize(T.pend + 1);
+    T.prole.resize(T.pend + 1);
     T.pbytes[slot] = bytes;
     T.ptag[slot] = T.tag;
+    T.prole[slot] = role;
     T.pend += 1;
 }
 
@@ -441,11 +443,12 @@ eft_status eft_kt_harvest(eft_ctx *ctx)
     for (int64_t i = 0; i < T.pend; ++i) {
         float ms = 0.0f;
         EFT_HIP(hipEventElapsedTime(&ms, T.ev[2 * i], T.ev[2 * i + 1]));
-        T.seconds += 1e-3 * ms;
-        T.launches += 1;
+        const int r = T.prole[i];
+        T.seconds[r] += 1e-3 * ms;
+        T.launches[r] += 1;
         if (T.pbytes[i] >= 0.0) {
-            T.active += 1;
-            T.bytes += T.pbytes[i];
+            T.active[r] += 1;
+            T.bytes[r] += T.pbytes[i];
         }
     }
     T.pend = 0;
@@ -619,30 +622,37 @@ eft_status eft_transport_solids(eft_ctx *ctx, const eft_state *lvl, eft_iterate 
     return st;
 }
 
-eft_status eft_time_kernel(eft_ctx *ctx, int32_t role)
+eft_status eft_time_kernel(eft_ctx *ctx, int32_t role_mask)
 {
     if (!ctx) return EFT_EINVAL;
-    if (role < EFT_KT_OFF || role > EFT_KT_SPMV) {
-        ctx->err = "eft_time_kernel: role must be 0, 1 or 2";
+    const uint32_t ok = (1u << EFT_KT_SMOOTH) | (1u << EFT_KT_SPMV) | (1u << EFT_KT_ASSEMBLE);
+    if ((uint32_t)role_mask & ~ok) {
+        ctx->err = "eft_time_kernel: role_mask may only set bits 1 (smoother), 2 (SpMV), 3 (assembly)";
         return EFT_EINVAL;
     }
     EFT_TRY(eft_kt_harvest(ctx));
     KTimer &T = ctx->kt;
-    T.role = role;
+    T.mask = (uint32_t)role_mask;
     T.tag = -1;
-    T.launches = T.active = 0;
-    T.seconds = T.bytes = 0.0;
+    for (int r = 0; r < EFT_KT_NROLE; ++r) {
+        T.launches[r] = T.active[r] = 0;
+        T.seconds[r] = T.bytes[r] = 0.0;
+    }
     return EFT_OK;
 }
 
-eft_status eft_kernel_time_read(eft_ctx *ctx, eft_kernel_time *out)
+eft_status eft_kernel_time_read(eft_ctx *ctx, int32_t role, eft_kernel_time *out)
 {
     if (!ctx || !out) return EFT_EINVAL;
+    if (role < 1 || role >= EFT_KT_NROLE) {
+        ctx->err = "eft_kernel_time_read: role must be 1, 2 or 3";
+        return EFT_EINVAL;
+    }
     EFT_TRY(eft_kt_harvest(ctx));
-    out->launches = ctx->kt.launches;
-    out->active = ctx->kt.active;
-    out->seconds = ctx->kt.seconds;
-    out->bytes = ctx->kt.bytes;
+    out->launches = ctx->kt.launches[role];
+    out->active = ctx->kt.active[role];
+    out->seconds = ctx->kt.seconds[role];
+    out->bytes = ctx->kt.bytes[role];
     return EFT_OK;
 }
 

@@ -95,21 +95,21 @@ struct MGLevel {
     double *x = nullptr, *x2 = nullptr, *b = nullptr, *r = nullptr;  // [N*bs]
 };
 
-// Optional HIP-event timing of one kernel role (a measurement hook): each
-// launch of that role is bracketed by two events on the context's stream and
-// carries its algorithmic bytes.  Launches inside a Krylov chunk are tagged
-// with their column; columns the solve never reached ran gated off and are
-// counted with zero bytes.
-enum { EFT_KT_OFF = 0, EFT_KT_SMOOTH = 1, EFT_KT_SPMV = 2 };
+// Optional HIP-event timing of kernel roles (a measurement hook): each
+// launch of a timed role is bracketed by two events on the context's stream
+// and carries its algorithmic bytes.  Launches inside a Krylov chunk are
+// tagged with their column; columns the solve never reached ran gated off and
+// are counted with zero bytes.
+enum { EFT_KT_SMOOTH = 1, EFT_KT_SPMV = 2, EFT_KT_ASSEMBLE = 3, EFT_KT_NROLE = 4 };
 struct KTimer {
-    int role = EFT_KT_OFF;
+    uint32_t mask = 0;              // bit r: role r is timed
     int tag = -1;                   // Krylov column being enqueued (-1: none)
     std::vector<hipEvent_t> ev;     // event pool, two per pending launch
     std::vector<double> pbytes;     // bytes of each pending launch
-    std::vector<int> ptag;          // tag of each pending launch
+    std::vector<int> ptag, prole;   // tag and role of each pending launch
     int64_t pend = 0;
-    int64_t launches = 0, active = 0;
-    double seconds = 0.0, bytes = 0.0;
+    int64_t launches[EFT_KT_NROLE] = {}, active[EFT_KT_NROLE] = {};
+    double seconds[EFT_KT_NROLE] = {}, bytes[EFT_KT_NROLE] = {};
 };
 
 struct eft_ctx {
@@ -261,6 +261,6 @@ eft_status eft_reserve_band_sys(eft_ctx *ctx, int64_t n, int64_t nnz);
 
 // kernel timing hook (abi.hip)
 int64_t eft_kt_begin(eft_ctx *ctx, int role);
-void eft_kt_end(eft_ctx *ctx, int64_t slot, double bytes);
+void eft_kt_end(eft_ctx *ctx, int64_t slot, double bytes, int role);
 void eft_kt_void_from(eft_ctx *ctx, int tag0);
 eft_status eft_kt_harvest(eft_ctx *ctx);

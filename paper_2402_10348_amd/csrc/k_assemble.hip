@@ -530,6 +530,16 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
     }
     const int nb = eft_grid(M.N, M.rpb);
     const size_t shm = (size_t)M.rpb * ((size_t)M.maxc * BS * BS + BS) * sizeof(double);
+    // kernel-timing hook on the mesh level (not the coarse levels).
+    // Algorithmic bytes: J and R written once, the connectivity and every
+    // node field the element evaluation reads, once.
+    const bool fine = M.conn == ctx->conn;
+    const int64_t slot = fine ? eft_kt_begin(ctx, EFT_KT_ASSEMBLE) : -1;
+    const int d = ctx->dim;
+    const double abytes =
+        (J ? (double)J->nnzb * BS * BS * (J->fp32 ? 4.0 : 8.0) : 0.0) + (double)M.N * BS * 8.0 +
+        (double)M.E * (d + 1) * 4.0 +
+        (double)M.N * 8.0 * (d + BS + d + d + 2 + (double)ctx->n_s * (1 + ctx->nv));
     if (ctx->dim == 2) {
         if (J && J->fp32) hipLaunchKernelGGL((k_ns_rows<2, float>), dim3(nb), dim3(256), shm, ctx->stream, a, J->val32);
         else hipLaunchKernelGGL((k_ns_rows<2, double>), dim3(nb), dim3(256), shm, ctx->stream, a, J ? J->val : nullptr);
@@ -538,6 +548,7 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
         else hipLaunchKernelGGL((k_ns_rows<3, double>), dim3(nb), dim3(256), shm, ctx->stream, a, J ? J->val : nullptr);
     }
     EFT_HIP(hipGetLastError());
+    eft_kt_end(ctx, slot, abytes, EFT_KT_ASSEMBLE);
     if (M.n_dir > 0) {
         const int nbd = eft_grid(M.n_dir, 128);
         if (J && J->fp32)

@@ -372,7 +372,7 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
                     EFT_TRY(eft_bj_apply(ctx, bs, n, K.Dinv, vj, zj, K.flag));
                 const int64_t slot = A == &ctx->J ? eft_kt_begin(ctx, EFT_KT_SPMV) : -1;
                 EFT_TRY(eft_spmv_flag(ctx, A, zj, K.w, K.flag));
-                eft_kt_end(ctx, slot, spmv_bytes(A));
+                eft_kt_end(ctx, slot, spmv_bytes(A), EFT_KT_SPMV);
                 // pass 1: dots with V[0..j] and ||w||^2
                 dim3 g1(nblk, (j + 2 + KC - 1) / KC);
                 hipLaunchKernelGGL(k_mdot, g1, dim3(RB), 0, ctx->stream, K.V, nd, j + 1, 1, K.w, K.part, nblk,

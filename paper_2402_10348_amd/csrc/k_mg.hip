@@ -843,7 +843,7 @@ void timed_sweep(eft_ctx *ctx, int l, const MGLevel &L, const double *b, const d
 {
     const int64_t slot = l == 0 ? eft_kt_begin(ctx, EFT_KT_SMOOTH) : -1;
     sweep(ctx, L, b, x, xo, flag);
-    eft_kt_end(ctx, slot, sweep_bytes(L.A));
+    eft_kt_end(ctx, slot, sweep_bytes(L.A), EFT_KT_SMOOTH);
 }
 
 void resid(eft_ctx *ctx, const eft_matrix &A, const double *b, const double *x, double *r, const int32_t *flag)

@@ -227,14 +227,18 @@ class Context:
             setattr(p, k, v)
         self._check(self.L.eft_set_params(self.ctx, C.byref(p)))
 
-    def time_kernel(self, role):
-        """Start HIP-event timing of one kernel role (0 off, 1 fine-level
-        smoother sweep, 2 momentum SpMV inside FGMRES); resets the counters."""
-        self._check(self.L.eft_time_kernel(self.ctx, C.c_int32(role)))
+    def time_kernel(self, *roles):
+        """Start HIP-event timing of kernel roles (1 fine-level smoother
+        sweep, 2 momentum SpMV inside FGMRES, 3 momentum/mass assembly); no
+        roles turns timing off.  Resets the counters."""
+        mask = 0
+        for r in roles:
+            mask |= 1 << r
+        self._check(self.L.eft_time_kernel(self.ctx, C.c_int32(mask)))
 
-    def kernel_time(self):
+    def kernel_time(self, role):
         out = KernelTime()
-        self._check(self.L.eft_kernel_time_read(self.ctx, C.byref(out)))
+        self._check(self.L.eft_kernel_time_read(self.ctx, C.c_int32(role), C.byref(out)))
         return dict(launches=out.launches, active=out.active, seconds=out.seconds, bytes=out.bytes)
 
     # ------------------------------------------------------------- the ABI

@@ -83,4 +83,4 @@ def test_null_arguments_are_rejected(lib):
     lib.eft_time_kernel.restype = ctypes.c_int
     assert lib.eft_time_kernel(None, 1) == 1
     lib.eft_kernel_time_read.restype = ctypes.c_int
-    assert lib.eft_kernel_time_read(None, None) == 1
+    assert lib.eft_kernel_time_read(None, 1, None) == 1

@@ -145,18 +145,24 @@ def test_kernel_timer_counts(torch_cuda):
     nu = prob.params.mg_nu
     sweep_b = nnzb * (bs * bs * 4 + 4) + (n + 1) * 4 + n * (bs * bs * 4 + 3 * bs * 8)
     spmv_b = nnzb * (bs * bs * 8 + 4) + (n + 1) * 4 + 2 * n * bs * 8
+    ctx.time_kernel(1, 2, 3)
+    x, info = ctx.fgmres(-R)
+    assert info["converged"] == 1
     for role, per_it, nbytes in ((1, 2 * nu - 1, sweep_b), (2, 1, spmv_b)):
-        ctx.time_kernel(role)
-        x, info = ctx.fgmres(-R)
-        kt = ctx.kernel_time()
+        kt = ctx.kernel_time(role)
         say(f"  role={role} iters={info['iters']} {kt}")
-        assert info["converged"] == 1
         assert kt["active"] == info["iters"] * per_it
         assert kt["launches"] >= kt["active"] and kt["seconds"] > 0.0
         assert kt["bytes"] == pytest.approx(kt["active"] * nbytes, rel=1e-12)
-    ctx.time_kernel(0)
+    assert ctx.kernel_time(3)["launches"] == 0           # no assembly in a solve
+    ctx.assemble(ctx.device_state(lvl), ctx.device_state(it))
+    ka = ctx.kernel_time(3)
+    E, d = prob.n_elems, prob.dim
+    asm_b = nnzb * bs * bs * 8 + n * bs * 8 + E * (d + 1) * 4 + n * 8 * (d + bs + d + d + 2 + 1 * (1 + 6))
+    assert ka["launches"] == 1 and ka["bytes"] == pytest.approx(asm_b, rel=1e-12)
+    ctx.time_kernel()
     ctx.fgmres(-R)
-    assert ctx.kernel_time()["launches"] == 0
+    assert ctx.kernel_time(1)["launches"] == 0
     ctx.close()
 
 
@@ -373,6 +379,36 @@ def test_step_matches_oracle(torch_cuda, name, nsteps, over):
         e = np.linalg.norm(st[k] - st0[k]) * dt / max(np.linalg.norm(st0[f]), 1e-300)
         say(f"  {k}: dt-scaled {e:.2e}")
         assert e < 1e-10, k
+
+
+@pytest.mark.parametrize("name,nsteps,over", [
+    ("disk2d_32", 2, dict(nl_fixed=3)),
+    ("sphere3d_8", 2, dict(nl_fixed=4)),
+    ("falling3d_5", 1, dict(nl_fixed=3)),
+])
+def test_mixed_precision_step_matches_oracle(torch_cuda, name, nsteps, over):
+    """Mixed path: the momentum Jacobian stored and applied in FP32 inside the
+    FP64 Newton/Krylov iteration (residual, Krylov vectors and
+    orthogonalization FP64).  Its Newton fixed point is the FP64 one, so after
+    the same nonlinear iterations the fields match the FP64 oracle to 1e-6."""
+    prob = W.cavity_sphere_3d(n=8) if name == "sphere3d_8" else CASES[name]()
+    say(f"[mixed] case={name} steps={nsteps} {over}")
+    over = dict(over, lin_rtol=1e-13, restart=200, lin_maxit=40000)
+    c = O.Case(prob, **over)
+    st0 = prob.state_copy()
+    for _ in range(nsteps):
+        c.step(st0)
+    ctx = ctx_for(prob, precision=1, **over)
+    st = ctx.device_state(prob.state_copy())
+    for _ in range(nsteps):
+        ctx.step(st)
+    for k in ("vp", "phi", "B"):
+        if st0[k].size == 0:
+            continue
+        e = relnorm(to_np(st[k]), st0[k])
+        say(f"  {k}: rel {e:.2e}")
+        assert e < 1e-6, k
+    ctx.close()
 
 
 def test_rest_state_on_gpu(torch_cuda):
