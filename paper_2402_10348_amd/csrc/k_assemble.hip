@@ -102,20 +102,34 @@ struct RowArgs {
 };
 
 template <int D, typename TJ>
-__global__ __launch_bounds__(256) void k_ns_rows(RowArgs a, TJ *__restrict__ Jv)
+__global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ Jv)
 {
     extern __shared__ double lds[];
     constexpr int NN = D + 1, BS = D + 1, B2 = BS * BS, NQ = Rule<D>::NQ, NVv = NV<D>::v;
+    // LDS strides padded to an odd number of doubles: with 4x4 blocks at a
+    // 128-byte stride, entry (i, k) of every block would sit in one bank and
+    // each atomic instruction would serialize over the wavefront
+    constexpr int BP = B2 | 1, RP = BS | 1;
     const int64_t r0 = (int64_t)blockIdx.x * a.rpb;
     const int64_t r1 = r0 + a.rpb < a.N ? r0 + a.rpb : a.N;
-    double *accJ = lds;                                 // [rpb][maxc][B2]
-    double *accR = lds + (int64_t)a.rpb * a.maxc * B2;  // [rpb][BS]
-    const int nacc = a.rpb * a.maxc * B2 + a.rpb * BS;
+    double *accJ = lds;                                 // [rpb][maxc][BP]
+    double *accR = lds + (int64_t)a.rpb * a.maxc * BP;  // [rpb][RP]
+    const int nacc = a.rpb * a.maxc * BP + a.rpb * RP;
+    __shared__ int maxinc;
+    if (threadIdx.x == 0) maxinc = 0;
     for (int t = threadIdx.x; t < nacc; t += blockDim.x) lds[t] = 0.0;
     __syncthreads();
+    const int nrow = (int)(r1 - r0);
+    if (threadIdx.x < nrow) atomicMax(&maxinc, a.iptr[r0 + threadIdx.x + 1] - a.iptr[r0 + threadIdx.x]);
+    __syncthreads();
     const double gv[3] = {a.g0, a.g1, a.g2};
-    const int i0 = a.iptr[r0], i1 = a.iptr[r1];
-    for (int ii = i0 + threadIdx.x; ii < i1; ii += blockDim.x) {
+    // (row, incident element) pairs are dealt row-interleaved: consecutive
+    // lanes take different rows, so the LDS atomics of one wavefront rarely
+    // hit the same block (all elements of a row add into its diagonal block)
+    for (int k = threadIdx.x; k < nrow * maxinc; k += blockDim.x) {
+        const int kr = k % nrow;
+        const int ii = a.iptr[r0 + kr] + k / nrow;
+        if (ii >= a.iptr[r0 + kr + 1]) continue;
         const int32_t ent = a.ient[ii];
         const int64_t e = ent >> 2;
         const int la = ent & 3;
@@ -168,9 +182,18 @@ __global__ __launch_bounds__(256) void k_ns_rows(RowArgs a, TJ *__restrict__ Jv)
         double rl[BS];
 #pragma unroll
         for (int i = 0; i < BS; ++i) rl[i] = 0.0;
-        double Wa[NQ], U[NN][NQ], TM[NQ];
-        double muI = 0.0, Tc = 0.0, Tp = 0.0;
+        // tangent sums per column node b, accumulated over the quadrature
+        // points: A_b = int W_a (c_t N_b + alpha u_b), C_b = int W_a N_b,
+        // Q1_b = int tau_m (c_t N_b + alpha u_b), Q2_b = int tau_m N_b, with
+        // W_a = rho (N_a + tau_m u_a) and u_b = v . grad N_b
+        double As[NN], Cs[NN], Q1s[NN], Q2s[NN];
 #pragma unroll
+        for (int b = 0; b < NN; ++b) As[b] = Cs[b] = Q1s[b] = Q2s[b] = 0.0;
+        double muI = 0.0, Tc = 0.0, Tp = 0.0, Pa = 0.0;
+        // not unrolled: nothing here is indexed by q, and one point's
+        // temporaries at a time keep the register count (and so the
+        // occupancy) in check
+#pragma unroll 1
         for (int q = 0; q < NQ; ++q) {
             double rq = 0.0, mq = 0.0, pq = 0.0, vq[D], aq[D];
 #pragma unroll
@@ -208,15 +231,10 @@ __global__ __launch_bounds__(256) void k_ns_rows(RowArgs a, TJ *__restrict__ Jv)
             const double nu = mq / rq;
             const double tau_m = 1.0 / sqrt(inv4dt2 + vGv + a.C_I * nu * nu * GG);
             const double tau_c = 1.0 / (trG * tau_m);
-#pragma unroll
-            for (int b = 0; b < NN; ++b) {
-                double s = 0.0;
-#pragma unroll
-                for (int j = 0; j < D; ++j) s += vq[j] * dN[b][j];
-                U[b][q] = s;
-            }
             const double Na = shape_at<D>(q, la);
-            const double ua = U[la][q];
+            double ua = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) ua += vq[j] * dN[la][j];
             double gR = 0.0;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
@@ -227,28 +245,66 @@ __global__ __launch_bounds__(256) void k_ns_rows(RowArgs a, TJ *__restrict__ Jv)
                 gR += dN[la][i] * Rm[i];
             }
             rl[D] += w * (Na * divv + (tau_m / rq) * gR);
-            Wa[q] = w * rq * (Na + tau_m * ua);
-            TM[q] = w * tau_m;
+            const double Wq = w * rq * (Na + tau_m * ua), TMq = w * tau_m;
+#pragma unroll
+            for (int b = 0; b < NN; ++b) {
+                double ub = 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) ub += vq[j] * dN[b][j];
+                const double Nb = shape_at<D>(q, b);
+                const double lin = a.ct * Nb + a.alpha * ub;
+                As[b] += Wq * lin;
+                Cs[b] += Wq * Nb;
+                Q1s[b] += TMq * lin;
+                Q2s[b] += TMq * Nb;
+            }
+            Pa += TMq * ua;
             muI += w * mq;
             Tc += w * tau_c * rq;
             Tp += w * tau_m / rq;
         }
-        // elastic stress mu_L (B - I) of every solid present on the element,
-        // and the sums its tangent needs (the dB/dv tangent is linear in them):
-        //   M2       = sum_s int alpha_s mu_L,s B_s
-        //   T[b][i][k] = sum_s (int N_b alpha_s mu_L,s) (dB_s/dx_k grad N_a)_i
-        double M2[D][D], T[NN][D][D];
-        bool solid = false;
+        // fluid (and pressure) blocks of the row: d(residual of node la)/d(node ib)
+        if (Jv != nullptr) {
+            const double al = a.alpha;
+            const double NI = w * (Rule<D>::QA + (NQ - 1) * Rule<D>::QB);
+            double aL[D];
 #pragma unroll
-        for (int i = 0; i < D; ++i)
+            for (int k = 0; k < D; ++k) {
+                double s = 0.0;
 #pragma unroll
-            for (int j = 0; j < D; ++j) M2[i][j] = 0.0;
+                for (int j = 0; j < D; ++j) s += dN[la][j] * L[j][k];
+                aL[k] = s;
+            }
+            const int64_t rbase = a.rowptr[row];
+#pragma unroll 1
+            for (int ib = 0; ib < NN; ++ib) {
+                const double A = As[ib], C = al * Cs[ib], Q1 = Q1s[ib], Q2 = Q2s[ib];
+                double gab = 0.0;
 #pragma unroll
-        for (int b = 0; b < NN; ++b)
+                for (int j = 0; j < D; ++j) gab += dN[la][j] * dN[ib][j];
+                const int slot = (int)(a.epos[e * NN * NN + la * NN + ib] - rbase);
+                double *blk = accJ + ((int64_t)lr * a.maxc + slot) * BP;
 #pragma unroll
-            for (int i = 0; i < D; ++i)
+                for (int i = 0; i < D; ++i) {
 #pragma unroll
-                for (int k = 0; k < D; ++k) T[b][i][k] = 0.0;
+                    for (int k = 0; k < D; ++k) {
+                        double val = C * L[i][k] + al * muI * dN[la][k] * dN[ib][i] + al * Tc * dN[la][i] * dN[ib][k];
+                        if (i == k) val += A + al * muI * gab;
+                        atomicAdd(blk + i * BS + k, val);
+                    }
+                    atomicAdd(blk + i * BS + D, -dN[la][i] * NI + Pa * dN[ib][i]);
+                }
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    atomicAdd(blk + D * BS + k, al * dN[ib][k] * NI + dN[la][k] * Q1 + al * aL[k] * Q2);
+                atomicAdd(blk + D * BS + D, Tp * gab);
+            }
+        }
+        // elastic stress mu_L (B - I) of every solid present on the element
+        // (residual), and its tangent through dB/dv, eq. (Bext), solid by
+        // solid: with W_b = int N_b alpha mu_L, M = int alpha mu_L B and
+        // D_k = (dB/dx_k) grad N_a, block (a, b) gains
+        //   alpha kappa (-W_b D_k[i] + dN_a[k] (M grad N_b)_i + delta_ik grad N_a . M grad N_b)
         for (int sI = 0; sI < a.n_s; ++sI) {
             double asn[NN];
             bool any = false;
@@ -258,17 +314,20 @@ __global__ __launch_bounds__(256) void k_ns_rows(RowArgs a, TJ *__restrict__ Jv)
                 any |= asn[b] != 0.0;
             }
             if (!any) continue;
-            solid = true;
             const double muL = a.muL[sI];
             double Bn[NN][NVv];
 #pragma unroll
             for (int b = 0; b < NN; ++b)
 #pragma unroll
                 for (int c = 0; c < NVv; ++c) Bn[b][c] = a.Ba[((int64_t)sI * a.N + nd[b]) * NVv + c];
-            double Wbs[NN];
+            double Wbs[NN], M2[D][D];
 #pragma unroll
             for (int b = 0; b < NN; ++b) Wbs[b] = 0.0;
 #pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) M2[i][j] = 0.0;
+#pragma unroll 1
             for (int q = 0; q < NQ; ++q) {
                 double aq = 0.0, bq[NVv];
 #pragma unroll
@@ -298,6 +357,7 @@ __global__ __launch_bounds__(256) void k_ns_rows(RowArgs a, TJ *__restrict__ Jv)
                     for (int j = 0; j < D; ++j) M2[i][j] += w * f * Bq[i][j];
             }
             if (Jv == nullptr) continue;
+            double Dk[D][D];   // Dk[i][k] = ((dB/dx_k) grad N_a)_i
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 double gk[NVv];
@@ -312,85 +372,47 @@ __global__ __launch_bounds__(256) void k_ns_rows(RowArgs a, TJ *__restrict__ Jv)
                 vfull<D>(gk, gf);
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
-                    double Dk = 0.0;
+                    double t = 0.0;
 #pragma unroll
-                    for (int j = 0; j < D; ++j) Dk += gf[i][j] * dN[la][j];
-#pragma unroll
-                    for (int b = 0; b < NN; ++b) T[b][i][k] += Wbs[b] * Dk;
+                    for (int j = 0; j < D; ++j) t += gf[i][j] * dN[la][j];
+                    Dk[i][k] = t;
                 }
+            }
+            const double ak = a.alpha * a.kappa;
+            const int64_t rbase = a.rowptr[row];
+#pragma unroll
+            for (int ib = 0; ib < NN; ++ib) {
+                const int slot = (int)(a.epos[e * NN * NN + la * NN + ib] - rbase);
+                double *blk = accJ + ((int64_t)lr * a.maxc + slot) * BP;
+                double Mb[D], aMb = 0.0;
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    double s2 = 0.0;
+#pragma unroll
+                    for (int l = 0; l < D; ++l) s2 += M2[i][l] * dN[ib][l];
+                    Mb[i] = s2;
+                    aMb += dN[la][i] * s2;
+                }
+#pragma unroll
+                for (int i = 0; i < D; ++i)
+#pragma unroll
+                    for (int k = 0; k < D; ++k)
+                        atomicAdd(blk + i * BS + k,
+                                  ak * (-Wbs[ib] * Dk[i][k] + dN[la][k] * Mb[i] + (i == k ? aMb : 0.0)));
             }
         }
         // residual of the row node
 #pragma unroll
-        for (int i = 0; i < BS; ++i) atomicAdd(accR + lr * BS + i, rl[i]);
-        if (Jv == nullptr) continue;
-        const double al = a.alpha, ct = a.ct;
-        const double NI = w * (Rule<D>::QA + (NQ - 1) * Rule<D>::QB);
-        double Pa = 0.0;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) Pa += TM[q] * U[la][q];
-        double aL[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            double s = 0.0;
-#pragma unroll
-            for (int j = 0; j < D; ++j) s += dN[la][j] * L[j][k];
-            aL[k] = s;
-        }
-        const int64_t rbase = a.rowptr[row];
-#pragma unroll
-        for (int ib = 0; ib < NN; ++ib) {
-            double A = 0.0, C = 0.0, Q1 = 0.0, Q2 = 0.0;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const double Nb = shape_at<D>(q, ib);
-                const double lin = ct * Nb + al * U[ib][q];
-                A += Wa[q] * lin;
-                C += Wa[q] * Nb;
-                Q1 += TM[q] * lin;
-                Q2 += TM[q] * Nb;
-            }
-            C *= al;
-            double gab = 0.0;
-#pragma unroll
-            for (int j = 0; j < D; ++j) gab += dN[la][j] * dN[ib][j];
-            const int slot = (int)(a.epos[e * NN * NN + la * NN + ib] - rbase);
-            double *blk = accJ + ((int64_t)lr * a.maxc + slot) * B2;
-            double Mb[D], aMb = 0.0;
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                double s2 = 0.0;
-#pragma unroll
-                for (int l = 0; l < D; ++l) s2 += M2[i][l] * dN[ib][l];
-                Mb[i] = s2;
-                aMb += dN[la][i] * s2;
-            }
-            const double ak = solid ? al * a.kappa : 0.0;
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    double val = C * L[i][k] + al * muI * dN[la][k] * dN[ib][i] + al * Tc * dN[la][i] * dN[ib][k];
-                    if (i == k) val += A + al * muI * gab;
-                    // elastic tangent through dB/dv, eq. (Bext)
-                    val += ak * (-T[ib][i][k] + dN[la][k] * Mb[i] + (i == k ? aMb : 0.0));
-                    atomicAdd(blk + i * BS + k, val);
-                }
-                atomicAdd(blk + i * BS + D, -dN[la][i] * NI + Pa * dN[ib][i]);
-            }
-#pragma unroll
-            for (int k = 0; k < D; ++k) atomicAdd(blk + D * BS + k, al * dN[ib][k] * NI + dN[la][k] * Q1 + al * aL[k] * Q2);
-            atomicAdd(blk + D * BS + D, Tp * gab);
-        }
+        for (int i = 0; i < BS; ++i) atomicAdd(accR + lr * RP + i, rl[i]);
     }
     __syncthreads();
     for (int64_t r = r0; r < r1; ++r) {
         const int lr = (int)(r - r0);
-        if (threadIdx.x < BS) a.R[r * BS + threadIdx.x] = accR[lr * BS + threadIdx.x];
+        if (threadIdx.x < BS) a.R[r * BS + threadIdx.x] = accR[lr * RP + threadIdx.x];
         if (Jv == nullptr) continue;
         const int64_t kb = a.rowptr[r], len = a.rowptr[r + 1] - kb;
         for (int t = threadIdx.x; t < len * B2; t += blockDim.x)
-            Jv[kb * B2 + t] = (TJ)accJ[(int64_t)lr * a.maxc * B2 + t];
+            Jv[kb * B2 + t] = (TJ)accJ[((int64_t)lr * a.maxc + t / B2) * BP + t % B2];
     }
 }
 
@@ -529,7 +551,7 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
         a.rowptr = ctx->J.rowptr;
     }
     const int nb = eft_grid(M.N, M.rpb);
-    const size_t shm = (size_t)M.rpb * ((size_t)M.maxc * BS * BS + BS) * sizeof(double);
+    const size_t shm = (size_t)M.rpb * ((size_t)M.maxc * ((BS * BS) | 1) + (BS | 1)) * sizeof(double);
     // kernel-timing hook on the mesh level (not the coarse levels).
     // Algorithmic bytes: J and R written once, the connectivity and every
     // node field the element evaluation reads, once.

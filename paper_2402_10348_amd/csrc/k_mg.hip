@@ -539,7 +539,7 @@ eft_status eft_build_graph(int64_t N, int64_t E, int nn, const int32_t *conn, st
     for (int64_t p = 0; p < N; ++p) maxc = std::max(maxc, rowptr[p + 1] - rowptr[p]);
     // rows per assembly workgroup: about two incident elements per thread, and
     // the row accumulators of the largest block size within 40 KB of LDS
-    const int64_t rowbytes = (int64_t)maxc * 36 * 8 + 6 * 8;
+    const int64_t rowbytes = (int64_t)maxc * 37 * 8 + 7 * 8;   // padded 6x6 blocks (transport)
     rpb = (int)std::max<int64_t>(1, std::min<int64_t>(512 / maxinc, 40960 / rowbytes));
     return EFT_OK;
 }

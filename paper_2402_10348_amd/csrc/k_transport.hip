@@ -361,10 +361,10 @@ template <int BS>
 __device__ __forceinline__ void band_rows_out(const TrArgs &a, int64_t r0, int64_t r1, const double *accJ,
                                               const double *accR)
 {
-    constexpr int B2 = BS * BS;
+    constexpr int B2 = BS * BS, BP = B2 | 1, RP = BS | 1;
     for (int64_t r = r0; r < r1; ++r) {
         const int lr = (int)(r - r0);
-        if (threadIdx.x < BS) a.R[r * BS + threadIdx.x] = accR[lr * BS + threadIdx.x];
+        if (threadIdx.x < BS) a.R[r * BS + threadIdx.x] = accR[lr * RP + threadIdx.x];
         const int64_t g = a.node[r];
         const int32_t *gc = a.gcol + a.grow[g];
         const int glen = a.grow[g + 1] - a.grow[g];
@@ -377,7 +377,7 @@ __device__ __forceinline__ void band_rows_out(const TrArgs &a, int64_t r0, int64
                 if (gc[mid] < col) lo = mid + 1;
                 else hi = mid;
             }
-            const double *src = accJ + ((int64_t)lr * a.maxc + lo) * B2;
+            const double *src = accJ + ((int64_t)lr * a.maxc + lo) * BP;
             double *dst = a.J + (kb + t) * B2;
 #pragma unroll
             for (int v = 0; v < B2; ++v) dst[v] = src[v];
@@ -399,22 +399,23 @@ __global__ __launch_bounds__(256) void k_ac_rows(TrArgs a, double eps, const dou
     const double kh = eps * eps, al = a.alpha, ct = a.ct, i4 = 4.0 / (a.dt * a.dt);
     // incidences of the workgroup's rows, flattened (band rows are not
     // contiguous global nodes)
-    __shared__ int pre[65];
-    if (threadIdx.x == 0) {
-        pre[0] = 0;
-        for (int64_t r = r0; r < r1; ++r) {
-            const int64_t gg = a.node[r];
-            pre[r - r0 + 1] = pre[r - r0] + (a.iptr[gg + 1] - a.iptr[gg]);
-        }
+    __shared__ int maxinc;
+    if (threadIdx.x == 0) maxinc = 0;
+    __syncthreads();
+    const int nrow = (int)(r1 - r0);
+    if (threadIdx.x < nrow) {
+        const int64_t gg = a.node[r0 + threadIdx.x];
+        atomicMax(&maxinc, a.iptr[gg + 1] - a.iptr[gg]);
     }
     __syncthreads();
-    const int nrow = (int)(r1 - r0), total = pre[nrow];
     {
-        for (int t = threadIdx.x; t < total; t += blockDim.x) {
-            int lr = 0;
-            while (pre[lr + 1] <= t) ++lr;
+        // pairs dealt row-interleaved: consecutive lanes take different
+        // rows, so the LDS atomics of one wavefront rarely hit one block
+        for (int t = threadIdx.x; t < nrow * maxinc; t += blockDim.x) {
+            const int lr = t % nrow;
             const int64_t g = a.node[r0 + lr];
-            const int ii = a.iptr[g] + (t - pre[lr]);
+            const int ii = a.iptr[g] + t / nrow;
+            if (ii >= a.iptr[g + 1]) continue;
             const int32_t ent = a.ient[ii];
             const int64_t e = ent >> 2;
             const int la = ent & 3;
@@ -524,30 +525,33 @@ __global__ __launch_bounds__(256) void k_b_rows(TrArgs a, const double *afr /*[N
 {
     extern __shared__ double lds[];
     constexpr int NN = D + 1, NQ = Rule<D>::NQ, NVv = NV<D>::v, B2 = NVv * NVv;
+    // LDS strides padded to an odd number of doubles (bank conflicts)
+    constexpr int BP = B2 | 1, RP = NVv | 1;
     const int64_t r0 = (int64_t)blockIdx.x * a.rpb;
     const int64_t r1 = r0 + a.rpb < a.n ? r0 + a.rpb : a.n;
-    double *accJ = lds, *accR = lds + (int64_t)a.rpb * a.maxc * B2;
-    for (int t = threadIdx.x; t < a.rpb * (a.maxc * B2 + NVv); t += blockDim.x) lds[t] = 0.0;
+    double *accJ = lds, *accR = lds + (int64_t)a.rpb * a.maxc * BP;
+    for (int t = threadIdx.x; t < a.rpb * (a.maxc * BP + RP); t += blockDim.x) lds[t] = 0.0;
     __syncthreads();
     const double al = a.alpha, ct = a.ct, i4 = 4.0 / (a.dt * a.dt);
     // incidences of the workgroup's rows, flattened (band rows are not
     // contiguous global nodes)
-    __shared__ int pre[65];
-    if (threadIdx.x == 0) {
-        pre[0] = 0;
-        for (int64_t r = r0; r < r1; ++r) {
-            const int64_t gg = a.node[r];
-            pre[r - r0 + 1] = pre[r - r0] + (a.iptr[gg + 1] - a.iptr[gg]);
-        }
+    __shared__ int maxinc;
+    if (threadIdx.x == 0) maxinc = 0;
+    __syncthreads();
+    const int nrow = (int)(r1 - r0);
+    if (threadIdx.x < nrow) {
+        const int64_t gg = a.node[r0 + threadIdx.x];
+        atomicMax(&maxinc, a.iptr[gg + 1] - a.iptr[gg]);
     }
     __syncthreads();
-    const int nrow = (int)(r1 - r0), total = pre[nrow];
     {
-        for (int t = threadIdx.x; t < total; t += blockDim.x) {
-            int lr = 0;
-            while (pre[lr + 1] <= t) ++lr;
+        // pairs dealt row-interleaved: consecutive lanes take different
+        // rows, so the LDS atomics of one wavefront rarely hit one block
+        for (int t = threadIdx.x; t < nrow * maxinc; t += blockDim.x) {
+            const int lr = t % nrow;
             const int64_t g = a.node[r0 + lr];
-            const int ii = a.iptr[g] + (t - pre[lr]);
+            const int ii = a.iptr[g] + t / nrow;
+            if (ii >= a.iptr[g + 1]) continue;
             const int32_t ent = a.ient[ii];
             const int64_t e = ent >> 2;
             const int la = ent & 3;
@@ -670,7 +674,7 @@ __global__ __launch_bounds__(256) void k_b_rows(TrArgs a, const double *afr /*[N
                 }
             }
 #pragma unroll
-            for (int c = 0; c < NVv; ++c) atomicAdd(accR + lr * NVv + c, re[c]);
+            for (int c = 0; c < NVv; ++c) atomicAdd(accR + lr * RP + c, re[c]);
             const int64_t gb0 = a.grow[g];
 #pragma unroll
             for (int ib = 0; ib < NN; ++ib) {
@@ -682,7 +686,7 @@ __global__ __launch_bounds__(256) void k_b_rows(TrArgs a, const double *afr /*[N
                     S2 += Wl[q] * AQ[q] * Nb;
                 }
                 S2 *= al;
-                double *blk = accJ + ((int64_t)lr * a.maxc + (a.epos[e * NN * NN + la * NN + ib] - gb0)) * B2;
+                double *blk = accJ + ((int64_t)lr * a.maxc + (a.epos[e * NN * NN + la * NN + ib] - gb0)) * BP;
 #pragma unroll
                 for (int c = 0; c < NVv; ++c)
 #pragma unroll
@@ -1019,7 +1023,7 @@ static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_itera
     const Band &B = ctx->band[ctx->solid_ind[s]];
     TrArgs a = tr_args(ctx, B, lvl->B + (int64_t)s * N * nv, lvl->Bdot + (int64_t)s * N * nv, it->B + (int64_t)s * N * nv);
     if (B.n > 0) {
-        const size_t shm = (size_t)a.rpb * ((size_t)a.maxc * nv * nv + nv) * sizeof(double);
+        const size_t shm = (size_t)a.rpb * ((size_t)a.maxc * ((nv * nv) | 1) + (nv | 1)) * sizeof(double);
         if (ctx->dim == 2)
             hipLaunchKernelGGL(k_b_rows<2>, dim3(eft_grid(B.n, a.rpb)), dim3(256), shm, ctx->stream, a,
                                ctx->as + (int64_t)s * N);
