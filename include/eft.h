@@ -96,7 +96,9 @@ typedef struct {
                                     cycle for the momentum/mass block when the mesh
                                     is a structured Kuhn box with even cell counts
                                     (point-block Jacobi otherwise, and always for
-                                    the band systems)                              */
+                                    the band systems); 2 learned preconditioner
+                                    (block Jacobi plus the network correction, see
+                                    eft_nn_init) for the momentum/mass block      */
     int32_t precision;           /* 0 FP64; 1 FP32 Jacobian values + FP64 rest     */
     double band_flat;            /* band seed: |phi^n| < 1 - band_flat             */
     int32_t band_cell;           /* mesh cells per grid cell and axis              */
@@ -247,6 +249,53 @@ eft_status eft_time_kernel(eft_ctx *ctx, int32_t role_mask);
  * (synchronizes the context's stream).  *out is a HOST struct.  EFT_EINVAL
  * for another role. */
 eft_status eft_kernel_time_read(eft_ctx *ctx, int32_t role, eft_kernel_time *out);
+
+/* ---- Learned right preconditioner (not in the paper).  FGMRES admits any
+ * variable right preconditioner M in eq. (LS_NS), so the network changes the
+ * iteration count only, never the converged answer.  With u = D^-1 r (node-
+ * block Jacobi), s = sqrt(mean(u^2)) and m the free-dof mask:
+ *   z = u + s (m * NN(u / s, m)),
+ * NN = a message-passing network on the matrix graph: input layer 2 bs -> H,
+ * L layers h <- relu([h, mean of neighbours' h] W_l + b_l), output H -> bs
+ * (H = 64, L = 4).  Parameters: one FP32 vector, W_in [2bs][H], b_in [H],
+ * then per layer W_l [2H][H], b_l [H], then W_out [H][bs].  The dense layers
+ * run on MFMA with BF16 operands and FP32 accumulation.  Training pairs
+ * (u = D^-1 r, e) with A e = r are harvested from the context's own momentum
+ * FGMRES solves. */
+
+/* Allocate (first call) and initialize the parameters from a seed; W_out = 0,
+ * so the preconditioner starts as block Jacobi.  Adam moments are reset. */
+eft_status eft_nn_init(eft_ctx *ctx, uint64_t seed);
+
+/* hidden width, layer count, parameter count (0 before eft_nn_init) and the
+ * number of harvested pairs held; any pointer may be NULL. */
+eft_status eft_nn_shape(eft_ctx *ctx, int32_t *hidden, int32_t *layers, int64_t *n_params, int64_t *pairs);
+
+/* Copy the parameters to (direction 0) or from (1) the HOST array host[n];
+ * n must equal the parameter count.  EFT_EINVAL otherwise or before init. */
+eft_status eft_nn_params(eft_ctx *ctx, float *host, int64_t n, int32_t direction);
+
+/* Keep the last `capacity` training pairs of the momentum FGMRES solves that
+ * follow: every Krylov column j gives (D^-1 A z_j, z_j), every converged solve
+ * (D^-1 b, x).  0 stops harvesting and frees the ring.  The pairs take
+ * 2 capacity N (d+1) FP32 values of device memory. */
+eft_status eft_nn_harvest(eft_ctx *ctx, int32_t capacity);
+
+/* Train on the harvested pairs: `steps` Adam steps (beta 0.9, 0.999), each on
+ * the summed gradient of `batch` pairs drawn with a xorshift generator seeded
+ * by `seed`, loss ||m (z(u) - e)||^2 / ||m e||^2.  losses (HOST, may be NULL)
+ * receives the loss of the first pair of every step.  EFT_EINVAL without
+ * pairs or before init. */
+eft_status eft_nn_train(eft_ctx *ctx, int32_t steps, int32_t batch, double lr, uint64_t seed, double *losses);
+
+/* Loss and gradient of one pair (u, e) (DEVICE FP64 [N][d+1]) at the current
+ * parameters; grad_host (HOST, parameter count, may be NULL) and loss (HOST)
+ * receive them.  For tests of the backward pass. */
+eft_status eft_nn_loss_grad(eft_ctx *ctx, const double *u, const double *e, float *grad_host, double *loss);
+
+/* z = u + s (m * NN(u / s, m)) for a DEVICE vector u (already block-Jacobi
+ * preconditioned), z DEVICE; both FP64 [N][d+1]. */
+eft_status eft_nn_apply(eft_ctx *ctx, const double *u, double *z);
 
 #ifdef __cplusplus
 }

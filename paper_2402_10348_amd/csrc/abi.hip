@@ -107,16 +107,17 @@ void free_all(eft_ctx *ctx)
     if (ctx->hscal) (void)hipHostFree(ctx->hscal);
     for (hipEvent_t e : ctx->kt.ev) (void)hipEventDestroy(e);
     ctx->kt.ev.clear();
+    eft_nn_free(ctx);
 }
 
 eft_status check_params(eft_ctx *ctx, const eft_params *p)
 {
     if (!(p->dt > 0.0) || !(p->eta > 0.0) || p->restart < 1 || p->restart > EFT_MAX_RESTART || p->lin_maxit < 1 ||
         p->band_cell < 1 || p->band_halo < 0 || p->nl_max < 1 || !(p->lin_rtol > 0.0) || p->rho_inf < 0.0 ||
-        p->rho_inf > 1.0 || (p->precision != 0 && p->precision != 1) || (p->precond != 0 && p->precond != 1) ||
+        p->rho_inf > 1.0 || (p->precision != 0 && p->precision != 1) || (p->precond < 0 || p->precond > 2) ||
         p->mg_nu < 1 || p->mg_nu > 8 || !(p->mg_omega > 0.0) || p->mg_omega > 1.5) {
         ctx->err = "invalid eft_params (dt, eta, lin_rtol > 0; 1 <= restart <= 512; band_cell >= 1; "
-                   "0 <= rho_inf <= 1; precision 0/1; precond 0/1; 1 <= mg_nu <= 8; 0 < mg_omega <= 1.5)";
+                   "0 <= rho_inf <= 1; precision 0/1; precond 0/1/2; 1 <= mg_nu <= 8; 0 < mg_omega <= 1.5)";
         return EFT_EINVAL;
     }
     return EFT_OK;

@@ -95,6 +95,33 @@ struct MGLevel {
     double *x = nullptr, *x2 = nullptr, *b = nullptr, *r = nullptr;  // [N*bs]
 };
 
+// Learned right preconditioner (not in the paper; the learned form of the
+// right preconditioner of the FGMRES solve): parameters, Adam moments,
+// activations of one vector, and harvested training pairs.
+struct NNState {
+    int H = 64, L = 4, bs = 0, F = 0;
+    int64_t np = 0;                     // parameters
+    int64_t cap_n = 0;                  // nodes the activations are sized for
+    float *theta = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
+    int64_t adam_t = 0;
+    float *mask = nullptr;              // [N][bs]: 1 free dof, 0 Dirichlet dof
+    float *f = nullptr;                 // [N][F] input features
+    float *pre = nullptr, *h = nullptr; // [L+1][N][H] pre-activations, activations
+    float *g = nullptr;                 // [L][N][H] neighbour means
+    float *d1 = nullptr, *d2 = nullptr; // [N][2H] backward scratch
+    float *delta = nullptr;             // [N][bs] network output
+    float *part = nullptr;              // split-K and column-sum partials
+    int64_t cap_part = 0;
+    double *u = nullptr;                // [N][bs] block-Jacobi vector of the input
+    double *red = nullptr;              // reduction partials; scalars at the end
+    double *losses = nullptr;           // [cap_steps] training losses
+    int64_t cap_steps = 0;
+    int32_t cap_pairs = 0;              // harvest ring (0: harvesting off)
+    int64_t stored = 0, next = 0;       // pairs written so far, next ring slot
+    float *hu = nullptr, *he = nullptr; // [cap_pairs][N][bs]: u = D^-1 r and e (A e = r)
+    bool ready = false;
+};
+
 // Optional HIP-event timing of kernel roles (a measurement hook): each
 // launch of a timed role is bracketed by two events on the context's stream
 // and carries its algorithmic bytes.  Launches inside a Krylov chunk are
@@ -126,6 +153,7 @@ struct eft_ctx {
     double g[3] = {0, 0, 0};
     eft_params par{};
     KTimer kt;
+    NNState net;                    // learned preconditioner
     // device mesh
     double *xyz = nullptr;
     int32_t *conn = nullptr;
@@ -264,3 +292,10 @@ int64_t eft_kt_begin(eft_ctx *ctx, int role);
 void eft_kt_end(eft_ctx *ctx, int64_t slot, double bytes, int role);
 void eft_kt_void_from(eft_ctx *ctx, int tag0);
 eft_status eft_kt_harvest(eft_ctx *ctx);
+
+// learned preconditioner (k_nn.hip)
+eft_status eft_nn_alloc(eft_ctx *ctx);
+void eft_nn_free(eft_ctx *ctx);
+eft_status eft_nn_precond(eft_ctx *ctx, const double *Dinv, const double *v, double *z, const int32_t *flag);
+eft_status eft_nn_store_pair(eft_ctx *ctx, const double *Dinv, const double *r, const double *e, int64_t slot,
+                             const int32_t *flag);

@@ -331,7 +331,16 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
     }
     const bool mg = eft_mg_active(ctx, A);   // hierarchy refreshed by the assembly
     inf.fallback_used = (ctx->par.precond == 1 && A == &ctx->J && !mg) ? 1 : 0;
-    if (!mg) EFT_TRY(eft_bj_setup(ctx, A, K.Dinv));
+    // learned preconditioner on the momentum system (block Jacobi elsewhere)
+    const bool learned = ctx->par.precond == 2 && A == &ctx->J;
+    if (learned && !ctx->net.ready) {
+        ctx->err = "precond = 2 needs eft_nn_init (learned preconditioner parameters)";
+        return EFT_EINVAL;
+    }
+    // training pairs (u = D^-1 A z_j, z_j) from the momentum solves
+    NNState &NS = ctx->net;
+    const bool harvest = NS.cap_pairs > 0 && A == &ctx->J;
+    if (!mg || harvest) EFT_TRY(eft_bj_setup(ctx, A, K.Dinv));
     const double tol = ctx->par.lin_rtol * bnorm;
     const int maxit = std::max(1, ctx->par.lin_maxit);
     int chunk = 8;   // columns enqueued between two reads of the solver state
@@ -368,11 +377,14 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
                 ctx->kt.tag = j;
                 if (mg)
                     EFT_TRY(eft_mg_vcycle(ctx, vj, zj, K.flag));
+                else if (learned)
+                    EFT_TRY(eft_nn_precond(ctx, K.Dinv, vj, zj, K.flag));
                 else
                     EFT_TRY(eft_bj_apply(ctx, bs, n, K.Dinv, vj, zj, K.flag));
                 const int64_t slot = A == &ctx->J ? eft_kt_begin(ctx, EFT_KT_SPMV) : -1;
                 EFT_TRY(eft_spmv_flag(ctx, A, zj, K.w, K.flag));
                 eft_kt_end(ctx, slot, spmv_bytes(A), EFT_KT_SPMV);
+                if (harvest) EFT_TRY(eft_nn_store_pair(ctx, K.Dinv, K.w, zj, (NS.next + j) % NS.cap_pairs, K.flag));
                 // pass 1: dots with V[0..j] and ||w||^2
                 dim3 g1(nblk, (j + 2 + KC - 1) / KC);
                 hipLaunchKernelGGL(k_mdot, g1, dim3(RB), 0, ctx->stream, K.V, nd, j + 1, 1, K.w, K.part, nblk,
@@ -435,6 +447,10 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
         EFT_HIP(hipGetLastError());
         total += jdone;
         inf.restarts += 1;
+        if (harvest) {
+            NS.next = (NS.next + jdone) % NS.cap_pairs;
+            NS.stored += jdone;
+        }
         // true residual
         EFT_TRY(eft_spmv_dev(ctx, A, x, K.r));
         hipLaunchKernelGGL(k_bmr, dim3(sg), dim3(RB), 0, ctx->stream, b, K.r, nd);
@@ -453,6 +469,11 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
         }
     }
     inf.iters = total;
+    if (harvest && st == EFT_OK) {   // the solve itself: (D^-1 b, x)
+        EFT_TRY(eft_nn_store_pair(ctx, K.Dinv, b, x, NS.next, nullptr));
+        NS.next = (NS.next + 1) % NS.cap_pairs;
+        NS.stored += 1;
+    }
     if (info) *info = inf;
     if (st == EFT_ENOTCONV) ctx->err = "FGMRES reached lin_maxit";
     return st;

@@ -80,7 +80,8 @@ class KernelTime(C.Structure):
 EXPORTS = ["eft_create", "eft_destroy", "eft_last_error", "eft_set_params", "eft_ns_matrix", "eft_matrix_shape",
            "eft_matrix_export", "eft_assemble", "eft_spmv", "eft_fgmres", "eft_bands_build", "eft_band_export",
            "eft_band_system", "eft_transport_solids", "eft_step", "eft_time_kernel",
-           "eft_kernel_time_read"]
+           "eft_kernel_time_read", "eft_nn_init", "eft_nn_shape", "eft_nn_params", "eft_nn_harvest", "eft_nn_train",
+           "eft_nn_loss_grad", "eft_nn_apply"]
 
 _lib = None
 
@@ -240,6 +241,47 @@ class Context:
         out = KernelTime()
         self._check(self.L.eft_kernel_time_read(self.ctx, C.c_int32(role), C.byref(out)))
         return dict(launches=out.launches, active=out.active, seconds=out.seconds, bytes=out.bytes)
+
+    # ---------------------------------------------- learned preconditioner
+    def nn_init(self, seed=0):
+        self._check(self.L.eft_nn_init(self.ctx, C.c_uint64(seed)))
+
+    def nn_shape(self):
+        h, l, npar, pairs = C.c_int32(), C.c_int32(), C.c_int64(), C.c_int64()
+        self._check(self.L.eft_nn_shape(self.ctx, C.byref(h), C.byref(l), C.byref(npar), C.byref(pairs)))
+        return dict(hidden=h.value, layers=l.value, n_params=npar.value, pairs=pairs.value)
+
+    def nn_params(self, theta=None):
+        """Export the parameters (theta None) or import theta (FP32 array)."""
+        n = self.nn_shape()["n_params"]
+        if theta is None:
+            out = np.zeros(n, dtype=np.float32)
+            self._check(self.L.eft_nn_params(self.ctx, out.ctypes.data_as(C.POINTER(C.c_float)), C.c_int64(n), 0))
+            return out
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        self._check(self.L.eft_nn_params(self.ctx, th.ctypes.data_as(C.POINTER(C.c_float)), C.c_int64(th.size), 1))
+
+    def nn_harvest(self, capacity):
+        self._check(self.L.eft_nn_harvest(self.ctx, C.c_int32(capacity)))
+
+    def nn_train(self, steps, batch=1, lr=1e-3, seed=0):
+        losses = np.zeros(max(steps, 1))
+        self._check(self.L.eft_nn_train(self.ctx, C.c_int32(steps), C.c_int32(batch), C.c_double(lr),
+                                        C.c_uint64(seed), losses.ctypes.data_as(C.POINTER(C.c_double))))
+        return losses[:steps]
+
+    def nn_loss_grad(self, u, e):
+        n = self.nn_shape()["n_params"]
+        g = np.zeros(n, dtype=np.float32)
+        loss = C.c_double()
+        self._check(self.L.eft_nn_loss_grad(self.ctx, _ptr(u), _ptr(e), g.ctypes.data_as(C.POINTER(C.c_float)),
+                                            C.byref(loss)))
+        return loss.value, g
+
+    def nn_apply(self, u):
+        z = self.torch.empty_like(u)
+        self._check(self.L.eft_nn_apply(self.ctx, _ptr(u), _ptr(z)))
+        return z
 
     # ------------------------------------------------------------- the ABI
     def assemble(self, lvl, it, with_J=True):
