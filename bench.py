@@ -51,6 +51,11 @@ def parse():
                          "3 assembly (all three are timed with HIP events over the timed steps); 0 no timing")
     ap.add_argument("--no-mixed", dest="mixed", action="store_false",
                     help="skip the mixed-precision (FP32 Jacobian) run of the same steps")
+    ap.add_argument("--no-learned", dest="learned", action="store_false",
+                    help="skip the learned-vs-plain preconditioner comparison")
+    ap.add_argument("--learned-n", type=int, default=32)
+    ap.add_argument("--learned-pairs", type=int, default=256)
+    ap.add_argument("--learned-train", type=int, default=400)
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB copied by a plain device copy before the timed steps (HBM counter calibration)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -68,6 +73,65 @@ KERNEL_NAME = {1: "k_sweep_rows<4, float> (fine-level multigrid smoother sweep, 
                2: "k_spmv_rows<4, double, true> (FP64 SpMV of the 4x4-block momentum Jacobian in FGMRES)",
                3: "k_ns_rows<3, double> (momentum/mass residual and Jacobian assembly, bytes: J and R written "
                   "once, connectivity and node fields read once)"}
+
+
+def timed_steps(ctx, st, steps, warmup, torch):
+    t_sim, step_no = 0.0, 0
+    for _ in range(warmup):
+        info = ctx.step(st, t=t_sim, step=step_no)
+        t_sim, step_no = info["t"], info["step"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for _ in range(steps):
+        info = ctx.step(st, t=t_sim, step=step_no)
+        t_sim, step_no = info["t"], info["step"]
+        its.append(info)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return el, its
+
+
+def run_learned(args, torch):
+    """Learned vs plain preconditioner at 1e-8 on the n^3 cavity (default
+    32^3, where block Jacobi still converges): the plain FP64 step with
+    point-block Jacobi against the mixed-precision step with the learned
+    preconditioner, trained in this run on pairs harvested from the plain
+    run's own momentum solves (training time reported apart)."""
+    from paper_2402_10348_amd import workloads as W
+    from paper_2402_10348_amd.eft import Context
+    prob = W.cavity_sphere_3d(n=args.learned_n)
+    common = dict(lin_rtol=1e-8, restart=100, lin_maxit=20000)
+    plain = Context(prob, precond=0, precision=0, **common)
+    plain.nn_init(seed=7)
+    plain.nn_harvest(args.learned_pairs)
+    st = plain.device_state(prob.state_copy())
+    el0, its0 = timed_steps(plain, st, args.steps, args.warmup, torch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = plain.nn_train(steps=args.learned_train, batch=4, lr=2e-3, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    theta = plain.nn_params()
+    plain.close()
+    learned = Context(prob, precond=2, precision=1, **common)
+    learned.nn_init(seed=7)
+    learned.nn_params(theta)
+    st = learned.device_state(prob.state_copy())
+    el1, its1 = timed_steps(learned, st, args.steps, args.warmup, torch)
+    learned.close()
+
+    def line(el, its):
+        return dict(steps_per_s=round(args.steps / el, 4), ms_per_step=round(1e3 * el / args.steps, 2),
+                    nl_iters_per_step=sum(i["nl_iters"] for i in its) / len(its),
+                    momentum_krylov_iters_per_step=sum(i["lin_iters_block"][0] for i in its) / len(its))
+    return dict(workload=f"3D cavity with elastic sphere, {args.learned_n}^3 x 6 P1 tets, FGMRES(100) to 1e-8",
+                plain=dict(precond="point-block Jacobi", dtype="f64", **line(el0, its0)),
+                learned=dict(precond="learned (block Jacobi + network)", dtype="f64 residual/Krylov, f32 Jacobian",
+                             **line(el1, its1)),
+                training=dict(pairs=args.learned_pairs, adam_steps=args.learned_train, seconds=round(t_train, 3),
+                              loss_first=float(losses[:10].mean()), loss_last=float(losses[-10:].mean())),
+                speedup=round(el0 / el1, 4))
 
 
 def run_mixed(args, prob, torch):
@@ -281,6 +345,10 @@ def main():
     mixed = None
     if args.mixed:
         mixed = run_mixed(args, prob, torch)
+    learned = None
+    if args.learned:
+        log(args, "[bench] learned vs plain preconditioner ...")
+        learned = run_learned(args, torch)
     cpu = None
     if not args.no_cpu:
         log(args, "[bench] timing the CPU oracle sample ...")
@@ -309,6 +377,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels": others,
         "mixed_precision": mixed,
+        "learned_vs_plain_precond": learned,
     }
     print(json.dumps(line), flush=True)
 
