@@ -172,6 +172,25 @@ class Case:
             lib().orc_ns_apply_bc(C.byref(self.P), _i(rowptr), _i(col), _d(R), _d(J))
         return R, J
 
+    def ns_rows(self, lvl, it, rows):
+        """Rows `rows` of the residual and Jacobian of eq. (PG_NS) with the
+        boundary rows applied, without assembling the rest: R [nr][bs] and a
+        list of (columns, blocks [len][bs][bs]) per row."""
+        rowptr, col = self.graph()
+        rows = np.ascontiguousarray(rows, dtype=np.int32)
+        S, keep = self._state(lvl)
+        vp, phi, B = _f64(it["vp"]), _f64(it["phi"]), _f64(it["B"])
+        lens = rowptr[rows + 1] - rowptr[rows]
+        R = np.zeros((rows.shape[0], self.bs))
+        J = np.zeros((int(lens.sum()), self.bs, self.bs))
+        lib().orc_ns_rows(C.byref(self.P), C.byref(S), _d(vp), _d(phi), _d(B), _i(rowptr), _i(col),
+                          int(rows.shape[0]), _i(rows), _d(R), _d(J))
+        out, o = [], 0
+        for q, r in enumerate(rows):
+            out.append((col[rowptr[r]:rowptr[r + 1]].copy(), J[o:o + lens[q]]))
+            o += lens[q]
+        return R, out
+
     def level_values(self, xn, xdn, xnp1):
         xn, xdn, xnp1 = _f64(xn), _f64(xdn), _f64(xnp1)
         xa, xd = np.zeros_like(xn), np.zeros_like(xn)

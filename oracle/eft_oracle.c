@@ -598,6 +598,86 @@ void orc_ns_assemble(const orc_problem *P, const orc_state *lvl, const double *i
     level_fields_free(&F);
 }
 
+/* The same residual and Jacobian as orc_ns_assemble followed by
+ * orc_ns_apply_bc, for a subset of rows only (for checks at sizes where the
+ * whole assembly is too slow): every element that touches one of the rows is
+ * evaluated and only those rows are accumulated, in element order as in the
+ * full assembly.  rows[nr] are node ids; R_out [nr][bs]; J_out holds the
+ * blocks of row q at offset sum over q' < q of the row lengths, in the order
+ * of col. */
+void orc_ns_rows(const orc_problem *P, const orc_state *lvl, const double *it_vp, const double *it_phi,
+                 const double *it_B, const int *rowptr, const int *col, int nr, const int *rows, double *R_out,
+                 double *J_out)
+{
+    int N = P->n_nodes, d = P->dim, nn = d + 1, bs = d + 1, ns = count_solids(P), nv = nvoigt(d);
+    galpha ga = galpha_of(P->rho_inf, P->dt);
+    int *pos = malloc(sizeof(int) * N);
+    size_t *off = malloc(sizeof(size_t) * (nr + 1));
+    for (int n = 0; n < N; ++n) pos[n] = -1;
+    off[0] = 0;
+    for (int q = 0; q < nr; ++q) {
+        pos[rows[q]] = q;
+        off[q + 1] = off[q] + (size_t)(rowptr[rows[q] + 1] - rowptr[rows[q]]);
+    }
+    level_fields F;
+    level_fields_alloc(P, &F);
+    level_fields_eval(P, &ga, lvl, it_vp, it_phi, it_B, &F);
+    double *af = malloc(sizeof(double) * (size_t)P->n_phase * N), *rho = malloc(sizeof(double) * N),
+           *mu = malloc(sizeof(double) * N);
+    nodal_properties(P, F.phi_a, af, rho, mu);
+    double *muL = malloc(sizeof(double) * (ns + 1));
+    for (int s = 0; s < ns; ++s) muL[s] = P->muL[phase_of_solid(P, s)];
+    memset(R_out, 0, sizeof(double) * (size_t)nr * bs);
+    memset(J_out, 0, sizeof(double) * off[nr] * bs * bs);
+    double *as = malloc(sizeof(double) * 4 * (ns + 1)), *Bv = malloc(sizeof(double) * 24 * (ns + 1));
+    for (int e = 0; e < P->n_elems; ++e) {
+        int touch = 0;
+        for (int a = 0; a < nn; ++a) touch |= pos[P->conn[(size_t)e * nn + a]] >= 0;
+        if (!touch) continue;
+        int nodes[4];
+        double X[4][3], v[4][3] = {{0}}, acc[4][3] = {{0}}, p[4], r4[4], m4[4], re[4][4], Ke[4][4][4][4];
+        element_coords(P, e, nodes, X);
+        for (int a = 0; a < nn; ++a) {
+            int n = nodes[a];
+            for (int i = 0; i < d; ++i) {
+                v[a][i] = F.v_a[(size_t)n * d + i];
+                acc[a][i] = F.acc[(size_t)n * d + i];
+            }
+            p[a] = F.p[n];
+            r4[a] = rho[n];
+            m4[a] = mu[n];
+            for (int s = 0; s < ns; ++s) {
+                as[s * 4 + a] = af[(size_t)phase_of_solid(P, s) * N + n];
+                for (int c = 0; c < nv; ++c) Bv[(s * 4 + a) * 6 + c] = F.B_a[((size_t)s * N + n) * nv + c];
+            }
+        }
+        ns_element(d, &ga, P->C_I, P->g, X, v, NULL, acc, p, r4, m4, ns, as, Bv, muL, re, Ke);
+        for (int a = 0; a < nn; ++a) {
+            int q = pos[nodes[a]];
+            if (q < 0) continue;
+            for (int i = 0; i < bs; ++i) R_out[(size_t)q * bs + i] += re[a][i];
+            for (int b = 0; b < nn; ++b) {
+                int k = find_col(rowptr, col, nodes[a], nodes[b]) - rowptr[nodes[a]];
+                for (int i = 0; i < bs; ++i)
+                    for (int j = 0; j < bs; ++j) J_out[((off[q] + k) * bs + i) * bs + j] += Ke[a][b][i][j];
+            }
+        }
+    }
+    for (int t = 0; t < P->n_dir; ++t) {
+        int n = P->dir_node[t], q = pos[n];
+        if (q < 0) continue;
+        for (int i = 0; i < bs; ++i) {
+            if (!((P->dir_mask[t] >> i) & 1)) continue;
+            R_out[(size_t)q * bs + i] = 0.0;
+            for (int k = rowptr[n]; k < rowptr[n + 1]; ++k)
+                for (int j = 0; j < bs; ++j)
+                    J_out[((off[q] + (k - rowptr[n])) * bs + i) * bs + j] = (col[k] == n && j == i) ? 1.0 : 0.0;
+        }
+    }
+    free(as); free(Bv); free(af); free(rho); free(mu); free(muL); free(pos); free(off);
+    level_fields_free(&F);
+}
+
 /* Dirichlet rows: residual 0, Jacobian row = unit row (the iterate already
  * holds the boundary value). */
 void orc_ns_apply_bc(const orc_problem *P, const int *rowptr, const int *col, double *R, double *Jval)

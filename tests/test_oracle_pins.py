@@ -806,3 +806,21 @@ def test_mixture_properties_stay_within_phase_bounds():
     assert rho.min() >= 1.0 - 1e-15 and rho.max() <= 5.0 + 1e-15
     assert mu.min() >= 0.01 - 1e-15 and mu.max() <= 0.3 + 1e-15
     assert np.allclose(af.sum(0), 1.0)
+
+
+@pytest.mark.parametrize("name", ["disk2d", "falling3d"])
+def test_row_subset_equals_full_assembly(name):
+    """The row-subset evaluation used for full-size checks gives exactly the
+    rows of the full assembly with boundary rows applied."""
+    prob = W.cavity_disk_2d(n=6) if name == "disk2d" else W.falling_sphere_3d(n=4)
+    c = O.Case(prob)
+    lvl, it = W.perturbed_state(prob, seed=12)
+    R, J = c.ns_assemble(lvl, it)
+    rowptr, col = c.graph()
+    rows = np.array(sorted(set([0, prob.n_nodes - 1] + list(rng(5).choice(prob.n_nodes, 25, replace=False)))))
+    Rs, Js = c.ns_rows(lvl, it, rows)
+    assert np.array_equal(Rs, R[rows])
+    for q, r in enumerate(rows):
+        cols, blocks = Js[q]
+        assert np.array_equal(cols, col[rowptr[r]:rowptr[r + 1]])
+        assert np.array_equal(blocks, J[rowptr[r]:rowptr[r + 1]])
