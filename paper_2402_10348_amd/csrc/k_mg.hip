@@ -253,21 +253,28 @@ __global__ __launch_bounds__(256) void k_restrict(Dims cd, Dims fd, int bs, cons
     const int ci = (int)(I % (cd.n[0] + 1));
     const int cj = (int)((I / (cd.n[0] + 1)) % (cd.n[1] + 1));
     const int ck = (int)(I / ((int64_t)(cd.n[0] + 1) * (cd.n[1] + 1)));
+    // all stencil points are visited unrolled, so their loads are in flight
+    // together (a rolled loop waits one memory latency per point)
     double acc[8];
-    for (int c = 0; c < bs; ++c) acc[c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+#pragma unroll
     for (int s = 0; s < Stencil<D>::S; ++s) {
         int a, b, c3;
         Stencil<D>::off(s, a, b, c3);
         const int fi = 2 * ci + a, fj = 2 * cj + b, fk = 2 * ck + c3;
-        if (fi < 0 || fj < 0 || fk < 0 || fi > fd.n[0] || fj > fd.n[1] || fk > fd.n[2]) continue;
-        const int64_t f = node_id(fd, fi, fj, fk);
-        const double w = s == 0 ? 1.0 : 0.5;
+        const bool in = !(fi < 0 || fj < 0 || fk < 0 || fi > fd.n[0] || fj > fd.n[1] || fk > fd.n[2]);
+        const int64_t f = in ? node_id(fd, fi, fj, fk) : 0;
+        const double w = in ? (s == 0 ? 1.0 : 0.5) : 0.0;
         const int m = fmask[f];
-        for (int c = 0; c < bs; ++c)
-            if ((m >> c) & 1) acc[c] += w * r[f * bs + c];
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (c < bs && ((m >> c) & 1)) acc[c] += w * r[f * bs + c];
     }
     const int mc = cmask[I];
-    for (int c = 0; c < bs; ++c) bc[I * bs + c] = ((mc >> c) & 1) ? acc[c] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        if (c < bs) bc[I * bs + c] = ((mc >> c) & 1) ? acc[c] : 0.0;
 }
 
 // x[i] += sum over parents I of i of w(i, I) xc[I] (free dofs only)

@@ -331,6 +331,69 @@ def falling_sphere_3d(n: int = 96, dt: float = 1e-3, lin_rtol: float = 1e-8) -> 
                    (0.0, 0.0, -9.81), params, sdfs, eps, dict(h=h))
 
 
+def floe_positions(n_floes: int, seed: int, x_range=(1.4, 3.9), width: float = 2.0,
+                   r_range=(0.1, 0.3), max_tries: int = 100000):
+    """Non-overlapping disc centres (x, y) and radii by rejection sampling:
+    radius uniform in r_range, centre x uniform in x_range, y keeping the disc
+    inside [0, width]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    tries = 0
+    while len(out) < n_floes:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("floe placement failed")
+        r = rng.uniform(*r_range)
+        x = rng.uniform(*x_range)
+        y = rng.uniform(r, width - r)
+        if all((x - a) ** 2 + (y - b) ** 2 > (r + c) ** 2 for a, b, c in out):
+            out.append((x, y, r))
+    return out
+
+
+def floe_field_3d(nx: int = 256, ny: int = 128, nz: int = 64, dt: float = 1e-3, lin_rtol: float = 1e-8,
+                  n_floes: int = 16, seed: int = 0, thickness: float = 0.02, water: float = 0.6) -> Problem:
+    """A box-like hull moving at 1 m/s among ice floes in an air-water domain.
+
+    Box [0,4]x[0,2]x[0,1] (z up, g = -9.81) at nx x ny x nz cells; water
+    (rho 1000, mu 1e-3) below z = water, air (1.2, 1.8e-5) above as the
+    background phase; hull box [0.5,1.1]x[0.85,1.15]x[0.5,0.75] (rho 500,
+    shear modulus 1e9) whose interior nodes carry v = (1, 0, 0); n_floes discs
+    of the given thickness centred on the water line (rho 900, shear modulus
+    1e8, radius uniform in [0.1, 0.3], centres x in [1.4, 3.9], seeded and
+    non-overlapping); solid viscosity 1e-3; eps = h, eta = 1000.  Slip walls
+    on the x and y sides (normal velocity 0), no-slip bottom, open top.  One
+    transported indicator per phase except the air: water, hull, floes.
+    """
+    xyz, conn, grid = box_mesh(3, (nx, ny, nz), hi=(4.0, 2.0, 1.0))
+    h = 4.0 / nx
+    eps = h
+    lo, hi = xyz.min(0), xyz.max(0)
+    tol = 1e-12
+    N = xyz.shape[0]
+    mask = np.zeros(N, dtype=np.uint8)
+    for k in range(2):
+        side = (np.abs(xyz[:, k] - lo[k]) < tol) | (np.abs(xyz[:, k] - hi[k]) < tol)
+        mask[side] |= np.uint8(1 << k)
+    mask[np.abs(xyz[:, 2] - lo[2]) < tol] |= np.uint8(0b111)
+    hull_lo, hull_hi = (0.5, 0.85, 0.5), (1.1, 1.15, 0.75)
+    d_hull = sdf_box(xyz, hull_lo, hull_hi)
+    inside = d_hull > 0.0
+    mask[inside] |= np.uint8(0b111)
+    nodes = np.nonzero(mask)[0].astype(np.int32)
+    val = np.zeros((nodes.shape[0], 4))
+    val[inside[nodes], 0] = 1.0
+    floes = floe_positions(n_floes, seed)
+    phases = [Phase(PHASE_FLUID, 0, 1.2, 1.8e-5), Phase(PHASE_FLUID, 1, 1000.0, 1e-3),
+              Phase(PHASE_SOLID, 1, 500.0, 1e-3, 1e9)]
+    phases += [Phase(PHASE_SOLID, 1, 900.0, 1e-3, 1e8) for _ in floes]
+    sdfs = [water - xyz[:, 2], d_hull]
+    sdfs += [sdf_disc(xyz, (x, y, water), r, thickness) for x, y, r in floes]
+    params = Params(dt=dt, eps=eps, eta=1000.0, lin_rtol=lin_rtol)
+    return _finish(f"floe_field_3d_{nx}x{ny}x{nz}", 3, xyz, conn, grid, (nodes, mask[nodes], val), phases,
+                   (0.0, 0.0, -9.81), params, sdfs, eps, dict(h=h, floes=floes))
+
+
 # ------------------------------------------------- random perturbations ----
 
 
@@ -369,11 +432,16 @@ def perturbed_state(prob: Problem, seed: int, amp_v: float = 0.3, amp_p: float =
 
 def make(name: str, **kw) -> Problem:
     """Workload by name: 'c1' (2D cavity, 32^2), 'c2' (3D cavity, 64^3),
-    'c3' (falling sphere, 96x96x192) or a builder name with keywords."""
+    'c3' (falling sphere, 96x96x192), 'c4' (hull among floes, 256x128x64),
+    'c5' (3D cavity, 128^3) or a builder name with keywords."""
     if name == "c1":
         return cavity_disk_2d(**kw)
     if name == "c2":
         return cavity_sphere_3d(**kw)
     if name == "c3":
         return falling_sphere_3d(**kw)
+    if name == "c4":
+        return floe_field_3d(**kw)
+    if name == "c5":
+        return cavity_sphere_3d(**dict(dict(n=128), **kw))
     return globals()[name](**kw)

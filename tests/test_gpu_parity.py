@@ -49,6 +49,7 @@ CASES = {
     "disk2d_32": lambda: W.cavity_disk_2d(n=32),
     "sphere3d_6": lambda: W.cavity_sphere_3d(n=6),
     "falling3d_5": lambda: W.falling_sphere_3d(n=5),
+    "floes_32x16x8": lambda: W.floe_field_3d(nx=32, ny=16, nz=8, n_floes=3),
 }
 
 
@@ -318,7 +319,7 @@ def test_band_systems_match_oracle(torch_cuda, name):
     ctx.close()
 
 
-@pytest.mark.parametrize("name", ["disk2d_32", "sphere3d_6", "falling3d_5"])
+@pytest.mark.parametrize("name", ["disk2d_32", "sphere3d_6", "falling3d_5", "floes_32x16x8"])
 def test_transport_matches_oracle(torch_cuda, name):
     prob = CASES[name]()
     say(f"[transport] case={name}")
@@ -357,6 +358,7 @@ def _run_steps(prob, nsteps, **over):
     ("disk2d_32", 2, dict(nl_fixed=3)),
     ("sphere3d_6", 2, dict(nl_fixed=0, nl_max=6)),
     ("falling3d_5", 1, dict(nl_fixed=2)),
+    ("floes_32x16x8", 1, dict(nl_fixed=2)),
 ])
 def test_step_matches_oracle(torch_cuda, name, nsteps, over):
     prob = CASES[name]()
