@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--precond", type=int, default=1, help="1 multigrid V-cycle, 0 point-block Jacobi")
     ap.add_argument("--mg-nu", type=int, default=2)
     ap.add_argument("--mg-omega", type=float, default=0.7)
+    ap.add_argument("--mg-bf16", type=int, default=0, help="1: finest multigrid level's matrix copy in BF16")
     ap.add_argument("--kernel-role", type=int, default=1,
                     help="kernel of the roofline object: 1 fine-level smoother sweep, 2 momentum SpMV in FGMRES, "
                          "3 assembly (all three are timed with HIP events over the timed steps); 0 no timing")
@@ -297,7 +298,7 @@ def main():
     torch.cuda.set_device(0)
     prob = W.cavity_sphere_3d(n=args.n)
     ctx = Context(prob, lin_rtol=1e-8, restart=args.restart, lin_maxit=20000, precision=args.precision,
-                  precond=args.precond, mg_nu=args.mg_nu, mg_omega=args.mg_omega)
+                  precond=args.precond, mg_nu=args.mg_nu, mg_omega=args.mg_omega, mg_bf16=args.mg_bf16)
     st = ctx.device_state(prob.state_copy())
     log(args, f"[bench] {args.n}^3 cavity N={prob.n_nodes} E={prob.n_elems} precision={args.precision}")
     t_sim, step_no = 0.0, 0

@@ -106,6 +106,9 @@ typedef struct {
     int32_t mg_nu;               /* multigrid: smoothing sweeps before and after
                                     the coarse correction (1..8)                   */
     double mg_omega;             /* multigrid: damping of the block-Jacobi sweeps  */
+    int32_t mg_bf16;             /* multigrid: 1 stores the finest level's matrix
+                                    copy in BF16 (block inverses from the FP64
+                                    diagonal blocks), 0 in FP32                    */
 } eft_params;
 
 /* State at time level n (Sec. 2.1.2): values and rates.  DEVICE arrays. */

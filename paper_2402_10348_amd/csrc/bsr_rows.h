@@ -23,6 +23,10 @@ typedef double eft_d2 __attribute__((ext_vector_type(2)));
 typedef float eft_f2 __attribute__((ext_vector_type(2)));
 typedef float eft_f4 __attribute__((ext_vector_type(4)));
 
+// Index of the wavefront in its workgroup, as a wave-uniform value (so that
+// loads indexed by it, such as the row pointers, go through the scalar unit).
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
 // One load, plain or non-temporal (streamed: not kept in the caches).
 template <bool NT, typename T> __device__ __forceinline__ T ld_hint(const T *p)
 {
@@ -77,6 +81,33 @@ template <int BS, bool NT> struct RowLoad<BS, float, NT> {
     }
 };
 
+// BF16 value (the upper half of an FP32 bit pattern)
+struct eft_bf16 {
+    uint16_t v;
+};
+
+__device__ __forceinline__ double bf16_to_double(uint32_t bits16) { return (double)__uint_as_float(bits16 << 16); }
+
+template <int BS, bool NT> struct RowLoad<BS, eft_bf16, NT> {
+    static __device__ __forceinline__ void get(const eft_bf16 *p, double (&v)[BS])
+    {
+        typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+        if constexpr (BS % 4 == 0) {
+#pragma unroll
+            for (int q = 0; q < BS / 4; ++q) {
+                const u2 t = ld_hint<NT>(reinterpret_cast<const u2 *>(p) + q);
+                v[4 * q] = bf16_to_double(t.x & 0xFFFFu);
+                v[4 * q + 1] = bf16_to_double(t.x >> 16);
+                v[4 * q + 2] = bf16_to_double(t.y & 0xFFFFu);
+                v[4 * q + 3] = bf16_to_double(t.y >> 16);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < BS; ++q) v[q] = bf16_to_double(p[q].v);
+        }
+    }
+};
+
 // bs entries of x under block column c (cached loads: x is re-read by every
 // row that couples to c).
 template <int BS> __device__ __forceinline__ void x_get(const double *__restrict__ x, int64_t c, double (&v)[BS])
@@ -95,24 +126,33 @@ template <int BS> __device__ __forceinline__ void x_get(const double *__restrict
     }
 }
 
-// (A x) of the block rows row[0..R-1] (rows >= n contribute nothing): the
-// result for scalar row r of row[q] ends in acc[q] of lane r (lanes
-// 0..bs-1); other lanes hold partial sums.  The first pass of every row is
+// (A x) of the block rows with extents [k0[q], k1[q]), q < R: the result for
+// scalar row r of row q ends in acc[q] of lane r (lanes 0..bs-1); other
+// lanes hold partial sums.  The first pass of every row is
 // unrolled across the R rows so that all their loads are in flight together.
+// Block extents [k0, k1) of wave-uniform rows (rows >= n get an empty
+// extent; rowptr has n + 1 entries).  The loads go through the scalar unit.
+template <int R>
+__device__ __forceinline__ void row_extents(const int64_t (&row)[R], int64_t n, const int32_t *__restrict__ rowptr,
+                                            int (&k0)[R], int (&k1)[R])
+{
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int64_t a = row[q] < n ? row[q] : n, b = row[q] + 1 < n ? row[q] + 1 : n;
+        k0[q] = rowptr[a];
+        k1[q] = rowptr[b];
+    }
+}
+
 template <int BS, typename TV, int R, bool NT>
-__device__ __forceinline__ void bsr_rows_dot(const int64_t (&row)[R], int64_t n, const int32_t *__restrict__ rowptr,
+__device__ __forceinline__ void bsr_rows_dot(const int (&k0)[R], const int (&k1)[R],
                                              const int32_t *__restrict__ col, const TV *__restrict__ val,
                                              const double *__restrict__ x, int lane, double (&acc)[R])
 {
     constexpr int J = 64 / BS;
     const int j = lane / BS, r = lane - j * BS;
-    int k0[R], k1[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-        k0[q] = row[q] < n ? rowptr[row[q]] : 0;
-        k1[q] = row[q] < n ? rowptr[row[q] + 1] : 0;
-        acc[q] = 0.0;
-    }
+    for (int q = 0; q < R; ++q) acc[q] = 0.0;
     if (j < J) {
         double v[R][BS], xv[R][BS];
 #pragma unroll

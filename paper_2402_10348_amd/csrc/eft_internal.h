@@ -26,7 +26,9 @@ struct eft_matrix {
     int32_t *rowptr = nullptr, *col = nullptr, *diag = nullptr;  // device
     double *val = nullptr;
     float *val32 = nullptr;
+    uint16_t *val16 = nullptr;   // BF16 values (the finest multigrid level's copy)
     bool fp32 = false;
+    bool bf16 = false;
 };
 
 // FGMRES workspace for vectors of length nd = n*bs and restart m.

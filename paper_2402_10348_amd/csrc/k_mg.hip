@@ -92,22 +92,23 @@ __global__ __launch_bounds__(256) void k_inject(InjArgs a)
 // x_out = x_in + omega D^-1 (b - A x_in), bs = 4, one wavefront per block row
 // x_out = x + omega D^-1 (b - A x) for bs in {3, 4}: SWEEP_R block rows per
 // wavefront (bsr_rows.h) with streamed value loads; lanes 0..bs-1 finish the
-// rows.  The block inverses D^-1 have the type of the matrix values.
+// rows.  Values FP64, FP32 or BF16; block inverses FP64 or FP32 (TD).
 constexpr int SWEEP_R = 2;
 
-template <int BS, typename TV>
+template <int BS, typename TV, typename TD>
 __global__ __launch_bounds__(256) void k_sweep_rows(int64_t n, const int32_t *__restrict__ rowptr,
                                                     const int32_t *__restrict__ col, const TV *__restrict__ val,
-                                                    const TV *__restrict__ Dinv, double omega,
+                                                    const TD *__restrict__ Dinv, double omega,
                                                     const double *__restrict__ b, const double *__restrict__ x,
                                                     double *__restrict__ xo, const int32_t *flag)
 {
-    if (*flag == 0) return;
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t w = (int64_t)blockIdx.x * 4 + wave_id();
     int64_t row[SWEEP_R];
 #pragma unroll
     for (int q = 0; q < SWEEP_R; ++q) row[q] = w * SWEEP_R + q;
-    if (row[0] >= n) return;
+    int k0[SWEEP_R], k1[SWEEP_R];
+    row_extents<SWEEP_R>(row, n, rowptr, k0, k1);
+    if (*flag == 0 || row[0] >= n) return;
     const int lane = threadIdx.x & 63;
     // row data of the update, loaded ahead of the product (lanes >= bs, and
     // rows past n, read the first row of the wavefront: in bounds, unused)
@@ -118,9 +119,9 @@ __global__ __launch_bounds__(256) void k_sweep_rows(int64_t n, const int32_t *__
         const int64_t rr = row[q] < n ? row[q] : row[0];
         br[q] = b[rr * BS + rl];
         xr[q] = x[rr * BS + rl];
-        RowLoad<BS, TV, false>::get(Dinv + (rr * BS + rl) * BS, d[q]);
+        RowLoad<BS, TD, false>::get(Dinv + (rr * BS + rl) * BS, d[q]);
     }
-    bsr_rows_dot<BS, TV, SWEEP_R, true>(row, n, rowptr, col, val, x, lane, ax);
+    bsr_rows_dot<BS, TV, SWEEP_R, true>(k0, k1, col, val, x, lane, ax);
 #pragma unroll
     for (int q = 0; q < SWEEP_R; ++q) {
         const double res = br[q] - ax[q];
@@ -128,42 +129,6 @@ __global__ __launch_bounds__(256) void k_sweep_rows(int64_t n, const int32_t *__
 #pragma unroll
         for (int c = 0; c < BS; ++c) u += d[q][c] * __shfl(res, c, 64);
         if (lane < BS && row[q] < n) xo[row[q] * BS + lane] = xr[q] + omega * u;
-    }
-}
-
-// general bs <= 8
-template <typename TV>
-__global__ __launch_bounds__(256) void k_sweepb(int64_t n, int bs, const int32_t *__restrict__ rowptr,
-                                                const int32_t *__restrict__ col, const TV *__restrict__ val,
-                                                const TV *__restrict__ Dinv, double omega,
-                                                const double *__restrict__ b, const double *__restrict__ x,
-                                                double *__restrict__ xo, const int32_t *flag)
-{
-    __shared__ double lds[256];
-    __shared__ double res[4][8];
-    if (*flag == 0) return;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int b2 = bs * bs, slots = 64 / b2;
-    const int slot = lane / b2, e = lane - slot * b2, c = e % bs;
-    double acc = 0.0;
-    if (row < n && slot < slots) {
-        const int k0 = rowptr[row], k1 = rowptr[row + 1];
-        for (int k = k0 + slot; k < k1; k += slots) acc += (double)val[(int64_t)k * b2 + e] * x[(int64_t)col[k] * bs + c];
-    }
-    lds[threadIdx.x] = acc;
-    __syncthreads();
-    if (row < n && lane < bs) {
-        double s = 0.0;
-        for (int sl = 0; sl < slots; ++sl)
-            for (int cc = 0; cc < bs; ++cc) s += lds[wv * 64 + sl * b2 + lane * bs + cc];
-        res[wv][lane] = b[row * bs + lane] - s;
-    }
-    __syncthreads();
-    if (row < n && lane < bs) {
-        double u = 0.0;
-        for (int cc = 0; cc < bs; ++cc) u += (double)Dinv[row * b2 + lane * bs + cc] * res[wv][cc];
-        xo[row * bs + lane] = x[row * bs + lane] + omega * u;
     }
 }
 
@@ -193,48 +158,22 @@ __global__ __launch_bounds__(256) void k_resid_rows(int64_t n, const int32_t *__
                                                     const double *__restrict__ b, const double *__restrict__ x,
                                                     double *__restrict__ r, const int32_t *flag)
 {
-    if (*flag == 0) return;
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t w = (int64_t)blockIdx.x * 4 + wave_id();
     int64_t row[RESID_R];
 #pragma unroll
     for (int q = 0; q < RESID_R; ++q) row[q] = w * RESID_R + q;
-    if (row[0] >= n) return;
+    int k0[RESID_R], k1[RESID_R];
+    row_extents<RESID_R>(row, n, rowptr, k0, k1);
+    if (*flag == 0 || row[0] >= n) return;
     const int lane = threadIdx.x & 63;
     const int rl = lane < BS ? lane : 0;
     double br[RESID_R], ax[RESID_R];
 #pragma unroll
     for (int q = 0; q < RESID_R; ++q) br[q] = b[(row[q] < n ? row[q] : row[0]) * BS + rl];
-    bsr_rows_dot<BS, TV, RESID_R, false>(row, n, rowptr, col, val, x, lane, ax);
+    bsr_rows_dot<BS, TV, RESID_R, false>(k0, k1, col, val, x, lane, ax);
 #pragma unroll
     for (int q = 0; q < RESID_R; ++q)
         if (lane < BS && row[q] < n) r[row[q] * BS + lane] = br[q] - ax[q];
-}
-
-template <typename TV>
-__global__ __launch_bounds__(256) void k_residb(int64_t n, int bs, const int32_t *__restrict__ rowptr,
-                                                const int32_t *__restrict__ col, const TV *__restrict__ val,
-                                                const double *__restrict__ b, const double *__restrict__ x,
-                                                double *__restrict__ r, const int32_t *flag)
-{
-    __shared__ double lds[256];
-    if (*flag == 0) return;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int b2 = bs * bs, slots = 64 / b2;
-    const int slot = lane / b2, e = lane - slot * b2, c = e % bs;
-    double acc = 0.0;
-    if (row < n && slot < slots) {
-        const int k0 = rowptr[row], k1 = rowptr[row + 1];
-        for (int k = k0 + slot; k < k1; k += slots) acc += (double)val[(int64_t)k * b2 + e] * x[(int64_t)col[k] * bs + c];
-    }
-    lds[threadIdx.x] = acc;
-    __syncthreads();
-    if (row < n && lane < bs) {
-        double s = 0.0;
-        for (int sl = 0; sl < slots; ++sl)
-            for (int cc = 0; cc < bs; ++cc) s += lds[wv * 64 + sl * b2 + lane * bs + cc];
-        r[row * bs + lane] = b[row * bs + lane] - s;
-    }
 }
 
 // --------------------------------------------------------- transfers ------
@@ -415,6 +354,16 @@ __global__ void k_to_f32(const double *a, float *b, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         b[i] = (float)a[i];
+}
+
+// BF16 copy (round to nearest even)
+template <typename T> __global__ void k_to_bf16(const T *a, uint16_t *b, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t u = __float_as_uint((float)a[i]);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        b[i] = (uint16_t)(u >> 16);
+    }
 }
 
 // ------------------------------------------------------------------ host --
@@ -659,8 +608,7 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
     F0.A.rowptr = ctx->J.rowptr;
     F0.A.col = ctx->J.col;
     F0.A.diag = ctx->J.diag;
-    F0.A.fp32 = true;
-    EFT_TRY(dmal(ctx, &F0.A.val32, ctx->J.nnzb * bs * bs));
+    F0.A.fp32 = true;   // storage (FP32 or BF16) is chosen and allocated in eft_mg_setup
     // coarsest level: dense inverse over its free dofs
     const MGLevel &Lc = ctx->mg.back();
     std::vector<uint8_t> cmh(Lc.N);
@@ -694,7 +642,7 @@ void eft_mg_free(eft_ctx *ctx)
             fr(L.Ba); fr(L.vp); fr(L.R); fr(L.dir_node); fr(L.dir_mask); fr(L.A.rowptr); fr(L.A.col); fr(L.A.diag);
             fr(L.A.val); fr(L.b); fr(L.iptr); fr(L.ient);
         }
-        fr(L.fmask); fr(L.Dinv); fr(L.Dinv32); fr(L.x); fr(L.x2); fr(L.r); fr(L.A.val32);
+        fr(L.fmask); fr(L.Dinv); fr(L.Dinv32); fr(L.x); fr(L.x2); fr(L.r); fr(L.A.val32); fr(L.A.val16);
     }
     ctx->mg.clear();
     fr(ctx->mg_dense);
@@ -718,16 +666,32 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
     const int bs = ctx->bs;
     const int64_t L = (int64_t)ctx->mg.size();
     MGLevel &F0 = ctx->mg[0];
-    if (ctx->J.fp32) {
-        EFT_HIP(hipMemcpyAsync(F0.A.val32, ctx->J.val32, sizeof(float) * ctx->J.nnzb * bs * bs,
-                               hipMemcpyDeviceToDevice, ctx->stream));
-    } else {
-        const int64_t nv = ctx->J.nnzb * bs * bs;
-        hipLaunchKernelGGL(k_to_f32, dim3((int)std::min<int64_t>(8192, (nv + 255) / 256)), dim3(256), 0, ctx->stream,
-                           ctx->J.val, F0.A.val32, nv);
+    const int64_t nv = ctx->J.nnzb * bs * bs;
+    const int cgrid = (int)std::min<int64_t>(8192, (nv + 255) / 256);
+    if (ctx->par.mg_bf16) {
+        // BF16 copy of the Jacobian; block inverses of its exact diagonal
+        if (!F0.A.val16) EFT_TRY(dmal(ctx, &F0.A.val16, nv));
+        F0.A.bf16 = true;
+        F0.A.fp32 = false;
+        if (ctx->J.fp32)
+            hipLaunchKernelGGL(k_to_bf16<float>, dim3(cgrid), dim3(256), 0, ctx->stream, ctx->J.val32, F0.A.val16, nv);
+        else
+            hipLaunchKernelGGL(k_to_bf16<double>, dim3(cgrid), dim3(256), 0, ctx->stream, ctx->J.val, F0.A.val16, nv);
         EFT_HIP(hipGetLastError());
+        EFT_TRY(eft_bj_setup32(ctx, &ctx->J, F0.Dinv32));
+    } else {
+        if (!F0.A.val32) EFT_TRY(dmal(ctx, &F0.A.val32, nv));
+        F0.A.bf16 = false;
+        F0.A.fp32 = true;
+        if (ctx->J.fp32) {
+            EFT_HIP(hipMemcpyAsync(F0.A.val32, ctx->J.val32, sizeof(float) * nv, hipMemcpyDeviceToDevice,
+                                   ctx->stream));
+        } else {
+            hipLaunchKernelGGL(k_to_f32, dim3(cgrid), dim3(256), 0, ctx->stream, ctx->J.val, F0.A.val32, nv);
+            EFT_HIP(hipGetLastError());
+        }
+        EFT_TRY(eft_bj_setup32(ctx, &F0.A, F0.Dinv32));
     }
-    EFT_TRY(eft_bj_setup32(ctx, &F0.A, F0.Dinv32));
     for (int64_t l = 1; l < L; ++l) {
         MGLevel &C = ctx->mg[l];
         InjArgs a;
@@ -789,46 +753,48 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
 
 namespace {
 
-template <typename TV>
-void launch_sweep(eft_ctx *ctx, const eft_matrix &A, const TV *val, const TV *Dinv, double omega, const double *b,
+template <typename TV, typename TD>
+void launch_sweep(eft_ctx *ctx, const eft_matrix &A, const TV *val, const TD *Dinv, double omega, const double *b,
                   const double *x, double *xo, const int32_t *flag)
 {
-    const dim3 g(eft_grid(A.n, 4 * SWEEP_R)), g1(eft_grid(A.n, 4)), t(256);
+    const dim3 g(eft_grid(A.n, 4 * SWEEP_R)), t(256);
     if (A.bs == 3)
-        hipLaunchKernelGGL((k_sweep_rows<3, TV>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, Dinv, omega, b, x,
-                           xo, flag);
-    else if (A.bs == 4)
-        hipLaunchKernelGGL((k_sweep_rows<4, TV>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, Dinv, omega, b, x,
-                           xo, flag);
+        hipLaunchKernelGGL((k_sweep_rows<3, TV, TD>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, Dinv, omega, b,
+                           x, xo, flag);
     else
-        hipLaunchKernelGGL(k_sweepb<TV>, g1, t, 0, ctx->stream, A.n, A.bs, A.rowptr, A.col, val, Dinv, omega, b, x, xo,
-                           flag);
+        hipLaunchKernelGGL((k_sweep_rows<4, TV, TD>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, Dinv, omega, b,
+                           x, xo, flag);
 }
 
 template <typename TV>
 void launch_resid(eft_ctx *ctx, const eft_matrix &A, const TV *val, const double *b, const double *x, double *r,
                   const int32_t *flag)
 {
-    const dim3 g(eft_grid(A.n, 4 * RESID_R)), g1(eft_grid(A.n, 4)), t(256);
+    const dim3 g(eft_grid(A.n, 4 * RESID_R)), t(256);
     if (A.bs == 3)
         hipLaunchKernelGGL((k_resid_rows<3, TV>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, b, x, r, flag);
-    else if (A.bs == 4)
-        hipLaunchKernelGGL((k_resid_rows<4, TV>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, b, x, r, flag);
     else
-        hipLaunchKernelGGL(k_residb<TV>, g1, t, 0, ctx->stream, A.n, A.bs, A.rowptr, A.col, val, b, x, r, flag);
+        hipLaunchKernelGGL((k_resid_rows<4, TV>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, b, x, r, flag);
 }
 
+// (the momentum/mass system has bs = d + 1, 3 or 4)
 void sweep(eft_ctx *ctx, const MGLevel &L, const double *b, const double *x, double *xo, const int32_t *flag)
 {
-    if (L.A.fp32) launch_sweep<float>(ctx, L.A, L.A.val32, L.Dinv32, ctx->par.mg_omega, b, x, xo, flag);
-    else launch_sweep<double>(ctx, L.A, L.A.val, L.Dinv, ctx->par.mg_omega, b, x, xo, flag);
+    const double om = ctx->par.mg_omega;
+    if (L.A.bf16)
+        launch_sweep<eft_bf16, float>(ctx, L.A, reinterpret_cast<const eft_bf16 *>(L.A.val16), L.Dinv32, om, b, x, xo,
+                                      flag);
+    else if (L.A.fp32)
+        launch_sweep<float, float>(ctx, L.A, L.A.val32, L.Dinv32, om, b, x, xo, flag);
+    else
+        launch_sweep<double, double>(ctx, L.A, L.A.val, L.Dinv, om, b, x, xo, flag);
 }
 
 // first sweep from x = 0
 void sweep0(eft_ctx *ctx, const MGLevel &L, const double *b, double *x, const int32_t *flag)
 {
     const int64_t nd = L.N * ctx->bs;
-    if (L.A.fp32)
+    if (L.A.fp32 || L.A.bf16)
         hipLaunchKernelGGL(k_sweep0<float>, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, nd, ctx->bs, L.Dinv32,
                            ctx->par.mg_omega, b, x, flag);
     else
@@ -840,8 +806,9 @@ void sweep0(eft_ctx *ctx, const MGLevel &L, const double *b, double *x, const in
 // once, the block inverses, b and x read and x_out written once.
 double sweep_bytes(const eft_matrix &A)
 {
-    const double vb = A.fp32 ? 4.0 : 8.0, b2 = (double)A.bs * A.bs;
-    return (double)A.nnzb * (b2 * vb + 4.0) + (double)(A.n + 1) * 4.0 + (double)A.n * (b2 * vb + 3.0 * A.bs * 8.0);
+    const double vb = A.bf16 ? 2.0 : A.fp32 ? 4.0 : 8.0, db = (A.bf16 || A.fp32) ? 4.0 : 8.0;
+    const double b2 = (double)A.bs * A.bs;
+    return (double)A.nnzb * (b2 * vb + 4.0) + (double)(A.n + 1) * 4.0 + (double)A.n * (b2 * db + 3.0 * A.bs * 8.0);
 }
 
 // fine-level sweeps carry the kernel-timing hook
@@ -855,7 +822,8 @@ void timed_sweep(eft_ctx *ctx, int l, const MGLevel &L, const double *b, const d
 
 void resid(eft_ctx *ctx, const eft_matrix &A, const double *b, const double *x, double *r, const int32_t *flag)
 {
-    if (A.fp32) launch_resid<float>(ctx, A, A.val32, b, x, r, flag);
+    if (A.bf16) launch_resid<eft_bf16>(ctx, A, reinterpret_cast<const eft_bf16 *>(A.val16), b, x, r, flag);
+    else if (A.fp32) launch_resid<float>(ctx, A, A.val32, b, x, r, flag);
     else launch_resid<double>(ctx, A, A.val, b, x, r, flag);
 }
 

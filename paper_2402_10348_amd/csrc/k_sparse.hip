@@ -23,15 +23,16 @@ __global__ __launch_bounds__(256) void k_spmv_rows(int64_t n, const int32_t *__r
                                                    const double *__restrict__ x, double *__restrict__ y,
                                                    const int32_t *active)
 {
-    if (GATED && *active == 0) return;
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t w = (int64_t)blockIdx.x * 4 + wave_id();
     int64_t row[SPMV_R];
 #pragma unroll
     for (int q = 0; q < SPMV_R; ++q) row[q] = w * SPMV_R + q;
-    if (row[0] >= n) return;
+    int k0[SPMV_R], k1[SPMV_R];
+    row_extents<SPMV_R>(row, n, rowptr, k0, k1);
+    if ((GATED && *active == 0) || row[0] >= n) return;
     const int lane = threadIdx.x & 63;
     double acc[SPMV_R];
-    bsr_rows_dot<BS, TV, SPMV_R, false>(row, n, rowptr, col, val, x, lane, acc);
+    bsr_rows_dot<BS, TV, SPMV_R, false>(k0, k1, col, val, x, lane, acc);
 #pragma unroll
     for (int q = 0; q < SPMV_R; ++q)
         if (lane < BS && row[q] < n) y[row[q] * BS + lane] = acc[q];

@@ -44,7 +44,8 @@ class Params(C.Structure):
                 ("nl_max", C.c_int32), ("nl_fixed", C.c_int32), ("lin_rtol", C.c_double),
                 ("restart", C.c_int32), ("lin_maxit", C.c_int32), ("precond", C.c_int32),
                 ("precision", C.c_int32), ("band_flat", C.c_double), ("band_cell", C.c_int32),
-                ("band_halo", C.c_int32), ("mg_nu", C.c_int32), ("mg_omega", C.c_double)]
+                ("band_halo", C.c_int32), ("mg_nu", C.c_int32), ("mg_omega", C.c_double),
+                ("mg_bf16", C.c_int32)]
 
 
 class State(C.Structure):
@@ -112,7 +113,8 @@ def params_struct(p, **over):
     vals = dict(dt=p.dt, rho_inf=p.rho_inf, eps=p.eps, eta=p.eta, C_I=p.C_I, di_cut=p.di_cut, nl_rtol=p.nl_rtol,
                 nl_max=p.nl_max, nl_fixed=p.nl_fixed, lin_rtol=p.lin_rtol, restart=p.restart,
                 lin_maxit=p.lin_maxit, precond=p.precond, precision=p.precision, band_flat=p.band_flat,
-                band_cell=p.band_cell, band_halo=p.band_halo, mg_nu=p.mg_nu, mg_omega=p.mg_omega)
+                band_cell=p.band_cell, band_halo=p.band_halo, mg_nu=p.mg_nu, mg_omega=p.mg_omega,
+                mg_bf16=p.mg_bf16)
     vals.update(over)
     P = Params()
     for k, v in vals.items():

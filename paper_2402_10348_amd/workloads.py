@@ -156,6 +156,7 @@ class Params:
     band_halo: int = 1
     mg_nu: int = 2
     mg_omega: float = 0.7
+    mg_bf16: int = 0
 
 
 @dataclass
