@@ -103,12 +103,14 @@ typedef struct {
     double band_flat;            /* band seed: |phi^n| < 1 - band_flat             */
     int32_t band_cell;           /* mesh cells per grid cell and axis              */
     int32_t band_halo;           /* grid-cell layers added around the seeds        */
-    int32_t mg_nu;               /* multigrid: smoothing sweeps before and after
-                                    the coarse correction (1..8)                   */
+    int32_t mg_nu;               /* multigrid: smoothing sweeps before the coarse
+                                    correction, the first from x = 0 (1..8)        */
     double mg_omega;             /* multigrid: damping of the block-Jacobi sweeps  */
     int32_t mg_bf16;             /* multigrid: 1 stores the finest level's matrix
                                     copy in BF16 (block inverses from the FP64
                                     diagonal blocks), 0 in FP32                    */
+    int32_t mg_nu_post;          /* multigrid: smoothing sweeps after the coarse
+                                    correction (1..8)                              */
 } eft_params;
 
 /* State at time level n (Sec. 2.1.2): values and rates.  DEVICE arrays. */

@@ -861,8 +861,9 @@ double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag, double
     double *xc = vcycle(ctx, l + 1, C.b, flag);
     hipLaunchKernelGGL(k_prolong, dim3(eft_grid(L.N, 256)), dim3(256), 0, ctx->stream, cd, fd, bs, C.fmask, L.fmask, xc,
                        cur, flag);
-    for (int s = 0; s < ctx->par.mg_nu; ++s) {
-        double *dst = (out && s + 1 == ctx->par.mg_nu) ? out : oth;
+    const int npost = ctx->par.mg_nu_post;
+    for (int s = 0; s < npost; ++s) {
+        double *dst = (out && s + 1 == npost) ? out : oth;
         timed_sweep(ctx, l, L, b, cur, dst, flag);
         oth = cur;
         cur = dst;

@@ -154,9 +154,10 @@ class Params:
     band_flat: float = 1e-6
     band_cell: int = 4
     band_halo: int = 1
-    mg_nu: int = 2
+    mg_nu: int = 1            # pre-smoothing sweeps (the first from zero)
     mg_omega: float = 0.7
     mg_bf16: int = 0
+    mg_nu_post: int = 3
 
 
 @dataclass

@@ -135,7 +135,7 @@ def test_multigrid_preconditioner_same_solution(torch_cuda, name, n):
 
 def test_kernel_timer_counts(torch_cuda):
     """The HIP-event timing hook sees every launch of the timed kernel role
-    in a solve: one SpMV and 2 nu - 1 fine-level sweeps per Krylov
+    in a solve: one SpMV and (pre - 1) + post fine-level sweeps per Krylov
     iteration that did work, each with the algorithmic bytes of its shape."""
     prob = W.cavity_sphere_3d(n=16)
     say("[timer] sphere3d n=16")
@@ -143,13 +143,13 @@ def test_kernel_timer_counts(torch_cuda):
     ctx = ctx_for(prob, lin_rtol=1e-10)
     R = ctx.assemble(ctx.device_state(lvl), ctx.device_state(it))
     n, nnzb, bs = ctx.matrix_shape()
-    nu = prob.params.mg_nu
+    fine_sweeps = (prob.params.mg_nu - 1) + prob.params.mg_nu_post   # the first pre-sweep is a separate kernel
     sweep_b = nnzb * (bs * bs * 4 + 4) + (n + 1) * 4 + n * (bs * bs * 4 + 3 * bs * 8)
     spmv_b = nnzb * (bs * bs * 8 + 4) + (n + 1) * 4 + 2 * n * bs * 8
     ctx.time_kernel(1, 2, 3)
     x, info = ctx.fgmres(-R)
     assert info["converged"] == 1
-    for role, per_it, nbytes in ((1, 2 * nu - 1, sweep_b), (2, 1, spmv_b)):
+    for role, per_it, nbytes in ((1, fine_sweeps, sweep_b), (2, 1, spmv_b)):
         kt = ctx.kernel_time(role)
         say(f"  role={role} iters={info['iters']} {kt}")
         assert kt["active"] == info["iters"] * per_it
