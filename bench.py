@@ -70,7 +70,7 @@ def log(args, *a):
         print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_NAME = {1: "k_sweep_rows<4, float> (fine-level multigrid smoother sweep, FP32 copy of the 4x4-block "
+KERNEL_NAME = {1: "k_sweep_rows<4, float, float> (fine-level multigrid smoother sweep, FP32 copy of the 4x4-block "
                   "momentum Jacobian)",
                2: "k_spmv_rows<4, double, true> (FP64 SpMV of the 4x4-block momentum Jacobian in FGMRES)",
                3: "k_ns_rows<3, double> (momentum/mass residual and Jacobian assembly, bytes: J and R written "
