@@ -148,8 +148,11 @@ typedef struct {
     double beta[64];             /* Lagrange multiplier per indicator              */
     int64_t band_nodes[64];      /* band size per indicator                        */
     int64_t band_elems[64];
-    int32_t lin_iters[128];      /* per indicator, then per solid                  */
+    int32_t lin_iters[128];      /* per indicator, then per solid: iterations of
+                                    the solve the system took part in             */
     double ratio[128];           /* ||dx||/||x|| per indicator, then per solid     */
+    int32_t ac_iters, b_iters;   /* Krylov iterations of the batched Allen-Cahn
+                                    solve (all indicators) and B solve (all solids)*/
 } eft_transport_info;
 
 typedef struct {
@@ -229,7 +232,10 @@ eft_status eft_band_system(eft_ctx *ctx, const eft_state *level_n, const eft_ite
 /* (c) One transport pass of the partitioned iteration (eqs. LS_AC, LS_MC):
  * for every indicator the mobility gamma (eq. tdm-num, RMS over |phi| <= 0.9),
  * beta, one Allen-Cahn solve on its band; then for every solid one B solve on
- * the band of its indicator with the updated phi.  Updates it->phi and it->B
+ * the band of its indicator with the updated phi.  The systems of one kind
+ * are solved together, as one block-diagonal system whose member rows are
+ * scaled by 1/||b_k||, to lin_rtol / sqrt(members), so that every member
+ * meets lin_rtol.  Updates it->phi and it->B
  * in place.  Requires eft_bands_build for the current level. */
 eft_status eft_transport_solids(eft_ctx *ctx, const eft_state *level_n, eft_iterate *it,
                                 eft_transport_info *info);

@@ -105,6 +105,11 @@ void free_all(eft_ctx *ctx)
     KrylovWs &K = ctx->kw;
     fr(K.V); fr(K.Z); fr(K.w); fr(K.r); fr(K.Dinv); fr(K.part); fr(K.small); fr(K.flag);
     if (ctx->hscal) (void)hipHostFree(ctx->hscal);
+    if (ctx->htsc) (void)hipHostFree(ctx->htsc);
+    fr(ctx->tsc);
+    for (eft_ctx::BandUnion *U : {&ctx->u_ac, &ctx->u_b}) {
+        fr(U->rowptr); fr(U->col); fr(U->diag);
+    }
     for (hipEvent_t e : ctx->kt.ev) (void)hipEventDestroy(e);
     ctx->kt.ev.clear();
     eft_nn_free(ctx);
@@ -380,6 +385,11 @@ eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *
     ctx->nred = (int32_t)(2 * ((N + 255) / 256) + 2 * ((E + 255) / 256) + 4096);
     EFT_TRY(dalloc(ctx, &ctx->red, ctx->nred));
     EFT_TRY(dalloc(ctx, &ctx->dscal, 64));
+    EFT_TRY(dalloc(ctx, &ctx->tsc, 1024));
+    if (hipHostMalloc((void **)&ctx->htsc, sizeof(double) * 1024, hipHostMallocDefault) != hipSuccess) {
+        ctx->err = "out of pinned host memory";
+        return EFT_ENOMEM;
+    }
     if (hipHostMalloc((void **)&ctx->hscal, sizeof(double) * 64, hipHostMallocDefault) != hipSuccess) {
         ctx->err = "pinned host allocation failed";
         return EFT_ENOMEM;
@@ -736,9 +746,9 @@ eft_status eft_step(eft_ctx *ctx, eft_state *st, double dt, eft_step_info *info)
                 restore();
                 return ts;
             }
+            inf.lin_iters_total += ti.ac_iters + ti.b_iters;
             for (int b = 0; b < ctx->n_ind + ctx->n_s; ++b) {
                 inf.block_ratio[1 + b] = ti.ratio[b];
-                inf.lin_iters_total += ti.lin_iters[b];
                 inf.lin_iters_block[1 + b] += ti.lin_iters[b];
                 if (!std::isfinite(ti.ratio[b])) {
                     restore();

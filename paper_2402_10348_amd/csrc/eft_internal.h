@@ -184,6 +184,16 @@ struct eft_ctx {
     // transport
     std::vector<Band> band;                    // per indicator
     bool bands_valid = false;
+    // block-diagonal union of the band systems of one kind (all Allen-Cahn
+    // systems, all B systems), solved together; rebuilt with the bands
+    struct BandUnion {
+        int64_t n = 0, nnz = 0, cap_n = 0, cap_nnz = 0;
+        int32_t *rowptr = nullptr, *col = nullptr, *diag = nullptr;
+        std::vector<int> band_of;              // band of each member system
+        std::vector<int64_t> roff, noff;       // row / block offsets of each member
+    } u_ac, u_b;
+    double *tsc = nullptr;                     // [1024] device transport scalars
+    double *htsc = nullptr;                    // [1024] pinned host copy
     uint8_t *seed = nullptr, *active = nullptr;  // [n_cells]
     uint8_t *nin = nullptr, *nout = nullptr;     // [N]
     uint8_t *ein = nullptr;                      // [E]
@@ -275,7 +285,8 @@ eft_status eft_spmv_flag(eft_ctx *ctx, const eft_matrix *A, const double *x, dou
 
 // k_krylov.hip
 eft_status eft_krylov_reserve(eft_ctx *ctx, int64_t n, int bs, int m);
-eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, double *x, eft_solve_info *info);
+eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, double *x, eft_solve_info *info,
+                          double rtol = 0.0);   // rtol <= 0: par.lin_rtol
 eft_status eft_norm2(eft_ctx *ctx, const double *x, int64_t n, double *out_host);
 eft_status eft_dot_dev(eft_ctx *ctx, const double *x, const double *y, int64_t n, double *out_dev);
 

@@ -305,7 +305,8 @@ static double spmv_bytes(const eft_matrix *A)
     return (double)A->nnzb * (b2 * vb + 4.0) + (double)(A->n + 1) * 4.0 + 2.0 * A->n * A->bs * 8.0;
 }
 
-eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, double *x, eft_solve_info *info)
+eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, double *x, eft_solve_info *info,
+                          double rtol)
 {
     const int bs = A->bs;
     const int64_t n = A->n, nd = n * bs;
@@ -341,7 +342,7 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
     NNState &NS = ctx->net;
     const bool harvest = NS.cap_pairs > 0 && A == &ctx->J;
     if (!mg || harvest) EFT_TRY(eft_bj_setup(ctx, A, K.Dinv));
-    const double tol = ctx->par.lin_rtol * bnorm;
+    const double tol = (rtol > 0.0 ? rtol : ctx->par.lin_rtol) * bnorm;
     const int maxit = std::max(1, ctx->par.lin_maxit);
     int chunk = 8;   // columns enqueued between two reads of the solver state
     int total = 0;

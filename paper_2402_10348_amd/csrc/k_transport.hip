@@ -731,6 +731,31 @@ __global__ __launch_bounds__(256) void k_band_update(int64_t n, int bs, const in
     x[(int64_t)node[r] * bs + c] += dx[t];
 }
 
+// member system of a block-diagonal union: rows shifted by roff, blocks by noff
+__global__ __launch_bounds__(256) void k_union_fill(int64_t n, int64_t nnz, const int32_t *rowptr,
+                                                    const int32_t *col, const int32_t *diag, int64_t roff,
+                                                    int64_t noff, int32_t *urow, int32_t *ucol, int32_t *udiag)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) {
+        urow[roff + t] = (int32_t)(rowptr[t] + noff);
+        udiag[roff + t] = (int32_t)(diag[t] + noff);
+    }
+    if (t < nnz) ucol[noff + t] = (int32_t)(col[t] + roff);
+}
+
+__global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
+
+// v *= 1/sqrt(*nrm2) (unscale: v *= sqrt(*nrm2)); factor 1 when *nrm2 = 0
+__global__ __launch_bounds__(256) void k_scale_member(int64_t n, double *v, const double *nrm2, int unscale)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double s2 = *nrm2;
+    if (!(s2 > 0.0)) return;
+    v[i] = unscale ? v[i] * sqrt(s2) : v[i] / sqrt(s2);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- host side --
@@ -804,6 +829,55 @@ eft_status eft_reserve_band_sys(eft_ctx *ctx, int64_t n, int64_t nnz)
         }
         ctx->bcap_nnz = c;
     }
+    return EFT_OK;
+}
+
+static eft_status build_union(eft_ctx *ctx, eft_ctx::BandUnion &U, const std::vector<int> &bands)
+{
+    U.band_of = bands;
+    U.roff.assign(bands.size(), 0);
+    U.noff.assign(bands.size(), 0);
+    int64_t n = 0, nnz = 0;
+    for (size_t q = 0; q < bands.size(); ++q) {
+        U.roff[q] = n;
+        U.noff[q] = nnz;
+        n += ctx->band[bands[q]].n;
+        nnz += ctx->band[bands[q]].nnz;
+    }
+    if (n + 1 > U.cap_n) {
+        if (U.rowptr) (void)hipFree(U.rowptr);
+        if (U.diag) (void)hipFree(U.diag);
+        U.rowptr = U.diag = nullptr;
+        U.cap_n = 0;
+        const int64_t c = n + n / 4 + 64;
+        if (hipMalloc(&U.rowptr, sizeof(int32_t) * c) != hipSuccess || hipMalloc(&U.diag, sizeof(int32_t) * c) != hipSuccess) {
+            ctx->err = "out of device memory (band union)";
+            return EFT_ENOMEM;
+        }
+        U.cap_n = c;
+    }
+    if (nnz > U.cap_nnz || !U.col) {
+        if (U.col) (void)hipFree(U.col);
+        U.col = nullptr;
+        U.cap_nnz = 0;
+        const int64_t c = nnz + nnz / 4 + 64;
+        if (hipMalloc(&U.col, sizeof(int32_t) * c) != hipSuccess) {
+            ctx->err = "out of device memory (band union)";
+            return EFT_ENOMEM;
+        }
+        U.cap_nnz = c;
+    }
+    U.n = n;
+    U.nnz = nnz;
+    for (size_t q = 0; q < bands.size(); ++q) {
+        const Band &B = ctx->band[bands[q]];
+        const int64_t m = std::max(B.n, B.nnz);
+        if (m > 0)
+            hipLaunchKernelGGL(k_union_fill, dim3(eft_grid(m, 256)), dim3(256), 0, ctx->stream, B.n, B.nnz, B.rowptr,
+                               B.col, B.diag, U.roff[q], U.noff[q], U.rowptr, U.col, U.diag);
+    }
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, ctx->stream, U.rowptr + n, (int32_t)nnz);
+    EFT_HIP(hipGetLastError());
     return EFT_OK;
 }
 
@@ -884,47 +958,42 @@ eft_status eft_bands_build_dev(eft_ctx *ctx, const double *phi_n)
         max_n = std::max(max_n, n);
         max_nnz = std::max(max_nnz, nnz);
     }
+    // unions of the Allen-Cahn systems (one per indicator) and of the B
+    // systems (one per solid, on its indicator's band)
+    std::vector<int> ac_bands, b_bands;
+    for (int k = 0; k < ctx->n_ind; ++k) ac_bands.push_back(k);
+    for (int sI = 0; sI < ctx->n_s; ++sI) b_bands.push_back(ctx->solid_ind[sI]);
+    EFT_TRY(build_union(ctx, ctx->u_ac, ac_bands));
+    EFT_TRY(build_union(ctx, ctx->u_b, b_bands));
+    max_n = std::max(ctx->u_ac.n, ctx->u_b.n);
+    max_nnz = std::max(ctx->u_ac.nnz, ctx->u_b.nnz);
     EFT_TRY(eft_reserve_band_sys(ctx, max_n, max_nnz));
     EFT_HIP(hipStreamSynchronize(ctx->stream));
     ctx->bands_valid = true;
     return EFT_OK;
 }
 
-static eft_status band_solve(eft_ctx *ctx, const Band &B, int bs, double *x_global, double *ratio_num,
-                             eft_solve_info *si)
-{
-    // the band system (unit rows already in place) -> rhs = -R
-    const int64_t nd = B.n * bs;
-    hipLaunchKernelGGL(k_negate, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, ctx->bR, nd);
-    EFT_HIP(hipGetLastError());
-    eft_matrix A;
-    A.bs = bs;
-    A.n = B.n;
-    A.nnzb = B.nnz;
-    A.rowptr = B.rowptr;
-    A.col = B.col;
-    A.diag = B.diag;
-    A.val = ctx->bval;
-    eft_status st = eft_fgmres_dev(ctx, &A, ctx->bR, ctx->bX, si);
-    if (st != EFT_OK && st != EFT_ENOTCONV) return st;
-    hipLaunchKernelGGL(k_band_update, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, B.n, bs, B.node, ctx->bX,
-                       x_global);
-    EFT_HIP(hipGetLastError());
-    EFT_TRY(eft_norm2(ctx, ctx->bX, nd, ratio_num));
-    return st;
-}
+// slots of ctx->tsc: per-indicator sums (S, count, beta numerator and
+// denominator), gamma and beta per indicator, per-member squared norms
+constexpr int TS_SUM = 0, TS_GB = 4 * EFT_MAX_IND, TS_NRM = 6 * EFT_MAX_IND, TS_DN = TS_NRM + 128,
+              TS_XN = TS_DN + 128;
 
-// gamma and beta of indicator k at the iterate (host values; also left in
-// dscal[4..5] for the element kernel)
-static eft_status mobility_beta(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, int k, double gb[2])
+// gamma and beta of every indicator at the iterate (eq. tdm-num with the RMS
+// over the diffuse region, and the multiplier of Sec. 2.2.1): the sums of all
+// indicators are read back in one transfer; gamma, beta are left on the
+// device at tsc[TS_GB + 2k] for the element kernels and returned in gb
+static eft_status mobility_beta_all(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, double *gb)
 {
     const int D = ctx->dim;
     const int64_t N = ctx->N;
-    const Band &B = ctx->band[k];
     GA ga = ga_of(ctx->par.rho_inf, ctx->par.dt);
-    const double *lphi = lvl->phi + (int64_t)k * N, *iphi = it->phi + (int64_t)k * N;
-    gb[0] = gb[1] = 0.0;
-    if (B.ne > 0) {
+    const int K = ctx->n_ind;
+    if (K == 0) return EFT_OK;
+    EFT_TRY(eft_fill(ctx, ctx->tsc + TS_SUM, 4 * (int64_t)K, 0.0));
+    for (int k = 0; k < K; ++k) {
+        const Band &B = ctx->band[k];
+        if (B.ne == 0) continue;
+        const double *lphi = lvl->phi + (int64_t)k * N, *iphi = it->phi + (int64_t)k * N;
         EFT_TRY(eft_fill(ctx, ctx->tnum, B.n, 0.0));
         EFT_TRY(eft_fill(ctx, ctx->tden, B.n, 0.0));
         if (D == 2)
@@ -936,7 +1005,7 @@ static eft_status mobility_beta(eft_ctx *ctx, const eft_state *lvl, const eft_it
         const int nbn = eft_grid(B.n, 256);
         hipLaunchKernelGGL(k_mob_node, dim3(nbn), dim3(256), 0, ctx->stream, B.n, B.node, lphi, iphi, ga.alpha,
                            ctx->par.di_cut, ctx->tnum, ctx->tden, ctx->red);
-        hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, ctx->stream, ctx->red, nbn, ctx->dscal);
+        hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, ctx->stream, ctx->red, nbn, ctx->tsc + TS_SUM + 4 * k);
         const int nbe = eft_grid(B.ne, 256);
         if (D == 2)
             hipLaunchKernelGGL(k_beta_elem<2>, dim3(nbe), dim3(256), 0, ctx->stream, B.ne, B.elem, ctx->conn, ctx->xyz,
@@ -944,18 +1013,22 @@ static eft_status mobility_beta(eft_ctx *ctx, const eft_state *lvl, const eft_it
         else
             hipLaunchKernelGGL(k_beta_elem<3>, dim3(nbe), dim3(256), 0, ctx->stream, B.ne, B.elem, ctx->conn, ctx->xyz,
                                lphi, iphi, ga.alpha, ctx->red + 2 * (int64_t)nbn);
-        hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, ctx->stream, ctx->red + 2 * (int64_t)nbn, nbe, ctx->dscal + 2);
+        hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, ctx->stream, ctx->red + 2 * (int64_t)nbn, nbe,
+                           ctx->tsc + TS_SUM + 4 * k + 2);
         EFT_HIP(hipGetLastError());
-        EFT_HIP(hipMemcpyAsync(ctx->hscal, ctx->dscal, sizeof(double) * 4, hipMemcpyDeviceToHost, ctx->stream));
-        EFT_HIP(hipStreamSynchronize(ctx->stream));
-        const double S = ctx->hscal[0], cnt = ctx->hscal[1], bnum = ctx->hscal[2], bden = ctx->hscal[3];
-        gb[0] = cnt > 0.0 ? sqrt(S / cnt) / ctx->par.eta : 0.0;
-        gb[1] = bden > 0.0 ? bnum / bden : 0.0;
     }
-    ctx->hscal[8] = gb[0];
-    ctx->hscal[9] = gb[1];
-    EFT_HIP(hipMemcpyAsync(ctx->dscal + 4, ctx->hscal + 8, sizeof(double) * 2, hipMemcpyHostToDevice, ctx->stream));
+    EFT_HIP(hipMemcpyAsync(ctx->htsc + TS_SUM, ctx->tsc + TS_SUM, sizeof(double) * 4 * K, hipMemcpyDeviceToHost,
+                           ctx->stream));
     EFT_HIP(hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < K; ++k) {
+        const double *h = ctx->htsc + TS_SUM + 4 * k;
+        gb[2 * k] = h[1] > 0.0 ? sqrt(h[0] / h[1]) / ctx->par.eta : 0.0;
+        gb[2 * k + 1] = h[3] > 0.0 ? h[2] / h[3] : 0.0;
+        ctx->htsc[TS_GB + 2 * k] = gb[2 * k];
+        ctx->htsc[TS_GB + 2 * k + 1] = gb[2 * k + 1];
+    }
+    EFT_HIP(hipMemcpyAsync(ctx->tsc + TS_GB, ctx->htsc + TS_GB, sizeof(double) * 2 * K, hipMemcpyHostToDevice,
+                           ctx->stream));
     return EFT_OK;
 }
 
@@ -991,37 +1064,41 @@ static TrArgs tr_args(eft_ctx *ctx, const Band &B, const double *lx, const doubl
     return a;
 }
 
-// Allen-Cahn system of indicator k on its band (unit rows for kept nodes);
-// gamma, beta must be in dscal[4..5]
-static eft_status assemble_ac(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, int k)
+// Allen-Cahn system of indicator k on its band (unit rows for kept nodes)
+// into R, J; gamma, beta at gb (device)
+static eft_status assemble_ac(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, int k, double *R, double *J,
+                              const double *gb)
 {
     const int64_t N = ctx->N;
     const Band &B = ctx->band[k];
     TrArgs a = tr_args(ctx, B, lvl->phi + (int64_t)k * N, lvl->phidot + (int64_t)k * N, it->phi + (int64_t)k * N);
+    a.R = R;
+    a.J = J;
     if (B.n > 0) {
         const size_t shm = (size_t)a.rpb * (a.maxc + 1) * sizeof(double);
         if (ctx->dim == 2)
             hipLaunchKernelGGL(k_ac_rows<2>, dim3(eft_grid(B.n, a.rpb)), dim3(256), shm, ctx->stream, a, ctx->par.eps,
-                               ctx->dscal + 4);
+                               gb);
         else
             hipLaunchKernelGGL(k_ac_rows<3>, dim3(eft_grid(B.n, a.rpb)), dim3(256), shm, ctx->stream, a, ctx->par.eps,
-                               ctx->dscal + 4);
-    }
-    if (B.n > 0)
+                               gb);
         hipLaunchKernelGGL(k_band_bc, dim3(eft_grid(B.n, 256)), dim3(256), 0, ctx->stream, B.n, 1, B.fre, B.rowptr,
-                           B.col, ctx->bR, ctx->bval);
+                           B.col, R, J);
+    }
     EFT_HIP(hipGetLastError());
     return EFT_OK;
 }
 
-// B system of solid s on the band of its indicator; the solid fractions in
-// ctx->as must come from the current order parameters
-static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, int s)
+// B system of solid s on the band of its indicator into R, J; the solid
+// fractions in ctx->as must come from the current order parameters
+static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, int s, double *R, double *J)
 {
     const int64_t N = ctx->N;
     const int nv = ctx->nv;
     const Band &B = ctx->band[ctx->solid_ind[s]];
     TrArgs a = tr_args(ctx, B, lvl->B + (int64_t)s * N * nv, lvl->Bdot + (int64_t)s * N * nv, it->B + (int64_t)s * N * nv);
+    a.R = R;
+    a.J = J;
     if (B.n > 0) {
         const size_t shm = (size_t)a.rpb * ((size_t)a.maxc * ((nv * nv) | 1) + (nv | 1)) * sizeof(double);
         if (ctx->dim == 2)
@@ -1030,12 +1107,71 @@ static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_itera
         else
             hipLaunchKernelGGL(k_b_rows<3>, dim3(eft_grid(B.n, a.rpb)), dim3(256), shm, ctx->stream, a,
                                ctx->as + (int64_t)s * N);
-    }
-    if (B.n > 0)
         hipLaunchKernelGGL(k_band_bc, dim3(eft_grid(B.n, 256)), dim3(256), 0, ctx->stream, B.n, nv, B.fre, B.rowptr,
-                           B.col, ctx->bR, ctx->bval);
+                           B.col, R, J);
+    }
     EFT_HIP(hipGetLastError());
     return EFT_OK;
+}
+
+// Solve the assembled union system (R in bR, matrix in bval) of one kind:
+// rhs = -R; with several members, member k's right-hand side is divided by
+// ||R_k|| (its solution multiplied back afterwards), which weights the
+// union residual like scaling the member's rows, and FGMRES runs to
+// lin_rtol/sqrt(members), so that every member meets lin_rtol; then
+// x_k += dx_k on the band nodes.  ratio[q] = ||dx_q|| / ||x_q|| (one
+// read-back for all members).
+static eft_status union_solve(eft_ctx *ctx, const eft_ctx::BandUnion &U, int bs, const std::vector<double *> &x,
+                              const std::vector<int64_t> &xlen, double *ratio, eft_solve_info *si)
+{
+    const int64_t nd = U.n * bs;
+    const int Q = (int)U.band_of.size();
+    hipLaunchKernelGGL(k_negate, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, ctx->bR, nd);
+    int members = 0;
+    for (int q = 0; q < Q; ++q) members += ctx->band[U.band_of[q]].n > 0 ? 1 : 0;
+    const bool scaled = members > 1;
+    if (scaled)
+        for (int q = 0; q < Q; ++q) {
+            const Band &B = ctx->band[U.band_of[q]];
+            if (B.n == 0) continue;
+            double *Rq = ctx->bR + U.roff[q] * bs;
+            EFT_TRY(eft_dot_dev(ctx, Rq, Rq, B.n * bs, ctx->tsc + TS_NRM + q));
+            hipLaunchKernelGGL(k_scale_member, dim3(eft_grid(B.n * bs, 256)), dim3(256), 0, ctx->stream, B.n * bs, Rq,
+                               ctx->tsc + TS_NRM + q, 0);
+        }
+    EFT_HIP(hipGetLastError());
+    eft_matrix A;
+    A.bs = bs;
+    A.n = U.n;
+    A.nnzb = U.nnz;
+    A.rowptr = U.rowptr;
+    A.col = U.col;
+    A.diag = U.diag;
+    A.val = ctx->bval;
+    const double rtol = ctx->par.lin_rtol / std::sqrt((double)std::max(members, 1));
+    eft_status st = eft_fgmres_dev(ctx, &A, ctx->bR, ctx->bX, si, rtol);
+    if (st != EFT_OK && st != EFT_ENOTCONV) return st;
+    for (int q = 0; q < Q; ++q) {
+        const Band &B = ctx->band[U.band_of[q]];
+        EFT_TRY(eft_fill(ctx, ctx->tsc + TS_DN + q, 1, 0.0));
+        if (B.n > 0) {
+            double *dx = ctx->bX + U.roff[q] * bs;
+            if (scaled)
+                hipLaunchKernelGGL(k_scale_member, dim3(eft_grid(B.n * bs, 256)), dim3(256), 0, ctx->stream, B.n * bs,
+                                   dx, ctx->tsc + TS_NRM + q, 1);
+            hipLaunchKernelGGL(k_band_update, dim3(eft_grid(B.n * bs, 256)), dim3(256), 0, ctx->stream, B.n, bs,
+                               B.node, dx, x[q]);
+            EFT_TRY(eft_dot_dev(ctx, dx, dx, B.n * bs, ctx->tsc + TS_DN + q));
+        }
+        EFT_TRY(eft_dot_dev(ctx, x[q], x[q], xlen[q], ctx->tsc + TS_XN + q));
+    }
+    EFT_HIP(hipGetLastError());
+    EFT_HIP(hipMemcpyAsync(ctx->htsc + TS_DN, ctx->tsc + TS_DN, sizeof(double) * 256, hipMemcpyDeviceToHost,
+                           ctx->stream));
+    EFT_HIP(hipStreamSynchronize(ctx->stream));
+    for (int q = 0; q < Q; ++q)
+        ratio[q] = std::sqrt(ctx->htsc[TS_DN + q]) / std::max(std::sqrt(ctx->htsc[TS_XN + q]), 1e-300);
+    return st;
 }
 
 eft_status eft_transport_dev(eft_ctx *ctx, const eft_state *lvl, eft_iterate *it, eft_transport_info *info)
@@ -1044,49 +1180,53 @@ eft_status eft_transport_dev(eft_ctx *ctx, const eft_state *lvl, eft_iterate *it
         ctx->err = "eft_bands_build must run before the transport";
         return EFT_EINVAL;
     }
-    const int nv = ctx->nv;
+    const int nv = ctx->nv, K = ctx->n_ind, S = ctx->n_s;
     const int64_t N = ctx->N;
     eft_transport_info inf{};
-    inf.n_ind = ctx->n_ind;
-    inf.n_solid = ctx->n_s;
+    inf.n_ind = K;
+    inf.n_solid = S;
     eft_status worst = EFT_OK;
     EFT_TRY(eft_props(ctx, lvl, it));
-    for (int k = 0; k < ctx->n_ind; ++k) {
-        const Band &B = ctx->band[k];
-        inf.band_nodes[k] = B.n;
-        inf.band_elems[k] = B.ne;
-        double gb[2];
-        EFT_TRY(mobility_beta(ctx, lvl, it, k, gb));
-        inf.gamma[k] = gb[0];
-        inf.beta[k] = gb[1];
-        if (B.n == 0) continue;
-        EFT_TRY(assemble_ac(ctx, lvl, it, k));
+    std::vector<double> gb(2 * std::max(K, 1));
+    EFT_TRY(mobility_beta_all(ctx, lvl, it, gb.data()));
+    for (int k = 0; k < K; ++k) {
+        inf.band_nodes[k] = ctx->band[k].n;
+        inf.band_elems[k] = ctx->band[k].ne;
+        inf.gamma[k] = gb[2 * k];
+        inf.beta[k] = gb[2 * k + 1];
+    }
+    // every Allen-Cahn system, one batched solve
+    if (K > 0 && ctx->u_ac.n > 0) {
+        const eft_ctx::BandUnion &U = ctx->u_ac;
+        for (int k = 0; k < K; ++k)
+            if (ctx->band[k].n > 0)
+                EFT_TRY(assemble_ac(ctx, lvl, it, k, ctx->bR + U.roff[k], ctx->bval + U.noff[k], ctx->tsc + TS_GB + 2 * k));
+        std::vector<double *> x(K);
+        std::vector<int64_t> xl(K, N);
+        for (int k = 0; k < K; ++k) x[k] = it->phi + (int64_t)k * N;
         eft_solve_info si{};
-        double dn = 0.0;
-        eft_status st = band_solve(ctx, B, 1, it->phi + (int64_t)k * N, &dn, &si);
+        eft_status st = union_solve(ctx, U, 1, x, xl, inf.ratio, &si);
         if (st != EFT_OK && st != EFT_ENOTCONV) return st;
         if (st == EFT_ENOTCONV) worst = st;
-        inf.lin_iters[k] = si.iters;
-        double xn;
-        EFT_TRY(eft_norm2(ctx, it->phi + (int64_t)k * N, N, &xn));
-        inf.ratio[k] = dn / std::max(xn, 1e-300);
+        inf.ac_iters = si.iters;
+        for (int k = 0; k < K; ++k) inf.lin_iters[k] = ctx->band[k].n > 0 ? si.iters : 0;
     }
-    if (ctx->n_s > 0) {
-        EFT_TRY(eft_props(ctx, lvl, it));   // solid fractions from the new phi
-        for (int s = 0; s < ctx->n_s; ++s) {
-            const Band &B = ctx->band[ctx->solid_ind[s]];
-            if (B.n == 0) continue;
-            EFT_TRY(assemble_b(ctx, lvl, it, s));
-            eft_solve_info si{};
-            double dn = 0.0;
-            eft_status st = band_solve(ctx, B, nv, it->B + (int64_t)s * N * nv, &dn, &si);
-            if (st != EFT_OK && st != EFT_ENOTCONV) return st;
-            if (st == EFT_ENOTCONV) worst = st;
-            inf.lin_iters[ctx->n_ind + s] = si.iters;
-            double xn;
-            EFT_TRY(eft_norm2(ctx, it->B + (int64_t)s * N * nv, N * nv, &xn));
-            inf.ratio[ctx->n_ind + s] = dn / std::max(xn, 1e-300);
-        }
+    // every B system (solid fractions from the new phi), one batched solve
+    if (S > 0 && ctx->u_b.n > 0) {
+        EFT_TRY(eft_props(ctx, lvl, it));
+        const eft_ctx::BandUnion &U = ctx->u_b;
+        for (int sI = 0; sI < S; ++sI)
+            if (ctx->band[ctx->solid_ind[sI]].n > 0)
+                EFT_TRY(assemble_b(ctx, lvl, it, sI, ctx->bR + U.roff[sI] * nv, ctx->bval + U.noff[sI] * nv * nv));
+        std::vector<double *> x(S);
+        std::vector<int64_t> xl(S, N * nv);
+        for (int sI = 0; sI < S; ++sI) x[sI] = it->B + (int64_t)sI * N * nv;
+        eft_solve_info si{};
+        eft_status st = union_solve(ctx, U, nv, x, xl, inf.ratio + K, &si);
+        if (st != EFT_OK && st != EFT_ENOTCONV) return st;
+        if (st == EFT_ENOTCONV) worst = st;
+        inf.b_iters = si.iters;
+        for (int sI = 0; sI < S; ++sI) inf.lin_iters[K + sI] = ctx->band[ctx->solid_ind[sI]].n > 0 ? si.iters : 0;
     }
     if (info) *info = inf;
     return worst;
@@ -1114,10 +1254,13 @@ eft_status eft_band_system_dev(eft_ctx *ctx, const eft_state *lvl, const eft_ite
     EFT_TRY(eft_props(ctx, lvl, it));
     double gb[2] = {0.0, 0.0};
     if (kind == 0) {
-        EFT_TRY(mobility_beta(ctx, lvl, it, index, gb));
-        EFT_TRY(assemble_ac(ctx, lvl, it, index));
+        std::vector<double> all(2 * ctx->n_ind);
+        EFT_TRY(mobility_beta_all(ctx, lvl, it, all.data()));
+        gb[0] = all[2 * index];
+        gb[1] = all[2 * index + 1];
+        EFT_TRY(assemble_ac(ctx, lvl, it, index, ctx->bR, ctx->bval, ctx->tsc + TS_GB + 2 * index));
     } else {
-        EFT_TRY(assemble_b(ctx, lvl, it, index));
+        EFT_TRY(assemble_b(ctx, lvl, it, index, ctx->bR, ctx->bval));
     }
     if (gamma_beta) {
         gamma_beta[0] = gb[0];

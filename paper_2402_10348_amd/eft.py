@@ -65,7 +65,8 @@ class SolveInfo(C.Structure):
 class TransportInfo(C.Structure):
     _fields_ = [("n_ind", C.c_int32), ("n_solid", C.c_int32), ("gamma", C.c_double * 64),
                 ("beta", C.c_double * 64), ("band_nodes", C.c_int64 * 64), ("band_elems", C.c_int64 * 64),
-                ("lin_iters", C.c_int32 * 128), ("ratio", C.c_double * 128)]
+                ("lin_iters", C.c_int32 * 128), ("ratio", C.c_double * 128), ("ac_iters", C.c_int32),
+                ("b_iters", C.c_int32)]
 
 
 class StepInfo(C.Structure):
@@ -361,7 +362,8 @@ class Context:
         ni, ns = info.n_ind, info.n_solid
         return dict(status=st, gamma=list(info.gamma[:ni]), beta=list(info.beta[:ni]),
                     band_nodes=list(info.band_nodes[:ni]), band_elems=list(info.band_elems[:ni]),
-                    lin_iters=list(info.lin_iters[:ni + ns]), ratio=list(info.ratio[:ni + ns]))
+                    lin_iters=list(info.lin_iters[:ni + ns]), ratio=list(info.ratio[:ni + ns]),
+                    ac_iters=info.ac_iters, b_iters=info.b_iters)
 
     def step(self, st, t=0.0, step=0, dt=0.0):
         """Advance the device state dict in place by one time step."""
