@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--precond", type=int, default=1, help="1 multigrid V-cycle, 0 point-block Jacobi")
     ap.add_argument("--mg-nu", type=int, default=1, help="multigrid pre-smoothing sweeps (the first from zero)")
     ap.add_argument("--mg-nu-post", type=int, default=3, help="multigrid post-smoothing sweeps")
+    ap.add_argument("--mg-smoother", type=int, default=0, help="0 damped block Jacobi, 1 multicolour block Gauss-Seidel")
     ap.add_argument("--mg-omega", type=float, default=0.7)
     ap.add_argument("--mg-bf16", type=int, default=0, help="1: finest multigrid level's matrix copy in BF16")
     ap.add_argument("--kernel-role", type=int, default=1,
@@ -141,7 +142,8 @@ def run_mixed(args, prob, torch):
     stored and applied in FP32 inside the FP64 Newton/Krylov iteration."""
     from paper_2402_10348_amd.eft import Context
     ctx = Context(prob, lin_rtol=1e-8, restart=args.restart, lin_maxit=20000, precision=1, precond=args.precond,
-                  mg_nu=args.mg_nu, mg_omega=args.mg_omega, mg_nu_post=args.mg_nu_post)
+                  mg_nu=args.mg_nu, mg_omega=args.mg_omega, mg_nu_post=args.mg_nu_post,
+                  mg_smoother=args.mg_smoother)
     st = ctx.device_state(prob.state_copy())
     t_sim, step_no = 0.0, 0
     for _ in range(args.warmup):
@@ -300,7 +302,7 @@ def main():
     prob = W.cavity_sphere_3d(n=args.n)
     ctx = Context(prob, lin_rtol=1e-8, restart=args.restart, lin_maxit=20000, precision=args.precision,
                   precond=args.precond, mg_nu=args.mg_nu, mg_omega=args.mg_omega, mg_bf16=args.mg_bf16,
-                  mg_nu_post=args.mg_nu_post)
+                  mg_nu_post=args.mg_nu_post, mg_smoother=args.mg_smoother)
     st = ctx.device_state(prob.state_copy())
     log(args, f"[bench] {args.n}^3 cavity N={prob.n_nodes} E={prob.n_elems} precision={args.precision}")
     t_sim, step_no = 0.0, 0

@@ -111,6 +111,10 @@ typedef struct {
                                     diagonal blocks), 0 in FP32                    */
     int32_t mg_nu_post;          /* multigrid: smoothing sweeps after the coarse
                                     correction (1..8)                              */
+    int32_t mg_smoother;         /* multigrid: 0 damped node-block Jacobi; 1 node-
+                                    block Gauss-Seidel over the parity colours of
+                                    the Kuhn mesh (forward before, backward after
+                                    the coarse correction)                         */
 } eft_params;
 
 /* State at time level n (Sec. 2.1.2): values and rates.  DEVICE arrays. */

@@ -95,6 +95,10 @@ struct MGLevel {
     double *Dinv = nullptr;          // [N][bs*bs] (levels with FP64 values)
     float *Dinv32 = nullptr;         // [N][bs*bs] (the level with FP32 values)
     double *x = nullptr, *x2 = nullptr, *b = nullptr, *r = nullptr;  // [N*bs]
+    int32_t *crow = nullptr;         // rows ordered by parity colour (i%2, j%2, k%2)
+    int64_t coff[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // colour c: crow[coff[c] .. coff[c+1])
+    int64_t cnnz[8] = {0, 0, 0, 0, 0, 0, 0, 0};     // blocks of the rows of each colour
+    int ncolor = 0;
 };
 
 // Learned right preconditioner (not in the paper; the learned form of the

@@ -132,6 +132,49 @@ __global__ __launch_bounds__(256) void k_sweep_rows(int64_t n, const int32_t *__
     }
 }
 
+// Block Gauss-Seidel on the rows of one colour, in place:
+// x_r <- x_r + omega D_r^-1 (b - A x)_r for r in rows[0..nc).  No two rows of
+// a colour are neighbours, so the rows of one launch read only values of
+// other colours (or their own old value).
+template <int BS, typename TV, typename TD>
+__global__ __launch_bounds__(256) void k_gs_rows(int64_t nc, const int32_t *__restrict__ rows,
+                                                 const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                                 const TV *__restrict__ val, const TD *__restrict__ Dinv, double omega,
+                                                 const double *__restrict__ b, double *x, const int32_t *flag)
+{
+    if (*flag == 0) return;
+    const int64_t w = (int64_t)blockIdx.x * 4 + wave_id();
+    if (w * SWEEP_R >= nc) return;
+    int64_t row[SWEEP_R];
+#pragma unroll
+    for (int q = 0; q < SWEEP_R; ++q) row[q] = rows[w * SWEEP_R + q < nc ? w * SWEEP_R + q : w * SWEEP_R];
+    const int64_t n_end = w * SWEEP_R + SWEEP_R <= nc ? SWEEP_R : nc - w * SWEEP_R;   // valid rows of this wave
+    int k0[SWEEP_R], k1[SWEEP_R];
+#pragma unroll
+    for (int q = 0; q < SWEEP_R; ++q) {
+        k0[q] = q < n_end ? rowptr[row[q]] : 0;
+        k1[q] = q < n_end ? rowptr[row[q] + 1] : 0;
+    }
+    const int lane = threadIdx.x & 63;
+    const int rl = lane < BS ? lane : 0;
+    double br[SWEEP_R], xr[SWEEP_R], d[SWEEP_R][BS], ax[SWEEP_R];
+#pragma unroll
+    for (int q = 0; q < SWEEP_R; ++q) {
+        br[q] = b[row[q] * BS + rl];
+        xr[q] = x[row[q] * BS + rl];
+        RowLoad<BS, TD, false>::get(Dinv + (row[q] * BS + rl) * BS, d[q]);
+    }
+    bsr_rows_dot<BS, TV, SWEEP_R, true>(k0, k1, col, val, x, lane, ax);
+#pragma unroll
+    for (int q = 0; q < SWEEP_R; ++q) {
+        const double res = br[q] - ax[q];
+        double u = 0.0;
+#pragma unroll
+        for (int c = 0; c < BS; ++c) u += d[q][c] * __shfl(res, c, 64);
+        if (lane < BS && q < n_end) x[row[q] * BS + lane] = xr[q] + omega * u;
+    }
+}
+
 // x = omega D^-1 b (first sweep from x = 0)
 template <typename TD>
 __global__ __launch_bounds__(256) void k_sweep0(int64_t nd, int bs, const TD *__restrict__ Dinv, double omega,
@@ -502,6 +545,31 @@ eft_status eft_build_graph(int64_t N, int64_t E, int nn, const int32_t *conn, st
 
 // Build the coarse levels.  grid: cells per axis of the fine mesh (known to be
 // a structured Kuhn mesh); dmask0: Dirichlet dof bits of each fine node.
+// rows of a structured level ordered by parity colour; per colour the
+// number of rows and of matrix blocks (rowptr on the host)
+static eft_status colour_rows(eft_ctx *ctx, MGLevel &L, int d, const std::vector<int32_t> &rowptr)
+{
+    const int64_t n0 = L.n[0] + 1, n1 = L.n[1] + 1;
+    L.ncolor = 1 << d;
+    std::vector<int64_t> cnt(9, 0);
+    std::vector<int> colour(L.N);
+    for (int64_t p = 0; p < L.N; ++p) {
+        const int64_t i = p % n0, j = (p / n0) % n1, k = p / (n0 * n1);
+        colour[p] = (int)((i & 1) | ((j & 1) << 1) | ((k & 1) << 2));
+        cnt[colour[p] + 1] += 1;
+    }
+    for (int c = 0; c < 8; ++c) cnt[c + 1] += cnt[c];
+    std::vector<int32_t> rows(L.N);
+    std::vector<int64_t> pos(cnt.begin(), cnt.end());
+    for (int c = 0; c < 8; ++c) L.cnnz[c] = 0;
+    for (int64_t p = 0; p < L.N; ++p) {
+        rows[pos[colour[p]]++] = (int32_t)p;
+        L.cnnz[colour[p]] += rowptr[p + 1] - rowptr[p];
+    }
+    for (int c = 0; c <= 8; ++c) L.coff[c] = cnt[c];
+    return dput(ctx, &L.crow, rows);
+}
+
 eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<uint8_t> &dmask0)
 {
     const int d = ctx->dim, bs = ctx->bs, nv = ctx->nv, nn = d + 1;
@@ -518,6 +586,11 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
     EFT_TRY(dmal(ctx, &L0.x, ctx->N * bs));
     EFT_TRY(dmal(ctx, &L0.x2, ctx->N * bs));
     EFT_TRY(dmal(ctx, &L0.r, ctx->N * bs));
+    {
+        std::vector<int32_t> rp0(ctx->N + 1);
+        EFT_HIP(hipMemcpy(rp0.data(), ctx->J.rowptr, sizeof(int32_t) * (ctx->N + 1), hipMemcpyDeviceToHost));
+        EFT_TRY(colour_rows(ctx, L0, d, rp0));
+    }
     ctx->mg.push_back(L0);
     // level-0 coordinates on the host, to carry to the coarse levels
     std::vector<double> xyz0(ctx->N * d);
@@ -590,6 +663,7 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
         EFT_TRY(dmal(ctx, &C.x2, C.N * bs));
         EFT_TRY(dmal(ctx, &C.b, C.N * bs));
         EFT_TRY(dmal(ctx, &C.r, C.N * bs));
+        EFT_TRY(colour_rows(ctx, C, d, rowptr));
         inj_prev = inj;
         ctx->mg.push_back(C);
     }
@@ -643,6 +717,7 @@ void eft_mg_free(eft_ctx *ctx)
             fr(L.A.val); fr(L.b); fr(L.iptr); fr(L.ient);
         }
         fr(L.fmask); fr(L.Dinv); fr(L.Dinv32); fr(L.x); fr(L.x2); fr(L.r); fr(L.A.val32); fr(L.A.val16);
+        fr(L.crow);
     }
     ctx->mg.clear();
     fr(ctx->mg_dense);
@@ -820,6 +895,45 @@ void timed_sweep(eft_ctx *ctx, int l, const MGLevel &L, const double *b, const d
     eft_kt_end(ctx, slot, sweep_bytes(L.A), EFT_KT_SMOOTH);
 }
 
+template <typename TV, typename TD>
+void launch_gs(eft_ctx *ctx, const MGLevel &L, int c, const TV *val, const TD *Dinv, const double *b, double *x,
+               const int32_t *flag)
+{
+    const int64_t nc = L.coff[c + 1] - L.coff[c];
+    if (nc == 0) return;
+    const dim3 g(eft_grid(nc, 4 * SWEEP_R)), t(256);
+    const double om = ctx->par.mg_omega;
+    if (L.A.bs == 3)
+        hipLaunchKernelGGL((k_gs_rows<3, TV, TD>), g, t, 0, ctx->stream, nc, L.crow + L.coff[c], L.A.rowptr, L.A.col,
+                           val, Dinv, om, b, x, flag);
+    else
+        hipLaunchKernelGGL((k_gs_rows<4, TV, TD>), g, t, 0, ctx->stream, nc, L.crow + L.coff[c], L.A.rowptr, L.A.col,
+                           val, Dinv, om, b, x, flag);
+}
+
+// One Gauss-Seidel sweep over all colours (reverse order when backward), in
+// place on x; on the finest level every colour launch carries the timing hook
+// with its own algorithmic bytes
+void gs_sweep(eft_ctx *ctx, int l, const MGLevel &L, const double *b, double *x, const int32_t *flag, bool backward)
+{
+    const int bs = L.A.bs;
+    for (int cc = 0; cc < L.ncolor; ++cc) {
+        const int c = backward ? L.ncolor - 1 - cc : cc;
+        const int64_t nc = L.coff[c + 1] - L.coff[c];
+        const double vb = L.A.bf16 ? 2.0 : L.A.fp32 ? 4.0 : 8.0, db = (L.A.bf16 || L.A.fp32) ? 4.0 : 8.0;
+        const double bytes = (double)L.cnnz[c] * (bs * bs * vb + 4.0) + (double)nc * (4.0 + 8.0 + bs * bs * db) +
+                             (double)nc * 3.0 * bs * 8.0;
+        const int64_t slot = l == 0 ? eft_kt_begin(ctx, EFT_KT_SMOOTH) : -1;
+        if (L.A.bf16)
+            launch_gs<eft_bf16, float>(ctx, L, c, reinterpret_cast<const eft_bf16 *>(L.A.val16), L.Dinv32, b, x, flag);
+        else if (L.A.fp32)
+            launch_gs<float, float>(ctx, L, c, L.A.val32, L.Dinv32, b, x, flag);
+        else
+            launch_gs<double, double>(ctx, L, c, L.A.val, L.Dinv, b, x, flag);
+        eft_kt_end(ctx, slot, bytes, EFT_KT_SMOOTH);
+    }
+}
+
 void resid(eft_ctx *ctx, const eft_matrix &A, const double *b, const double *x, double *r, const int32_t *flag)
 {
     if (A.bf16) launch_resid<eft_bf16>(ctx, A, reinterpret_cast<const eft_bf16 *>(A.val16), b, x, r, flag);
@@ -842,11 +956,17 @@ double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag, double
                            ctx->mg_free, nd, b, cur, flag);
         return cur;
     }
+    const bool gs = ctx->par.mg_smoother == 1 && L.ncolor > 0;
+    if (gs && out) cur = out;   // in-place smoothing works on the output directly
     sweep0(ctx, L, b, cur, flag);
     const int nu = last ? 40 : ctx->par.mg_nu;
     for (int s = 1; s < nu; ++s) {
-        timed_sweep(ctx, l, L, b, cur, oth, flag);
-        std::swap(cur, oth);
+        if (gs) {
+            gs_sweep(ctx, l, L, b, cur, flag, false);
+        } else {
+            timed_sweep(ctx, l, L, b, cur, oth, flag);
+            std::swap(cur, oth);
+        }
     }
     if (last) return cur;
     MGLevel &C = ctx->mg[l + 1];
@@ -862,6 +982,10 @@ double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag, double
     hipLaunchKernelGGL(k_prolong, dim3(eft_grid(L.N, 256)), dim3(256), 0, ctx->stream, cd, fd, bs, C.fmask, L.fmask, xc,
                        cur, flag);
     const int npost = ctx->par.mg_nu_post;
+    if (gs) {
+        for (int s = 0; s < npost; ++s) gs_sweep(ctx, l, L, b, cur, flag, true);
+        return cur;
+    }
     for (int s = 0; s < npost; ++s) {
         double *dst = (out && s + 1 == npost) ? out : oth;
         timed_sweep(ctx, l, L, b, cur, dst, flag);

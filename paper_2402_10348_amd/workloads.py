@@ -158,6 +158,7 @@ class Params:
     mg_omega: float = 0.7
     mg_bf16: int = 0
     mg_nu_post: int = 3
+    mg_smoother: int = 0      # 0 damped block Jacobi, 1 multicolour block Gauss-Seidel
 
 
 @dataclass

@@ -131,6 +131,18 @@ def test_multigrid_preconditioner_same_solution(torch_cuda, name, n):
         ctx.close()
     assert relnorm(res[1][0], res[0][0]) < 1e-7
     assert res[1][1] * 3 < res[0][1]
+    # the multicolour Gauss-Seidel smoother reaches the same solution
+    ctx = ctx_for(prob, precond=1, mg_smoother=1, mg_omega=1.0, mg_nu=2, mg_nu_post=2, lin_rtol=1e-11,
+                  restart=200, lin_maxit=20000)
+    R = ctx.assemble(ctx.device_state(lvl), ctx.device_state(it))
+    x, info = ctx.fgmres(-R)
+    r = -R - ctx.spmv(x)
+    rel = float(torch.linalg.norm(r) / torch.linalg.norm(R))
+    say(f"  Gauss-Seidel smoother iters={info['iters']} rel_res={rel:.2e}")
+    assert info["converged"] == 1 and rel <= 1.0001e-11
+    assert relnorm(to_np(x), res[0][0]) < 1e-7
+    assert info["iters"] * 3 < res[0][1]
+    ctx.close()
 
 
 def test_kernel_timer_counts(torch_cuda):
