@@ -30,11 +30,16 @@ import numpy as np
 # ---------------------------------------------------------------- mesh ----
 
 
-def box_mesh(dim: int, n, lo=None, hi=None):
+def box_mesh(dim: int, n, lo=None, hi=None, mirror_z: bool = False):
     """Structured simplex mesh of a box.
 
     Returns ``xyz`` float64 [N][dim], ``conn`` int32 [E][dim+1] (positive
     orientation) and ``grid`` int32 [3] (cell counts; 1 for unused axes).
+    3D cells are split into the 6 Kuhn tetrahedra along the cell diagonal
+    (0,0,0)-(1,1,1); with mirror_z the cells of the upper half (k >= nz/2) use
+    the split reflected in z (diagonal (0,0,1)-(1,1,0)), which keeps the mesh
+    conforming (the mid-plane faces keep their x-y diagonal) and makes it
+    symmetric under z -> 1 - z.
     """
     n = [int(v) for v in n]
     assert len(n) == dim
@@ -58,19 +63,21 @@ def box_mesh(dim: int, n, lo=None, hi=None):
         sx, sy = 1, n[0] + 1
         sz = (n[0] + 1) * (n[1] + 1)
         k, j, i = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
-        v0 = (i * sx + j * sy + k * sz).ravel()
-        step = [sx, sy, sz]
+        up = (k >= n[2] // 2).ravel() if mirror_z else np.zeros(k.size, dtype=bool)
+        # start corner and z step of every cell (reflected cells start on top)
+        v0 = (i * sx + j * sy + k * sz).ravel() + np.where(up, sz, 0)
+        zs = np.where(up, -sz, sz)
         tets = []
         for perm in itertools.permutations(range(3)):
-            a = v0 + step[perm[0]]
-            b = a + step[perm[1]]
-            c = b + step[perm[2]]
-            # parity of the permutation decides the orientation
+            steps = [np.full(v0.shape, sx), np.full(v0.shape, sy), zs]
+            a = v0 + steps[perm[0]]
+            b = a + steps[perm[1]]
+            c = b + steps[perm[2]]
+            # parity of the permutation decides the orientation; a reflected
+            # cell has the opposite one
             inv = sum(1 for x in range(3) for y in range(x + 1, 3) if perm[x] > perm[y])
-            if inv % 2 == 0:
-                tets.append(np.stack([v0, a, b, c], axis=1))
-            else:
-                tets.append(np.stack([v0, b, a, c], axis=1))
+            even = (inv % 2 == 0) != up
+            tets.append(np.where(even[:, None], np.stack([v0, a, b, c], axis=1), np.stack([v0, b, a, c], axis=1)))
         conn = np.stack(tets, axis=1).reshape(-1, 4)
         grid = np.array(n, dtype=np.int32)
     else:
@@ -287,13 +294,13 @@ def cavity_disk_2d(n: int = 32, dt: float = 0.01, lin_rtol: float = 1e-10, nl_fi
 
 
 def cavity_sphere_3d(n: int = 64, dt: float = 0.005, lin_rtol: float = 1e-8, nl_fixed: int = 0,
-                     mu_L: float = 0.1, eps_h: float = 1.5) -> Problem:
+                     mu_L: float = 0.1, eps_h: float = 1.5, mirror_z: bool = False) -> Problem:
     """3D lid-driven cavity with one elastic sphere (r=0.2 at (0.6,0.5,0.5)).
 
     Fluid rho=1, mu=0.01; solid rho=1, mu=0.01, shear modulus mu_L; interface
     width eps = 1.5h; eta = 0.2; lid v_x = 1 on y = 1.
     """
-    xyz, conn, grid = box_mesh(3, (n, n, n))
+    xyz, conn, grid = box_mesh(3, (n, n, n), mirror_z=mirror_z)
     h = 1.0 / n
     eps = eps_h * h
     dirs = cavity_dirichlet(xyz, 3, lid_axis=1)

@@ -824,3 +824,40 @@ def test_row_subset_equals_full_assembly(name):
         cols, blocks = Js[q]
         assert np.array_equal(cols, col[rowptr[r]:rowptr[r + 1]])
         assert np.array_equal(blocks, J[rowptr[r]:rowptr[r + 1]])
+
+
+def test_cavity_step_is_symmetric_on_the_mirrored_mesh():
+    """The 3D cavity (lid along x on y = 1, sphere centred at z = 1/2) on the
+    z-mirrored Kuhn mesh is symmetric under z -> 1 - z: after a step v_x, v_y,
+    p, phi and B_xx, B_yy, B_zz, B_xy are even, v_z, B_yz, B_xz odd.  A
+    transposed operand, a wrong sign or an orientation-dependent term in any
+    block breaks it."""
+    n = 8
+    prob = W.cavity_sphere_3d(n=n, mirror_z=True, nl_fixed=2, lin_rtol=1e-13)
+    # the mesh itself is mirror symmetric
+    xyz = prob.xyz
+    flip = np.lexsort((xyz[:, 0], xyz[:, 1], 1.0 - xyz[:, 2]))
+    order = np.lexsort((xyz[:, 0], xyz[:, 1], xyz[:, 2]))
+    mirror = np.empty(prob.n_nodes, dtype=np.int64)
+    mirror[order] = flip
+    assert np.allclose(xyz[mirror, 2], 1.0 - xyz[:, 2]) and np.allclose(xyz[mirror, :2], xyz[:, :2])
+    tets = {tuple(sorted(t)) for t in prob.conn.tolist()}
+    assert {tuple(sorted(mirror[list(t)])) for t in tets} == tets
+    c = O.Case(prob, restart=200, lin_maxit=40000)
+    st = prob.state_copy()
+    info = c.step(st)
+    assert info["status"] == 0
+    vp, phi, B = st["vp"], st["phi"][0], st["B"][0]
+    scale_v = np.abs(vp[:, :3]).max()
+    even_v = [0, 1]
+    for k in even_v:
+        assert np.abs(vp[mirror, k] - vp[:, k]).max() <= 1e-9 * scale_v
+    assert np.abs(vp[mirror, 2] + vp[:, 2]).max() <= 1e-9 * scale_v
+    assert np.abs(vp[:, 2]).max() > 1e-6 * scale_v            # the odd part is not trivially zero
+    sp = np.abs(vp[:, 3] - vp[:, 3].mean()).max()
+    assert np.abs(vp[mirror, 3] - vp[:, 3]).max() <= 1e-9 * sp
+    assert np.abs(phi[mirror] - phi).max() <= 1e-10
+    # Voigt [11, 22, 33, 12, 23, 13]: 23 and 13 change sign under z -> -z
+    for comp, sign in zip(range(6), (1, 1, 1, 1, -1, -1)):
+        d = B[mirror, comp] - sign * B[:, comp]
+        assert np.abs(d).max() <= 1e-10, comp
