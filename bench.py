@@ -71,8 +71,8 @@ def log(args, *a):
         print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_NAME = {1: "k_sweep_rows<4, float, float> (fine-level multigrid smoother sweep, FP32 copy of the 4x4-block "
-                  "momentum Jacobian)",
+KERNEL_NAME = {1: "k_sweep_blk<4, float, float> (fine-level multigrid smoother sweep, FP32 copy of the 4x4-block "
+                  "momentum Jacobian, one block per lane)",
                2: "k_spmv_rows<4, double, true> (FP64 SpMV of the 4x4-block momentum Jacobian in FGMRES)",
                3: "k_ns_rows<3, double> (momentum/mass residual and Jacobian assembly, bytes: J and R written "
                   "once, connectivity and node fields read once)"}
@@ -167,7 +167,7 @@ def run_mixed(args, prob, torch):
 # HBM bytes per launch of the fine-level sweep from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE counters, with the hash of the kernel's sources when they were
 # taken: a changed kernel has no measured traffic.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_rows_cavity64_hbm_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_blk_cavity64_hbm_traffic.md")
 TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2402_10348_amd", "csrc", f) for f in ("bsr_rows.h", "k_mg.hip")]
 
 

@@ -13,6 +13,12 @@
 //
 // Blocks are stored row-major (value (i, c) of block k at k*bs*bs + i*bs + c)
 // and the value array starts 256-byte aligned.
+//
+// For narrow values (FP32, BF16) a second layout is faster: one block per
+// lane (bsr_block_dot).  There a lane's loads are a whole block, and x under
+// the block's column is gathered once per block instead of once per scalar
+// row, which halves the gather requests that bound the layout above when
+// the values are half as wide as x.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -190,4 +196,71 @@ __device__ __forceinline__ void bsr_rows_dot(const int (&k0)[R], const int (&k1)
             const double o = __shfl_down(acc[q], s * BS, 64);
             if (j + s < J) acc[q] += o;
         }
+}
+
+// ---------------------------------------------------------------------------
+// One block per lane.  The wavefront is split into segments of SEG lanes, one
+// block row per segment (64 / SEG consecutive rows per wavefront); lane j of a
+// segment takes blocks k0 + j, k0 + j + SEG, ... of its row whole, gathers the
+// bs entries of x once per block and accumulates all bs outputs.  A butterfly
+// over the segment leaves the row's product in every lane of the segment.
+
+// Lanes per segment: the 3D Kuhn pattern has <= 15 blocks per row, the 2D one
+// <= 7 (longer rows take further passes).
+template <int BS> struct BlockSeg {
+    static constexpr int SEG = BS <= 3 ? 8 : 16;
+    static constexpr int RPW = 64 / SEG;   // rows per wavefront
+};
+
+// Extents [k0, k1) of row row0 + q (q = the lane's segment) from the RPW + 1
+// wave-uniform row pointers at row0 (scalar loads; rows >= n are empty).
+template <int RPW>
+__device__ __forceinline__ void seg_extents(int64_t row0, int64_t n, const int32_t *__restrict__ rowptr, int q,
+                                            int &k0, int &k1)
+{
+    int rp[RPW + 1];
+#pragma unroll
+    for (int t = 0; t <= RPW; ++t) rp[t] = rowptr[row0 + t < n ? row0 + t : n];
+    k0 = rp[0];
+    k1 = rp[1];
+#pragma unroll
+    for (int t = 1; t < RPW; ++t)
+        if (q == t) {
+            k0 = rp[t];
+            k1 = rp[t + 1];
+        }
+}
+
+template <int BS, typename TV, int SEG>
+__device__ __forceinline__ void bsr_block_dot(int k0, int k1, const int32_t *__restrict__ col,
+                                              const TV *__restrict__ val, const double *__restrict__ x, int j,
+                                              double (&acc)[BS])
+{
+#pragma unroll
+    for (int i = 0; i < BS; ++i) acc[i] = 0.0;
+    for (int k = k0 + j; k < k1; k += SEG) {
+        const int c = col[k];
+        double v[BS][BS], xx[BS];
+#pragma unroll
+        for (int i = 0; i < BS; ++i) RowLoad<BS, TV, false>::get(val + (int64_t)k * (BS * BS) + i * BS, v[i]);
+        x_get<BS>(x, c, xx);
+#pragma unroll
+        for (int i = 0; i < BS; ++i)
+#pragma unroll
+            for (int e = 0; e < BS; ++e) acc[i] += v[i][e] * xx[e];
+    }
+#pragma unroll
+    for (int s = SEG / 2; s > 0; s >>= 1)
+#pragma unroll
+        for (int i = 0; i < BS; ++i) acc[i] += __shfl_xor(acc[i], s, 64);
+}
+
+// acc[i] for a runtime i < BS (selects, no scratch indexing)
+template <int BS> __device__ __forceinline__ double pick(const double (&a)[BS], int i)
+{
+    double r = a[0];
+#pragma unroll
+    for (int t = 1; t < BS; ++t)
+        if (i == t) r = a[t];
+    return r;
 }

@@ -23,7 +23,7 @@ namespace {
 // ------------------------------------------------------------- helpers ----
 
 struct Dims {
-    int n[3];   // cells per axis (1 for unused axes)
+    int n[3];   // cells per axis (0 for the unused axis in 2D)
 };
 
 __device__ __forceinline__ int64_t node_id(const Dims &d, int i, int j, int k)
@@ -132,6 +132,36 @@ __global__ __launch_bounds__(256) void k_sweep_rows(int64_t n, const int32_t *__
     }
 }
 
+// The same sweep with one block per lane (narrow values, bs 3 or 4): lane j
+// < bs of a row's segment finishes component j of the row.
+template <int BS, typename TV, typename TD>
+__global__ __launch_bounds__(256) void k_sweep_blk(int64_t n, const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                   const TD *__restrict__ Dinv, double omega,
+                                                   const double *__restrict__ b, const double *__restrict__ x,
+                                                   double *__restrict__ xo, const int32_t *flag)
+{
+    constexpr int SEG = BlockSeg<BS>::SEG, RPW = BlockSeg<BS>::RPW;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave_id()) * RPW;
+    if (*flag == 0 || row0 >= n) return;
+    const int lane = threadIdx.x & 63, q = lane / SEG, j = lane - q * SEG;
+    const int64_t row = row0 + q, rr = row < n ? row : row0;   // rr: in bounds, unused past n
+    const int jj = j < BS ? j : 0;
+    // row data of the update, loaded ahead of the product
+    double bb[BS], d[BS];
+    x_get<BS>(b, rr, bb);
+    RowLoad<BS, TD, false>::get(Dinv + (rr * BS + jj) * BS, d);
+    const double xr = x[rr * BS + jj];
+    int k0, k1;
+    seg_extents<RPW>(row0, n, rowptr, q, k0, k1);
+    double ax[BS];
+    bsr_block_dot<BS, TV, SEG>(k0, k1, col, val, x, j, ax);
+    double u = 0.0;
+#pragma unroll
+    for (int c = 0; c < BS; ++c) u += d[c] * (bb[c] - ax[c]);
+    if (j < BS && row < n) xo[row * BS + j] = xr + omega * u;
+}
+
 // Block Gauss-Seidel on the rows of one colour, in place:
 // x_r <- x_r + omega D_r^-1 (b - A x)_r for r in rows[0..nc).  No two rows of
 // a colour are neighbours, so the rows of one launch read only values of
@@ -219,27 +249,48 @@ __global__ __launch_bounds__(256) void k_resid_rows(int64_t n, const int32_t *__
         if (lane < BS && row[q] < n) r[row[q] * BS + lane] = br[q] - ax[q];
 }
 
+// r = b - A x with one block per lane (narrow values, bs 3 or 4)
+template <int BS, typename TV>
+__global__ __launch_bounds__(256) void k_resid_blk(int64_t n, const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                   const double *__restrict__ b, const double *__restrict__ x,
+                                                   double *__restrict__ r, const int32_t *flag)
+{
+    constexpr int SEG = BlockSeg<BS>::SEG, RPW = BlockSeg<BS>::RPW;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave_id()) * RPW;
+    if (*flag == 0 || row0 >= n) return;
+    const int lane = threadIdx.x & 63, q = lane / SEG, j = lane - q * SEG;
+    const int64_t row = row0 + q, rr = row < n ? row : row0;
+    const double br = b[rr * BS + (j < BS ? j : 0)];
+    int k0, k1;
+    seg_extents<RPW>(row0, n, rowptr, q, k0, k1);
+    double ax[BS];
+    bsr_block_dot<BS, TV, SEG>(k0, k1, col, val, x, j, ax);
+    if (j < BS && row < n) r[row * BS + j] = br - pick<BS>(ax, j);
+}
+
 // --------------------------------------------------------- transfers ------
 
 // coarse b[I] = sum over children i of I (fine nodes 2I + s, s in the Kuhn
 // stencil) of w(i, I) r[i], masked by the free dofs of both levels
 template <int D>
-__global__ __launch_bounds__(256) void k_restrict(Dims cd, Dims fd, int bs, const uint8_t *__restrict__ cmask,
+__global__ __launch_bounds__(256) void k_restrict(Dims cd, Dims fd, const uint8_t *__restrict__ cmask,
                                                   const uint8_t *__restrict__ fmask, const double *__restrict__ r,
                                                   double *__restrict__ bc, const int32_t *flag)
 {
+    constexpr int BS = D + 1;
     if (*flag == 0) return;
-    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t Nc = (int64_t)(cd.n[0] + 1) * (cd.n[1] + 1) * (cd.n[2] + 1);
-    if (I >= Nc) return;
-    const int ci = (int)(I % (cd.n[0] + 1));
-    const int cj = (int)((I / (cd.n[0] + 1)) % (cd.n[1] + 1));
-    const int ck = (int)(I / ((int64_t)(cd.n[0] + 1) * (cd.n[1] + 1)));
-    // all stencil points are visited unrolled, so their loads are in flight
-    // together (a rolled loop waits one memory latency per point)
-    double acc[8];
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nx = cd.n[0] + 1, ny = cd.n[1] + 1;
+    if (I >= nx * ny * (cd.n[2] + 1)) return;
+    const int ci = I % nx, cj = (I / nx) % ny, ck = I / (nx * ny);
+    // every load is issued unconditionally (index 0 and weight 0 outside the
+    // mesh, the Dirichlet mask applied by a select), so the loads of all
+    // stencil points are in flight together instead of one round trip per
+    // masked branch
+    double acc[BS];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+    for (int c = 0; c < BS; ++c) acc[c] = 0.0;
 #pragma unroll
     for (int s = 0; s < Stencil<D>::S; ++s) {
         int a, b, c3;
@@ -250,43 +301,39 @@ __global__ __launch_bounds__(256) void k_restrict(Dims cd, Dims fd, int bs, cons
         const double w = in ? (s == 0 ? 1.0 : 0.5) : 0.0;
         const int m = fmask[f];
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-            if (c < bs && ((m >> c) & 1)) acc[c] += w * r[f * bs + c];
+        for (int c = 0; c < BS; ++c) {
+            const double v = r[f * BS + c];
+            acc[c] += ((m >> c) & 1) ? w * v : 0.0;
+        }
     }
     const int mc = cmask[I];
 #pragma unroll
-    for (int c = 0; c < 8; ++c)
-        if (c < bs) bc[I * bs + c] = ((mc >> c) & 1) ? acc[c] : 0.0;
+    for (int c = 0; c < BS; ++c) bc[(int64_t)I * BS + c] = ((mc >> c) & 1) ? acc[c] : 0.0;
 }
 
 // x[i] += sum over parents I of i of w(i, I) xc[I] (free dofs only)
-__global__ __launch_bounds__(256) void k_prolong(Dims cd, Dims fd, int bs, const uint8_t *__restrict__ cmask,
+template <int D>
+__global__ __launch_bounds__(256) void k_prolong(Dims cd, Dims fd, const uint8_t *__restrict__ cmask,
                                                  const uint8_t *__restrict__ fmask, const double *__restrict__ xc,
                                                  double *__restrict__ x, const int32_t *flag)
 {
+    constexpr int BS = D + 1;
     if (*flag == 0) return;
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t Nf = (int64_t)(fd.n[0] + 1) * (fd.n[1] + 1) * (fd.n[2] + 1);
-    if (f >= Nf) return;
-    const int fi = (int)(f % (fd.n[0] + 1));
-    const int fj = (int)((f / (fd.n[0] + 1)) % (fd.n[1] + 1));
-    const int fk = (int)(f / ((int64_t)(fd.n[0] + 1) * (fd.n[1] + 1)));
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nx = fd.n[0] + 1, ny = fd.n[1] + 1;
+    if (f >= nx * ny * (fd.n[2] + 1)) return;
+    const int fi = f % nx, fj = (f / nx) % ny, fk = f / (nx * ny);
     const int64_t I0 = node_id(cd, fi >> 1, fj >> 1, fk >> 1);
     const bool mid = (fi & 1) | (fj & 1) | (fk & 1);
     const int64_t I1 = mid ? node_id(cd, (fi >> 1) + (fi & 1), (fj >> 1) + (fj & 1), (fk >> 1) + (fk & 1)) : I0;
     const int m = fmask[f];
     const int m0 = cmask[I0], m1 = cmask[I1];
-    for (int c = 0; c < bs; ++c) {
-        if (!((m >> c) & 1)) continue;
-        double v;
-        if (mid) {
-            const double a0 = ((m0 >> c) & 1) ? xc[I0 * bs + c] : 0.0;
-            const double a1 = ((m1 >> c) & 1) ? xc[I1 * bs + c] : 0.0;
-            v = 0.5 * (a0 + a1);
-        } else {
-            v = ((m0 >> c) & 1) ? xc[I0 * bs + c] : 0.0;
-        }
-        x[f * bs + c] += v;
+    const double w = mid ? 0.5 : 1.0;   // a node of the coarse mesh takes its own value once
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+        const double a0 = xc[I0 * BS + c], a1 = xc[I1 * BS + c], xv = x[(int64_t)f * BS + c];
+        const double v = ((m0 >> c) & 1 ? a0 : 0.0) + (mid && ((m1 >> c) & 1) ? a1 : 0.0);
+        x[(int64_t)f * BS + c] = ((m >> c) & 1) ? xv + w * v : xv;
     }
 }
 
@@ -374,6 +421,87 @@ __global__ __launch_bounds__(256) void k_gauss_jordan(double *M, double *Inv, in
         for (int i = t; i < nd; i += 256)
             if (i != k) M[(int64_t)i * nd + k] = 0.0;
         __syncthreads();
+    }
+}
+
+// The same inversion with the augmented matrix [M | I] resident in LDS (nd
+// up to GJ_LDS_MAX): no global memory round trip inside the pivot loop.
+constexpr int GJ_LDS_MAX = 88;
+inline size_t gj_lds_bytes(int nd) { return sizeof(double) * ((size_t)2 * nd * nd + nd); }
+
+__global__ __launch_bounds__(256) void k_gauss_jordan_lds(const double *__restrict__ M, double *__restrict__ Inv, int nd)
+{
+    extern __shared__ double sm[];
+    double *A = sm;                  // [nd][2 nd]
+    double *colk = sm + 2 * nd * nd; // [nd]
+    __shared__ double wv[4];
+    __shared__ int wi[4];
+    __shared__ int piv;
+    const int t = threadIdx.x, lane = t & 63, wv_id = t >> 6, W = 2 * nd;
+    for (int e = t; e < nd * W; e += 256) {
+        const int i = e / W, j = e - i * W;
+        A[e] = j < nd ? M[i * nd + j] : (j - nd == i ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    for (int k = 0; k < nd; ++k) {
+        // pivot: largest |A[i][k]| over i >= k (lowest i among equals)
+        double best = -1.0;
+        int bi = nd;
+        for (int i = k + t; i < nd; i += 256) {
+            const double a = fabs(A[i * W + k]);
+            if (a > best) {
+                best = a;
+                bi = i;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(best, o, 64);
+            const int oi = __shfl_xor(bi, o, 64);
+            if (ob > best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+            }
+        }
+        if (lane == 0) {
+            wv[wv_id] = best;
+            wi[wv_id] = bi;
+        }
+        __syncthreads();
+        if (t == 0) {
+            double b = wv[0];
+            int p = wi[0];
+            for (int w = 1; w < 4; ++w)
+                if (wv[w] > b || (wv[w] == b && wi[w] < p)) {
+                    b = wv[w];
+                    p = wi[w];
+                }
+            piv = p < nd ? p : k;
+        }
+        __syncthreads();
+        const int p = piv;
+        if (p != k)
+            for (int j = t; j < W; j += 256) {
+                const double a = A[k * W + j];
+                A[k * W + j] = A[p * W + j];
+                A[p * W + j] = a;
+            }
+        __syncthreads();
+        const double d = A[k * W + k];
+        const double inv = d != 0.0 ? 1.0 / d : 0.0;
+        for (int i = t; i < nd; i += 256) colk[i] = A[i * W + k];
+        __syncthreads();
+        for (int j = t; j < W; j += 256) A[k * W + j] *= inv;
+        __syncthreads();
+        for (int e = t; e < nd * W; e += 256) {
+            const int i = e / W, j = e - i * W;
+            if (i == k) continue;
+            A[e] = j == k ? 0.0 : A[e] - colk[i] * A[k * W + j];
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < nd * nd; e += 256) {
+        const int i = e / nd, j = e - i * nd;
+        Inv[e] = A[i * W + nd + j];
     }
 }
 
@@ -700,6 +828,9 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
         EFT_TRY(dput(ctx, &ctx->mg_free, fdof));
         EFT_TRY(dmal(ctx, &ctx->mg_dense, ctx->mg_nd * ctx->mg_nd));
         EFT_TRY(dmal(ctx, &ctx->mg_inv, ctx->mg_nd * ctx->mg_nd));
+        if (ctx->mg_nd <= GJ_LDS_MAX)
+            EFT_HIP(hipFuncSetAttribute((const void *)k_gauss_jordan_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)gj_lds_bytes(GJ_LDS_MAX)));
     }
     return EFT_OK;
 }
@@ -819,8 +950,12 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
         const MGLevel &Cc = ctx->mg.back();
         hipLaunchKernelGGL(k_dense_fill<double>, dim3(eft_grid(Cc.N, 64)), dim3(64), 0, ctx->stream, Cc.N, bs,
                            Cc.A.rowptr, Cc.A.col, Cc.A.val, ctx->mg_fidx, ctx->mg_dense, ctx->mg_nd);
-        hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(256), 0, ctx->stream, ctx->mg_dense, ctx->mg_inv,
-                           (int)ctx->mg_nd);
+        const int nd = (int)ctx->mg_nd;
+        if (nd <= GJ_LDS_MAX)
+            hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(1), dim3(256), gj_lds_bytes(nd), ctx->stream, ctx->mg_dense,
+                               ctx->mg_inv, nd);
+        else
+            hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(256), 0, ctx->stream, ctx->mg_dense, ctx->mg_inv, nd);
         EFT_HIP(hipGetLastError());
     }
     return EFT_OK;
@@ -832,7 +967,17 @@ template <typename TV, typename TD>
 void launch_sweep(eft_ctx *ctx, const eft_matrix &A, const TV *val, const TD *Dinv, double omega, const double *b,
                   const double *x, double *xo, const int32_t *flag)
 {
-    const dim3 g(eft_grid(A.n, 4 * SWEEP_R)), t(256);
+    const dim3 t(256);
+    if constexpr (sizeof(TV) < 8) {   // narrow values: one block per lane
+        if (A.bs == 3)
+            hipLaunchKernelGGL((k_sweep_blk<3, TV, TD>), dim3(eft_grid(A.n, 4 * BlockSeg<3>::RPW)), t, 0, ctx->stream,
+                               A.n, A.rowptr, A.col, val, Dinv, omega, b, x, xo, flag);
+        else
+            hipLaunchKernelGGL((k_sweep_blk<4, TV, TD>), dim3(eft_grid(A.n, 4 * BlockSeg<4>::RPW)), t, 0, ctx->stream,
+                               A.n, A.rowptr, A.col, val, Dinv, omega, b, x, xo, flag);
+        return;
+    }
+    const dim3 g(eft_grid(A.n, 4 * SWEEP_R));
     if (A.bs == 3)
         hipLaunchKernelGGL((k_sweep_rows<3, TV, TD>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, Dinv, omega, b,
                            x, xo, flag);
@@ -845,7 +990,17 @@ template <typename TV>
 void launch_resid(eft_ctx *ctx, const eft_matrix &A, const TV *val, const double *b, const double *x, double *r,
                   const int32_t *flag)
 {
-    const dim3 g(eft_grid(A.n, 4 * RESID_R)), t(256);
+    const dim3 t(256);
+    if constexpr (sizeof(TV) < 8) {   // narrow values: one block per lane
+        if (A.bs == 3)
+            hipLaunchKernelGGL((k_resid_blk<3, TV>), dim3(eft_grid(A.n, 4 * BlockSeg<3>::RPW)), t, 0, ctx->stream, A.n,
+                               A.rowptr, A.col, val, b, x, r, flag);
+        else
+            hipLaunchKernelGGL((k_resid_blk<4, TV>), dim3(eft_grid(A.n, 4 * BlockSeg<4>::RPW)), t, 0, ctx->stream, A.n,
+                               A.rowptr, A.col, val, b, x, r, flag);
+        return;
+    }
+    const dim3 g(eft_grid(A.n, 4 * RESID_R));
     if (A.bs == 3)
         hipLaunchKernelGGL((k_resid_rows<3, TV>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, b, x, r, flag);
     else
@@ -973,14 +1128,18 @@ double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag, double
     resid(ctx, A, b, cur, L.r, flag);
     const Dims fd = dims_of(L), cd = dims_of(C);
     if (ctx->dim == 2)
-        hipLaunchKernelGGL(k_restrict<2>, dim3(eft_grid(C.N, 256)), dim3(256), 0, ctx->stream, cd, fd, bs, C.fmask,
+        hipLaunchKernelGGL(k_restrict<2>, dim3(eft_grid(C.N, 256)), dim3(256), 0, ctx->stream, cd, fd, C.fmask,
                            L.fmask, L.r, C.b, flag);
     else
-        hipLaunchKernelGGL(k_restrict<3>, dim3(eft_grid(C.N, 256)), dim3(256), 0, ctx->stream, cd, fd, bs, C.fmask,
+        hipLaunchKernelGGL(k_restrict<3>, dim3(eft_grid(C.N, 256)), dim3(256), 0, ctx->stream, cd, fd, C.fmask,
                            L.fmask, L.r, C.b, flag);
     double *xc = vcycle(ctx, l + 1, C.b, flag);
-    hipLaunchKernelGGL(k_prolong, dim3(eft_grid(L.N, 256)), dim3(256), 0, ctx->stream, cd, fd, bs, C.fmask, L.fmask, xc,
-                       cur, flag);
+    if (ctx->dim == 2)
+        hipLaunchKernelGGL(k_prolong<2>, dim3(eft_grid(L.N, 256)), dim3(256), 0, ctx->stream, cd, fd, C.fmask, L.fmask,
+                           xc, cur, flag);
+    else
+        hipLaunchKernelGGL(k_prolong<3>, dim3(eft_grid(L.N, 256)), dim3(256), 0, ctx->stream, cd, fd, C.fmask, L.fmask,
+                           xc, cur, flag);
     const int npost = ctx->par.mg_nu_post;
     if (gs) {
         for (int s = 0; s < npost; ++s) gs_sweep(ctx, l, L, b, cur, flag, true);

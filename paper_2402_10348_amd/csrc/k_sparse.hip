@@ -3,8 +3,8 @@
 //
 // SpMV layout for bs = 3, 4, 6 (the momentum/mass system in 2D and 3D and
 // the 3D B system): one wavefront per block row, one lane per scalar row of
-// a block (bsr_rows.h).  Other bs: one value per lane, LDS reduction.  bs = 1
-// uses 16 lanes per row.
+// a block (bsr_rows.h); FP32 values of bs 3 and 4 take one block per lane.
+// Other bs: one value per lane, LDS reduction.  bs = 1 uses 16 lanes per row.
 #include "bsr_rows.h"
 #include "dev_common.h"
 #include "eft_internal.h"
@@ -36,6 +36,25 @@ __global__ __launch_bounds__(256) void k_spmv_rows(int64_t n, const int32_t *__r
 #pragma unroll
     for (int q = 0; q < SPMV_R; ++q)
         if (lane < BS && row[q] < n) y[row[q] * BS + lane] = acc[q];
+}
+
+// The same product with one block per lane (narrow values, bs 3 or 4).
+template <int BS, typename TV, bool GATED>
+__global__ __launch_bounds__(256) void k_spmv_blk(int64_t n, const int32_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                  const double *__restrict__ x, double *__restrict__ y,
+                                                  const int32_t *active)
+{
+    constexpr int SEG = BlockSeg<BS>::SEG, RPW = BlockSeg<BS>::RPW;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave_id()) * RPW;
+    if ((GATED && *active == 0) || row0 >= n) return;
+    const int lane = threadIdx.x & 63, q = lane / SEG, j = lane - q * SEG;
+    int k0, k1;
+    seg_extents<RPW>(row0, n, rowptr, q, k0, k1);
+    double acc[BS];
+    bsr_block_dot<BS, TV, SEG>(k0, k1, col, val, x, j, acc);
+    const int64_t row = row0 + q;
+    if (j < BS && row < n) y[row * BS + j] = pick<BS>(acc, j);
 }
 
 // general bs in 2..8: LDS reduction per wavefront.
@@ -92,7 +111,15 @@ template <int BS, typename TV>
 static void spmv_rows_launch(eft_ctx *ctx, int64_t n, const int32_t *rowptr, const int32_t *col, const TV *val,
                              const double *x, double *y, const int32_t *active)
 {
-    if (active)
+    if constexpr (sizeof(TV) < 8 && BS <= 4) {
+        const dim3 g(eft_grid(n, 4 * BlockSeg<BS>::RPW));
+        if (active)
+            hipLaunchKernelGGL((k_spmv_blk<BS, TV, true>), g, dim3(256), 0, ctx->stream, n, rowptr, col, val, x, y,
+                               active);
+        else
+            hipLaunchKernelGGL((k_spmv_blk<BS, TV, false>), g, dim3(256), 0, ctx->stream, n, rowptr, col, val, x, y,
+                               active);
+    } else if (active)
         hipLaunchKernelGGL((k_spmv_rows<BS, TV, true>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream, n,
                            rowptr, col, val, x, y, active);
     else

@@ -793,7 +793,9 @@ static eft_status grow(eft_ctx *ctx, void **p, int64_t bytes, int64_t *cap_bytes
     if (*p) (void)hipFree(*p);
     *p = nullptr;
     *cap_bytes = 0;
-    const int64_t want = std::max<int64_t>(bytes + bytes / 4, 1024);
+    // bands move and grow from step to step: twice the size asked for keeps
+    // reallocations (each a device synchronization) rare
+    const int64_t want = std::max<int64_t>(2 * bytes, 1024);
     if (hipMalloc(p, want) != hipSuccess) {
         ctx->err = "out of device memory (band)";
         return EFT_ENOMEM;
@@ -810,7 +812,7 @@ eft_status eft_reserve_band_sys(eft_ctx *ctx, int64_t n, int64_t nnz)
         if (ctx->bX) (void)hipFree(ctx->bX);
         if (ctx->tnum) (void)hipFree(ctx->tnum);
         if (ctx->tden) (void)hipFree(ctx->tden);
-        const int64_t c = n + n / 4 + 64;
+        const int64_t c = 2 * n + 64;
         if (hipMalloc(&ctx->bR, sizeof(double) * c * nv) != hipSuccess ||
             hipMalloc(&ctx->bX, sizeof(double) * c * nv) != hipSuccess ||
             hipMalloc(&ctx->tnum, sizeof(double) * c) != hipSuccess ||
@@ -822,7 +824,7 @@ eft_status eft_reserve_band_sys(eft_ctx *ctx, int64_t n, int64_t nnz)
     }
     if (nnz > ctx->bcap_nnz) {
         if (ctx->bval) (void)hipFree(ctx->bval);
-        const int64_t c = nnz + nnz / 4 + 64;
+        const int64_t c = 2 * nnz + 64;
         if (hipMalloc(&ctx->bval, sizeof(double) * c * nv * nv) != hipSuccess) {
             ctx->err = "out of device memory (band matrix)";
             return EFT_ENOMEM;
@@ -849,7 +851,7 @@ static eft_status build_union(eft_ctx *ctx, eft_ctx::BandUnion &U, const std::ve
         if (U.diag) (void)hipFree(U.diag);
         U.rowptr = U.diag = nullptr;
         U.cap_n = 0;
-        const int64_t c = n + n / 4 + 64;
+        const int64_t c = 2 * n + 64;
         if (hipMalloc(&U.rowptr, sizeof(int32_t) * c) != hipSuccess || hipMalloc(&U.diag, sizeof(int32_t) * c) != hipSuccess) {
             ctx->err = "out of device memory (band union)";
             return EFT_ENOMEM;
@@ -860,7 +862,7 @@ static eft_status build_union(eft_ctx *ctx, eft_ctx::BandUnion &U, const std::ve
         if (U.col) (void)hipFree(U.col);
         U.col = nullptr;
         U.cap_nnz = 0;
-        const int64_t c = nnz + nnz / 4 + 64;
+        const int64_t c = 2 * nnz + 64;
         if (hipMalloc(&U.col, sizeof(int32_t) * c) != hipSuccess) {
             ctx->err = "out of device memory (band union)";
             return EFT_ENOMEM;
@@ -935,9 +937,7 @@ eft_status eft_bands_build_dev(eft_ctx *ctx, const double *phi_n)
         int64_t nnz = 0;
         // exclusive scan of the row counts, in place (rowptr[n] = total)
         EFT_TRY(scan_compact<int32_t>(ctx, B.rowptr, n, B.rowptr, nullptr, nullptr, &nnz));
-        int32_t nnz32 = (int32_t)nnz;
-        EFT_HIP(hipMemcpyAsync(B.rowptr + n, &nnz32, sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
-        EFT_HIP(hipStreamSynchronize(ctx->stream));
+        hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, ctx->stream, B.rowptr + n, (int32_t)nnz);
         B.nnz = nnz;
         EFT_TRY(grow(ctx, (void **)&B.col, sizeof(int32_t) * std::max<int64_t>(nnz, 1), &caps[5]));
         EFT_TRY(grow(ctx, (void **)&B.epos, sizeof(int32_t) * std::max<int64_t>(ne, 1) * NN * NN, &caps[6]));
