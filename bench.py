@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--mg-nu", type=int, default=1, help="multigrid pre-smoothing sweeps (the first from zero)")
     ap.add_argument("--mg-nu-post", type=int, default=3, help="multigrid post-smoothing sweeps")
     ap.add_argument("--mg-smoother", type=int, default=0, help="0 damped block Jacobi, 1 multicolour block Gauss-Seidel")
+    ap.add_argument("--band-sweeps", type=int, default=None,
+                    help="damped block-Jacobi sweeps preconditioning the Allen-Cahn and B systems")
+    ap.add_argument("--band-omega", type=float, default=None)
     ap.add_argument("--mg-omega", type=float, default=0.7)
     ap.add_argument("--mg-bf16", type=int, default=0, help="1: finest multigrid level's matrix copy in BF16")
     ap.add_argument("--kernel-role", type=int, default=1,
@@ -64,6 +67,16 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
+
+
+def band_over(args):
+    """Band-system preconditioner settings given on the command line."""
+    o = {}
+    if args.band_sweeps is not None:
+        o["band_sweeps"] = args.band_sweeps
+    if args.band_omega is not None:
+        o["band_omega"] = args.band_omega
+    return o
 
 
 def log(args, *a):
@@ -143,7 +156,7 @@ def run_mixed(args, prob, torch):
     from paper_2402_10348_amd.eft import Context
     ctx = Context(prob, lin_rtol=1e-8, restart=args.restart, lin_maxit=20000, precision=1, precond=args.precond,
                   mg_nu=args.mg_nu, mg_omega=args.mg_omega, mg_nu_post=args.mg_nu_post,
-                  mg_smoother=args.mg_smoother)
+                  mg_smoother=args.mg_smoother, **band_over(args))
     st = ctx.device_state(prob.state_copy())
     t_sim, step_no = 0.0, 0
     for _ in range(args.warmup):
@@ -302,7 +315,7 @@ def main():
     prob = W.cavity_sphere_3d(n=args.n)
     ctx = Context(prob, lin_rtol=1e-8, restart=args.restart, lin_maxit=20000, precision=args.precision,
                   precond=args.precond, mg_nu=args.mg_nu, mg_omega=args.mg_omega, mg_bf16=args.mg_bf16,
-                  mg_nu_post=args.mg_nu_post, mg_smoother=args.mg_smoother)
+                  mg_nu_post=args.mg_nu_post, mg_smoother=args.mg_smoother, **band_over(args))
     st = ctx.device_state(prob.state_copy())
     log(args, f"[bench] {args.n}^3 cavity N={prob.n_nodes} E={prob.n_elems} precision={args.precision}")
     t_sim, step_no = 0.0, 0

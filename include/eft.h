@@ -115,6 +115,11 @@ typedef struct {
                                     block Gauss-Seidel over the parity colours of
                                     the Kuhn mesh (forward before, backward after
                                     the coarse correction)                         */
+    int32_t band_sweeps;         /* preconditioner of the Allen-Cahn and B band
+                                    systems: this many damped point-block Jacobi
+                                    sweeps from z = 0 (1..8; 1 with band_omega = 1
+                                    is plain point-block Jacobi)                    */
+    double band_omega;           /* damping of those sweeps (0 < omega <= 1.5)      */
 } eft_params;
 
 /* State at time level n (Sec. 2.1.2): values and rates.  DEVICE arrays. */

@@ -122,9 +122,10 @@ eft_status check_params(eft_ctx *ctx, const eft_params *p)
         p->rho_inf > 1.0 || (p->precision != 0 && p->precision != 1) || (p->precond < 0 || p->precond > 2) ||
         p->mg_nu < 1 || p->mg_nu > 8 || !(p->mg_omega > 0.0) || p->mg_omega > 1.5 ||
         (p->mg_bf16 != 0 && p->mg_bf16 != 1) || p->mg_nu_post < 1 || p->mg_nu_post > 8 ||
-        (p->mg_smoother != 0 && p->mg_smoother != 1)) {
+        (p->mg_smoother != 0 && p->mg_smoother != 1) || p->band_sweeps < 1 || p->band_sweeps > 8 ||
+        !(p->band_omega > 0.0 && p->band_omega <= 1.5)) {
         ctx->err = "invalid eft_params (dt, eta, lin_rtol > 0; 1 <= restart <= 512; band_cell >= 1; "
-                   "0 <= rho_inf <= 1; precision 0/1; precond 0/1/2; 1 <= mg_nu <= 8; 0 < mg_omega <= 1.5; mg_bf16 0/1; 1 <= mg_nu_post <= 8; mg_smoother 0/1)";
+                   "0 <= rho_inf <= 1; precision 0/1; precond 0/1/2; 1 <= mg_nu <= 8; 0 < mg_omega <= 1.5; mg_bf16 0/1; 1 <= mg_nu_post <= 8; mg_smoother 0/1; 1 <= band_sweeps <= 8; 0 < band_omega <= 1.5)";
         return EFT_EINVAL;
     }
     return EFT_OK;

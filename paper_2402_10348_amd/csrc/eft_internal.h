@@ -285,6 +285,10 @@ eft_status eft_bj_setup(eft_ctx *ctx, const eft_matrix *A, double *Dinv);
 eft_status eft_bj_setup32(eft_ctx *ctx, const eft_matrix *A, float *Dinv);
 eft_status eft_bj_apply(eft_ctx *ctx, int bs, int64_t n, const double *Dinv, const double *x, double *z,
                         const int32_t *active);
+// z = M v with M = `sweeps` damped point-block Jacobi sweeps from z = 0
+// (tmp: scratch of the size of v; sweeps = 1, omega = 1 is block Jacobi)
+eft_status eft_jacobi_apply(eft_ctx *ctx, const eft_matrix *A, const double *Dinv, const double *v, double *z,
+                            double *tmp, int sweeps, double omega, const int32_t *active);
 eft_status eft_spmv_flag(eft_ctx *ctx, const eft_matrix *A, const double *x, double *y, const int32_t *active);
 
 // k_krylov.hip

@@ -380,8 +380,11 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
                     EFT_TRY(eft_mg_vcycle(ctx, vj, zj, K.flag));
                 else if (learned)
                     EFT_TRY(eft_nn_precond(ctx, K.Dinv, vj, zj, K.flag));
-                else
+                else if (A == &ctx->J)
                     EFT_TRY(eft_bj_apply(ctx, bs, n, K.Dinv, vj, zj, K.flag));
+                else   // band systems (w is free until the product below)
+                    EFT_TRY(eft_jacobi_apply(ctx, A, K.Dinv, vj, zj, K.w, ctx->par.band_sweeps, ctx->par.band_omega,
+                                             K.flag));
                 const int64_t slot = A == &ctx->J ? eft_kt_begin(ctx, EFT_KT_SPMV) : -1;
                 EFT_TRY(eft_spmv_flag(ctx, A, zj, K.w, K.flag));
                 eft_kt_end(ctx, slot, spmv_bytes(A), EFT_KT_SPMV);

@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) void k_bj_setup(int64_t n, int bs, const int32
         for (int j = 0; j < bs; ++j) out[i * bs + j] = (TD)(ok ? I[i][j] : (i == j ? 1.0 : 0.0));
 }
 
-__global__ __launch_bounds__(256) void k_bj_apply(int64_t nd, int bs, const double *__restrict__ Dinv,
+__global__ __launch_bounds__(256) void k_bj_apply(int64_t nd, int bs, const double *__restrict__ Dinv, double omega,
                                                   const double *__restrict__ x, double *__restrict__ z,
                                                   const int32_t *active)
 {
@@ -226,7 +226,67 @@ __global__ __launch_bounds__(256) void k_bj_apply(int64_t nd, int bs, const doub
     const double *xr = x + r * bs;
     double s = 0.0;
     for (int c = 0; c < bs; ++c) s += D[c] * xr[c];
-    z[t] = s;
+    z[t] = omega * s;
+}
+
+// One damped point-block Jacobi sweep zo = z + omega D^-1 (v - A z) (FP64).
+// bs = 1: 16 lanes per row as the scalar product.
+__global__ __launch_bounds__(256) void k_jsweep1(int64_t n, const int32_t *__restrict__ rowptr,
+                                                 const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                 const double *__restrict__ Dinv, double omega,
+                                                 const double *__restrict__ v, const double *__restrict__ z,
+                                                 double *__restrict__ zo, const int32_t *active)
+{
+    if (*active == 0) return;
+    const int sub = threadIdx.x & 15;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    double acc = 0.0;
+    if (row < n) {
+        const int k0 = rowptr[row], k1 = rowptr[row + 1];
+        for (int k = k0 + sub; k < k1; k += 16) acc += val[k] * z[col[k]];
+    }
+    acc += __shfl_xor(acc, 1, 16);
+    acc += __shfl_xor(acc, 2, 16);
+    acc += __shfl_xor(acc, 4, 16);
+    acc += __shfl_xor(acc, 8, 16);
+    if (row < n && sub == 0) zo[row] = z[row] + omega * Dinv[row] * (v[row] - acc);
+}
+
+// bs in {3, 6}: SPMV_R block rows per wavefront (bsr_rows.h), lanes 0..bs-1
+// finish the rows.
+template <int BS>
+__global__ __launch_bounds__(256) void k_jsweep_rows(int64_t n, const int32_t *__restrict__ rowptr,
+                                                     const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                     const double *__restrict__ Dinv, double omega,
+                                                     const double *__restrict__ v, const double *__restrict__ z,
+                                                     double *__restrict__ zo, const int32_t *active)
+{
+    const int64_t w = (int64_t)blockIdx.x * 4 + wave_id();
+    int64_t row[SPMV_R];
+#pragma unroll
+    for (int q = 0; q < SPMV_R; ++q) row[q] = w * SPMV_R + q;
+    int k0[SPMV_R], k1[SPMV_R];
+    row_extents<SPMV_R>(row, n, rowptr, k0, k1);
+    if (*active == 0 || row[0] >= n) return;
+    const int lane = threadIdx.x & 63;
+    const int rl = lane < BS ? lane : 0;
+    double vr[SPMV_R], zr[SPMV_R], d[SPMV_R][BS], az[SPMV_R];
+#pragma unroll
+    for (int q = 0; q < SPMV_R; ++q) {
+        const int64_t rr = row[q] < n ? row[q] : row[0];
+        vr[q] = v[rr * BS + rl];
+        zr[q] = z[rr * BS + rl];
+        RowLoad<BS, double, false>::get(Dinv + (rr * BS + rl) * BS, d[q]);
+    }
+    bsr_rows_dot<BS, double, SPMV_R, false>(k0, k1, col, val, z, lane, az);
+#pragma unroll
+    for (int q = 0; q < SPMV_R; ++q) {
+        const double res = vr[q] - az[q];
+        double u = 0.0;
+#pragma unroll
+        for (int c = 0; c < BS; ++c) u += d[q][c] * __shfl(res, c, 64);
+        if (lane < BS && row[q] < n) zo[row[q] * BS + lane] = zr[q] + omega * u;
+    }
 }
 
 template <typename TD> static eft_status bj_setup(eft_ctx *ctx, const eft_matrix *A, TD *Dinv)
@@ -261,7 +321,42 @@ eft_status eft_bj_apply(eft_ctx *ctx, int bs, int64_t n, const double *Dinv, con
 {
     const int64_t nd = n * bs;
     if (nd == 0) return EFT_OK;
-    hipLaunchKernelGGL(k_bj_apply, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, nd, bs, Dinv, x, z, active);
+    hipLaunchKernelGGL(k_bj_apply, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, nd, bs, Dinv, 1.0, x, z,
+                       active);
+    EFT_HIP(hipGetLastError());
+    return EFT_OK;
+}
+
+eft_status eft_jacobi_apply(eft_ctx *ctx, const eft_matrix *A, const double *Dinv, const double *v, double *z,
+                            double *tmp, int sweeps, double omega, const int32_t *active)
+{
+    const int bs = A->bs;
+    const int64_t n = A->n, nd = n * bs;
+    if (nd == 0) return EFT_OK;
+    const bool sweepable = !A->fp32 && (bs == 1 || bs == 3 || bs == 6);
+    if (sweeps < 1 || (sweeps > 1 && !sweepable)) {
+        ctx->err = "Jacobi sweeps need FP64 values and bs 1, 3 or 6";
+        return EFT_EINVAL;
+    }
+    // sweep s writes z when (sweeps - 1 - s) is even, tmp otherwise, so the
+    // last one ends in z
+    double *buf[2] = {z, tmp};
+    double *cur = buf[(sweeps - 1) & 1];
+    hipLaunchKernelGGL(k_bj_apply, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, nd, bs, Dinv, omega, v, cur,
+                       active);
+    for (int s = 1; s < sweeps; ++s) {
+        double *nxt = buf[(sweeps - 1 - s) & 1];
+        if (bs == 1)
+            hipLaunchKernelGGL(k_jsweep1, dim3(eft_grid(n, 16)), dim3(256), 0, ctx->stream, n, A->rowptr, A->col,
+                               A->val, Dinv, omega, v, cur, nxt, active);
+        else if (bs == 3)
+            hipLaunchKernelGGL(k_jsweep_rows<3>, dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream, n,
+                               A->rowptr, A->col, A->val, Dinv, omega, v, cur, nxt, active);
+        else
+            hipLaunchKernelGGL(k_jsweep_rows<6>, dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream, n,
+                               A->rowptr, A->col, A->val, Dinv, omega, v, cur, nxt, active);
+        cur = nxt;
+    }
     EFT_HIP(hipGetLastError());
     return EFT_OK;
 }

@@ -385,6 +385,62 @@ __device__ __forceinline__ void band_rows_out(const TrArgs &a, int64_t r0, int64
     }
 }
 
+// Accumulator of one B-system block in LDS: s1, then M[i][k] (D x D).
+template <int D> struct BAcc {
+    static constexpr int N = 1 + D * D;
+    static constexpr int P = N | 1;   // odd stride
+};
+
+// Block (c, cc) of the B tangent from its accumulator: s1 delta(c, cc) -
+// LE(M)[c][cc], LE(M)[c][cc] = (M E + E M^T)_{ij} for the symmetric unit
+// direction E of Voigt index cc and (i, j) the pair of Voigt index c.
+template <int D>
+__device__ __forceinline__ double b_block_entry(const double *acc, int c, int cc)
+{
+    int i, j, k, l;
+    vpair<D>(c, i, j);
+    vpair<D>(cc, k, l);
+    const double *M = acc + 1;
+    double s = 0.0;
+    if (l == j) s += M[i * D + k];
+    if (k == j && k != l) s += M[i * D + l];
+    if (l == i) s += M[j * D + k];
+    if (k == i && k != l) s += M[j * D + l];
+    return (c == cc ? acc[0] : 0.0) - s;
+}
+
+// Rows [r0, r1) of the B system out of LDS (blocks expanded from their
+// accumulators, one block per thread).
+template <int D>
+__device__ __forceinline__ void band_rows_out_b(const TrArgs &a, int64_t r0, int64_t r1, const double *accJ,
+                                                const double *accR)
+{
+    constexpr int NVv = NV<D>::v, B2 = NVv * NVv, BP = BAcc<D>::P, RP = NVv | 1;
+    for (int64_t r = r0; r < r1; ++r) {
+        const int lr = (int)(r - r0);
+        if (threadIdx.x < NVv) a.R[r * NVv + threadIdx.x] = accR[lr * RP + threadIdx.x];
+        const int64_t g = a.node[r];
+        const int32_t *gc = a.gcol + a.grow[g];
+        const int glen = a.grow[g + 1] - a.grow[g];
+        const int64_t kb = a.brow[r], len = a.brow[r + 1] - kb;
+        for (int t = threadIdx.x; t < len; t += blockDim.x) {
+            const int32_t col = a.node[a.bcol[kb + t]];
+            int lo = 0, hi = glen - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (gc[mid] < col) lo = mid + 1;
+                else hi = mid;
+            }
+            const double *src = accJ + ((int64_t)lr * a.maxc + lo) * BP;
+            double *dst = a.J + (kb + t) * B2;
+#pragma unroll
+            for (int c = 0; c < NVv; ++c)
+#pragma unroll
+                for (int cc = 0; cc < NVv; ++cc) dst[c * NVv + cc] = b_block_entry<D>(src, c, cc);
+        }
+    }
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_ac_rows(TrArgs a, double eps, const double *gb /* gamma, beta */)
 {
@@ -524,9 +580,13 @@ template <int D>
 __global__ __launch_bounds__(256) void k_b_rows(TrArgs a, const double *afr /*[N]*/)
 {
     extern __shared__ double lds[];
-    constexpr int NN = D + 1, NQ = Rule<D>::NQ, NVv = NV<D>::v, B2 = NVv * NVv;
-    // LDS strides padded to an odd number of doubles (bank conflicts)
-    constexpr int BP = B2 | 1, RP = NVv | 1;
+    constexpr int NN = D + 1, NQ = Rule<D>::NQ, NVv = NV<D>::v;
+    // A block of the tangent is s1 I - LE(M) with M = sum over elements of
+    // s2 L_e (LE linear in its argument, see below), so each block
+    // accumulates 1 + D*D numbers instead of NVv^2 (3x fewer LDS atomics in
+    // 3D) and is expanded when written out.  LDS strides padded to an odd
+    // number of doubles (bank conflicts).
+    constexpr int BP = BAcc<D>::P, RP = NVv | 1;
     const int64_t r0 = (int64_t)blockIdx.x * a.rpb;
     const int64_t r1 = r0 + a.rpb < a.n ? r0 + a.rpb : a.n;
     double *accJ = lds, *accR = lds + (int64_t)a.rpb * a.maxc * BP;
@@ -600,10 +660,16 @@ __global__ __launch_bounds__(256) void k_b_rows(TrArgs a, const double *afr /*[N
                 vfull<D>(gk, gB[k]);
             }
             const double w = vol * Rule<D>::WF;
-            double re[NVv], Wl[NQ], U[NN][NQ], AQ[NQ];
+            // quadrature points one at a time (rolled: the live set of the
+            // unrolled loop exceeds 256 registers); the weights of the
+            // tangent blocks, S1 for the identity part and S2 for the L part,
+            // are accumulated per column node as the points pass
+            double re[NVv], S1[NN], S2[NN];
 #pragma unroll
             for (int c = 0; c < NVv; ++c) re[c] = 0.0;
 #pragma unroll
+            for (int b = 0; b < NN; ++b) S1[b] = S2[b] = 0.0;
+#pragma unroll 1
             for (int q = 0; q < NQ; ++q) {
                 double vq[D], aq = 0.0, bq[NVv], bdq[NVv];
 #pragma unroll
@@ -631,15 +697,16 @@ __global__ __launch_bounds__(256) void k_b_rows(TrArgs a, const double *afr /*[N
 #pragma unroll
                     for (int j = 0; j < D; ++j) vGv += vq[i] * G[i][j] * vq[j];
                 const double tau = 1.0 / sqrt(i4 + vGv);
+                double U[NN], Ula = 0.0;
 #pragma unroll
                 for (int b = 0; b < NN; ++b) {
                     double s = 0.0;
 #pragma unroll
                     for (int j = 0; j < D; ++j) s += vq[j] * dN[b][j];
-                    U[b][q] = s;
+                    U[b] = s;
+                    if (b == la) Ula = s;
                 }
-                Wl[q] = w * (shape_at<D>(q, la) + tau * U[la][q]);
-                AQ[q] = aq;
+                const double Wl = w * (shape_at<D>(q, la) + tau * Ula);
 #pragma unroll
                 for (int c = 0; c < NVv; ++c) {
                     int i, j;
@@ -652,25 +719,13 @@ __global__ __launch_bounds__(256) void k_b_rows(TrArgs a, const double *afr /*[N
                         BL += Bq[i][k] * L[j][k];
                     }
                     const double RB = aq * (Bdq[i][j] + conv - LB - BL) + (1.0 - aq) * (Bq[i][j] - (i == j ? 1.0 : 0.0));
-                    re[c] += Wl[q] * RB;
+                    re[c] += Wl * RB;
                 }
-            }
-            // LE[c][cc] = (L E + E L^T)_{ij(c)} for the symmetric unit direction E of cc
-            double LE[NVv][NVv];
 #pragma unroll
-            for (int cc = 0; cc < NVv; ++cc) {
-                int k, l;
-                vpair<D>(cc, k, l);
-#pragma unroll
-                for (int c = 0; c < NVv; ++c) {
-                    int i, j;
-                    vpair<D>(c, i, j);
-                    double s = 0.0;
-                    if (l == j) s += L[i][k];
-                    if (k == j && k != l) s += L[i][l];
-                    if (l == i) s += L[j][k];
-                    if (k == i && k != l) s += L[j][l];
-                    LE[c][cc] = s;
+                for (int ib = 0; ib < NN; ++ib) {
+                    const double Nb = shape_at<D>(q, ib);
+                    S1[ib] += Wl * (aq * (ct * Nb + al * U[ib]) + (1.0 - aq) * al * Nb);
+                    S2[ib] += Wl * aq * Nb;
                 }
             }
 #pragma unroll
@@ -678,27 +733,21 @@ __global__ __launch_bounds__(256) void k_b_rows(TrArgs a, const double *afr /*[N
             const int64_t gb0 = a.grow[g];
 #pragma unroll
             for (int ib = 0; ib < NN; ++ib) {
-                double S1 = 0.0, S2 = 0.0;
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    const double Nb = shape_at<D>(q, ib);
-                    S1 += Wl[q] * (AQ[q] * (ct * Nb + al * U[ib][q]) + (1.0 - AQ[q]) * al * Nb);
-                    S2 += Wl[q] * AQ[q] * Nb;
-                }
-                S2 *= al;
+                const double s2 = al * S2[ib];
                 double *blk = accJ + ((int64_t)lr * a.maxc + (a.epos[e * NN * NN + la * NN + ib] - gb0)) * BP;
+                atomicAdd(blk, S1[ib]);
 #pragma unroll
-                for (int c = 0; c < NVv; ++c)
+                for (int i = 0; i < D; ++i)
 #pragma unroll
-                    for (int cc = 0; cc < NVv; ++cc) {
-                        const double val = (c == cc ? S1 : 0.0) - S2 * LE[c][cc];
-                        if (val != 0.0) atomicAdd(blk + c * NVv + cc, val);
+                    for (int k = 0; k < D; ++k) {
+                        const double val = s2 * L[i][k];
+                        if (val != 0.0) atomicAdd(blk + 1 + i * D + k, val);
                     }
             }
         }
     }
     __syncthreads();
-    band_rows_out<NVv>(a, r0, r1, accJ, accR);
+    band_rows_out_b<D>(a, r0, r1, accJ, accR);
 }
 
 // Rows of nodes that keep their value: residual 0, unit row.
@@ -1100,7 +1149,8 @@ static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_itera
     a.R = R;
     a.J = J;
     if (B.n > 0) {
-        const size_t shm = (size_t)a.rpb * ((size_t)a.maxc * ((nv * nv) | 1) + (nv | 1)) * sizeof(double);
+        const int bp = ctx->dim == 2 ? BAcc<2>::P : BAcc<3>::P;
+        const size_t shm = (size_t)a.rpb * ((size_t)a.maxc * bp + (nv | 1)) * sizeof(double);
         if (ctx->dim == 2)
             hipLaunchKernelGGL(k_b_rows<2>, dim3(eft_grid(B.n, a.rpb)), dim3(256), shm, ctx->stream, a,
                                ctx->as + (int64_t)s * N);

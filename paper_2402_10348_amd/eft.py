@@ -45,7 +45,8 @@ class Params(C.Structure):
                 ("restart", C.c_int32), ("lin_maxit", C.c_int32), ("precond", C.c_int32),
                 ("precision", C.c_int32), ("band_flat", C.c_double), ("band_cell", C.c_int32),
                 ("band_halo", C.c_int32), ("mg_nu", C.c_int32), ("mg_omega", C.c_double),
-                ("mg_bf16", C.c_int32), ("mg_nu_post", C.c_int32), ("mg_smoother", C.c_int32)]
+                ("mg_bf16", C.c_int32), ("mg_nu_post", C.c_int32), ("mg_smoother", C.c_int32),
+                ("band_sweeps", C.c_int32), ("band_omega", C.c_double)]
 
 
 class State(C.Structure):
@@ -115,7 +116,8 @@ def params_struct(p, **over):
                 nl_max=p.nl_max, nl_fixed=p.nl_fixed, lin_rtol=p.lin_rtol, restart=p.restart,
                 lin_maxit=p.lin_maxit, precond=p.precond, precision=p.precision, band_flat=p.band_flat,
                 band_cell=p.band_cell, band_halo=p.band_halo, mg_nu=p.mg_nu, mg_omega=p.mg_omega,
-                mg_bf16=p.mg_bf16, mg_nu_post=p.mg_nu_post, mg_smoother=p.mg_smoother)
+                mg_bf16=p.mg_bf16, mg_nu_post=p.mg_nu_post, mg_smoother=p.mg_smoother,
+                band_sweeps=p.band_sweeps, band_omega=p.band_omega)
     vals.update(over)
     P = Params()
     for k, v in vals.items():

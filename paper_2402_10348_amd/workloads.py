@@ -166,6 +166,8 @@ class Params:
     mg_bf16: int = 0
     mg_nu_post: int = 3
     mg_smoother: int = 0      # 0 damped block Jacobi, 1 multicolour block Gauss-Seidel
+    band_sweeps: int = 2      # Allen-Cahn and B systems: damped block-Jacobi sweeps from zero
+    band_omega: float = 0.6   # below 2 / 2.5: P1 consistent mass has lambda_max(D^-1 M) <= 2.5
 
 
 @dataclass
