@@ -577,7 +577,7 @@ __global__ __launch_bounds__(256) void k_ac_rows(TrArgs a, double eps, const dou
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void k_b_rows(TrArgs a, const double *afr /*[N]*/)
+__global__ __launch_bounds__(256, 2) void k_b_rows(TrArgs a, const double *afr /*[N]*/)
 {
     extern __shared__ double lds[];
     constexpr int NN = D + 1, NQ = Rule<D>::NQ, NVv = NV<D>::v;
@@ -616,23 +616,18 @@ __global__ __launch_bounds__(256) void k_b_rows(TrArgs a, const double *afr /*[N
             const int64_t e = ent >> 2;
             const int la = ent & 3;
             if (!a.eflag[e]) continue;
-            double X[NN][D], v[NN][D], am[NN], Bn[NN][NVv], Bd[NN][NVv];
+            double X[NN][D], v[NN][D], am[NN];
+            int64_t nid[NN];
 #pragma unroll
             for (int b = 0; b < NN; ++b) {
                 const int64_t n = a.conn[e * NN + b];
+                nid[b] = n;
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
                     X[b][i] = a.xyz[n * D + i];
                     v[b][i] = a.va[n * D + i];
                 }
                 am[b] = afr[n];
-#pragma unroll
-                for (int c = 0; c < NVv; ++c) {
-                    const double xn = a.lx[n * NVv + c], xd = a.ldx[n * NVv + c], x1 = a.ix[n * NVv + c];
-                    const double xd1 = xd + (x1 - xn - a.dt * xd) / (a.vs * a.dt);
-                    Bd[b][c] = xd + a.alpha_m * (xd1 - xd);
-                    Bn[b][c] = xn + a.alpha * (x1 - xn);
-                }
             }
             double dN[NN][D], G[D][D];
             const double vol = simplex_geom<D>(X, dN, G);
@@ -646,51 +641,34 @@ __global__ __launch_bounds__(256) void k_b_rows(TrArgs a, const double *afr /*[N
                     for (int b = 0; b < NN; ++b) s += v[b][i] * dN[b][j];
                     L[i][j] = s;
                 }
-            double gB[D][D][D];
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                double gk[NVv];
-#pragma unroll
-                for (int c = 0; c < NVv; ++c) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int b = 0; b < NN; ++b) s += dN[b][k] * Bn[b][c];
-                    gk[c] = s;
-                }
-                vfull<D>(gk, gB[k]);
-            }
+            // Every term of the residual integrand is a quadrature-point
+            // scalar times a function linear in the nodal B values (the
+            // interpolants B_q, dB/dt_q, the element-constant gradient of B,
+            // and L B_q + B_q L^T with L constant on the element), so the
+            // quadrature sums reduce to per-node weights and the nodal B
+            // values enter once, after the loop:
+            //   S2[b] = sum_q W_q a_q N_b(q)          (rate and L terms)
+            //   T2[b] = sum_q W_q (1 - a_q) N_b(q),  T3 = sum_q W_q (1 - a_q)
+            //   Wv    = sum_q W_q a_q v_q             (advection)
+            // with W_q the SUPG-weighted test function of row node la.
             const double w = vol * Rule<D>::WF;
-            // quadrature points one at a time (rolled: the live set of the
-            // unrolled loop exceeds 256 registers); the weights of the
-            // tangent blocks, S1 for the identity part and S2 for the L part,
-            // are accumulated per column node as the points pass
-            double re[NVv], S1[NN], S2[NN];
+            double S1[NN], S2[NN], T2[NN], T3 = 0.0, Wv[D];
 #pragma unroll
-            for (int c = 0; c < NVv; ++c) re[c] = 0.0;
+            for (int b = 0; b < NN; ++b) S1[b] = S2[b] = T2[b] = 0.0;
 #pragma unroll
-            for (int b = 0; b < NN; ++b) S1[b] = S2[b] = 0.0;
-#pragma unroll 1
+            for (int i = 0; i < D; ++i) Wv[i] = 0.0;
+#pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                double vq[D], aq = 0.0, bq[NVv], bdq[NVv];
+                double vq[D], aq = 0.0;
 #pragma unroll
                 for (int i = 0; i < D; ++i) vq[i] = 0.0;
-#pragma unroll
-                for (int c = 0; c < NVv; ++c) bq[c] = bdq[c] = 0.0;
 #pragma unroll
                 for (int b = 0; b < NN; ++b) {
                     const double Nb = shape_at<D>(q, b);
                     aq += Nb * am[b];
 #pragma unroll
                     for (int i = 0; i < D; ++i) vq[i] += Nb * v[b][i];
-#pragma unroll
-                    for (int c = 0; c < NVv; ++c) {
-                        bq[c] += Nb * Bn[b][c];
-                        bdq[c] += Nb * Bd[b][c];
-                    }
                 }
-                double Bq[D][D], Bdq[D][D];
-                vfull<D>(bq, Bq);
-                vfull<D>(bdq, Bdq);
                 double vGv = 0.0;
 #pragma unroll
                 for (int i = 0; i < D; ++i)
@@ -707,26 +685,48 @@ __global__ __launch_bounds__(256) void k_b_rows(TrArgs a, const double *afr /*[N
                     if (b == la) Ula = s;
                 }
                 const double Wl = w * (shape_at<D>(q, la) + tau * Ula);
+                const double wa = Wl * aq, wr = Wl * (1.0 - aq);
+                T3 += wr;
 #pragma unroll
-                for (int c = 0; c < NVv; ++c) {
-                    int i, j;
-                    vpair<D>(c, i, j);
-                    double conv = 0.0, LB = 0.0, BL = 0.0;
-#pragma unroll
-                    for (int k = 0; k < D; ++k) {
-                        conv += vq[k] * gB[k][i][j];
-                        LB += L[i][k] * Bq[k][j];
-                        BL += Bq[i][k] * L[j][k];
-                    }
-                    const double RB = aq * (Bdq[i][j] + conv - LB - BL) + (1.0 - aq) * (Bq[i][j] - (i == j ? 1.0 : 0.0));
-                    re[c] += Wl * RB;
-                }
+                for (int i = 0; i < D; ++i) Wv[i] += wa * vq[i];
 #pragma unroll
                 for (int ib = 0; ib < NN; ++ib) {
                     const double Nb = shape_at<D>(q, ib);
                     S1[ib] += Wl * (aq * (ct * Nb + al * U[ib]) + (1.0 - aq) * al * Nb);
-                    S2[ib] += Wl * aq * Nb;
+                    S2[ib] += wa * Nb;
+                    T2[ib] += wr * Nb;
                 }
+            }
+            // residual: nodal B values streamed once
+            double re[NVv], P[NVv];
+#pragma unroll
+            for (int c = 0; c < NVv; ++c) re[c] = P[c] = 0.0;
+#pragma unroll
+            for (int b = 0; b < NN; ++b) {
+                double wu = T2[b];
+#pragma unroll
+                for (int k = 0; k < D; ++k) wu += Wv[k] * dN[b][k];
+                const int64_t n = nid[b];
+#pragma unroll
+                for (int c = 0; c < NVv; ++c) {
+                    const double xn = a.lx[n * NVv + c], xd = a.ldx[n * NVv + c], x1 = a.ix[n * NVv + c];
+                    const double xd1 = xd + (x1 - xn - a.dt * xd) / (a.vs * a.dt);
+                    const double bd = xd + a.alpha_m * (xd1 - xd);
+                    const double bn = xn + a.alpha * (x1 - xn);
+                    re[c] += S2[b] * bd + wu * bn;
+                    P[c] += S2[b] * bn;
+                }
+            }
+            double Pf[D][D];
+            vfull<D>(P, Pf);
+#pragma unroll
+            for (int c = 0; c < NVv; ++c) {
+                int i, j;
+                vpair<D>(c, i, j);
+                double LP = 0.0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) LP += L[i][k] * Pf[k][j] + Pf[i][k] * L[j][k];
+                re[c] -= LP + (i == j ? T3 : 0.0);
             }
 #pragma unroll
             for (int c = 0; c < NVv; ++c) atomicAdd(accR + lr * RP + c, re[c]);
