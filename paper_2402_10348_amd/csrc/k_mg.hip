@@ -510,12 +510,16 @@ __global__ __launch_bounds__(256) void k_gauss_jordan_lds(const double *__restri
 __global__ __launch_bounds__(256) void k_dense_apply(const double *Inv, int nd, const int32_t *free_dof, int64_t ndof,
                                                      const double *b, double *x, const int32_t *flag)
 {
+    __shared__ double bl[512];   // the free entries of b (nd <= 512)
     if (*flag == 0) return;
+    for (int j = threadIdx.x; j < nd; j += 256) bl[j] = b[free_dof[j]];
     for (int64_t i = threadIdx.x; i < ndof; i += 256) x[i] = 0.0;
     __syncthreads();
     for (int i = threadIdx.x; i < nd; i += 256) {
+        const double *row = Inv + (int64_t)i * nd;
         double s = 0.0;
-        for (int j = 0; j < nd; ++j) s += Inv[(int64_t)i * nd + j] * b[free_dof[j]];
+#pragma unroll 8
+        for (int j = 0; j < nd; ++j) s += row[j] * bl[j];
         x[free_dof[i]] = s;
     }
 }
@@ -802,7 +806,14 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
     // the fine-level smoother works on an FP32 copy of the Jacobian (the
     // preconditioner only shapes the Krylov space; FGMRES keeps FP64), which
     // halves the bytes of the most expensive kernel of the cycle.  The coarse
-    // levels (1/8 of the rows per level) keep FP64 values.
+    // levels are assembled in FP32 as well, except the coarsest, whose FP64
+    // values feed the dense inverse.
+    for (size_t l = 1; l + 1 < ctx->mg.size(); ++l) {
+        MGLevel &C = ctx->mg[l];
+        C.A.fp32 = true;
+        EFT_TRY(dmal(ctx, &C.A.val32, C.A.nnzb * bs * bs));
+        EFT_TRY(dmal(ctx, &C.Dinv32, C.N * bs * bs));
+    }
     MGLevel &F0 = ctx->mg[0];
     F0.A.bs = bs;
     F0.A.n = ctx->N;
@@ -944,7 +955,8 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
         M.maxc = C.maxc;
         M.rpb = C.rpb;
         EFT_TRY(eft_ns_level(ctx, M, C.vp, C.R, &C.A));
-        EFT_TRY(eft_bj_setup(ctx, &C.A, C.Dinv));
+        if (C.A.fp32) EFT_TRY(eft_bj_setup32(ctx, &C.A, C.Dinv32));
+        else EFT_TRY(eft_bj_setup(ctx, &C.A, C.Dinv));
     }
     if (ctx->mg_inv) {
         const MGLevel &Cc = ctx->mg.back();
