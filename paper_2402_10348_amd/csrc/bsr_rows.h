@@ -254,13 +254,3 @@ __device__ __forceinline__ void bsr_block_dot(int k0, int k1, const int32_t *__r
 #pragma unroll
         for (int i = 0; i < BS; ++i) acc[i] += __shfl_xor(acc[i], s, 64);
 }
-
-// acc[i] for a runtime i < BS (selects, no scratch indexing)
-template <int BS> __device__ __forceinline__ double pick(const double (&a)[BS], int i)
-{
-    double r = a[0];
-#pragma unroll
-    for (int t = 1; t < BS; ++t)
-        if (i == t) r = a[t];
-    return r;
-}

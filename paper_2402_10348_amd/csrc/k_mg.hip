@@ -135,15 +135,13 @@ __global__ __launch_bounds__(256) void k_sweep_rows(int64_t n, const int32_t *__
 // The same sweep with one block per lane (narrow values, bs 3 or 4): lane j
 // < bs of a row's segment finishes component j of the row.
 template <int BS, typename TV, typename TD>
-__global__ __launch_bounds__(256) void k_sweep_blk(int64_t n, const int32_t *__restrict__ rowptr,
-                                                   const int32_t *__restrict__ col, const TV *__restrict__ val,
-                                                   const TD *__restrict__ Dinv, double omega,
-                                                   const double *__restrict__ b, const double *__restrict__ x,
-                                                   double *__restrict__ xo, const int32_t *flag)
+__device__ __forceinline__ void sweep_blk_rows(int64_t row0, int64_t n, const int32_t *__restrict__ rowptr,
+                                               const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                               const TD *__restrict__ Dinv, double omega,
+                                               const double *__restrict__ b, const double *__restrict__ x,
+                                               double *__restrict__ xo)
 {
     constexpr int SEG = BlockSeg<BS>::SEG, RPW = BlockSeg<BS>::RPW;
-    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave_id()) * RPW;
-    if (*flag == 0 || row0 >= n) return;
     const int lane = threadIdx.x & 63, q = lane / SEG, j = lane - q * SEG;
     const int64_t row = row0 + q, rr = row < n ? row : row0;   // rr: in bounds, unused past n
     const int jj = j < BS ? j : 0;
@@ -160,6 +158,20 @@ __global__ __launch_bounds__(256) void k_sweep_blk(int64_t n, const int32_t *__r
 #pragma unroll
     for (int c = 0; c < BS; ++c) u += d[c] * (bb[c] - ax[c]);
     if (j < BS && row < n) xo[row * BS + j] = xr + omega * u;
+}
+
+// The same sweep with one block per lane (narrow values, bs 3 or 4): lane j
+// < bs of a row's segment finishes component j of the row.
+template <int BS, typename TV, typename TD>
+__global__ __launch_bounds__(256) void k_sweep_blk(int64_t n, const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                   const TD *__restrict__ Dinv, double omega,
+                                                   const double *__restrict__ b, const double *__restrict__ x,
+                                                   double *__restrict__ xo, const int32_t *flag)
+{
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave_id()) * BlockSeg<BS>::RPW;
+    if (*flag == 0 || row0 >= n) return;
+    sweep_blk_rows<BS, TV, TD>(row0, n, rowptr, col, val, Dinv, omega, b, x, xo);
 }
 
 // Block Gauss-Seidel on the rows of one colour, in place:
@@ -251,14 +263,12 @@ __global__ __launch_bounds__(256) void k_resid_rows(int64_t n, const int32_t *__
 
 // r = b - A x with one block per lane (narrow values, bs 3 or 4)
 template <int BS, typename TV>
-__global__ __launch_bounds__(256) void k_resid_blk(int64_t n, const int32_t *__restrict__ rowptr,
-                                                   const int32_t *__restrict__ col, const TV *__restrict__ val,
-                                                   const double *__restrict__ b, const double *__restrict__ x,
-                                                   double *__restrict__ r, const int32_t *flag)
+__device__ __forceinline__ void resid_blk_rows(int64_t row0, int64_t n, const int32_t *__restrict__ rowptr,
+                                               const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                               const double *__restrict__ b, const double *__restrict__ x,
+                                               double *__restrict__ r)
 {
     constexpr int SEG = BlockSeg<BS>::SEG, RPW = BlockSeg<BS>::RPW;
-    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave_id()) * RPW;
-    if (*flag == 0 || row0 >= n) return;
     const int lane = threadIdx.x & 63, q = lane / SEG, j = lane - q * SEG;
     const int64_t row = row0 + q, rr = row < n ? row : row0;
     const double br = b[rr * BS + (j < BS ? j : 0)];
@@ -266,28 +276,39 @@ __global__ __launch_bounds__(256) void k_resid_blk(int64_t n, const int32_t *__r
     seg_extents<RPW>(row0, n, rowptr, q, k0, k1);
     double ax[BS];
     bsr_block_dot<BS, TV, SEG>(k0, k1, col, val, x, j, ax);
-    if (j < BS && row < n) r[row * BS + j] = br - pick<BS>(ax, j);
+    // component j of the row, stored by lane j (unrolled: no dynamically
+    // indexed private array)
+#pragma unroll
+    for (int c = 0; c < BS; ++c)
+        if (j == c && row < n) r[row * BS + c] = br - ax[c];
+}
+
+template <int BS, typename TV>
+__global__ __launch_bounds__(256) void k_resid_blk(int64_t n, const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                   const double *__restrict__ b, const double *__restrict__ x,
+                                                   double *__restrict__ r, const int32_t *flag)
+{
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave_id()) * BlockSeg<BS>::RPW;
+    if (*flag == 0 || row0 >= n) return;
+    resid_blk_rows<BS, TV>(row0, n, rowptr, col, val, b, x, r);
 }
 
 // --------------------------------------------------------- transfers ------
 
 // coarse b[I] = sum over children i of I (fine nodes 2I + s, s in the Kuhn
-// stencil) of w(i, I) r[i], masked by the free dofs of both levels
+// stencil) of w(i, I) r[i], masked by the free dofs of both levels.  Every
+// load is issued unconditionally (index 0 and weight 0 outside the mesh, the
+// Dirichlet mask applied by a select), so the loads of all stencil points are
+// in flight together instead of one round trip per masked branch.
 template <int D>
-__global__ __launch_bounds__(256) void k_restrict(Dims cd, Dims fd, const uint8_t *__restrict__ cmask,
-                                                  const uint8_t *__restrict__ fmask, const double *__restrict__ r,
-                                                  double *__restrict__ bc, const int32_t *flag)
+__device__ __forceinline__ void restrict_node(const Dims &cd, const Dims &fd, const uint8_t *__restrict__ cmask,
+                                              const uint8_t *__restrict__ fmask, const double *__restrict__ r,
+                                              double *__restrict__ bc, int I)
 {
     constexpr int BS = D + 1;
-    if (*flag == 0) return;
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int nx = cd.n[0] + 1, ny = cd.n[1] + 1;
-    if (I >= nx * ny * (cd.n[2] + 1)) return;
     const int ci = I % nx, cj = (I / nx) % ny, ck = I / (nx * ny);
-    // every load is issued unconditionally (index 0 and weight 0 outside the
-    // mesh, the Dirichlet mask applied by a select), so the loads of all
-    // stencil points are in flight together instead of one round trip per
-    // masked branch
     double acc[BS];
 #pragma unroll
     for (int c = 0; c < BS; ++c) acc[c] = 0.0;
@@ -311,17 +332,25 @@ __global__ __launch_bounds__(256) void k_restrict(Dims cd, Dims fd, const uint8_
     for (int c = 0; c < BS; ++c) bc[(int64_t)I * BS + c] = ((mc >> c) & 1) ? acc[c] : 0.0;
 }
 
+template <int D>
+__global__ __launch_bounds__(256) void k_restrict(Dims cd, Dims fd, const uint8_t *__restrict__ cmask,
+                                                  const uint8_t *__restrict__ fmask, const double *__restrict__ r,
+                                                  double *__restrict__ bc, const int32_t *flag)
+{
+    if (*flag == 0) return;
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= (cd.n[0] + 1) * (cd.n[1] + 1) * (cd.n[2] + 1)) return;
+    restrict_node<D>(cd, fd, cmask, fmask, r, bc, I);
+}
+
 // x[i] += sum over parents I of i of w(i, I) xc[I] (free dofs only)
 template <int D>
-__global__ __launch_bounds__(256) void k_prolong(Dims cd, Dims fd, const uint8_t *__restrict__ cmask,
-                                                 const uint8_t *__restrict__ fmask, const double *__restrict__ xc,
-                                                 double *__restrict__ x, const int32_t *flag)
+__device__ __forceinline__ void prolong_node(const Dims &cd, const Dims &fd, const uint8_t *__restrict__ cmask,
+                                             const uint8_t *__restrict__ fmask, const double *__restrict__ xc,
+                                             double *__restrict__ x, int f)
 {
     constexpr int BS = D + 1;
-    if (*flag == 0) return;
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
     const int nx = fd.n[0] + 1, ny = fd.n[1] + 1;
-    if (f >= nx * ny * (fd.n[2] + 1)) return;
     const int fi = f % nx, fj = (f / nx) % ny, fk = f / (nx * ny);
     const int64_t I0 = node_id(cd, fi >> 1, fj >> 1, fk >> 1);
     const bool mid = (fi & 1) | (fj & 1) | (fk & 1);
@@ -335,6 +364,17 @@ __global__ __launch_bounds__(256) void k_prolong(Dims cd, Dims fd, const uint8_t
         const double v = ((m0 >> c) & 1 ? a0 : 0.0) + (mid && ((m1 >> c) & 1) ? a1 : 0.0);
         x[(int64_t)f * BS + c] = ((m >> c) & 1) ? xv + w * v : xv;
     }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_prolong(Dims cd, Dims fd, const uint8_t *__restrict__ cmask,
+                                                 const uint8_t *__restrict__ fmask, const double *__restrict__ xc,
+                                                 double *__restrict__ x, const int32_t *flag)
+{
+    if (*flag == 0) return;
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= (fd.n[0] + 1) * (fd.n[1] + 1) * (fd.n[2] + 1)) return;
+    prolong_node<D>(cd, fd, cmask, fmask, xc, x, f);
 }
 
 // -------------------------------------------------------- coarsest level --
@@ -507,21 +547,28 @@ __global__ __launch_bounds__(256) void k_gauss_jordan_lds(const double *__restri
 
 // x = A^-1 b on the coarsest level: free dofs from the dense inverse, the
 // Dirichlet dofs zero
-__global__ __launch_bounds__(256) void k_dense_apply(const double *Inv, int nd, const int32_t *free_dof, int64_t ndof,
-                                                     const double *b, double *x, const int32_t *flag)
+template <int T>
+__device__ __forceinline__ void dense_apply_block(const double *Inv, int nd, const int32_t *free_dof, int64_t ndof,
+                                                  const double *b, double *x, double *bl /* LDS, nd */)
 {
-    __shared__ double bl[512];   // the free entries of b (nd <= 512)
-    if (*flag == 0) return;
-    for (int j = threadIdx.x; j < nd; j += 256) bl[j] = b[free_dof[j]];
-    for (int64_t i = threadIdx.x; i < ndof; i += 256) x[i] = 0.0;
+    for (int j = threadIdx.x; j < nd; j += T) bl[j] = b[free_dof[j]];
+    for (int64_t i = threadIdx.x; i < ndof; i += T) x[i] = 0.0;
     __syncthreads();
-    for (int i = threadIdx.x; i < nd; i += 256) {
+    for (int i = threadIdx.x; i < nd; i += T) {
         const double *row = Inv + (int64_t)i * nd;
         double s = 0.0;
 #pragma unroll 8
         for (int j = 0; j < nd; ++j) s += row[j] * bl[j];
         x[free_dof[i]] = s;
     }
+}
+
+__global__ __launch_bounds__(256) void k_dense_apply(const double *Inv, int nd, const int32_t *free_dof, int64_t ndof,
+                                                     const double *b, double *x, const int32_t *flag)
+{
+    __shared__ double bl[512];   // the free entries of b (nd <= 512)
+    if (*flag == 0) return;
+    dense_apply_block<256>(Inv, nd, free_dof, ndof, b, x, bl);
 }
 
 // FP32 copy of a matrix's values (multigrid works on FP32 matrices)

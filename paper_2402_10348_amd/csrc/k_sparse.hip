@@ -54,7 +54,9 @@ __global__ __launch_bounds__(256) void k_spmv_blk(int64_t n, const int32_t *__re
     double acc[BS];
     bsr_block_dot<BS, TV, SEG>(k0, k1, col, val, x, j, acc);
     const int64_t row = row0 + q;
-    if (j < BS && row < n) y[row * BS + j] = pick<BS>(acc, j);
+#pragma unroll
+    for (int c = 0; c < BS; ++c)
+        if (j == c && row < n) y[row * BS + c] = acc[c];
 }
 
 // general bs in 2..8: LDS reduction per wavefront.
