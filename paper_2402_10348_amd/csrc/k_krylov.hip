@@ -4,9 +4,11 @@
 //
 // Every kernel of an iteration reads a device flag and returns at once after
 // convergence, so the host enqueues iterations in chunks and reads the status
-// once per chunk; Hessenberg, Givens rotations and the triangular solve run in
-// single-thread device kernels.  Dot products reduce deterministically: each
-// block writes a partial, a second kernel sums the partials in a fixed order.
+// once per chunk; the Hessenberg column, Givens rotations and the triangular
+// solve run in single-workgroup kernels (the column's bookkeeping is fused
+// with the last reduction of its pass).  Dot products reduce
+// deterministically: each block writes a partial, a second kernel sums the
+// partials in a fixed order.
 #include "dev_common.h"
 #include "eft_internal.h"
 
@@ -97,31 +99,10 @@ __global__ __launch_bounds__(RB) void k_maxpy(const double *__restrict__ V, int6
     }
 }
 
-// After pass 1: store the dots as Hessenberg column j, decide on pass 2.
-__global__ void k_after_pass1(double *small, int m, int j, int32_t *flag)
+// Givens update of column j of H (in place), residual estimate, convergence
+// and breakdown flags; one thread.
+__device__ void givens_column(double *small, int m, int j, int32_t *flag)
 {
-    if (flag[0] == 0) return;
-    Small L{m};
-    double *H = small + L.H(), *h = small + L.h();
-    for (int i = 0; i <= j; ++i) H[(int64_t)i * m + j] = h[i];
-    const double ww = h[j + 1], nw = small[L.sc() + 0];
-    flag[3] = (nw < 0.5 * ww) ? 1 : 0;
-    if (!flag[3]) H[(int64_t)(j + 1) * m + j] = sqrt(nw);
-}
-
-__global__ void k_after_pass2(double *small, int m, int j, int32_t *flag)
-{
-    if (flag[0] == 0 || flag[3] == 0) return;
-    Small L{m};
-    double *H = small + L.H(), *h2 = small + L.h2();
-    for (int i = 0; i <= j; ++i) H[(int64_t)i * m + j] += h2[i];
-    H[(int64_t)(j + 1) * m + j] = sqrt(small[L.sc() + 1]);
-}
-
-// Givens update of column j, residual estimate, convergence / breakdown.
-__global__ void k_givens(double *small, int m, int j, int32_t *flag)
-{
-    if (flag[0] == 0) return;
     Small L{m};
     double *H = small + L.H(), *cs = small + L.cs(), *sn = small + L.sn(), *g = small + L.g();
     for (int i = 0; i < j; ++i) {
@@ -148,6 +129,37 @@ __global__ void k_givens(double *small, int m, int j, int32_t *flag)
         flag[2] = 1;
     }
     if (j + 1 >= m) flag[0] = 0;
+}
+
+// End of an orthogonalization pass of column j (one workgroup): ||w||^2
+// from the update's partials, then pass 1 stores the dots as the column and
+// decides on pass 2 (taken when pass 1 removed more than half of ||w||^2);
+// the pass that completes the column sets H[j+1][j] = ||w|| and applies the
+// Givens rotations.
+__global__ __launch_bounds__(RB) void k_close_pass(const double *__restrict__ part, int nblk, double *small, int m,
+                                                   int j, int pass, int32_t *flag)
+{
+    __shared__ double lds[RB / 64];
+    if (flag[0] == 0 || (pass == 2 && flag[3] == 0)) return;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += RB) s += part[b];
+    s = block_sum<RB>(s, lds);
+    if (threadIdx.x != 0) return;
+    Small L{m};
+    double *H = small + L.H();
+    if (pass == 1) {
+        const double *h = small + L.h();
+        for (int i = 0; i <= j; ++i) H[(int64_t)i * m + j] = h[i];
+        small[L.sc() + 0] = s;
+        flag[3] = (s < 0.5 * h[j + 1]) ? 1 : 0;
+        if (flag[3]) return;   // pass 2 completes the column
+    } else {
+        const double *h2 = small + L.h2();
+        for (int i = 0; i <= j; ++i) H[(int64_t)i * m + j] += h2[i];
+        small[L.sc() + 1] = s;
+    }
+    H[(int64_t)(j + 1) * m + j] = sqrt(s);
+    givens_column(small, m, j, flag);
 }
 
 // v_{j+1} = w / H[j+1][j]
@@ -397,9 +409,8 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
                                    K.flag, 0);
                 hipLaunchKernelGGL(k_maxpy, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, j + 1, small + L.h(), -1.0,
                                    K.w, K.part, nblk, K.flag, 0);
-                hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, small + L.sc(),
-                                   K.flag, 0);
-                hipLaunchKernelGGL(k_after_pass1, dim3(1), dim3(1), 0, ctx->stream, small, m, j, K.flag);
+                hipLaunchKernelGGL(k_close_pass, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, small, m, j, 1,
+                                   K.flag);
                 // pass 2 (gated)
                 dim3 g2(nblk, (j + 1 + KC - 1) / KC);
                 hipLaunchKernelGGL(k_mdot, g2, dim3(RB), 0, ctx->stream, K.V, nd, j + 1, 0, K.w, K.part, nblk, K.flag,
@@ -408,10 +419,8 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
                                    K.flag, 1);
                 hipLaunchKernelGGL(k_maxpy, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, j + 1, small + L.h2(),
                                    -1.0, K.w, K.part, nblk, K.flag, 1);
-                hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, small + L.sc() + 1,
-                                   K.flag, 1);
-                hipLaunchKernelGGL(k_after_pass2, dim3(1), dim3(1), 0, ctx->stream, small, m, j, K.flag);
-                hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, ctx->stream, small, m, j, K.flag);
+                hipLaunchKernelGGL(k_close_pass, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, small, m, j, 2,
+                                   K.flag);
                 hipLaunchKernelGGL(k_normalize, dim3(sg), dim3(RB), 0, ctx->stream, K.w, K.V + (int64_t)(j + 1) * nd,
                                    nd, small, m, j, K.flag);
             }

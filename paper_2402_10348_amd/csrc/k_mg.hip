@@ -343,6 +343,34 @@ __global__ __launch_bounds__(256) void k_restrict(Dims cd, Dims fd, const uint8_
     restrict_node<D>(cd, fd, cmask, fmask, r, bc, I);
 }
 
+// Restriction fused with the coarse level's first sweep from zero: node I
+// gets b[I] and x[I] = omega D_I^-1 b[I] (the arithmetic of k_sweep0 per
+// component), one launch instead of two.
+template <int D, typename TD>
+__global__ __launch_bounds__(256) void k_restrict_sweep0(Dims cd, Dims fd, const uint8_t *__restrict__ cmask,
+                                                         const uint8_t *__restrict__ fmask,
+                                                         const double *__restrict__ r, double *__restrict__ bc,
+                                                         const TD *__restrict__ Dinv, double omega,
+                                                         double *__restrict__ xc, const int32_t *flag)
+{
+    constexpr int BS = D + 1;
+    if (*flag == 0) return;
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= (cd.n[0] + 1) * (cd.n[1] + 1) * (cd.n[2] + 1)) return;
+    restrict_node<D>(cd, fd, cmask, fmask, r, bc, I);
+    double bb[BS];
+#pragma unroll
+    for (int c = 0; c < BS; ++c) bb[c] = bc[(int64_t)I * BS + c];
+#pragma unroll
+    for (int i = 0; i < BS; ++i) {
+        const TD *Dr = Dinv + ((int64_t)I * BS + i) * BS;
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < BS; ++c) s += (double)Dr[c] * bb[c];
+        xc[(int64_t)I * BS + i] = omega * s;
+    }
+}
+
 // x[i] += sum over parents I of i of w(i, I) xc[I] (free dofs only)
 template <int D>
 __device__ __forceinline__ void prolong_node(const Dims &cd, const Dims &fd, const uint8_t *__restrict__ cmask,
@@ -1157,7 +1185,10 @@ void resid(eft_ctx *ctx, const eft_matrix &A, const double *b, const double *x, 
 
 // V-cycle on level l with right-hand side b; returns the buffer holding x
 // (out, when given, receives the last post-smoothing sweep)
-double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag, double *out = nullptr)
+// (x0_done: the first sweep from zero was fused into the restriction that
+// produced b and already sits in the level's x)
+double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag, double *out = nullptr,
+               bool x0_done = false)
 {
     MGLevel &L = ctx->mg[l];
     const eft_matrix &A = L.A;
@@ -1172,7 +1203,7 @@ double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag, double
     }
     const bool gs = ctx->par.mg_smoother == 1 && L.ncolor > 0;
     if (gs && out) cur = out;   // in-place smoothing works on the output directly
-    sweep0(ctx, L, b, cur, flag);
+    if (!x0_done) sweep0(ctx, L, b, cur, flag);
     const int nu = last ? 40 : ctx->par.mg_nu;
     for (int s = 1; s < nu; ++s) {
         if (gs) {
@@ -1186,13 +1217,34 @@ double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag, double
     MGLevel &C = ctx->mg[l + 1];
     resid(ctx, A, b, cur, L.r, flag);
     const Dims fd = dims_of(L), cd = dims_of(C);
-    if (ctx->dim == 2)
-        hipLaunchKernelGGL(k_restrict<2>, dim3(eft_grid(C.N, 256)), dim3(256), 0, ctx->stream, cd, fd, C.fmask,
-                           L.fmask, L.r, C.b, flag);
-    else
-        hipLaunchKernelGGL(k_restrict<3>, dim3(eft_grid(C.N, 256)), dim3(256), 0, ctx->stream, cd, fd, C.fmask,
-                           L.fmask, L.r, C.b, flag);
-    double *xc = vcycle(ctx, l + 1, C.b, flag);
+    // the coarse level starts with a sweep from zero into its x unless it
+    // is the coarsest with a dense solve: fuse that sweep into the restriction
+    const bool c_last = l + 2 == (int)ctx->mg.size();
+    const bool fuse = !(c_last && ctx->mg_inv);
+    const dim3 gr(eft_grid(C.N, 256)), tr(256);
+    const bool c32 = C.A.fp32 || C.A.bf16;
+    const double om = ctx->par.mg_omega;
+    if (!fuse) {
+        if (ctx->dim == 2)
+            hipLaunchKernelGGL(k_restrict<2>, gr, tr, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.r, C.b, flag);
+        else
+            hipLaunchKernelGGL(k_restrict<3>, gr, tr, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.r, C.b, flag);
+    } else if (ctx->dim == 2) {
+        if (c32)
+            hipLaunchKernelGGL((k_restrict_sweep0<2, float>), gr, tr, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.r,
+                               C.b, C.Dinv32, om, C.x, flag);
+        else
+            hipLaunchKernelGGL((k_restrict_sweep0<2, double>), gr, tr, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.r,
+                               C.b, C.Dinv, om, C.x, flag);
+    } else {
+        if (c32)
+            hipLaunchKernelGGL((k_restrict_sweep0<3, float>), gr, tr, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.r,
+                               C.b, C.Dinv32, om, C.x, flag);
+        else
+            hipLaunchKernelGGL((k_restrict_sweep0<3, double>), gr, tr, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.r,
+                               C.b, C.Dinv, om, C.x, flag);
+    }
+    double *xc = vcycle(ctx, l + 1, C.b, flag, nullptr, fuse);
     if (ctx->dim == 2)
         hipLaunchKernelGGL(k_prolong<2>, dim3(eft_grid(L.N, 256)), dim3(256), 0, ctx->stream, cd, fd, C.fmask, L.fmask,
                            xc, cur, flag);
