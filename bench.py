@@ -87,8 +87,8 @@ def log(args, *a):
 KERNEL_NAME = {1: "k_sweep_blk<4, float, float> (fine-level multigrid smoother sweep, FP32 copy of the 4x4-block "
                   "momentum Jacobian, one block per lane)",
                2: "k_spmv_rows<4, double, true> (FP64 SpMV of the 4x4-block momentum Jacobian in FGMRES)",
-               3: "k_ns_rows<3, double> (momentum/mass residual and Jacobian assembly, bytes: J and R written "
-                  "once, connectivity and node fields read once)"}
+               3: "k_ns_rows<3, double> (momentum/mass residual and Jacobian assembly, bytes: J, its FP32 copy "
+                  "for the multigrid and R written once, connectivity and node fields read once)"}
 
 
 def timed_steps(ctx, st, steps, warmup, torch):

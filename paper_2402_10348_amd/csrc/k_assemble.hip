@@ -99,6 +99,7 @@ struct RowArgs {
     const double *as, *Ba, *muL;
     double ct, alpha, kappa, dt, C_I, g0, g1, g2;
     double *R;
+    float *J32;   // optional FP32 copy of the values
 };
 
 template <int D, typename TJ>
@@ -412,7 +413,11 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
         if (Jv == nullptr) continue;
         const int64_t kb = a.rowptr[r], len = a.rowptr[r + 1] - kb;
         for (int t = threadIdx.x; t < len * B2; t += blockDim.x)
-            Jv[kb * B2 + t] = (TJ)accJ[((int64_t)lr * a.maxc + t / B2) * BP + t % B2];
+        {
+            const double v = accJ[((int64_t)lr * a.maxc + t / B2) * BP + t % B2];
+            Jv[kb * B2 + t] = (TJ)v;
+            if (a.J32) a.J32[kb * B2 + t] = (float)v;
+        }
     }
 }
 
@@ -513,7 +518,7 @@ eft_status eft_props(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it)
 // node fields va, acc, rho, mu, as, Ba must be current, see eft_props).
 // Residual and Jacobian of the momentum/mass block on one mesh level (the
 // node fields of the view must be current).
-eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, double *R, eft_matrix *J)
+eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, double *R, eft_matrix *J, float *J32)
 {
     GA ga = ga_of(ctx->par.rho_inf, ctx->par.dt);
     const int BS = ctx->bs;
@@ -546,6 +551,7 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
     a.g1 = ctx->g[1];
     a.g2 = ctx->g[2];
     a.R = R;
+    a.J32 = (J && !J->fp32) ? J32 : nullptr;
     if (!J) {
         // residual only: one row of accumulators suffices for the pattern-free path
         a.rowptr = ctx->J.rowptr;
@@ -553,13 +559,14 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
     const int nb = eft_grid(M.N, M.rpb);
     const size_t shm = (size_t)M.rpb * ((size_t)M.maxc * ((BS * BS) | 1) + (BS | 1)) * sizeof(double);
     // kernel-timing hook on the mesh level (not the coarse levels).
-    // Algorithmic bytes: J and R written once, the connectivity and every
-    // node field the element evaluation reads, once.
+    // Algorithmic bytes: J (and its FP32 copy when written) and R written
+    // once, the connectivity and every node field the element evaluation
+    // reads, once.
     const bool fine = M.conn == ctx->conn;
     const int64_t slot = fine ? eft_kt_begin(ctx, EFT_KT_ASSEMBLE) : -1;
     const int d = ctx->dim;
     const double abytes =
-        (J ? (double)J->nnzb * BS * BS * (J->fp32 ? 4.0 : 8.0) : 0.0) + (double)M.N * BS * 8.0 +
+        (J ? (double)J->nnzb * BS * BS * ((J->fp32 ? 4.0 : 8.0) + (a.J32 ? 4.0 : 0.0)) : 0.0) + (double)M.N * BS * 8.0 +
         (double)M.E * (d + 1) * 4.0 +
         (double)M.N * 8.0 * (d + BS + d + d + 2 + (double)ctx->n_s * (1 + ctx->nv));
     if (ctx->dim == 2) {
@@ -580,6 +587,9 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
             hipLaunchKernelGGL(k_bc_rows<double>, dim3(nbd), dim3(128), 0, ctx->stream, M.n_dir, M.dir_node,
                                M.dir_mask, J ? J->rowptr : nullptr, J ? J->col : nullptr, BS, R,
                                J ? J->val : (double *)nullptr);
+        if (a.J32)   // the same unit rows in the FP32 copy
+            hipLaunchKernelGGL(k_bc_rows<float>, dim3(nbd), dim3(128), 0, ctx->stream, M.n_dir, M.dir_node, M.dir_mask,
+                               J->rowptr, J->col, BS, (double *)nullptr, a.J32);
         EFT_HIP(hipGetLastError());
     }
     return EFT_OK;
@@ -609,7 +619,12 @@ eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_ma
     M.ient = ctx->ient;
     M.maxc = ctx->maxc;
     M.rpb = ctx->rpb;
-    EFT_TRY(eft_ns_level(ctx, M, it->vp, R, J));
-    if (J && eft_mg_active(ctx, J)) EFT_TRY(eft_mg_setup(ctx, it->vp));
+    // with the multigrid active, the assembly also writes the finest level's
+    // FP32 copy of the values (no separate conversion pass over J)
+    const bool mg = J && eft_mg_active(ctx, J);
+    float *J32 = (mg && !ctx->par.mg_bf16 && !J->fp32) ? ctx->mg[0].A.val32 : nullptr;
+    EFT_TRY(eft_ns_level(ctx, M, it->vp, R, J, J32));
+    ctx->mg_f32_fresh = J32 != nullptr;
+    if (mg) EFT_TRY(eft_mg_setup(ctx, it->vp));
     return EFT_OK;
 }

@@ -978,10 +978,11 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
         if (ctx->J.fp32) {
             EFT_HIP(hipMemcpyAsync(F0.A.val32, ctx->J.val32, sizeof(float) * nv, hipMemcpyDeviceToDevice,
                                    ctx->stream));
-        } else {
+        } else if (!ctx->mg_f32_fresh) {   // (else the assembly wrote the copy)
             hipLaunchKernelGGL(k_to_f32, dim3(cgrid), dim3(256), 0, ctx->stream, ctx->J.val, F0.A.val32, nv);
             EFT_HIP(hipGetLastError());
         }
+        ctx->mg_f32_fresh = false;
         EFT_TRY(eft_bj_setup32(ctx, &F0.A, F0.Dinv32));
     }
     for (int64_t l = 1; l < L; ++l) {

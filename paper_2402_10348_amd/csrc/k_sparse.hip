@@ -5,6 +5,8 @@
 // the 3D B system): one wavefront per block row, one lane per scalar row of
 // a block (bsr_rows.h); FP32 values of bs 3 and 4 take one block per lane.
 // Other bs: one value per lane, LDS reduction.  bs = 1 uses 16 lanes per row.
+#include <type_traits>
+
 #include "bsr_rows.h"
 #include "dev_common.h"
 #include "eft_internal.h"
@@ -215,6 +217,73 @@ __global__ __launch_bounds__(256) void k_bj_setup(int64_t n, int bs, const int32
         for (int j = 0; j < bs; ++j) out[i * bs + j] = (TD)(ok ? I[i][j] : (i == j ? 1.0 : 0.0));
 }
 
+// The same elimination with the block size fixed at compile time: every
+// loop unrolls and the row exchange of the pivot search is a predicated swap
+// at static indices, so the block stays in registers (with a run-time size
+// the arrays above live in scratch memory).
+template <int BS, typename TV, typename TD>
+__global__ __launch_bounds__(256) void k_bj_setup_t(int64_t n, const int32_t *__restrict__ diag,
+                                                    const TV *__restrict__ val, TD *__restrict__ Dinv)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double A[BS][BS], I[BS][BS];
+    const TV *blk = val + (int64_t)diag[r] * BS * BS;
+#pragma unroll
+    for (int i = 0; i < BS; ++i)
+#pragma unroll
+        for (int j = 0; j < BS; ++j) {
+            A[i][j] = (double)blk[i * BS + j];
+            I[i][j] = (i == j) ? 1.0 : 0.0;
+        }
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < BS; ++k) {
+        int pr = k;
+        double best = fabs(A[k][k]);
+#pragma unroll
+        for (int i = k + 1; i < BS; ++i)
+            if (fabs(A[i][k]) > best) {
+                best = fabs(A[i][k]);
+                pr = i;
+            }
+        ok = ok && best != 0.0;
+#pragma unroll
+        for (int i = k + 1; i < BS; ++i)
+            if (i == pr)
+#pragma unroll
+                for (int j = 0; j < BS; ++j) {
+                    double t = A[k][j];
+                    A[k][j] = A[i][j];
+                    A[i][j] = t;
+                    t = I[k][j];
+                    I[k][j] = I[i][j];
+                    I[i][j] = t;
+                }
+        const double inv = best != 0.0 ? 1.0 / A[k][k] : 0.0;
+#pragma unroll
+        for (int j = 0; j < BS; ++j) {
+            A[k][j] *= inv;
+            I[k][j] *= inv;
+        }
+#pragma unroll
+        for (int i = 0; i < BS; ++i) {
+            if (i == k) continue;
+            const double f = A[i][k];
+#pragma unroll
+            for (int j = 0; j < BS; ++j) {
+                A[i][j] -= f * A[k][j];
+                I[i][j] -= f * I[k][j];
+            }
+        }
+    }
+    TD *out = Dinv + r * BS * BS;
+#pragma unroll
+    for (int i = 0; i < BS; ++i)
+#pragma unroll
+        for (int j = 0; j < BS; ++j) out[i * BS + j] = (TD)(ok ? I[i][j] : (i == j ? 1.0 : 0.0));
+}
+
 __global__ __launch_bounds__(256) void k_bj_apply(int64_t nd, int bs, const double *__restrict__ Dinv, double omega,
                                                   const double *__restrict__ x, double *__restrict__ z,
                                                   const int32_t *active)
@@ -298,12 +367,21 @@ template <typename TD> static eft_status bj_setup(eft_ctx *ctx, const eft_matrix
         ctx->err = "block size above 8";
         return EFT_EINVAL;
     }
-    if (A->fp32)
-        hipLaunchKernelGGL((k_bj_setup<float, TD>), dim3(eft_grid(A->n, 256)), dim3(256), 0, ctx->stream, A->n,
-                           A->bs, A->diag, A->val32, Dinv);
+    const dim3 g(eft_grid(A->n, 256)), t(256);
+    auto fixed = [&](auto bsc) {
+        constexpr int BS = decltype(bsc)::value;
+        if (A->fp32)
+            hipLaunchKernelGGL((k_bj_setup_t<BS, float, TD>), g, t, 0, ctx->stream, A->n, A->diag, A->val32, Dinv);
+        else
+            hipLaunchKernelGGL((k_bj_setup_t<BS, double, TD>), g, t, 0, ctx->stream, A->n, A->diag, A->val, Dinv);
+    };
+    if (A->bs == 3) fixed(std::integral_constant<int, 3>{});
+    else if (A->bs == 4) fixed(std::integral_constant<int, 4>{});
+    else if (A->bs == 6) fixed(std::integral_constant<int, 6>{});
+    else if (A->fp32)
+        hipLaunchKernelGGL((k_bj_setup<float, TD>), g, t, 0, ctx->stream, A->n, A->bs, A->diag, A->val32, Dinv);
     else
-        hipLaunchKernelGGL((k_bj_setup<double, TD>), dim3(eft_grid(A->n, 256)), dim3(256), 0, ctx->stream, A->n,
-                           A->bs, A->diag, A->val, Dinv);
+        hipLaunchKernelGGL((k_bj_setup<double, TD>), g, t, 0, ctx->stream, A->n, A->bs, A->diag, A->val, Dinv);
     EFT_HIP(hipGetLastError());
     return EFT_OK;
 }
