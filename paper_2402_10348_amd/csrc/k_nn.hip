@@ -327,15 +327,20 @@ __global__ void k_relu_mask(int64_t n, const float *pre, float *x)
     if (t < n && !(pre[t] > 0.0f)) x[t] = 0.0f;
 }
 
-// column sums of x [n][H]: part[blk][c]
+// column sums of x [n][H] (H <= 64): part[blk][c] over rows_per_blk rows; the
+// 256 threads of a block take 4 interleaved row sequences per column, summed
+// in LDS at the end
 __global__ __launch_bounds__(256) void k_colsum(int64_t n, int H, const float *x, int64_t rows_per_blk, float *part)
 {
-    const int c = threadIdx.x;
-    if (c >= H) return;
+    __shared__ float ls[4][64];
+    const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk, r1 = r0 + rows_per_blk < n ? r0 + rows_per_blk : n;
     float s = 0.0f;
-    for (int64_t r = r0; r < r1; ++r) s += x[r * H + c];
-    part[(int64_t)blockIdx.x * H + c] = s;
+    if (c < H)
+        for (int64_t r = r0 + q; r < r1; r += 4) s += x[r * H + c];
+    ls[q][c] = s;
+    __syncthreads();
+    if (q == 0 && c < H) part[(int64_t)blockIdx.x * H + c] = ls[0][c] + ls[1][c] + ls[2][c] + ls[3][c];
 }
 
 __global__ void k_adam(int64_t n, float *theta, const float *grad, float *m1, float *m2, float lr, float c1, float c2)
@@ -414,7 +419,9 @@ void gemm(eft_ctx *ctx, GemmArgs a)
     hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, ctx->stream, a);
 }
 
-constexpr int64_t KCHUNK = 4096;   // nodes per split of the weight-gradient GEMMs
+// nodes per split of the weight-gradient GEMMs and of the bias sums (short
+// splits: enough workgroups to fill the GPU at the sizes trained here)
+constexpr int64_t KCHUNK = 256;
 
 // forward of the network on ctx->net.u (scale in red[0]); z gets the result
 void forward(eft_ctx *ctx, double *z, const int32_t *flag)
@@ -503,7 +510,7 @@ void bias_grad(eft_ctx *ctx, const float *dY, float *db)
     NNState &S = ctx->net;
     const int64_t n = ctx->N, H = S.H;
     const int64_t nblk = (n + KCHUNK - 1) / KCHUNK;
-    hipLaunchKernelGGL(k_colsum, dim3((unsigned)nblk), dim3(64), 0, ctx->stream, n, (int)H, dY, KCHUNK, S.part);
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)nblk), dim3(256), 0, ctx->stream, n, (int)H, dY, KCHUNK, S.part);
     hipLaunchKernelGGL(k_sum_splits, dim3(grid_of(H, 256)), dim3(256), 0, ctx->stream, S.part, nblk, H, db, 1);
 }
 
