@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB copied by a plain device copy before the timed steps (HBM counter calibration)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-full-domain", dest="full_domain", action="store_false",
+                    help="skip the full-domain (no band) transport run")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -148,6 +150,40 @@ def run_learned(args, torch):
                 training=dict(pairs=args.learned_pairs, adam_steps=args.learned_train, seconds=round(t_train, 3),
                               loss_first=float(losses[:10].mean()), loss_last=float(losses[-10:].mean())),
                 speedup=round(el0 / el1, 4))
+
+
+def run_full_domain(args, prob, torch, band_final):
+    """The same warmup and timed steps with the transport on the whole mesh
+    (band_flat < 0: no band), and the band's truncation: the relative
+    difference of the final fields of the banded and the full-domain runs."""
+    import numpy as np
+    from paper_2402_10348_amd.eft import Context
+    ctx = Context(prob, lin_rtol=1e-8, restart=args.restart, lin_maxit=20000, precision=args.precision,
+                  precond=args.precond, mg_nu=args.mg_nu, mg_omega=args.mg_omega, mg_bf16=args.mg_bf16,
+                  mg_nu_post=args.mg_nu_post, mg_smoother=args.mg_smoother, band_flat=-1.0, **band_over(args))
+    st = ctx.device_state(prob.state_copy())
+    t_sim, step_no = 0.0, 0
+    for _ in range(args.warmup):
+        info = ctx.step(st, t=t_sim, step=step_no)
+        t_sim, step_no = info["t"], info["step"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for _ in range(args.steps):
+        info = ctx.step(st, t=t_sim, step=step_no)
+        t_sim, step_no = info["t"], info["step"]
+        its.append(info)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    fin = {k: st[k].cpu().numpy() for k in ("vp", "phi", "B")}
+    ctx.close()
+    trunc = {k: float(np.linalg.norm(band_final[k] - fin[k]) / max(np.linalg.norm(fin[k]), 1e-300))
+             for k in fin}
+    return dict(value=round(args.steps / el, 4), unit="steps/s", ms_per_step=round(1e3 * el / args.steps, 2),
+                transport_ms_per_step=round(1e3 * float(np.mean([i["t_transport"] for i in its])), 2),
+                krylov_iters_per_step_by_block=[float(v) for v in np.mean([i["lin_iters_block"] for i in its],
+                                                                          axis=0)],
+                band_truncation_rel=trunc)
 
 
 def run_mixed(args, prob, torch):
@@ -345,6 +381,7 @@ def main():
     kblk = [float(v) for v in np.mean([i["lin_iters_block"] for i in infos], axis=0)]
 
     kts = {r: ctx.kernel_time(r) for r in (1, 2, 3)} if args.kernel_role else {}
+    final = {k: st[k].cpu().numpy() for k in ("vp", "phi", "B")} if args.full_domain else None
     ctx.close()
 
     def hbm(role, traffic=None):
@@ -363,6 +400,9 @@ def main():
     mixed = None
     if args.mixed:
         mixed = run_mixed(args, prob, torch)
+    full = None
+    if args.full_domain:
+        full = run_full_domain(args, prob, torch, final)
     learned = None
     if args.learned:
         log(args, "[bench] learned vs plain preconditioner ...")
@@ -395,6 +435,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels": others,
         "mixed_precision": mixed,
+        "full_domain_transport": full,
         "learned_vs_plain_precond": learned,
     }
     print(json.dumps(line), flush=True)

@@ -100,7 +100,9 @@ typedef struct {
                                     (block Jacobi plus the network correction, see
                                     eft_nn_init) for the momentum/mass block      */
     int32_t precision;           /* 0 FP64; 1 FP32 Jacobian values + FP64 rest     */
-    double band_flat;            /* band seed: |phi^n| < 1 - band_flat             */
+    double band_flat;            /* band seed: |phi^n| < 1 - band_flat; a negative
+                                    value seeds every cell, so the transport runs
+                                    on the whole mesh (no band)                   */
     int32_t band_cell;           /* mesh cells per grid cell and axis              */
     int32_t band_halo;           /* grid-cell layers added around the seeds        */
     int32_t mg_nu;               /* multigrid: smoothing sweeps before the coarse

@@ -861,3 +861,17 @@ def test_cavity_step_is_symmetric_on_the_mirrored_mesh():
     for comp, sign in zip(range(6), (1, 1, 1, 1, -1, -1)):
         d = B[mirror, comp] - sign * B[:, comp]
         assert np.abs(d).max() <= 1e-10, comp
+
+
+def test_band_flat_negative_is_the_whole_mesh():
+    """The band is the seeded grid cells dilated by the halo; with band_flat < 0
+    every element seeds (|phi| <= 1 < 1 - band_flat), so the band is the whole
+    mesh and no node is held fixed: the transport runs on the full domain."""
+    prob = W.cavity_disk_2d(n=64)
+    c = O.Case(prob)
+    be, fr = c.band(prob.phi[0])
+    assert 0 < int(be.sum()) < prob.n_elems          # the default band is a strict subset here
+    c_full = O.Case(prob, band_flat=-1.0)
+    be, fr = c_full.band(prob.phi[0])
+    assert int(be.sum()) == prob.n_elems and int(fr.sum()) == prob.n_nodes
+
