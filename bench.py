@@ -66,7 +66,7 @@ def parse():
                     help="MiB copied by a plain device copy before the timed steps (HBM counter calibration)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-full-domain", dest="full_domain", action="store_false",
-                    help="skip the full-domain (no band) transport run")
+                    help="skip the paper-literal variants (full-domain transport, background indicator)")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -152,15 +152,14 @@ def run_learned(args, torch):
                 speedup=round(el0 / el1, 4))
 
 
-def run_full_domain(args, prob, torch, band_final):
-    """The same warmup and timed steps with the transport on the whole mesh
-    (band_flat < 0: no band), and the band's truncation: the relative
-    difference of the final fields of the banded and the full-domain runs."""
+def run_variant(args, prob, torch, **over):
+    """The bench's warmup and timed steps on a variant of the workload;
+    returns the timing line and the final fields."""
     import numpy as np
     from paper_2402_10348_amd.eft import Context
     ctx = Context(prob, lin_rtol=1e-8, restart=args.restart, lin_maxit=20000, precision=args.precision,
                   precond=args.precond, mg_nu=args.mg_nu, mg_omega=args.mg_omega, mg_bf16=args.mg_bf16,
-                  mg_nu_post=args.mg_nu_post, mg_smoother=args.mg_smoother, band_flat=-1.0, **band_over(args))
+                  mg_nu_post=args.mg_nu_post, mg_smoother=args.mg_smoother, **dict(band_over(args), **over))
     st = ctx.device_state(prob.state_copy())
     t_sim, step_no = 0.0, 0
     for _ in range(args.warmup):
@@ -177,13 +176,33 @@ def run_full_domain(args, prob, torch, band_final):
     el = time.perf_counter() - t0
     fin = {k: st[k].cpu().numpy() for k in ("vp", "phi", "B")}
     ctx.close()
-    trunc = {k: float(np.linalg.norm(band_final[k] - fin[k]) / max(np.linalg.norm(fin[k]), 1e-300))
-             for k in fin}
-    return dict(value=round(args.steps / el, 4), unit="steps/s", ms_per_step=round(1e3 * el / args.steps, 2),
+    line = dict(value=round(args.steps / el, 4), unit="steps/s", ms_per_step=round(1e3 * el / args.steps, 2),
                 transport_ms_per_step=round(1e3 * float(np.mean([i["t_transport"] for i in its])), 2),
+                nl_iters_per_step=float(np.mean([i["nl_iters"] for i in its])),
                 krylov_iters_per_step_by_block=[float(v) for v in np.mean([i["lin_iters_block"] for i in its],
-                                                                          axis=0)],
-                band_truncation_rel=trunc)
+                                                                          axis=0)])
+    return line, fin
+
+
+def run_full_domain(args, prob, torch, band_final):
+    """The same steps with the transport on the whole mesh (band_flat < 0:
+    no band), and the band's truncation: the relative difference of the
+    final fields of the banded and the full-domain runs."""
+    import numpy as np
+    line, fin = run_variant(args, prob, torch, band_flat=-1.0)
+    line["band_truncation_rel"] = {k: float(np.linalg.norm(band_final[k] - fin[k]) /
+                                            max(np.linalg.norm(fin[k]), 1e-300)) for k in fin}
+    return line
+
+
+def run_background(args, prob, torch):
+    """The same steps with one transported order parameter per phase, the
+    background fluid included (two Allen-Cahn systems instead of one)."""
+    from paper_2402_10348_amd import workloads as W
+    pb = W.with_background_indicator(prob)
+    line, _ = run_variant(args, pb, torch)
+    line["indicators"] = pb.n_ind
+    return line
 
 
 def run_mixed(args, prob, torch):
@@ -400,9 +419,10 @@ def main():
     mixed = None
     if args.mixed:
         mixed = run_mixed(args, prob, torch)
-    full = None
+    full = background = None
     if args.full_domain:
         full = run_full_domain(args, prob, torch, final)
+        background = run_background(args, prob, torch)
     learned = None
     if args.learned:
         log(args, "[bench] learned vs plain preconditioner ...")
@@ -436,6 +456,7 @@ def main():
         "kernels": others,
         "mixed_precision": mixed,
         "full_domain_transport": full,
+        "background_indicator": background,
         "learned_vs_plain_precond": learned,
     }
     print(json.dumps(line), flush=True)

@@ -22,7 +22,7 @@ from __future__ import annotations
 
 import itertools
 import math
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 from typing import Dict, List, Optional
 
 import numpy as np
@@ -404,6 +404,35 @@ def floe_field_3d(nx: int = 256, ny: int = 128, nz: int = 64, dt: float = 1e-3, 
     params = Params(dt=dt, eps=eps, eta=1000.0, lin_rtol=lin_rtol)
     return _finish(f"floe_field_3d_{nx}x{ny}x{nz}", 3, xyz, conn, grid, (nodes, mask[nodes], val), phases,
                    (0.0, 0.0, -9.81), params, sdfs, eps, dict(h=h, floes=floes))
+
+
+# ------------------------------------------- paper-literal indicator set ----
+
+
+def with_background_indicator(prob: Problem) -> Problem:
+    """The variant with one transported order parameter per phase, the
+    background included (the default treats the background as the complement
+    of the others).  Its indicator starts from that complement: alpha_bg =
+    clamp(1 - sum of the other fractions), phi_bg = 2 alpha_bg - 1; the
+    indicators keep the phase order."""
+    bg = [i for i, p in enumerate(prob.phases) if not p.transported]
+    if not bg:
+        return prob
+    b = bg[0]
+    alpha = np.clip(0.5 * (1.0 + prob.phi), 0.0, 1.0)
+    a_bg = np.clip(1.0 - alpha.sum(axis=0), 0.0, 1.0)
+    rows, rates, k = [], [], 0
+    for i, p in enumerate(prob.phases):
+        if i == b:
+            rows.append(2.0 * a_bg - 1.0)
+            rates.append(np.zeros(prob.n_nodes))
+        elif p.transported:
+            rows.append(prob.phi[k])
+            rates.append(prob.phidot[k])
+            k += 1
+    phases = [replace(p, transported=1) if i == b else p for i, p in enumerate(prob.phases)]
+    return replace(prob, name=prob.name + "+background", phases=phases, phi=np.array(rows), phidot=np.array(rates),
+                   info=dict(prob.info))
 
 
 # ------------------------------------------------- random perturbations ----

@@ -404,6 +404,21 @@ def test_step_matches_oracle(torch_cuda, name, nsteps, over):
         assert e < 1e-10, k
 
 
+@pytest.mark.parametrize("name", ["sphere3d_6", "floes_32x16x8"])
+def test_background_indicator_step_matches_oracle(torch_cuda, name):
+    """Paper-literal indicator set: every phase, the background included,
+    carries its own transported order parameter (one more Allen-Cahn system
+    in the batched union); one step matches the oracle's."""
+    prob = W.with_background_indicator(CASES[name]())
+    say(f"[background indicator] case={name} indicators={prob.n_ind}")
+    over = dict(nl_fixed=2, lin_rtol=1e-13, restart=200, lin_maxit=40000)
+    st0, infos0, st, infos = _run_steps(prob, 1, **over)
+    for k in ("vp", "phi", "B"):
+        e = relnorm(st[k], st0[k])
+        say(f"  {k}: rel {e:.2e}")
+        assert e < 1e-10, k
+
+
 def test_full_domain_transport_matches_oracle(torch_cuda):
     """Paper-literal variant without the band (band_flat < 0 seeds every
     cell): two steps match the oracle's full-domain steps, and the band's

@@ -875,3 +875,15 @@ def test_band_flat_negative_is_the_whole_mesh():
     be, fr = c_full.band(prob.phi[0])
     assert int(be.sum()) == prob.n_elems and int(fr.sum()) == prob.n_nodes
 
+
+def test_background_indicator_starts_as_the_complement():
+    """Transporting the background phase's own order parameter (one indicator
+    per phase) starts from the complement fraction, so at t = 0 the nodal
+    fractions, rho and mu equal those of the complement treatment exactly."""
+    p0 = W.floe_field_3d(nx=32, ny=16, nz=8, n_floes=3)
+    p1 = W.with_background_indicator(p0)
+    assert p1.n_ind == p0.n_ind + 1 and all(ph.transported for ph in p1.phases)
+    a0, r0, m0 = O.Case(p0).nodal_properties(p0.phi)
+    a1, r1, m1 = O.Case(p1).nodal_properties(p1.phi)
+    assert np.array_equal(a0, a1) and np.array_equal(r0, r1) and np.array_equal(m0, m1)
+
