@@ -152,6 +152,29 @@ def run_learned(args, torch):
                 speedup=round(el0 / el1, 4))
 
 
+def diagnostics(ctx, st, prob):
+    """Wall time per call of the solid diagnostics on the final state: the
+    centre of mass of every indicator's region (Sec. 3) and one particle
+    tracking step (Appendix) of 16 particles around the sphere's centre."""
+    import numpy as np
+    reps = 20
+    ctx.center_of_mass(st["phi"])
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        xc, m = ctx.center_of_mass(st["phi"])
+    t_com = (time.perf_counter() - t0) / reps
+    rng = np.random.Generator(np.random.PCG64(0))
+    pts = 0.5 + rng.uniform(-0.15, 0.15, (16, prob.dim))
+    ctx.track_particles(st["vp"], pts, prob.params.dt)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pts, el = ctx.track_particles(st["vp"], pts, prob.params.dt)
+    t_pt = (time.perf_counter() - t0) / reps
+    return dict(center_of_mass_us=round(1e6 * t_com, 1), sphere_center=[round(float(v), 6) for v in xc[0]],
+                sphere_measure=float(m[0]), track_particles_us=round(1e6 * t_pt, 1), n_particles=16,
+                particles_found=int((el >= 0).sum()))
+
+
 def run_variant(args, prob, torch, **over):
     """The bench's warmup and timed steps on a variant of the workload;
     returns the timing line and the final fields."""
@@ -401,6 +424,7 @@ def main():
 
     kts = {r: ctx.kernel_time(r) for r in (1, 2, 3)} if args.kernel_role else {}
     final = {k: st[k].cpu().numpy() for k in ("vp", "phi", "B")} if args.full_domain else None
+    diag = diagnostics(ctx, st, prob)
     ctx.close()
 
     def hbm(role, traffic=None):
@@ -456,6 +480,7 @@ def main():
         "kernels": others,
         "mixed_precision": mixed,
         "full_domain_transport": full,
+        "diagnostics": diag,
         "background_indicator": background,
         "learned_vs_plain_precond": learned,
     }

@@ -251,6 +251,26 @@ eft_status eft_band_system(eft_ctx *ctx, const eft_state *level_n, const eft_ite
 eft_status eft_transport_solids(eft_ctx *ctx, const eft_state *level_n, eft_iterate *it,
                                 eft_transport_info *info);
 
+/* Centre of mass of the region of each order parameter (Sec. 3, rotating
+ * disk case): x_c = int x alpha dOmega / int alpha dOmega with alpha =
+ * clamp((1 + phi)/2, 0, 1) at the nodes, interpolated linearly; per element
+ * the degree-2 simplex rule (exact here); partial sums reduced in a fixed
+ * order.  phi [n_ind][N] is a DEVICE array; xc [n_ind][3] (components past
+ * dim are 0; xc = 0 where the measure is 0) and mass [n_ind] (int alpha
+ * dOmega) are HOST arrays.  Synchronizes the context stream. */
+eft_status eft_center_of_mass(eft_ctx *ctx, const double *phi, double *xc, double *mass);
+
+/* Particle tracking (Appendix, parallel particle tracking): for each of the
+ * n_p particles x [n_p][dim] (HOST, in/out) every element is tested; the
+ * particle lies in an element when all its P1 shape functions at x are in
+ * [-tol, 1 + tol] (the lowest element index wins on shared faces); it then
+ * moves by dt sum_a N_a(x) v_a with the velocities of vp [N][dim+1]
+ * (DEVICE; one explicit Euler step).  elem [n_p] (HOST) receives the
+ * element, or -1 when none contains x (x unchanged).  n_p <= 4096, tol >=
+ * 0; EFT_EINVAL otherwise.  Synchronizes the context stream. */
+eft_status eft_track_particles(eft_ctx *ctx, const double *vp, int32_t n_p, double dt, double tol, double *x,
+                               int32_t *elem);
+
 /* One time step (Sec. 2.4): predictor, bands, nonlinear iterations
  * NS -> indicators -> solids until every block satisfies ||dx||/||x|| <
  * nl_rtol or nl_max (exactly nl_fixed when > 0), corrector.  Advances *st in

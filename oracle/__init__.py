@@ -77,6 +77,8 @@ def lib():
         L.orc_beta.restype = C.c_double
         L.orc_step.restype = C.c_int
         L.orc_simplex_geometry.restype = C.c_double
+        L.orc_center_of_mass.restype = C.c_double
+        L.orc_track_particle.restype = C.c_int
     return _lib
 
 
@@ -262,6 +264,21 @@ class Case:
                               restart or self.P.restart, maxit or self.P.lin_maxit,
                               C.c_double(self.P.lin_rtol if rtol is None else rtol), C.byref(its), C.byref(rr))
         return x, dict(status=st, iters=its.value, relres=rr.value)
+
+    # ---------------------------------------------------------- diagnostics
+    def center_of_mass(self, phi):
+        """(x_c [dim], int alpha dOmega) of the region of one order parameter."""
+        xc = np.zeros(3)
+        m = lib().orc_center_of_mass(C.byref(self.P), _d(_f64(phi)), _d(xc))
+        return xc[:self.dim].copy(), m
+
+    def track_particle(self, vp, x, dt, tol=1e-10):
+        """Moves the particle x [dim] by one explicit step; returns (x_new,
+        element or -1, shape functions)."""
+        xx = _f64(np.array(x, dtype=np.float64).copy())
+        Nv = np.zeros(4)
+        e = lib().orc_track_particle(C.byref(self.P), _d(_f64(vp)), C.c_double(dt), C.c_double(tol), _d(xx), _d(Nv))
+        return xx, e, Nv[:self.dim + 1].copy()
 
     # --------------------------------------------------------------- step
     def step(self, st):

@@ -1414,3 +1414,106 @@ double orc_simplex_geometry(int dim, const double *X, double *dN, double *G)
 {
     return simplex_geometry(dim, (const double(*)[3])X, (double(*)[3])dN, (double(*)[3])G);
 }
+
+/* ------------------------------------------------------------ diagnostics */
+
+/* Centre of mass of the region of one order parameter (Sec. 3, the rotating
+ * disk case): x_c = (int x dOmega^s) / (int 1 dOmega^s) with dOmega^s =
+ * alpha(phi) dOmega, alpha = clamp((1 + phi)/2, 0, 1) at the nodes and
+ * interpolated linearly (READING: the nodal clamp of the phase fractions).
+ * On each simplex the integrands have degree <= 2 and the degree-2 rule
+ * integrates them exactly.  Writes xc[0..dim) and returns int alpha dOmega
+ * (xc = 0 when that is 0). */
+double orc_center_of_mass(const orc_problem *P, const double *phi, double *xc)
+{
+    int d = P->dim, nn = d + 1;
+    double bary[4][4], wq;
+    int nq = quad_rule(d, bary, &wq);
+    double m = 0.0, mx[3] = {0.0, 0.0, 0.0};
+    for (int e = 0; e < P->n_elems; ++e) {
+        int nodes[4];
+        double X[4][3], dN[4][3], G[3][3], al[4];
+        element_coords(P, e, nodes, X);
+        double vol = simplex_geometry(d, X, dN, G);
+        for (int a = 0; a < nn; ++a) al[a] = clamp01(0.5 * (1.0 + phi[nodes[a]]));
+        for (int q = 0; q < nq; ++q) {
+            double aq = 0.0, xq[3] = {0.0, 0.0, 0.0};
+            for (int a = 0; a < nn; ++a) {
+                aq += bary[q][a] * al[a];
+                for (int i = 0; i < d; ++i) xq[i] += bary[q][a] * X[a][i];
+            }
+            double w = wq * vol;
+            m += w * aq;
+            for (int i = 0; i < d; ++i) mx[i] += w * aq * xq[i];
+        }
+    }
+    for (int i = 0; i < d; ++i) xc[i] = m > 0.0 ? mx[i] / m : 0.0;
+    return m;
+}
+
+/* Inverse of an n x n matrix (n <= 4), Gauss-Jordan with partial pivoting;
+ * returns 0 when singular. */
+static int small_inverse(int n, const double A[4][4], double Ai[4][4])
+{
+    double M[4][8];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < 2 * n; ++j) M[i][j] = j < n ? A[i][j] : (j - n == i ? 1.0 : 0.0);
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        for (int i = k + 1; i < n; ++i)
+            if (fabs(M[i][k]) > fabs(M[p][k])) p = i;
+        if (M[p][k] == 0.0) return 0;
+        for (int j = 0; j < 2 * n; ++j) { double t = M[k][j]; M[k][j] = M[p][j]; M[p][j] = t; }
+        double inv = 1.0 / M[k][k];
+        for (int j = 0; j < 2 * n; ++j) M[k][j] *= inv;
+        for (int i = 0; i < n; ++i) {
+            if (i == k) continue;
+            double f = M[i][k];
+            for (int j = 0; j < 2 * n; ++j) M[i][j] -= f * M[k][j];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Ai[i][j] = M[i][n + j];
+    return 1;
+}
+
+/* Particle tracking (Appendix, parallel implementation of particle
+ * tracking): every simplex is tested; its shape-function coefficients are
+ * the columns of the inverse of the matrix whose rows are [x_a, y_a, (z_a,)
+ * 1], N_a(x) = sum_k C[k][a] [x, 1]_k, and x lies in the simplex when every
+ * N_a(x) is in [0, 1] (READING: within tol, for points on shared faces; the
+ * lowest element index wins).  The velocity is sum_a N_a v_a and the particle
+ * moves by dt v (READING: one explicit Euler step with the given nodal
+ * velocity).  vp is [N][dim+1] (velocity, pressure).  Returns the element,
+ * or -1 when none contains x (x unchanged); N_out[0..dim] receives the shape
+ * functions. */
+int orc_track_particle(const orc_problem *P, const double *vp, double dt, double tol, double *x, double *N_out)
+{
+    int d = P->dim, nn = d + 1;
+    for (int e = 0; e < P->n_elems; ++e) {
+        int nodes[4];
+        double X[4][3], A[4][4] = {{0.0}}, C[4][4];
+        element_coords(P, e, nodes, X);
+        for (int a = 0; a < nn; ++a) {
+            for (int i = 0; i < d; ++i) A[a][i] = X[a][i];
+            A[a][d] = 1.0;
+        }
+        if (!small_inverse(nn, A, C)) continue;
+        double Nv[4];
+        int inside = 1;
+        for (int a = 0; a < nn; ++a) {
+            double s = C[d][a];
+            for (int k = 0; k < d; ++k) s += C[k][a] * x[k];
+            Nv[a] = s;
+            if (s < -tol || s > 1.0 + tol) inside = 0;
+        }
+        if (!inside) continue;
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < nn; ++a)
+            for (int i = 0; i < d; ++i) v[i] += Nv[a] * vp[(size_t)nodes[a] * (d + 1) + i];
+        for (int i = 0; i < d; ++i) x[i] += dt * v[i];
+        for (int a = 0; a < nn; ++a) N_out[a] = Nv[a];
+        return e;
+    }
+    return -1;
+}

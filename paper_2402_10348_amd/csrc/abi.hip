@@ -107,6 +107,7 @@ void free_all(eft_ctx *ctx)
     if (ctx->hscal) (void)hipHostFree(ctx->hscal);
     if (ctx->htsc) (void)hipHostFree(ctx->htsc);
     fr(ctx->tsc);
+    fr(ctx->dg);
     for (eft_ctx::BandUnion *U : {&ctx->u_ac, &ctx->u_b}) {
         fr(U->rowptr); fr(U->col); fr(U->diag);
     }

@@ -222,6 +222,9 @@ struct eft_ctx {
     int32_t *mg_fidx = nullptr, *mg_free = nullptr;  // dof -> free index, free index -> dof
     int64_t mg_nd = 0;
     bool mg_f32_fresh = false;   // the finest level's FP32 copy was written by the assembly
+    // diagnostics workspace (centre of mass partials, particles)
+    double *dg = nullptr;
+    int64_t dg_cap = 0;
 };
 
 // ------------------------------------------------------------- helpers ----

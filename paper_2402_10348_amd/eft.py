@@ -84,7 +84,7 @@ EXPORTS = ["eft_create", "eft_destroy", "eft_last_error", "eft_set_params", "eft
            "eft_matrix_export", "eft_assemble", "eft_spmv", "eft_fgmres", "eft_bands_build", "eft_band_export",
            "eft_band_system", "eft_transport_solids", "eft_step", "eft_time_kernel",
            "eft_kernel_time_read", "eft_nn_init", "eft_nn_shape", "eft_nn_params", "eft_nn_harvest", "eft_nn_train",
-           "eft_nn_loss_grad", "eft_nn_apply"]
+           "eft_nn_loss_grad", "eft_nn_apply", "eft_center_of_mass", "eft_track_particles"]
 
 _lib = None
 
@@ -101,6 +101,7 @@ def load():
         getattr(L, name).restype = C.c_int
     L.eft_last_error.restype = C.c_char_p
     L.eft_create.argtypes = [C.POINTER(Mesh), C.POINTER(Materials), C.POINTER(Params), vp_, C.POINTER(vp_)]
+    L.eft_track_particles.argtypes = [vp_, vp_, C.c_int32, C.c_double, C.c_double, vp_, vp_]
     _lib = L
     return L
 
@@ -366,6 +367,27 @@ class Context:
                     band_nodes=list(info.band_nodes[:ni]), band_elems=list(info.band_elems[:ni]),
                     lin_iters=list(info.lin_iters[:ni + ns]), ratio=list(info.ratio[:ni + ns]),
                     ac_iters=info.ac_iters, b_iters=info.b_iters)
+
+    def center_of_mass(self, phi):
+        """Centre of mass [n_ind][dim] and measure int alpha dOmega [n_ind] of
+        the region of every order parameter of phi [n_ind][N] (device)."""
+        import numpy as np
+        K = self.n_ind
+        xc = np.zeros((max(K, 1), 3))
+        m = np.zeros(max(K, 1))
+        self._check(self.L.eft_center_of_mass(self.ctx, _ptr(phi), xc.ctypes.data_as(C.c_void_p),
+                                               m.ctypes.data_as(C.c_void_p)))
+        return xc[:K, :self.dim].copy(), m[:K].copy()
+
+    def track_particles(self, vp, x, dt, tol=1e-10):
+        """One explicit step of the particles x [n_p][dim] (host) in the
+        velocity of vp [N][dim+1] (device); returns (x_new, element or -1)."""
+        import numpy as np
+        xx = np.ascontiguousarray(np.array(x, dtype=np.float64).reshape(-1, self.dim))
+        el = np.zeros(xx.shape[0], dtype=np.int32)
+        self._check(self.L.eft_track_particles(self.ctx, _ptr(vp), xx.shape[0], float(dt), float(tol),
+                                                xx.ctypes.data_as(C.c_void_p), el.ctypes.data_as(C.c_void_p)))
+        return xx, el
 
     def step(self, st, t=0.0, step=0, dt=0.0):
         """Advance the device state dict in place by one time step."""

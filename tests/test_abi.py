@@ -84,3 +84,9 @@ def test_null_arguments_are_rejected(lib):
     assert lib.eft_time_kernel(None, 1) == 1
     lib.eft_kernel_time_read.restype = ctypes.c_int
     assert lib.eft_kernel_time_read(None, 1, None) == 1
+    lib.eft_center_of_mass.restype = ctypes.c_int
+    assert lib.eft_center_of_mass(None, None, None, None) == 1
+    lib.eft_track_particles.restype = ctypes.c_int
+    lib.eft_track_particles.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.eft_track_particles(None, None, 1, 0.1, 1e-10, None, None) == 1

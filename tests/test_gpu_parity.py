@@ -532,3 +532,50 @@ def test_full_size_cavity_step(torch_cuda):
     r = -R - ctx.spmv(xs)
     assert float(torch.linalg.norm(r) / torch.linalg.norm(R)) <= prob.params.lin_rtol * 1.0001
     ctx.close()
+
+
+# ------------------------------------------------------------ diagnostics --
+
+@pytest.mark.parametrize("name", ["disk2d_32", "sphere3d_8", "floes_32x16x8"])
+def test_center_of_mass_matches_oracle(torch_cuda, name):
+    """Centre of mass and measure of every indicator's region (Sec. 3
+    definition) against the oracle, at a perturbed state (FP64; the sums
+    run in different orders, 1e-12 relative)."""
+    prob = W.cavity_sphere_3d(n=8) if name == "sphere3d_8" else CASES[name]()
+    say(f"[centre of mass] case={name} indicators={prob.n_ind}")
+    lvl, _ = W.perturbed_state(prob, seed=3, amp_phi=0.05)
+    c = O.Case(prob)
+    ctx = ctx_for(prob)
+    xc, m = ctx.center_of_mass(ctx.tensor(lvl["phi"]))
+    for k in range(prob.n_ind):
+        x0, m0 = c.center_of_mass(lvl["phi"][k])
+        say(f"  indicator {k}: mass {m[k]:.6e} (oracle {m0:.6e}), x_c {xc[k]} (oracle {x0})")
+        assert abs(m[k] - m0) <= 1e-12 * abs(m0)
+        assert np.allclose(xc[k], x0, rtol=0, atol=1e-12)
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["disk2d_32", "sphere3d_8"])
+def test_particle_tracking_matches_oracle(torch_cuda, name):
+    """Particle tracking (Appendix): the element found and the moved
+    particle agree with the oracle's for random interior particles, mesh
+    nodes (shared by several elements: the lowest index wins on both sides)
+    and a point outside the mesh."""
+    prob = W.cavity_sphere_3d(n=8) if name == "sphere3d_8" else CASES[name]()
+    say(f"[particles] case={name}")
+    d = prob.dim
+    lvl, _ = W.perturbed_state(prob, seed=9, amp_v=0.5)
+    rng = np.random.Generator(np.random.PCG64(17))
+    pts = np.concatenate([rng.uniform(0.0, 1.0, (40, d)), prob.xyz[[0, 5, prob.n_nodes // 2, prob.n_nodes - 1]],
+                          np.full((1, d), 1.5)])
+    c = O.Case(prob)
+    ctx = ctx_for(prob)
+    xg, eg = ctx.track_particles(ctx.tensor(lvl["vp"]), pts, 0.01)
+    ctx.close()
+    for p in range(pts.shape[0]):
+        x0, e0, _ = c.track_particle(lvl["vp"], pts[p], 0.01)
+        assert eg[p] == e0, p
+        assert np.allclose(xg[p], x0, rtol=0, atol=1e-13), p
+    assert eg[-1] == -1 and np.array_equal(xg[-1], pts[-1])
+    say(f"  {pts.shape[0]} particles agree; elements {eg[:5]} ...")
+

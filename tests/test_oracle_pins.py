@@ -887,3 +887,55 @@ def test_background_indicator_starts_as_the_complement():
     a1, r1, m1 = O.Case(p1).nodal_properties(p1.phi)
     assert np.array_equal(a0, a1) and np.array_equal(r0, r1) and np.array_equal(m0, m1)
 
+
+
+# ------------------------------------------------------------ diagnostics --
+
+def test_center_of_mass_closed_forms():
+    """Centre of mass of alpha dOmega on the unit cube (Sec. 3 definition):
+    alpha = 1 gives the centroid (1/2, 1/2, 1/2) and measure 1; alpha = x
+    (phi = 2x - 1, linear, so its P1 interpolant is exact) gives measure 1/2
+    and x_c = (int x^2 / int x, 1/2, 1/2) = (2/3, 1/2, 1/2); phi = -1 gives
+    measure 0."""
+    prob = W.cavity_sphere_3d(n=6)
+    c = O.Case(prob)
+    x = prob.xyz
+    xc, m = c.center_of_mass(np.ones(prob.n_nodes))
+    assert abs(m - 1.0) < 1e-13 and np.allclose(xc, [0.5, 0.5, 0.5], atol=1e-13)
+    xc, m = c.center_of_mass(2.0 * x[:, 0] - 1.0)
+    assert abs(m - 0.5) < 1e-13 and np.allclose(xc, [2.0 / 3.0, 0.5, 0.5], atol=1e-13)
+    xc, m = c.center_of_mass(-np.ones(prob.n_nodes))
+    assert m == 0.0 and np.all(xc == 0.0)
+    # 2D: alpha = y on the unit square: measure 1/2, y_c = 2/3
+    p2 = W.cavity_disk_2d(n=8)
+    xc, m = O.Case(p2).center_of_mass(2.0 * p2.xyz[:, 1] - 1.0)
+    assert abs(m - 0.5) < 1e-13 and np.allclose(xc, [0.5, 2.0 / 3.0], atol=1e-13)
+
+
+def test_particle_tracking_linear_fields():
+    """Appendix particle tracking: P1 interpolation reproduces a linear
+    velocity field exactly, so one step moves a particle by dt v(x) with
+    v = A x + c; the element found contains x (shape functions in [0, 1],
+    summing to 1); a point outside the mesh is not found and stays."""
+    prob = W.cavity_sphere_3d(n=6)
+    c = O.Case(prob)
+    A = np.array([[0.1, -0.2, 0.3], [0.05, 0.0, -0.1], [0.2, 0.1, 0.0]])
+    cvec = np.array([0.3, -0.1, 0.2])
+    vp = np.zeros((prob.n_nodes, 4))
+    vp[:, :3] = prob.xyz @ A.T + cvec
+    rng = np.random.Generator(np.random.PCG64(5))
+    for _ in range(20):
+        x0 = rng.uniform(0.0, 1.0, 3)
+        x1, e, Nv = c.track_particle(vp, x0, 0.01)
+        assert e >= 0
+        assert np.all(Nv >= -1e-10) and np.all(Nv <= 1 + 1e-10) and abs(Nv.sum() - 1.0) < 1e-12
+        nodes = prob.conn[e]
+        assert np.allclose(Nv @ prob.xyz[nodes], x0, atol=1e-12)
+        assert np.allclose(x1, x0 + 0.01 * (A @ x0 + cvec), atol=1e-13)
+    x1, e, _ = c.track_particle(vp, [1.5, 0.5, 0.5], 0.01)
+    assert e == -1 and np.array_equal(x1, [1.5, 0.5, 0.5])
+    # a mesh node lies in every incident element: the lowest index is taken
+    node = 7 * 7 * 3 + 7 * 3 + 3
+    x1, e, Nv = c.track_particle(vp, prob.xyz[node], 0.0)
+    inc = np.nonzero((prob.conn == node).any(axis=1))[0]
+    assert e == inc.min() and abs(Nv.max() - 1.0) < 1e-12
