@@ -170,9 +170,30 @@ def diagnostics(ctx, st, prob):
     for _ in range(reps):
         pts, el = ctx.track_particles(st["vp"], pts, prob.params.dt)
     t_pt = (time.perf_counter() - t0) / reps
-    return dict(center_of_mass_us=round(1e6 * t_com, 1), sphere_center=[round(float(v), 6) for v in xc[0]],
+    # order parameter of a triangulated sphere (r = 1/4, 20,480 triangles)
+    # on the 64^3 mesh, 8^3 grid cells, against tanh of the exact distance;
+    # the centre is moved off the mesh planes by fractions of a cell so that
+    # no +X ray is tangent to the sphere at a vertex (such a ray counts as a
+    # crossing in the method)
+    from paper_2402_10348_amd import workloads as W
+    ctr = np.array([0.5 + 1.0 / 192, 0.5 + 1.0 / 320, 0.5 + 1.0 / 448])
+    v, t = W.icosphere(0.25, ctr, 5)
+    eps = 1.5 / 64
+    ctx.init_phase(v, t, eps, [8, 8, 8])
+    torch = ctx.torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        phi, cr = ctx.init_phase(v, t, eps, [8, 8, 8])
+    t_init = (time.perf_counter() - t0) / 5
+    d = 0.25 - np.linalg.norm(prob.xyz - ctr, axis=1)
+    ref = np.tanh(d / (np.sqrt(2.0) * eps))
+    e2 = float(np.linalg.norm(phi.cpu().numpy() - ref) / np.linalg.norm(ref))
+    return dict(center_of_mass_us=round(1e6 * t_com, 1), sphere_center=[round(float(v_), 6) for v_ in xc[0]],
                 sphere_measure=float(m[0]), track_particles_us=round(1e6 * t_pt, 1), n_particles=16,
-                particles_found=int((el >= 0).sum()))
+                particles_found=int((el >= 0).sum()),
+                init_phase=dict(ms=round(1e3 * t_init, 3), triangles=int(t.shape[0]), grid_cells=[8, 8, 8],
+                                rel_l2_error_vs_exact_sdf=e2, most_crossings=int(cr[0])))
 
 
 def run_variant(args, prob, torch, **over):

@@ -271,6 +271,32 @@ eft_status eft_center_of_mass(eft_ctx *ctx, const double *phi, double *xc, doubl
 eft_status eft_track_particles(eft_ctx *ctx, const double *vp, int32_t n_p, double dt, double tol, double *x,
                                int32_t *elem);
 
+/* Closed triangle surface mesh (HOST arrays): vert [n_vert][3], tri
+ * [n_tri][3] vertex indices. */
+typedef struct {
+    int32_t n_vert, n_tri;
+    const double *vert;
+    const int32_t *tri;
+} eft_surface;
+
+/* Order parameter of the solid bounded by a closed surface mesh, on the
+ * mesh nodes (the paper's phase-field interface processing: grid cells,
+ * Algorithm "distance", ray casting with non-duplicated plane partitioning,
+ * Algorithm "sign"; 3D only, EFT_EUNSUPPORTED in 2D).  ncell[3] grid cells
+ * over the nodes' bounding box; a triangle belongs to the cells its bounding
+ * box grown by 3 eps overlaps.  Nodes of cells with triangles: |phi| =
+ * tanh(|d| / (sqrt2 eps)), |d| the shortest distance to those triangles'
+ * vertices; other nodes |phi| = 1.  Sign by a +X ray, crossings in the Y-Z
+ * projection when A1 + A2 + A3 - A0 <= 2 chi (areas), classified as element,
+ * edge or node crosses and counted once per vertex-id combination; odd:
+ * inside, phi > 0.  A ray that only touches the surface at a vertex counts
+ * as a crossing (the method's limit).  phi [N] is a DEVICE array (output).
+ * crossings [2] (HOST, may be NULL): the most distinct crossings of one ray
+ * and 1 when a ray had more than 32 (its count truncated).  Allocates and
+ * frees its own temporaries; synchronizes the context stream. */
+eft_status eft_init_phase(eft_ctx *ctx, const eft_surface *surf, double eps, const int32_t *ncell, double chi,
+                          double *phi, int32_t *crossings);
+
 /* One time step (Sec. 2.4): predictor, bands, nonlinear iterations
  * NS -> indicators -> solids until every block satisfies ||dx||/||x|| <
  * nl_rtol or nl_max (exactly nl_fixed when > 0), corrector.  Advances *st in

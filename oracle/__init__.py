@@ -280,6 +280,18 @@ class Case:
         e = lib().orc_track_particle(C.byref(self.P), _d(_f64(vp)), C.c_double(dt), C.c_double(tol), _d(xx), _d(Nv))
         return xx, e, Nv[:self.dim + 1].copy()
 
+    def init_phase(self, vert, tri, eps, ncell, chi=1e-12):
+        """Order parameter of the solid inside the closed surface (vert
+        [nv][3], tri [nt][3]) on the mesh nodes (3D); returns (phi, stats)."""
+        vert = _f64(vert)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        nc = np.ascontiguousarray(ncell, dtype=np.int32)
+        phi = np.zeros(self.N)
+        stats = np.zeros(2, dtype=np.int32)
+        lib().orc_init_phase(C.byref(self.P), vert.shape[0], _d(vert), tri.shape[0], _i(tri), C.c_double(eps),
+                             _i(nc), C.c_double(chi), _d(phi), _i(stats))
+        return phi, stats
+
     # --------------------------------------------------------------- step
     def step(self, st):
         """Advance the state dict in place by one time step; returns info."""

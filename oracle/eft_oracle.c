@@ -1517,3 +1517,191 @@ int orc_track_particle(const orc_problem *P, const double *vp, double dt, double
     }
     return -1;
 }
+
+/* ----------------------------------------- phase-field initialization -- */
+/*
+ * Order parameter of a solid given by a closed triangle surface mesh (Sec.
+ * "phase-field interface processing": grid cells, Algorithm distance, ray
+ * casting with non-duplicated plane partitioning, Algorithm sign), 3D only.
+ *
+ * Grid cells: ncell[] cells over the bounding box of the Eulerian nodes;
+ * a point goes to cell floor((x - x_min) / h) per axis (READING: the paper
+ * writes floor(x / h) for a box starting at 0; the top face is clamped into
+ * the last cell).  Each triangle is assigned to every cell its bounding box,
+ * grown by 3 eps, overlaps.
+ * Distance: a node of a cell with triangles takes |d| = the shortest
+ * distance to the vertices of those triangles and |phi| = tanh(|d| / (sqrt2
+ * eps)); nodes of cells without triangles take |phi| = 1.
+ * Sign: a ray from the node in +X.  Candidates are the triangles of the
+ * cells (i..n_x-1, j, k); in the node's own cell only those with a vertex at
+ * x > x_p.  Projected to the Y-Z plane, A0 is the triangle's area and A_i
+ * the area of the node with the edge opposite vertex i; the ray crosses when
+ * A1 + A2 + A3 - A0 <= 2 chi (READING: and the crossing point, interpolated
+ * with the weights A_i / A0, lies at x > x_p; a projected area A0 <= chi is
+ * skipped).  The crossing is an element cross (all A_i > chi, vertex ids
+ * i, j, k recorded), an edge cross (one A_i <= chi: the two ids of the edge
+ * opposite i) or a node cross (two A_i <= chi: the remaining vertex id);
+ * only distinct id combinations count.  Odd count: inside, phi > 0.  A cell
+ * without triangles is decided by its lowest-index node and the sign copied
+ * to its other nodes.
+ * stats[0] = most distinct crossings of one ray, stats[1] = 1 when a ray had
+ * more than 32 (then the count is truncated).
+ */
+static double area2d(const double a[2], const double b[2], const double c[2])
+{
+    return 0.5 * fabs((b[0] - a[0]) * (c[1] - a[1]) - (c[0] - a[0]) * (b[1] - a[1]));
+}
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+void orc_init_phase(const orc_problem *P, int nvert, const double *vert, int ntri, const int *tri, double eps,
+                    const int *ncell, double chi, double *phi, int *stats)
+{
+    int N = P->n_nodes;
+    double lo[3], hi[3], h[3];
+    for (int i = 0; i < 3; ++i) { lo[i] = 1e300; hi[i] = -1e300; }
+    for (int p = 0; p < N; ++p)
+        for (int i = 0; i < 3; ++i) {
+            double x = P->xyz[(size_t)p * 3 + i];
+            if (x < lo[i]) lo[i] = x;
+            if (x > hi[i]) hi[i] = x;
+        }
+    for (int i = 0; i < 3; ++i) h[i] = (hi[i] - lo[i]) / ncell[i];
+    int nx = ncell[0], ny = ncell[1], nz = ncell[2];
+    size_t nc = (size_t)nx * ny * nz;
+    /* triangles of each cell */
+    int *cnt = calloc(nc, sizeof(int)), *off = malloc(sizeof(int) * (nc + 1));
+    int rng[6];
+    for (int pass = 0; pass < 2; ++pass) {
+        int *list = NULL;
+        if (pass == 1) {
+            off[0] = 0;
+            for (size_t c = 0; c < nc; ++c) off[c + 1] = off[c] + cnt[c];
+            list = malloc(sizeof(int) * (size_t)(off[nc] > 0 ? off[nc] : 1));
+            memset(cnt, 0, nc * sizeof(int));
+        }
+        for (int t = 0; t < ntri; ++t) {
+            for (int i = 0; i < 3; ++i) {
+                double mn = 1e300, mx = -1e300;
+                for (int v = 0; v < 3; ++v) {
+                    double x = vert[(size_t)tri[(size_t)t * 3 + v] * 3 + i];
+                    if (x < mn) mn = x;
+                    if (x > mx) mx = x;
+                }
+                rng[2 * i] = clampi((int)floor((mn - 3.0 * eps - lo[i]) / h[i]), 0, ncell[i] - 1);
+                rng[2 * i + 1] = clampi((int)floor((mx + 3.0 * eps - lo[i]) / h[i]), 0, ncell[i] - 1);
+            }
+            for (int k = rng[4]; k <= rng[5]; ++k)
+                for (int j = rng[2]; j <= rng[3]; ++j)
+                    for (int i = rng[0]; i <= rng[1]; ++i) {
+                        size_t c = (size_t)i + (size_t)nx * (j + (size_t)ny * k);
+                        if (pass == 1) list[off[c] + cnt[c]] = t;
+                        cnt[c]++;
+                    }
+        }
+        if (pass == 1) {
+            /* node cells */
+            int *ncl = malloc(sizeof(int) * (size_t)N);
+            int *rep = malloc(sizeof(int) * nc);
+            for (size_t c = 0; c < nc; ++c) rep[c] = -1;
+            for (int p = 0; p < N; ++p) {
+                int ci[3];
+                for (int i = 0; i < 3; ++i)
+                    ci[i] = clampi((int)floor((P->xyz[(size_t)p * 3 + i] - lo[i]) / h[i]), 0, ncell[i] - 1);
+                size_t c = (size_t)ci[0] + (size_t)nx * (ci[1] + (size_t)ny * ci[2]);
+                ncl[p] = (int)c;
+                if (rep[c] < 0) rep[c] = p;
+            }
+            /* sign of one node by ray casting with the partitioning */
+            stats[0] = 0;
+            stats[1] = 0;
+            int *csign = calloc(nc, sizeof(int));
+            for (int pass2 = 0; pass2 < 2; ++pass2)
+                for (int p = 0; p < N; ++p) {
+                    size_t c = (size_t)ncl[p];
+                    int interface = off[c + 1] > off[c];
+                    /* pass 0: interface-cell nodes and cell representatives; pass 1: copy */
+                    if (pass2 == 1) {
+                        if (!interface) phi[p] = csign[c] > 0 ? 1.0 : -1.0;
+                        continue;
+                    }
+                    if (!interface && rep[c] != p) continue;
+                    const double *xp = P->xyz + (size_t)p * 3;
+                    int ci = (int)(c % nx), cj = (int)((c / nx) % ny), ck = (int)(c / ((size_t)nx * ny));
+                    int tup[32][3], ntup = 0, over = 0;
+                    for (int ii = ci; ii < nx; ++ii) {
+                        size_t cc = (size_t)ii + (size_t)nx * (cj + (size_t)ny * ck);
+                        for (int q = off[cc]; q < off[cc + 1]; ++q) {
+                            int t = list[q];
+                            const int *tv = tri + (size_t)t * 3;
+                            double X[3][3];
+                            for (int v = 0; v < 3; ++v)
+                                for (int i = 0; i < 3; ++i) X[v][i] = vert[(size_t)tv[v] * 3 + i];
+                            if (ii == ci && !(X[0][0] > xp[0] || X[1][0] > xp[0] || X[2][0] > xp[0])) continue;
+                            double pv[3][2], pp[2] = {xp[1], xp[2]};
+                            for (int v = 0; v < 3; ++v) { pv[v][0] = X[v][1]; pv[v][1] = X[v][2]; }
+                            double A0 = area2d(pv[0], pv[1], pv[2]);
+                            if (A0 <= chi) continue;
+                            double A[3] = {area2d(pp, pv[1], pv[2]), area2d(pp, pv[2], pv[0]), area2d(pp, pv[0], pv[1])};
+                            if (A[0] + A[1] + A[2] - A0 > 2.0 * chi) continue;
+                            double xc = (A[0] * X[0][0] + A[1] * X[1][0] + A[2] * X[2][0]) / A0;
+                            if (!(xc > xp[0])) continue;
+                            int small[3], ns = 0;
+                            for (int v = 0; v < 3; ++v) { small[v] = A[v] <= chi; ns += small[v]; }
+                            int id[3] = {-1, -1, -1};
+                            if (ns == 0) {
+                                id[0] = tv[0]; id[1] = tv[1]; id[2] = tv[2];
+                            } else if (ns == 1) {
+                                int m = small[0] ? 0 : (small[1] ? 1 : 2), o = 0;
+                                for (int v = 0; v < 3; ++v)
+                                    if (v != m) id[o++] = tv[v];
+                            } else if (ns == 2) {
+                                int m = !small[0] ? 0 : (!small[1] ? 1 : 2);
+                                id[0] = tv[m];
+                            } else {
+                                continue;
+                            }
+                            /* sort ids (descending, -1 last) */
+                            for (int a = 0; a < 3; ++a)
+                                for (int b = a + 1; b < 3; ++b)
+                                    if (id[b] > id[a]) { int s = id[a]; id[a] = id[b]; id[b] = s; }
+                            int dup = 0;
+                            for (int u = 0; u < ntup && !dup; ++u)
+                                dup = tup[u][0] == id[0] && tup[u][1] == id[1] && tup[u][2] == id[2];
+                            if (dup) continue;
+                            if (ntup < 32) {
+                                tup[ntup][0] = id[0]; tup[ntup][1] = id[1]; tup[ntup][2] = id[2];
+                                ++ntup;
+                            } else {
+                                over = 1;
+                            }
+                        }
+                    }
+                    if (ntup > stats[0]) stats[0] = ntup;
+                    if (over) stats[1] = 1;
+                    int s = (ntup % 2 == 1) ? 1 : -1;
+                    if (!interface) {
+                        csign[c] = s;
+                        continue;
+                    }
+                    /* distance to the vertices of the cell's triangles */
+                    double d2 = 1e300;
+                    for (int q = off[c]; q < off[c + 1]; ++q)
+                        for (int v = 0; v < 3; ++v) {
+                            const double *y = vert + (size_t)tri[(size_t)list[q] * 3 + v] * 3;
+                            double dd = 0.0;
+                            for (int i = 0; i < 3; ++i) dd += (xp[i] - y[i]) * (xp[i] - y[i]);
+                            if (dd < d2) d2 = dd;
+                        }
+                    phi[p] = s * tanh(sqrt(d2) / (sqrt(2.0) * eps));
+                }
+            free(csign);
+            free(ncl);
+            free(rep);
+            free(list);
+        }
+    }
+    free(cnt);
+    free(off);
+    (void)nvert;
+}

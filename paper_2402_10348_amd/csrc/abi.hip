@@ -310,6 +310,10 @@ eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *
             lo[i] = std::min(lo[i], mesh->xyz[p * d + i]);
             hi[i] = std::max(hi[i], mesh->xyz[p * d + i]);
         }
+    for (int i = 0; i < d; ++i) {
+        ctx->bb_lo[i] = lo[i];
+        ctx->bb_hi[i] = hi[i];
+    }
     double hg[3] = {1, 1, 1};
     for (int i = 0; i < 3; ++i) ctx->ng[i] = 1;
     for (int i = 0; i < d; ++i) {

@@ -225,6 +225,8 @@ struct eft_ctx {
     // diagnostics workspace (centre of mass partials, particles)
     double *dg = nullptr;
     int64_t dg_cap = 0;
+    // bounding box of the mesh nodes (host)
+    double bb_lo[3] = {0, 0, 0}, bb_hi[3] = {0, 0, 0};
 };
 
 // ------------------------------------------------------------- helpers ----

@@ -84,7 +84,7 @@ EXPORTS = ["eft_create", "eft_destroy", "eft_last_error", "eft_set_params", "eft
            "eft_matrix_export", "eft_assemble", "eft_spmv", "eft_fgmres", "eft_bands_build", "eft_band_export",
            "eft_band_system", "eft_transport_solids", "eft_step", "eft_time_kernel",
            "eft_kernel_time_read", "eft_nn_init", "eft_nn_shape", "eft_nn_params", "eft_nn_harvest", "eft_nn_train",
-           "eft_nn_loss_grad", "eft_nn_apply", "eft_center_of_mass", "eft_track_particles"]
+           "eft_nn_loss_grad", "eft_nn_apply", "eft_center_of_mass", "eft_track_particles", "eft_init_phase"]
 
 _lib = None
 
@@ -102,8 +102,13 @@ def load():
     L.eft_last_error.restype = C.c_char_p
     L.eft_create.argtypes = [C.POINTER(Mesh), C.POINTER(Materials), C.POINTER(Params), vp_, C.POINTER(vp_)]
     L.eft_track_particles.argtypes = [vp_, vp_, C.c_int32, C.c_double, C.c_double, vp_, vp_]
+    L.eft_init_phase.argtypes = [vp_, C.POINTER(Surface), C.c_double, vp_, C.c_double, vp_, vp_]
     _lib = L
     return L
+
+
+class Surface(C.Structure):
+    _fields_ = [("n_vert", C.c_int32), ("n_tri", C.c_int32), ("vert", C.c_void_p), ("tri", C.c_void_p)]
 
 
 class EftError(RuntimeError):
@@ -388,6 +393,20 @@ class Context:
         self._check(self.L.eft_track_particles(self.ctx, _ptr(vp), xx.shape[0], float(dt), float(tol),
                                                 xx.ctypes.data_as(C.c_void_p), el.ctypes.data_as(C.c_void_p)))
         return xx, el
+
+    def init_phase(self, vert, tri, eps, ncell, chi=1e-12):
+        """Order parameter [N] (device tensor) of the solid inside the closed
+        surface (vert [nv][3], tri [nt][3], host); returns (phi, crossings)."""
+        import numpy as np
+        v = np.ascontiguousarray(vert, dtype=np.float64)
+        t = np.ascontiguousarray(tri, dtype=np.int32)
+        nc = np.ascontiguousarray(ncell, dtype=np.int32)
+        S = Surface(v.shape[0], t.shape[0], v.ctypes.data_as(C.c_void_p), t.ctypes.data_as(C.c_void_p))
+        phi = self.torch.empty(self.N, dtype=self.torch.float64, device=self.dev)
+        cr = np.zeros(2, dtype=np.int32)
+        self._check(self.L.eft_init_phase(self.ctx, C.byref(S), float(eps), nc.ctypes.data_as(C.c_void_p),
+                                           float(chi), _ptr(phi), cr.ctypes.data_as(C.c_void_p)))
+        return phi, cr
 
     def step(self, st, t=0.0, step=0, dt=0.0):
         """Advance the device state dict in place by one time step."""

@@ -406,6 +406,65 @@ def floe_field_3d(nx: int = 256, ny: int = 128, nz: int = 64, dt: float = 1e-3, 
                    (0.0, 0.0, -9.81), params, sdfs, eps, dict(h=h, floes=floes))
 
 
+# ------------------------------------------------ closed surface meshes ----
+
+
+def icosphere(radius: float, center, level: int):
+    """Triangulated sphere: the icosahedron with every face split into four
+    `level` times and the vertices pushed onto the sphere.  Returns (vert
+    [nv][3], tri [nt][3]); edge length about 1.05 r / 2^level."""
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    f = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2), (10, 7, 6),
+         (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11), (6, 2, 10),
+         (8, 6, 7), (9, 8, 1)]
+    verts = [np.array(p, dtype=np.float64) / np.linalg.norm(p) for p in v]
+    for _ in range(level):
+        mid, nf = {}, []
+
+        def midpoint(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in mid:
+                m = verts[a] + verts[b]
+                verts.append(m / np.linalg.norm(m))
+                mid[key] = len(verts) - 1
+            return mid[key]
+        for a, b, c in f:
+            ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        f = nf
+    vert = np.array(verts) * radius + np.asarray(center, dtype=np.float64)
+    return vert, np.array(f, dtype=np.int32)
+
+
+def cube_surface(lo, hi, m: int):
+    """Surface of the box [lo, hi]^3: every face an m x m grid of squares,
+    each split into two triangles (shared vertices).  Returns (vert, tri)."""
+    lo, hi = float(lo), float(hi)
+    g = np.linspace(lo, hi, m + 1)
+    index, verts, tris = {}, [], []
+
+    def vid(p):
+        key = tuple(np.round(p, 12))
+        if key not in index:
+            index[key] = len(verts)
+            verts.append(p)
+        return index[key]
+    for axis in range(3):
+        for side in (lo, hi):
+            a1, a2 = [k for k in range(3) if k != axis]
+            for i in range(m):
+                for j in range(m):
+                    q = []
+                    for di, dj in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                        p = np.zeros(3)
+                        p[axis], p[a1], p[a2] = side, g[i + di], g[j + dj]
+                        q.append(vid(p))
+                    tris += [(q[0], q[1], q[2]), (q[0], q[2], q[3])]
+    return np.array(verts), np.array(tris, dtype=np.int32)
+
+
 # ------------------------------------------- paper-literal indicator set ----
 
 
