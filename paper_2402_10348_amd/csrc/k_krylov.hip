@@ -99,27 +99,32 @@ __global__ __launch_bounds__(RB) void k_maxpy(const double *__restrict__ V, int6
     }
 }
 
-// Givens update of column j of H (in place), residual estimate, convergence
-// and breakdown flags; one thread.
-__device__ void givens_column(double *small, int m, int j, int32_t *flag)
+// Givens update of column j (col[0..j+1], in LDS), residual estimate,
+// convergence and breakdown flags; one thread.  cs, sn are the earlier
+// rotations (LDS copies); the new rotation, g and the column go to small.
+__device__ void givens_column(double *small, int m, int j, double *col, const double *csl, const double *snl,
+                              int32_t *flag)
 {
     Small L{m};
     double *H = small + L.H(), *cs = small + L.cs(), *sn = small + L.sn(), *g = small + L.g();
     for (int i = 0; i < j; ++i) {
-        const double a = H[(int64_t)i * m + j], b = H[(int64_t)(i + 1) * m + j];
-        H[(int64_t)i * m + j] = cs[i] * a + sn[i] * b;
-        H[(int64_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+        const double a = col[i], b = col[i + 1];
+        col[i] = csl[i] * a + snl[i] * b;
+        col[i + 1] = -snl[i] * a + csl[i] * b;
     }
-    const double a = H[(int64_t)j * m + j], b = H[(int64_t)(j + 1) * m + j];
+    const double a = col[j], b = col[j + 1];
     const double hn = b;
     small[L.sc() + 4] = hn;   // ||w||, kept for the normalization of v_{j+1}
     const double den = sqrt(a * a + b * b);
-    cs[j] = den == 0.0 ? 1.0 : a / den;
-    sn[j] = den == 0.0 ? 0.0 : b / den;
-    H[(int64_t)j * m + j] = cs[j] * a + sn[j] * b;
-    H[(int64_t)(j + 1) * m + j] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
+    const double c = den == 0.0 ? 1.0 : a / den, sv = den == 0.0 ? 0.0 : b / den;
+    cs[j] = c;
+    sn[j] = sv;
+    col[j] = c * a + sv * b;
+    col[j + 1] = 0.0;
+    for (int i = 0; i <= j + 1; ++i) H[(int64_t)i * m + j] = col[i];
+    const double gj = g[j];
+    g[j + 1] = -sv * gj;
+    g[j] = c * gj;
     small[L.sc() + 5] = fabs(g[j + 1]);   // residual estimate after column j
     flag[1] = j + 1;
     const double tol = small[L.sc() + 2];
@@ -135,31 +140,40 @@ __device__ void givens_column(double *small, int m, int j, int32_t *flag)
 // from the update's partials, then pass 1 stores the dots as the column and
 // decides on pass 2 (taken when pass 1 removed more than half of ||w||^2);
 // the pass that completes the column sets H[j+1][j] = ||w|| and applies the
-// Givens rotations.
+// Givens rotations.  The column and the earlier rotations are staged in LDS
+// by the whole workgroup, so the serial rotation loop reads no global memory.
 __global__ __launch_bounds__(RB) void k_close_pass(const double *__restrict__ part, int nblk, double *small, int m,
                                                    int j, int pass, int32_t *flag)
 {
     __shared__ double lds[RB / 64];
+    __shared__ double col[EFT_MAX_RESTART + 2], csl[EFT_MAX_RESTART], snl[EFT_MAX_RESTART];
     if (flag[0] == 0 || (pass == 2 && flag[3] == 0)) return;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += RB) s += part[b];
-    s = block_sum<RB>(s, lds);
-    if (threadIdx.x != 0) return;
     Small L{m};
     double *H = small + L.H();
+    const double *h = small + L.h(), *h2 = small + L.h2();
+    for (int i = threadIdx.x; i <= j; i += RB) {
+        col[i] = pass == 1 ? h[i] : H[(int64_t)i * m + j] + h2[i];
+        if (i < j) {
+            csl[i] = small[L.cs() + i];
+            snl[i] = small[L.sn() + i];
+        }
+    }
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += RB) s += part[b];
+    s = block_sum<RB>(s, lds);   // (its barriers also publish col, csl, snl)
+    if (threadIdx.x != 0) return;
     if (pass == 1) {
-        const double *h = small + L.h();
-        for (int i = 0; i <= j; ++i) H[(int64_t)i * m + j] = h[i];
         small[L.sc() + 0] = s;
         flag[3] = (s < 0.5 * h[j + 1]) ? 1 : 0;
-        if (flag[3]) return;   // pass 2 completes the column
+        if (flag[3]) {   // pass 2 completes the column: store the dots
+            for (int i = 0; i <= j; ++i) H[(int64_t)i * m + j] = col[i];
+            return;
+        }
     } else {
-        const double *h2 = small + L.h2();
-        for (int i = 0; i <= j; ++i) H[(int64_t)i * m + j] += h2[i];
         small[L.sc() + 1] = s;
     }
-    H[(int64_t)(j + 1) * m + j] = sqrt(s);
-    givens_column(small, m, j, flag);
+    col[j + 1] = sqrt(s);
+    givens_column(small, m, j, col, csl, snl, flag);
 }
 
 // v_{j+1} = w / H[j+1][j]

@@ -129,14 +129,20 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
     }
 }
 
-// out[i] (+)= sum over splits z of part[z][i]
+// out[i] (+)= sum over splits z of part[z][i]; eight running sums per
+// thread keep eight loads in flight (fixed order: deterministic)
 __global__ void k_sum_splits(const float *part, int64_t nsplit, int64_t n, float *out, int accumulate)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    float s = 0.0f;
-    for (int64_t z = 0; z < nsplit; ++z) s += part[z * n + i];
-    out[i] = accumulate ? out[i] + s : s;
+    float s[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    int64_t z = 0;
+    for (; z + 8 <= nsplit; z += 8)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += part[(z + u) * n + i];
+    for (; z < nsplit; ++z) s[0] += part[z * n + i];
+    const float t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    out[i] = accumulate ? out[i] + t : t;
 }
 
 // --------------------------------------------------------- node kernels --
