@@ -93,6 +93,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
     eft_f16v acc0, acc1;
 #pragma unroll
     for (int t = 0; t < 16; ++t) acc0[t] = acc1[t] = 0.0f;
+    // (unrolled: the loads of four k steps are issued before their MFMAs)
+#pragma unroll 4
     for (int64_t k0 = kb; k0 < ke; k0 += 8) {
         eft_bf4 a, b0, b1;
 #pragma unroll
