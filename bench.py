@@ -51,7 +51,7 @@ def parse():
                     help="damped block-Jacobi sweeps preconditioning the Allen-Cahn and B systems")
     ap.add_argument("--band-omega", type=float, default=None)
     ap.add_argument("--mg-omega", type=float, default=0.7)
-    ap.add_argument("--mg-bf16", type=int, default=0, help="1: finest multigrid level's matrix copy in BF16")
+    ap.add_argument("--mg-bf16", type=int, default=1, help="1: finest multigrid level's matrix copy in BF16, 0: FP32")
     ap.add_argument("--kernel-role", type=int, default=1,
                     help="kernel of the roofline object: 1 fine-level smoother sweep, 2 momentum SpMV in FGMRES, "
                          "3 assembly (all three are timed with HIP events over the timed steps); 0 no timing")
@@ -71,6 +71,10 @@ def parse():
     return ap.parse_args()
 
 
+KERNEL_NAME_FP32 = ("k_sweep_blk<4, float, float> (finest-level multigrid smoother sweep, FP32 copy of the "
+                    "4x4-block momentum Jacobian, one block per lane)")
+
+
 def band_over(args):
     """Band-system preconditioner settings given on the command line."""
     o = {}
@@ -86,11 +90,11 @@ def log(args, *a):
         print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_NAME = {1: "k_sweep_blk<4, float, float> (fine-level multigrid smoother sweep, FP32 copy of the 4x4-block "
-                  "momentum Jacobian, one block per lane)",
+KERNEL_NAME = {1: "k_sweep_blk<4, eft_bf16, float> (finest-level multigrid smoother sweep, BF16 copy of the "
+                  "4x4-block momentum Jacobian, FP32 block inverses, FP64 vectors and arithmetic, one block per lane)",
                2: "k_spmv_rows<4, double, true> (FP64 SpMV of the 4x4-block momentum Jacobian in FGMRES)",
-               3: "k_ns_rows<3, double> (momentum/mass residual and Jacobian assembly, bytes: J, its FP32 copy "
-                  "for the multigrid and R written once, connectivity and node fields read once)"}
+               3: "k_ns_rows<3, double> (momentum/mass residual and Jacobian assembly, bytes: J, its BF16 or "
+                  "FP32 copy for the multigrid and R written once, connectivity and node fields read once)"}
 
 
 def timed_steps(ctx, st, steps, warmup, torch):
@@ -291,7 +295,9 @@ def sources_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(kernel):
+    """HBM bytes per launch of the fine-level sweep from the committed counter
+    summary, if it was taken on this kernel variant and these sources."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -299,7 +305,7 @@ def measured_traffic():
         if ":" in line and line.startswith("- "):
             k, v = line[2:].split(":", 1)
             kv[k.strip()] = v.strip().strip("`")
-    if kv.get("sources_sha256") != sources_hash():
+    if kv.get("sources_sha256") != sources_hash() or not kernel.startswith(kv.get("kernel", "?") + " "):
         return None
     try:
         return float(kv["traffic_bytes_per_launch"])
@@ -454,11 +460,15 @@ def main():
             return None
         achieved = kt["bytes"] / kt["seconds"] / 1e9
         return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=KERNEL_NAME[role],
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                    kernel=(KERNEL_NAME_FP32 if role == 1 and not args.mg_bf16 else KERNEL_NAME[role]),
                     launches=kt["launches"], active_launches=kt["active"],
                     bytes_per_launch=round(kt["bytes"] / kt["launches"]), mean_launch_s=kt["seconds"] / kt["launches"])
 
-    roofline = hbm(args.kernel_role, measured_traffic() if args.kernel_role == 1 else None) if args.kernel_role else None
+    roofline = None
+    if args.kernel_role:
+        kname = KERNEL_NAME_FP32 if args.kernel_role == 1 and not args.mg_bf16 else KERNEL_NAME[args.kernel_role]
+        roofline = hbm(args.kernel_role, measured_traffic(kname) if args.kernel_role == 1 else None)
     others = {name: hbm(r) for name, r in (("spmv", 2), ("assembly", 3)) if args.kernel_role and r != args.kernel_role}
 
     mixed = None

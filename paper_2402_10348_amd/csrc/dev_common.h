@@ -123,6 +123,15 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// BF16 bit pattern of f, round to nearest even (the upper half of the FP32
+// pattern after adding the rounding bias).
+__device__ __forceinline__ uint16_t to_bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
 // Sum over a block of BLOCK threads; result valid in thread 0.
 template <int BLOCK> __device__ __forceinline__ double block_sum(double v, double *lds)
 {

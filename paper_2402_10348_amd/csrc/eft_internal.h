@@ -221,7 +221,7 @@ struct eft_ctx {
     double *mg_dense = nullptr, *mg_inv = nullptr;   // coarsest level [nd][nd] over its free dofs
     int32_t *mg_fidx = nullptr, *mg_free = nullptr;  // dof -> free index, free index -> dof
     int64_t mg_nd = 0;
-    bool mg_f32_fresh = false;   // the finest level's FP32 copy was written by the assembly
+    bool mg_f32_fresh = false;   // the finest level's FP32 or BF16 copy was written by the assembly
     // diagnostics workspace (centre of mass partials, particles)
     double *dg = nullptr;
     int64_t dg_cap = 0;
@@ -269,9 +269,10 @@ static inline GA ga_of(double rho_inf, double dt)
 // k_assemble.hip
 eft_status eft_props(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it);
 eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_matrix *J);
-// (J32: when given, an FP32 copy of the values written by the same launch)
+// (J32, J16: when given, an FP32 or BF16 copy of the values written by the
+// same launch)
 eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, double *R, eft_matrix *J,
-                        float *J32 = nullptr);
+                        float *J32 = nullptr, uint16_t *J16 = nullptr);
 
 // k_mg.hip
 eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<uint8_t> &dmask0);

@@ -99,7 +99,8 @@ struct RowArgs {
     const double *as, *Ba, *muL;
     double ct, alpha, kappa, dt, C_I, g0, g1, g2;
     double *R;
-    float *J32;   // optional FP32 copy of the values
+    float *J32;      // optional FP32 copy of the values
+    uint16_t *J16;   // optional BF16 copy of the values
 };
 
 template <int D, typename TJ>
@@ -417,11 +418,16 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
             const double v = accJ[((int64_t)lr * a.maxc + t / B2) * BP + t % B2];
             Jv[kb * B2 + t] = (TJ)v;
             if (a.J32) a.J32[kb * B2 + t] = (float)v;
+            if (a.J16) a.J16[kb * B2 + t] = to_bf16_rne((float)v);
         }
     }
 }
 
 // ------------------------------------------------------ boundary rows ----
+
+// 1 or 0 in the value type of a matrix copy (uint16_t: BF16 bit pattern)
+template <typename TJ> __device__ __forceinline__ TJ unit_or_zero(bool one) { return one ? TJ(1) : TJ(0); }
+template <> __device__ __forceinline__ uint16_t unit_or_zero<uint16_t>(bool one) { return one ? 0x3F80u : 0u; }
 
 template <typename TJ>
 __global__ void k_bc_rows(int64_t n_dir, const int32_t *dir_node, const uint8_t *dir_mask, const int32_t *rowptr,
@@ -436,7 +442,7 @@ __global__ void k_bc_rows(int64_t n_dir, const int32_t *dir_node, const uint8_t 
         if (R) R[(int64_t)n * BS + i] = 0.0;
         if (!Jv) continue;
         for (int k = rowptr[n]; k < rowptr[n + 1]; ++k)
-            for (int j = 0; j < BS; ++j) Jv[((int64_t)k * BS + i) * BS + j] = (col[k] == n && j == i) ? TJ(1) : TJ(0);
+            for (int j = 0; j < BS; ++j) Jv[((int64_t)k * BS + i) * BS + j] = unit_or_zero<TJ>(col[k] == n && j == i);
     }
 }
 
@@ -518,7 +524,8 @@ eft_status eft_props(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it)
 // node fields va, acc, rho, mu, as, Ba must be current, see eft_props).
 // Residual and Jacobian of the momentum/mass block on one mesh level (the
 // node fields of the view must be current).
-eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, double *R, eft_matrix *J, float *J32)
+eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, double *R, eft_matrix *J, float *J32,
+                        uint16_t *J16)
 {
     GA ga = ga_of(ctx->par.rho_inf, ctx->par.dt);
     const int BS = ctx->bs;
@@ -552,6 +559,7 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
     a.g2 = ctx->g[2];
     a.R = R;
     a.J32 = (J && !J->fp32) ? J32 : nullptr;
+    a.J16 = (J && !J->fp32) ? J16 : nullptr;
     if (!J) {
         // residual only: one row of accumulators suffices for the pattern-free path
         a.rowptr = ctx->J.rowptr;
@@ -566,7 +574,8 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
     const int64_t slot = fine ? eft_kt_begin(ctx, EFT_KT_ASSEMBLE) : -1;
     const int d = ctx->dim;
     const double abytes =
-        (J ? (double)J->nnzb * BS * BS * ((J->fp32 ? 4.0 : 8.0) + (a.J32 ? 4.0 : 0.0)) : 0.0) + (double)M.N * BS * 8.0 +
+        (J ? (double)J->nnzb * BS * BS * ((J->fp32 ? 4.0 : 8.0) + (a.J32 ? 4.0 : 0.0) + (a.J16 ? 2.0 : 0.0)) : 0.0) +
+        (double)M.N * BS * 8.0 +
         (double)M.E * (d + 1) * 4.0 +
         (double)M.N * 8.0 * (d + BS + d + d + 2 + (double)ctx->n_s * (1 + ctx->nv));
     if (ctx->dim == 2) {
@@ -590,6 +599,9 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
         if (a.J32)   // the same unit rows in the FP32 copy
             hipLaunchKernelGGL(k_bc_rows<float>, dim3(nbd), dim3(128), 0, ctx->stream, M.n_dir, M.dir_node, M.dir_mask,
                                J->rowptr, J->col, BS, (double *)nullptr, a.J32);
+        if (a.J16)   // and in the BF16 copy
+            hipLaunchKernelGGL(k_bc_rows<uint16_t>, dim3(nbd), dim3(128), 0, ctx->stream, M.n_dir, M.dir_node,
+                               M.dir_mask, J->rowptr, J->col, BS, (double *)nullptr, a.J16);
         EFT_HIP(hipGetLastError());
     }
     return EFT_OK;
@@ -623,8 +635,9 @@ eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_ma
     // FP32 copy of the values (no separate conversion pass over J)
     const bool mg = J && eft_mg_active(ctx, J);
     float *J32 = (mg && !ctx->par.mg_bf16 && !J->fp32) ? ctx->mg[0].A.val32 : nullptr;
-    EFT_TRY(eft_ns_level(ctx, M, it->vp, R, J, J32));
-    ctx->mg_f32_fresh = J32 != nullptr;
+    uint16_t *J16 = (mg && ctx->par.mg_bf16 && !J->fp32) ? ctx->mg[0].A.val16 : nullptr;
+    EFT_TRY(eft_ns_level(ctx, M, it->vp, R, J, J32, J16));
+    ctx->mg_f32_fresh = J32 != nullptr || J16 != nullptr;
     if (mg) EFT_TRY(eft_mg_setup(ctx, it->vp));
     return EFT_OK;
 }

@@ -609,11 +609,8 @@ __global__ void k_to_f32(const double *a, float *b, int64_t n)
 // BF16 copy (round to nearest even)
 template <typename T> __global__ void k_to_bf16(const T *a, uint16_t *b, int64_t n)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t u = __float_as_uint((float)a[i]);
-        u += 0x7FFFu + ((u >> 16) & 1u);
-        b[i] = (uint16_t)(u >> 16);
-    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = to_bf16_rne((float)a[i]);
 }
 
 // ------------------------------------------------------------------ host --
@@ -967,8 +964,9 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
         F0.A.fp32 = false;
         if (ctx->J.fp32)
             hipLaunchKernelGGL(k_to_bf16<float>, dim3(cgrid), dim3(256), 0, ctx->stream, ctx->J.val32, F0.A.val16, nv);
-        else
+        else if (!ctx->mg_f32_fresh)   // (else the assembly wrote the copy)
             hipLaunchKernelGGL(k_to_bf16<double>, dim3(cgrid), dim3(256), 0, ctx->stream, ctx->J.val, F0.A.val16, nv);
+        ctx->mg_f32_fresh = false;
         EFT_HIP(hipGetLastError());
         EFT_TRY(eft_bj_setup32(ctx, &ctx->J, F0.Dinv32));
     } else {
