@@ -99,6 +99,52 @@ __global__ __launch_bounds__(RB) void k_maxpy(const double *__restrict__ V, int6
     }
 }
 
+// The first pass's update w' = w - sum_k c[k] V[k] fused with the second
+// pass's dots V[k].w' and ||w'||^2: each lane keeps its entries of the nvec
+// (<= NV) basis vectors in registers, so V is read once for both.  Partials:
+// part[b] = ||w'||^2 of block b, part[(1 + k) nblk + b] = its V[k].w'.
+template <int NV>
+__global__ __launch_bounds__(RB) void k_maxpy_mdot(const double *__restrict__ V, int64_t nd, int nvec,
+                                                   const double *__restrict__ c, double *__restrict__ w,
+                                                   double *__restrict__ part, int nblk, const int32_t *flag)
+{
+    __shared__ double cl[NV];
+    __shared__ double red[RB / 64][NV + 1];
+    if (flag[0] == 0) return;
+    for (int k = threadIdx.x; k < NV; k += RB) cl[k] = k < nvec ? -c[k] : 0.0;
+    __syncthreads();
+    double acc[NV + 1];
+#pragma unroll
+    for (int k = 0; k <= NV; ++k) acc[k] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < nd; i += (int64_t)nblk * RB) {
+        double v[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = k < nvec ? V[(int64_t)k * nd + i] : 0.0;
+        double s = w[i];
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            if (k < nvec) s += cl[k] * v[k];
+        w[i] = s;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) acc[k] += v[k] * s;
+        acc[NV] += s * s;
+    }
+    const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
+#pragma unroll
+    for (int k = 0; k <= NV; ++k) {
+        const double t = wave_sum(acc[k]);
+        if (ln == 0) red[wv][k] = t;
+    }
+    __syncthreads();
+    const int k = threadIdx.x;
+    if (k < nvec || k == NV) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < RB / 64; ++q) t += red[q][k];
+        part[(k == NV ? 0 : (int64_t)(1 + k) * nblk) + blockIdx.x] = t;
+    }
+}
+
 // Givens update of column j (col[0..j+1], in LDS), residual estimate,
 // convergence and breakdown flags; one thread.  cs, sn are the earlier
 // rotations (LDS copies); the new rotation, g and the column go to small.
@@ -142,13 +188,25 @@ __device__ void givens_column(double *small, int m, int j, double *col, const do
 // the pass that completes the column sets H[j+1][j] = ||w|| and applies the
 // Givens rotations.  The column and the earlier rotations are staged in LDS
 // by the whole workgroup, so the serial rotation loop reads no global memory.
-__global__ __launch_bounds__(RB) void k_close_pass(const double *__restrict__ part, int nblk, double *small, int m,
-                                                   int j, int pass, int32_t *flag)
+// With ndots > 0 (pass 1 fused with the second pass's dots) it also sums the
+// ndots dot partials that follow the norm partials into h2, one wavefront
+// per dot.
+__global__ __launch_bounds__(RB) void k_close_pass(const double *__restrict__ part, int nblk, int ndots, double *small,
+                                                   int m, int j, int pass, int32_t *flag)
 {
     __shared__ double lds[RB / 64];
     __shared__ double col[EFT_MAX_RESTART + 2], csl[EFT_MAX_RESTART], snl[EFT_MAX_RESTART];
     if (flag[0] == 0 || (pass == 2 && flag[3] == 0)) return;
     Small L{m};
+    if (ndots > 0) {
+        const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
+        for (int k = wv; k < ndots; k += RB / 64) {
+            double t = 0.0;
+            for (int b = ln; b < nblk; b += 64) t += part[(int64_t)(1 + k) * nblk + b];
+            t = wave_sum(t);
+            if (ln == 0) small[L.h2() + k] = t;
+        }
+    }
     double *H = small + L.H();
     const double *h = small + L.h(), *h2 = small + L.h2();
     for (int i = threadIdx.x; i <= j; i += RB) {
@@ -421,19 +479,36 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
                                    K.flag, 0);
                 hipLaunchKernelGGL(k_sum_parts, dim3(j + 2), dim3(RB), 0, ctx->stream, K.part, nblk, small + L.h(),
                                    K.flag, 0);
-                hipLaunchKernelGGL(k_maxpy, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, j + 1, small + L.h(), -1.0,
-                                   K.w, K.part, nblk, K.flag, 0);
-                hipLaunchKernelGGL(k_close_pass, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, small, m, j, 1,
-                                   K.flag);
+                if (j + 1 <= 32) {
+                    // pass 1's update with pass 2's dots (used if pass 2 is taken)
+                    const int nv1 = j + 1;
+                    if (nv1 <= 8)
+                        hipLaunchKernelGGL(k_maxpy_mdot<8>, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, nv1,
+                                           small + L.h(), K.w, K.part, nblk, K.flag);
+                    else if (nv1 <= 16)
+                        hipLaunchKernelGGL(k_maxpy_mdot<16>, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, nv1,
+                                           small + L.h(), K.w, K.part, nblk, K.flag);
+                    else
+                        hipLaunchKernelGGL(k_maxpy_mdot<32>, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, nv1,
+                                           small + L.h(), K.w, K.part, nblk, K.flag);
+                    hipLaunchKernelGGL(k_close_pass, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, nv1, small, m,
+                                       j, 1, K.flag);
+                } else {
+                    hipLaunchKernelGGL(k_maxpy, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, j + 1, small + L.h(),
+                                       -1.0, K.w, K.part, nblk, K.flag, 0);
+                    hipLaunchKernelGGL(k_close_pass, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, 0, small, m, j,
+                                       1, K.flag);
+                    // pass 2's dots (gated)
+                    dim3 g2(nblk, (j + 1 + KC - 1) / KC);
+                    hipLaunchKernelGGL(k_mdot, g2, dim3(RB), 0, ctx->stream, K.V, nd, j + 1, 0, K.w, K.part, nblk,
+                                       K.flag, 1);
+                    hipLaunchKernelGGL(k_sum_parts, dim3(j + 1), dim3(RB), 0, ctx->stream, K.part, nblk,
+                                       small + L.h2(), K.flag, 1);
+                }
                 // pass 2 (gated)
-                dim3 g2(nblk, (j + 1 + KC - 1) / KC);
-                hipLaunchKernelGGL(k_mdot, g2, dim3(RB), 0, ctx->stream, K.V, nd, j + 1, 0, K.w, K.part, nblk, K.flag,
-                                   1);
-                hipLaunchKernelGGL(k_sum_parts, dim3(j + 1), dim3(RB), 0, ctx->stream, K.part, nblk, small + L.h2(),
-                                   K.flag, 1);
                 hipLaunchKernelGGL(k_maxpy, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, j + 1, small + L.h2(),
                                    -1.0, K.w, K.part, nblk, K.flag, 1);
-                hipLaunchKernelGGL(k_close_pass, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, small, m, j, 2,
+                hipLaunchKernelGGL(k_close_pass, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, 0, small, m, j, 2,
                                    K.flag);
                 hipLaunchKernelGGL(k_normalize, dim3(sg), dim3(RB), 0, ctx->stream, K.w, K.V + (int64_t)(j + 1) * nd,
                                    nd, small, m, j, K.flag);

@@ -590,18 +590,22 @@ def test_particle_tracking_matches_oracle(torch_cuda, name):
     say(f"  {pts.shape[0]} particles agree; elements {eg[:5]} ...")
 
 
-@pytest.mark.parametrize("shape,ncell", [("sphere", (1, 1, 1)), ("sphere", (6, 6, 6)), ("cube", (5, 4, 3))])
-def test_init_phase_matches_oracle(torch_cuda, shape, ncell):
+@pytest.mark.parametrize("shape,ncell,n,m", [
+    ("sphere", (1, 1, 1), 30, 4), ("sphere", (6, 6, 6), 30, 4), ("cube", (5, 4, 3), 30, 16),
+    # the paper's grid-cell demonstration (Sec. 4.2): 729 cells, a cube,
+    # h_E = 0.02 and surface spacing 0.005 (120,000 triangles)
+    ("cube", (9, 9, 9), 50, 100)])
+def test_init_phase_matches_oracle(torch_cuda, shape, ncell, n, m):
     """Phase-field initialization from a surface mesh (grid cells, vertex
     distance, ray casting with the non-duplicated partitioning) on the GPU
     against the oracle: the same sign on every node and |phi| within 1e-14
     (the same arithmetic; FMA contraction may move the last bits)."""
-    prob = W.cavity_sphere_3d(n=30)
-    say(f"[init phase] {shape} cells={ncell}")
+    prob = W.cavity_sphere_3d(n=n)
+    say(f"[init phase] {shape} cells={ncell} n={n} m={m}")
     if shape == "sphere":
-        v, t = W.icosphere(0.25, [0.5, 0.5, 0.5], 4)
+        v, t = W.icosphere(0.25, [0.5, 0.5, 0.5], m)
     else:
-        v, t = W.cube_surface(0.25, 0.75, 16)
+        v, t = W.cube_surface(0.25, 0.75, m)
     c = O.Case(prob)
     p0, s0 = c.init_phase(v, t, 0.02, ncell)
     ctx = ctx_for(prob)
