@@ -16,6 +16,21 @@ namespace {
 
 constexpr int RB = 256;   // reduction block size
 constexpr int KC = 8;     // vectors per multi-dot block
+constexpr int MAXBLK = 4 * RB;   // most partials of one reduction (blocks of a reduction grid)
+
+// This thread's share of the sum of p[0..nblk) (nblk <= MAXBLK): four
+// unguarded loads at clamped indices, masked by a product, all in flight
+// together.
+__device__ __forceinline__ double part_share(const double *__restrict__ p, int nblk)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < MAXBLK / RB; ++u) {
+        const int b = threadIdx.x + u * RB;
+        s += p[b < nblk ? b : nblk - 1] * (b < nblk ? 1.0 : 0.0);
+    }
+    return s;
+}
 
 // layout of KrylovWs::small (doubles) for restart m
 struct Small {
@@ -69,8 +84,7 @@ __global__ __launch_bounds__(RB) void k_sum_parts(const double *__restrict__ par
 {
     __shared__ double lds[RB / 64];
     if (flag && (flag[0] == 0 || (gated && flag[3] == 0))) return;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += RB) s += part[(int64_t)blockIdx.x * nblk + b];
+    double s = part_share(part + (int64_t)blockIdx.x * nblk, nblk);
     s = block_sum<RB>(s, lds);
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
@@ -197,14 +211,26 @@ __global__ __launch_bounds__(RB) void k_close_pass(const double *__restrict__ pa
     __shared__ double lds[RB / 64];
     __shared__ double col[EFT_MAX_RESTART + 2], csl[EFT_MAX_RESTART], snl[EFT_MAX_RESTART];
     if (flag[0] == 0 || (pass == 2 && flag[3] == 0)) return;
+    __shared__ double red[RB / 64][32];
     Small L{m};
     if (ndots > 0) {
+        // (ndots <= 32) eight dots at a time, their loads issued together
         const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
-        for (int k = wv; k < ndots; k += RB / 64) {
-            double t = 0.0;
-            for (int b = ln; b < nblk; b += 64) t += part[(int64_t)(1 + k) * nblk + b];
-            t = wave_sum(t);
-            if (ln == 0) small[L.h2() + k] = t;
+        for (int k0 = 0; k0 < ndots; k0 += 8) {
+            double t[8];
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                // unguarded loads at clamped indices, masked by a product
+                // (dots past ndots are summed and never read), so that the
+                // 32 loads are in flight together
+                const int k = k0 + kk;
+                t[kk] = part_share(part + (int64_t)(1 + (k < ndots ? k : ndots - 1)) * nblk, nblk);
+            }
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                const double v = wave_sum(t[kk]);
+                if (ln == 0) red[wv][k0 + kk] = v;   // (k0 + kk < 32)
+            }
         }
     }
     double *H = small + L.H();
@@ -216,9 +242,14 @@ __global__ __launch_bounds__(RB) void k_close_pass(const double *__restrict__ pa
             snl[i] = small[L.sn() + i];
         }
     }
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += RB) s += part[b];
-    s = block_sum<RB>(s, lds);   // (its barriers also publish col, csl, snl)
+    double s = part_share(part, nblk);
+    s = block_sum<RB>(s, lds);   // (its barriers also publish col, csl, snl, red)
+    if ((int)threadIdx.x < ndots) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < RB / 64; ++q) v += red[q][threadIdx.x];
+        small[L.h2() + threadIdx.x] = v;
+    }
     if (threadIdx.x != 0) return;
     if (pass == 1) {
         small[L.sc() + 0] = s;
@@ -301,7 +332,7 @@ __global__ __launch_bounds__(RB) void k_dot_part(const double *__restrict__ x, c
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
-int nblk_for(int64_t nd) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (nd + RB - 1) / RB)); }
+int nblk_for(int64_t nd) { return (int)std::max<int64_t>(1, std::min<int64_t>(MAXBLK, (nd + RB - 1) / RB)); }
 int stream_grid(int64_t nd) { return (int)std::max<int64_t>(1, std::min<int64_t>(8192, (nd + RB - 1) / RB)); }
 
 }  // namespace

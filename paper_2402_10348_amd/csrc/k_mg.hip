@@ -234,6 +234,29 @@ __global__ __launch_bounds__(256) void k_sweep0(int64_t nd, int bs, const TD *__
     x[t] = omega * s;
 }
 
+// The same with one node per lane (bs 3 or 4): its block inverse and b read
+// as whole rows, several loads in flight per lane.
+template <int BS, typename TD>
+__global__ __launch_bounds__(256) void k_sweep0_nodes(int64_t n, const TD *__restrict__ Dinv, double omega,
+                                                      const double *__restrict__ b, double *__restrict__ x,
+                                                      const int32_t *flag)
+{
+    if (*flag == 0) return;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double bb[BS], d[BS][BS];
+    x_get<BS>(b, r, bb);
+#pragma unroll
+    for (int i = 0; i < BS; ++i) RowLoad<BS, TD, false>::get(Dinv + (r * BS + i) * BS, d[i]);
+#pragma unroll
+    for (int i = 0; i < BS; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < BS; ++c) s += d[i][c] * bb[c];
+        x[r * BS + i] = omega * s;
+    }
+}
+
 // r = b - A x, RESID_R block rows per wavefront (as the plain product)
 constexpr int RESID_R = 2;
 
@@ -1110,7 +1133,14 @@ void sweep(eft_ctx *ctx, const MGLevel &L, const double *b, const double *x, dou
 void sweep0(eft_ctx *ctx, const MGLevel &L, const double *b, double *x, const int32_t *flag)
 {
     const int64_t nd = L.N * ctx->bs;
-    if (L.A.fp32 || L.A.bf16)
+    const dim3 gn(eft_grid(L.N, 256));
+    if ((L.A.fp32 || L.A.bf16) && ctx->bs == 4)
+        hipLaunchKernelGGL((k_sweep0_nodes<4, float>), gn, dim3(256), 0, ctx->stream, L.N, L.Dinv32, ctx->par.mg_omega,
+                           b, x, flag);
+    else if ((L.A.fp32 || L.A.bf16) && ctx->bs == 3)
+        hipLaunchKernelGGL((k_sweep0_nodes<3, float>), gn, dim3(256), 0, ctx->stream, L.N, L.Dinv32, ctx->par.mg_omega,
+                           b, x, flag);
+    else if (L.A.fp32 || L.A.bf16)
         hipLaunchKernelGGL(k_sweep0<float>, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, nd, ctx->bs, L.Dinv32,
                            ctx->par.mg_omega, b, x, flag);
     else
