@@ -58,17 +58,26 @@ __global__ __launch_bounds__(RB) void k_mdot(const double *__restrict__ V, int64
     if (flag[0] == 0 || (gated && flag[3] == 0)) return;
     const int k0 = blockIdx.y * KC;
     const int ntot = nvec + with_ww;
-    double acc[KC];
+    // every slot loads a basis vector (clamped index) and is masked by a
+    // product, so that the KC loads of an element are in flight together
+    // rather than each behind its own branch
+    const double *vk[KC];
+    double mv[KC], mw[KC], acc[KC];
 #pragma unroll
-    for (int kk = 0; kk < KC; ++kk) acc[kk] = 0.0;
+    for (int kk = 0; kk < KC; ++kk) {
+        const int k = k0 + kk;
+        vk[kk] = V + (int64_t)(k < nvec ? k : nvec - 1) * nd;
+        mv[kk] = k < nvec ? 1.0 : 0.0;
+        mw[kk] = (k == nvec && with_ww) ? 1.0 : 0.0;
+        acc[kk] = 0.0;
+    }
     for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < nd; i += (int64_t)nblk * RB) {
         const double wi = w[i];
+        double v[KC];
 #pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-            const int k = k0 + kk;
-            if (k < nvec) acc[kk] += V[(int64_t)k * nd + i] * wi;
-            else if (k == nvec && with_ww) acc[kk] += wi * wi;
-        }
+        for (int kk = 0; kk < KC; ++kk) v[kk] = vk[kk][i];
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) acc[kk] += (v[kk] * mv[kk] + wi * mw[kk]) * wi;
     }
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
