@@ -27,6 +27,7 @@ struct eft_matrix {
     double *val = nullptr;
     float *val32 = nullptr;
     uint16_t *val16 = nullptr;   // BF16 values (the finest multigrid level's copy)
+    float *pc32 = nullptr;       // FP32 copy of val for the preconditioner's sweeps (band systems)
     bool fp32 = false;
     bool bf16 = false;
 };
@@ -207,6 +208,7 @@ struct eft_ctx {
     int64_t scan_cap = 0;
     double *bR = nullptr, *bX = nullptr;         // band system rhs / solution [cap][nv]
     double *bval = nullptr;                      // band matrix values [cap_nnz][nv*nv]
+    float *bval32 = nullptr;                     // their FP32 copy (B systems' preconditioner sweeps)
     int64_t bcap_n = 0, bcap_nnz = 0;
     double *tnum = nullptr, *tden = nullptr;     // mobility projection sums [cap_n]
     // reductions and host mirror
@@ -295,7 +297,8 @@ eft_status eft_bj_setup32(eft_ctx *ctx, const eft_matrix *A, float *Dinv);
 eft_status eft_bj_apply(eft_ctx *ctx, int bs, int64_t n, const double *Dinv, const double *x, double *z,
                         const int32_t *active);
 // z = M v with M = `sweeps` damped point-block Jacobi sweeps from z = 0
-// (tmp: scratch of the size of v; sweeps = 1, omega = 1 is block Jacobi)
+// (tmp: scratch of the size of v; sweeps = 1, omega = 1 is block Jacobi;
+// the products of the later sweeps read A->pc32 when it is set)
 eft_status eft_jacobi_apply(eft_ctx *ctx, const eft_matrix *A, const double *Dinv, const double *v, double *z,
                             double *tmp, int sweeps, double omega, const int32_t *active);
 eft_status eft_spmv_flag(eft_ctx *ctx, const eft_matrix *A, const double *x, double *y, const int32_t *active);

@@ -324,10 +324,10 @@ __global__ __launch_bounds__(256) void k_jsweep1(int64_t n, const int32_t *__res
 }
 
 // bs in {3, 6}: SPMV_R block rows per wavefront (bsr_rows.h), lanes 0..bs-1
-// finish the rows.
-template <int BS>
+// finish the rows.  Values FP64 or an FP32 copy (the arithmetic FP64).
+template <int BS, typename TV>
 __global__ __launch_bounds__(256) void k_jsweep_rows(int64_t n, const int32_t *__restrict__ rowptr,
-                                                     const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                     const int32_t *__restrict__ col, const TV *__restrict__ val,
                                                      const double *__restrict__ Dinv, double omega,
                                                      const double *__restrict__ v, const double *__restrict__ z,
                                                      double *__restrict__ zo, const int32_t *active)
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(256) void k_jsweep_rows(int64_t n, const int32_t *_
         zr[q] = z[rr * BS + rl];
         RowLoad<BS, double, false>::get(Dinv + (rr * BS + rl) * BS, d[q]);
     }
-    bsr_rows_dot<BS, double, SPMV_R, false>(k0, k1, col, val, z, lane, az);
+    bsr_rows_dot<BS, TV, SPMV_R, false>(k0, k1, col, val, z, lane, az);
 #pragma unroll
     for (int q = 0; q < SPMV_R; ++q) {
         const double res = vr[q] - az[q];
@@ -429,12 +429,18 @@ eft_status eft_jacobi_apply(eft_ctx *ctx, const eft_matrix *A, const double *Din
         if (bs == 1)
             hipLaunchKernelGGL(k_jsweep1, dim3(eft_grid(n, 16)), dim3(256), 0, ctx->stream, n, A->rowptr, A->col,
                                A->val, Dinv, omega, v, cur, nxt, active);
+        else if (bs == 3 && A->pc32)
+            hipLaunchKernelGGL((k_jsweep_rows<3, float>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream, n,
+                               A->rowptr, A->col, A->pc32, Dinv, omega, v, cur, nxt, active);
         else if (bs == 3)
-            hipLaunchKernelGGL(k_jsweep_rows<3>, dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream, n,
-                               A->rowptr, A->col, A->val, Dinv, omega, v, cur, nxt, active);
+            hipLaunchKernelGGL((k_jsweep_rows<3, double>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream,
+                               n, A->rowptr, A->col, A->val, Dinv, omega, v, cur, nxt, active);
+        else if (A->pc32)
+            hipLaunchKernelGGL((k_jsweep_rows<6, float>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream, n,
+                               A->rowptr, A->col, A->pc32, Dinv, omega, v, cur, nxt, active);
         else
-            hipLaunchKernelGGL(k_jsweep_rows<6>, dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream, n,
-                               A->rowptr, A->col, A->val, Dinv, omega, v, cur, nxt, active);
+            hipLaunchKernelGGL((k_jsweep_rows<6, double>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream,
+                               n, A->rowptr, A->col, A->val, Dinv, omega, v, cur, nxt, active);
         cur = nxt;
     }
     EFT_HIP(hipGetLastError());

@@ -355,6 +355,7 @@ struct TrArgs {
     const double *lx, *ldx, *ix;            // level value, level rate, iterate of the field
     double alpha, alpha_m, vs, dt, ct;
     double *R, *J;
+    float *J32;   // optional FP32 copy of J (B systems)
 };
 
 template <int BS>
@@ -433,10 +434,15 @@ __device__ __forceinline__ void band_rows_out_b(const TrArgs &a, int64_t r0, int
             }
             const double *src = accJ + ((int64_t)lr * a.maxc + lo) * BP;
             double *dst = a.J + (kb + t) * B2;
+            float *dst32 = a.J32 ? a.J32 + (kb + t) * B2 : nullptr;
 #pragma unroll
             for (int c = 0; c < NVv; ++c)
 #pragma unroll
-                for (int cc = 0; cc < NVv; ++cc) dst[c * NVv + cc] = b_block_entry<D>(src, c, cc);
+                for (int cc = 0; cc < NVv; ++cc) {
+                    const double v = b_block_entry<D>(src, c, cc);
+                    dst[c * NVv + cc] = v;
+                    if (dst32) dst32[c * NVv + cc] = (float)v;
+                }
         }
     }
 }
@@ -752,14 +758,18 @@ __global__ __launch_bounds__(256, 2) void k_b_rows(TrArgs a, const double *afr /
 
 // Rows of nodes that keep their value: residual 0, unit row.
 __global__ __launch_bounds__(256) void k_band_bc(int64_t n, int bs, const uint8_t *fre, const int32_t *rowptr,
-                                                 const int32_t *col, double *R, double *J)
+                                                 const int32_t *col, double *R, double *J, float *J32)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n || fre[r]) return;
     for (int i = 0; i < bs; ++i) {
         R[r * bs + i] = 0.0;
         for (int k = rowptr[r]; k < rowptr[r + 1]; ++k)
-            for (int j = 0; j < bs; ++j) J[((int64_t)k * bs + i) * bs + j] = (col[k] == r && i == j) ? 1.0 : 0.0;
+            for (int j = 0; j < bs; ++j) {
+                const bool one = col[k] == r && i == j;
+                J[((int64_t)k * bs + i) * bs + j] = one ? 1.0 : 0.0;
+                if (J32) J32[((int64_t)k * bs + i) * bs + j] = one ? 1.0f : 0.0f;
+            }
     }
 }
 
@@ -873,8 +883,12 @@ eft_status eft_reserve_band_sys(eft_ctx *ctx, int64_t n, int64_t nnz)
     }
     if (nnz > ctx->bcap_nnz) {
         if (ctx->bval) (void)hipFree(ctx->bval);
+        if (ctx->bval32) (void)hipFree(ctx->bval32);
+        ctx->bval = nullptr;
+        ctx->bval32 = nullptr;
         const int64_t c = 2 * nnz + 64;
-        if (hipMalloc(&ctx->bval, sizeof(double) * c * nv * nv) != hipSuccess) {
+        if (hipMalloc(&ctx->bval, sizeof(double) * c * nv * nv) != hipSuccess ||
+            hipMalloc(&ctx->bval32, sizeof(float) * c * nv * nv) != hipSuccess) {
             ctx->err = "out of device memory (band matrix)";
             return EFT_ENOMEM;
         }
@@ -1085,6 +1099,7 @@ static TrArgs tr_args(eft_ctx *ctx, const Band &B, const double *lx, const doubl
 {
     GA ga = ga_of(ctx->par.rho_inf, ctx->par.dt);
     TrArgs a;
+    a.J32 = nullptr;
     a.n = B.n;
     a.rpb = std::min(ctx->rpb, 64);
     a.maxc = ctx->maxc;
@@ -1132,7 +1147,7 @@ static eft_status assemble_ac(eft_ctx *ctx, const eft_state *lvl, const eft_iter
             hipLaunchKernelGGL(k_ac_rows<3>, dim3(eft_grid(B.n, a.rpb)), dim3(256), shm, ctx->stream, a, ctx->par.eps,
                                gb);
         hipLaunchKernelGGL(k_band_bc, dim3(eft_grid(B.n, 256)), dim3(256), 0, ctx->stream, B.n, 1, B.fre, B.rowptr,
-                           B.col, R, J);
+                           B.col, R, J, (float *)nullptr);
     }
     EFT_HIP(hipGetLastError());
     return EFT_OK;
@@ -1140,7 +1155,8 @@ static eft_status assemble_ac(eft_ctx *ctx, const eft_state *lvl, const eft_iter
 
 // B system of solid s on the band of its indicator into R, J; the solid
 // fractions in ctx->as must come from the current order parameters
-static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, int s, double *R, double *J)
+static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, int s, double *R, double *J,
+                             float *J32)
 {
     const int64_t N = ctx->N;
     const int nv = ctx->nv;
@@ -1148,6 +1164,7 @@ static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_itera
     TrArgs a = tr_args(ctx, B, lvl->B + (int64_t)s * N * nv, lvl->Bdot + (int64_t)s * N * nv, it->B + (int64_t)s * N * nv);
     a.R = R;
     a.J = J;
+    a.J32 = J32;
     if (B.n > 0) {
         const int bp = ctx->dim == 2 ? BAcc<2>::P : BAcc<3>::P;
         const size_t shm = (size_t)a.rpb * ((size_t)a.maxc * bp + (nv | 1)) * sizeof(double);
@@ -1158,7 +1175,7 @@ static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_itera
             hipLaunchKernelGGL(k_b_rows<3>, dim3(eft_grid(B.n, a.rpb)), dim3(256), shm, ctx->stream, a,
                                ctx->as + (int64_t)s * N);
         hipLaunchKernelGGL(k_band_bc, dim3(eft_grid(B.n, 256)), dim3(256), 0, ctx->stream, B.n, nv, B.fre, B.rowptr,
-                           B.col, R, J);
+                           B.col, R, J, J32);
     }
     EFT_HIP(hipGetLastError());
     return EFT_OK;
@@ -1198,6 +1215,7 @@ static eft_status union_solve(eft_ctx *ctx, const eft_ctx::BandUnion &U, int bs,
     A.col = U.col;
     A.diag = U.diag;
     A.val = ctx->bval;
+    A.pc32 = bs > 1 ? ctx->bval32 : nullptr;   // (the B systems' assembly writes the copy)
     const double rtol = ctx->par.lin_rtol / std::sqrt((double)std::max(members, 1));
     eft_status st = eft_fgmres_dev(ctx, &A, ctx->bR, ctx->bX, si, rtol);
     if (st != EFT_OK && st != EFT_ENOTCONV) return st;
@@ -1267,7 +1285,8 @@ eft_status eft_transport_dev(eft_ctx *ctx, const eft_state *lvl, eft_iterate *it
         const eft_ctx::BandUnion &U = ctx->u_b;
         for (int sI = 0; sI < S; ++sI)
             if (ctx->band[ctx->solid_ind[sI]].n > 0)
-                EFT_TRY(assemble_b(ctx, lvl, it, sI, ctx->bR + U.roff[sI] * nv, ctx->bval + U.noff[sI] * nv * nv));
+                EFT_TRY(assemble_b(ctx, lvl, it, sI, ctx->bR + U.roff[sI] * nv, ctx->bval + U.noff[sI] * nv * nv,
+                                   ctx->bval32 + U.noff[sI] * nv * nv));
         std::vector<double *> x(S);
         std::vector<int64_t> xl(S, N * nv);
         for (int sI = 0; sI < S; ++sI) x[sI] = it->B + (int64_t)sI * N * nv;
@@ -1310,7 +1329,7 @@ eft_status eft_band_system_dev(eft_ctx *ctx, const eft_state *lvl, const eft_ite
         gb[1] = all[2 * index + 1];
         EFT_TRY(assemble_ac(ctx, lvl, it, index, ctx->bR, ctx->bval, ctx->tsc + TS_GB + 2 * index));
     } else {
-        EFT_TRY(assemble_b(ctx, lvl, it, index, ctx->bR, ctx->bval));
+        EFT_TRY(assemble_b(ctx, lvl, it, index, ctx->bR, ctx->bval, ctx->bval32));
     }
     if (gamma_beta) {
         gamma_beta[0] = gb[0];
