@@ -351,6 +351,7 @@ struct TrArgs {
     const uint8_t *eflag;                   // [E] 1 for band elements
     const int32_t *conn, *epos, *grow, *gcol;
     const int32_t *brow, *bcol;             // band pattern, band-local columns
+    const uint8_t *fre;                     // band row is free (else a unit row with residual 0)
     const double *xyz, *va;
     const double *lx, *ldx, *ix;            // level value, level rate, iterate of the field
     double alpha, alpha_m, vs, dt, ct;
@@ -365,11 +366,21 @@ __device__ __forceinline__ void band_rows_out(const TrArgs &a, int64_t r0, int64
     constexpr int B2 = BS * BS, BP = B2 | 1, RP = BS | 1;
     for (int64_t r = r0; r < r1; ++r) {
         const int lr = (int)(r - r0);
+        const int64_t kb = a.brow[r], len = a.brow[r + 1] - kb;
+        if (!a.fre[r]) {   // a node that keeps its value: residual 0, unit row
+            if (threadIdx.x < BS) a.R[r * BS + threadIdx.x] = 0.0;
+            for (int t = threadIdx.x; t < len; t += blockDim.x) {
+                double *dst = a.J + (kb + t) * B2;
+                const bool dg = a.bcol[kb + t] == r;
+#pragma unroll
+                for (int v = 0; v < B2; ++v) dst[v] = (dg && v % (BS + 1) == 0) ? 1.0 : 0.0;
+            }
+            continue;
+        }
         if (threadIdx.x < BS) a.R[r * BS + threadIdx.x] = accR[lr * RP + threadIdx.x];
         const int64_t g = a.node[r];
         const int32_t *gc = a.gcol + a.grow[g];
         const int glen = a.grow[g + 1] - a.grow[g];
-        const int64_t kb = a.brow[r], len = a.brow[r + 1] - kb;
         for (int t = threadIdx.x; t < len; t += blockDim.x) {
             const int32_t col = a.node[a.bcol[kb + t]];
             int lo = 0, hi = glen - 1;
@@ -419,11 +430,26 @@ __device__ __forceinline__ void band_rows_out_b(const TrArgs &a, int64_t r0, int
     constexpr int NVv = NV<D>::v, B2 = NVv * NVv, BP = BAcc<D>::P, RP = NVv | 1;
     for (int64_t r = r0; r < r1; ++r) {
         const int lr = (int)(r - r0);
+        const int64_t kb = a.brow[r], len = a.brow[r + 1] - kb;
+        if (!a.fre[r]) {   // a node that keeps its value: residual 0, unit row
+            if (threadIdx.x < NVv) a.R[r * NVv + threadIdx.x] = 0.0;
+            for (int t = threadIdx.x; t < len; t += blockDim.x) {
+                double *dst = a.J + (kb + t) * B2;
+                float *dst32 = a.J32 ? a.J32 + (kb + t) * B2 : nullptr;
+                const bool dg = a.bcol[kb + t] == r;
+#pragma unroll
+                for (int v = 0; v < B2; ++v) {
+                    const bool one = dg && v % (NVv + 1) == 0;
+                    dst[v] = one ? 1.0 : 0.0;
+                    if (dst32) dst32[v] = one ? 1.0f : 0.0f;
+                }
+            }
+            continue;
+        }
         if (threadIdx.x < NVv) a.R[r * NVv + threadIdx.x] = accR[lr * RP + threadIdx.x];
         const int64_t g = a.node[r];
         const int32_t *gc = a.gcol + a.grow[g];
         const int glen = a.grow[g + 1] - a.grow[g];
-        const int64_t kb = a.brow[r], len = a.brow[r + 1] - kb;
         for (int t = threadIdx.x; t < len; t += blockDim.x) {
             const int32_t col = a.node[a.bcol[kb + t]];
             int lo = 0, hi = glen - 1;
@@ -475,6 +501,7 @@ __global__ __launch_bounds__(256) void k_ac_rows(TrArgs a, double eps, const dou
         // rows, so the LDS atomics of one wavefront rarely hit one block
         for (int t = threadIdx.x; t < nrow * maxinc; t += blockDim.x) {
             const int lr = t % nrow;
+            if (!a.fre[r0 + lr]) continue;   // (written as a unit row)
             const int64_t g = a.node[r0 + lr];
             const int ii = a.iptr[g] + t / nrow;
             if (ii >= a.iptr[g + 1]) continue;
@@ -615,6 +642,7 @@ __global__ __launch_bounds__(256, 2) void k_b_rows(TrArgs a, const double *afr /
         // rows, so the LDS atomics of one wavefront rarely hit one block
         for (int t = threadIdx.x; t < nrow * maxinc; t += blockDim.x) {
             const int lr = t % nrow;
+            if (!a.fre[r0 + lr]) continue;   // (written as a unit row)
             const int64_t g = a.node[r0 + lr];
             const int ii = a.iptr[g] + t / nrow;
             if (ii >= a.iptr[g + 1]) continue;
@@ -754,23 +782,6 @@ __global__ __launch_bounds__(256, 2) void k_b_rows(TrArgs a, const double *afr /
     }
     __syncthreads();
     band_rows_out_b<D>(a, r0, r1, accJ, accR);
-}
-
-// Rows of nodes that keep their value: residual 0, unit row.
-__global__ __launch_bounds__(256) void k_band_bc(int64_t n, int bs, const uint8_t *fre, const int32_t *rowptr,
-                                                 const int32_t *col, double *R, double *J, float *J32)
-{
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n || fre[r]) return;
-    for (int i = 0; i < bs; ++i) {
-        R[r * bs + i] = 0.0;
-        for (int k = rowptr[r]; k < rowptr[r + 1]; ++k)
-            for (int j = 0; j < bs; ++j) {
-                const bool one = col[k] == r && i == j;
-                J[((int64_t)k * bs + i) * bs + j] = one ? 1.0 : 0.0;
-                if (J32) J32[((int64_t)k * bs + i) * bs + j] = one ? 1.0f : 0.0f;
-            }
-    }
 }
 
 __global__ __launch_bounds__(256) void k_negate(double *x, int64_t n)
@@ -1100,6 +1111,7 @@ static TrArgs tr_args(eft_ctx *ctx, const Band &B, const double *lx, const doubl
     GA ga = ga_of(ctx->par.rho_inf, ctx->par.dt);
     TrArgs a;
     a.J32 = nullptr;
+    a.fre = B.fre;
     a.n = B.n;
     a.rpb = std::min(ctx->rpb, 64);
     a.maxc = ctx->maxc;
@@ -1146,8 +1158,6 @@ static eft_status assemble_ac(eft_ctx *ctx, const eft_state *lvl, const eft_iter
         else
             hipLaunchKernelGGL(k_ac_rows<3>, dim3(eft_grid(B.n, a.rpb)), dim3(256), shm, ctx->stream, a, ctx->par.eps,
                                gb);
-        hipLaunchKernelGGL(k_band_bc, dim3(eft_grid(B.n, 256)), dim3(256), 0, ctx->stream, B.n, 1, B.fre, B.rowptr,
-                           B.col, R, J, (float *)nullptr);
     }
     EFT_HIP(hipGetLastError());
     return EFT_OK;
@@ -1174,8 +1184,6 @@ static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_itera
         else
             hipLaunchKernelGGL(k_b_rows<3>, dim3(eft_grid(B.n, a.rpb)), dim3(256), shm, ctx->stream, a,
                                ctx->as + (int64_t)s * N);
-        hipLaunchKernelGGL(k_band_bc, dim3(eft_grid(B.n, 256)), dim3(256), 0, ctx->stream, B.n, nv, B.fre, B.rowptr,
-                           B.col, R, J, J32);
     }
     EFT_HIP(hipGetLastError());
     return EFT_OK;
