@@ -432,21 +432,29 @@ __global__ __launch_bounds__(256) void k_prolong(Dims cd, Dims fd, const uint8_t
 
 // Dense matrix of the coarsest level restricted to its free dofs: fidx maps a
 // dof to its free index (-1 for Dirichlet dofs, whose rows are unit rows).
+// M must be zero beforehand; one thread per (block, row of the block) writes
+// the free entries of that block row.
 template <typename TV>
-__global__ void k_dense_fill(int64_t n, int bs, const int32_t *rowptr, const int32_t *col, const TV *val,
-                             const int32_t *fidx, double *M, int64_t nd)
+__global__ void k_dense_fill(int64_t nnzb, int bs, const int32_t *rowptr, const int32_t *col, const TV *val,
+                             const int32_t *fidx, double *M, int64_t nd, int64_t n)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    for (int i = 0; i < bs; ++i) {
-        const int fi = fidx[r * bs + i];
-        if (fi < 0) continue;
-        for (int64_t j = 0; j < nd; ++j) M[fi * nd + j] = 0.0;
-        for (int k = rowptr[r]; k < rowptr[r + 1]; ++k)
-            for (int j = 0; j < bs; ++j) {
-                const int fj = fidx[(int64_t)col[k] * bs + j];
-                if (fj >= 0) M[fi * nd + fj] = (double)val[((int64_t)k * bs + i) * bs + j];
-            }
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nnzb * bs) return;
+    const int64_t k = t / bs;
+    const int i = (int)(t - k * bs);
+    // block row of block k: the last r with rowptr[r] <= k
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (rowptr[mid] <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    const int fi = fidx[lo * bs + i];
+    if (fi < 0) return;
+    const int64_t c = col[k];
+    for (int j = 0; j < bs; ++j) {
+        const int fj = fidx[c * bs + j];
+        if (fj >= 0) M[fi * nd + fj] = (double)val[(k * bs + i) * bs + j];
     }
 }
 
@@ -522,71 +530,57 @@ inline size_t gj_lds_bytes(int nd) { return sizeof(double) * ((size_t)2 * nd * n
 
 __global__ __launch_bounds__(256) void k_gauss_jordan_lds(const double *__restrict__ M, double *__restrict__ Inv, int nd)
 {
+    // thread j owns column j of [M | I] (2 nd <= 256 columns): the swap, the
+    // scaling and the elimination of a pivot step touch only the thread's own
+    // column, so a step needs two barriers (after the pivot search and the
+    // broadcast of the pivot column, and after the update)
     extern __shared__ double sm[];
     double *A = sm;                  // [nd][2 nd]
-    double *colk = sm + 2 * nd * nd; // [nd]
-    __shared__ double wv[4];
-    __shared__ int wi[4];
+    double *colk = sm + 2 * nd * nd; // [nd] pivot column after the swap, 0 at row k
     __shared__ int piv;
-    const int t = threadIdx.x, lane = t & 63, wv_id = t >> 6, W = 2 * nd;
+    __shared__ double pinv;
+    const int t = threadIdx.x, W = 2 * nd;
     for (int e = t; e < nd * W; e += 256) {
         const int i = e / W, j = e - i * W;
         A[e] = j < nd ? M[i * nd + j] : (j - nd == i ? 1.0 : 0.0);
     }
     __syncthreads();
     for (int k = 0; k < nd; ++k) {
-        // pivot: largest |A[i][k]| over i >= k (lowest i among equals)
-        double best = -1.0;
-        int bi = nd;
-        for (int i = k + t; i < nd; i += 256) {
-            const double a = fabs(A[i * W + k]);
-            if (a > best) {
-                best = a;
-                bi = i;
-            }
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            const double ob = __shfl_xor(best, o, 64);
-            const int oi = __shfl_xor(bi, o, 64);
-            if (ob > best || (ob == best && oi < bi)) {
-                best = ob;
-                bi = oi;
-            }
-        }
-        if (lane == 0) {
-            wv[wv_id] = best;
-            wi[wv_id] = bi;
-        }
-        __syncthreads();
-        if (t == 0) {
-            double b = wv[0];
-            int p = wi[0];
-            for (int w = 1; w < 4; ++w)
-                if (wv[w] > b || (wv[w] == b && wi[w] < p)) {
-                    b = wv[w];
-                    p = wi[w];
+        if (t < 64) {
+            // pivot: largest |A[i][k]| over i >= k (lowest i among equals)
+            double best = -1.0;
+            int bi = nd;
+            for (int i = k + t; i < nd; i += 64) {
+                const double a = fabs(A[i * W + k]);
+                if (a > best) {
+                    best = a;
+                    bi = i;
                 }
-            piv = p < nd ? p : k;
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ob = __shfl_xor(best, o, 64);
+                const int oi = __shfl_xor(bi, o, 64);
+                if (ob > best || (ob == best && oi < bi)) {
+                    best = ob;
+                    bi = oi;
+                }
+            }
+            const int p = bi < nd ? bi : k;
+            for (int i = t; i < nd; i += 64) colk[i] = i == k ? 0.0 : A[(i == p ? k : i) * W + k];
+            if (t == 0) {
+                piv = p;
+                const double d = A[p * W + k];
+                pinv = d != 0.0 ? 1.0 / d : 0.0;
+            }
         }
         __syncthreads();
-        const int p = piv;
-        if (p != k)
-            for (int j = t; j < W; j += 256) {
-                const double a = A[k * W + j];
-                A[k * W + j] = A[p * W + j];
-                A[p * W + j] = a;
-            }
-        __syncthreads();
-        const double d = A[k * W + k];
-        const double inv = d != 0.0 ? 1.0 / d : 0.0;
-        for (int i = t; i < nd; i += 256) colk[i] = A[i * W + k];
-        __syncthreads();
-        for (int j = t; j < W; j += 256) A[k * W + j] *= inv;
-        __syncthreads();
-        for (int e = t; e < nd * W; e += 256) {
-            const int i = e / W, j = e - i * W;
-            if (i == k) continue;
-            A[e] = j == k ? 0.0 : A[e] - colk[i] * A[k * W + j];
+        if (t < W) {
+            const int p = piv;
+            const double akj = A[p * W + t] * pinv;
+            if (p != k) A[p * W + t] = A[k * W + t];
+            A[k * W + t] = akj;
+            for (int i = 0; i < nd; ++i)
+                if (i != k) A[i * W + t] = t == k ? 0.0 : A[i * W + t] - colk[i] * akj;
         }
         __syncthreads();
     }
@@ -1057,8 +1051,10 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
     }
     if (ctx->mg_inv) {
         const MGLevel &Cc = ctx->mg.back();
-        hipLaunchKernelGGL(k_dense_fill<double>, dim3(eft_grid(Cc.N, 64)), dim3(64), 0, ctx->stream, Cc.N, bs,
-                           Cc.A.rowptr, Cc.A.col, Cc.A.val, ctx->mg_fidx, ctx->mg_dense, ctx->mg_nd);
+        EFT_TRY(eft_fill(ctx, ctx->mg_dense, ctx->mg_nd * ctx->mg_nd, 0.0));
+        hipLaunchKernelGGL(k_dense_fill<double>, dim3(eft_grid(Cc.A.nnzb * bs, 64)), dim3(64), 0, ctx->stream,
+                           Cc.A.nnzb, bs, Cc.A.rowptr, Cc.A.col, Cc.A.val, ctx->mg_fidx, ctx->mg_dense, ctx->mg_nd,
+                           Cc.N);
         const int nd = (int)ctx->mg_nd;
         if (nd <= GJ_LDS_MAX)
             hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(1), dim3(256), gj_lds_bytes(nd), ctx->stream, ctx->mg_dense,
