@@ -360,6 +360,35 @@ __global__ __launch_bounds__(256) void k_jsweep_rows(int64_t n, const int32_t *_
     }
 }
 
+// The same sweep with one block per lane (FP32 values, bs 6): a 16-lane
+// segment per block row, lane j < bs finishes component j.
+template <int BS, typename TV>
+__global__ __launch_bounds__(256) void k_jsweep_blk(int64_t n, const int32_t *__restrict__ rowptr,
+                                                    const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                    const double *__restrict__ Dinv, double omega,
+                                                    const double *__restrict__ v, const double *__restrict__ z,
+                                                    double *__restrict__ zo, const int32_t *active)
+{
+    constexpr int SEG = BlockSeg<BS>::SEG, RPW = BlockSeg<BS>::RPW;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave_id()) * RPW;
+    if (*active == 0 || row0 >= n) return;
+    const int lane = threadIdx.x & 63, q = lane / SEG, j = lane - q * SEG;
+    const int64_t row = row0 + q, rr = row < n ? row : row0;   // rr: in bounds, unused past n
+    const int jj = j < BS ? j : 0;
+    double vv[BS], d[BS];
+    x_get<BS>(v, rr, vv);
+    RowLoad<BS, double, false>::get(Dinv + (rr * BS + jj) * BS, d);
+    const double zr = z[rr * BS + jj];
+    int k0, k1;
+    seg_extents<RPW>(row0, n, rowptr, q, k0, k1);
+    double az[BS];
+    bsr_block_dot<BS, TV, SEG>(k0, k1, col, val, z, j, az);
+    double u = 0.0;
+#pragma unroll
+    for (int c = 0; c < BS; ++c) u += d[c] * (vv[c] - az[c]);
+    if (j < BS && row < n) zo[row * BS + j] = zr + omega * u;
+}
+
 template <typename TD> static eft_status bj_setup(eft_ctx *ctx, const eft_matrix *A, TD *Dinv)
 {
     if (A->n == 0) return EFT_OK;
@@ -436,8 +465,8 @@ eft_status eft_jacobi_apply(eft_ctx *ctx, const eft_matrix *A, const double *Din
             hipLaunchKernelGGL((k_jsweep_rows<3, double>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream,
                                n, A->rowptr, A->col, A->val, Dinv, omega, v, cur, nxt, active);
         else if (A->pc32)
-            hipLaunchKernelGGL((k_jsweep_rows<6, float>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream, n,
-                               A->rowptr, A->col, A->pc32, Dinv, omega, v, cur, nxt, active);
+            hipLaunchKernelGGL((k_jsweep_blk<6, float>), dim3(eft_grid(n, 4 * BlockSeg<6>::RPW)), dim3(256), 0,
+                               ctx->stream, n, A->rowptr, A->col, A->pc32, Dinv, omega, v, cur, nxt, active);
         else
             hipLaunchKernelGGL((k_jsweep_rows<6, double>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream,
                                n, A->rowptr, A->col, A->val, Dinv, omega, v, cur, nxt, active);
