@@ -297,7 +297,8 @@ eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *
         }
     }
     std::vector<int32_t> rowptr, col, diag, epos, iptr, ient;
-    EFT_TRY(eft_build_graph(N, E, nn, conn, rowptr, col, diag, epos, iptr, ient, ctx->maxc, ctx->rpb, ctx->err));
+    EFT_TRY(eft_build_graph(N, E, nn, conn, rowptr, col, diag, epos, iptr, ient, ctx->maxc, ctx->rpb, ctx->rpb_ns,
+                            ctx->err));
     const int64_t nnzb = (int64_t)col.size();
     // band grid: cells of band_cell mesh cells, element -> cell of its centroid
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};

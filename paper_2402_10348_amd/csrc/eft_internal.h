@@ -166,7 +166,8 @@ struct eft_ctx {
     int32_t *conn = nullptr;
     int32_t *epos = nullptr;        // [E][nn*nn] position of (a,b) in the NS pattern
     int32_t *iptr = nullptr, *ient = nullptr;  // node -> incident (element << 2 | local node)
-    int maxc = 0, rpb = 1;          // longest row of the node graph, rows per assembly workgroup
+    int maxc = 0, rpb = 1;          // longest row of the node graph, rows per band-assembly workgroup
+    int rpb_ns = 1;                 // rows per momentum/mass assembly workgroup
     int32_t *cell_of = nullptr;     // [E] band grid cell of each element
     int64_t n_dir = 0;
     int32_t *dir_node = nullptr;
@@ -285,7 +286,7 @@ bool eft_mg_active(const eft_ctx *ctx, const eft_matrix *A);
 eft_status eft_build_graph(int64_t N, int64_t E, int nn, const int32_t *conn, std::vector<int32_t> &rowptr,
                            std::vector<int32_t> &col, std::vector<int32_t> &diag, std::vector<int32_t> &epos,
                            std::vector<int32_t> &iptr, std::vector<int32_t> &ient, int &maxc, int &rpb,
-                           std::string &err);
+                           int &rpb_ns, std::string &err);
 eft_status eft_fill(eft_ctx *ctx, double *p, int64_t n, double v);
 eft_status eft_fill32(eft_ctx *ctx, float *p, int64_t n, float v);
 eft_status eft_fill_u8(eft_ctx *ctx, uint8_t *p, int64_t n);

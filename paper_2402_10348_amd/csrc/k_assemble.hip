@@ -630,7 +630,7 @@ eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_ma
     M.iptr = ctx->iptr;
     M.ient = ctx->ient;
     M.maxc = ctx->maxc;
-    M.rpb = ctx->rpb;
+    M.rpb = ctx->rpb_ns;
     // with the multigrid active, the assembly also writes the finest level's
     // FP32 copy of the values (no separate conversion pass over J)
     const bool mg = J && eft_mg_active(ctx, J);

@@ -692,10 +692,12 @@ Dims dims_of(const MGLevel &L) { return Dims{{L.n[0], L.n[1], L.n[2]}}; }
 // Node graph of a simplex mesh: sorted columns per row (self included), the
 // diagonal position per row and, per element, the position of each node
 // pair (a, b) in row a.
+constexpr int64_t NS_PAIRS = 512;   // (row, element) pairs per momentum-assembly workgroup
+
 eft_status eft_build_graph(int64_t N, int64_t E, int nn, const int32_t *conn, std::vector<int32_t> &rowptr,
                            std::vector<int32_t> &col, std::vector<int32_t> &diag, std::vector<int32_t> &epos,
                            std::vector<int32_t> &iptr, std::vector<int32_t> &ient, int &maxc, int &rpb,
-                           std::string &err)
+                           int &rpb_ns, std::string &err)
 {
     if (E >= (1LL << 29) || (int64_t)E * nn >= 2000000000LL) {
         err = "too many elements for 32-bit incidence entries";
@@ -761,6 +763,11 @@ eft_status eft_build_graph(int64_t N, int64_t E, int nn, const int32_t *conn, st
     // the row accumulators of the largest block size within 40 KB of LDS
     const int64_t rowbytes = (int64_t)maxc * 37 * 8 + 7 * 8;   // padded 6x6 blocks (transport)
     rpb = (int)std::max<int64_t>(1, std::min<int64_t>(512 / maxinc, 40960 / rowbytes));
+    // the momentum/mass assembly (padded nn x nn blocks): about NS_PAIRS
+    // (row, element) pairs per 256-thread workgroup, within 64 KB of LDS (its
+    // register count allows two workgroups per compute unit)
+    const int64_t rowbytes_ns = (int64_t)maxc * ((nn * nn) | 1) * 8 + (nn | 1) * 8;
+    rpb_ns = (int)std::max<int64_t>(1, std::min<int64_t>(NS_PAIRS / maxinc, 65536 / rowbytes_ns));
     return EFT_OK;
 }
 
@@ -852,8 +859,9 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
             }
         }
         std::vector<int32_t> rowptr, col, diag, epos, iptr, ient;
-        EFT_TRY(eft_build_graph(C.N, C.E, nn, conn.data(), rowptr, col, diag, epos, iptr, ient, C.maxc, C.rpb,
-                                ctx->err));
+        int rpb_band = 1;   // (no band systems on the coarse levels)
+        EFT_TRY(eft_build_graph(C.N, C.E, nn, conn.data(), rowptr, col, diag, epos, iptr, ient, C.maxc, rpb_band,
+                                C.rpb, ctx->err));
         EFT_TRY(dput(ctx, &C.iptr, iptr));
         EFT_TRY(dput(ctx, &C.ient, ient));
         EFT_TRY(dput(ctx, &C.conn, conn));
