@@ -759,9 +759,11 @@ eft_status eft_build_graph(int64_t N, int64_t E, int nn, const int32_t *conn, st
     }
     maxc = 1;
     for (int64_t p = 0; p < N; ++p) maxc = std::max(maxc, rowptr[p + 1] - rowptr[p]);
-    // rows per assembly workgroup: about two incident elements per thread, and
-    // the row accumulators of the largest block size within 40 KB of LDS
-    const int64_t rowbytes = (int64_t)maxc * 37 * 8 + 7 * 8;   // padded 6x6 blocks (transport)
+    // rows per band-assembly workgroup: about two incident elements per
+    // thread, and the row accumulators within 40 KB of LDS (a B-system block
+    // accumulates 1 + 3 x 3 numbers, 11 doubles with the odd padding; a
+    // residual row 7)
+    const int64_t rowbytes = (int64_t)maxc * 11 * 8 + 7 * 8;
     rpb = (int)std::max<int64_t>(1, std::min<int64_t>(512 / maxinc, 40960 / rowbytes));
     // the momentum/mass assembly (padded nn x nn blocks): about NS_PAIRS
     // (row, element) pairs per 256-thread workgroup, within 64 KB of LDS (its
