@@ -90,7 +90,7 @@ void free_all(eft_ctx *ctx)
     auto fr = [](void *p) {
         if (p) (void)hipFree(p);
     };
-    fr(ctx->xyz); fr(ctx->conn); fr(ctx->epos); fr(ctx->iptr); fr(ctx->ient); fr(ctx->cell_of); fr(ctx->dir_node); fr(ctx->dir_mask);
+    fr(ctx->xyz); fr(ctx->conn); fr(ctx->epos); fr(ctx->iptr); fr(ctx->ient); fr(ctx->cell_of); fr(ctx->dir_node); fr(ctx->dir_mask); fr(ctx->fmask0);
     fr(ctx->dir_val); fr(ctx->phase_tab); fr(ctx->ind_of_phase);
     fr(ctx->J.rowptr); fr(ctx->J.col); fr(ctx->J.diag); fr(ctx->J.val); fr(ctx->J.val32);
     fr(ctx->va); fr(ctx->acc); fr(ctx->rho); fr(ctx->mu); fr(ctx->as); fr(ctx->Ba); fr(ctx->R); fr(ctx->dx);
@@ -361,13 +361,15 @@ eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *
     EFT_TRY(upload(ctx, &ctx->J.col, col.data(), nnzb));
     EFT_TRY(upload(ctx, &ctx->J.diag, diag.data(), N));
     EFT_TRY(alloc_jacobian_values(ctx));
+    // Dirichlet bits of every node, and the free bits the assembly writes
+    // unit rows by
+    std::vector<uint8_t> dm(N, 0), fm(N);
+    for (int64_t t = 0; t < mesh->n_dir; ++t) dm[mesh->dir_node[t]] |= mesh->dir_mask[t];
+    for (int64_t p = 0; p < N; ++p) fm[p] = (uint8_t)(~dm[p] & ((1 << bs) - 1));
+    EFT_TRY(upload(ctx, &ctx->fmask0, fm.data(), N));
     // geometric multigrid needs the structured Kuhn layout of a box
     ctx->structured = structured_kuhn(d, mesh->grid, N, E, mesh->xyz, conn);
-    if (ctx->structured) {
-        std::vector<uint8_t> dm(N, 0);
-        for (int64_t t = 0; t < mesh->n_dir; ++t) dm[mesh->dir_node[t]] |= mesh->dir_mask[t];
-        EFT_TRY(eft_mg_create(ctx, mesh->grid, dm));
-    }
+    if (ctx->structured) EFT_TRY(eft_mg_create(ctx, mesh->grid, dm));
     const int mx = std::max(bs, nv);
     EFT_TRY(dalloc(ctx, &ctx->va, N * d));
     EFT_TRY(dalloc(ctx, &ctx->acc, N * d));

@@ -74,6 +74,7 @@ struct MeshView {
     const uint8_t *dir_mask = nullptr;
     const int32_t *iptr = nullptr, *ient = nullptr;  // node -> (element << 2 | local node)
     int maxc = 0, rpb = 1;                           // longest matrix row, rows per workgroup
+    const uint8_t *fmask = nullptr;                  // [N] bit c set when dof c is free (others: unit rows)
 };
 
 // One level of the geometric multigrid hierarchy on nested Kuhn meshes.
@@ -166,6 +167,7 @@ struct eft_ctx {
     int32_t *conn = nullptr;
     int32_t *epos = nullptr;        // [E][nn*nn] position of (a,b) in the NS pattern
     int32_t *iptr = nullptr, *ient = nullptr;  // node -> incident (element << 2 | local node)
+    uint8_t *fmask0 = nullptr;      // [N] bit c set when dof c of the node is free (not Dirichlet)
     int maxc = 0, rpb = 1;          // longest row of the node graph, rows per band-assembly workgroup
     int rpb_ns = 1;                 // rows per momentum/mass assembly workgroup
     int32_t *cell_of = nullptr;     // [E] band grid cell of each element

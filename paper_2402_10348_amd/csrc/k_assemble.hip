@@ -101,6 +101,8 @@ struct RowArgs {
     double *R;
     float *J32;      // optional FP32 copy of the values
     uint16_t *J16;   // optional BF16 copy of the values
+    const int32_t *col;      // block columns of the pattern
+    const uint8_t *fmask;    // [N] free-dof bits: a Dirichlet dof's row is written as a unit row, residual 0
 };
 
 template <int D, typename TJ>
@@ -410,39 +412,19 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
     __syncthreads();
     for (int64_t r = r0; r < r1; ++r) {
         const int lr = (int)(r - r0);
-        if (threadIdx.x < BS) a.R[r * BS + threadIdx.x] = accR[lr * RP + threadIdx.x];
+        const int fm = a.fmask[r];
+        if (threadIdx.x < BS) a.R[r * BS + threadIdx.x] = ((fm >> threadIdx.x) & 1) ? accR[lr * RP + threadIdx.x] : 0.0;
         if (Jv == nullptr) continue;
         const int64_t kb = a.rowptr[r], len = a.rowptr[r + 1] - kb;
         for (int t = threadIdx.x; t < len * B2; t += blockDim.x)
         {
-            const double v = accJ[((int64_t)lr * a.maxc + t / B2) * BP + t % B2];
+            const int kk = t / B2, e = t - kk * B2;
+            double v = accJ[((int64_t)lr * a.maxc + kk) * BP + e];
+            if (!((fm >> (e / BS)) & 1)) v = (a.col[kb + kk] == r && e % (BS + 1) == 0) ? 1.0 : 0.0;
             Jv[kb * B2 + t] = (TJ)v;
             if (a.J32) a.J32[kb * B2 + t] = (float)v;
             if (a.J16) a.J16[kb * B2 + t] = to_bf16_rne((float)v);
         }
-    }
-}
-
-// ------------------------------------------------------ boundary rows ----
-
-// 1 or 0 in the value type of a matrix copy (uint16_t: BF16 bit pattern)
-template <typename TJ> __device__ __forceinline__ TJ unit_or_zero(bool one) { return one ? TJ(1) : TJ(0); }
-template <> __device__ __forceinline__ uint16_t unit_or_zero<uint16_t>(bool one) { return one ? 0x3F80u : 0u; }
-
-template <typename TJ>
-__global__ void k_bc_rows(int64_t n_dir, const int32_t *dir_node, const uint8_t *dir_mask, const int32_t *rowptr,
-                          const int32_t *col, int BS, double *R, TJ *Jv)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_dir) return;
-    const int n = dir_node[t];
-    const int m = dir_mask[t];
-    for (int i = 0; i < BS; ++i) {
-        if (!((m >> i) & 1)) continue;
-        if (R) R[(int64_t)n * BS + i] = 0.0;
-        if (!Jv) continue;
-        for (int k = rowptr[n]; k < rowptr[n + 1]; ++k)
-            for (int j = 0; j < BS; ++j) Jv[((int64_t)k * BS + i) * BS + j] = unit_or_zero<TJ>(col[k] == n && j == i);
     }
 }
 
@@ -539,6 +521,12 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
     a.conn = M.conn;
     a.epos = M.epos;
     a.rowptr = J ? J->rowptr : nullptr;
+    a.col = J ? J->col : nullptr;
+    a.fmask = M.fmask;
+    if (!M.fmask) {
+        ctx->err = "assembly without the free-dof mask";
+        return EFT_EINVAL;
+    }
     a.xyz = M.xyz;
     a.va = M.va;
     a.acc = M.acc;
@@ -567,9 +555,9 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
     const int nb = eft_grid(M.N, M.rpb);
     const size_t shm = (size_t)M.rpb * ((size_t)M.maxc * ((BS * BS) | 1) + (BS | 1)) * sizeof(double);
     // kernel-timing hook on the mesh level (not the coarse levels).
-    // Algorithmic bytes: J (and its FP32 copy when written) and R written
-    // once, the connectivity and every node field the element evaluation
-    // reads, once.
+    // Algorithmic bytes: J (and its FP32 or BF16 copy when written) and R
+    // written once, the connectivity, every node field the element
+    // evaluation reads and the free-dof bits, once.
     const bool fine = M.conn == ctx->conn;
     const int64_t slot = fine ? eft_kt_begin(ctx, EFT_KT_ASSEMBLE) : -1;
     const int d = ctx->dim;
@@ -577,7 +565,7 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
         (J ? (double)J->nnzb * BS * BS * ((J->fp32 ? 4.0 : 8.0) + (a.J32 ? 4.0 : 0.0) + (a.J16 ? 2.0 : 0.0)) : 0.0) +
         (double)M.N * BS * 8.0 +
         (double)M.E * (d + 1) * 4.0 +
-        (double)M.N * 8.0 * (d + BS + d + d + 2 + (double)ctx->n_s * (1 + ctx->nv));
+        (double)M.N * 8.0 * (d + BS + d + d + 2 + (double)ctx->n_s * (1 + ctx->nv)) + (double)M.N;
     if (ctx->dim == 2) {
         if (J && J->fp32) hipLaunchKernelGGL((k_ns_rows<2, float>), dim3(nb), dim3(256), shm, ctx->stream, a, J->val32);
         else hipLaunchKernelGGL((k_ns_rows<2, double>), dim3(nb), dim3(256), shm, ctx->stream, a, J ? J->val : nullptr);
@@ -587,23 +575,6 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
     }
     EFT_HIP(hipGetLastError());
     eft_kt_end(ctx, slot, abytes, EFT_KT_ASSEMBLE);
-    if (M.n_dir > 0) {
-        const int nbd = eft_grid(M.n_dir, 128);
-        if (J && J->fp32)
-            hipLaunchKernelGGL(k_bc_rows<float>, dim3(nbd), dim3(128), 0, ctx->stream, M.n_dir, M.dir_node, M.dir_mask,
-                               J->rowptr, J->col, BS, R, J->val32);
-        else
-            hipLaunchKernelGGL(k_bc_rows<double>, dim3(nbd), dim3(128), 0, ctx->stream, M.n_dir, M.dir_node,
-                               M.dir_mask, J ? J->rowptr : nullptr, J ? J->col : nullptr, BS, R,
-                               J ? J->val : (double *)nullptr);
-        if (a.J32)   // the same unit rows in the FP32 copy
-            hipLaunchKernelGGL(k_bc_rows<float>, dim3(nbd), dim3(128), 0, ctx->stream, M.n_dir, M.dir_node, M.dir_mask,
-                               J->rowptr, J->col, BS, (double *)nullptr, a.J32);
-        if (a.J16)   // and in the BF16 copy
-            hipLaunchKernelGGL(k_bc_rows<uint16_t>, dim3(nbd), dim3(128), 0, ctx->stream, M.n_dir, M.dir_node,
-                               M.dir_mask, J->rowptr, J->col, BS, (double *)nullptr, a.J16);
-        EFT_HIP(hipGetLastError());
-    }
     return EFT_OK;
 }
 
@@ -627,6 +598,7 @@ eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_ma
     M.n_dir = ctx->n_dir;
     M.dir_node = ctx->dir_node;
     M.dir_mask = ctx->dir_mask;
+    M.fmask = ctx->fmask0;
     M.iptr = ctx->iptr;
     M.ient = ctx->ient;
     M.maxc = ctx->maxc;

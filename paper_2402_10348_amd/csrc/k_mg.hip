@@ -1051,6 +1051,7 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
         M.n_dir = C.n_dir;
         M.dir_node = C.dir_node;
         M.dir_mask = C.dir_mask;
+        M.fmask = C.fmask;
         M.iptr = C.iptr;
         M.ient = C.ient;
         M.maxc = C.maxc;
