@@ -474,7 +474,7 @@ __device__ __forceinline__ void band_rows_out_b(const TrArgs &a, int64_t r0, int
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void k_ac_rows(TrArgs a, double eps, const double *gb /* gamma, beta */)
+__global__ __launch_bounds__(256, 3) void k_ac_rows(TrArgs a, double eps, const double *gb /* gamma, beta */)
 {
     extern __shared__ double lds[];
     constexpr int NN = D + 1, NQ = Rule<D>::NQ;
