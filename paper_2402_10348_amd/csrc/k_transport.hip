@@ -183,18 +183,29 @@ __global__ __launch_bounds__(256) void k_band_fill(int64_t n, const int32_t *nod
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void k_band_epos(int64_t ne, const int32_t *elem, const int32_t *conn,
-                                                   const int32_t *epos, const int32_t *gpos2b, const int32_t *g2b,
-                                                   int32_t *bepos, int32_t *bconn)
+__global__ __launch_bounds__(256) void k_band_epos(int64_t ne, const int32_t *__restrict__ elem,
+                                                   const int32_t *__restrict__ conn, const int32_t *__restrict__ epos,
+                                                   const int32_t *__restrict__ gpos2b, const int32_t *__restrict__ g2b,
+                                                   int32_t *__restrict__ bepos, int32_t *__restrict__ bconn)
 {
     const int64_t be = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (be >= ne) return;
     constexpr int NN = D + 1;
     const int64_t e = elem[be];
+    // all indices, then all gathers, then the stores: three round trips
+    int32_t c[NN], ep[NN * NN];
 #pragma unroll
-    for (int a = 0; a < NN; ++a) bconn[be * NN + a] = g2b[conn[e * NN + a]];
+    for (int a = 0; a < NN; ++a) c[a] = conn[e * NN + a];
 #pragma unroll
-    for (int t = 0; t < NN * NN; ++t) bepos[be * NN * NN + t] = gpos2b[epos[e * NN * NN + t]];
+    for (int t = 0; t < NN * NN; ++t) ep[t] = epos[e * NN * NN + t];
+#pragma unroll
+    for (int a = 0; a < NN; ++a) c[a] = g2b[c[a]];
+#pragma unroll
+    for (int t = 0; t < NN * NN; ++t) ep[t] = gpos2b[ep[t]];
+#pragma unroll
+    for (int a = 0; a < NN; ++a) bconn[be * NN + a] = c[a];
+#pragma unroll
+    for (int t = 0; t < NN * NN; ++t) bepos[be * NN * NN + t] = ep[t];
 }
 
 // ------------------------------------------------------------ mobility ----
@@ -487,13 +498,20 @@ __global__ __launch_bounds__(256, 3) void k_ac_rows(TrArgs a, double eps, const 
     const double kh = eps * eps, al = a.alpha, ct = a.ct, i4 = 4.0 / (a.dt * a.dt);
     // incidences of the workgroup's rows, flattened (band rows are not
     // contiguous global nodes)
-    __shared__ int maxinc;
+    // per row, staged in LDS (at most 64 rows): first incidence, end of the
+    // incidences (the first again for a row that keeps its value, written
+    // as a unit row), first block of the row in the global pattern
+    __shared__ int maxinc, s_ip0[64], s_ip1[64], s_gb0[64];
     if (threadIdx.x == 0) maxinc = 0;
     __syncthreads();
     const int nrow = (int)(r1 - r0);
     if (threadIdx.x < nrow) {
         const int64_t gg = a.node[r0 + threadIdx.x];
-        atomicMax(&maxinc, a.iptr[gg + 1] - a.iptr[gg]);
+        const int i0 = a.iptr[gg], i1 = a.iptr[gg + 1];
+        s_ip0[threadIdx.x] = i0;
+        s_ip1[threadIdx.x] = a.fre[r0 + threadIdx.x] ? i1 : i0;
+        s_gb0[threadIdx.x] = a.grow[gg];
+        atomicMax(&maxinc, i1 - i0);
     }
     __syncthreads();
     {
@@ -501,18 +519,20 @@ __global__ __launch_bounds__(256, 3) void k_ac_rows(TrArgs a, double eps, const 
         // rows, so the LDS atomics of one wavefront rarely hit one block
         for (int t = threadIdx.x; t < nrow * maxinc; t += blockDim.x) {
             const int lr = t % nrow;
-            if (!a.fre[r0 + lr]) continue;   // (written as a unit row)
-            const int64_t g = a.node[r0 + lr];
-            const int ii = a.iptr[g] + t / nrow;
-            if (ii >= a.iptr[g + 1]) continue;
+            const int ii = s_ip0[lr] + t / nrow;
+            if (ii >= s_ip1[lr]) continue;
             const int32_t ent = a.ient[ii];
             const int64_t e = ent >> 2;
             const int la = ent & 3;
+            // the element's nodes are loaded together with its band flag
+            int64_t nid[NN];
+#pragma unroll
+            for (int b = 0; b < NN; ++b) nid[b] = a.conn[e * NN + b];
             if (!a.eflag[e]) continue;
             double X[NN][D], v[NN][D], f[NN], fd[NN];
 #pragma unroll
             for (int b = 0; b < NN; ++b) {
-                const int64_t n = a.conn[e * NN + b];
+                const int64_t n = nid[b];
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
                     X[b][i] = a.xyz[n * D + i];
@@ -600,7 +620,7 @@ __global__ __launch_bounds__(256, 3) void k_ac_rows(TrArgs a, double eps, const 
                 }
             }
             atomicAdd(accR + lr, re);
-            const int64_t gb0 = a.grow[g];
+            const int64_t gb0 = s_gb0[lr];
 #pragma unroll
             for (int ib = 0; ib < NN; ++ib) atomicAdd(accJ + (int64_t)lr * a.maxc + (a.epos[e * NN * NN + la * NN + ib] - gb0), K[ib]);
         }
@@ -628,13 +648,20 @@ __global__ __launch_bounds__(256, 2) void k_b_rows(TrArgs a, const double *afr /
     const double al = a.alpha, ct = a.ct, i4 = 4.0 / (a.dt * a.dt);
     // incidences of the workgroup's rows, flattened (band rows are not
     // contiguous global nodes)
-    __shared__ int maxinc;
+    // per row, staged in LDS (at most 64 rows): first incidence, end of the
+    // incidences (the first again for a row that keeps its value, written
+    // as a unit row), first block of the row in the global pattern
+    __shared__ int maxinc, s_ip0[64], s_ip1[64], s_gb0[64];
     if (threadIdx.x == 0) maxinc = 0;
     __syncthreads();
     const int nrow = (int)(r1 - r0);
     if (threadIdx.x < nrow) {
         const int64_t gg = a.node[r0 + threadIdx.x];
-        atomicMax(&maxinc, a.iptr[gg + 1] - a.iptr[gg]);
+        const int i0 = a.iptr[gg], i1 = a.iptr[gg + 1];
+        s_ip0[threadIdx.x] = i0;
+        s_ip1[threadIdx.x] = a.fre[r0 + threadIdx.x] ? i1 : i0;
+        s_gb0[threadIdx.x] = a.grow[gg];
+        atomicMax(&maxinc, i1 - i0);
     }
     __syncthreads();
     {
@@ -642,20 +669,20 @@ __global__ __launch_bounds__(256, 2) void k_b_rows(TrArgs a, const double *afr /
         // rows, so the LDS atomics of one wavefront rarely hit one block
         for (int t = threadIdx.x; t < nrow * maxinc; t += blockDim.x) {
             const int lr = t % nrow;
-            if (!a.fre[r0 + lr]) continue;   // (written as a unit row)
-            const int64_t g = a.node[r0 + lr];
-            const int ii = a.iptr[g] + t / nrow;
-            if (ii >= a.iptr[g + 1]) continue;
+            const int ii = s_ip0[lr] + t / nrow;
+            if (ii >= s_ip1[lr]) continue;
             const int32_t ent = a.ient[ii];
             const int64_t e = ent >> 2;
             const int la = ent & 3;
-            if (!a.eflag[e]) continue;
-            double X[NN][D], v[NN][D], am[NN];
+            // the element's nodes are loaded together with its band flag
             int64_t nid[NN];
 #pragma unroll
+            for (int b = 0; b < NN; ++b) nid[b] = a.conn[e * NN + b];
+            if (!a.eflag[e]) continue;
+            double X[NN][D], v[NN][D], am[NN];
+#pragma unroll
             for (int b = 0; b < NN; ++b) {
-                const int64_t n = a.conn[e * NN + b];
-                nid[b] = n;
+                const int64_t n = nid[b];
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
                     X[b][i] = a.xyz[n * D + i];
@@ -764,7 +791,7 @@ __global__ __launch_bounds__(256, 2) void k_b_rows(TrArgs a, const double *afr /
             }
 #pragma unroll
             for (int c = 0; c < NVv; ++c) atomicAdd(accR + lr * RP + c, re[c]);
-            const int64_t gb0 = a.grow[g];
+            const int64_t gb0 = s_gb0[lr];
 #pragma unroll
             for (int ib = 0; ib < NN; ++ib) {
                 const double s2 = al * S2[ib];
