@@ -547,7 +547,7 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
     a.g2 = ctx->g[2];
     a.R = R;
     a.J32 = (J && !J->fp32) ? J32 : nullptr;
-    a.J16 = (J && !J->fp32) ? J16 : nullptr;
+    a.J16 = J ? J16 : nullptr;
     if (!J) {
         // residual only: one row of accumulators suffices for the pattern-free path
         a.rowptr = ctx->J.rowptr;

@@ -911,6 +911,7 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
         MGLevel &C = ctx->mg[l];
         C.A.fp32 = true;
         EFT_TRY(dmal(ctx, &C.A.val32, C.A.nnzb * bs * bs));
+        EFT_TRY(dmal(ctx, &C.A.val16, C.A.nnzb * bs * bs));
         EFT_TRY(dmal(ctx, &C.Dinv32, C.N * bs * bs));
     }
     MGLevel &F0 = ctx->mg[0];
@@ -1056,7 +1057,10 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
         M.ient = C.ient;
         M.maxc = C.maxc;
         M.rpb = C.rpb;
-        EFT_TRY(eft_ns_level(ctx, M, C.vp, C.R, &C.A));
+        // intermediate levels: FP32 values (block inverses) and, with
+        // mg_bf16, a BF16 copy for the sweeps and residuals
+        C.A.bf16 = C.A.fp32 && ctx->par.mg_bf16 != 0;
+        EFT_TRY(eft_ns_level(ctx, M, C.vp, C.R, &C.A, nullptr, C.A.bf16 ? C.A.val16 : nullptr));
         if (C.A.fp32) EFT_TRY(eft_bj_setup32(ctx, &C.A, C.Dinv32));
         else EFT_TRY(eft_bj_setup(ctx, &C.A, C.Dinv));
     }
