@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) void k_jsweep1(int64_t n, const int32_t *__res
 }
 
 // bs in {3, 6}: SPMV_R block rows per wavefront (bsr_rows.h), lanes 0..bs-1
-// finish the rows.  Values FP64 or an FP32 copy (the arithmetic FP64).
+// finish the rows.  Values FP64 or a BF16 copy (the arithmetic FP64).
 template <int BS, typename TV>
 __global__ __launch_bounds__(256) void k_jsweep_rows(int64_t n, const int32_t *__restrict__ rowptr,
                                                      const int32_t *__restrict__ col, const TV *__restrict__ val,
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(256) void k_jsweep_rows(int64_t n, const int32_t *_
     }
 }
 
-// The same sweep with one block per lane (FP32 values, bs 6): a 16-lane
+// The same sweep with one block per lane (narrow values, bs 6): a 16-lane
 // segment per block row, lane j < bs finishes component j.
 template <int BS, typename TV>
 __global__ __launch_bounds__(256) void k_jsweep_blk(int64_t n, const int32_t *__restrict__ rowptr,
@@ -458,15 +458,17 @@ eft_status eft_jacobi_apply(eft_ctx *ctx, const eft_matrix *A, const double *Din
         if (bs == 1)
             hipLaunchKernelGGL(k_jsweep1, dim3(eft_grid(n, 16)), dim3(256), 0, ctx->stream, n, A->rowptr, A->col,
                                A->val, Dinv, omega, v, cur, nxt, active);
-        else if (bs == 3 && A->pc32)
-            hipLaunchKernelGGL((k_jsweep_rows<3, float>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream, n,
-                               A->rowptr, A->col, A->pc32, Dinv, omega, v, cur, nxt, active);
+        else if (bs == 3 && A->pc16)
+            hipLaunchKernelGGL((k_jsweep_rows<3, eft_bf16>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream,
+                               n, A->rowptr, A->col, reinterpret_cast<const eft_bf16 *>(A->pc16), Dinv, omega, v,
+                               cur, nxt, active);
         else if (bs == 3)
             hipLaunchKernelGGL((k_jsweep_rows<3, double>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream,
                                n, A->rowptr, A->col, A->val, Dinv, omega, v, cur, nxt, active);
-        else if (A->pc32)
-            hipLaunchKernelGGL((k_jsweep_blk<6, float>), dim3(eft_grid(n, 4 * BlockSeg<6>::RPW)), dim3(256), 0,
-                               ctx->stream, n, A->rowptr, A->col, A->pc32, Dinv, omega, v, cur, nxt, active);
+        else if (A->pc16)
+            hipLaunchKernelGGL((k_jsweep_blk<6, eft_bf16>), dim3(eft_grid(n, 4 * BlockSeg<6>::RPW)), dim3(256), 0,
+                               ctx->stream, n, A->rowptr, A->col, reinterpret_cast<const eft_bf16 *>(A->pc16), Dinv,
+                               omega, v, cur, nxt, active);
         else
             hipLaunchKernelGGL((k_jsweep_rows<6, double>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream,
                                n, A->rowptr, A->col, A->val, Dinv, omega, v, cur, nxt, active);
