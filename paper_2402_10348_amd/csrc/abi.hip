@@ -99,7 +99,7 @@ void free_all(eft_ctx *ctx)
         fr(B.node); fr(B.elem); fr(B.epos); fr(B.bconn_); fr(B.fre); fr(B.eflag); fr(B.rowptr); fr(B.col); fr(B.diag);
     }
     fr(ctx->seed); fr(ctx->active); fr(ctx->nin); fr(ctx->nout); fr(ctx->ein); fr(ctx->g2b); fr(ctx->gpos2b);
-    fr(ctx->scan_tmp); fr(ctx->bR); fr(ctx->bX); fr(ctx->bval); fr(ctx->bval16); fr(ctx->tnum); fr(ctx->tden); fr(ctx->red);
+    fr(ctx->scan_tmp); fr(ctx->bR); fr(ctx->bX); fr(ctx->bval); fr(ctx->bcmp); fr(ctx->tnum); fr(ctx->tden); fr(ctx->red);
     fr(ctx->dscal);
     eft_mg_free(ctx);
     KrylovWs &K = ctx->kw;

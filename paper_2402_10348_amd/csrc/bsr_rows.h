@@ -121,13 +121,6 @@ template <int BS, bool NT> struct RowLoad<BS, eft_bf16, NT> {
                 v[4 * q + 2] = bf16_to_double(t.y & 0xFFFFu);
                 v[4 * q + 3] = bf16_to_double(t.y >> 16);
             }
-        } else if constexpr (BS % 2 == 0) {
-#pragma unroll
-            for (int q = 0; q < BS / 2; ++q) {
-                const uint32_t t = ld_hint<NT>(reinterpret_cast<const uint32_t *>(p) + q);
-                v[2 * q] = bf16_to_double(t & 0xFFFFu);
-                v[2 * q + 1] = bf16_to_double(t >> 16);
-            }
         } else {
 #pragma unroll
             for (int q = 0; q < BS; ++q) v[q] = bf16_to_double(p[q].v);

@@ -27,7 +27,7 @@ struct eft_matrix {
     double *val = nullptr;
     float *val32 = nullptr;
     uint16_t *val16 = nullptr;   // BF16 values (the finest multigrid level's copy)
-    uint16_t *pc16 = nullptr;    // BF16 copy of val for the preconditioner's sweeps (band systems)
+    const double *bcmp = nullptr;  // B systems: the blocks in compact form (s1, M), see eft_bcmp_*
     bool fp32 = false;
     bool bf16 = false;
 };
@@ -211,7 +211,7 @@ struct eft_ctx {
     int64_t scan_cap = 0;
     double *bR = nullptr, *bX = nullptr;         // band system rhs / solution [cap][nv]
     double *bval = nullptr;                      // band matrix values [cap_nnz][nv*nv]
-    uint16_t *bval16 = nullptr;                  // their BF16 copy (B systems' preconditioner sweeps)
+    double *bcmp = nullptr;                      // B blocks in compact form [cap_nnz][1 + dim^2]
     int64_t bcap_n = 0, bcap_nnz = 0;
     double *tnum = nullptr, *tden = nullptr;     // mobility projection sums [cap_n]
     // reductions and host mirror
@@ -301,10 +301,15 @@ eft_status eft_bj_apply(eft_ctx *ctx, int bs, int64_t n, const double *Dinv, con
                         const int32_t *active);
 // z = M v with M = `sweeps` damped point-block Jacobi sweeps from z = 0
 // (tmp: scratch of the size of v; sweeps = 1, omega = 1 is block Jacobi;
-// the products of the later sweeps read A->pc16 when it is set)
+// the products read the compact blocks A->bcmp when they are set)
 eft_status eft_jacobi_apply(eft_ctx *ctx, const eft_matrix *A, const double *Dinv, const double *v, double *z,
                             double *tmp, int sweeps, double omega, const int32_t *active);
 eft_status eft_spmv_flag(eft_ctx *ctx, const eft_matrix *A, const double *x, double *y, const int32_t *active);
+// B-system products from the compact blocks (A->bcmp, bs 3 or 6): y = A x,
+// and one damped Jacobi sweep zo = z + omega D^-1 (v - A z)
+eft_status eft_bcmp_spmv(eft_ctx *ctx, const eft_matrix *A, const double *x, double *y, const int32_t *active);
+eft_status eft_bcmp_sweep(eft_ctx *ctx, const eft_matrix *A, const double *Dinv, double omega, const double *v,
+                          const double *z, double *zo, const int32_t *active);
 
 // k_krylov.hip
 eft_status eft_krylov_reserve(eft_ctx *ctx, int64_t n, int bs, int m);

@@ -152,6 +152,7 @@ static void spmv_launch(eft_ctx *ctx, int64_t n, int bs, const int32_t *rowptr, 
 eft_status eft_spmv_flag(eft_ctx *ctx, const eft_matrix *A, const double *x, double *y, const int32_t *active)
 {
     if (A->n == 0) return EFT_OK;
+    if (A->bcmp) return eft_bcmp_spmv(ctx, A, x, y, active);
     if (A->fp32)
         spmv_launch<float>(ctx, A->n, A->bs, A->rowptr, A->col, A->val32, x, y, active);
     else
@@ -360,33 +361,118 @@ __global__ __launch_bounds__(256) void k_jsweep_rows(int64_t n, const int32_t *_
     }
 }
 
-// The same sweep with one block per lane (narrow values, bs 6): a 16-lane
-// segment per block row, lane j < bs finishes component j.
-template <int BS, typename TV>
-__global__ __launch_bounds__(256) void k_jsweep_blk(int64_t n, const int32_t *__restrict__ rowptr,
-                                                    const int32_t *__restrict__ col, const TV *__restrict__ val,
-                                                    const double *__restrict__ Dinv, double omega,
-                                                    const double *__restrict__ v, const double *__restrict__ z,
-                                                    double *__restrict__ zo, const int32_t *active)
+// ------------------------------------------- compact B-system blocks ----
+
+// A block of a B (left Cauchy-Green) band system is s1 I - LE(M): the
+// scalar s1 and the D x D matrix M (1 + D*D numbers, the assembly's
+// accumulators) define all NV x NV entries, and (LE(M) x)_c = (M X + X M^T)_ij
+// for the Voigt pair (i, j) of c, X the symmetric tensor of x (Voigt order
+// 11, 22, 33, 12, 23, 13 / 11, 22, 12).  The products read this compact form
+// (80 instead of 288 bytes per 6x6 block) and expand it on the fly, in FP64.
+template <int D> struct BCmp {
+    static constexpr int NV = D == 3 ? 6 : 3, NC = 1 + D * D;
+};
+
+template <int D>
+__device__ __forceinline__ void bcmp_block_apply(const double (&cm)[BCmp<D>::NC], const double (&xv)[BCmp<D>::NV],
+                                                 double (&acc)[BCmp<D>::NV])
 {
-    constexpr int SEG = BlockSeg<BS>::SEG, RPW = BlockSeg<BS>::RPW;
+    constexpr int NV = BCmp<D>::NV;
+    double X[D][D];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        int i, j;
+        vpair<D>(c, i, j);
+        X[i][j] = xv[c];
+        X[j][i] = xv[c];
+    }
+    double MX[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) t += cm[1 + i * D + k] * X[k][j];
+            MX[i][j] = t;
+        }
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        int i, j;
+        vpair<D>(c, i, j);
+        acc[c] += cm[0] * xv[c] - (MX[i][j] + MX[j][i]);
+    }
+}
+
+// (A z) of the segment's block row, one compact block per lane, reduced
+// over the segment (every lane of it holds the row's sums)
+template <int D, int SEG>
+__device__ __forceinline__ void bcmp_row_dot(int k0, int k1, const int32_t *__restrict__ col,
+                                             const double *__restrict__ cmp, const double *__restrict__ z, int j,
+                                             double (&acc)[BCmp<D>::NV])
+{
+    constexpr int NV = BCmp<D>::NV, NC = BCmp<D>::NC;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) acc[c] = 0.0;
+    for (int k = k0 + j; k < k1; k += SEG) {
+        double cm[NC], xv[NV];
+        RowLoad<NC, double, false>::get(cmp + (int64_t)k * NC, cm);
+        x_get<NV>(z, col[k], xv);
+        bcmp_block_apply<D>(cm, xv, acc);
+    }
+#pragma unroll
+    for (int s = SEG / 2; s > 0; s >>= 1)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) acc[c] += __shfl_xor(acc[c], s, 64);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_spmv_bcmp(int64_t n, const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ col, const double *__restrict__ cmp,
+                                                   const double *__restrict__ x, double *__restrict__ y,
+                                                   const int32_t *active)
+{
+    constexpr int NV = BCmp<D>::NV, SEG = BlockSeg<NV>::SEG, RPW = BlockSeg<NV>::RPW;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave_id()) * RPW;
+    if ((active && *active == 0) || row0 >= n) return;
+    const int lane = threadIdx.x & 63, q = lane / SEG, j = lane - q * SEG;
+    int k0, k1;
+    seg_extents<RPW>(row0, n, rowptr, q, k0, k1);
+    double acc[NV];
+    bcmp_row_dot<D, SEG>(k0, k1, col, cmp, x, j, acc);
+    const int64_t row = row0 + q;
+#pragma unroll
+    for (int c = 0; c < NV; ++c)
+        if (j == c && row < n) y[row * NV + c] = acc[c];
+}
+
+// damped block-Jacobi sweep zo = z + omega D^-1 (v - A z), lane j < NV of a
+// row's segment finishes component j
+template <int D>
+__global__ __launch_bounds__(256) void k_jsweep_bcmp(int64_t n, const int32_t *__restrict__ rowptr,
+                                                     const int32_t *__restrict__ col, const double *__restrict__ cmp,
+                                                     const double *__restrict__ Dinv, double omega,
+                                                     const double *__restrict__ v, const double *__restrict__ z,
+                                                     double *__restrict__ zo, const int32_t *active)
+{
+    constexpr int NV = BCmp<D>::NV, SEG = BlockSeg<NV>::SEG, RPW = BlockSeg<NV>::RPW;
     const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave_id()) * RPW;
     if (*active == 0 || row0 >= n) return;
     const int lane = threadIdx.x & 63, q = lane / SEG, j = lane - q * SEG;
     const int64_t row = row0 + q, rr = row < n ? row : row0;   // rr: in bounds, unused past n
-    const int jj = j < BS ? j : 0;
-    double vv[BS], d[BS];
-    x_get<BS>(v, rr, vv);
-    RowLoad<BS, double, false>::get(Dinv + (rr * BS + jj) * BS, d);
-    const double zr = z[rr * BS + jj];
+    const int jj = j < NV ? j : 0;
+    double vv[NV], d[NV];
+    x_get<NV>(v, rr, vv);
+    RowLoad<NV, double, false>::get(Dinv + (rr * NV + jj) * NV, d);
+    const double zr = z[rr * NV + jj];
     int k0, k1;
     seg_extents<RPW>(row0, n, rowptr, q, k0, k1);
-    double az[BS];
-    bsr_block_dot<BS, TV, SEG>(k0, k1, col, val, z, j, az);
+    double az[NV];
+    bcmp_row_dot<D, SEG>(k0, k1, col, cmp, z, j, az);
     double u = 0.0;
 #pragma unroll
-    for (int c = 0; c < BS; ++c) u += d[c] * (vv[c] - az[c]);
-    if (j < BS && row < n) zo[row * BS + j] = zr + omega * u;
+    for (int c = 0; c < NV; ++c) u += d[c] * (vv[c] - az[c]);
+    if (j < NV && row < n) zo[row * NV + j] = zr + omega * u;
 }
 
 template <typename TD> static eft_status bj_setup(eft_ctx *ctx, const eft_matrix *A, TD *Dinv)
@@ -455,24 +541,55 @@ eft_status eft_jacobi_apply(eft_ctx *ctx, const eft_matrix *A, const double *Din
                        active);
     for (int s = 1; s < sweeps; ++s) {
         double *nxt = buf[(sweeps - 1 - s) & 1];
-        if (bs == 1)
+        if (A->bcmp)
+            EFT_TRY(eft_bcmp_sweep(ctx, A, Dinv, omega, v, cur, nxt, active));
+        else if (bs == 1)
             hipLaunchKernelGGL(k_jsweep1, dim3(eft_grid(n, 16)), dim3(256), 0, ctx->stream, n, A->rowptr, A->col,
                                A->val, Dinv, omega, v, cur, nxt, active);
-        else if (bs == 3 && A->pc16)
-            hipLaunchKernelGGL((k_jsweep_rows<3, eft_bf16>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream,
-                               n, A->rowptr, A->col, reinterpret_cast<const eft_bf16 *>(A->pc16), Dinv, omega, v,
-                               cur, nxt, active);
         else if (bs == 3)
             hipLaunchKernelGGL((k_jsweep_rows<3, double>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream,
                                n, A->rowptr, A->col, A->val, Dinv, omega, v, cur, nxt, active);
-        else if (A->pc16)
-            hipLaunchKernelGGL((k_jsweep_blk<6, eft_bf16>), dim3(eft_grid(n, 4 * BlockSeg<6>::RPW)), dim3(256), 0,
-                               ctx->stream, n, A->rowptr, A->col, reinterpret_cast<const eft_bf16 *>(A->pc16), Dinv,
-                               omega, v, cur, nxt, active);
         else
             hipLaunchKernelGGL((k_jsweep_rows<6, double>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream,
                                n, A->rowptr, A->col, A->val, Dinv, omega, v, cur, nxt, active);
         cur = nxt;
+    }
+    EFT_HIP(hipGetLastError());
+    return EFT_OK;
+}
+
+eft_status eft_bcmp_spmv(eft_ctx *ctx, const eft_matrix *A, const double *x, double *y, const int32_t *active)
+{
+    const int64_t n = A->n;
+    if (n == 0) return EFT_OK;
+    if (A->bs == 6)
+        hipLaunchKernelGGL(k_spmv_bcmp<3>, dim3(eft_grid(n, 4 * BlockSeg<6>::RPW)), dim3(256), 0, ctx->stream, n,
+                           A->rowptr, A->col, A->bcmp, x, y, active);
+    else if (A->bs == 3)
+        hipLaunchKernelGGL(k_spmv_bcmp<2>, dim3(eft_grid(n, 4 * BlockSeg<3>::RPW)), dim3(256), 0, ctx->stream, n,
+                           A->rowptr, A->col, A->bcmp, x, y, active);
+    else {
+        ctx->err = "compact B blocks need bs 3 or 6";
+        return EFT_EINVAL;
+    }
+    EFT_HIP(hipGetLastError());
+    return EFT_OK;
+}
+
+eft_status eft_bcmp_sweep(eft_ctx *ctx, const eft_matrix *A, const double *Dinv, double omega, const double *v,
+                          const double *z, double *zo, const int32_t *active)
+{
+    const int64_t n = A->n;
+    if (n == 0) return EFT_OK;
+    if (A->bs == 6)
+        hipLaunchKernelGGL(k_jsweep_bcmp<3>, dim3(eft_grid(n, 4 * BlockSeg<6>::RPW)), dim3(256), 0, ctx->stream, n,
+                           A->rowptr, A->col, A->bcmp, Dinv, omega, v, z, zo, active);
+    else if (A->bs == 3)
+        hipLaunchKernelGGL(k_jsweep_bcmp<2>, dim3(eft_grid(n, 4 * BlockSeg<3>::RPW)), dim3(256), 0, ctx->stream, n,
+                           A->rowptr, A->col, A->bcmp, Dinv, omega, v, z, zo, active);
+    else {
+        ctx->err = "compact B blocks need bs 3 or 6";
+        return EFT_EINVAL;
     }
     EFT_HIP(hipGetLastError());
     return EFT_OK;

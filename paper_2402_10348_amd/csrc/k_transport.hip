@@ -367,7 +367,7 @@ struct TrArgs {
     const double *lx, *ldx, *ix;            // level value, level rate, iterate of the field
     double alpha, alpha_m, vs, dt, ct;
     double *R, *J;
-    uint16_t *J16;   // optional BF16 copy of J (B systems)
+    double *Jc;      // optional compact blocks (s1, M) of J (B systems)
 };
 
 template <int BS>
@@ -446,13 +446,13 @@ __device__ __forceinline__ void band_rows_out_b(const TrArgs &a, int64_t r0, int
             if (threadIdx.x < NVv) a.R[r * NVv + threadIdx.x] = 0.0;
             for (int t = threadIdx.x; t < len; t += blockDim.x) {
                 double *dst = a.J + (kb + t) * B2;
-                uint16_t *dst16 = a.J16 ? a.J16 + (kb + t) * B2 : nullptr;
                 const bool dg = a.bcol[kb + t] == r;
 #pragma unroll
-                for (int v = 0; v < B2; ++v) {
-                    const bool one = dg && v % (NVv + 1) == 0;
-                    dst[v] = one ? 1.0 : 0.0;
-                    if (dst16) dst16[v] = one ? 0x3F80u : 0u;   // (BF16 1 and 0)
+                for (int v = 0; v < B2; ++v) dst[v] = (dg && v % (NVv + 1) == 0) ? 1.0 : 0.0;
+                if (a.Jc) {   // compact unit block: s1 = 1, M = 0
+                    double *dc = a.Jc + (kb + t) * BAcc<D>::N;
+#pragma unroll
+                    for (int v = 0; v < BAcc<D>::N; ++v) dc[v] = (dg && v == 0) ? 1.0 : 0.0;
                 }
             }
             continue;
@@ -471,15 +471,15 @@ __device__ __forceinline__ void band_rows_out_b(const TrArgs &a, int64_t r0, int
             }
             const double *src = accJ + ((int64_t)lr * a.maxc + lo) * BP;
             double *dst = a.J + (kb + t) * B2;
-            uint16_t *dst16 = a.J16 ? a.J16 + (kb + t) * B2 : nullptr;
 #pragma unroll
             for (int c = 0; c < NVv; ++c)
 #pragma unroll
-                for (int cc = 0; cc < NVv; ++cc) {
-                    const double v = b_block_entry<D>(src, c, cc);
-                    dst[c * NVv + cc] = v;
-                    if (dst16) dst16[c * NVv + cc] = to_bf16_rne((float)v);
-                }
+                for (int cc = 0; cc < NVv; ++cc) dst[c * NVv + cc] = b_block_entry<D>(src, c, cc);
+            if (a.Jc) {   // the accumulators themselves: s1, then M
+                double *dc = a.Jc + (kb + t) * BAcc<D>::N;
+#pragma unroll
+                for (int v = 0; v < BAcc<D>::N; ++v) dc[v] = src[v];
+            }
         }
     }
 }
@@ -921,12 +921,12 @@ eft_status eft_reserve_band_sys(eft_ctx *ctx, int64_t n, int64_t nnz)
     }
     if (nnz > ctx->bcap_nnz) {
         if (ctx->bval) (void)hipFree(ctx->bval);
-        if (ctx->bval16) (void)hipFree(ctx->bval16);
+        if (ctx->bcmp) (void)hipFree(ctx->bcmp);
         ctx->bval = nullptr;
-        ctx->bval16 = nullptr;
+        ctx->bcmp = nullptr;
         const int64_t c = 2 * nnz + 64;
         if (hipMalloc(&ctx->bval, sizeof(double) * c * nv * nv) != hipSuccess ||
-            hipMalloc(&ctx->bval16, sizeof(uint16_t) * c * nv * nv) != hipSuccess) {
+            hipMalloc(&ctx->bcmp, sizeof(double) * c * (1 + ctx->dim * ctx->dim)) != hipSuccess) {
             ctx->err = "out of device memory (band matrix)";
             return EFT_ENOMEM;
         }
@@ -1137,7 +1137,7 @@ static TrArgs tr_args(eft_ctx *ctx, const Band &B, const double *lx, const doubl
 {
     GA ga = ga_of(ctx->par.rho_inf, ctx->par.dt);
     TrArgs a;
-    a.J16 = nullptr;
+    a.Jc = nullptr;
     a.fre = B.fre;
     a.n = B.n;
     a.rpb = std::min(ctx->rpb, 64);
@@ -1193,7 +1193,7 @@ static eft_status assemble_ac(eft_ctx *ctx, const eft_state *lvl, const eft_iter
 // B system of solid s on the band of its indicator into R, J; the solid
 // fractions in ctx->as must come from the current order parameters
 static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, int s, double *R, double *J,
-                             uint16_t *J16)
+                             double *Jc)
 {
     const int64_t N = ctx->N;
     const int nv = ctx->nv;
@@ -1201,7 +1201,7 @@ static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_itera
     TrArgs a = tr_args(ctx, B, lvl->B + (int64_t)s * N * nv, lvl->Bdot + (int64_t)s * N * nv, it->B + (int64_t)s * N * nv);
     a.R = R;
     a.J = J;
-    a.J16 = J16;
+    a.Jc = Jc;
     if (B.n > 0) {
         const int bp = ctx->dim == 2 ? BAcc<2>::P : BAcc<3>::P;
         const size_t shm = (size_t)a.rpb * ((size_t)a.maxc * bp + (nv | 1)) * sizeof(double);
@@ -1250,7 +1250,7 @@ static eft_status union_solve(eft_ctx *ctx, const eft_ctx::BandUnion &U, int bs,
     A.col = U.col;
     A.diag = U.diag;
     A.val = ctx->bval;
-    A.pc16 = bs > 1 ? ctx->bval16 : nullptr;   // (the B systems' assembly writes the copy)
+    A.bcmp = bs > 1 ? ctx->bcmp : nullptr;   // (the B systems' assembly writes the compact blocks)
     const double rtol = ctx->par.lin_rtol / std::sqrt((double)std::max(members, 1));
     eft_status st = eft_fgmres_dev(ctx, &A, ctx->bR, ctx->bX, si, rtol);
     if (st != EFT_OK && st != EFT_ENOTCONV) return st;
@@ -1321,7 +1321,7 @@ eft_status eft_transport_dev(eft_ctx *ctx, const eft_state *lvl, eft_iterate *it
         for (int sI = 0; sI < S; ++sI)
             if (ctx->band[ctx->solid_ind[sI]].n > 0)
                 EFT_TRY(assemble_b(ctx, lvl, it, sI, ctx->bR + U.roff[sI] * nv, ctx->bval + U.noff[sI] * nv * nv,
-                                   ctx->bval16 + U.noff[sI] * nv * nv));
+                                   ctx->bcmp + U.noff[sI] * (1 + ctx->dim * ctx->dim)));
         std::vector<double *> x(S);
         std::vector<int64_t> xl(S, N * nv);
         for (int sI = 0; sI < S; ++sI) x[sI] = it->B + (int64_t)sI * N * nv;
@@ -1364,7 +1364,7 @@ eft_status eft_band_system_dev(eft_ctx *ctx, const eft_state *lvl, const eft_ite
         gb[1] = all[2 * index + 1];
         EFT_TRY(assemble_ac(ctx, lvl, it, index, ctx->bR, ctx->bval, ctx->tsc + TS_GB + 2 * index));
     } else {
-        EFT_TRY(assemble_b(ctx, lvl, it, index, ctx->bR, ctx->bval, ctx->bval16));
+        EFT_TRY(assemble_b(ctx, lvl, it, index, ctx->bR, ctx->bval, ctx->bcmp));
     }
     if (gamma_beta) {
         gamma_beta[0] = gb[0];
