@@ -368,6 +368,7 @@ struct TrArgs {
     double alpha, alpha_m, vs, dt, ct;
     double *R, *J;
     double *Jc;      // optional compact blocks (s1, M) of J (B systems)
+    int full_b;      // B systems with Jc: 1 writes every block of J in full, 0 only the diagonal ones
 };
 
 template <int BS>
@@ -447,8 +448,9 @@ __device__ __forceinline__ void band_rows_out_b(const TrArgs &a, int64_t r0, int
             for (int t = threadIdx.x; t < len; t += blockDim.x) {
                 double *dst = a.J + (kb + t) * B2;
                 const bool dg = a.bcol[kb + t] == r;
+                if (dg || a.full_b || !a.Jc)
 #pragma unroll
-                for (int v = 0; v < B2; ++v) dst[v] = (dg && v % (NVv + 1) == 0) ? 1.0 : 0.0;
+                    for (int v = 0; v < B2; ++v) dst[v] = (dg && v % (NVv + 1) == 0) ? 1.0 : 0.0;
                 if (a.Jc) {   // compact unit block: s1 = 1, M = 0
                     double *dc = a.Jc + (kb + t) * BAcc<D>::N;
 #pragma unroll
@@ -471,10 +473,11 @@ __device__ __forceinline__ void band_rows_out_b(const TrArgs &a, int64_t r0, int
             }
             const double *src = accJ + ((int64_t)lr * a.maxc + lo) * BP;
             double *dst = a.J + (kb + t) * B2;
+            if (a.full_b || !a.Jc || a.bcol[kb + t] == r)   // (the diagonal blocks feed the block inverses)
 #pragma unroll
-            for (int c = 0; c < NVv; ++c)
+                for (int c = 0; c < NVv; ++c)
 #pragma unroll
-                for (int cc = 0; cc < NVv; ++cc) dst[c * NVv + cc] = b_block_entry<D>(src, c, cc);
+                    for (int cc = 0; cc < NVv; ++cc) dst[c * NVv + cc] = b_block_entry<D>(src, c, cc);
             if (a.Jc) {   // the accumulators themselves: s1, then M
                 double *dc = a.Jc + (kb + t) * BAcc<D>::N;
 #pragma unroll
@@ -1138,6 +1141,7 @@ static TrArgs tr_args(eft_ctx *ctx, const Band &B, const double *lx, const doubl
     GA ga = ga_of(ctx->par.rho_inf, ctx->par.dt);
     TrArgs a;
     a.Jc = nullptr;
+    a.full_b = 1;
     a.fre = B.fre;
     a.n = B.n;
     a.rpb = std::min(ctx->rpb, 64);
@@ -1192,8 +1196,10 @@ static eft_status assemble_ac(eft_ctx *ctx, const eft_state *lvl, const eft_iter
 
 // B system of solid s on the band of its indicator into R, J; the solid
 // fractions in ctx->as must come from the current order parameters
+// (Jc: the compact blocks; full: every block of J also in full, else only
+// the diagonal blocks)
 static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, int s, double *R, double *J,
-                             double *Jc)
+                             double *Jc, bool full)
 {
     const int64_t N = ctx->N;
     const int nv = ctx->nv;
@@ -1202,6 +1208,7 @@ static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_itera
     a.R = R;
     a.J = J;
     a.Jc = Jc;
+    a.full_b = full ? 1 : 0;
     if (B.n > 0) {
         const int bp = ctx->dim == 2 ? BAcc<2>::P : BAcc<3>::P;
         const size_t shm = (size_t)a.rpb * ((size_t)a.maxc * bp + (nv | 1)) * sizeof(double);
@@ -1321,7 +1328,7 @@ eft_status eft_transport_dev(eft_ctx *ctx, const eft_state *lvl, eft_iterate *it
         for (int sI = 0; sI < S; ++sI)
             if (ctx->band[ctx->solid_ind[sI]].n > 0)
                 EFT_TRY(assemble_b(ctx, lvl, it, sI, ctx->bR + U.roff[sI] * nv, ctx->bval + U.noff[sI] * nv * nv,
-                                   ctx->bcmp + U.noff[sI] * (1 + ctx->dim * ctx->dim)));
+                                   ctx->bcmp + U.noff[sI] * (1 + ctx->dim * ctx->dim), false));
         std::vector<double *> x(S);
         std::vector<int64_t> xl(S, N * nv);
         for (int sI = 0; sI < S; ++sI) x[sI] = it->B + (int64_t)sI * N * nv;
@@ -1364,7 +1371,7 @@ eft_status eft_band_system_dev(eft_ctx *ctx, const eft_state *lvl, const eft_ite
         gb[1] = all[2 * index + 1];
         EFT_TRY(assemble_ac(ctx, lvl, it, index, ctx->bR, ctx->bval, ctx->tsc + TS_GB + 2 * index));
     } else {
-        EFT_TRY(assemble_b(ctx, lvl, it, index, ctx->bR, ctx->bval, ctx->bcmp));
+        EFT_TRY(assemble_b(ctx, lvl, it, index, ctx->bR, ctx->bval, ctx->bcmp, true));
     }
     if (gamma_beta) {
         gamma_beta[0] = gb[0];
