@@ -6,7 +6,12 @@
 // convergence, so the host enqueues iterations in chunks and reads the status
 // once per chunk; the Hessenberg column, Givens rotations and the triangular
 // solve run in single-workgroup kernels (the column's bookkeeping is fused
-// with the last reduction of its pass).  Dot products reduce
+// with the last reduction of its pass).  With at most 32 basis vectors the
+// first pass's update also yields the second pass's dots, the first pass's
+// closing kernel completes the column (with the second pass, ||w''||^2 is
+// ||w'||^2 - ||h2||^2: the basis is orthonormal to working precision and the
+// second pass removes little), and the second pass's update runs fused with
+// the normalization of v_{j+1}.  Dot products reduce
 // deterministically: each block writes a partial, a second kernel sums the
 // partials in a fixed order.
 #include "dev_common.h"
@@ -253,14 +258,36 @@ __global__ __launch_bounds__(RB) void k_close_pass(const double *__restrict__ pa
     }
     double s = part_share(part, nblk);
     s = block_sum<RB>(s, lds);   // (its barriers also publish col, csl, snl, red)
-    if ((int)threadIdx.x < ndots) {
-        double v = 0.0;
+    __shared__ double hh2[32];
+    if (ndots > 0) {
+        if ((int)threadIdx.x < ndots) {
+            double v = 0.0;
 #pragma unroll
-        for (int q = 0; q < RB / 64; ++q) v += red[q][threadIdx.x];
-        small[L.h2() + threadIdx.x] = v;
+            for (int q = 0; q < RB / 64; ++q) v += red[q][threadIdx.x];
+            small[L.h2() + threadIdx.x] = v;
+            hh2[threadIdx.x] = v;
+        }
+        __syncthreads();
     }
     if (threadIdx.x != 0) return;
-    if (pass == 1) {
+    if (pass == 1 && ndots > 0) {
+        // the second pass's dots are known, so this pass completes the
+        // column either way: with the second pass, the column gains its
+        // dots and ||w''||^2 = ||w'||^2 - ||h2||^2 (the basis is orthonormal
+        // and the second pass removes little), and the second pass's update
+        // runs fused with the normalization
+        small[L.sc() + 0] = s;
+        flag[3] = (s < 0.5 * h[j + 1]) ? 1 : 0;
+        if (flag[3]) {
+            double q = 0.0;
+            for (int i = 0; i <= j; ++i) {
+                col[i] += hh2[i];
+                q += hh2[i] * hh2[i];
+            }
+            s = fmax(s - q, 0.0);
+            small[L.sc() + 1] = s;
+        }
+    } else if (pass == 1) {
         small[L.sc() + 0] = s;
         flag[3] = (s < 0.5 * h[j + 1]) ? 1 : 0;
         if (flag[3]) {   // pass 2 completes the column: store the dots
@@ -272,6 +299,26 @@ __global__ __launch_bounds__(RB) void k_close_pass(const double *__restrict__ pa
     }
     col[j + 1] = sqrt(s);
     givens_column(small, m, j, col, csl, snl, flag);
+}
+
+// v_{j+1} = (w - sum_k h2[k] V[k]) / H[j+1][j], the update only when the
+// second pass was taken (nvec <= 32)
+__global__ __launch_bounds__(RB) void k_update_normalize(const double *__restrict__ V, int64_t nd, int nvec,
+                                                         const double *__restrict__ w, double *__restrict__ v,
+                                                         const double *small, int m, const int32_t *flag)
+{
+    __shared__ double cl[32];
+    if (flag[0] == 0) return;
+    Small L{m};
+    const double inv = 1.0 / small[L.sc() + 4];
+    const int nv = flag[3] ? nvec : 0;
+    for (int k = threadIdx.x; k < nv; k += RB) cl[k] = -small[L.h2() + k];
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < nd; i += (int64_t)gridDim.x * RB) {
+        double s = w[i];
+        for (int k = 0; k < nv; ++k) s += cl[k] * V[(int64_t)k * nd + i];
+        v[i] = s * inv;
+    }
 }
 
 // v_{j+1} = w / H[j+1][j]
@@ -533,6 +580,9 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
                                            small + L.h(), K.w, K.part, nblk, K.flag);
                     hipLaunchKernelGGL(k_close_pass, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, nv1, small, m,
                                        j, 1, K.flag);
+                    // the second pass's update (when taken) with the normalization
+                    hipLaunchKernelGGL(k_update_normalize, dim3(sg), dim3(RB), 0, ctx->stream, K.V, nd, nv1, K.w,
+                                       K.V + (int64_t)(j + 1) * nd, small, m, K.flag);
                 } else {
                     hipLaunchKernelGGL(k_maxpy, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, j + 1, small + L.h(),
                                        -1.0, K.w, K.part, nblk, K.flag, 0);
@@ -544,14 +594,14 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
                                        K.flag, 1);
                     hipLaunchKernelGGL(k_sum_parts, dim3(j + 1), dim3(RB), 0, ctx->stream, K.part, nblk,
                                        small + L.h2(), K.flag, 1);
+                    // pass 2 (gated)
+                    hipLaunchKernelGGL(k_maxpy, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, j + 1, small + L.h2(),
+                                       -1.0, K.w, K.part, nblk, K.flag, 1);
+                    hipLaunchKernelGGL(k_close_pass, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, 0, small, m, j,
+                                       2, K.flag);
+                    hipLaunchKernelGGL(k_normalize, dim3(sg), dim3(RB), 0, ctx->stream, K.w,
+                                       K.V + (int64_t)(j + 1) * nd, nd, small, m, j, K.flag);
                 }
-                // pass 2 (gated)
-                hipLaunchKernelGGL(k_maxpy, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, j + 1, small + L.h2(),
-                                   -1.0, K.w, K.part, nblk, K.flag, 1);
-                hipLaunchKernelGGL(k_close_pass, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, 0, small, m, j, 2,
-                                   K.flag);
-                hipLaunchKernelGGL(k_normalize, dim3(sg), dim3(RB), 0, ctx->stream, K.w, K.V + (int64_t)(j + 1) * nd,
-                                   nd, small, m, j, K.flag);
             }
             EFT_HIP(hipGetLastError());
             ctx->kt.tag = -1;
