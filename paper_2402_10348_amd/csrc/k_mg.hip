@@ -530,17 +530,18 @@ inline size_t gj_lds_bytes(int nd) { return sizeof(double) * ((size_t)2 * nd * n
 
 __global__ __launch_bounds__(256) void k_gauss_jordan_lds(const double *__restrict__ M, double *__restrict__ Inv, int nd)
 {
-    // thread j owns column j of [M | I] (2 nd <= 256 columns): the swap, the
-    // scaling and the elimination of a pivot step touch only the thread's own
-    // column, so a step needs two barriers (after the pivot search and the
-    // broadcast of the pivot column, and after the update)
+    // thread j owns column j of [M | I] (2 nd <= blockDim.x columns; one
+    // wavefront when 2 nd <= 64): the swap, the scaling and the elimination
+    // of a pivot step touch only the thread's own column, so a step needs
+    // two barriers (after the pivot search and the broadcast of the pivot
+    // column, and after the update)
     extern __shared__ double sm[];
     double *A = sm;                  // [nd][2 nd]
     double *colk = sm + 2 * nd * nd; // [nd] pivot column after the swap, 0 at row k
     __shared__ int piv;
     __shared__ double pinv;
     const int t = threadIdx.x, W = 2 * nd;
-    for (int e = t; e < nd * W; e += 256) {
+    for (int e = t; e < nd * W; e += (int)blockDim.x) {
         const int i = e / W, j = e - i * W;
         A[e] = j < nd ? M[i * nd + j] : (j - nd == i ? 1.0 : 0.0);
     }
@@ -584,7 +585,7 @@ __global__ __launch_bounds__(256) void k_gauss_jordan_lds(const double *__restri
         }
         __syncthreads();
     }
-    for (int e = t; e < nd * nd; e += 256) {
+    for (int e = t; e < nd * nd; e += (int)blockDim.x) {
         const int i = e / nd, j = e - i * nd;
         Inv[e] = A[i * W + nd + j];
     }
@@ -1071,9 +1072,9 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
                            Cc.A.nnzb, bs, Cc.A.rowptr, Cc.A.col, Cc.A.val, ctx->mg_fidx, ctx->mg_dense, ctx->mg_nd,
                            Cc.N);
         const int nd = (int)ctx->mg_nd;
-        if (nd <= GJ_LDS_MAX)
-            hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(1), dim3(256), gj_lds_bytes(nd), ctx->stream, ctx->mg_dense,
-                               ctx->mg_inv, nd);
+        if (nd <= GJ_LDS_MAX)   // (one wavefront when the 2 nd columns fit in it)
+            hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(1), dim3(2 * nd <= 64 ? 64 : 256), gj_lds_bytes(nd),
+                               ctx->stream, ctx->mg_dense, ctx->mg_inv, nd);
         else
             hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(256), 0, ctx->stream, ctx->mg_dense, ctx->mg_inv, nd);
         EFT_HIP(hipGetLastError());
