@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--band-sweeps", type=int, default=None,
                     help="damped block-Jacobi sweeps preconditioning the Allen-Cahn and B systems")
     ap.add_argument("--band-omega", type=float, default=None)
-    ap.add_argument("--mg-omega", type=float, default=0.7)
+    ap.add_argument("--mg-omega", type=float, default=0.75)
     ap.add_argument("--mg-bf16", type=int, default=1, help="1: finest multigrid level's matrix copy in BF16, 0: FP32")
     ap.add_argument("--kernel-role", type=int, default=1,
                     help="kernel of the roofline object: 1 fine-level smoother sweep, 2 momentum SpMV in FGMRES, "

@@ -162,7 +162,7 @@ class Params:
     band_cell: int = 4
     band_halo: int = 1
     mg_nu: int = 1            # pre-smoothing sweeps (the first from zero)
-    mg_omega: float = 0.7
+    mg_omega: float = 0.75
     mg_bf16: int = 1          # finest multigrid level's matrix copy in BF16 (0: FP32)
     mg_nu_post: int = 3
     mg_smoother: int = 0      # 0 damped block Jacobi, 1 multicolour block Gauss-Seidel
