@@ -406,8 +406,8 @@ def cpu_baseline(prob, counts, args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the box has one MI355X)",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU sharding is a "
+              "design, not an implementation)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
