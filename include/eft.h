@@ -42,7 +42,9 @@ typedef enum {
     EFT_EDEVICE = 3,         /* a HIP call failed                                  */
     EFT_ENOTCONV = 4,        /* Krylov solve hit its iteration cap (best iterate
                                 returned, info filled)                             */
-    EFT_EBREAKDOWN = 5,      /* Krylov breakdown on a singular system              */
+    EFT_EBREAKDOWN = 5,      /* singular system: the point-block Jacobi
+                                preconditioner met a singular diagonal block, or
+                                FGMRES could make no progress                      */
     EFT_ENAN = 6,            /* NaN/Inf met; fields keep the last good iterate     */
     EFT_EBAND_OVERFLOW = 7,  /* max|v| dt exceeds the band halo width              */
     EFT_EUNSUPPORTED = 8     /* valid request the library does not implement       */
@@ -122,6 +124,20 @@ typedef struct {
                                     sweeps from z = 0 (1..8; 1 with band_omega = 1
                                     is plain point-block Jacobi)                    */
     double band_omega;           /* damping of those sweeps (0 < omega <= 1.5)      */
+    int32_t nn_maxit;            /* learned preconditioner: Krylov iterations of
+                                    one momentum solve after which the rest of the
+                                    solve uses block Jacobi, its fallback
+                                    (<= 0: lin_maxit / 2)                          */
+    double band_reserve;         /* band storage reserved at eft_create and
+                                    eft_set_params: the bands of all indicators
+                                    together may hold this many times the mesh's
+                                    elements (with band_flat < 0 at least the
+                                    indicator count); <= 0 picks 1, but never less
+                                    than 2^20 elements or every band the whole
+                                    mesh, the smaller of the two.  A step whose
+                                    bands need
+                                    more returns EFT_ENOMEM with the state
+                                    unchanged; eft_step itself never allocates.   */
 } eft_params;
 
 /* State at time level n (Sec. 2.1.2): values and rates.  DEVICE arrays. */
@@ -147,8 +163,13 @@ typedef struct {
     int32_t iters;               /* Krylov iterations                              */
     int32_t restarts;            /* completed restart cycles                       */
     int32_t converged;           /* 1 if ||b - A x|| <= lin_rtol ||b||             */
-    int32_t fallback_used;       /* 1: multigrid requested but unavailable (point-
-                                    block Jacobi used)                             */
+    int32_t fallback_used;       /* 1: the requested preconditioner gave way to
+                                    point-block Jacobi: multigrid unavailable (mesh
+                                    not a structured Kuhn box, or the matrix not
+                                    assembled by eft_assemble/eft_step), or the
+                                    learned one produced a non-finite value (those
+                                    nodes) or passed nn_maxit iterations (the rest
+                                    of the solve)                                 */
     double rel_res0;             /* ||b - A x0|| / ||b|| (x0 = 0: 1)               */
     double rel_res;              /* final true relative residual                   */
 } eft_solve_info;
@@ -205,6 +226,14 @@ eft_status eft_matrix_shape(const eft_matrix *A, int64_t *n_rows, int64_t *nnzb,
  * buffers: rowptr [n_rows+1], col [nnzb], val [nnzb][bs][bs] row-major. */
 eft_status eft_matrix_export(eft_ctx *ctx, const eft_matrix *A, int32_t *rowptr, int32_t *col, double *val);
 
+/* Overwrite the values of a context matrix with caller values val
+ * [nnzb][bs][bs] (FP64, DEVICE, row-major blocks in the pattern of
+ * eft_matrix_export; narrowed when the matrix holds FP32 values).  The
+ * matrix is then no longer the assembled Jacobian: until the next assembly
+ * its solves use point-block Jacobi (the multigrid hierarchy is built by the
+ * assembly).  For solving other systems of the same pattern, and tests. */
+eft_status eft_matrix_import(eft_ctx *ctx, eft_matrix *A, const double *val);
+
 /* (a) Momentum/mass residual R [N][d+1] (FP64) and Jacobian J of eq. (PG_NS)
  * at the iterate, with the elastic tangent of eq. (Bext), Dirichlet rows
  * replaced by unit rows and zero residual.  J may be NULL (residual only). */
@@ -214,9 +243,13 @@ eft_status eft_assemble(eft_ctx *ctx, const eft_state *level_n, const eft_iterat
 /* (b) y = A x for a context matrix; x, y [n_rows][bs]. */
 eft_status eft_spmv(eft_ctx *ctx, const eft_matrix *A, const double *x, double *y);
 
-/* (b) Solve A x = b with right-preconditioned FGMRES(restart), x0 = 0,
- * point-block Jacobi; classical Gram-Schmidt with reorthogonalization in FP64.
- * x is output only.  EFT_ENOTCONV if lin_maxit is reached (x = best iterate). */
+/* (b) Solve A x = b with right-preconditioned FGMRES(restart), x0 = 0, the
+ * preconditioner chosen by par.precond (point-block Jacobi, the multigrid
+ * V-cycle, or the learned one with its block-Jacobi fallback); classical
+ * Gram-Schmidt with a conditional second pass, all in FP64.  x is output
+ * only.  EFT_ENOTCONV if lin_maxit is reached (x = best iterate);
+ * EFT_EBREAKDOWN on a singular diagonal block (point-block Jacobi); EFT_ENAN
+ * on a non-finite right-hand side or iterate. */
 eft_status eft_fgmres(eft_ctx *ctx, const eft_matrix *A, const double *b, double *x, eft_solve_info *info);
 
 /* (c) Build the transport band of every indicator from phi^n (grid cells of
@@ -307,7 +340,8 @@ eft_status eft_step(eft_ctx *ctx, eft_state *st, double dt, eft_step_info *info)
 /* Measurement hook, not part of the method: time every launch of the kernel
  * roles set in role_mask with a pair of HIP events on the context's stream.
  * Bit 1 = fine-level multigrid smoother sweep (x + omega D^-1 (b - A x) with
- * the FP32 copy of the momentum Jacobian), bit 2 = SpMV of the momentum
+ * the finest level's copy of the momentum Jacobian: BF16 with mg_bf16 = 1,
+ * the default, FP32 otherwise), bit 2 = SpMV of the momentum
  * Jacobian inside FGMRES, bit 3 = momentum/mass assembly on the mesh (not the
  * coarse levels).  0 turns timing off.  Resets the counters; two event records
  * per timed launch are added to the stream.  EFT_EINVAL for other bits. */

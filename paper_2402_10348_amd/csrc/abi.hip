@@ -95,11 +95,9 @@ void free_all(eft_ctx *ctx)
     fr(ctx->J.rowptr); fr(ctx->J.col); fr(ctx->J.diag); fr(ctx->J.val); fr(ctx->J.val32);
     fr(ctx->va); fr(ctx->acc); fr(ctx->rho); fr(ctx->mu); fr(ctx->as); fr(ctx->Ba); fr(ctx->R); fr(ctx->dx);
     fr(ctx->l_vp); fr(ctx->l_vdot); fr(ctx->l_phi); fr(ctx->l_phidot); fr(ctx->l_B); fr(ctx->l_Bdot);
-    for (Band &B : ctx->band) {
-        fr(B.node); fr(B.elem); fr(B.epos); fr(B.bconn_); fr(B.fre); fr(B.eflag); fr(B.rowptr); fr(B.col); fr(B.diag);
-    }
+    eft_band_free(ctx);
     fr(ctx->seed); fr(ctx->active); fr(ctx->nin); fr(ctx->nout); fr(ctx->ein); fr(ctx->g2b); fr(ctx->gpos2b);
-    fr(ctx->scan_tmp); fr(ctx->bR); fr(ctx->bX); fr(ctx->bval); fr(ctx->bcmp); fr(ctx->tnum); fr(ctx->tden); fr(ctx->red);
+    fr(ctx->red);
     fr(ctx->dscal);
     eft_mg_free(ctx);
     KrylovWs &K = ctx->kw;
@@ -108,9 +106,6 @@ void free_all(eft_ctx *ctx)
     if (ctx->htsc) (void)hipHostFree(ctx->htsc);
     fr(ctx->tsc);
     fr(ctx->dg);
-    for (eft_ctx::BandUnion *U : {&ctx->u_ac, &ctx->u_b}) {
-        fr(U->rowptr); fr(U->col); fr(U->diag);
-    }
     for (hipEvent_t e : ctx->kt.ev) (void)hipEventDestroy(e);
     ctx->kt.ev.clear();
     eft_nn_free(ctx);
@@ -334,6 +329,34 @@ eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *
         cell_of[e] = ci[0] + ctx->ng[0] * (ci[1] + ctx->ng[1] * ci[2]);
     }
     const int64_t ncell = (int64_t)ctx->ng[0] * ctx->ng[1] * ctx->ng[2];
+    ctx->h_min = 1e300;
+    for (int i = 0; i < d; ++i) ctx->h_min = std::min(ctx->h_min, (hi[i] - lo[i]) / mesh->grid[i]);
+    // the most nodes per element over the grid cells: a band of cells holds
+    // at most this many nodes per band element (sizes the band storage)
+    {
+        std::vector<int64_t> ecount(ncell, 0), ncount(ncell, 0);
+        constexpr int SL = 8;
+        std::vector<int32_t> slot((size_t)N * SL, -1);
+        bool over = false;
+        for (int64_t e = 0; e < E; ++e) {
+            const int32_t c = cell_of[e];
+            ecount[c] += 1;
+            for (int a = 0; a < nn && !over; ++a) {
+                int32_t *sl = &slot[(size_t)conn[e * nn + a] * SL];
+                int k = 0;
+                while (k < SL && sl[k] >= 0 && sl[k] != c) ++k;
+                if (k == SL) over = true;
+                else if (sl[k] < 0) {
+                    sl[k] = c;
+                    ncount[c] += 1;
+                }
+            }
+        }
+        double r = 0.0;
+        for (int64_t c = 0; c < ncell; ++c)
+            if (ecount[c] > 0) r = std::max(r, (double)ncount[c] / (double)ecount[c]);
+        ctx->band_node_ratio = over ? (double)nn : std::max(r, 1e-3);
+    }
     // device copies
     EFT_TRY(upload(ctx, &ctx->xyz, mesh->xyz, N * d));
     EFT_TRY(upload(ctx, &ctx->conn, conn, E * nn));
@@ -369,7 +392,10 @@ eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *
     EFT_TRY(upload(ctx, &ctx->fmask0, fm.data(), N));
     // geometric multigrid needs the structured Kuhn layout of a box
     ctx->structured = structured_kuhn(d, mesh->grid, N, E, mesh->xyz, conn);
-    if (ctx->structured) EFT_TRY(eft_mg_create(ctx, mesh->grid, dm));
+    if (ctx->structured) {
+        EFT_TRY(eft_mg_create(ctx, mesh->grid, dm));
+        EFT_TRY(eft_mg_reserve(ctx));
+    }
     const int mx = std::max(bs, nv);
     EFT_TRY(dalloc(ctx, &ctx->va, N * d));
     EFT_TRY(dalloc(ctx, &ctx->acc, N * d));
@@ -406,7 +432,7 @@ eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *
     }
     // Krylov workspace for the largest system: momentum block or a full-size band
     EFT_TRY(eft_krylov_reserve(ctx, N, mx, par->restart));
-    if (ctx->n_ind > 0) EFT_TRY(eft_reserve_band_sys(ctx, N / 8 + 64, nnzb / 8 + 64));
+    EFT_TRY(eft_band_reserve(ctx));
     EFT_HIP(hipDeviceSynchronize());
     return EFT_OK;
 }
@@ -527,8 +553,15 @@ eft_status eft_set_params(eft_ctx *ctx, const eft_params *par)
         return EFT_EINVAL;
     }
     if (par->restart > ctx->kw.cap_m) EFT_TRY(eft_krylov_reserve(ctx, ctx->N, std::max(ctx->bs, ctx->nv), par->restart));
+    const bool rebands = par->band_reserve != ctx->par.band_reserve || ((par->band_flat < 0.0) != (ctx->par.band_flat < 0.0));
     ctx->par = *par;
-    if (prec) EFT_TRY(alloc_jacobian_values(ctx));
+    if (prec) {
+        EFT_TRY(alloc_jacobian_values(ctx));
+        ctx->mg_valid = false;
+    }
+    EFT_TRY(eft_mg_reserve(ctx));
+    if (rebands) EFT_TRY(eft_band_reserve(ctx));
+    else if (par->restart > ctx->kw.cap_m) EFT_TRY(eft_krylov_reserve(ctx, ctx->bp.cap_n, ctx->nv, par->restart));
     ctx->bands_valid = false;
     return EFT_OK;
 }
@@ -563,6 +596,32 @@ eft_status eft_matrix_export(eft_ctx *ctx, const eft_matrix *A, int32_t *rowptr,
             EFT_HIP(hipMemcpyAsync(val, A->val, sizeof(double) * nv, hipMemcpyDeviceToDevice, ctx->stream));
         }
     }
+    EFT_HIP(hipStreamSynchronize(ctx->stream));
+    return EFT_OK;
+}
+
+__global__ void k_narrow(const double *a, float *b, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}
+
+eft_status eft_matrix_import(eft_ctx *ctx, eft_matrix *A, const double *val)
+{
+    if (!ctx || !A || !val) return EFT_EINVAL;
+    if (A != &ctx->J) {
+        ctx->err = "only the context's momentum matrix can be imported";
+        return EFT_EINVAL;
+    }
+    const int64_t nv = A->nnzb * A->bs * A->bs;
+    if (A->fp32) {
+        hipLaunchKernelGGL(k_narrow, dim3(sgrid(nv)), dim3(256), 0, ctx->stream, val, A->val32, nv);
+        EFT_HIP(hipGetLastError());
+    } else {
+        EFT_HIP(hipMemcpyAsync(A->val, val, sizeof(double) * nv, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    ctx->mg_f32_fresh = false;   // the multigrid hierarchy belongs to the assembled Jacobian
+    ctx->mg_valid = false;
     EFT_HIP(hipStreamSynchronize(ctx->stream));
     return EFT_OK;
 }
@@ -703,13 +762,15 @@ eft_status eft_step(eft_ctx *ctx, eft_state *st, double dt, eft_step_info *info)
     }
     eft_state lvl{ctx->l_vp, ctx->l_vdot, ctx->l_phi, ctx->l_phidot, ctx->l_B, ctx->l_Bdot, st->t, st->step};
     eft_iterate it{st->vp, st->phi, st->B};
+    // bands of phi^n (within the storage reserved at creation; the state is
+    // untouched if they do not fit)
+    if (ctx->n_ind > 0) EFT_TRY(eft_bands_build_dev(ctx, ctx->l_phi));
     // predictor: same values (rates follow from the update formula), boundary data
     if (ctx->n_dir > 0) {
         hipLaunchKernelGGL(k_apply_dirichlet, dim3(eft_grid(ctx->n_dir, 128)), dim3(128), 0, ctx->stream, ctx->n_dir,
                            ctx->dir_node, ctx->dir_mask, ctx->dir_val, bs, st->vp);
         EFT_HIP(hipGetLastError());
     }
-    if (ctx->n_ind > 0) EFT_TRY(eft_bands_build_dev(ctx, ctx->l_phi));
     auto restore = [&]() {
         (void)hipMemcpyAsync(st->vp, ctx->l_vp, sizeof(double) * nvp, hipMemcpyDeviceToDevice, ctx->stream);
         if (nphi) (void)hipMemcpyAsync(st->phi, ctx->l_phi, sizeof(double) * nphi, hipMemcpyDeviceToDevice, ctx->stream);
@@ -732,7 +793,7 @@ eft_status eft_step(eft_ctx *ctx, eft_state *st, double dt, eft_step_info *info)
         eft_status ls = eft_fgmres_dev(ctx, &ctx->J, ctx->R, ctx->dx, &si);
         inf.lin_iters_total += si.iters;
         inf.lin_iters_block[0] += si.iters;
-        if (ls == EFT_ENAN || ls == EFT_EDEVICE || ls == EFT_ENOMEM) {
+        if (ls == EFT_ENAN || ls == EFT_EDEVICE || ls == EFT_ENOMEM || ls == EFT_EBREAKDOWN || ls == EFT_EINVAL) {
             restore();
             return ls;
         }

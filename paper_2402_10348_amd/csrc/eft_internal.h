@@ -45,14 +45,15 @@ struct KrylovWs {
     double *Dinv = nullptr;     // [n][bs*bs]
     double *part = nullptr;     // reduction partials
     double *small = nullptr;    // device scalars: H, cs, sn, g, y, h, norms
-    int32_t *flag = nullptr;    // [4]: active, j_done, breakdown, nan
+    int32_t *flag = nullptr;    // [8]: active, columns done, breakdown, second-pass gate, -,
+                                // learned fallback, singular diagonal block, -
     int32_t nblk = 0;           // blocks of the reduction kernels
 };
 
-// Compact system on the band of one indicator.
+// Compact system on the band of one indicator.  Its arrays are slices of
+// the context's band pool (BandPool), reserved at creation.
 struct Band {
     int64_t n = 0, ne = 0, nnz = 0;            // band nodes, band elements, pattern size
-    int64_t cap_n = 0, cap_ne = 0, cap_nnz = 0;
     int32_t *node = nullptr;                   // [n] global id of band node
     int32_t *elem = nullptr;                   // [ne] global id of band element
     int32_t *epos = nullptr;                   // [ne][nn*nn] position in band pattern
@@ -60,7 +61,20 @@ struct Band {
     uint8_t *fre = nullptr;                    // [n] 1 if the node is solved for
     uint8_t *eflag = nullptr;                  // [E] 1 for band elements
     int32_t *rowptr = nullptr, *col = nullptr, *diag = nullptr;
-    int64_t cap[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}; // allocation sizes in bytes
+};
+
+// Storage of the bands of all indicators, sized once (eft_create,
+// eft_set_params) for band_reserve x the mesh's elements, so that building
+// the bands inside a time step allocates nothing.  Band k takes the next
+// slices of each array.
+struct BandPool {
+    int64_t cap_e = 0, cap_n = 0, cap_nnz = 0;     // elements, nodes, pattern entries of all bands
+    int64_t used_n = 0;                            // nodes of the bands built last
+    int32_t *elem = nullptr, *epos = nullptr, *bconn = nullptr;       // [cap_e], [cap_e nn^2], [cap_e nn]
+    int32_t *node = nullptr, *rowptr = nullptr, *diag = nullptr;      // [cap_n], [cap_n + n_ind], [cap_n]
+    uint8_t *fre = nullptr;                                           // [cap_n]
+    int32_t *col = nullptr;                                           // [cap_nnz]
+    uint8_t *eflag = nullptr;                                         // [n_ind][E]
 };
 
 // One level of the mesh with the node fields the element kernels read.
@@ -191,6 +205,9 @@ struct eft_ctx {
            *l_Bdot = nullptr;
     // transport
     std::vector<Band> band;                    // per indicator
+    BandPool bp;
+    double band_node_ratio = 1.0;              // most nodes per element over the band grid's cells
+    double h_min = 0.0;                        // smallest mesh spacing of the box (band overflow test)
     bool bands_valid = false;
     // block-diagonal union of the band systems of one kind (all Allen-Cahn
     // systems, all B systems), solved together; rebuilt with the bands
@@ -212,7 +229,8 @@ struct eft_ctx {
     double *bR = nullptr, *bX = nullptr;         // band system rhs / solution [cap][nv]
     double *bval = nullptr;                      // band matrix values [cap_nnz][nv*nv]
     double *bcmp = nullptr;                      // B blocks in compact form [cap_nnz][1 + dim^2]
-    int64_t bcap_n = 0, bcap_nnz = 0;
+    double *bdiag = nullptr;                     // B systems: diagonal blocks [cap_n][nv^2] by union row
+    int32_t *iota = nullptr;                     // [cap_n]: i (diagonal index of bdiag)
     double *tnum = nullptr, *tden = nullptr;     // mobility projection sums [cap_n]
     // reductions and host mirror
     double *red = nullptr;                       // partial sums
@@ -227,6 +245,7 @@ struct eft_ctx {
     int32_t *mg_fidx = nullptr, *mg_free = nullptr;  // dof -> free index, free index -> dof
     int64_t mg_nd = 0;
     bool mg_f32_fresh = false;   // the finest level's FP32 or BF16 copy was written by the assembly
+    bool mg_valid = false;       // the hierarchy belongs to the Jacobian now in J (set by eft_mg_setup)
     // diagnostics workspace (centre of mass partials, particles)
     double *dg = nullptr;
     int64_t dg_cap = 0;
@@ -284,7 +303,11 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
 eft_status eft_mg_setup(eft_ctx *ctx, const double *vp);
 eft_status eft_mg_vcycle(eft_ctx *ctx, const double *b0, double *z, const int32_t *flag);
 void eft_mg_free(eft_ctx *ctx);
+// the multigrid preconditioner is requested and possible for A / and its
+// hierarchy belongs to the Jacobian now in A
+bool eft_mg_enabled(const eft_ctx *ctx, const eft_matrix *A);
 bool eft_mg_active(const eft_ctx *ctx, const eft_matrix *A);
+eft_status eft_mg_reserve(eft_ctx *ctx);
 eft_status eft_build_graph(int64_t N, int64_t E, int nn, const int32_t *conn, std::vector<int32_t> &rowptr,
                            std::vector<int32_t> &col, std::vector<int32_t> &diag, std::vector<int32_t> &epos,
                            std::vector<int32_t> &iptr, std::vector<int32_t> &ient, int &maxc, int &rpb,
@@ -295,7 +318,9 @@ eft_status eft_fill_u8(eft_ctx *ctx, uint8_t *p, int64_t n);
 
 // k_sparse.hip
 eft_status eft_spmv_dev(eft_ctx *ctx, const eft_matrix *A, const double *x, double *y);
-eft_status eft_bj_setup(eft_ctx *ctx, const eft_matrix *A, double *Dinv);
+// (sing: optional device flag set to 1 when a diagonal block is singular; its
+// inverse is then replaced by the identity)
+eft_status eft_bj_setup(eft_ctx *ctx, const eft_matrix *A, double *Dinv, int32_t *sing = nullptr);
 eft_status eft_bj_setup32(eft_ctx *ctx, const eft_matrix *A, float *Dinv);
 eft_status eft_bj_apply(eft_ctx *ctx, int bs, int64_t n, const double *Dinv, const double *x, double *z,
                         const int32_t *active);
@@ -325,8 +350,10 @@ eft_status eft_band_system_dev(eft_ctx *ctx, const eft_state *lvl, const eft_ite
                                int64_t *n, int64_t *nnz, int32_t *node, int32_t *rowptr, int32_t *col, double *R,
                                double *J, double *gamma_beta);
 
-// abi helpers
-eft_status eft_reserve_band_sys(eft_ctx *ctx, int64_t n, int64_t nnz);
+// band pool and band-system workspaces for band_reserve (frees the old ones;
+// invalidates the bands)
+eft_status eft_band_reserve(eft_ctx *ctx);
+void eft_band_free(eft_ctx *ctx);
 
 // kernel timing hook (abi.hip)
 int64_t eft_kt_begin(eft_ctx *ctx, int role);
@@ -337,6 +364,8 @@ eft_status eft_kt_harvest(eft_ctx *ctx);
 // learned preconditioner (k_nn.hip)
 eft_status eft_nn_alloc(eft_ctx *ctx);
 void eft_nn_free(eft_ctx *ctx);
-eft_status eft_nn_precond(eft_ctx *ctx, const double *Dinv, const double *v, double *z, const int32_t *flag);
+// (flag[5] is set to 1 when a network output was not finite and the node
+// fell back to block Jacobi)
+eft_status eft_nn_precond(eft_ctx *ctx, const double *Dinv, const double *v, double *z, int32_t *flag);
 eft_status eft_nn_store_pair(eft_ctx *ctx, const double *Dinv, const double *r, const double *e, int64_t slot,
                              const int32_t *flag);

@@ -1,15 +1,17 @@
 // Element assembly of the unified momentum/mass system, eq. (PG_NS).
 //
-// Three kernels:
-//   k_props       per node: generalized-alpha level values (Sec. 2.1.2) and
-//                 phase-interpolated rho, mu (Sec. 2.1.1), solid fractions and
-//                 B at n+alpha;
-//   k_ns_fluid    per element: Galerkin + SUPG/PSPG/LSIC residual and tangent
-//                 of the Newtonian part (tau_m, tau_c formula), scattered with
-//                 hardware FP64 atomics into the residual and the BSR Jacobian;
-//   k_ns_elastic  per element touched by a solid: the left-Cauchy-Green stress
-//                 mu_L (B - I) in the residual and its tangent through
-//                 dB/dv of eq. (Bext) / Appendix B.
+// Two kernels:
+//   k_props    per node: generalized-alpha level values (Sec. 2.1.2) and
+//              phase-interpolated rho, mu (Sec. 2.1.1), solid fractions and
+//              B at n+alpha;
+//   k_ns_rows  row-owned assembly: a workgroup owns a set of block rows; each
+//              (row, incident element) pair evaluates the element at its
+//              quadrature points (Galerkin + SUPG/PSPG/LSIC with the tau_m,
+//              tau_c formula, the Newtonian stress, the left-Cauchy-Green
+//              stress mu_L (B - I) and its tangent through dB/dv of eq.
+//              (Bext) / Appendix B) and adds only that row's residual and
+//              blocks into LDS accumulators; the rows are written out whole
+//              (no global atomics), with the unit rows of Dirichlet dofs.
 // The tangent is factored: per element the quadrature sums that multiply each
 // node-pair block are formed once (about 10 scalars per pair), so a 4x4 block
 // costs a few dozen flops instead of a loop over quadrature points.
@@ -605,7 +607,7 @@ eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_ma
     M.rpb = ctx->rpb_ns;
     // with the multigrid active, the assembly also writes the finest level's
     // FP32 copy of the values (no separate conversion pass over J)
-    const bool mg = J && eft_mg_active(ctx, J);
+    const bool mg = J && eft_mg_enabled(ctx, J);
     float *J32 = (mg && !ctx->par.mg_bf16 && !J->fp32) ? ctx->mg[0].A.val32 : nullptr;
     uint16_t *J16 = (mg && ctx->par.mg_bf16 && !J->fp32) ? ctx->mg[0].A.val16 : nullptr;
     EFT_TRY(eft_ns_level(ctx, M, it->vp, R, J, J32, J16));

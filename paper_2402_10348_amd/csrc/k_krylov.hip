@@ -284,7 +284,12 @@ __global__ __launch_bounds__(RB) void k_close_pass(const double *__restrict__ pa
                 col[i] += hh2[i];
                 q += hh2[i] * hh2[i];
             }
-            s = fmax(s - q, 0.0);
+            // ||w''||^2 by subtraction keeps its digits while s - q is not
+            // far below s; below 1e-8 s it would be mostly rounding, and
+            // w'' is then within 1e-4 of the span of the basis: the column
+            // ends the cycle as a breakdown (H[j+1][j] = 0), and the restart
+            // from the true residual takes over
+            s = (s - q > 1e-8 * s) ? s - q : 0.0;
             small[L.sc() + 1] = s;
         }
     } else if (pass == 1) {
@@ -342,6 +347,12 @@ __global__ void k_trisolve(double *small, int m, const int32_t *flag)
         for (int k = i + 1; k < jj; ++k) s -= H[(int64_t)i * m + k] * y[k];
         y[i] = s / H[(int64_t)i * m + i];
     }
+}
+
+// flags of a solve, before its first cycle
+__global__ void k_clear_flags(int32_t *flag)
+{
+    if (threadIdx.x < 8) flag[threadIdx.x] = 0;
 }
 
 // start of a cycle: v0 = r / beta, g = (beta, 0, ...), flags
@@ -504,17 +515,21 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
     const bool mg = eft_mg_active(ctx, A);   // hierarchy refreshed by the assembly
     inf.fallback_used = (ctx->par.precond == 1 && A == &ctx->J && !mg) ? 1 : 0;
     // learned preconditioner on the momentum system (block Jacobi elsewhere)
-    const bool learned = ctx->par.precond == 2 && A == &ctx->J;
+    bool learned = ctx->par.precond == 2 && A == &ctx->J;
     if (learned && !ctx->net.ready) {
         ctx->err = "precond = 2 needs eft_nn_init (learned preconditioner parameters)";
         return EFT_EINVAL;
     }
+    const int maxit = std::max(1, ctx->par.lin_maxit);
+    // past this many iterations a learned-preconditioned solve continues with
+    // block Jacobi, its fallback (FGMRES admits the change between columns)
+    const int nn_budget = ctx->par.nn_maxit > 0 ? ctx->par.nn_maxit : std::max(1, maxit / 2);
     // training pairs (u = D^-1 A z_j, z_j) from the momentum solves
     NNState &NS = ctx->net;
     const bool harvest = NS.cap_pairs > 0 && A == &ctx->J;
-    if (!mg || harvest) EFT_TRY(eft_bj_setup(ctx, A, K.Dinv));
+    hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, ctx->stream, K.flag);
+    if (!mg || harvest) EFT_TRY(eft_bj_setup(ctx, A, K.Dinv, K.flag + 6));
     const double tol = (rtol > 0.0 ? rtol : ctx->par.lin_rtol) * bnorm;
-    const int maxit = std::max(1, ctx->par.lin_maxit);
     int chunk = 8;   // columns enqueued between two reads of the solver state
     int total = 0;
     double *small = K.small;
@@ -605,14 +620,25 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
             }
             EFT_HIP(hipGetLastError());
             ctx->kt.tag = -1;
-            EFT_HIP(hipMemcpyAsync(ctx->hscal, K.flag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, ctx->stream));
-            EFT_HIP(hipMemcpyAsync(ctx->hscal + 2, small + L.sc() + 5, sizeof(double), hipMemcpyDeviceToHost,
+            EFT_HIP(hipMemcpyAsync(ctx->hscal, K.flag, sizeof(int32_t) * 8, hipMemcpyDeviceToHost, ctx->stream));
+            EFT_HIP(hipMemcpyAsync(ctx->hscal + 4, small + L.sc() + 5, sizeof(double), hipMemcpyDeviceToHost,
                                    ctx->stream));
             EFT_HIP(hipStreamSynchronize(ctx->stream));
             const int32_t *hf = (const int32_t *)ctx->hscal;
             jdone = hf[1];
+            if (hf[5]) inf.fallback_used = 1;
             eft_kt_void_from(ctx, jdone);
             EFT_TRY(eft_kt_harvest(ctx));
+            if (hf[6]) {
+                ctx->err = "singular diagonal block in the point-block Jacobi preconditioner (singular system)";
+                inf.iters = total + jdone;
+                if (info) *info = inf;
+                return EFT_EBREAKDOWN;
+            }
+            if (learned && total + jdone >= nn_budget) {
+                learned = false;
+                inf.fallback_used = 1;
+            }
             if (hf[0] == 0) break;
             // next chunk: half the columns still needed at the faster of two
             // convergence rates, the cycle's mean and the last chunk's (at
@@ -620,7 +646,7 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
             // enqueued past convergence still cost their (gated) launches,
             // while a shorter chunk costs one more read of the state, so the
             // prediction is taken short.
-            const double est = ctx->hscal[2];
+            const double est = ctx->hscal[4];
             chunk = 8;
             if (est > 0.0 && est < beta && jdone > 0) {
                 double rate = std::log(est / beta) / (double)jdone;
@@ -670,3 +696,4 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
     if (st == EFT_ENOTCONV) ctx->err = "FGMRES reached lin_maxit";
     return st;
 }
+

@@ -972,9 +972,27 @@ void eft_mg_free(eft_ctx *ctx)
     ctx->mg_nd = 0;
 }
 
-bool eft_mg_active(const eft_ctx *ctx, const eft_matrix *A)
+bool eft_mg_enabled(const eft_ctx *ctx, const eft_matrix *A)
 {
     return ctx->par.precond == 1 && ctx->mg.size() >= 2 && A == &ctx->J;
+}
+
+bool eft_mg_active(const eft_ctx *ctx, const eft_matrix *A)
+{
+    return eft_mg_enabled(ctx, A) && ctx->mg_valid;
+}
+
+// Storage of the finest level's narrow copy (BF16 with mg_bf16, else FP32),
+// reserved at creation and when mg_bf16 changes, so that the set-up inside a
+// time step allocates nothing.
+eft_status eft_mg_reserve(eft_ctx *ctx)
+{
+    if (ctx->mg.size() < 2) return EFT_OK;
+    MGLevel &F0 = ctx->mg[0];
+    const int64_t nv = ctx->J.nnzb * ctx->bs * ctx->bs;
+    if (ctx->par.mg_bf16 && !F0.A.val16) EFT_TRY(dmal(ctx, &F0.A.val16, nv));
+    if (!ctx->par.mg_bf16 && !F0.A.val32) EFT_TRY(dmal(ctx, &F0.A.val32, nv));
+    return EFT_OK;
 }
 
 // Refresh the hierarchy for the current Jacobian: inject node fields,
@@ -988,7 +1006,10 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
     const int cgrid = (int)std::min<int64_t>(8192, (nv + 255) / 256);
     if (ctx->par.mg_bf16) {
         // BF16 copy of the Jacobian; block inverses of its exact diagonal
-        if (!F0.A.val16) EFT_TRY(dmal(ctx, &F0.A.val16, nv));
+        if (!F0.A.val16) {
+            ctx->err = "multigrid BF16 copy not reserved";
+            return EFT_EINVAL;
+        }
         F0.A.bf16 = true;
         F0.A.fp32 = false;
         if (ctx->J.fp32)
@@ -999,7 +1020,10 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
         EFT_HIP(hipGetLastError());
         EFT_TRY(eft_bj_setup32(ctx, &ctx->J, F0.Dinv32));
     } else {
-        if (!F0.A.val32) EFT_TRY(dmal(ctx, &F0.A.val32, nv));
+        if (!F0.A.val32) {
+            ctx->err = "multigrid FP32 copy not reserved";
+            return EFT_EINVAL;
+        }
         F0.A.bf16 = false;
         F0.A.fp32 = true;
         if (ctx->J.fp32) {
@@ -1079,6 +1103,7 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
             hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(256), 0, ctx->stream, ctx->mg_dense, ctx->mg_inv, nd);
         EFT_HIP(hipGetLastError());
     }
+    ctx->mg_valid = true;
     return EFT_OK;
 }
 

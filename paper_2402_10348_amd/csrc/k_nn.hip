@@ -598,6 +598,21 @@ void load_u(eft_ctx *ctx, const float *src)
 
 }  // namespace
 
+// Fallback of the learned preconditioner, per node: an output with a non-
+// finite entry is replaced by the block-Jacobi vector u of that node.
+static __global__ __launch_bounds__(256) void k_nn_guard(int64_t n, int bs, const double *__restrict__ u, double *z,
+                                                  int32_t *flag)
+{
+    if (flag && flag[0] == 0) return;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    bool bad = false;
+    for (int c = 0; c < bs; ++c) bad |= !isfinite(z[p * bs + c]);
+    if (!bad) return;
+    for (int c = 0; c < bs; ++c) z[p * bs + c] = u[p * bs + c];
+    if (flag) flag[5] = 1;
+}
+
 // ------------------------------------------------------------ host side --
 
 eft_status eft_nn_alloc(eft_ctx *ctx)
@@ -650,8 +665,11 @@ void eft_nn_free(eft_ctx *ctx)
     S.L = L;
 }
 
-// z = u + s (m * NN(u / s, m)) with u = D^-1 v; gated by the Krylov flag
-eft_status eft_nn_precond(eft_ctx *ctx, const double *Dinv, const double *v, double *z, const int32_t *flag)
+// z = u + s (m * NN(u / s, m)) with u = D^-1 v; gated by the Krylov flag.
+// A node whose output is not finite takes the block-Jacobi value u instead
+// (flag[5] = 1 records the fallback; FGMRES admits a preconditioner that
+// changes between columns, so the solve stays valid).
+eft_status eft_nn_precond(eft_ctx *ctx, const double *Dinv, const double *v, double *z, int32_t *flag)
 {
     NNState &S = ctx->net;
     const int64_t nd = ctx->N * S.bs;
@@ -659,6 +677,7 @@ eft_status eft_nn_precond(eft_ctx *ctx, const double *Dinv, const double *v, dou
     hipLaunchKernelGGL(k_bj_u, dim3(nblk), dim3(NB), 0, ctx->stream, ctx->N, S.bs, Dinv, v, S.u, S.red + 8, flag);
     hipLaunchKernelGGL(k_scale, dim3(1), dim3(NB), 0, ctx->stream, S.red + 8, nblk, nd, S.red, flag);
     forward(ctx, z, flag);
+    hipLaunchKernelGGL(k_nn_guard, dim3(grid_of(ctx->N, 256)), dim3(256), 0, ctx->stream, ctx->N, S.bs, S.u, z, flag);
     EFT_HIP(hipGetLastError());
     return EFT_OK;
 }

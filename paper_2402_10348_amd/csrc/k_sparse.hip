@@ -172,7 +172,7 @@ eft_status eft_spmv_dev(eft_ctx *ctx, const eft_matrix *A, const double *x, doub
 // pivoting.  A block with a zero pivot gets the identity (no scaling).
 template <typename TV, typename TD>
 __global__ __launch_bounds__(256) void k_bj_setup(int64_t n, int bs, const int32_t *__restrict__ diag,
-                                                  const TV *__restrict__ val, TD *__restrict__ Dinv)
+                                                  const TV *__restrict__ val, TD *__restrict__ Dinv, int32_t *sing)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
@@ -216,6 +216,7 @@ __global__ __launch_bounds__(256) void k_bj_setup(int64_t n, int bs, const int32
     TD *out = Dinv + r * b2;
     for (int i = 0; i < bs; ++i)
         for (int j = 0; j < bs; ++j) out[i * bs + j] = (TD)(ok ? I[i][j] : (i == j ? 1.0 : 0.0));
+    if (!ok && sing) *sing = 1;
 }
 
 // The same elimination with the block size fixed at compile time: every
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(256) void k_bj_setup(int64_t n, int bs, const int32
 // the arrays above live in scratch memory).
 template <int BS, typename TV, typename TD>
 __global__ __launch_bounds__(256) void k_bj_setup_t(int64_t n, const int32_t *__restrict__ diag,
-                                                    const TV *__restrict__ val, TD *__restrict__ Dinv)
+                                                    const TV *__restrict__ val, TD *__restrict__ Dinv, int32_t *sing)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
@@ -283,6 +284,7 @@ __global__ __launch_bounds__(256) void k_bj_setup_t(int64_t n, const int32_t *__
     for (int i = 0; i < BS; ++i)
 #pragma unroll
         for (int j = 0; j < BS; ++j) out[i * BS + j] = (TD)(ok ? I[i][j] : (i == j ? 1.0 : 0.0));
+    if (!ok && sing) *sing = 1;
 }
 
 __global__ __launch_bounds__(256) void k_bj_apply(int64_t nd, int bs, const double *__restrict__ Dinv, double omega,
@@ -475,7 +477,7 @@ __global__ __launch_bounds__(256) void k_jsweep_bcmp(int64_t n, const int32_t *_
     if (j < NV && row < n) zo[row * NV + j] = zr + omega * u;
 }
 
-template <typename TD> static eft_status bj_setup(eft_ctx *ctx, const eft_matrix *A, TD *Dinv)
+template <typename TD> static eft_status bj_setup(eft_ctx *ctx, const eft_matrix *A, TD *Dinv, int32_t *sing)
 {
     if (A->n == 0) return EFT_OK;
     if (A->bs > 8) {
@@ -486,29 +488,33 @@ template <typename TD> static eft_status bj_setup(eft_ctx *ctx, const eft_matrix
     auto fixed = [&](auto bsc) {
         constexpr int BS = decltype(bsc)::value;
         if (A->fp32)
-            hipLaunchKernelGGL((k_bj_setup_t<BS, float, TD>), g, t, 0, ctx->stream, A->n, A->diag, A->val32, Dinv);
+            hipLaunchKernelGGL((k_bj_setup_t<BS, float, TD>), g, t, 0, ctx->stream, A->n, A->diag, A->val32, Dinv,
+                               sing);
         else
-            hipLaunchKernelGGL((k_bj_setup_t<BS, double, TD>), g, t, 0, ctx->stream, A->n, A->diag, A->val, Dinv);
+            hipLaunchKernelGGL((k_bj_setup_t<BS, double, TD>), g, t, 0, ctx->stream, A->n, A->diag, A->val, Dinv,
+                               sing);
     };
     if (A->bs == 3) fixed(std::integral_constant<int, 3>{});
     else if (A->bs == 4) fixed(std::integral_constant<int, 4>{});
     else if (A->bs == 6) fixed(std::integral_constant<int, 6>{});
     else if (A->fp32)
-        hipLaunchKernelGGL((k_bj_setup<float, TD>), g, t, 0, ctx->stream, A->n, A->bs, A->diag, A->val32, Dinv);
+        hipLaunchKernelGGL((k_bj_setup<float, TD>), g, t, 0, ctx->stream, A->n, A->bs, A->diag, A->val32, Dinv,
+                           sing);
     else
-        hipLaunchKernelGGL((k_bj_setup<double, TD>), g, t, 0, ctx->stream, A->n, A->bs, A->diag, A->val, Dinv);
+        hipLaunchKernelGGL((k_bj_setup<double, TD>), g, t, 0, ctx->stream, A->n, A->bs, A->diag, A->val, Dinv,
+                           sing);
     EFT_HIP(hipGetLastError());
     return EFT_OK;
 }
 
-eft_status eft_bj_setup(eft_ctx *ctx, const eft_matrix *A, double *Dinv)
+eft_status eft_bj_setup(eft_ctx *ctx, const eft_matrix *A, double *Dinv, int32_t *sing)
 {
-    return bj_setup<double>(ctx, A, Dinv);
+    return bj_setup<double>(ctx, A, Dinv, sing);
 }
 
 eft_status eft_bj_setup32(eft_ctx *ctx, const eft_matrix *A, float *Dinv)
 {
-    return bj_setup<float>(ctx, A, Dinv);
+    return bj_setup<float>(ctx, A, Dinv, nullptr);
 }
 
 eft_status eft_bj_apply(eft_ctx *ctx, int bs, int64_t n, const double *Dinv, const double *x, double *z,

@@ -368,7 +368,9 @@ struct TrArgs {
     double alpha, alpha_m, vs, dt, ct;
     double *R, *J;
     double *Jc;      // optional compact blocks (s1, M) of J (B systems)
-    int full_b;      // B systems with Jc: 1 writes every block of J in full, 0 only the diagonal ones
+    int full_b;      // B systems with Jc: 1 writes every block of J in full, 0 only the diagonal
+                     // blocks, into Jd (one per band row)
+    double *Jd;      // B systems, full_b = 0: diagonal blocks [n][nv*nv] by band row
 };
 
 template <int BS>
@@ -446,9 +448,10 @@ __device__ __forceinline__ void band_rows_out_b(const TrArgs &a, int64_t r0, int
         if (!a.fre[r]) {   // a node that keeps its value: residual 0, unit row
             if (threadIdx.x < NVv) a.R[r * NVv + threadIdx.x] = 0.0;
             for (int t = threadIdx.x; t < len; t += blockDim.x) {
-                double *dst = a.J + (kb + t) * B2;
                 const bool dg = a.bcol[kb + t] == r;
-                if (dg || a.full_b || !a.Jc)
+                const bool full = a.full_b || !a.Jc;
+                double *dst = full ? a.J + (kb + t) * B2 : a.Jd + r * B2;
+                if (dg || full)
 #pragma unroll
                     for (int v = 0; v < B2; ++v) dst[v] = (dg && v % (NVv + 1) == 0) ? 1.0 : 0.0;
                 if (a.Jc) {   // compact unit block: s1 = 1, M = 0
@@ -472,8 +475,9 @@ __device__ __forceinline__ void band_rows_out_b(const TrArgs &a, int64_t r0, int
                 else hi = mid;
             }
             const double *src = accJ + ((int64_t)lr * a.maxc + lo) * BP;
-            double *dst = a.J + (kb + t) * B2;
-            if (a.full_b || !a.Jc || a.bcol[kb + t] == r)   // (the diagonal blocks feed the block inverses)
+            const bool full = a.full_b || !a.Jc;
+            double *dst = full ? a.J + (kb + t) * B2 : a.Jd + r * B2;
+            if (full || a.bcol[kb + t] == r)   // (the diagonal blocks feed the block inverses)
 #pragma unroll
                 for (int c = 0; c < NVv; ++c)
 #pragma unroll
@@ -847,6 +851,23 @@ __global__ __launch_bounds__(256) void k_union_fill(int64_t n, int64_t nnz, cons
 __global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
 
 // v *= 1/sqrt(*nrm2) (unscale: v *= sqrt(*nrm2)); factor 1 when *nrm2 = 0
+// Largest |v|^2 over the band nodes (all bands): per-thread maxima, a
+// wavefront maximum, one atomic maximum per wavefront on the bit pattern
+// (non-negative doubles order like their bits).  *out must start at 0.
+__global__ __launch_bounds__(256) void k_band_vmax(int64_t n, const int32_t *node, const double *vp, int bs, int d,
+                                                   unsigned long long *out)
+{
+    double m = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const double *v = vp + (int64_t)node[r] * bs;
+        double s = 0.0;
+        for (int i = 0; i < d; ++i) s += v[i] * v[i];
+        m = fmax(m, s);
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0 && m > 0.0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
 __global__ __launch_bounds__(256) void k_scale_member(int64_t n, double *v, const double *nrm2, int unscale)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -860,82 +881,136 @@ __global__ __launch_bounds__(256) void k_scale_member(int64_t n, double *v, cons
 
 // ------------------------------------------------------------- host side --
 
+// Exclusive scan over n items of `in` (flags or counts), in two calls: the
+// count (returns the total through the host), then the writes (offsets out,
+// compacted indices idx, map), so that a caller can check the total against
+// its storage before anything is written.  Uses ctx->scan_tmp (reserved with
+// the bands).
 template <typename TI>
-static eft_status scan_compact(eft_ctx *ctx, const TI *in, int64_t n, int32_t *out, int32_t *idx, int32_t *map,
-                               int64_t *count)
+static eft_status scan_count(eft_ctx *ctx, const TI *in, int64_t n, int64_t *count)
 {
     const int nb = (int)std::max<int64_t>(1, (n + TILE - 1) / TILE);
     if (ctx->scan_cap < nb + 1) {
-        if (ctx->scan_tmp) (void)hipFree(ctx->scan_tmp);
-        ctx->scan_cap = 0;
-        if (hipMalloc(&ctx->scan_tmp, sizeof(int32_t) * (nb + 1)) != hipSuccess) {
-            ctx->err = "out of device memory (scan)";
-            return EFT_ENOMEM;
-        }
-        ctx->scan_cap = nb + 1;
+        ctx->err = "scan workspace too small";
+        return EFT_EINVAL;
     }
     int32_t *bsum = ctx->scan_tmp;
     hipLaunchKernelGGL(k_scan_count<TI>, dim3(nb), dim3(SB), 0, ctx->stream, in, n, bsum);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SB), 0, ctx->stream, bsum, nb, bsum + nb);
-    hipLaunchKernelGGL(k_scan_write<TI>, dim3(nb), dim3(SB), 0, ctx->stream, in, n, bsum, out, idx, map);
     EFT_HIP(hipGetLastError());
-    int32_t tot = 0;
     EFT_HIP(hipMemcpyAsync(ctx->hscal, bsum + nb, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
     EFT_HIP(hipStreamSynchronize(ctx->stream));
-    tot = *(int32_t *)ctx->hscal;
-    *count = tot;
+    *count = *(int32_t *)ctx->hscal;
     return EFT_OK;
 }
 
-static eft_status grow(eft_ctx *ctx, void **p, int64_t bytes, int64_t *cap_bytes)
+template <typename TI>
+static eft_status scan_write(eft_ctx *ctx, const TI *in, int64_t n, int32_t *out, int32_t *idx, int32_t *map)
 {
-    if (bytes <= *cap_bytes) return EFT_OK;
-    if (*p) (void)hipFree(*p);
+    const int nb = (int)std::max<int64_t>(1, (n + TILE - 1) / TILE);
+    hipLaunchKernelGGL(k_scan_write<TI>, dim3(nb), dim3(SB), 0, ctx->stream, in, n, ctx->scan_tmp, out, idx, map);
+    EFT_HIP(hipGetLastError());
+    return EFT_OK;
+}
+
+template <typename T> static eft_status tmal(eft_ctx *ctx, T **p, int64_t count)
+{
     *p = nullptr;
-    *cap_bytes = 0;
-    // bands move and grow from step to step: twice the size asked for keeps
-    // reallocations (each a device synchronization) rare
-    const int64_t want = std::max<int64_t>(2 * bytes, 1024);
-    if (hipMalloc(p, want) != hipSuccess) {
-        ctx->err = "out of device memory (band)";
+    if (hipMalloc((void **)p, sizeof(T) * (size_t)std::max<int64_t>(count, 1)) != hipSuccess) {
+        ctx->err = "out of device memory (band reserve of " + std::to_string(count) + " entries)";
         return EFT_ENOMEM;
     }
-    *cap_bytes = want;
     return EFT_OK;
 }
 
-eft_status eft_reserve_band_sys(eft_ctx *ctx, int64_t n, int64_t nnz)
+void eft_band_free(eft_ctx *ctx)
 {
-    const int nv = std::max(ctx->nv, 1);
-    if (n > ctx->bcap_n) {
-        if (ctx->bR) (void)hipFree(ctx->bR);
-        if (ctx->bX) (void)hipFree(ctx->bX);
-        if (ctx->tnum) (void)hipFree(ctx->tnum);
-        if (ctx->tden) (void)hipFree(ctx->tden);
-        const int64_t c = 2 * n + 64;
-        if (hipMalloc(&ctx->bR, sizeof(double) * c * nv) != hipSuccess ||
-            hipMalloc(&ctx->bX, sizeof(double) * c * nv) != hipSuccess ||
-            hipMalloc(&ctx->tnum, sizeof(double) * c) != hipSuccess ||
-            hipMalloc(&ctx->tden, sizeof(double) * c) != hipSuccess) {
-            ctx->err = "out of device memory (band system)";
-            return EFT_ENOMEM;
-        }
-        ctx->bcap_n = c;
+    auto fr = [](void *p) {
+        if (p) (void)hipFree(p);
+    };
+    BandPool &P = ctx->bp;
+    fr(P.elem); fr(P.epos); fr(P.bconn); fr(P.node); fr(P.rowptr); fr(P.diag); fr(P.fre); fr(P.col); fr(P.eflag);
+    P = BandPool{};
+    for (eft_ctx::BandUnion *U : {&ctx->u_ac, &ctx->u_b}) {
+        fr(U->rowptr); fr(U->col); fr(U->diag);
+        U->rowptr = U->col = U->diag = nullptr;
+        U->cap_n = U->cap_nnz = U->n = U->nnz = 0;
     }
-    if (nnz > ctx->bcap_nnz) {
-        if (ctx->bval) (void)hipFree(ctx->bval);
-        if (ctx->bcmp) (void)hipFree(ctx->bcmp);
-        ctx->bval = nullptr;
-        ctx->bcmp = nullptr;
-        const int64_t c = 2 * nnz + 64;
-        if (hipMalloc(&ctx->bval, sizeof(double) * c * nv * nv) != hipSuccess ||
-            hipMalloc(&ctx->bcmp, sizeof(double) * c * (1 + ctx->dim * ctx->dim)) != hipSuccess) {
-            ctx->err = "out of device memory (band matrix)";
-            return EFT_ENOMEM;
-        }
-        ctx->bcap_nnz = c;
+    fr(ctx->bR); fr(ctx->bX); fr(ctx->tnum); fr(ctx->tden); fr(ctx->bval); fr(ctx->bcmp); fr(ctx->bdiag); fr(ctx->iota);
+    fr(ctx->scan_tmp);
+    ctx->bR = ctx->bX = ctx->tnum = ctx->tden = ctx->bval = ctx->bcmp = ctx->bdiag = nullptr;
+    ctx->iota = nullptr;
+    ctx->scan_tmp = nullptr;
+    ctx->scan_cap = 0;
+    ctx->band.assign(ctx->n_ind, Band{});
+    ctx->bands_valid = false;
+}
+
+static __global__ void k_iota(int32_t *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (int32_t)i;
+}
+
+eft_status eft_band_reserve(eft_ctx *ctx)
+{
+    eft_band_free(ctx);
+    if (ctx->n_ind == 0) return EFT_OK;
+    const int NN = ctx->nn, nv = ctx->nv, K = ctx->n_ind;
+    const int64_t N = ctx->N, E = ctx->E, nnzb = ctx->J.nnzb;
+    double fr = ctx->par.band_reserve > 0.0 ? ctx->par.band_reserve : 1.0;
+    if (ctx->par.band_flat < 0.0) fr = std::max(fr, (double)K);
+    BandPool &P = ctx->bp;
+    // (by default small meshes reserve for every band covering the whole
+    // mesh: at least 2^20 elements, which costs little)
+    int64_t want = (int64_t)std::ceil(fr * (double)E);
+    if (!(ctx->par.band_reserve > 0.0)) want = std::max<int64_t>(want, 1 << 20);
+    P.cap_e = std::max<int64_t>(1, std::min<int64_t>((int64_t)K * E, want));
+    P.cap_n = std::max<int64_t>(1, std::min<int64_t>((int64_t)K * N,
+                                                     (int64_t)std::ceil(ctx->band_node_ratio * (double)P.cap_e) + 8 * K));
+    P.cap_nnz = std::max<int64_t>(1, std::min<int64_t>((int64_t)K * nnzb, (int64_t)ctx->maxc * P.cap_n));
+    EFT_TRY(tmal(ctx, &P.elem, P.cap_e));
+    EFT_TRY(tmal(ctx, &P.epos, P.cap_e * NN * NN));
+    EFT_TRY(tmal(ctx, &P.bconn, P.cap_e * NN));
+    EFT_TRY(tmal(ctx, &P.node, P.cap_n));
+    EFT_TRY(tmal(ctx, &P.rowptr, P.cap_n + K));
+    EFT_TRY(tmal(ctx, &P.diag, P.cap_n));
+    EFT_TRY(tmal(ctx, &P.fre, P.cap_n));
+    EFT_TRY(tmal(ctx, &P.col, P.cap_nnz));
+    EFT_TRY(tmal(ctx, &P.eflag, (int64_t)K * E));
+    for (eft_ctx::BandUnion *U : {&ctx->u_ac, &ctx->u_b}) {
+        EFT_TRY(tmal(ctx, &U->rowptr, P.cap_n + 1));
+        EFT_TRY(tmal(ctx, &U->diag, P.cap_n));
+        EFT_TRY(tmal(ctx, &U->col, P.cap_nnz));
+        U->cap_n = P.cap_n + 1;
+        U->cap_nnz = P.cap_nnz;
     }
+    EFT_TRY(tmal(ctx, &ctx->bR, P.cap_n * nv));
+    EFT_TRY(tmal(ctx, &ctx->bX, P.cap_n * nv));
+    EFT_TRY(tmal(ctx, &ctx->tnum, P.cap_n));
+    EFT_TRY(tmal(ctx, &ctx->tden, P.cap_n));
+    EFT_TRY(tmal(ctx, &ctx->bval, P.cap_nnz));   // Allen-Cahn values (1 x 1 blocks)
+    EFT_TRY(tmal(ctx, &ctx->bcmp, P.cap_nnz * (1 + ctx->dim * ctx->dim)));
+    EFT_TRY(tmal(ctx, &ctx->bdiag, P.cap_n * nv * nv));
+    EFT_TRY(tmal(ctx, &ctx->iota, P.cap_n));
+    const int64_t nb = (std::max(E, N) + TILE - 1) / TILE + 1;
+    EFT_TRY(tmal(ctx, &ctx->scan_tmp, nb + 1));
+    ctx->scan_cap = nb + 1;
+    hipLaunchKernelGGL(k_iota, dim3(eft_grid(P.cap_n, 256)), dim3(256), 0, ctx->stream, ctx->iota, P.cap_n);
+    EFT_HIP(hipGetLastError());
+    // the band unions are Krylov systems too: the Allen-Cahn union has up to
+    // cap_n rows, the B union up to cap_n rows of nv
+    EFT_TRY(eft_krylov_reserve(ctx, P.cap_n, nv, ctx->par.restart));
     return EFT_OK;
+}
+
+static eft_status band_full(eft_ctx *ctx, const char *what, int64_t need, int64_t cap)
+{
+    ctx->bands_valid = false;
+    ctx->err = std::string("the bands of all indicators need ") + std::to_string(need) + " " + what +
+               ", more than the " + std::to_string(cap) + " reserved (band_reserve = " +
+               std::to_string(ctx->par.band_reserve) + "); raise band_reserve with eft_set_params";
+    return EFT_ENOMEM;
 }
 
 static eft_status build_union(eft_ctx *ctx, eft_ctx::BandUnion &U, const std::vector<int> &bands)
@@ -950,29 +1025,8 @@ static eft_status build_union(eft_ctx *ctx, eft_ctx::BandUnion &U, const std::ve
         n += ctx->band[bands[q]].n;
         nnz += ctx->band[bands[q]].nnz;
     }
-    if (n + 1 > U.cap_n) {
-        if (U.rowptr) (void)hipFree(U.rowptr);
-        if (U.diag) (void)hipFree(U.diag);
-        U.rowptr = U.diag = nullptr;
-        U.cap_n = 0;
-        const int64_t c = 2 * n + 64;
-        if (hipMalloc(&U.rowptr, sizeof(int32_t) * c) != hipSuccess || hipMalloc(&U.diag, sizeof(int32_t) * c) != hipSuccess) {
-            ctx->err = "out of device memory (band union)";
-            return EFT_ENOMEM;
-        }
-        U.cap_n = c;
-    }
-    if (nnz > U.cap_nnz || !U.col) {
-        if (U.col) (void)hipFree(U.col);
-        U.col = nullptr;
-        U.cap_nnz = 0;
-        const int64_t c = 2 * nnz + 64;
-        if (hipMalloc(&U.col, sizeof(int32_t) * c) != hipSuccess) {
-            ctx->err = "out of device memory (band union)";
-            return EFT_ENOMEM;
-        }
-        U.cap_nnz = c;
-    }
+    if (n + 1 > U.cap_n) return band_full(ctx, "union rows", n + 1, U.cap_n);
+    if (nnz > U.cap_nnz) return band_full(ctx, "union pattern entries", nnz, U.cap_nnz);
     U.n = n;
     U.nnz = nnz;
     for (size_t q = 0; q < bands.size(); ++q) {
@@ -992,9 +1046,15 @@ eft_status eft_bands_build_dev(eft_ctx *ctx, const double *phi_n)
     const int D = ctx->dim, NN = D + 1;
     const int64_t N = ctx->N, E = ctx->E;
     const int64_t ncell = (int64_t)ctx->ng[0] * ctx->ng[1] * ctx->ng[2];
-    ctx->band.resize(ctx->n_ind);
+    BandPool &P = ctx->bp;
+    if (!P.elem) {
+        ctx->err = "band storage not reserved";
+        return EFT_EINVAL;
+    }
+    ctx->bands_valid = false;
+    ctx->band.assign(ctx->n_ind, Band{});
     const double thr = 1.0 - ctx->par.band_flat;
-    int64_t max_n = 0, max_nnz = 0;
+    int64_t eoff = 0, noff = 0, zoff = 0;   // pool slices taken so far
     for (int k = 0; k < ctx->n_ind; ++k) {
         const double *phi = phi_n + (int64_t)k * N;
         Band &B = ctx->band[k];
@@ -1016,21 +1076,26 @@ eft_status eft_bands_build_dev(eft_ctx *ctx, const double *phi_n)
             hipLaunchKernelGGL(k_mark<3>, dim3(eft_grid(E, 256)), dim3(256), 0, ctx->stream, E, ctx->conn, ctx->cell_of,
                                ctx->active, ctx->ein, ctx->nin, ctx->nout);
         EFT_HIP(hipGetLastError());
-        // element list
-        int64_t ne = 0, n = 0;
-        int64_t *caps = B.cap;
-        // element and node lists are sized for the worst case (all of the mesh)
-        EFT_TRY(grow(ctx, (void **)&B.eflag, E, &caps[8]));
+        B.eflag = P.eflag + (int64_t)k * E;
         EFT_HIP(hipMemcpyAsync(B.eflag, ctx->ein, E, hipMemcpyDeviceToDevice, ctx->stream));
-        EFT_TRY(grow(ctx, (void **)&B.elem, sizeof(int32_t) * E, &caps[0]));
-        EFT_TRY(scan_compact<uint8_t>(ctx, ctx->ein, E, nullptr, B.elem, nullptr, &ne));
-        EFT_TRY(grow(ctx, (void **)&B.node, sizeof(int32_t) * N, &caps[1]));
-        EFT_TRY(scan_compact<uint8_t>(ctx, ctx->nin, N, nullptr, B.node, ctx->g2b, &n));
+        // element list
+        int64_t ne = 0, n = 0, nnz = 0;
+        EFT_TRY(scan_count<uint8_t>(ctx, ctx->ein, E, &ne));
+        if (eoff + ne > P.cap_e) return band_full(ctx, "elements", eoff + ne, P.cap_e);
+        B.elem = P.elem + eoff;
+        B.epos = P.epos + eoff * NN * NN;
+        B.bconn_ = P.bconn + eoff * NN;
+        EFT_TRY(scan_write<uint8_t>(ctx, ctx->ein, E, nullptr, B.elem, nullptr));
+        // node list and the global -> band map
+        EFT_TRY(scan_count<uint8_t>(ctx, ctx->nin, N, &n));
+        if (noff + n > P.cap_n) return band_full(ctx, "nodes", noff + n, P.cap_n);
+        B.node = P.node + noff;
+        B.fre = P.fre + noff;
+        B.diag = P.diag + noff;
+        B.rowptr = P.rowptr + noff + k;
+        EFT_TRY(scan_write<uint8_t>(ctx, ctx->nin, N, nullptr, B.node, ctx->g2b));
         B.n = n;
         B.ne = ne;
-        EFT_TRY(grow(ctx, (void **)&B.fre, std::max<int64_t>(n, 1), &caps[2]));
-        EFT_TRY(grow(ctx, (void **)&B.rowptr, sizeof(int32_t) * (n + 1), &caps[3]));
-        EFT_TRY(grow(ctx, (void **)&B.diag, sizeof(int32_t) * std::max<int64_t>(n, 1), &caps[4]));
         if (n > 0) {
             hipLaunchKernelGGL(k_band_free, dim3(eft_grid(n, 256)), dim3(256), 0, ctx->stream, n, B.node, ctx->nout,
                                B.fre);
@@ -1038,14 +1103,13 @@ eft_status eft_bands_build_dev(eft_ctx *ctx, const double *phi_n)
                                ctx->J.rowptr, ctx->J.col, ctx->g2b, B.rowptr);
             EFT_HIP(hipGetLastError());
         }
-        int64_t nnz = 0;
         // exclusive scan of the row counts, in place (rowptr[n] = total)
-        EFT_TRY(scan_compact<int32_t>(ctx, B.rowptr, n, B.rowptr, nullptr, nullptr, &nnz));
+        EFT_TRY(scan_count<int32_t>(ctx, B.rowptr, n, &nnz));
+        if (zoff + nnz > P.cap_nnz) return band_full(ctx, "pattern entries", zoff + nnz, P.cap_nnz);
+        EFT_TRY(scan_write<int32_t>(ctx, B.rowptr, n, B.rowptr, nullptr, nullptr));
         hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, ctx->stream, B.rowptr + n, (int32_t)nnz);
         B.nnz = nnz;
-        EFT_TRY(grow(ctx, (void **)&B.col, sizeof(int32_t) * std::max<int64_t>(nnz, 1), &caps[5]));
-        EFT_TRY(grow(ctx, (void **)&B.epos, sizeof(int32_t) * std::max<int64_t>(ne, 1) * NN * NN, &caps[6]));
-        EFT_TRY(grow(ctx, (void **)&B.bconn_, sizeof(int32_t) * std::max<int64_t>(ne, 1) * NN, &caps[7]));
+        B.col = P.col + zoff;
         if (n > 0) {
             hipLaunchKernelGGL(k_band_fill, dim3(eft_grid(n, 256)), dim3(256), 0, ctx->stream, n, B.node, ctx->J.rowptr,
                                ctx->J.col, ctx->g2b, B.rowptr, B.col, B.diag, ctx->gpos2b);
@@ -1059,9 +1123,11 @@ eft_status eft_bands_build_dev(eft_ctx *ctx, const double *phi_n)
                                    ctx->conn, ctx->epos, ctx->gpos2b, ctx->g2b, B.epos, B.bconn_);
         }
         EFT_HIP(hipGetLastError());
-        max_n = std::max(max_n, n);
-        max_nnz = std::max(max_nnz, nnz);
+        eoff += ne;
+        noff += n;
+        zoff += nnz;
     }
+    P.used_n = noff;
     // unions of the Allen-Cahn systems (one per indicator) and of the B
     // systems (one per solid, on its indicator's band)
     std::vector<int> ac_bands, b_bands;
@@ -1069,9 +1135,6 @@ eft_status eft_bands_build_dev(eft_ctx *ctx, const double *phi_n)
     for (int sI = 0; sI < ctx->n_s; ++sI) b_bands.push_back(ctx->solid_ind[sI]);
     EFT_TRY(build_union(ctx, ctx->u_ac, ac_bands));
     EFT_TRY(build_union(ctx, ctx->u_b, b_bands));
-    max_n = std::max(ctx->u_ac.n, ctx->u_b.n);
-    max_nnz = std::max(ctx->u_ac.nnz, ctx->u_b.nnz);
-    EFT_TRY(eft_reserve_band_sys(ctx, max_n, max_nnz));
     EFT_HIP(hipStreamSynchronize(ctx->stream));
     ctx->bands_valid = true;
     return EFT_OK;
@@ -1080,13 +1143,14 @@ eft_status eft_bands_build_dev(eft_ctx *ctx, const double *phi_n)
 // slots of ctx->tsc: per-indicator sums (S, count, beta numerator and
 // denominator), gamma and beta per indicator, per-member squared norms
 constexpr int TS_SUM = 0, TS_GB = 4 * EFT_MAX_IND, TS_NRM = 6 * EFT_MAX_IND, TS_DN = TS_NRM + 128,
-              TS_XN = TS_DN + 128;
+              TS_XN = TS_DN + 128, TS_VMAX = TS_XN + 128;
 
 // gamma and beta of every indicator at the iterate (eq. tdm-num with the RMS
 // over the diffuse region, and the multiplier of Sec. 2.2.1): the sums of all
 // indicators are read back in one transfer; gamma, beta are left on the
 // device at tsc[TS_GB + 2k] for the element kernels and returned in gb
-static eft_status mobility_beta_all(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, double *gb)
+static eft_status mobility_beta_all(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, double *gb,
+                                    double *vmax = nullptr)
 {
     const int D = ctx->dim;
     const int64_t N = ctx->N;
@@ -1094,6 +1158,12 @@ static eft_status mobility_beta_all(eft_ctx *ctx, const eft_state *lvl, const ef
     const int K = ctx->n_ind;
     if (K == 0) return EFT_OK;
     EFT_TRY(eft_fill(ctx, ctx->tsc + TS_SUM, 4 * (int64_t)K, 0.0));
+    EFT_TRY(eft_fill(ctx, ctx->tsc + TS_VMAX, 1, 0.0));
+    if (vmax && ctx->bp.used_n > 0) {
+        const int64_t nb = std::min<int64_t>(1024, eft_grid(ctx->bp.used_n, 256));
+        hipLaunchKernelGGL(k_band_vmax, dim3(nb), dim3(256), 0, ctx->stream, ctx->bp.used_n, ctx->bp.node, it->vp,
+                           ctx->bs, ctx->dim, (unsigned long long *)(ctx->tsc + TS_VMAX));
+    }
     for (int k = 0; k < K; ++k) {
         const Band &B = ctx->band[k];
         if (B.ne == 0) continue;
@@ -1123,7 +1193,10 @@ static eft_status mobility_beta_all(eft_ctx *ctx, const eft_state *lvl, const ef
     }
     EFT_HIP(hipMemcpyAsync(ctx->htsc + TS_SUM, ctx->tsc + TS_SUM, sizeof(double) * 4 * K, hipMemcpyDeviceToHost,
                            ctx->stream));
+    EFT_HIP(hipMemcpyAsync(ctx->htsc + TS_VMAX, ctx->tsc + TS_VMAX, sizeof(double), hipMemcpyDeviceToHost,
+                           ctx->stream));
     EFT_HIP(hipStreamSynchronize(ctx->stream));
+    if (vmax) *vmax = std::sqrt(ctx->htsc[TS_VMAX]);
     for (int k = 0; k < K; ++k) {
         const double *h = ctx->htsc + TS_SUM + 4 * k;
         gb[2 * k] = h[1] > 0.0 ? sqrt(h[0] / h[1]) / ctx->par.eta : 0.0;
@@ -1142,6 +1215,7 @@ static TrArgs tr_args(eft_ctx *ctx, const Band &B, const double *lx, const doubl
     TrArgs a;
     a.Jc = nullptr;
     a.full_b = 1;
+    a.Jd = nullptr;
     a.fre = B.fre;
     a.n = B.n;
     a.rpb = std::min(ctx->rpb, 64);
@@ -1199,7 +1273,7 @@ static eft_status assemble_ac(eft_ctx *ctx, const eft_state *lvl, const eft_iter
 // (Jc: the compact blocks; full: every block of J also in full, else only
 // the diagonal blocks)
 static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, int s, double *R, double *J,
-                             double *Jc, bool full)
+                             double *Jc, bool full, double *Jd)
 {
     const int64_t N = ctx->N;
     const int nv = ctx->nv;
@@ -1209,6 +1283,7 @@ static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_itera
     a.J = J;
     a.Jc = Jc;
     a.full_b = full ? 1 : 0;
+    a.Jd = Jd;
     if (B.n > 0) {
         const int bp = ctx->dim == 2 ? BAcc<2>::P : BAcc<3>::P;
         const size_t shm = (size_t)a.rpb * ((size_t)a.maxc * bp + (nv | 1)) * sizeof(double);
@@ -1257,7 +1332,12 @@ static eft_status union_solve(eft_ctx *ctx, const eft_ctx::BandUnion &U, int bs,
     A.col = U.col;
     A.diag = U.diag;
     A.val = ctx->bval;
-    A.bcmp = bs > 1 ? ctx->bcmp : nullptr;   // (the B systems' assembly writes the compact blocks)
+    A.bcmp = nullptr;
+    if (bs > 1) {   // B systems: compact blocks for the products, diagonal blocks by row for the inverses
+        A.bcmp = ctx->bcmp;
+        A.val = ctx->bdiag;
+        A.diag = ctx->iota;
+    }
     const double rtol = ctx->par.lin_rtol / std::sqrt((double)std::max(members, 1));
     eft_status st = eft_fgmres_dev(ctx, &A, ctx->bR, ctx->bX, si, rtol);
     if (st != EFT_OK && st != EFT_ENOTCONV) return st;
@@ -1298,7 +1378,18 @@ eft_status eft_transport_dev(eft_ctx *ctx, const eft_state *lvl, eft_iterate *it
     eft_status worst = EFT_OK;
     EFT_TRY(eft_props(ctx, lvl, it));
     std::vector<double> gb(2 * std::max(K, 1));
-    EFT_TRY(mobility_beta_all(ctx, lvl, it, gb.data()));
+    double vmax = 0.0;
+    EFT_TRY(mobility_beta_all(ctx, lvl, it, gb.data(), &vmax));
+    // the band must hold the interface through the step: its halo covers
+    // max|v| dt (grid-cell band; no test for the whole-mesh transport)
+    if (ctx->par.band_flat >= 0.0) {
+        const double reach = vmax * ctx->par.dt, room = ctx->par.band_halo * ctx->par.band_cell * ctx->h_min;
+        if (!(reach < room)) {
+            ctx->err = "band overflow: max|v| dt = " + std::to_string(reach) + " on the bands reaches band_halo band_cell h = " +
+                       std::to_string(room) + " (raise band_halo or lower dt)";
+            return EFT_EBAND_OVERFLOW;
+        }
+    }
     for (int k = 0; k < K; ++k) {
         inf.band_nodes[k] = ctx->band[k].n;
         inf.band_elems[k] = ctx->band[k].ne;
@@ -1327,8 +1418,9 @@ eft_status eft_transport_dev(eft_ctx *ctx, const eft_state *lvl, eft_iterate *it
         const eft_ctx::BandUnion &U = ctx->u_b;
         for (int sI = 0; sI < S; ++sI)
             if (ctx->band[ctx->solid_ind[sI]].n > 0)
-                EFT_TRY(assemble_b(ctx, lvl, it, sI, ctx->bR + U.roff[sI] * nv, ctx->bval + U.noff[sI] * nv * nv,
-                                   ctx->bcmp + U.noff[sI] * (1 + ctx->dim * ctx->dim), false));
+                EFT_TRY(assemble_b(ctx, lvl, it, sI, ctx->bR + U.roff[sI] * nv, nullptr,
+                                   ctx->bcmp + U.noff[sI] * (1 + ctx->dim * ctx->dim), false,
+                                   ctx->bdiag + U.roff[sI] * nv * nv));
         std::vector<double *> x(S);
         std::vector<int64_t> xl(S, N * nv);
         for (int sI = 0; sI < S; ++sI) x[sI] = it->B + (int64_t)sI * N * nv;
@@ -1370,8 +1462,10 @@ eft_status eft_band_system_dev(eft_ctx *ctx, const eft_state *lvl, const eft_ite
         gb[0] = all[2 * index];
         gb[1] = all[2 * index + 1];
         EFT_TRY(assemble_ac(ctx, lvl, it, index, ctx->bR, ctx->bval, ctx->tsc + TS_GB + 2 * index));
+    } else if (J) {   // every block in full, straight into the caller's buffer
+        EFT_TRY(assemble_b(ctx, lvl, it, index, ctx->bR, J, ctx->bcmp, true, nullptr));
     } else {
-        EFT_TRY(assemble_b(ctx, lvl, it, index, ctx->bR, ctx->bval, ctx->bcmp, true));
+        EFT_TRY(assemble_b(ctx, lvl, it, index, ctx->bR, nullptr, ctx->bcmp, false, ctx->bdiag));
     }
     if (gamma_beta) {
         gamma_beta[0] = gb[0];
@@ -1381,7 +1475,7 @@ eft_status eft_band_system_dev(eft_ctx *ctx, const eft_state *lvl, const eft_ite
     if (rowptr) EFT_HIP(hipMemcpyAsync(rowptr, B.rowptr, sizeof(int32_t) * (B.n + 1), hipMemcpyDeviceToDevice, ctx->stream));
     if (col) EFT_HIP(hipMemcpyAsync(col, B.col, sizeof(int32_t) * B.nnz, hipMemcpyDeviceToDevice, ctx->stream));
     if (R) EFT_HIP(hipMemcpyAsync(R, ctx->bR, sizeof(double) * B.n * bs, hipMemcpyDeviceToDevice, ctx->stream));
-    if (J) EFT_HIP(hipMemcpyAsync(J, ctx->bval, sizeof(double) * B.nnz * bs * bs, hipMemcpyDeviceToDevice, ctx->stream));
+    if (J && kind == 0) EFT_HIP(hipMemcpyAsync(J, ctx->bval, sizeof(double) * B.nnz, hipMemcpyDeviceToDevice, ctx->stream));
     EFT_HIP(hipStreamSynchronize(ctx->stream));
     return EFT_OK;
 }

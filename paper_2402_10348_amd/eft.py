@@ -46,7 +46,8 @@ class Params(C.Structure):
                 ("precision", C.c_int32), ("band_flat", C.c_double), ("band_cell", C.c_int32),
                 ("band_halo", C.c_int32), ("mg_nu", C.c_int32), ("mg_omega", C.c_double),
                 ("mg_bf16", C.c_int32), ("mg_nu_post", C.c_int32), ("mg_smoother", C.c_int32),
-                ("band_sweeps", C.c_int32), ("band_omega", C.c_double)]
+                ("band_sweeps", C.c_int32), ("band_omega", C.c_double), ("nn_maxit", C.c_int32),
+                ("band_reserve", C.c_double)]
 
 
 class State(C.Structure):
@@ -81,7 +82,7 @@ class KernelTime(C.Structure):
 
 
 EXPORTS = ["eft_create", "eft_destroy", "eft_last_error", "eft_set_params", "eft_ns_matrix", "eft_matrix_shape",
-           "eft_matrix_export", "eft_assemble", "eft_spmv", "eft_fgmres", "eft_bands_build", "eft_band_export",
+           "eft_matrix_export", "eft_matrix_import", "eft_assemble", "eft_spmv", "eft_fgmres", "eft_bands_build", "eft_band_export",
            "eft_band_system", "eft_transport_solids", "eft_step", "eft_time_kernel",
            "eft_kernel_time_read", "eft_nn_init", "eft_nn_shape", "eft_nn_params", "eft_nn_harvest", "eft_nn_train",
            "eft_nn_loss_grad", "eft_nn_apply", "eft_center_of_mass", "eft_track_particles", "eft_init_phase"]
@@ -123,7 +124,7 @@ def params_struct(p, **over):
                 lin_maxit=p.lin_maxit, precond=p.precond, precision=p.precision, band_flat=p.band_flat,
                 band_cell=p.band_cell, band_halo=p.band_halo, mg_nu=p.mg_nu, mg_omega=p.mg_omega,
                 mg_bf16=p.mg_bf16, mg_nu_post=p.mg_nu_post, mg_smoother=p.mg_smoother,
-                band_sweeps=p.band_sweeps, band_omega=p.band_omega)
+                band_sweeps=p.band_sweeps, band_omega=p.band_omega, nn_maxit=p.nn_maxit, band_reserve=p.band_reserve)
     vals.update(over)
     P = Params()
     for k, v in vals.items():
@@ -316,6 +317,10 @@ class Context:
         val = t.empty((nnz, bs, bs), dtype=t.float64, device=self.dev)
         self._check(self.L.eft_matrix_export(self.ctx, self.J, _ptr(rowptr), _ptr(col), _ptr(val)))
         return rowptr, col, val
+
+    def matrix_import(self, val):
+        """Overwrite the context matrix's values with val [nnzb][bs][bs] (device FP64)."""
+        self._check(self.L.eft_matrix_import(self.ctx, self.J, _ptr(val.contiguous())))
 
     def spmv(self, x, y=None):
         if y is None:

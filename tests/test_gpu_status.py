@@ -1,0 +1,159 @@
+"""Error statuses of the C ABI, each forced from the host with every kernel
+ending normally: a NaN in the state (EFT_ENAN), an interface faster than its
+band's halo (EFT_EBAND_OVERFLOW), a singular diagonal block (EFT_EBREAKDOWN),
+bands past their reserved storage (EFT_ENOMEM), and the learned
+preconditioner's fallback to block Jacobi.  A failed step leaves the state
+as it was."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2402_10348_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def ctx_for(prob, **over):
+    from paper_2402_10348_amd.eft import Context
+    return Context(prob, **over)
+
+
+def snapshot(st):
+    return {k: v.detach().cpu().numpy().copy() for k, v in st.items()}
+
+
+def same(a, b):
+    return all(np.array_equal(a[k], b[k], equal_nan=True) for k in a)
+
+
+def test_nan_in_state_returns_enan(torch_cuda):
+    from paper_2402_10348_amd.eft import EftError, ENAN
+    prob = W.cavity_disk_2d(n=16)
+    say("[status] NaN in the state -> EFT_ENAN")
+    ctx = ctx_for(prob)
+    st = ctx.device_state(prob.state_copy())
+    free = int(np.setdiff1d(np.arange(prob.n_nodes), prob.dir_node)[7])
+    st["vp"][free, 0] = float("nan")
+    before = snapshot(st)
+    with pytest.raises(EftError) as ei:
+        ctx.step(st)
+    assert ei.value.status == ENAN
+    assert same(snapshot(st), before)
+    ctx.close()
+
+
+def test_fast_interface_returns_band_overflow(torch_cuda):
+    from paper_2402_10348_amd.eft import EftError, EBAND_OVERFLOW
+    prob = W.cavity_disk_2d(n=32)
+    say("[status] max|v| dt past the band halo -> EFT_EBAND_OVERFLOW")
+    ctx = ctx_for(prob)
+    # the transport call alone, with an iterate moving at 50 (50 * 0.01 > 1 * 4 / 32)
+    lvl = ctx.device_state(prob.state_copy())
+    ctx.bands_build(lvl)
+    it = {k: lvl[k].clone() for k in ("vp", "phi", "B")}
+    it["vp"][:, 0] = 50.0
+    with pytest.raises(EftError) as ei:
+        ctx.transport(lvl, it)
+    assert ei.value.status == EBAND_OVERFLOW and "band overflow" in str(ei.value)
+    # a whole step from a state already moving that fast: a divergence-free
+    # swirl with zero wall velocity (stream function 20 sin^2(pi x) sin^2(pi y),
+    # speeds up to about 60), which the step keeps; the state is restored
+    s0 = prob.state_copy()
+    x, y = prob.xyz[:, 0], prob.xyz[:, 1]
+    s0["vp"][:, 0] = 20.0 * np.pi * np.sin(np.pi * x) ** 2 * np.sin(2 * np.pi * y)
+    s0["vp"][:, 1] = -20.0 * np.pi * np.sin(2 * np.pi * x) * np.sin(np.pi * y) ** 2
+    st = ctx.device_state(s0)
+    before = snapshot(st)
+    with pytest.raises(EftError) as ei:
+        ctx.step(st)
+    assert ei.value.status == EBAND_OVERFLOW
+    assert same(snapshot(st), before)
+    # the same velocity is within the band's reach with a time step 100 x shorter
+    ctx.set_params(dt=1e-4)
+    ctx.bands_build(lvl)
+    info = ctx.transport(lvl, it)
+    assert info["status"] in (0, 4)
+    ctx.close()
+
+
+def test_singular_block_returns_breakdown(torch_cuda):
+    from paper_2402_10348_amd.eft import EftError, EBREAKDOWN
+    torch = torch_cuda
+    prob = W.cavity_disk_2d(n=8)
+    say("[status] singular diagonal block -> EFT_EBREAKDOWN")
+    lvl, it = W.perturbed_state(prob, seed=5)
+    ctx = ctx_for(prob, precond=0)
+    R = ctx.assemble(ctx.device_state(lvl), ctx.device_state(it))
+    rowptr, col, val = ctx.matrix()
+    free = int(np.setdiff1d(np.arange(prob.n_nodes), prob.dir_node)[3])
+    r0, r1 = int(rowptr[free]), int(rowptr[free + 1])
+    val[r0:r1] = 0.0   # the node's whole block row, its diagonal block included
+    ctx.matrix_import(val)
+    with pytest.raises(EftError) as ei:
+        ctx.fgmres(-R)
+    assert ei.value.status == EBREAKDOWN and "singular" in str(ei.value)
+    ctx.close()
+
+
+def test_bands_past_reserve_return_enomem(torch_cuda):
+    from paper_2402_10348_amd.eft import EftError, ENOMEM
+    prob = W.cavity_disk_2d(n=32)
+    say("[status] bands past band_reserve -> EFT_ENOMEM, state unchanged")
+    ctx = ctx_for(prob, band_reserve=0.01)
+    st = ctx.device_state(prob.state_copy())
+    before = snapshot(st)
+    with pytest.raises(EftError) as ei:
+        ctx.step(st)
+    assert ei.value.status == ENOMEM and "band_reserve" in str(ei.value)
+    assert same(snapshot(st), before)
+    ctx.set_params(band_reserve=1.0)
+    info = ctx.step(st)
+    assert info["nl_iters"] == 3
+    ctx.close()
+
+
+def test_learned_preconditioner_falls_back_to_block_jacobi(torch_cuda):
+    """NaN network parameters: every output is replaced by the block-Jacobi
+    value, the solve converges to the block-Jacobi solve's answer, and
+    fallback_used is set.  A budget of 3 iterations hands the rest of a healthy
+    learned solve to block Jacobi as well."""
+    torch = torch_cuda
+    prob = W.cavity_sphere_3d(n=6)
+    say("[status] learned preconditioner fallback")
+    lvl, it = W.perturbed_state(prob, seed=6)
+    over = dict(lin_rtol=1e-12, restart=100, lin_maxit=20000)
+    ref = ctx_for(prob, precond=0, **over)
+    R = ref.assemble(ref.device_state(lvl), ref.device_state(it))
+    x0, i0 = ref.fgmres(-R)
+    assert i0["converged"] == 1
+    ctx = ctx_for(prob, precond=2, **over)
+    R2 = ctx.assemble(ctx.device_state(lvl), ctx.device_state(it))
+    ctx.nn_init(seed=1)
+    th = ctx.nn_params()
+    ctx.nn_params(np.full_like(th, np.nan))
+    x1, i1 = ctx.fgmres(-R2)
+    say(f"  NaN network: iters {i1['iters']} (block Jacobi {i0['iters']}) fallback {i1['fallback']}")
+    assert i1["converged"] == 1 and i1["fallback"] == 1
+    a, b = x1.cpu().numpy(), x0.cpu().numpy()
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-9
+    ctx.nn_init(seed=1)
+    ctx.set_params(nn_maxit=3)
+    x2, i2 = ctx.fgmres(-R2)
+    assert i2["converged"] == 1 and i2["fallback"] == 1
+    c2 = x2.cpu().numpy()
+    assert np.linalg.norm(c2 - b) / np.linalg.norm(b) < 1e-9
+    ctx.close()
+    ref.close()
