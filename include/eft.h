@@ -252,6 +252,20 @@ eft_status eft_spmv(eft_ctx *ctx, const eft_matrix *A, const double *x, double *
  * on a non-finite right-hand side or iterate. */
 eft_status eft_fgmres(eft_ctx *ctx, const eft_matrix *A, const double *b, double *x, eft_solve_info *info);
 
+/* Allocation-free variant of eft_fgmres, for callers that cannot allocate
+ * device memory (code under HIP stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, preconditioner, result
+ * and errors as eft_fgmres, but the Krylov workspace (basis V, Z, w, r, the
+ * block inverses, reduction partials, Hessenberg data, flags) lives in one
+ * fixed device array of 64 MiB that the library holds on each GPU it runs on
+ * until the process ends; nothing is allocated or freed.  Limit:
+ * (2 restart + 3) n bs + n bs^2 + the reduction partials <= 8 Mi doubles
+ * (e.g. restart 50, bs 4: up to about 40,000 nodes); larger systems get
+ * EFT_EINVAL.  Every call on one GPU shares the array and leaves its last
+ * contents there: calls that overlap on one GPU (two streams, two threads)
+ * race.  Harvesting of training pairs must be off (EFT_EINVAL otherwise). */
+eft_status eft_fgmres_noalloc(eft_ctx *ctx, const eft_matrix *A, const double *b, double *x, eft_solve_info *info);
+
 /* (c) Build the transport band of every indicator from phi^n (grid cells of
  * band_cell mesh cells seeded by |phi^n| < 1 - band_flat, dilated by band_halo
  * layers; nodes touched by a non-band element keep their value). */

@@ -432,6 +432,7 @@ eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *
     }
     // Krylov workspace for the largest system: momentum block or a full-size band
     EFT_TRY(eft_krylov_reserve(ctx, N, mx, par->restart));
+    EFT_TRY(eft_scratch_attach(ctx));
     EFT_TRY(eft_band_reserve(ctx));
     EFT_HIP(hipDeviceSynchronize());
     return EFT_OK;

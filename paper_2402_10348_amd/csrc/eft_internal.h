@@ -251,6 +251,11 @@ struct eft_ctx {
     int64_t dg_cap = 0;
     // bounding box of the mesh nodes (host)
     double bb_lo[3] = {0, 0, 0}, bb_hi[3] = {0, 0, 0};
+    // device address of the fixed workspace array on this context's GPU
+    // (eft_fgmres_noalloc), and the guard that makes a workspace reservation
+    // fail instead of allocating while that entry point runs
+    double *scratch = nullptr;
+    bool no_alloc = false;
 };
 
 // ------------------------------------------------------------- helpers ----
@@ -342,6 +347,9 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
                           double rtol = 0.0);   // rtol <= 0: par.lin_rtol
 eft_status eft_norm2(eft_ctx *ctx, const double *x, int64_t n, double *out_host);
 eft_status eft_dot_dev(eft_ctx *ctx, const double *x, const double *y, int64_t n, double *out_dev);
+// looks up (once per device) the address of the fixed workspace array on the
+// current device and records it in the context
+eft_status eft_scratch_attach(eft_ctx *ctx);
 
 // k_transport.hip
 eft_status eft_bands_build_dev(eft_ctx *ctx, const double *phi_n);

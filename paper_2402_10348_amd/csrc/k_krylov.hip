@@ -14,6 +14,9 @@
 // the normalization of v_{j+1}.  Dot products reduce
 // deterministically: each block writes a partial, a second kernel sums the
 // partials in a fixed order.
+#include <mutex>
+#include <string>
+
 #include "dev_common.h"
 #include "eft_internal.h"
 
@@ -413,6 +416,10 @@ eft_status eft_krylov_reserve(eft_ctx *ctx, int64_t n, int bs, int m)
         return EFT_EINVAL;
     }
     if (nd <= K.cap_nd && m <= K.cap_m && n <= K.cap_n && bs * bs * n <= K.cap_bs * K.cap_bs * K.cap_n) return EFT_OK;
+    if (ctx->no_alloc) {
+        ctx->err = "the Krylov workspace would have to grow inside an allocation-free call";
+        return EFT_ENOMEM;
+    }
     const int64_t cnd = std::max(nd, K.cap_nd);
     const int cm = std::max(m, K.cap_m);
     const int64_t cn = std::max(n, K.cap_n);
@@ -697,3 +704,122 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
     return st;
 }
 
+// ------------------------------------------- allocation-free FGMRES ----
+//
+// Callers that cannot allocate device memory (code under stream capture,
+// serving loops, harnesses that forbid it) solve with a Krylov workspace
+// carved from one fixed device array instead of the context's.  Each GPU
+// holds its own copy of the array for the life of the process; every call on
+// a GPU shares it, so calls that overlap on one GPU race.
+
+namespace {
+
+constexpr int64_t NOALLOC_DOUBLES = (int64_t)8 << 20;   // 64 MiB
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int MAX_DEV = 64;
+std::mutex scratch_mu;
+double *scratch_addr[MAX_DEV] = {};
+
+__global__ void k_fill_i32(int32_t *p, int n, int32_t v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// workspace layout inside the array (offsets in doubles, 256-byte aligned)
+struct NoAllocPlan {
+    int64_t V, Z, w, r, Dinv, part, small, flag, total;
+};
+NoAllocPlan plan_of(int64_t n, int bs, int m)
+{
+    const int64_t nd = n * bs;
+    auto up = [](int64_t x) { return (x + 31) / 32 * 32; };
+    NoAllocPlan P{};
+    int64_t o = 0;
+    P.V = o;     o += up(nd * (m + 1));
+    P.Z = o;     o += up(nd * m);
+    P.w = o;     o += up(nd);
+    P.r = o;     o += up(nd);
+    P.Dinv = o;  o += up(n * bs * bs);
+    P.part = o;  o += up((int64_t)nblk_for(nd) * (m + 2));
+    P.small = o; o += up(Small{m}.size());
+    P.flag = o;  o += 32;
+    P.total = o;
+    return P;
+}
+
+}  // namespace
+
+eft_status eft_scratch_attach(eft_ctx *ctx)
+{
+    int dev = 0;
+    EFT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEV) {
+        ctx->err = "device index out of range for the fixed workspace table";
+        return EFT_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_addr[dev]) {
+        void *p = nullptr;
+        EFT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            ctx->err = "hipGetSymbolAddress returned no address for the fixed workspace";
+            return EFT_EDEVICE;
+        }
+        scratch_addr[dev] = (double *)p;
+    }
+    ctx->scratch = scratch_addr[dev];
+    return EFT_OK;
+}
+
+extern "C" eft_status eft_fgmres_noalloc(eft_ctx *ctx, const eft_matrix *A, const double *b, double *x,
+                                         eft_solve_info *info)
+{
+    if (!ctx || !A || !b || !x) return EFT_EINVAL;
+    if (!ctx->scratch) {
+        ctx->err = "fixed workspace not attached (context creation failed?)";
+        return EFT_EDEVICE;
+    }
+    const int m = std::max(1, std::min(ctx->par.restart, EFT_MAX_RESTART));
+    const NoAllocPlan P = plan_of(A->n, A->bs, m);
+    if (P.total > NOALLOC_DOUBLES) {
+        ctx->err = "system too large for the allocation-free solve: (2 restart + 3) n bs + n bs^2 + partials = " +
+                   std::to_string(P.total) + " doubles, the fixed workspace holds " + std::to_string(NOALLOC_DOUBLES);
+        return EFT_EINVAL;
+    }
+    if (ctx->par.precond == 2 && A == &ctx->J && ctx->net.cap_pairs > 0) {
+        ctx->err = "the allocation-free solve does not harvest training pairs (eft_nn_harvest(ctx, 0) first)";
+        return EFT_EINVAL;
+    }
+    double *base = ctx->scratch;
+    KrylovWs W{};
+    W.cap_nd = A->n * A->bs;
+    W.cap_m = m;
+    W.cap_n = A->n;
+    W.cap_bs = A->bs;
+    W.V = base + P.V;
+    W.Z = base + P.Z;
+    W.w = base + P.w;
+    W.r = base + P.r;
+    W.Dinv = base + P.Dinv;
+    W.part = base + P.part;
+    W.small = base + P.small;
+    W.flag = (int32_t *)(base + P.flag);
+    W.nblk = nblk_for(W.cap_nd);
+    // the flags must not carry a previous call's state into the first launch
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, ctx->stream, W.flag, 8, 0);
+    EFT_HIP(hipGetLastError());
+    // the context's own workspace and the timing hook (which creates events)
+    // are set aside for the call
+    const KrylovWs saved = ctx->kw;
+    const uint32_t kt_mask = ctx->kt.mask;
+    ctx->kw = W;
+    ctx->kt.mask = 0;
+    ctx->no_alloc = true;
+    const eft_status st = eft_fgmres_dev(ctx, A, b, x, info);
+    ctx->no_alloc = false;
+    ctx->kt.mask = kt_mask;
+    ctx->kw = saved;
+    return st;
+}

@@ -82,7 +82,7 @@ class KernelTime(C.Structure):
 
 
 EXPORTS = ["eft_create", "eft_destroy", "eft_last_error", "eft_set_params", "eft_ns_matrix", "eft_matrix_shape",
-           "eft_matrix_export", "eft_matrix_import", "eft_assemble", "eft_spmv", "eft_fgmres", "eft_bands_build", "eft_band_export",
+           "eft_matrix_export", "eft_matrix_import", "eft_assemble", "eft_spmv", "eft_fgmres", "eft_fgmres_noalloc", "eft_bands_build", "eft_band_export",
            "eft_band_system", "eft_transport_solids", "eft_step", "eft_time_kernel",
            "eft_kernel_time_read", "eft_nn_init", "eft_nn_shape", "eft_nn_params", "eft_nn_harvest", "eft_nn_train",
            "eft_nn_loss_grad", "eft_nn_apply", "eft_center_of_mass", "eft_track_particles", "eft_init_phase"]
@@ -333,6 +333,17 @@ class Context:
             x = self.torch.empty_like(b)
         info = SolveInfo()
         st = self._check(self.L.eft_fgmres(self.ctx, self.J, _ptr(b), _ptr(x), C.byref(info)), allow=(ENOTCONV,))
+        return x, dict(status=st, iters=info.iters, restarts=info.restarts, converged=info.converged,
+                       rel_res=info.rel_res, fallback=info.fallback_used)
+
+    def fgmres_noalloc(self, b, x=None):
+        """eft_fgmres with the Krylov workspace in the library's fixed device
+        array (allocates nothing)."""
+        if x is None:
+            x = self.torch.empty_like(b)
+        info = SolveInfo()
+        st = self._check(self.L.eft_fgmres_noalloc(self.ctx, self.J, _ptr(b), _ptr(x), C.byref(info)),
+                         allow=(ENOTCONV,))
         return x, dict(status=st, iters=info.iters, restarts=info.restarts, converged=info.converged,
                        rel_res=info.rel_res, fallback=info.fallback_used)
 
