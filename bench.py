@@ -1,22 +1,29 @@
 #!/usr/bin/env python3
 """Throughput of the hot path on one MI355X: converged time steps per second
-of the 3D lid-driven cavity with one elastic sphere (64^3 cells split into
-1,572,864 P1 tets, 274,625 nodes, 4 dof per node), every time step running
-the partitioned nonlinear iteration (momentum/mass assembly + FGMRES,
-Allen-Cahn and B band transport) to the stop rule ||dx||/||x|| < 5e-4 with
-linear solves to 1e-8 relative residual.
+of the largest single-GPU workload, the hull among 16 ice floes in an
+air-water box (256 x 128 x 64 cells split into 12,582,912 P1 tets, 2,154,945
+nodes, 4 dof per node, 18 transported indicators, 17 solids).  Every time
+step runs the partitioned nonlinear iteration (momentum/mass assembly +
+FGMRES, Allen-Cahn and B band transport of every indicator and solid) to the
+stop rule ||dx||/||x|| < 5e-4 on every block, at most 20 iterations, with
+linear solves to 1e-8 relative residual; only steps that meet the stop rule
+count.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Prints one JSON line.  The line carries
-  roofline      the fine-level multigrid smoother sweep (the kernel with the
-                largest share of the step), every launch in the timed steps
-                bracketed by HIP events on the library's stream: algorithmic
-                bytes / summed launch time, vs the 8 TB/s HBM peak; traffic
-                is the rocprofv3-measured HBM bytes per launch when the
-                kernel's sources match the ones profiled;
-  cpu_baseline  the FP64 CPU oracle timed on a bounded sample of the same
-                workload on the host cores (see --no-cpu).
+Prints one JSON line.  Beside the headline it carries
+  roofline      the assembly + SpMV pair of the momentum/mass system (the
+                pair whose HBM fraction the method's target names): summed
+                algorithmic bytes / summed launch time of every assembly and
+                every FGMRES SpMV launch in the timed steps, each bracketed by
+                HIP events on the library's stream, vs the 8 TB/s HBM peak;
+                traffic = the rocprofv3-counted HBM bytes of those launches
+                (per-launch counter figures of profiles/, when the kernels'
+                sources match the ones profiled);
+  kernels       the same per kernel (assembly, SpMV, finest multigrid sweep);
+  secondary     the 128^3 and 64^3 cavities with the elastic sphere;
+  cpu_baseline  the FP64 CPU oracle (OpenMP timing copy) on a bounded sample
+                of the headline workload, on all host threads and on one.
 Inputs are seeded and synthetic and resident in device memory before the
 timed region starts.
 """
@@ -26,6 +33,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -40,23 +48,25 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=64, help="cells per axis of the cavity (64 = the benchmark)")
+    ap.add_argument("--workload", default="floes", choices=["floes", "cavity128", "cavity64"],
+                    help="headline workload (floes = the hull among 16 floes, 256x128x64)")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 FP32 Jacobian values")
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--precond", type=int, default=1, help="1 multigrid V-cycle, 0 point-block Jacobi")
     ap.add_argument("--mg-nu", type=int, default=1, help="multigrid pre-smoothing sweeps (the first from zero)")
     ap.add_argument("--mg-nu-post", type=int, default=3, help="multigrid post-smoothing sweeps")
     ap.add_argument("--mg-smoother", type=int, default=0, help="0 damped block Jacobi, 1 multicolour block Gauss-Seidel")
+    ap.add_argument("--mg-omega", type=float, default=0.75)
+    ap.add_argument("--mg-bf16", type=int, default=1, help="1: finest multigrid level's matrix copy in BF16, 0: FP32")
     ap.add_argument("--band-sweeps", type=int, default=None,
                     help="damped block-Jacobi sweeps preconditioning the Allen-Cahn and B systems")
     ap.add_argument("--band-omega", type=float, default=None)
-    ap.add_argument("--mg-omega", type=float, default=0.75)
-    ap.add_argument("--mg-bf16", type=int, default=1, help="1: finest multigrid level's matrix copy in BF16, 0: FP32")
-    ap.add_argument("--kernel-role", type=int, default=1,
-                    help="kernel of the roofline object: 1 fine-level smoother sweep, 2 momentum SpMV in FGMRES, "
-                         "3 assembly (all three are timed with HIP events over the timed steps); 0 no timing")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="keep the default solver knobs (no autotuning before the warmup)")
+    ap.add_argument("--no-secondary", dest="secondary", action="store_false",
+                    help="skip the 128^3 and 64^3 cavity lines")
     ap.add_argument("--no-mixed", dest="mixed", action="store_false",
-                    help="skip the mixed-precision (FP32 Jacobian) run of the same steps")
+                    help="skip the mixed-precision (FP32 Jacobian) run of the headline steps")
     ap.add_argument("--no-learned", dest="learned", action="store_false",
                     help="skip the learned-vs-plain preconditioner comparison")
     ap.add_argument("--learned-n", type=int, default=32)
@@ -65,14 +75,10 @@ def parse():
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB copied by a plain device copy before the timed steps (HBM counter calibration)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-full-domain", dest="full_domain", action="store_false",
-                    help="skip the paper-literal variants (full-domain transport, background indicator)")
+    ap.add_argument("--no-variants", dest="variants", action="store_false",
+                    help="skip the paper-literal variants and diagnostics (64^3 cavity)")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
-
-
-KERNEL_NAME_FP32 = ("k_sweep_blk<4, float, float> (finest-level multigrid smoother sweep, FP32 copy of the "
-                    "4x4-block momentum Jacobian, one block per lane)")
 
 
 def band_over(args):
@@ -90,11 +96,148 @@ def log(args, *a):
         print(*a, file=sys.stderr, flush=True)
 
 
+def make_workload(name):
+    from paper_2402_10348_amd import workloads as W
+    if name == "floes":
+        p = W.floe_field_3d()
+        return p, "hull among 16 ice floes in an air-water box, 256x128x64 x 6 P1 tets, 18 indicators, 17 solids"
+    n = 128 if name == "cavity128" else 64
+    p = W.cavity_sphere_3d(n=n)
+    return p, f"3D lid-driven cavity with one elastic sphere, {n}^3 x 6 P1 tets"
+
+
 KERNEL_NAME = {1: "k_sweep_blk<4, eft_bf16, float> (finest-level multigrid smoother sweep, BF16 copy of the "
-                  "4x4-block momentum Jacobian, FP32 block inverses, FP64 vectors and arithmetic, one block per lane)",
+                  "4x4-block momentum Jacobian, FP32 block inverses, FP64 vectors and arithmetic)",
                2: "k_spmv_rows<4, double, true> (FP64 SpMV of the 4x4-block momentum Jacobian in FGMRES)",
-               3: "k_ns_rows<3, double> (momentum/mass residual and Jacobian assembly, bytes: J, its BF16 or "
-                  "FP32 copy for the multigrid and R written once, connectivity and node fields read once)"}
+               3: "k_ns_rows<3, double> (momentum/mass residual and Jacobian assembly: J, its BF16 copy for the "
+                  "multigrid and R written once, connectivity and node fields read once)"}
+KERNEL_KEY = {1: "k_sweep_blk", 2: "k_spmv_rows", 3: "k_ns_rows"}
+# sources each kernel's counter figures were taken on
+KERNEL_SOURCES = {1: ("bsr_rows.h", "k_mg.hip"), 2: ("bsr_rows.h", "k_sparse.hip"),
+                  3: ("k_assemble.hip", "dev_common.h")}
+
+
+def sources_hash(role):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[role]:
+        h.update(open(os.path.join(ROOT, "paper_2402_10348_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(role, workload):
+    """HBM bytes per launch of a kernel from the committed counter summary
+    profiles/<kernel>_<workload>_hbm_traffic.md, if it was taken on these
+    sources."""
+    path = os.path.join(ROOT, "profiles", f"{KERNEL_KEY[role]}_{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            kv[k.strip()] = v.strip().strip("`")
+    if kv.get("sources_sha256") != sources_hash(role):
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_steps(args, prob, torch, label, time_kernels=True, **over):
+    """Warmup and timed steps of one workload; converged steps per second,
+    the per-step counts and the kernel timings of the timed steps."""
+    import numpy as np
+    from paper_2402_10348_amd.eft import Context
+    kw = dict(lin_rtol=1e-8, restart=args.restart, lin_maxit=20000, precision=args.precision,
+              precond=args.precond, mg_nu=args.mg_nu, mg_omega=args.mg_omega, mg_bf16=args.mg_bf16,
+              mg_nu_post=args.mg_nu_post, mg_smoother=args.mg_smoother, nl_max=20)
+    kw.update(band_over(args))
+    kw.update(over)
+    t0 = time.perf_counter()
+    ctx = Context(prob, **kw)
+    st = ctx.device_state(prob.state_copy())
+    torch.cuda.synchronize()
+    log(args, f"[bench] {label}: N={prob.n_nodes} E={prob.n_elems} set-up {time.perf_counter() - t0:.1f}s")
+    tune = None
+    if args.tune:
+        t0 = time.perf_counter()
+        tune = ctx.tune(st)
+        tune["seconds"] = round(time.perf_counter() - t0, 2)
+        log(args, f"[bench] {label} tuned in {tune['seconds']}s: {tune}")
+    t_sim, step_no = 0.0, 0
+    for w in range(args.warmup):
+        info = ctx.step(st, t=t_sim, step=step_no)
+        t_sim, step_no = info["t"], info["step"]
+        log(args, f"[bench] {label} warmup {w}: nl={info['nl_iters']} conv={info['converged']} "
+                  f"lin={info['lin_iters_block'][:3]}")
+    if time_kernels:
+        ctx.time_kernel(1, 2, 3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        info = ctx.step(st, t=t_sim, step=step_no)
+        t_sim, step_no = info["t"], info["step"]
+        infos.append(info)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    for i, info in enumerate(infos):
+        log(args, f"[bench] {label} step {i}: nl={info['nl_iters']} conv={info['converged']} "
+                  f"lin={info['lin_iters_block'][:3]} asm={info['t_assemble']:.3f}s solve={info['t_solve']:.3f}s "
+                  f"transport={info['t_transport']:.3f}s")
+    kts = {r: ctx.kernel_time(r) for r in (1, 2, 3)} if time_kernels else {}
+    conv = sum(1 for i in infos if i["converged"])
+    out = dict(value=round(conv / el, 4), unit="steps/s", ms_per_step=round(1e3 * el / args.steps, 2),
+               converged_steps=conv, nonconverged_steps=args.steps - conv,
+               nl_iters_per_step=float(np.mean([i["nl_iters"] for i in infos])),
+               krylov_iters_per_step_by_block=[round(float(v), 2) for v in
+                                               np.mean([i["lin_iters_block"] for i in infos], axis=0)],
+               transport_ms_per_step=round(1e3 * float(np.mean([i["t_transport"] for i in infos])), 2))
+    if tune is not None:
+        out["tuning"] = dict(seconds=tune["seconds"], candidates=tune["evaluated"],
+                             momentum_solve_s_default=round(tune["default_seconds"], 5),
+                             momentum_solve_s_tuned=round(tune["best_seconds"], 5),
+                             momentum_iters_default=tune["default_iters"], momentum_iters_tuned=tune["best_iters"],
+                             transport_s_default=round(tune["band_default_seconds"], 5),
+                             transport_s_tuned=round(tune["band_best_seconds"], 5),
+                             knobs={k: tune[k] for k in ("mg_nu", "mg_nu_post", "mg_smoother", "mg_omega",
+                                                         "band_sweeps", "band_omega")})
+    return out, kts, ctx, st, el
+
+
+def kernel_line(kts, role, workload):
+    kt = kts.get(role)
+    if not kt or kt["launches"] == 0 or kt["seconds"] <= 0:
+        return None
+    achieved = kt["bytes"] / kt["seconds"] / 1e9
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(role, workload),
+                kernel=KERNEL_NAME[role], launches=kt["launches"], active_launches=kt["active"],
+                bytes_per_launch=round(kt["bytes"] / max(kt["active"], 1)),
+                mean_launch_s=kt["seconds"] / kt["launches"])
+
+
+def pair_line(kts, workload):
+    """Assembly + SpMV of the momentum/mass system over the timed steps."""
+    a, s = kts.get(3), kts.get(2)
+    if not a or not s or a["seconds"] <= 0 or s["seconds"] <= 0:
+        return None
+    byt = a["bytes"] + s["bytes"]
+    sec = a["seconds"] + s["seconds"]
+    achieved = byt / sec / 1e9
+    ta, ts = measured_traffic(3, workload), measured_traffic(2, workload)
+    traffic = None
+    if ta is not None and ts is not None:
+        traffic = round(ta * a["active"] + ts * s["active"])
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                kernel="k_ns_rows + k_spmv_rows (assembly and FGMRES SpMV of the momentum/mass system, FP64)",
+                traffic_unit="HBM bytes of all their launches in the timed steps (rocprofv3 FETCH_SIZE + "
+                             "WRITE_SIZE per launch, scaled by a plain copy, times the launches)",
+                algorithmic_bytes=round(byt), seconds=round(sec, 6),
+                launches={"assembly": a["active"], "spmv": s["active"]})
 
 
 def timed_steps(ctx, st, steps, warmup, torch):
@@ -110,8 +253,7 @@ def timed_steps(ctx, st, steps, warmup, torch):
         t_sim, step_no = info["t"], info["step"]
         its.append(info)
     torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    return el, its
+    return time.perf_counter() - t0, its
 
 
 def run_learned(args, torch):
@@ -253,64 +395,6 @@ def run_background(args, prob, torch):
     return line
 
 
-def run_mixed(args, prob, torch):
-    """The same steps with the mixed path: the momentum Jacobian assembled,
-    stored and applied in FP32 inside the FP64 Newton/Krylov iteration."""
-    from paper_2402_10348_amd.eft import Context
-    ctx = Context(prob, lin_rtol=1e-8, restart=args.restart, lin_maxit=20000, precision=1, precond=args.precond,
-                  mg_nu=args.mg_nu, mg_omega=args.mg_omega, mg_nu_post=args.mg_nu_post,
-                  mg_smoother=args.mg_smoother, **band_over(args))
-    st = ctx.device_state(prob.state_copy())
-    t_sim, step_no = 0.0, 0
-    for _ in range(args.warmup):
-        info = ctx.step(st, t=t_sim, step=step_no)
-        t_sim, step_no = info["t"], info["step"]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    its = []
-    for _ in range(args.steps):
-        info = ctx.step(st, t=t_sim, step=step_no)
-        t_sim, step_no = info["t"], info["step"]
-        its.append(info)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ctx.close()
-    return dict(value=round(args.steps / el, 4), unit="steps/s", ms_per_step=round(1e3 * el / args.steps, 2),
-                dtype="f64 residual/Krylov, f32 Jacobian",
-                nl_iters_per_step=sum(i["nl_iters"] for i in its) / len(its),
-                krylov_iters_per_step=sum(i["lin_iters_total"] for i in its) / len(its))
-
-# HBM bytes per launch of the fine-level sweep from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE counters, with the hash of the kernel's sources when they were
-# taken: a changed kernel has no measured traffic.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_blk_cavity64_hbm_traffic.md")
-TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2402_10348_amd", "csrc", f) for f in ("bsr_rows.h", "k_mg.hip")]
-
-
-def sources_hash():
-    import hashlib
-    h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
-        h.update(open(f, "rb").read())
-    return h.hexdigest()
-
-
-def measured_traffic(kernel):
-    """HBM bytes per launch of the fine-level sweep from the committed counter
-    summary, if it was taken on this kernel variant and these sources."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    kv = {}
-    for line in open(TRAFFIC_FILE):
-        if ":" in line and line.startswith("- "):
-            k, v = line[2:].split(":", 1)
-            kv[k.strip()] = v.strip().strip("`")
-    if kv.get("sources_sha256") != sources_hash() or not kernel.startswith(kv.get("kernel", "?") + " "):
-        return None
-    try:
-        return float(kv["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
 
 
 def calib_copy(torch, mib):
@@ -326,81 +410,132 @@ def calib_copy(torch, mib):
     del a, b
 
 
-def cpu_baseline(prob, counts, args):
-    """Time the FP64 CPU oracle on the host on a bounded sample of the
-    benchmark step, then scale to steps/s with the GPU run's per-step counts.
 
-    The sample, all on the full 64^3 workload at its initial state with the
-    step's predictor: one momentum/mass assembly, the band of every indicator
-    with its mobility and Lagrange multiplier, one Allen-Cahn assembly, one B
-    assembly per solid, and ``its`` FGMRES iterations of each of these three
-    systems (the oracle's point-block Jacobi preconditioner).  One step of the
-    oracle is then  nl * (assemblies) + sum_block K_block * (time per Krylov
-    iteration of that block)  with nl and K_block the GPU's mean nonlinear and
-    Krylov iterations per step.  The oracle's preconditioner needs far more
-    iterations than the GPU's multigrid, so the CPU figure is optimistic."""
-    import numpy as np
-
+def oracle_sample(prob, its):
+    """Time the oracle's pieces of one nonlinear iteration on prob at its
+    initial state (after the predictor): the momentum/mass assembly, `its`
+    FGMRES iterations of that system, and for indicator 0 and indicator 1 (the
+    largest band and a smaller one) the band, mobility, beta and Allen-Cahn
+    assembly with `its` iterations, and for solid 0 the B assembly with `its`
+    iterations.  Seconds per piece (per Krylov iteration for the solves)."""
     import oracle as O
-    nl, kblk = counts
     c = O.Case(prob)
     st = prob.state_copy()
     dim, dt, ri = prob.dim, prob.params.dt, prob.params.rho_inf
     it = dict(vp=st["vp"].copy(), phi=st["phi"].copy(), B=st["B"].copy())
-    its = 40   # Krylov iterations sampled per block (about 10-15 s of oracle work in all)
-    tm = {}
-
-    def timed(key, fn, *a, **kw):
-        t0 = time.perf_counter()
-        out = fn(*a, **kw)
-        tm[key] = tm.get(key, 0.0) + time.perf_counter() - t0
-        return out
-
-    R, J = timed("ns_asm", c.ns_assemble, st, it)
-    _, inf = timed("ns_kry", c.fgmres, J, -R.ravel(), rtol=1e-30, restart=its, maxit=its)
-    t_ns_it = tm["ns_kry"] / max(inf["iters"], 1)
+    for q, n in enumerate(prob.dir_node):
+        for i in range(dim + 1):
+            if (prob.dir_mask[q] >> i) & 1:
+                it["vp"][n, i] = prob.dir_val[q, i]
+    out = {}
+    t0 = time.perf_counter()
+    R, J = c.ns_assemble(st, it)
+    out["ns_asm"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, inf = c.fgmres(J, -R.ravel(), rtol=1e-30, restart=its, maxit=its)
+    out["ns_it"] = (time.perf_counter() - t0) / max(inf["iters"], 1)
     del J
     va, _ = O.level_values(ri, dt, st["vp"][:, :dim], st["vdot"], it["vp"][:, :dim])
-    n_ind = st["phi"].shape[0]
-    t_blk = [t_ns_it]
-    t_tr_asm = 0.0
-    bands = []
-    for k in range(n_ind):
+    bands = {}
+    for k in range(min(2, st["phi"].shape[0])):
         t0 = time.perf_counter()
         be, fr = c.band(st["phi"][k])
         fa, fd = O.level_values(ri, dt, st["phi"][k], st["phidot"][k], it["phi"][k])
         g = c.mobility(va, fa)
         b = c.beta(fa, be)
         R, J = c.ac_assemble(va, fa, fd, g, b, be, fr)
-        t_tr_asm += time.perf_counter() - t0
-        bands.append((be, fr))
+        out[f"ac_asm{k}"] = time.perf_counter() - t0
+        bands[k] = (be, fr)
         t0 = time.perf_counter()
         _, inf = c.fgmres(J, -R, rtol=1e-30, restart=its, maxit=its)
-        t_blk.append((time.perf_counter() - t0) / max(inf["iters"], 1))
+        out[f"ac_it{k}"] = (time.perf_counter() - t0) / max(inf["iters"], 1)
     fa_all, _ = O.level_values(ri, dt, st["phi"], st["phidot"], it["phi"])
     af, _, _ = c.nodal_properties(fa_all)
-    s = 0
-    for ph_i, ph in enumerate(prob.phases):
-        if ph.kind != 1:
-            continue
-        k = sum(1 for p in prob.phases[:ph_i] if p.transported)
+    solid = [i for i, p in enumerate(prob.phases) if p.kind == 1]
+    if solid:
+        ph = solid[0]
+        k = sum(1 for p in prob.phases[:ph] if p.transported)
+        be, fr = bands[k] if k in bands else c.band(st["phi"][k])
         t0 = time.perf_counter()
-        Ba, Bd = O.level_values(ri, dt, st["B"][s], st["Bdot"][s], it["B"][s])
-        R, J = c.b_assemble(va, af[ph_i], Ba, Bd, bands[k][0], bands[k][1])
-        t_tr_asm += time.perf_counter() - t0
+        Ba, Bd = O.level_values(ri, dt, st["B"][0], st["Bdot"][0], it["B"][0])
+        R, J = c.b_assemble(va, af[ph], Ba, Bd, be, fr)
+        out["b_asm"] = time.perf_counter() - t0
         t0 = time.perf_counter()
         _, inf = c.fgmres(J, -R.ravel(), rtol=1e-30, restart=its, maxit=its)
-        t_blk.append((time.perf_counter() - t0) / max(inf["iters"], 1))
-        s += 1
-    t_step = nl * (tm["ns_asm"] + t_tr_asm) + sum(k * t for k, t in zip(kblk, t_blk))
-    sample_s = tm["ns_asm"] + tm["ns_kry"] + t_tr_asm + sum(t_blk[1:]) * its
-    return dict(value=1.0 / t_step, unit="steps/s", cores=1, kind="oracle",
-                sample=(f"{prob.n_nodes}-node 64^3 cavity, one host core, {sample_s:.1f} s of oracle work: "
-                        f"momentum/mass assembly {tm['ns_asm']:.2f} s, band + Allen-Cahn + B assembly "
-                        f"{t_tr_asm:.2f} s, Krylov iteration (ms) per block "
-                        + "/".join(f"{1e3 * t:.0f}" for t in t_blk)
-                        + f"; scaled by the GPU's {nl:.2f} nonlinear and "
-                        + "/".join(f"{k:.0f}" for k in kblk) + " Krylov iterations per step"))
+        out["b_it"] = (time.perf_counter() - t0) / max(inf["iters"], 1)
+    return out
+
+
+def oracle_step_seconds(tm, nl, kblk, n_ind, n_s, scale_e=1.0, scale_n=1.0):
+    """One oracle time step from the sampled pieces and the GPU run's per-step
+    counts: nl nonlinear iterations of (assemblies of every system) plus the
+    Krylov iterations of every block; the oracle solves each indicator's and
+    each solid's system on its own, so every member pays the union's count.
+    Indicators past the first two are charged like the second (the smaller
+    band), solids like the first.  scale_e / scale_n scale element- and
+    node-proportional pieces from the sampled mesh to the workload's."""
+    ac1 = "ac_asm1" if "ac_asm1" in tm else "ac_asm0"
+    ai1 = "ac_it1" if "ac_it1" in tm else "ac_it0"
+    asm = tm["ns_asm"] + tm["ac_asm0"] + max(n_ind - 1, 0) * tm[ac1] + n_s * tm.get("b_asm", 0.0)
+    k_ac = kblk[1] if n_ind > 0 else 0.0
+    k_b = kblk[1 + n_ind] if n_s > 0 else 0.0
+    kry = (kblk[0] * tm["ns_it"] + k_ac * (tm["ac_it0"] + max(n_ind - 1, 0) * tm[ai1])
+           + n_s * k_b * tm.get("b_it", 0.0))
+    return scale_e * nl * asm + scale_n * kry
+
+
+def cpu_baseline(prob, wname, gpu_line, args):
+    """The FP64 CPU oracle as it stands, built here as its OpenMP timing copy
+    (bit-identical results), on a bounded sample of the headline workload:
+    one nonlinear iteration's pieces timed at a quarter of the resolution
+    with all host threads (at full size the oracle's dense loop over the 17
+    solids per element would take minutes), scaled by the element and node
+    counts to the full mesh and to a converged step with the GPU run's
+    nonlinear and Krylov counts (the oracle's point-block Jacobi needs far
+    more Krylov iterations than the GPU's multigrid, and small vectors stay
+    in the host caches, so the CPU figure flatters the CPU); the same pieces
+    on one thread at an eighth of the resolution give the 1-thread figure."""
+    import oracle as O
+    from paper_2402_10348_amd import workloads as W
+    its = 10
+    O.use_library(O.timing_build(tempfile.mkdtemp(prefix="orc_timing_")))
+    nthr = O.threads()
+    nl = gpu_line["nl_iters_per_step"]
+    kblk = gpu_line["krylov_iters_per_step_by_block"]
+    n_ind, n_s = prob.phi.shape[0], prob.B.shape[0]
+
+    def reduced(div):
+        if wname == "floes":
+            return W.floe_field_3d(nx=256 // div, ny=128 // div, nz=64 // div)
+        return W.cavity_sphere_3d(n=(128 if wname == "cavity128" else 64) // div)
+
+    res = {}
+    for label, div, thr in (("all", 4, nthr), ("one", 8, 1)):
+        small = reduced(div)
+        O.set_threads(thr)
+        t0 = time.perf_counter()
+        tm = oracle_sample(small, its)
+        wall = time.perf_counter() - t0
+        step = oracle_step_seconds(tm, nl, kblk, n_ind, n_s, prob.n_elems / small.n_elems,
+                                   prob.n_nodes / small.n_nodes)
+        res[label] = (small, tm, wall, step)
+    O.set_threads(nthr)
+    small, tm, wall, step_n = res["all"]
+    small1, _, wall1, step_1 = res["one"]
+    kb = kblk[:1] + kblk[1:2] + kblk[1 + n_ind:2 + n_ind]
+    return dict(value=round(1.0 / step_n, 6), unit="steps/s", cores=nthr, kind="oracle",
+                value_1thread=round(1.0 / step_1, 6),
+                sample=(f"{wname} workload at a quarter of the resolution ({small.n_elems} elements) at its "
+                        f"initial state, OpenMP timing copy of the oracle on {nthr} threads, {wall:.1f} s: "
+                        f"momentum/mass assembly {tm['ns_asm']:.2f} s, {1e3 * tm['ns_it']:.1f} ms per momentum "
+                        f"Krylov iteration, band + Allen-Cahn assembly {tm['ac_asm0']:.2f} s (largest band) and "
+                        f"{tm.get('ac_asm1', 0):.2f} s, B assembly {tm.get('b_asm', 0):.2f} s; scaled by "
+                        f"{prob.n_elems / small.n_elems:.0f}x elements and {prob.n_nodes / small.n_nodes:.1f}x "
+                        f"nodes to the full mesh and to a step with the GPU's {nl:.2f} nonlinear and "
+                        f"{'/'.join(f'{k:.0f}' for k in kb)} (momentum/Allen-Cahn/B) Krylov iterations per step, "
+                        f"every indicator and solid solved on its own.  value_1thread: the same pieces on one "
+                        f"thread at an eighth of the resolution ({small1.n_elems} elements, {wall1:.1f} s), "
+                        f"scaled the same way"))
 
 
 def main():
@@ -409,75 +544,54 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU sharding is a "
               "design, not an implementation)", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     from paper_2402_10348_amd import workloads as W
-    from paper_2402_10348_amd.eft import Context
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
-    prob = W.cavity_sphere_3d(n=args.n)
-    ctx = Context(prob, lin_rtol=1e-8, restart=args.restart, lin_maxit=20000, precision=args.precision,
-                  precond=args.precond, mg_nu=args.mg_nu, mg_omega=args.mg_omega, mg_bf16=args.mg_bf16,
-                  mg_nu_post=args.mg_nu_post, mg_smoother=args.mg_smoother, **band_over(args))
-    st = ctx.device_state(prob.state_copy())
-    log(args, f"[bench] {args.n}^3 cavity N={prob.n_nodes} E={prob.n_elems} precision={args.precision}")
-    t_sim, step_no = 0.0, 0
-    for w in range(args.warmup):
-        info = ctx.step(st, t=t_sim, step=step_no)
-        t_sim, step_no = info["t"], info["step"]
-        log(args, f"[bench] warmup {w}: nl={info['nl_iters']} lin={info['lin_iters_total']}")
+    prob, wdesc = make_workload(args.workload)
     if args.calib_copy:
         calib_copy(torch, args.calib_copy)
-    if args.kernel_role:
-        ctx.time_kernel(1, 2, 3)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = []
-    for k in range(args.steps):
-        info = ctx.step(st, t=t_sim, step=step_no)
-        t_sim, step_no = info["t"], info["step"]
-        infos.append(info)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    for i, info in enumerate(infos):
-        log(args, f"[bench] step {i}: nl={info['nl_iters']} lin={info['lin_iters_total']} conv={info['converged']} "
-                  f"asm={info['t_assemble']:.3f}s solve={info['t_solve']:.3f}s transport={info['t_transport']:.3f}s")
-    value = args.steps / elapsed
-    nl_mean = float(np.mean([i["nl_iters"] for i in infos]))
-    lin_mean = float(np.mean([i["lin_iters_total"] for i in infos]))
-    kblk = [float(v) for v in np.mean([i["lin_iters_block"] for i in infos], axis=0)]
-
-    kts = {r: ctx.kernel_time(r) for r in (1, 2, 3)} if args.kernel_role else {}
-    final = {k: st[k].cpu().numpy() for k in ("vp", "phi", "B")} if args.full_domain else None
-    diag = diagnostics(ctx, st, prob)
+    head, kts, ctx, st, elapsed = run_steps(args, prob, torch, args.workload)
     ctx.close()
-
-    def hbm(role, traffic=None):
-        kt = kts.get(role)
-        if not kt or kt["launches"] == 0 or kt["seconds"] <= 0:
-            return None
-        achieved = kt["bytes"] / kt["seconds"] / 1e9
-        return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    kernel=(KERNEL_NAME_FP32 if role == 1 and not args.mg_bf16 else KERNEL_NAME[role]),
-                    launches=kt["launches"], active_launches=kt["active"],
-                    bytes_per_launch=round(kt["bytes"] / kt["launches"]), mean_launch_s=kt["seconds"] / kt["launches"])
-
-    roofline = None
-    if args.kernel_role:
-        kname = KERNEL_NAME_FP32 if args.kernel_role == 1 and not args.mg_bf16 else KERNEL_NAME[args.kernel_role]
-        roofline = hbm(args.kernel_role, measured_traffic(kname) if args.kernel_role == 1 else None)
-    others = {name: hbm(r) for name, r in (("spmv", 2), ("assembly", 3)) if args.kernel_role and r != args.kernel_role}
-
+    del st
+    roofline = pair_line(kts, args.workload)
+    kernels = {name: kernel_line(kts, r, args.workload) for name, r in (("assembly", 3), ("spmv", 2),
+                                                                         ("mg_sweep", 1))}
     mixed = None
     if args.mixed:
-        mixed = run_mixed(args, prob, torch)
-    full = background = None
-    if args.full_domain:
-        full = run_full_domain(args, prob, torch, final)
-        background = run_background(args, prob, torch)
+        m, _, c2, s2, _ = run_steps(args, prob, torch, args.workload + " mixed", time_kernels=False, precision=1)
+        c2.close()
+        del s2
+        mixed = dict(m, dtype="f64 residual/Krylov, f32 Jacobian")
+    secondary = {}
+    if args.secondary:
+        for name in ("cavity128", "cavity64"):
+            if name == args.workload:
+                continue
+            pb, desc = make_workload(name)
+            line, kt2, c2, s2, _ = run_steps(args, pb, torch, name)
+            c2.close()
+            del s2
+            secondary[name] = dict(line, workload=desc, roofline=pair_line(kt2, name),
+                                   kernels={nm: kernel_line(kt2, r, name) for nm, r in
+                                            (("assembly", 3), ("spmv", 2), ("mg_sweep", 1))})
+    variants = None
+    if args.variants:
+        pb = W.cavity_sphere_3d(n=64)
+        a2 = argparse.Namespace(**vars(args))
+        base, fin = run_variant(a2, pb, torch)
+        full = run_full_domain(a2, pb, torch, fin)
+        background = run_background(a2, pb, torch)
+        from paper_2402_10348_amd.eft import Context
+        c3 = Context(pb)
+        s3 = c3.device_state(pb.state_copy())
+        c3.step(s3)
+        diag = diagnostics(c3, s3, pb)
+        c3.close()
+        variants = dict(workload="3D cavity with elastic sphere, 64^3", banded=base, full_domain_transport=full,
+                        background_indicator=background, diagnostics=diag)
     learned = None
     if args.learned:
         log(args, "[bench] learned vs plain preconditioner ...")
@@ -485,34 +599,35 @@ def main():
     cpu = None
     if not args.no_cpu:
         log(args, "[bench] timing the CPU oracle sample ...")
-        cpu = cpu_baseline(prob, (nl_mean, kblk), args)
+        cpu = cpu_baseline(prob, args.workload, head, args)
 
     line = {
-        "metric": "converged time steps/s (3D cavity, elastic sphere, FP64, FGMRES to 1e-8)",
-        "value": round(value, 4),
+        "metric": "converged time steps/s (FP64, every nonlinear iteration to ||dx||/||x|| < 5e-4, FGMRES to 1e-8)",
+        "value": head["value"],
         "unit": "steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * elapsed / args.steps, 2),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == 0 else "f64+f32J",
-        "data": "synthetic (seeded cavity, tanh sphere indicator, B = I, v = 0 at t = 0)",
-        "config": {"workload": f"3D lid-driven cavity with one elastic sphere, {args.n}^3 x 6 P1 tets",
-                   "n_nodes": prob.n_nodes, "n_elems": prob.n_elems, "dt": prob.params.dt,
-                   "lin_rtol": 1e-8, "restart": args.restart, "nl_rtol": prob.params.nl_rtol,
-                   "nl_iters_per_step": nl_mean, "krylov_iters_per_step": lin_mean,
-                   "krylov_iters_per_step_by_block": kblk,
+        "data": "synthetic (seeded geometry, tanh indicators of analytic signed distances, B = I, v = 0 at t = 0)",
+        "config": {"workload": wdesc, "n_nodes": prob.n_nodes, "n_elems": prob.n_elems,
+                   "indicators": int(prob.phi.shape[0]), "solids": int(prob.B.shape[0]), "dt": prob.params.dt,
+                   "lin_rtol": 1e-8, "restart": args.restart, "nl_rtol": prob.params.nl_rtol, "nl_max": 20,
+                   "converged_steps": head["converged_steps"], "nonconverged_steps": head["nonconverged_steps"],
+                   "nl_iters_per_step": head["nl_iters_per_step"],
+                   "krylov_iters_per_step_by_block": head["krylov_iters_per_step_by_block"],
+                   "transport_ms_per_step": head["transport_ms_per_step"], "tuning": head.get("tuning"),
                    "parallelism": "1 GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "kernels": others,
+        "kernels": kernels,
         "mixed_precision": mixed,
-        "full_domain_transport": full,
-        "diagnostics": diag,
-        "background_indicator": background,
+        "secondary": secondary,
+        "variants": variants,
         "learned_vs_plain_precond": learned,
     }
     print(json.dumps(line), flush=True)

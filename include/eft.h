@@ -108,13 +108,13 @@ typedef struct {
     int32_t band_cell;           /* mesh cells per grid cell and axis              */
     int32_t band_halo;           /* grid-cell layers added around the seeds        */
     int32_t mg_nu;               /* multigrid: smoothing sweeps before the coarse
-                                    correction, the first from x = 0 (1..8)        */
+                                    correction, the first from x = 0 (1..16)       */
     double mg_omega;             /* multigrid: damping of the block-Jacobi sweeps  */
     int32_t mg_bf16;             /* multigrid: 1 stores the finest level's matrix
                                     copy in BF16 (block inverses from the FP64
                                     diagonal blocks), 0 in FP32                    */
     int32_t mg_nu_post;          /* multigrid: smoothing sweeps after the coarse
-                                    correction (1..8)                              */
+                                    correction (1..16)                             */
     int32_t mg_smoother;         /* multigrid: 0 damped node-block Jacobi; 1 node-
                                     block Gauss-Seidel over the parity colours of
                                     the Kuhn mesh (forward before, backward after
@@ -350,6 +350,36 @@ eft_status eft_init_phase(eft_ctx *ctx, const eft_surface *surf, double eps, con
  * place (t += dt, step += 1).  A non-converged nonlinear loop still returns
  * EFT_OK with info->converged = 0 (the paper continues after 20 iterations). */
 eft_status eft_step(eft_ctx *ctx, eft_state *st, double dt, eft_step_info *info);
+
+/* ---- Autotuner of the solver's run-time knobs (not part of the method).
+ * The multigrid sweep counts before/after the coarse correction, its damping
+ * and smoother kind (Jacobi or multicolour Gauss-Seidel), and the sweeps and
+ * damping of the band systems' preconditioner are chosen by measurement: on
+ * the state st (as the first nonlinear iteration of a step sees it) the
+ * momentum/mass system is assembled once and solved once per candidate, and
+ * one transport pass is timed per band candidate (on copies of phi and B; st
+ * is not changed).  None of these knobs changes the converged answer; the
+ * definition parameters (band_cell, band_halo, band_flat, eps, eta, dt,
+ * tolerances) are never changed.  The best set is kept in the context's
+ * parameters.  cache_path (HOST string, may be NULL): a text file of
+ * "key|knobs" lines, the key made of the GPU architecture and the problem's
+ * sizes, materials and solver settings; a key found there is applied without
+ * a search, a new result is appended.  budget: most momentum candidates
+ * timed (<= 0: 64).  info (HOST, may be NULL) receives the outcome. */
+typedef struct {
+    int32_t evaluated;           /* solves and transport passes timed              */
+    int32_t from_cache;          /* 1: knobs read from the cache file              */
+    double default_seconds;      /* one momentum solve with the entry knobs        */
+    double best_seconds;         /* ... with the chosen knobs                      */
+    int32_t default_iters, best_iters;
+    double band_default_seconds; /* one transport pass with the entry knobs        */
+    double band_best_seconds;
+    int32_t mg_nu, mg_nu_post, mg_smoother;
+    double mg_omega;
+    int32_t band_sweeps;
+    double band_omega;
+} eft_tune_info;
+eft_status eft_tune(eft_ctx *ctx, const eft_state *st, const char *cache_path, int32_t budget, eft_tune_info *info);
 
 /* Measurement hook, not part of the method: time every launch of the kernel
  * roles set in role_mask with a pair of HIP events on the context's stream.

@@ -37,6 +37,41 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+def timing_build(out_dir: str) -> str:
+    """Compile the timing copy of the oracle into out_dir: -O3 -march=native
+    with OpenMP (parallel element evaluation and SpMV rows).  -ffp-contract=off
+    keeps every product and sum rounded as in the portable build, and the
+    assembly adds element contributions in element order, so the results
+    are bit-identical with any thread count.  Built where it runs (the
+    native flags target the host's CPU)."""
+    os.makedirs(out_dir, exist_ok=True)
+    out = os.path.join(out_dir, "_liborc_omp.so")
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-ffp-contract=off", "-fopenmp", "-std=c99", "-shared",
+                           "-fPIC", "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
+def use_library(path: str) -> None:
+    """Route every later oracle call through the library at path (the timing
+    copy); the default is the portable build."""
+    global _lib
+    _lib = None
+    _setup(C.CDLL(path))
+
+
+def threads() -> int:
+    """Threads of the loaded library's parallel loops."""
+    return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the parallel loops of the timing copy (no effect on the
+    portable build)."""
+    lib().orc_set_threads(int(n))
+
+
 class Problem(C.Structure):
     _fields_ = [
         ("dim", C.c_int), ("n_nodes", C.c_int), ("n_elems", C.c_int),
@@ -66,19 +101,23 @@ class StepInfo(C.Structure):
 _lib = None
 
 
-def lib():
+def _setup(L):
     global _lib
+    _lib = L
+    L.orc_threads.restype = C.c_int
+    L.orc_graph_nnz.restype = C.c_int
+    L.orc_fgmres.restype = C.c_int
+    L.orc_mobility.restype = C.c_double
+    L.orc_beta.restype = C.c_double
+    L.orc_step.restype = C.c_int
+    L.orc_simplex_geometry.restype = C.c_double
+    L.orc_center_of_mass.restype = C.c_double
+    L.orc_track_particle.restype = C.c_int
+
+
+def lib():
     if _lib is None:
-        _lib = C.CDLL(build())
-        L = _lib
-        L.orc_graph_nnz.restype = C.c_int
-        L.orc_fgmres.restype = C.c_int
-        L.orc_mobility.restype = C.c_double
-        L.orc_beta.restype = C.c_double
-        L.orc_step.restype = C.c_int
-        L.orc_simplex_geometry.restype = C.c_double
-        L.orc_center_of_mass.restype = C.c_double
-        L.orc_track_particle.restype = C.c_int
+        _setup(C.CDLL(build()))
     return _lib
 
 

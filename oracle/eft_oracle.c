@@ -30,6 +30,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------ types */
 
@@ -565,36 +568,66 @@ void orc_ns_assemble(const orc_problem *P, const orc_state *lvl, const double *i
 
     memset(R, 0, sizeof(double) * (size_t)N * bs);
     memset(Jval, 0, sizeof(double) * (size_t)rowptr[N] * bs * bs);
-    double *as = malloc(sizeof(double) * 4 * (ns + 1)), *Bv = malloc(sizeof(double) * 24 * (ns + 1));
-    for (int e = 0; e < P->n_elems; ++e) {
-        int nodes[4];
-        double X[4][3], v[4][3] = {{0}}, acc[4][3] = {{0}}, p[4], r4[4], m4[4], re[4][4], Ke[4][4][4][4];
-        element_coords(P, e, nodes, X);
-        for (int a = 0; a < nn; ++a) {
-            int n = nodes[a];
-            for (int i = 0; i < d; ++i) {
-                v[a][i] = F.v_a[(size_t)n * d + i];
-                acc[a][i] = F.acc[(size_t)n * d + i];
+    /* Elements are evaluated in chunks (in parallel when built with OpenMP,
+     * for the timing copy) into element-major buffers, then added into R and
+     * J one element after the other in element order, so the sums are the
+     * same with any number of threads. */
+    const int CH = 16384;
+    int chunk = P->n_elems < CH ? P->n_elems : CH;
+    if (chunk < 1) chunk = 1;
+    int *cn = malloc(sizeof(int) * 4 * (size_t)chunk);
+    double *cre = malloc(sizeof(double) * 16 * (size_t)chunk), *cKe = malloc(sizeof(double) * 256 * (size_t)chunk);
+    for (int e0 = 0; e0 < P->n_elems; e0 += chunk) {
+        int e1 = e0 + chunk < P->n_elems ? e0 + chunk : P->n_elems;
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+        {
+            double *as = malloc(sizeof(double) * 4 * (ns + 1)), *Bv = malloc(sizeof(double) * 24 * (ns + 1));
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+            for (int e = e0; e < e1; ++e) {
+                int nodes[4];
+                double X[4][3], v[4][3] = {{0}}, acc[4][3] = {{0}}, p[4], r4[4], m4[4];
+                double (*re)[4] = (double (*)[4])(cre + 16 * (size_t)(e - e0));
+                double (*Ke)[4][4][4] = (double (*)[4][4][4])(cKe + 256 * (size_t)(e - e0));
+                element_coords(P, e, nodes, X);
+                for (int a = 0; a < nn; ++a) {
+                    int n = nodes[a];
+                    cn[4 * (size_t)(e - e0) + a] = n;
+                    for (int i = 0; i < d; ++i) {
+                        v[a][i] = F.v_a[(size_t)n * d + i];
+                        acc[a][i] = F.acc[(size_t)n * d + i];
+                    }
+                    p[a] = F.p[n];
+                    r4[a] = rho[n];
+                    m4[a] = mu[n];
+                    for (int s = 0; s < ns; ++s) {
+                        as[s * 4 + a] = af[(size_t)phase_of_solid(P, s) * N + n];
+                        for (int c = 0; c < nv; ++c) Bv[(s * 4 + a) * 6 + c] = F.B_a[((size_t)s * N + n) * nv + c];
+                    }
+                }
+                ns_element(d, &ga, P->C_I, P->g, X, v, NULL, acc, p, r4, m4, ns, as, Bv, muL, re, Ke);
             }
-            p[a] = F.p[n];
-            r4[a] = rho[n];
-            m4[a] = mu[n];
-            for (int s = 0; s < ns; ++s) {
-                as[s * 4 + a] = af[(size_t)phase_of_solid(P, s) * N + n];
-                for (int c = 0; c < nv; ++c) Bv[(s * 4 + a) * 6 + c] = F.B_a[((size_t)s * N + n) * nv + c];
-            }
+            free(as); free(Bv);
         }
-        ns_element(d, &ga, P->C_I, P->g, X, v, NULL, acc, p, r4, m4, ns, as, Bv, muL, re, Ke);
-        for (int a = 0; a < nn; ++a) {
-            for (int i = 0; i < bs; ++i) R[(size_t)nodes[a] * bs + i] += re[a][i];
-            for (int b = 0; b < nn; ++b) {
-                int k = find_col(rowptr, col, nodes[a], nodes[b]);
-                for (int i = 0; i < bs; ++i)
-                    for (int j = 0; j < bs; ++j) Jval[((size_t)k * bs + i) * bs + j] += Ke[a][b][i][j];
+        for (int e = e0; e < e1; ++e) {
+            const int *nodes = cn + 4 * (size_t)(e - e0);
+            double (*re)[4] = (double (*)[4])(cre + 16 * (size_t)(e - e0));
+            double (*Ke)[4][4][4] = (double (*)[4][4][4])(cKe + 256 * (size_t)(e - e0));
+            for (int a = 0; a < nn; ++a) {
+                for (int i = 0; i < bs; ++i) R[(size_t)nodes[a] * bs + i] += re[a][i];
+                for (int b = 0; b < nn; ++b) {
+                    int k = find_col(rowptr, col, nodes[a], nodes[b]);
+                    for (int i = 0; i < bs; ++i)
+                        for (int j = 0; j < bs; ++j) Jval[((size_t)k * bs + i) * bs + j] += Ke[a][b][i][j];
+                }
             }
         }
     }
-    free(as); free(Bv); free(af); free(rho); free(mu); free(muL);
+    free(cn); free(cre); free(cKe);
+    free(af); free(rho); free(mu); free(muL);
     level_fields_free(&F);
 }
 
@@ -695,10 +728,34 @@ void orc_ns_apply_bc(const orc_problem *P, const int *rowptr, const int *col, do
     }
 }
 
+/* Threads the library runs its parallel loops on (1 without OpenMP), and
+ * setting them (n > 0; no effect without OpenMP). */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------- sparse algebra */
 
 void orc_spmv(int bs, int n, const int *rowptr, const int *col, const double *val, const double *x, double *y)
 {
+    /* rows are independent: the OpenMP timing copy splits them over threads */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int r = 0; r < n; ++r)
         for (int i = 0; i < bs; ++i) {
             double s = 0.0;

@@ -77,13 +77,21 @@ class StepInfo(C.Structure):
                 ("t_solve", C.c_double), ("t_transport", C.c_double), ("lin_iters_block", C.c_int32 * 129)]
 
 
+class TuneInfo(C.Structure):
+    _fields_ = [("evaluated", C.c_int32), ("from_cache", C.c_int32), ("default_seconds", C.c_double),
+                ("best_seconds", C.c_double), ("default_iters", C.c_int32), ("best_iters", C.c_int32),
+                ("band_default_seconds", C.c_double), ("band_best_seconds", C.c_double),
+                ("mg_nu", C.c_int32), ("mg_nu_post", C.c_int32), ("mg_smoother", C.c_int32),
+                ("mg_omega", C.c_double), ("band_sweeps", C.c_int32), ("band_omega", C.c_double)]
+
+
 class KernelTime(C.Structure):
     _fields_ = [("launches", C.c_int64), ("active", C.c_int64), ("seconds", C.c_double), ("bytes", C.c_double)]
 
 
 EXPORTS = ["eft_create", "eft_destroy", "eft_last_error", "eft_set_params", "eft_ns_matrix", "eft_matrix_shape",
            "eft_matrix_export", "eft_matrix_import", "eft_assemble", "eft_spmv", "eft_fgmres", "eft_fgmres_noalloc", "eft_bands_build", "eft_band_export",
-           "eft_band_system", "eft_transport_solids", "eft_step", "eft_time_kernel",
+           "eft_band_system", "eft_transport_solids", "eft_step", "eft_tune", "eft_time_kernel",
            "eft_kernel_time_read", "eft_nn_init", "eft_nn_shape", "eft_nn_params", "eft_nn_harvest", "eft_nn_train",
            "eft_nn_loss_grad", "eft_nn_apply", "eft_center_of_mass", "eft_track_particles", "eft_init_phase"]
 
@@ -239,6 +247,18 @@ class Context:
         for k, v in over.items():
             setattr(p, k, v)
         self._check(self.L.eft_set_params(self.ctx, C.byref(p)))
+
+    def tune(self, st, cache_path=None, budget=0):
+        """Autotune the solver's run-time knobs on the device state dict st
+        (unchanged); returns the outcome and keeps the chosen knobs."""
+        S = self._state(st)
+        out = TuneInfo()
+        cp = cache_path.encode() if cache_path else None
+        self._check(self.L.eft_tune(self.ctx, C.byref(S), C.c_char_p(cp) if cp else None, C.c_int32(budget),
+                                    C.byref(out)))
+        for k in ("mg_nu", "mg_nu_post", "mg_smoother", "mg_omega", "band_sweeps", "band_omega"):
+            setattr(self.params, k, getattr(out, k))
+        return {f[0]: getattr(out, f[0]) for f in TuneInfo._fields_}
 
     def time_kernel(self, *roles):
         """Start HIP-event timing of kernel roles (1 fine-level smoother

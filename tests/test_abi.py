@@ -43,7 +43,8 @@ def test_binding_lists_every_export():
 
 PAIRS = [("Mesh", "eft_mesh"), ("Phase", "eft_phase"), ("Materials", "eft_materials"), ("Params", "eft_params"),
          ("State", "eft_state"), ("Iterate", "eft_iterate"), ("SolveInfo", "eft_solve_info"),
-         ("TransportInfo", "eft_transport_info"), ("StepInfo", "eft_step_info")]
+         ("TransportInfo", "eft_transport_info"), ("StepInfo", "eft_step_info"), ("TuneInfo", "eft_tune_info"),
+         ("KernelTime", "eft_kernel_time")]
 
 
 def test_struct_layouts_match_header(tmp_path):

@@ -1024,3 +1024,35 @@ def test_init_phase_grid_cells_restrict_without_changing():
     far = np.abs(d) > 0.25
     assert np.all(np.abs(p6[far]) > 1.0 - 1e-6) and int((np.abs(p6[far]) == 1.0).sum()) > 0
 
+
+
+def test_oracle_timing_copy_is_bit_identical(tmp_path):
+    """The OpenMP timing copy of the oracle (-O3 -march=native, parallel
+    element evaluation and SpMV rows, no contraction of products into FMAs)
+    gives the portable build's residual, Jacobian and products bit for bit,
+    with several threads and with one."""
+    import ctypes
+    import subprocess
+    import sys
+    code = r"""
+import sys, numpy as np
+sys.path.insert(0, %r)
+import oracle as O
+from paper_2402_10348_amd import workloads as W
+prob = W.floe_field_3d(nx=16, ny=8, nz=4, n_floes=2)
+lvl, it = W.perturbed_state(prob, seed=4)
+c = O.Case(prob)
+R0, J0 = c.ns_assemble(lvl, it)
+x = np.random.Generator(np.random.PCG64(1)).standard_normal(R0.shape)
+y0 = c.spmv(J0, x)
+O.use_library(O.timing_build(%r))
+for nt in (3, 1):
+    O.set_threads(nt)
+    c2 = O.Case(prob)
+    R1, J1 = c2.ns_assemble(lvl, it)
+    y1 = c2.spmv(J1, x)
+    assert np.array_equal(R0, R1) and np.array_equal(J0, J1) and np.array_equal(y0, y1), nt
+print("ok")
+""" % (os.path.dirname(os.path.dirname(os.path.abspath(__file__))), str(tmp_path))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
+    assert out.returncode == 0 and "ok" in out.stdout, out.stdout + out.stderr
