@@ -6,9 +6,14 @@ package, and the HIP package never imports it.  Problems are passed in as any
 object with the attributes of a workload description (dim, xyz, conn, grid,
 dir_node, dir_mask, dir_val, phases, g, params).
 
-Functions whose parity is not pinned by an independent check: none besides the
-grid-cell band, whose definition is this implementation's own (checked by brute
-force in the tests).
+Every function is pinned by a check independent of its own code (see the
+tests): closed forms, printed values, invariants, finite differences, a dense
+solve, manufactured-solution convergence rates of the momentum/mass and
+Allen-Cahn discretizations, and, for the grid-cell band (a definition of this
+implementation's own), a brute-force restatement plus the geometric decay of
+its difference to the full-domain transport with the halo width.  Parity
+unpinned: only the paper's physical trajectories (figures without data) and
+the bound |phi| <= 1 + delta.
 """
 from __future__ import annotations
 

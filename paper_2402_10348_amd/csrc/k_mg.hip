@@ -830,9 +830,11 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
     for (int64_t p = 0; p < ctx->N; ++p) inj_prev[p] = p;
     for (;;) {
         const MGLevel &F = ctx->mg.back();
-        // coarsen while every axis has an even cell count of at least 4
+        // coarsen while every axis has an even cell count (down to one cell
+        // per axis, so that anisotropic boxes still end on a coarsest level
+        // small enough for the LDS-resident dense inverse)
         bool can = true;
-        for (int k = 0; k < d; ++k) can &= F.n[k] % 2 == 0 && F.n[k] >= 4;
+        for (int k = 0; k < d; ++k) can &= F.n[k] % 2 == 0 && F.n[k] >= 2;
         if (!can) break;
         MGLevel C;
         for (int k = 0; k < 3; ++k) C.n[k] = k < d ? F.n[k] / 2 : 0;

@@ -1056,3 +1056,157 @@ print("ok")
 """ % (os.path.dirname(os.path.dirname(os.path.abspath(__file__))), str(tmp_path))
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
     assert out.returncode == 0 and "ok" in out.stdout, out.stdout + out.stderr
+
+
+# ------------------------------------------- manufactured-solution rates --
+#
+# The discrete systems below are the oracle's own (its assembly of eq. PG_NS
+# and eq. PPV_AC); their Newton updates are solved with a sparse direct
+# solver so that the rates measure the discretization, not the iteration.
+
+def _newton(assemble, x0, bs, graph, iters=30, tol=1e-13):
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    rowptr, col = graph
+    n = rowptr.shape[0] - 1
+    x = x0.copy()
+    for _ in range(iters):
+        R, J = assemble(x)
+        if bs == 1:
+            A = sp.csr_matrix((J, col, rowptr), shape=(n, n)).tocsc()
+        else:
+            A = sp.bsr_matrix((J.reshape(-1, bs, bs), col, rowptr), shape=(n * bs, n * bs)).tocsc()
+        dx = spl.spsolve(A, -R.ravel()).reshape(x.shape)
+        x += dx
+        if np.linalg.norm(dx) <= tol * np.linalg.norm(x):
+            break
+    return x
+
+
+def _kovasznay(n, Re=40.0):
+    """Kovasznay's steady Navier-Stokes flow on [-0.5, 1.5] x [-0.5, 0.5]
+    (2n x n cells): v = (1 - e^(lam x) cos 2 pi y, lam/(2 pi) e^(lam x) sin 2 pi y),
+    p = (1 - e^(2 lam x))/2, lam = Re/2 - sqrt(Re^2/4 + 4 pi^2), rho = 1,
+    mu = 1/Re, no body force; exact velocity on the boundary, p pinned at a
+    corner.  dt = 1e6 makes the time step a steady solve."""
+    xyz, conn, grid = W.box_mesh(2, (2 * n, n), lo=(-0.5, -0.5), hi=(1.5, 0.5))
+    lam = Re / 2 - math.sqrt(Re * Re / 4 + 4 * math.pi ** 2)
+    x, y = xyz[:, 0], xyz[:, 1]
+    ex = np.zeros((xyz.shape[0], 3))
+    ex[:, 0] = 1 - np.exp(lam * x) * np.cos(2 * math.pi * y)
+    ex[:, 1] = lam / (2 * math.pi) * np.exp(lam * x) * np.sin(2 * math.pi * y)
+    ex[:, 2] = 0.5 * (1 - np.exp(2 * lam * x))
+    lo, hi = xyz.min(0), xyz.max(0)
+    bnd = np.zeros(xyz.shape[0], bool)
+    for k in range(2):
+        bnd |= (np.abs(xyz[:, k] - lo[k]) < 1e-12) | (np.abs(xyz[:, k] - hi[k]) < 1e-12)
+    nodes = np.nonzero(bnd)[0].astype(np.int32)
+    mask = np.full(nodes.shape[0], 0b011, np.uint8)
+    mask[nodes == 0] |= 0b100
+    N = xyz.shape[0]
+    prob = W.Problem(name="kovasznay", dim=2, xyz=xyz, conn=conn, grid=grid, dir_node=nodes, dir_mask=mask,
+                     dir_val=ex[nodes].copy(), phases=[W.Phase(W.PHASE_FLUID, 0, 1.0, 1.0 / Re)], g=np.zeros(3),
+                     params=W.Params(dt=1e6), vp=ex.copy(), vdot=np.zeros((N, 2)), phi=np.zeros((0, N)),
+                     phidot=np.zeros((0, N)), B=np.zeros((0, N, 3)), Bdot=np.zeros((0, N, 3)))
+    return prob, ex
+
+
+def test_ns_manufactured_pressure_and_velocity_rates():
+    """Eq. PG_NS (with the tau_m/tau_c stabilization) on Kovasznay's exact
+    flow: the pressure error falls at least as h^1.5 and the velocity error
+    close to h^2 (n = 16, 32, 64)."""
+    ev, ep = [], []
+    for n in (16, 32, 64):
+        prob, ex = _kovasznay(n)
+        c = O.Case(prob)
+        lvl = prob.state_copy()
+
+        def asm(vp):
+            it = {"vp": vp, "phi": lvl["phi"], "B": lvl["B"]}
+            return c.ns_assemble(lvl, it)
+
+        vp = _newton(asm, lvl["vp"], 3, c.graph())
+        dv = vp[:, :2] - ex[:, :2]
+        dp = (vp[:, 2] - vp[:, 2].mean()) - (ex[:, 2] - ex[:, 2].mean())
+        ev.append(math.sqrt((dv ** 2).sum(1).mean()))
+        ep.append(math.sqrt((dp ** 2).mean()))
+    rp = [math.log2(ep[i - 1] / ep[i]) for i in (1, 2)]
+    rv = [math.log2(ev[i - 1] / ev[i]) for i in (1, 2)]
+    assert min(rp) >= 1.5, (ep, rp)
+    assert rv[-1] >= 1.8 and min(rv) >= 1.6, (ev, rv)
+
+
+def _ac_strip(n, eps, U, dt, steps, gamma, x0, phi0, phid0):
+    """Allen-Cahn (eq. PPV_AC) on a strip of n x 2 cells with the prescribed
+    velocity (U, 0) and mobility gamma: `steps` generalized-alpha steps
+    (rho_inf = 0), each to Newton convergence.  Returns phi."""
+    xyz, conn, grid = W.box_mesh(2, (n, 2), hi=(1.0, 2.0 / n))
+    N = xyz.shape[0]
+    prob = W.Problem(name="ac", dim=2, xyz=xyz, conn=conn, grid=grid, dir_node=np.zeros(0, np.int32),
+                     dir_mask=np.zeros(0, np.uint8), dir_val=np.zeros((0, 3)),
+                     phases=[W.Phase(W.PHASE_FLUID, 0, 1.0, 1.0), W.Phase(W.PHASE_FLUID, 1, 1.0, 1.0)],
+                     g=np.zeros(3), params=W.Params(dt=dt, eps=eps), vp=np.zeros((N, 3)), vdot=np.zeros((N, 2)),
+                     phi=np.zeros((1, N)), phidot=np.zeros((1, N)), B=np.zeros((0, N, 3)), Bdot=np.zeros((0, N, 3)))
+    c = O.Case(prob)
+    x = xyz[:, 0]
+    phi, phid = phi0(x), phid0(x)
+    va = np.zeros((N, 2))
+    va[:, 0] = U
+    allE, allN = np.ones(prob.n_elems, np.uint8), np.ones(N, np.uint8)
+    for _ in range(steps):
+        pn, pdn = phi.copy(), phid.copy()
+
+        def asm(it):
+            fa, fd = O.level_values(0.0, dt, pn, pdn, it)
+            return c.ac_assemble(va, fa, fd, gamma, c.beta(fa, allE), allE, allN)
+
+        phi = _newton(asm, pn, 1, c.graph())
+        phid = pdn + (phi - pn - dt * pdn) / dt   # the update formula with varsigma = 1
+    return x, phi
+
+
+def test_ac_manufactured_rates():
+    """Eq. PPV_AC with a forced mobility: (1) at rest, the discrete
+    equilibrium converges to the exact tanh profile (eps^2 phi'' = F'(phi),
+    beta = 0) at O(h^2); (2) advected by a prescribed uniform velocity at a
+    fixed Courant number, the profile translates with an error falling at
+    least as h^2."""
+    eps = 0.025
+    s2e = math.sqrt(2.0) * eps
+    errs = []
+    for n in (48, 96, 192):
+        x, phi = _ac_strip(n, eps, 0.0, 1e6, 1, 1.0, 0.5, lambda x: np.tanh((x - 0.5) / (1.3 * s2e)),
+                           lambda x: np.zeros_like(x))
+        errs.append(math.sqrt(((phi - np.tanh((x - 0.5) / s2e)) ** 2).mean()))
+    r = [math.log2(errs[i - 1] / errs[i]) for i in (1, 2)]
+    assert min(r) >= 1.9, (errs, r)
+    U, T, x0 = 1.0, 0.3, 0.35
+    errs = []
+    for n in (96, 192, 384):
+        steps = int(round(T / (0.5 / n)))
+        x, phi = _ac_strip(n, eps, U, T / steps, steps, 1.0, x0, lambda x: np.tanh((x - x0) / s2e),
+                           lambda x: -U * (1 - np.tanh((x - x0) / s2e) ** 2) / s2e)
+        errs.append(math.sqrt(((phi - np.tanh((x - x0 - U * T) / s2e)) ** 2).mean()))
+    r = [math.log2(errs[i - 1] / errs[i]) for i in (1, 2)]
+    assert min(r) >= 1.9, (errs, r)
+
+
+def test_band_truncation_decays_with_halo():
+    """The grid-cell band is a definition, not an exact restriction: the
+    consistent mass, the eps^2 diffusion and the SUPG coupling tie band-edge
+    rows to the flat region outside.  Its difference to the full-domain
+    transport must fall geometrically with every added halo layer (one mesh
+    cell per grid cell here), by at least 3x per layer for phi and B."""
+    prob = W.cavity_disk_2d(n=48)
+    over = dict(nl_fixed=2, lin_rtol=1e-14, restart=300, lin_maxit=20000, band_cell=1)
+    full = prob.state_copy()
+    O.Case(prob, band_flat=-1.0, **over).step(full)
+    d = []
+    for halo in (1, 2, 3, 4):
+        st = prob.state_copy()
+        O.Case(prob, band_halo=halo, **over).step(st)
+        d.append([np.linalg.norm(st[k] - full[k]) / np.linalg.norm(full[k]) for k in ("phi", "B")])
+    d = np.array(d)
+    assert d[0, 0] > 1e-7 and d[0, 1] > 1e-7, d   # the band does truncate
+    ratio = d[:-1] / d[1:]
+    assert (ratio >= 3.0).all(), (d, ratio)
