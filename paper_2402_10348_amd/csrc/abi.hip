@@ -93,7 +93,7 @@ void free_all(eft_ctx *ctx)
     fr(ctx->xyz); fr(ctx->conn); fr(ctx->epos); fr(ctx->iptr); fr(ctx->ient); fr(ctx->cell_of); fr(ctx->dir_node); fr(ctx->dir_mask); fr(ctx->fmask0);
     fr(ctx->dir_val); fr(ctx->phase_tab); fr(ctx->ind_of_phase);
     fr(ctx->J.rowptr); fr(ctx->J.col); fr(ctx->J.diag); fr(ctx->J.val); fr(ctx->J.val32);
-    fr(ctx->va); fr(ctx->acc); fr(ctx->rho); fr(ctx->mu); fr(ctx->as); fr(ctx->Ba); fr(ctx->R); fr(ctx->dx);
+    fr(ctx->va); fr(ctx->acc); fr(ctx->rho); fr(ctx->mu); fr(ctx->smask); fr(ctx->solid_ind_d); fr(ctx->R); fr(ctx->dx);
     fr(ctx->l_vp); fr(ctx->l_vdot); fr(ctx->l_phi); fr(ctx->l_phidot); fr(ctx->l_B); fr(ctx->l_Bdot);
     eft_band_free(ctx);
     fr(ctx->seed); fr(ctx->active); fr(ctx->nin); fr(ctx->nout); fr(ctx->ein); fr(ctx->g2b); fr(ctx->gpos2b);
@@ -401,8 +401,12 @@ eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *
     EFT_TRY(dalloc(ctx, &ctx->acc, N * d));
     EFT_TRY(dalloc(ctx, &ctx->rho, N));
     EFT_TRY(dalloc(ctx, &ctx->mu, N));
-    EFT_TRY(dalloc(ctx, &ctx->as, N * std::max(ctx->n_s, 1)));
-    EFT_TRY(dalloc(ctx, &ctx->Ba, N * nv * std::max(ctx->n_s, 1)));
+    EFT_TRY(dalloc(ctx, &ctx->smask, N));
+    {
+        std::vector<int32_t> si(std::max(ctx->n_s, 1), 0);
+        for (int s = 0; s < ctx->n_s; ++s) si[s] = ctx->solid_ind[s];
+        EFT_TRY(upload(ctx, &ctx->solid_ind_d, si.data(), (int64_t)si.size()));
+    }
     EFT_TRY(dalloc(ctx, &ctx->R, N * mx));
     EFT_TRY(dalloc(ctx, &ctx->dx, N * mx));
     EFT_TRY(dalloc(ctx, &ctx->l_vp, N * bs));

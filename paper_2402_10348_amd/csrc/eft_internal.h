@@ -83,6 +83,7 @@ struct MeshView {
     const int32_t *conn = nullptr, *epos = nullptr;
     const double *xyz = nullptr;
     const double *va = nullptr, *acc = nullptr, *rho = nullptr, *mu = nullptr, *as = nullptr, *Ba = nullptr;
+    const uint64_t *smask = nullptr;                 // [N] bit s: solid s has a non-zero fraction at the node
     int64_t n_dir = 0;
     const int32_t *dir_node = nullptr;
     const uint8_t *dir_mask = nullptr;
@@ -102,6 +103,7 @@ struct MGLevel {
     int maxc = 0, rpb = 1;
     double *xyz = nullptr;
     double *va = nullptr, *acc = nullptr, *rho = nullptr, *mu = nullptr, *as = nullptr, *Ba = nullptr;
+    uint64_t *smask = nullptr;       // [N] solids present at each node (injected from the fine level)
     double *vp = nullptr, *R = nullptr;
     int64_t n_dir = 0;
     int32_t *dir_node = nullptr;
@@ -197,8 +199,12 @@ struct eft_ctx {
     eft_matrix J;
     double *va = nullptr, *acc = nullptr;      // [N][d]
     double *rho = nullptr, *mu = nullptr;      // [N]
-    double *as = nullptr;                      // [n_s][N]
-    double *Ba = nullptr;                      // [n_s][N][nv]
+    uint64_t *smask = nullptr;                 // [N] bit s: solid s has a non-zero fraction at the node
+    int32_t *solid_ind_d = nullptr;            // [n_s] indicator of each solid (device)
+    // the level-n and iterate arrays eft_props last read: the element kernels
+    // compute solid fractions and B at n+alpha from them for the solids
+    // present, instead of reading full per-solid arrays
+    const double *src_lphi = nullptr, *src_iphi = nullptr, *src_lB = nullptr, *src_iB = nullptr;
     double *R = nullptr, *dx = nullptr;        // [N][max(bs,nv)]
     // level-n copies used by eft_step
     double *l_vp = nullptr, *l_vdot = nullptr, *l_phi = nullptr, *l_phidot = nullptr, *l_B = nullptr,

@@ -29,9 +29,18 @@ struct PropsArgs {
     const int32_t *solid_ind;   // [n_s] indicator of each solid
     const double *l_vp, *l_vdot, *it_vp;
     const double *l_phi, *it_phi;
-    const double *l_B, *it_B;
-    double *va, *acc, *rho, *mu, *as, *Ba;
+    double *va, *acc, *rho, *mu;
+    uint64_t *smask;            // [N] bit s set where solid s has a non-zero fraction
 };
+
+// Fraction of the phase of an order parameter at n+alpha (reading 2: nodal
+// clamp of (1 + phi)/2), from phi^n and the iterate.  Every kernel that needs
+// a solid fraction evaluates this same expression, so they agree bit for bit.
+__device__ __forceinline__ double phase_fraction(double fn, double f1, double alpha)
+{
+    const double fa = fn + alpha * (f1 - fn);
+    return fmin(fmax(0.5 * (1.0 + fa), 0.0), 1.0);
+}
 
 template <int D>
 __global__ __launch_bounds__(256) void k_props(PropsArgs a)
@@ -70,16 +79,14 @@ __global__ __launch_bounds__(256) void k_props(PropsArgs a)
     }
     a.rho[p] = r;
     a.mu[p] = m;
+    uint64_t sm = 0;
     for (int s = 0; s < a.n_s; ++s) {
         const int k = a.solid_ind[s];
-        const double fn = a.l_phi[(int64_t)k * a.N + p], f1 = a.it_phi[(int64_t)k * a.N + p];
-        const double fa = fn + a.alpha * (f1 - fn);
-        a.as[(int64_t)s * a.N + p] = fmin(fmax(0.5 * (1.0 + fa), 0.0), 1.0);
-        for (int c = 0; c < NVv; ++c) {
-            const int64_t o = ((int64_t)s * a.N + p) * NVv + c;
-            a.Ba[o] = a.l_B[o] + a.alpha * (a.it_B[o] - a.l_B[o]);
-        }
+        const double al = phase_fraction(a.l_phi[(int64_t)k * a.N + p], a.it_phi[(int64_t)k * a.N + p], a.alpha);
+        if (al != 0.0) sm |= (uint64_t)1 << s;
     }
+    a.smask[p] = sm;
+    (void)NVv;
 }
 
 // ------------------------------------------------------ row-owned kernel --
@@ -98,7 +105,12 @@ struct RowArgs {
     const int32_t *conn, *epos, *rowptr;
     const double *xyz, *va, *acc, *vp, *rho, *mu;
     int n_s;
-    const double *as, *Ba, *muL;
+    const double *as, *Ba, *muL;   // per-solid fraction and B at n+alpha ([n_s][N], [n_s][N][nv]), or null:
+    const uint64_t *smask;         // [N] solids present at each node
+    // with as = null the fractions and B at n+alpha of the present solids are
+    // evaluated from phi^n, phi, B^n, B (solid s: order parameter solid_ind[s])
+    const double *lphi, *iphi, *lB, *iB;
+    const int32_t *solid_ind;
     double ct, alpha, kappa, dt, C_I, g0, g1, g2;
     double *R;
     float *J32;      // optional FP32 copy of the values
@@ -311,21 +323,35 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
         // solid: with W_b = int N_b alpha mu_L, M = int alpha mu_L B and
         // D_k = (dB/dx_k) grad N_a, block (a, b) gains
         //   alpha kappa (-W_b D_k[i] + dN_a[k] (M grad N_b)_i + delta_ik grad N_a . M grad N_b)
-        for (int sI = 0; sI < a.n_s; ++sI) {
+        uint64_t present = 0;
+        if (a.n_s > 0)
+#pragma unroll
+            for (int b = 0; b < NN; ++b) present |= a.smask[nd[b]];
+        while (present) {   // the solids present on the element, in increasing order
+            const int sI = __ffsll((unsigned long long)present) - 1;
+            present &= present - 1;
             double asn[NN];
-            bool any = false;
-#pragma unroll
-            for (int b = 0; b < NN; ++b) {
-                asn[b] = a.as[(int64_t)sI * a.N + nd[b]];
-                any |= asn[b] != 0.0;
-            }
-            if (!any) continue;
-            const double muL = a.muL[sI];
             double Bn[NN][NVv];
+            if (a.as) {
 #pragma unroll
-            for (int b = 0; b < NN; ++b)
+                for (int b = 0; b < NN; ++b) {
+                    asn[b] = a.as[(int64_t)sI * a.N + nd[b]];
 #pragma unroll
-                for (int c = 0; c < NVv; ++c) Bn[b][c] = a.Ba[((int64_t)sI * a.N + nd[b]) * NVv + c];
+                    for (int c = 0; c < NVv; ++c) Bn[b][c] = a.Ba[((int64_t)sI * a.N + nd[b]) * NVv + c];
+                }
+            } else {
+                const int64_t ko = (int64_t)a.solid_ind[sI] * a.N;
+#pragma unroll
+                for (int b = 0; b < NN; ++b) {
+                    asn[b] = phase_fraction(a.lphi[ko + nd[b]], a.iphi[ko + nd[b]], a.alpha);
+#pragma unroll
+                    for (int c = 0; c < NVv; ++c) {
+                        const int64_t o = ((int64_t)sI * a.N + nd[b]) * NVv + c;
+                        Bn[b][c] = a.lB[o] + a.alpha * (a.iB[o] - a.lB[o]);
+                    }
+                }
+            }
+            const double muL = a.muL[sI];
             double Wbs[NN], M2[D][D];
 #pragma unroll
             for (int b = 0; b < NN; ++b) Wbs[b] = 0.0;
@@ -480,20 +506,21 @@ eft_status eft_props(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it)
     a.dt = ga.dt;
     a.tab = ctx->phase_tab;
     a.ind_of_phase = ctx->ind_of_phase;
-    a.solid_ind = ctx->ind_of_phase + EFT_MAX_PHASE;
     a.l_vp = lvl->vp;
     a.l_vdot = lvl->vdot;
     a.it_vp = it->vp;
     a.l_phi = lvl->phi;
     a.it_phi = it->phi;
-    a.l_B = lvl->B;
-    a.it_B = it->B;
     a.va = ctx->va;
     a.acc = ctx->acc;
     a.rho = ctx->rho;
     a.mu = ctx->mu;
-    a.as = ctx->as;
-    a.Ba = ctx->Ba;
+    a.smask = ctx->smask;
+    a.solid_ind = ctx->solid_ind_d;
+    ctx->src_lphi = lvl->phi;
+    ctx->src_iphi = it->phi;
+    ctx->src_lB = lvl->B;
+    ctx->src_iB = it->B;
     const int nb = eft_grid(ctx->N, 256);
     if (ctx->dim == 2)
         hipLaunchKernelGGL(k_props<2>, dim3(nb), dim3(256), 0, ctx->stream, a);
@@ -505,7 +532,7 @@ eft_status eft_props(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it)
 
 
 // Residual and Jacobian of the momentum/mass block at the iterate (the
-// node fields va, acc, rho, mu, as, Ba must be current, see eft_props).
+// node fields va, acc, rho, mu and the solid mask must be current, see eft_props).
 // Residual and Jacobian of the momentum/mass block on one mesh level (the
 // node fields of the view must be current).
 eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, double *R, eft_matrix *J, float *J32,
@@ -538,6 +565,12 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
     a.n_s = ctx->n_s;
     a.as = M.as;
     a.Ba = M.Ba;
+    a.smask = M.smask;
+    a.lphi = ctx->src_lphi;
+    a.iphi = ctx->src_iphi;
+    a.lB = ctx->src_lB;
+    a.iB = ctx->src_iB;
+    a.solid_ind = ctx->solid_ind_d;
     a.muL = ctx->phase_tab + 5 * EFT_MAX_PHASE;  // mu_L of each solid
     a.ct = gq.ct;
     a.alpha = gq.alpha;
@@ -581,7 +614,7 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
 }
 
 // Residual and Jacobian of the momentum/mass block at the iterate (the node
-// fields va, acc, rho, mu, as, Ba must be current, see eft_props); with a
+// fields va, acc, rho, mu and the solid mask must be current, see eft_props); with a
 // Jacobian, the multigrid levels are refreshed too.
 eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_matrix *J)
 {
@@ -595,8 +628,9 @@ eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_ma
     M.acc = ctx->acc;
     M.rho = ctx->rho;
     M.mu = ctx->mu;
-    M.as = ctx->as;
-    M.Ba = ctx->Ba;
+    M.as = nullptr;   // (fractions and B at n+alpha from the arrays eft_props read)
+    M.Ba = nullptr;
+    M.smask = ctx->smask;
     M.n_dir = ctx->n_dir;
     M.dir_node = ctx->dir_node;
     M.dir_mask = ctx->dir_mask;

@@ -64,9 +64,14 @@ template <> struct Stencil<2> {
 struct InjArgs {
     int64_t Nc, Nf;
     int d, bs, nv, n_s;
+    double alpha;
     const int32_t *inj;
-    const double *va, *acc, *rho, *mu, *as, *Ba, *vp;
+    const double *va, *acc, *rho, *mu, *vp;
+    const uint64_t *smask;
+    const double *lphi, *iphi, *lB, *iB;   // fine level: phi^n, phi, B^n, B (fractions and B at n+alpha)
+    const int32_t *solid_ind;
     double *cva, *cacc, *crho, *cmu, *cas, *cBa, *cvp;
+    uint64_t *csmask;
 };
 
 __global__ __launch_bounds__(256) void k_inject(InjArgs a)
@@ -81,9 +86,23 @@ __global__ __launch_bounds__(256) void k_inject(InjArgs a)
     for (int i = 0; i < a.bs; ++i) a.cvp[I * a.bs + i] = a.vp[f * a.bs + i];
     a.crho[I] = a.rho[f];
     a.cmu[I] = a.mu[f];
+    const uint64_t sm = a.n_s > 0 ? a.smask[f] : 0;
+    if (a.n_s > 0) a.csmask[I] = sm;
     for (int s = 0; s < a.n_s; ++s) {
-        a.cas[(int64_t)s * a.Nc + I] = a.as[(int64_t)s * a.Nf + f];
-        for (int c = 0; c < a.nv; ++c) a.cBa[((int64_t)s * a.Nc + I) * a.nv + c] = a.Ba[((int64_t)s * a.Nf + f) * a.nv + c];
+        // (fraction and B at n+alpha: the expressions of the fine level)
+        const bool on = (sm >> s) & 1;
+        const int64_t k = a.solid_ind[s];
+        double al = 0.0;
+        if (on) {
+            const double fn = a.lphi[k * a.Nf + f], f1 = a.iphi[k * a.Nf + f];
+            const double fa = fn + a.alpha * (f1 - fn);
+            al = fmin(fmax(0.5 * (1.0 + fa), 0.0), 1.0);
+        }
+        a.cas[(int64_t)s * a.Nc + I] = al;
+        for (int c = 0; c < a.nv; ++c) {
+            const int64_t o = ((int64_t)s * a.Nf + f) * a.nv + c;
+            a.cBa[((int64_t)s * a.Nc + I) * a.nv + c] = a.lB[o] + a.alpha * (a.iB[o] - a.lB[o]);
+        }
     }
 }
 
@@ -890,6 +909,7 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
         EFT_TRY(dmal(ctx, &C.mu, C.N));
         EFT_TRY(dmal(ctx, &C.as, C.N * std::max(ctx->n_s, 1)));
         EFT_TRY(dmal(ctx, &C.Ba, C.N * nv * std::max(ctx->n_s, 1)));
+        EFT_TRY(dmal(ctx, &C.smask, C.N));
         EFT_TRY(dmal(ctx, &C.vp, C.N * bs));
         EFT_TRY(dmal(ctx, &C.R, C.N * bs));
         EFT_TRY(dmal(ctx, &C.Dinv, C.N * bs * bs));
@@ -958,7 +978,7 @@ void eft_mg_free(eft_ctx *ctx)
         MGLevel &L = ctx->mg[l];
         if (l > 0) {
             fr(L.conn); fr(L.epos); fr(L.inj); fr(L.xyz); fr(L.va); fr(L.acc); fr(L.rho); fr(L.mu); fr(L.as);
-            fr(L.Ba); fr(L.vp); fr(L.R); fr(L.dir_node); fr(L.dir_mask); fr(L.A.rowptr); fr(L.A.col); fr(L.A.diag);
+            fr(L.Ba); fr(L.smask); fr(L.vp); fr(L.R); fr(L.dir_node); fr(L.dir_mask); fr(L.A.rowptr); fr(L.A.col); fr(L.A.diag);
             fr(L.A.val); fr(L.b); fr(L.iptr); fr(L.ient);
         }
         fr(L.fmask); fr(L.Dinv); fr(L.Dinv32); fr(L.x); fr(L.x2); fr(L.r); fr(L.A.val32); fr(L.A.val16);
@@ -1052,8 +1072,13 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
         a.acc = ctx->acc;
         a.rho = ctx->rho;
         a.mu = ctx->mu;
-        a.as = ctx->as;
-        a.Ba = ctx->Ba;
+        a.alpha = ga_of(ctx->par.rho_inf, ctx->par.dt).alpha;
+        a.smask = ctx->smask;
+        a.lphi = ctx->src_lphi;
+        a.iphi = ctx->src_iphi;
+        a.lB = ctx->src_lB;
+        a.iB = ctx->src_iB;
+        a.solid_ind = ctx->solid_ind_d;
         a.vp = vp;
         a.cva = C.va;
         a.cacc = C.acc;
@@ -1062,6 +1087,7 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
         a.cas = C.as;
         a.cBa = C.Ba;
         a.cvp = C.vp;
+        a.csmask = C.smask;
         hipLaunchKernelGGL(k_inject, dim3(eft_grid(C.N, 256)), dim3(256), 0, ctx->stream, a);
         EFT_HIP(hipGetLastError());
         MeshView M;
@@ -1076,6 +1102,7 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
         M.mu = C.mu;
         M.as = C.as;
         M.Ba = C.Ba;
+        M.smask = C.smask;
         M.n_dir = C.n_dir;
         M.dir_node = C.dir_node;
         M.dir_mask = C.dir_mask;

@@ -637,7 +637,7 @@ __global__ __launch_bounds__(256, 3) void k_ac_rows(TrArgs a, double eps, const 
 }
 
 template <int D>
-__global__ __launch_bounds__(256, 2) void k_b_rows(TrArgs a, const double *afr /*[N]*/)
+__global__ __launch_bounds__(256, 2) void k_b_rows(TrArgs a, const double *lphi /*[N]*/, const double *iphi)
 {
     extern __shared__ double lds[];
     constexpr int NN = D + 1, NQ = Rule<D>::NQ, NVv = NV<D>::v;
@@ -695,7 +695,10 @@ __global__ __launch_bounds__(256, 2) void k_b_rows(TrArgs a, const double *afr /
                     X[b][i] = a.xyz[n * D + i];
                     v[b][i] = a.va[n * D + i];
                 }
-                am[b] = afr[n];
+                // the solid's fraction at n+alpha (the same expression as the
+                // momentum assembly's): clamp((1 + phi_a)/2, 0, 1)
+                const double fn = lphi[n], fa = fn + al * (iphi[n] - fn);
+                am[b] = fmin(fmax(0.5 * (1.0 + fa), 0.0), 1.0);
             }
             double dN[NN][D], G[D][D];
             const double vol = simplex_geom<D>(X, dN, G);
@@ -1287,12 +1290,13 @@ static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_itera
     if (B.n > 0) {
         const int bp = ctx->dim == 2 ? BAcc<2>::P : BAcc<3>::P;
         const size_t shm = (size_t)a.rpb * ((size_t)a.maxc * bp + (nv | 1)) * sizeof(double);
+        const int64_t ko = (int64_t)ctx->solid_ind[s] * N;
         if (ctx->dim == 2)
             hipLaunchKernelGGL(k_b_rows<2>, dim3(eft_grid(B.n, a.rpb)), dim3(256), shm, ctx->stream, a,
-                               ctx->as + (int64_t)s * N);
+                               lvl->phi + ko, it->phi + ko);
         else
             hipLaunchKernelGGL(k_b_rows<3>, dim3(eft_grid(B.n, a.rpb)), dim3(256), shm, ctx->stream, a,
-                               ctx->as + (int64_t)s * N);
+                               lvl->phi + ko, it->phi + ko);
     }
     EFT_HIP(hipGetLastError());
     return EFT_OK;
@@ -1412,9 +1416,9 @@ eft_status eft_transport_dev(eft_ctx *ctx, const eft_state *lvl, eft_iterate *it
         inf.ac_iters = si.iters;
         for (int k = 0; k < K; ++k) inf.lin_iters[k] = ctx->band[k].n > 0 ? si.iters : 0;
     }
-    // every B system (solid fractions from the new phi), one batched solve
+    // every B system (solid fractions from the new phi, evaluated by the
+    // assembly), one batched solve
     if (S > 0 && ctx->u_b.n > 0) {
-        EFT_TRY(eft_props(ctx, lvl, it));
         const eft_ctx::BandUnion &U = ctx->u_b;
         for (int sI = 0; sI < S; ++sI)
             if (ctx->band[ctx->solid_ind[sI]].n > 0)
