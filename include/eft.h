@@ -124,6 +124,10 @@ typedef struct {
                                     sweeps from z = 0 (1..8; 1 with band_omega = 1
                                     is plain point-block Jacobi)                    */
     double band_omega;           /* damping of those sweeps (0 < omega <= 1.5)      */
+    int32_t mg_galerkin;         /* multigrid coarse operators: 0 rediscretized (the
+                                    element kernels on node fields injected from
+                                    the fine mesh), 1 Galerkin products P^T A P of
+                                    the fine operator with the V-cycle's transfers */
     int32_t nn_maxit;            /* learned preconditioner: Krylov iterations of
                                     one momentum solve after which the rest of the
                                     solve uses block Jacobi, its fallback
@@ -233,6 +237,16 @@ eft_status eft_matrix_export(eft_ctx *ctx, const eft_matrix *A, int32_t *rowptr,
  * its solves use point-block Jacobi (the multigrid hierarchy is built by the
  * assembly).  For solving other systems of the same pattern, and tests. */
 eft_status eft_matrix_import(eft_ctx *ctx, eft_matrix *A, const double *val);
+
+/* Multigrid hierarchy of the momentum/mass preconditioner (test hook):
+ * level 0 is the mesh itself; level l has cells of 2^l mesh cells.  With
+ * null buffers: *levels, and for level `level` (when valid) its rows n and
+ * pattern size nnzb.  Otherwise copies the level's pattern and operator into
+ * DEVICE buffers rowptr [n+1], col [nnzb], val [nnzb][bs][bs] (FP64; FP32
+ * levels are widened; level 0 gives the FP64 Jacobian).  The operators are
+ * those of the last assembly.  EFT_EINVAL without a hierarchy. */
+eft_status eft_mg_export(eft_ctx *ctx, int32_t level, int32_t *levels, int64_t *n, int64_t *nnzb, int32_t *rowptr,
+                         int32_t *col, double *val);
 
 /* (a) Momentum/mass residual R [N][d+1] (FP64) and Jacobian J of eq. (PG_NS)
  * at the iterate, with the elastic tangent of eq. (Bext), Dirichlet rows
@@ -352,8 +366,9 @@ eft_status eft_init_phase(eft_ctx *ctx, const eft_surface *surf, double eps, con
 eft_status eft_step(eft_ctx *ctx, eft_state *st, double dt, eft_step_info *info);
 
 /* ---- Autotuner of the solver's run-time knobs (not part of the method).
- * The multigrid sweep counts before/after the coarse correction, its damping
- * and smoother kind (Jacobi or multicolour Gauss-Seidel), and the sweeps and
+ * The multigrid sweep counts before/after the coarse correction, its damping,
+ * smoother kind (Jacobi or multicolour Gauss-Seidel) and coarse operators
+ * (rediscretized or Galerkin), and the sweeps and
  * damping of the band systems' preconditioner are chosen by measurement: on
  * the state st (as the first nonlinear iteration of a step sees it) the
  * momentum/mass system is assembled once and solved once per candidate, and
@@ -376,6 +391,7 @@ typedef struct {
     double band_best_seconds;
     int32_t mg_nu, mg_nu_post, mg_smoother;
     double mg_omega;
+    int32_t mg_galerkin;
     int32_t band_sweeps;
     double band_omega;
 } eft_tune_info;

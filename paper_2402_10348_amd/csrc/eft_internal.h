@@ -249,6 +249,7 @@ struct eft_ctx {
     std::vector<MGLevel> mg;
     double *mg_dense = nullptr, *mg_inv = nullptr;   // coarsest level [nd][nd] over its free dofs
     int32_t *mg_fidx = nullptr, *mg_free = nullptr;  // dof -> free index, free index -> dof
+    int32_t *mg_miss = nullptr;                      // Galerkin product found no slot (consistency flag)
     int64_t mg_nd = 0;
     bool mg_f32_fresh = false;   // the finest level's FP32 or BF16 copy was written by the assembly
     bool mg_valid = false;       // the hierarchy belongs to the Jacobian now in J (set by eft_mg_setup)

@@ -13,6 +13,7 @@
 // the equal-order stabilized system; the coarsest level is inverted exactly.
 // Dirichlet dofs are removed from the coarse space (masked in transfer).
 #include <algorithm>
+#include <type_traits>
 
 #include "bsr_rows.h"
 #include "dev_common.h"
@@ -445,6 +446,110 @@ __global__ __launch_bounds__(256) void k_prolong(Dims cd, Dims fd, const uint8_t
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= (fd.n[0] + 1) * (fd.n[1] + 1) * (fd.n[2] + 1)) return;
     prolong_node<D>(cd, fd, cmask, fmask, xc, x, f);
+}
+
+// ------------------------------------------------ Galerkin coarsening ----
+//
+// A_c = P^T A_f P with the transfers of the V-cycle: P interpolates linearly
+// on the nested Kuhn meshes (weights 1 and 1/2), masked on the Dirichlet
+// dofs of both levels, so that coarse block (I, J) sums
+//   w(i, I) w(j, J) M_f(i) A_f(i, j) M_f(j)
+// over the fine nodes i of I's star (2I + s, s in the Kuhn stencil) and the
+// columns j of row i whose parents J (the coarse node at j, or the two ends
+// of the coarse edge j is the midpoint of) lie in row I; then coarse masks,
+// unit rows for Dirichlet dofs of the coarse level.  One wavefront per coarse
+// row; its blocks accumulate in LDS (FP64); the pattern of row I is the
+// coarse mesh's (the product of P1 spaces of nested meshes stays within it).
+struct RapArgs {
+    Dims cd, fd;
+    int64_t nc;
+    const int32_t *frow, *fcol, *crow, *ccol;
+    const uint8_t *fmask, *cmask;
+    int32_t *miss;          // set when a contribution had no slot (never expected)
+};
+
+template <int D, typename TF, typename TC>
+__global__ __launch_bounds__(256) void k_rap_rows(RapArgs a, const TF *__restrict__ fval, TC *__restrict__ cval,
+                                                  uint16_t *__restrict__ cval16)
+{
+    constexpr int BS = D + 1, B2 = BS * BS, BP = B2 | 1, S = Stencil<D>::S, MAXC = Stencil<D>::S;
+    __shared__ double acc[4][MAXC * BP];
+    __shared__ int32_t ccol[4][MAXC];
+    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int64_t I = (int64_t)blockIdx.x * 4 + w;
+    const bool live = I < a.nc;
+    const int nxc = a.cd.n[0] + 1, nyc = a.cd.n[1] + 1;
+    int clen = 0;
+    int64_t c0 = 0;
+    if (live) {
+        c0 = a.crow[I];
+        clen = a.crow[I + 1] - (int)c0;
+        if (lane < clen) ccol[w][lane] = a.ccol[c0 + lane];
+    }
+    for (int t = lane; t < MAXC * BP; t += 64) acc[w][t] = 0.0;
+    __syncthreads();
+    if (live) {
+        const int ci = (int)(I % nxc), cj = (int)((I / nxc) % nyc), ck = D == 3 ? (int)(I / ((int64_t)nxc * nyc)) : 0;
+        const int nxf = a.fd.n[0] + 1, nyf = a.fd.n[1] + 1;
+        for (int t = lane; t < S * MAXC; t += 64) {
+            const int s = t / MAXC, kk = t % MAXC;
+            int o0, o1, o2;
+            Stencil<D>::off(s, o0, o1, o2);
+            const int fi = 2 * ci + o0, fj = 2 * cj + o1, fk = 2 * ck + o2;
+            if (fi < 0 || fj < 0 || fk < 0 || fi > a.fd.n[0] || fj > a.fd.n[1] || (D == 3 && fk > a.fd.n[2])) continue;
+            const int64_t i = node_id(a.fd, fi, fj, fk);
+            const int64_t k = a.frow[i] + kk;
+            if (k >= a.frow[i + 1]) continue;
+            const int mi = a.fmask[i];
+            if (mi == 0) continue;
+            const int64_t j = a.fcol[k];
+            const int mj = a.fmask[j];
+            if (mj == 0) continue;
+            const double wi = s == 0 ? 1.0 : 0.5;
+            // parents of j: the coarse node at j, or the ends of its coarse edge
+            const int gi = (int)(j % nxf), gj = (int)((j / nxf) % nyf), gk = D == 3 ? (int)(j / ((int64_t)nxf * nyf)) : 0;
+            const int odd = (gi & 1) | (gj & 1) | (gk & 1);
+            const int64_t J0 = node_id(a.cd, gi >> 1, gj >> 1, gk >> 1);
+            const int64_t J1 = odd ? node_id(a.cd, (gi >> 1) + (gi & 1), (gj >> 1) + (gj & 1), (gk >> 1) + (gk & 1)) : -1;
+            const double wj = odd ? 0.5 : 1.0;
+            double blk[B2];
+            const TF *src = fval + k * B2;
+#pragma unroll
+            for (int r = 0; r < BS; ++r)
+#pragma unroll
+                for (int c = 0; c < BS; ++c)
+                    blk[r * BS + c] = (((mi >> r) & 1) && ((mj >> c) & 1)) ? wi * wj * (double)src[r * BS + c] : 0.0;
+#pragma unroll
+            for (int par = 0; par < 2; ++par) {
+                const int64_t J = par == 0 ? J0 : J1;
+                if (J < 0) continue;
+                int q = -1;
+                for (int u = 0; u < clen; ++u)
+                    if (ccol[w][u] == J) q = u;
+                if (q < 0) {
+                    *a.miss = 1;
+                    continue;
+                }
+                double *dst = &acc[w][q * BP];
+#pragma unroll
+                for (int e = 0; e < B2; ++e)
+                    if (blk[e] != 0.0) atomicAdd(dst + e, blk[e]);
+            }
+        }
+    }
+    __syncthreads();
+    if (!live) return;
+    const int mI = a.cmask[I];
+    for (int t = lane; t < clen * B2; t += 64) {
+        const int q = t / B2, e = t % B2, r = e / BS, c = e % BS;
+        const int64_t J = ccol[w][q];
+        const int mJ = a.cmask[J];
+        double v;
+        if (!((mI >> r) & 1)) v = (J == I && r == c) ? 1.0 : 0.0;   // Dirichlet dof: unit row
+        else v = ((mJ >> c) & 1) ? acc[w][q * BP + e] : 0.0;
+        cval[(c0 + q) * B2 + e] = (TC)v;
+        if (cval16) cval16[(c0 + q) * B2 + e] = to_bf16_rne((float)v);
+    }
 }
 
 // -------------------------------------------------------- coarsest level --
@@ -937,6 +1042,8 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
         EFT_TRY(dmal(ctx, &C.A.val16, C.A.nnzb * bs * bs));
         EFT_TRY(dmal(ctx, &C.Dinv32, C.N * bs * bs));
     }
+    EFT_TRY(dmal(ctx, &ctx->mg_miss, 1));
+    EFT_HIP(hipMemset(ctx->mg_miss, 0, sizeof(int32_t)));
     MGLevel &F0 = ctx->mg[0];
     F0.A.bs = bs;
     F0.A.n = ctx->N;
@@ -989,7 +1096,8 @@ void eft_mg_free(eft_ctx *ctx)
     fr(ctx->mg_inv);
     fr(ctx->mg_fidx);
     fr(ctx->mg_free);
-    ctx->mg_fidx = ctx->mg_free = nullptr;
+    fr(ctx->mg_miss);
+    ctx->mg_fidx = ctx->mg_free = ctx->mg_miss = nullptr;
     ctx->mg_dense = ctx->mg_inv = nullptr;
     ctx->mg_nd = 0;
 }
@@ -1058,7 +1166,46 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
         ctx->mg_f32_fresh = false;
         EFT_TRY(eft_bj_setup32(ctx, &F0.A, F0.Dinv32));
     }
-    for (int64_t l = 1; l < L; ++l) {
+    for (int64_t l = 1; l < L && ctx->par.mg_galerkin; ++l) {
+        // Galerkin coarse operator from the level above
+        MGLevel &C = ctx->mg[l];
+        const MGLevel &F = ctx->mg[l - 1];
+        C.A.bf16 = C.A.fp32 && ctx->par.mg_bf16 != 0;
+        RapArgs ra;
+        ra.cd = dims_of(C);
+        ra.fd = dims_of(F);
+        ra.nc = C.N;
+        ra.frow = F.A.rowptr;
+        ra.fcol = F.A.col;
+        ra.crow = C.A.rowptr;
+        ra.ccol = C.A.col;
+        ra.fmask = F.fmask;
+        ra.cmask = C.fmask;
+        ra.miss = ctx->mg_miss;
+        const dim3 g(eft_grid(C.N, 4)), t(256);
+        uint16_t *c16 = C.A.bf16 ? C.A.val16 : nullptr;
+        auto launch = [&](auto fv) {
+            using TF = std::remove_cv_t<std::remove_pointer_t<decltype(fv)>>;
+            if (ctx->dim == 2) {
+                if (C.A.fp32) hipLaunchKernelGGL((k_rap_rows<2, TF, float>), g, t, 0, ctx->stream, ra, fv, C.A.val32, c16);
+                else hipLaunchKernelGGL((k_rap_rows<2, TF, double>), g, t, 0, ctx->stream, ra, fv, C.A.val, c16);
+            } else {
+                if (C.A.fp32) hipLaunchKernelGGL((k_rap_rows<3, TF, float>), g, t, 0, ctx->stream, ra, fv, C.A.val32, c16);
+                else hipLaunchKernelGGL((k_rap_rows<3, TF, double>), g, t, 0, ctx->stream, ra, fv, C.A.val, c16);
+            }
+        };
+        if (l == 1) {
+            if (ctx->J.fp32) launch((const float *)ctx->J.val32);
+            else launch((const double *)ctx->J.val);
+        } else {
+            if (F.A.fp32) launch((const float *)F.A.val32);
+            else launch((const double *)F.A.val);
+        }
+        EFT_HIP(hipGetLastError());
+        if (C.A.fp32) EFT_TRY(eft_bj_setup32(ctx, &C.A, C.Dinv32));
+        else EFT_TRY(eft_bj_setup(ctx, &C.A, C.Dinv));
+    }
+    for (int64_t l = 1; l < L && !ctx->par.mg_galerkin; ++l) {
         MGLevel &C = ctx->mg[l];
         InjArgs a;
         a.Nc = C.N;
@@ -1370,5 +1517,42 @@ eft_status eft_mg_vcycle(eft_ctx *ctx, const double *b0, double *z, const int32_
     EFT_HIP(hipGetLastError());
     if (x != z)
         EFT_HIP(hipMemcpyAsync(z, x, sizeof(double) * L0.N * ctx->bs, hipMemcpyDeviceToDevice, ctx->stream));
+    return EFT_OK;
+}
+
+namespace {
+__global__ void k_widen32(const float *a, double *b, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (double)a[i];
+}
+}  // namespace
+
+extern "C" eft_status eft_mg_export(eft_ctx *ctx, int32_t level, int32_t *levels, int64_t *n, int64_t *nnzb,
+                                    int32_t *rowptr, int32_t *col, double *val)
+{
+    if (!ctx) return EFT_EINVAL;
+    if (levels) *levels = (int32_t)ctx->mg.size();
+    if (ctx->mg.size() < 2 || level < 0 || level >= (int)ctx->mg.size()) {
+        ctx->err = "no multigrid level " + std::to_string(level);
+        return EFT_EINVAL;
+    }
+    const MGLevel &L = ctx->mg[level];
+    const eft_matrix &A = level == 0 ? ctx->J : L.A;
+    if (n) *n = A.n;
+    if (nnzb) *nnzb = A.nnzb;
+    if (rowptr) EFT_HIP(hipMemcpyAsync(rowptr, A.rowptr, sizeof(int32_t) * (A.n + 1), hipMemcpyDeviceToDevice, ctx->stream));
+    if (col) EFT_HIP(hipMemcpyAsync(col, A.col, sizeof(int32_t) * A.nnzb, hipMemcpyDeviceToDevice, ctx->stream));
+    const int64_t nv = A.nnzb * A.bs * A.bs;
+    if (val) {
+        if (A.fp32) {
+            hipLaunchKernelGGL(k_widen32, dim3((int)std::min<int64_t>(8192, (nv + 255) / 256)), dim3(256), 0,
+                               ctx->stream, A.val32, val, nv);
+            EFT_HIP(hipGetLastError());
+        } else {
+            EFT_HIP(hipMemcpyAsync(val, A.val, sizeof(double) * nv, hipMemcpyDeviceToDevice, ctx->stream));
+        }
+    }
+    EFT_HIP(hipStreamSynchronize(ctx->stream));
     return EFT_OK;
 }

@@ -45,13 +45,14 @@ __global__ void k_negate_copy(const double *a, double *b, int64_t n)
 struct Knobs {
     int mg_nu, mg_nu_post, mg_smoother;
     double mg_omega;
+    int mg_galerkin;
     int band_sweeps;
     double band_omega;
 };
 
 Knobs knobs_of(const eft_params &p)
 {
-    return Knobs{p.mg_nu, p.mg_nu_post, p.mg_smoother, p.mg_omega, p.band_sweeps, p.band_omega};
+    return Knobs{p.mg_nu, p.mg_nu_post, p.mg_smoother, p.mg_omega, p.mg_galerkin, p.band_sweeps, p.band_omega};
 }
 
 void set_knobs(eft_params &p, const Knobs &k)
@@ -60,6 +61,7 @@ void set_knobs(eft_params &p, const Knobs &k)
     p.mg_nu_post = k.mg_nu_post;
     p.mg_smoother = k.mg_smoother;
     p.mg_omega = k.mg_omega;
+    p.mg_galerkin = k.mg_galerkin;
     p.band_sweeps = k.band_sweeps;
     p.band_omega = k.band_omega;
 }
@@ -67,15 +69,18 @@ void set_knobs(eft_params &p, const Knobs &k)
 std::string knobs_text(const Knobs &k)
 {
     char b[256];
-    std::snprintf(b, sizeof b, "mg_nu=%d mg_nu_post=%d mg_smoother=%d mg_omega=%.6g band_sweeps=%d band_omega=%.6g",
-                  k.mg_nu, k.mg_nu_post, k.mg_smoother, k.mg_omega, k.band_sweeps, k.band_omega);
+    std::snprintf(b, sizeof b,
+                  "mg_nu=%d mg_nu_post=%d mg_smoother=%d mg_omega=%.6g mg_galerkin=%d band_sweeps=%d band_omega=%.6g",
+                  k.mg_nu, k.mg_nu_post, k.mg_smoother, k.mg_omega, k.mg_galerkin, k.band_sweeps, k.band_omega);
     return b;
 }
 
 bool parse_knobs(const std::string &s, Knobs &k)
 {
-    return std::sscanf(s.c_str(), "mg_nu=%d mg_nu_post=%d mg_smoother=%d mg_omega=%lf band_sweeps=%d band_omega=%lf",
-                       &k.mg_nu, &k.mg_nu_post, &k.mg_smoother, &k.mg_omega, &k.band_sweeps, &k.band_omega) == 6;
+    return std::sscanf(s.c_str(),
+                       "mg_nu=%d mg_nu_post=%d mg_smoother=%d mg_omega=%lf mg_galerkin=%d band_sweeps=%d band_omega=%lf",
+                       &k.mg_nu, &k.mg_nu_post, &k.mg_smoother, &k.mg_omega, &k.mg_galerkin, &k.band_sweeps,
+                       &k.band_omega) == 7;
 }
 
 std::string tune_key(eft_ctx *ctx)
@@ -138,6 +143,7 @@ extern "C" eft_status eft_tune(eft_ctx *ctx, const eft_state *st, const char *ca
         inf.mg_nu_post = best.mg_nu_post;
         inf.mg_smoother = best.mg_smoother;
         inf.mg_omega = best.mg_omega;
+        inf.mg_galerkin = best.mg_galerkin;
         inf.band_sweeps = best.band_sweeps;
         inf.band_omega = best.band_omega;
         if (info) *info = inf;
@@ -231,15 +237,32 @@ extern "C" eft_status eft_tune(eft_ctx *ctx, const eft_state *st, const char *ca
         };
         const int pre[] = {1, 2, 4, 6, 8};
         const int post[] = {2, 4, 8, 12, 16};
-        for (int a : pre)
-            for (int c : post) {
-                if (c < a) continue;
-                Knobs k = best;
-                k.mg_smoother = 0;
-                k.mg_nu = a;
-                k.mg_nu_post = c;
-                TUNE_TRY(consider(k));
+        // both kinds of coarse operators; switching rebuilds the hierarchy
+        // (the assembly's set-up of the multigrid levels) before the timings
+        const int gal0 = entry.mg_galerkin;
+        for (int gi = 0; gi < 2; ++gi) {
+            const int gal = gi == 0 ? gal0 : 1 - gal0;
+            if (gal != ctx->par.mg_galerkin) {
+                ctx->par.mg_galerkin = gal;
+                TUNE_TRY(eft_ns_kernels(ctx, &it, ctx->R, &ctx->J));
+                TUNE_TRY(hipStreamSynchronize(ctx->stream) == hipSuccess ? EFT_OK : EFT_EDEVICE);
             }
+            for (int a : pre)
+                for (int c : post) {
+                    if (c < a) continue;
+                    Knobs k = best;
+                    k.mg_galerkin = gal;
+                    k.mg_smoother = 0;
+                    k.mg_nu = a;
+                    k.mg_nu_post = c;
+                    TUNE_TRY(consider(k));
+                }
+        }
+        // the hierarchy of the best candidate's coarse operators
+        if (best.mg_galerkin != ctx->par.mg_galerkin) {
+            ctx->par.mg_galerkin = best.mg_galerkin;
+            TUNE_TRY(eft_ns_kernels(ctx, &it, ctx->R, &ctx->J));
+        }
         for (double om : {0.65, 0.85}) {
             Knobs k = best;
             k.mg_omega = om;
@@ -255,16 +278,24 @@ extern "C" eft_status eft_tune(eft_ctx *ctx, const eft_state *st, const char *ca
         }
         // confirm against the entry settings with a second timing of both
         if (!(best.mg_nu == entry.mg_nu && best.mg_nu_post == entry.mg_nu_post &&
-              best.mg_smoother == entry.mg_smoother && best.mg_omega == entry.mg_omega)) {
+              best.mg_smoother == entry.mg_smoother && best.mg_omega == entry.mg_omega &&
+              best.mg_galerkin == entry.mg_galerkin)) {
             int i1 = 0, i2 = 0;
             const double t1 = time_solve(best, maxit0, &i1);
-            const double t2 = time_solve(entry, maxit0, &i2);
+            double t2 = t_entry;
+            if (entry.mg_galerkin == best.mg_galerkin) t2 = time_solve(entry, maxit0, &i2);
+            else i2 = it_entry;
             if (stt != EFT_OK) return fail(stt);
             if (!(t1 > 0.0) || (t2 > 0.0 && t2 <= t1)) {
+                if (best.mg_galerkin != entry.mg_galerkin) {
+                    ctx->par.mg_galerkin = entry.mg_galerkin;
+                    TUNE_TRY(eft_ns_kernels(ctx, &it, ctx->R, &ctx->J));
+                }
                 best.mg_nu = entry.mg_nu;
                 best.mg_nu_post = entry.mg_nu_post;
                 best.mg_smoother = entry.mg_smoother;
                 best.mg_omega = entry.mg_omega;
+                best.mg_galerkin = entry.mg_galerkin;
                 t_best = t2;
                 it_best = i2;
             } else {
@@ -336,6 +367,7 @@ extern "C" eft_status eft_tune(eft_ctx *ctx, const eft_state *st, const char *ca
     inf.mg_nu_post = best.mg_nu_post;
     inf.mg_smoother = best.mg_smoother;
     inf.mg_omega = best.mg_omega;
+    inf.mg_galerkin = best.mg_galerkin;
     inf.band_sweeps = best.band_sweeps;
     inf.band_omega = best.band_omega;
     if (info) *info = inf;

@@ -46,7 +46,8 @@ class Params(C.Structure):
                 ("precision", C.c_int32), ("band_flat", C.c_double), ("band_cell", C.c_int32),
                 ("band_halo", C.c_int32), ("mg_nu", C.c_int32), ("mg_omega", C.c_double),
                 ("mg_bf16", C.c_int32), ("mg_nu_post", C.c_int32), ("mg_smoother", C.c_int32),
-                ("band_sweeps", C.c_int32), ("band_omega", C.c_double), ("nn_maxit", C.c_int32),
+                ("band_sweeps", C.c_int32), ("band_omega", C.c_double), ("mg_galerkin", C.c_int32),
+                ("nn_maxit", C.c_int32),
                 ("band_reserve", C.c_double)]
 
 
@@ -82,7 +83,8 @@ class TuneInfo(C.Structure):
                 ("best_seconds", C.c_double), ("default_iters", C.c_int32), ("best_iters", C.c_int32),
                 ("band_default_seconds", C.c_double), ("band_best_seconds", C.c_double),
                 ("mg_nu", C.c_int32), ("mg_nu_post", C.c_int32), ("mg_smoother", C.c_int32),
-                ("mg_omega", C.c_double), ("band_sweeps", C.c_int32), ("band_omega", C.c_double)]
+                ("mg_omega", C.c_double), ("mg_galerkin", C.c_int32), ("band_sweeps", C.c_int32),
+                ("band_omega", C.c_double)]
 
 
 class KernelTime(C.Structure):
@@ -93,7 +95,8 @@ EXPORTS = ["eft_create", "eft_destroy", "eft_last_error", "eft_set_params", "eft
            "eft_matrix_export", "eft_matrix_import", "eft_assemble", "eft_spmv", "eft_fgmres", "eft_fgmres_noalloc", "eft_bands_build", "eft_band_export",
            "eft_band_system", "eft_transport_solids", "eft_step", "eft_tune", "eft_time_kernel",
            "eft_kernel_time_read", "eft_nn_init", "eft_nn_shape", "eft_nn_params", "eft_nn_harvest", "eft_nn_train",
-           "eft_nn_loss_grad", "eft_nn_apply", "eft_center_of_mass", "eft_track_particles", "eft_init_phase"]
+           "eft_nn_loss_grad", "eft_nn_apply", "eft_center_of_mass", "eft_track_particles", "eft_init_phase",
+           "eft_mg_export"]
 
 _lib = None
 
@@ -132,7 +135,7 @@ def params_struct(p, **over):
                 lin_maxit=p.lin_maxit, precond=p.precond, precision=p.precision, band_flat=p.band_flat,
                 band_cell=p.band_cell, band_halo=p.band_halo, mg_nu=p.mg_nu, mg_omega=p.mg_omega,
                 mg_bf16=p.mg_bf16, mg_nu_post=p.mg_nu_post, mg_smoother=p.mg_smoother,
-                band_sweeps=p.band_sweeps, band_omega=p.band_omega, nn_maxit=p.nn_maxit, band_reserve=p.band_reserve)
+                band_sweeps=p.band_sweeps, band_omega=p.band_omega, mg_galerkin=p.mg_galerkin, nn_maxit=p.nn_maxit, band_reserve=p.band_reserve)
     vals.update(over)
     P = Params()
     for k, v in vals.items():
@@ -256,7 +259,7 @@ class Context:
         cp = cache_path.encode() if cache_path else None
         self._check(self.L.eft_tune(self.ctx, C.byref(S), C.c_char_p(cp) if cp else None, C.c_int32(budget),
                                     C.byref(out)))
-        for k in ("mg_nu", "mg_nu_post", "mg_smoother", "mg_omega", "band_sweeps", "band_omega"):
+        for k in ("mg_nu", "mg_nu_post", "mg_smoother", "mg_omega", "mg_galerkin", "band_sweeps", "band_omega"):
             setattr(self.params, k, getattr(out, k))
         return {f[0]: getattr(out, f[0]) for f in TuneInfo._fields_}
 
@@ -341,6 +344,20 @@ class Context:
     def matrix_import(self, val):
         """Overwrite the context matrix's values with val [nnzb][bs][bs] (device FP64)."""
         self._check(self.L.eft_matrix_import(self.ctx, self.J, _ptr(val.contiguous())))
+
+    def mg_level(self, level):
+        """(rowptr, col, val[nnzb][bs][bs]) of multigrid level `level` (device
+        tensors, FP64) and the number of levels."""
+        t = self.torch
+        nl, n, nnz = C.c_int32(), C.c_int64(), C.c_int64()
+        self._check(self.L.eft_mg_export(self.ctx, C.c_int32(level), C.byref(nl), C.byref(n), C.byref(nnz),
+                                         None, None, None))
+        rowptr = t.empty(n.value + 1, dtype=t.int32, device=self.dev)
+        col = t.empty(nnz.value, dtype=t.int32, device=self.dev)
+        val = t.empty((nnz.value, self.bs, self.bs), dtype=t.float64, device=self.dev)
+        self._check(self.L.eft_mg_export(self.ctx, C.c_int32(level), None, None, None, _ptr(rowptr), _ptr(col),
+                                         _ptr(val)))
+        return rowptr, col, val, nl.value
 
     def spmv(self, x, y=None):
         if y is None:

@@ -168,6 +168,7 @@ class Params:
     mg_smoother: int = 0      # 0 damped block Jacobi, 1 multicolour block Gauss-Seidel
     band_sweeps: int = 2      # Allen-Cahn and B systems: damped block-Jacobi sweeps from zero
     band_omega: float = 0.6   # below 2 / 2.5: P1 consistent mass has lambda_max(D^-1 M) <= 2.5
+    mg_galerkin: int = 0       # multigrid coarse operators: 0 rediscretized, 1 Galerkin P^T A P
     nn_maxit: int = 0          # learned preconditioner: iterations before block Jacobi takes over (0: lin_maxit/2)
     band_reserve: float = 0.0  # band storage for all indicators together, in mesh element counts (0: auto)
 
