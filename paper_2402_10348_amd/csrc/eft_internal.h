@@ -236,6 +236,10 @@ struct eft_ctx {
     double *bval = nullptr;                      // band matrix values [cap_nnz][nv*nv]
     double *bcmp = nullptr;                      // B blocks in compact form [cap_nnz][1 + dim^2]
     double *bdiag = nullptr;                     // B systems: diagonal blocks [cap_n][nv^2] by union row
+    void *hmem = nullptr, *dmem = nullptr;       // member descriptors and unit tables of the batched
+                                                 // transport launches (pinned host, device)
+    double *tpart = nullptr;                     // partial sums of the batched mobility / beta
+    int64_t tpart_cap = 0;
     int32_t *iota = nullptr;                     // [cap_n]: i (diagonal index of bdiag)
     double *tnum = nullptr, *tden = nullptr;     // mobility projection sums [cap_n]
     // reductions and host mirror

@@ -346,6 +346,14 @@ __global__ __launch_bounds__(256) void k_sum2(const double *part, int nb, double
     }
 }
 
+// ------------------------------------- mobility and beta, all indicators --
+//
+// The same arithmetic as k_mob_elem, k_mob_node and k_beta_elem for every
+// indicator in one launch each: work units are the single-indicator
+// launches' blocks, their partial sums land in one array, and k_seg_sum2
+// adds each indicator's partials in the single-indicator order.  (The
+// member descriptors are declared with the band-system kernels below.)
+
 // ---------------------------------------------- band systems, row-owned ----
 //
 // Same organization as the momentum assembly: a workgroup owns a block of
@@ -372,6 +380,198 @@ struct TrArgs {
                      // blocks, into Jd (one per band row)
     double *Jd;      // B systems, full_b = 0: diagonal blocks [n][nv*nv] by band row
 };
+
+// What differs between the members of a batched launch (the band systems of
+// the indicators, or of the solids): the band, the field, the outputs.
+struct MemberDesc {
+    int64_t n;                                  // band rows
+    const int32_t *node, *brow, *bcol;
+    const uint8_t *fre, *eflag;
+    const double *lx, *ldx, *ix;                // the member's field: level value, level rate, iterate
+    double *R, *J, *Jc, *Jd;
+    const double *gb;                           // Allen-Cahn: gamma, beta
+    const double *lphi, *iphi;                  // B: the solid's order parameter (level, iterate)
+    int64_t ne;                                 // band elements
+    const int32_t *elem, *bconn;                // band elements, their band-local nodes
+    int64_t noff;                               // first pool node of the band (mobility sums)
+};
+
+__device__ __forceinline__ void apply_member(TrArgs &a, const MemberDesc &m)
+{
+    a.n = m.n;
+    a.node = m.node;
+    a.brow = m.brow;
+    a.bcol = m.bcol;
+    a.fre = m.fre;
+    a.eflag = m.eflag;
+    a.lx = m.lx;
+    a.ldx = m.ldx;
+    a.ix = m.ix;
+    a.R = m.R;
+    a.J = m.J;
+    a.Jc = m.Jc;
+    a.Jd = m.Jd;
+}
+
+// member m with off[m] <= u < off[m + 1] (off ascending, off[0] = 0)
+__device__ __forceinline__ int member_of(const int32_t *__restrict__ off, int nmem, int u)
+{
+    int lo = 0, hi = nmem - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= u) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_mob_elem_all(int64_t ne_tot, const int32_t *__restrict__ eoff, int nmem,
+                                                      const MemberDesc *__restrict__ mem, const int32_t *conn,
+                                                      const double *xyz, const double *va, double alpha, double *num,
+                                                      double *den)
+{
+    const int64_t bg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (bg >= ne_tot) return;
+    const int m = member_of(eoff, nmem, (int)bg);
+    const MemberDesc &M = mem[m];
+    const int64_t be = bg - eoff[m];
+    constexpr int NN = D + 1;
+    const int64_t e = M.elem[be];
+    double X[NN][D], v[NN][D], f[NN];
+#pragma unroll
+    for (int a = 0; a < NN; ++a) {
+        const int64_t g = conn[e * NN + a];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            X[a][i] = xyz[g * D + i];
+            v[a][i] = va[g * D + i];
+        }
+        f[a] = M.lx[g] + alpha * (M.ix[g] - M.lx[g]);
+    }
+    double dN[NN][D], G[D][D];
+    const double vol = simplex_geom<D>(X, dN, G);
+    double gf[D], L[D][D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        double sg = 0.0;
+#pragma unroll
+        for (int a = 0; a < NN; ++a) sg += f[a] * dN[a][j];
+        gf[j] = sg;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double t = 0.0;
+#pragma unroll
+            for (int a = 0; a < NN; ++a) t += v[a][i] * dN[a][j];
+            L[i][j] = t;
+        }
+    }
+    double g2 = 0.0, gLg = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        g2 += gf[i] * gf[i];
+#pragma unroll
+        for (int j = 0; j < D; ++j) gLg += gf[i] * L[i][j] * gf[j];
+    }
+    const double q = g2 > 0.0 ? gLg / g2 : 0.0;
+    const double share = vol * Rule<D>::WF * (Rule<D>::QA + (Rule<D>::NQ - 1) * Rule<D>::QB);
+#pragma unroll
+    for (int a = 0; a < NN; ++a) {
+        const int64_t l = M.noff + M.bconn[be * NN + a];
+        unsafeAtomicAdd(num + l, q * share);
+        unsafeAtomicAdd(den + l, share);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mob_node_all(const int32_t *__restrict__ uoff, int nmem,
+                                                      const MemberDesc *__restrict__ mem, double alpha, double cut,
+                                                      const double *num, const double *den, double *part)
+{
+    __shared__ double lds[4];
+    const int u = blockIdx.x;
+    const int m = member_of(uoff, nmem, u);
+    const MemberDesc &M = mem[m];
+    const int64_t r = (int64_t)(u - uoff[m]) * blockDim.x + threadIdx.x;
+    double sq = 0.0, c = 0.0;
+    if (r < M.n) {
+        const int g = M.node[r];
+        const double f = M.lx[g] + alpha * (M.ix[g] - M.lx[g]);
+        if (fabs(f) <= cut) {
+            const double nu = num[M.noff + r], de = den[M.noff + r];
+            const double Q = fabs(de > 0.0 ? nu / de : 0.0);
+            sq = Q * Q;
+            c = 1.0;
+        }
+    }
+    sq = block_sum<256>(sq, lds);
+    c = block_sum<256>(c, lds);
+    if (threadIdx.x == 0) {
+        part[2 * u] = sq;
+        part[2 * u + 1] = c;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_beta_elem_all(const int32_t *__restrict__ uoff, int nmem,
+                                                       const MemberDesc *__restrict__ mem, const int32_t *conn,
+                                                       const double *xyz, double alpha, double *part)
+{
+    __shared__ double lds[4];
+    const int u = blockIdx.x;
+    const int m = member_of(uoff, nmem, u);
+    const MemberDesc &M = mem[m];
+    const int64_t be = (int64_t)(u - uoff[m]) * blockDim.x + threadIdx.x;
+    constexpr int NN = D + 1, NQ = Rule<D>::NQ;
+    double sn = 0.0, sd = 0.0;
+    if (be < M.ne) {
+        const int64_t e = M.elem[be];
+        double X[NN][D], f[NN];
+#pragma unroll
+        for (int a = 0; a < NN; ++a) {
+            const int64_t g = conn[e * NN + a];
+#pragma unroll
+            for (int i = 0; i < D; ++i) X[a][i] = xyz[g * D + i];
+            f[a] = M.lx[g] + alpha * (M.ix[g] - M.lx[g]);
+        }
+        double dN[NN][D], G[D][D];
+        const double w = simplex_geom<D>(X, dN, G) * Rule<D>::WF;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            double fq = 0.0;
+#pragma unroll
+            for (int a = 0; a < NN; ++a) fq += shape_at<D>(q, a) * f[a];
+            sn += w * (fq * fq * fq - fq);
+            sd += w * 0.5 * fabs(fq * fq - 1.0);
+        }
+    }
+    sn = block_sum<256>(sn, lds);
+    sd = block_sum<256>(sd, lds);
+    if (threadIdx.x == 0) {
+        part[2 * u] = sn;
+        part[2 * u + 1] = sd;
+    }
+}
+
+// out[m * stride + 0..1] = the sums of member m's (pair) partials
+// part[2u], part[2u + 1], u in [uoff[m], uoff[m+1]), in the order of k_sum2
+__global__ __launch_bounds__(256) void k_seg_sum2(const double *part, const int32_t *__restrict__ uoff, double *out,
+                                                  int stride)
+{
+    __shared__ double lds[4];
+    const int m = blockIdx.x;
+    const int u0 = uoff[m], nb = uoff[m + 1] - u0;
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) {
+        a += part[2 * (u0 + i)];
+        b += part[2 * (u0 + i) + 1];
+    }
+    a = block_sum<256>(a, lds);
+    b = block_sum<256>(b, lds);
+    if (threadIdx.x == 0) {
+        out[m * stride] = a;
+        out[m * stride + 1] = b;
+    }
+}
 
 template <int BS>
 __device__ __forceinline__ void band_rows_out(const TrArgs &a, int64_t r0, int64_t r1, const double *accJ,
@@ -492,11 +692,10 @@ __device__ __forceinline__ void band_rows_out_b(const TrArgs &a, int64_t r0, int
 }
 
 template <int D>
-__global__ __launch_bounds__(256, 3) void k_ac_rows(TrArgs a, double eps, const double *gb /* gamma, beta */)
+__device__ __forceinline__ void ac_rows_unit(const TrArgs &a, int64_t r0, double eps, const double *gb,
+                                             double *lds)
 {
-    extern __shared__ double lds[];
     constexpr int NN = D + 1, NQ = Rule<D>::NQ;
-    const int64_t r0 = (int64_t)blockIdx.x * a.rpb;
     const int64_t r1 = r0 + a.rpb < a.n ? r0 + a.rpb : a.n;
     double *accJ = lds, *accR = lds + (int64_t)a.rpb * a.maxc;
     for (int t = threadIdx.x; t < a.rpb * (a.maxc + 1); t += blockDim.x) lds[t] = 0.0;
@@ -637,9 +836,34 @@ __global__ __launch_bounds__(256, 3) void k_ac_rows(TrArgs a, double eps, const 
 }
 
 template <int D>
-__global__ __launch_bounds__(256, 2) void k_b_rows(TrArgs a, const double *lphi /*[N]*/, const double *iphi)
+__global__ __launch_bounds__(256, 3) void k_ac_rows(TrArgs a, double eps, const double *gb /* gamma, beta */)
 {
     extern __shared__ double lds[];
+    ac_rows_unit<D>(a, (int64_t)blockIdx.x * a.rpb, eps, gb, lds);
+}
+
+// All Allen-Cahn systems in one launch: a grid-stride loop over work units
+// (blocks of rpb rows of one member), the member found from the units'
+// prefix offsets; every unit is the single-member kernel's workgroup.
+template <int D>
+__global__ __launch_bounds__(256, 3) void k_ac_rows_all(TrArgs a, double eps, const MemberDesc *__restrict__ mem,
+                                                        const int32_t *__restrict__ uoff, int nmem)
+{
+    extern __shared__ double lds[];
+    const int total = uoff[nmem];
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int m = member_of(uoff, nmem, u);
+        TrArgs am = a;
+        apply_member(am, mem[m]);
+        ac_rows_unit<D>(am, (int64_t)(u - uoff[m]) * a.rpb, eps, mem[m].gb, lds);
+        __syncthreads();
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void b_rows_unit(const TrArgs &a, int64_t r0, const double *lphi, const double *iphi,
+                                            double *lds)
+{
     constexpr int NN = D + 1, NQ = Rule<D>::NQ, NVv = NV<D>::v;
     // A block of the tangent is s1 I - LE(M) with M = sum over elements of
     // s2 L_e (LE linear in its argument, see below), so each block
@@ -647,7 +871,6 @@ __global__ __launch_bounds__(256, 2) void k_b_rows(TrArgs a, const double *lphi 
     // 3D) and is expanded when written out.  LDS strides padded to an odd
     // number of doubles (bank conflicts).
     constexpr int BP = BAcc<D>::P, RP = NVv | 1;
-    const int64_t r0 = (int64_t)blockIdx.x * a.rpb;
     const int64_t r1 = r0 + a.rpb < a.n ? r0 + a.rpb : a.n;
     double *accJ = lds, *accR = lds + (int64_t)a.rpb * a.maxc * BP;
     for (int t = threadIdx.x; t < a.rpb * (a.maxc * BP + RP); t += blockDim.x) lds[t] = 0.0;
@@ -821,6 +1044,29 @@ __global__ __launch_bounds__(256, 2) void k_b_rows(TrArgs a, const double *lphi 
     band_rows_out_b<D>(a, r0, r1, accJ, accR);
 }
 
+template <int D>
+__global__ __launch_bounds__(256, 2) void k_b_rows(TrArgs a, const double *lphi /*[N]*/, const double *iphi)
+{
+    extern __shared__ double lds[];
+    b_rows_unit<D>(a, (int64_t)blockIdx.x * a.rpb, lphi, iphi, lds);
+}
+
+// All B systems in one launch (as k_ac_rows_all)
+template <int D>
+__global__ __launch_bounds__(256, 2) void k_b_rows_all(TrArgs a, const MemberDesc *__restrict__ mem,
+                                                       const int32_t *__restrict__ uoff, int nmem)
+{
+    extern __shared__ double lds[];
+    const int total = uoff[nmem];
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int m = member_of(uoff, nmem, u);
+        TrArgs am = a;
+        apply_member(am, mem[m]);
+        b_rows_unit<D>(am, (int64_t)(u - uoff[m]) * a.rpb, mem[m].lphi, mem[m].iphi, lds);
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(256) void k_negate(double *x, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -884,6 +1130,37 @@ __global__ __launch_bounds__(256) void k_scale_member(int64_t n, double *v, cons
 
 // ------------------------------------------------------------- host side --
 
+// slots of ctx->tsc: per-indicator sums (S, count, beta numerator and
+// denominator), gamma and beta per indicator, per-member squared norms
+constexpr int TS_SUM = 0, TS_GB = 4 * EFT_MAX_IND, TS_NRM = 6 * EFT_MAX_IND, TS_DN = TS_NRM + 128,
+              TS_XN = TS_DN + 128, TS_VMAX = TS_XN + 128;
+
+// Layout of the descriptor block (host pinned and device): the members of
+// the Allen-Cahn launch, then those of the B launch, then the int32 tables
+// (element offsets in the pool, node-block units, element-block units, row
+// units of the two launches), each EFT_MAX_IND + 1 long.
+constexpr int64_t MEM_DESC = 2 * EFT_MAX_IND;
+constexpr int64_t MEM_TAB = EFT_MAX_IND + 1;
+constexpr int64_t MEM_BYTES = MEM_DESC * (int64_t)sizeof(MemberDesc) + 5 * MEM_TAB * (int64_t)sizeof(int32_t);
+struct MemTabs {
+    MemberDesc *ac, *b;
+    int32_t *eoff, *unode, *uelem, *uac, *ub;
+};
+static MemTabs mem_tabs(void *base)
+{
+    MemTabs t;
+    t.ac = (MemberDesc *)base;
+    t.b = t.ac + EFT_MAX_IND;
+    t.eoff = (int32_t *)(t.b + EFT_MAX_IND);
+    t.unode = t.eoff + MEM_TAB;
+    t.uelem = t.unode + MEM_TAB;
+    t.uac = t.uelem + MEM_TAB;
+    t.ub = t.uac + MEM_TAB;
+    return t;
+}
+
+
+
 // Exclusive scan over n items of `in` (flags or counts), in two calls: the
 // count (returns the total through the host), then the writes (offsets out,
 // compacted indices idx, map), so that a caller can check the total against
@@ -941,6 +1218,12 @@ void eft_band_free(eft_ctx *ctx)
     }
     fr(ctx->bR); fr(ctx->bX); fr(ctx->tnum); fr(ctx->tden); fr(ctx->bval); fr(ctx->bcmp); fr(ctx->bdiag); fr(ctx->iota);
     fr(ctx->scan_tmp);
+    fr(ctx->dmem);
+    fr(ctx->tpart);
+    if (ctx->hmem) (void)hipHostFree(ctx->hmem);
+    ctx->hmem = ctx->dmem = nullptr;
+    ctx->tpart = nullptr;
+    ctx->tpart_cap = 0;
     ctx->bR = ctx->bX = ctx->tnum = ctx->tden = ctx->bval = ctx->bcmp = ctx->bdiag = nullptr;
     ctx->iota = nullptr;
     ctx->scan_tmp = nullptr;
@@ -1000,10 +1283,81 @@ eft_status eft_band_reserve(eft_ctx *ctx)
     EFT_TRY(tmal(ctx, &ctx->scan_tmp, nb + 1));
     ctx->scan_cap = nb + 1;
     hipLaunchKernelGGL(k_iota, dim3(eft_grid(P.cap_n, 256)), dim3(256), 0, ctx->stream, ctx->iota, P.cap_n);
+    // batched transport: member descriptors and unit tables, partial sums
+    if (hipHostMalloc(&ctx->hmem, MEM_BYTES, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(&ctx->dmem, MEM_BYTES) != hipSuccess) {
+        ctx->err = "out of memory (transport descriptors)";
+        return EFT_ENOMEM;
+    }
+    ctx->tpart_cap = 2 * (P.cap_n / 256 + P.cap_e / 256 + 4 * K + 64);
+    EFT_TRY(tmal(ctx, &ctx->tpart, ctx->tpart_cap));
     EFT_HIP(hipGetLastError());
     // the band unions are Krylov systems too: the Allen-Cahn union has up to
     // cap_n rows, the B union up to cap_n rows of nv
     EFT_TRY(eft_krylov_reserve(ctx, P.cap_n, nv, ctx->par.restart));
+    return EFT_OK;
+}
+
+// Descriptors of every Allen-Cahn member (indicator) and every B member
+// (solid) for the current bands and fields, uploaded in one copy.
+static eft_status upload_members(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, int rpb)
+{
+    const int K = ctx->n_ind, S = ctx->n_s, nv = ctx->nv, d2 = 1 + ctx->dim * ctx->dim;
+    const int64_t N = ctx->N;
+    MemTabs h = mem_tabs(ctx->hmem);
+    const BandPool &P = ctx->bp;
+    h.eoff[0] = h.unode[0] = h.uelem[0] = h.uac[0] = h.ub[0] = 0;
+    for (int k = 0; k < K; ++k) {
+        const Band &B = ctx->band[k];
+        MemberDesc &m = h.ac[k];
+        m = MemberDesc{};
+        m.n = B.n;
+        m.node = B.node;
+        m.brow = B.rowptr;
+        m.bcol = B.col;
+        m.fre = B.fre;
+        m.eflag = B.eflag;
+        m.lx = lvl->phi + (int64_t)k * N;
+        m.ldx = lvl->phidot + (int64_t)k * N;
+        m.ix = it->phi + (int64_t)k * N;
+        m.R = ctx->bR + ctx->u_ac.roff[k];
+        m.J = ctx->bval + ctx->u_ac.noff[k];
+        m.gb = ctx->tsc + TS_GB + 2 * k;
+        m.ne = B.ne;
+        m.elem = B.elem;
+        m.bconn = B.bconn_;
+        m.noff = B.node - P.node;
+        h.eoff[k + 1] = h.eoff[k] + (int32_t)B.ne;
+        h.unode[k + 1] = h.unode[k] + (int32_t)((B.n + 255) / 256);
+        h.uelem[k + 1] = h.uelem[k] + (int32_t)((B.ne + 255) / 256);
+        h.uac[k + 1] = h.uac[k] + (int32_t)((B.n + rpb - 1) / rpb);
+    }
+    for (int sI = 0; sI < S; ++sI) {
+        const int k = ctx->solid_ind[sI];
+        const Band &B = ctx->band[k];
+        MemberDesc &m = h.b[sI];
+        m = MemberDesc{};
+        m.n = B.n;
+        m.node = B.node;
+        m.brow = B.rowptr;
+        m.bcol = B.col;
+        m.fre = B.fre;
+        m.eflag = B.eflag;
+        m.lx = lvl->B + (int64_t)sI * N * nv;
+        m.ldx = lvl->Bdot + (int64_t)sI * N * nv;
+        m.ix = it->B + (int64_t)sI * N * nv;
+        m.R = ctx->bR + ctx->u_b.roff[sI] * nv;
+        m.Jc = ctx->bcmp + ctx->u_b.noff[sI] * d2;
+        m.Jd = ctx->bdiag + ctx->u_b.roff[sI] * nv * nv;
+        m.lphi = lvl->phi + (int64_t)k * N;
+        m.iphi = it->phi + (int64_t)k * N;
+        m.ne = B.ne;
+        m.elem = B.elem;
+        m.bconn = B.bconn_;
+        m.noff = B.node - P.node;
+        h.ub[sI + 1] = h.ub[sI] + (int32_t)((B.n + rpb - 1) / rpb);
+    }
+    EFT_HIP(hipMemcpyAsync(ctx->dmem, ctx->hmem, MEM_BYTES, hipMemcpyHostToDevice, ctx->stream));
     return EFT_OK;
 }
 
@@ -1143,10 +1497,7 @@ eft_status eft_bands_build_dev(eft_ctx *ctx, const double *phi_n)
     return EFT_OK;
 }
 
-// slots of ctx->tsc: per-indicator sums (S, count, beta numerator and
-// denominator), gamma and beta per indicator, per-member squared norms
-constexpr int TS_SUM = 0, TS_GB = 4 * EFT_MAX_IND, TS_NRM = 6 * EFT_MAX_IND, TS_DN = TS_NRM + 128,
-              TS_XN = TS_DN + 128, TS_VMAX = TS_XN + 128;
+
 
 // gamma and beta of every indicator at the iterate (eq. tdm-num with the RMS
 // over the diffuse region, and the multiplier of Sec. 2.2.1): the sums of all
@@ -1167,33 +1518,45 @@ static eft_status mobility_beta_all(eft_ctx *ctx, const eft_state *lvl, const ef
         hipLaunchKernelGGL(k_band_vmax, dim3(nb), dim3(256), 0, ctx->stream, ctx->bp.used_n, ctx->bp.node, it->vp,
                            ctx->bs, ctx->dim, (unsigned long long *)(ctx->tsc + TS_VMAX));
     }
-    for (int k = 0; k < K; ++k) {
-        const Band &B = ctx->band[k];
-        if (B.ne == 0) continue;
-        const double *lphi = lvl->phi + (int64_t)k * N, *iphi = it->phi + (int64_t)k * N;
-        EFT_TRY(eft_fill(ctx, ctx->tnum, B.n, 0.0));
-        EFT_TRY(eft_fill(ctx, ctx->tden, B.n, 0.0));
-        if (D == 2)
-            hipLaunchKernelGGL(k_mob_elem<2>, dim3(eft_grid(B.ne, 256)), dim3(256), 0, ctx->stream, B.ne, B.elem,
-                               B.bconn_, ctx->conn, ctx->xyz, ctx->va, lphi, iphi, ga.alpha, ctx->tnum, ctx->tden);
-        else
-            hipLaunchKernelGGL(k_mob_elem<3>, dim3(eft_grid(B.ne, 256)), dim3(256), 0, ctx->stream, B.ne, B.elem,
-                               B.bconn_, ctx->conn, ctx->xyz, ctx->va, lphi, iphi, ga.alpha, ctx->tnum, ctx->tden);
-        const int nbn = eft_grid(B.n, 256);
-        hipLaunchKernelGGL(k_mob_node, dim3(nbn), dim3(256), 0, ctx->stream, B.n, B.node, lphi, iphi, ga.alpha,
-                           ctx->par.di_cut, ctx->tnum, ctx->tden, ctx->red);
-        hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, ctx->stream, ctx->red, nbn, ctx->tsc + TS_SUM + 4 * k);
-        const int nbe = eft_grid(B.ne, 256);
-        if (D == 2)
-            hipLaunchKernelGGL(k_beta_elem<2>, dim3(nbe), dim3(256), 0, ctx->stream, B.ne, B.elem, ctx->conn, ctx->xyz,
-                               lphi, iphi, ga.alpha, ctx->red + 2 * (int64_t)nbn);
-        else
-            hipLaunchKernelGGL(k_beta_elem<3>, dim3(nbe), dim3(256), 0, ctx->stream, B.ne, B.elem, ctx->conn, ctx->xyz,
-                               lphi, iphi, ga.alpha, ctx->red + 2 * (int64_t)nbn);
-        hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, ctx->stream, ctx->red + 2 * (int64_t)nbn, nbe,
-                           ctx->tsc + TS_SUM + 4 * k + 2);
-        EFT_HIP(hipGetLastError());
+    // every indicator at once (the member descriptors hold each one's band
+    // and field; the sums land per indicator in the single-indicator order)
+    EFT_TRY(upload_members(ctx, lvl, it, std::min(ctx->rpb, 64)));
+    const MemTabs T = mem_tabs(ctx->dmem);
+    const MemTabs H = mem_tabs(ctx->hmem);
+    const int64_t ne_tot = H.eoff[K], nu_node = H.unode[K], nu_elem = H.uelem[K];
+    if (2 * std::max(nu_node, nu_elem) > ctx->tpart_cap) {
+        ctx->err = "transport partial-sum buffer too small";
+        return EFT_EINVAL;
     }
+    if (ctx->bp.used_n > 0) {
+        EFT_TRY(eft_fill(ctx, ctx->tnum, ctx->bp.used_n, 0.0));
+        EFT_TRY(eft_fill(ctx, ctx->tden, ctx->bp.used_n, 0.0));
+    }
+    if (ne_tot > 0) {
+        if (D == 2)
+            hipLaunchKernelGGL(k_mob_elem_all<2>, dim3(eft_grid(ne_tot, 256)), dim3(256), 0, ctx->stream, ne_tot,
+                               T.eoff, K, T.ac, ctx->conn, ctx->xyz, ctx->va, ga.alpha, ctx->tnum, ctx->tden);
+        else
+            hipLaunchKernelGGL(k_mob_elem_all<3>, dim3(eft_grid(ne_tot, 256)), dim3(256), 0, ctx->stream, ne_tot,
+                               T.eoff, K, T.ac, ctx->conn, ctx->xyz, ctx->va, ga.alpha, ctx->tnum, ctx->tden);
+    }
+    if (nu_node > 0) {
+        hipLaunchKernelGGL(k_mob_node_all, dim3(nu_node), dim3(256), 0, ctx->stream, T.unode, K, T.ac, ga.alpha,
+                           ctx->par.di_cut, ctx->tnum, ctx->tden, ctx->tpart);
+        hipLaunchKernelGGL(k_seg_sum2, dim3(K), dim3(256), 0, ctx->stream, ctx->tpart, T.unode, ctx->tsc + TS_SUM, 4);
+    }
+    if (nu_elem > 0) {
+        if (D == 2)
+            hipLaunchKernelGGL(k_beta_elem_all<2>, dim3(nu_elem), dim3(256), 0, ctx->stream, T.uelem, K, T.ac,
+                               ctx->conn, ctx->xyz, ga.alpha, ctx->tpart);
+        else
+            hipLaunchKernelGGL(k_beta_elem_all<3>, dim3(nu_elem), dim3(256), 0, ctx->stream, T.uelem, K, T.ac,
+                               ctx->conn, ctx->xyz, ga.alpha, ctx->tpart);
+        hipLaunchKernelGGL(k_seg_sum2, dim3(K), dim3(256), 0, ctx->stream, ctx->tpart, T.uelem, ctx->tsc + TS_SUM + 2,
+                           4);
+    }
+    EFT_HIP(hipGetLastError());
+    (void)N;
     EFT_HIP(hipMemcpyAsync(ctx->htsc + TS_SUM, ctx->tsc + TS_SUM, sizeof(double) * 4 * K, hipMemcpyDeviceToHost,
                            ctx->stream));
     EFT_HIP(hipMemcpyAsync(ctx->htsc + TS_VMAX, ctx->tsc + TS_VMAX, sizeof(double), hipMemcpyDeviceToHost,
@@ -1302,6 +1665,43 @@ static eft_status assemble_b(eft_ctx *ctx, const eft_state *lvl, const eft_itera
     return EFT_OK;
 }
 
+// Every band system of one kind in one launch (kind 0: the Allen-Cahn
+// systems of all indicators, with gamma, beta on the device; kind 1: the B
+// systems of all solids, compact blocks and diagonal blocks).  The member
+// descriptors were uploaded by mobility_beta_all for these fields.
+static eft_status assemble_all(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it, int kind)
+{
+    const int K = ctx->n_ind, S = ctx->n_s;
+    const MemTabs T = mem_tabs(ctx->dmem), H = mem_tabs(ctx->hmem);
+    TrArgs a = tr_args(ctx, ctx->band[0], nullptr, nullptr, nullptr);
+    a.full_b = 0;
+    const int nmem = kind == 0 ? K : S;
+    const int units = kind == 0 ? H.uac[K] : H.ub[S];
+    if (units == 0) return EFT_OK;
+    const int grid = std::min(units, 4096);
+    if (kind == 0) {
+        const size_t shm = (size_t)a.rpb * (a.maxc + 1) * sizeof(double);
+        if (ctx->dim == 2)
+            hipLaunchKernelGGL(k_ac_rows_all<2>, dim3(grid), dim3(256), shm, ctx->stream, a, ctx->par.eps, T.ac, T.uac,
+                               nmem);
+        else
+            hipLaunchKernelGGL(k_ac_rows_all<3>, dim3(grid), dim3(256), shm, ctx->stream, a, ctx->par.eps, T.ac, T.uac,
+                               nmem);
+    } else {
+        const int nv = ctx->nv;
+        const int bp = ctx->dim == 2 ? BAcc<2>::P : BAcc<3>::P;
+        const size_t shm = (size_t)a.rpb * ((size_t)a.maxc * bp + (nv | 1)) * sizeof(double);
+        if (ctx->dim == 2)
+            hipLaunchKernelGGL(k_b_rows_all<2>, dim3(grid), dim3(256), shm, ctx->stream, a, T.b, T.ub, nmem);
+        else
+            hipLaunchKernelGGL(k_b_rows_all<3>, dim3(grid), dim3(256), shm, ctx->stream, a, T.b, T.ub, nmem);
+    }
+    EFT_HIP(hipGetLastError());
+    (void)lvl;
+    (void)it;
+    return EFT_OK;
+}
+
 // Solve the assembled union system (R in bR, matrix in bval) of one kind:
 // rhs = -R; with several members, member k's right-hand side is divided by
 // ||R_k|| (its solution multiplied back afterwards), which weights the
@@ -1403,9 +1803,7 @@ eft_status eft_transport_dev(eft_ctx *ctx, const eft_state *lvl, eft_iterate *it
     // every Allen-Cahn system, one batched solve
     if (K > 0 && ctx->u_ac.n > 0) {
         const eft_ctx::BandUnion &U = ctx->u_ac;
-        for (int k = 0; k < K; ++k)
-            if (ctx->band[k].n > 0)
-                EFT_TRY(assemble_ac(ctx, lvl, it, k, ctx->bR + U.roff[k], ctx->bval + U.noff[k], ctx->tsc + TS_GB + 2 * k));
+        EFT_TRY(assemble_all(ctx, lvl, it, 0));
         std::vector<double *> x(K);
         std::vector<int64_t> xl(K, N);
         for (int k = 0; k < K; ++k) x[k] = it->phi + (int64_t)k * N;
@@ -1420,11 +1818,7 @@ eft_status eft_transport_dev(eft_ctx *ctx, const eft_state *lvl, eft_iterate *it
     // assembly), one batched solve
     if (S > 0 && ctx->u_b.n > 0) {
         const eft_ctx::BandUnion &U = ctx->u_b;
-        for (int sI = 0; sI < S; ++sI)
-            if (ctx->band[ctx->solid_ind[sI]].n > 0)
-                EFT_TRY(assemble_b(ctx, lvl, it, sI, ctx->bR + U.roff[sI] * nv, nullptr,
-                                   ctx->bcmp + U.noff[sI] * (1 + ctx->dim * ctx->dim), false,
-                                   ctx->bdiag + U.roff[sI] * nv * nv));
+        EFT_TRY(assemble_all(ctx, lvl, it, 1));
         std::vector<double *> x(S);
         std::vector<int64_t> xl(S, N * nv);
         for (int sI = 0; sI < S; ++sI) x[sI] = it->B + (int64_t)sI * N * nv;
