@@ -90,7 +90,7 @@ void free_all(eft_ctx *ctx)
     auto fr = [](void *p) {
         if (p) (void)hipFree(p);
     };
-    fr(ctx->xyz); fr(ctx->conn); fr(ctx->epos); fr(ctx->iptr); fr(ctx->ient); fr(ctx->cell_of); fr(ctx->dir_node); fr(ctx->dir_mask); fr(ctx->fmask0);
+    fr(ctx->xyz); fr(ctx->conn); fr(ctx->epos); fr(ctx->iptr); fr(ctx->ient); fr(ctx->islot); fr(ctx->cell_of); fr(ctx->dir_node); fr(ctx->dir_mask); fr(ctx->fmask0);
     fr(ctx->dir_val); fr(ctx->phase_tab); fr(ctx->ind_of_phase);
     fr(ctx->J.rowptr); fr(ctx->J.col); fr(ctx->J.diag); fr(ctx->J.val); fr(ctx->J.val32);
     fr(ctx->va); fr(ctx->acc); fr(ctx->rho); fr(ctx->mu); fr(ctx->smask); fr(ctx->solid_ind_d); fr(ctx->R); fr(ctx->dx);
@@ -292,7 +292,8 @@ eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *
         }
     }
     std::vector<int32_t> rowptr, col, diag, epos, iptr, ient;
-    EFT_TRY(eft_build_graph(N, E, nn, conn, rowptr, col, diag, epos, iptr, ient, ctx->maxc, ctx->rpb, ctx->rpb_ns,
+    std::vector<uint32_t> islot;
+    EFT_TRY(eft_build_graph(N, E, nn, conn, rowptr, col, diag, epos, iptr, ient, islot, ctx->maxc, ctx->rpb, ctx->rpb_ns,
                             ctx->err));
     const int64_t nnzb = (int64_t)col.size();
     // band grid: cells of band_cell mesh cells, element -> cell of its centroid
@@ -363,6 +364,7 @@ eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *
     EFT_TRY(upload(ctx, &ctx->epos, epos.data(), E * nn * nn));
     EFT_TRY(upload(ctx, &ctx->iptr, iptr.data(), N + 1));
     EFT_TRY(upload(ctx, &ctx->ient, ient.data(), E * nn));
+    EFT_TRY(upload(ctx, &ctx->islot, islot.data(), E * nn));
     EFT_TRY(upload(ctx, &ctx->cell_of, cell_of.data(), E));
     ctx->n_dir = mesh->n_dir;
     if (mesh->n_dir > 0) {

@@ -88,6 +88,7 @@ struct MeshView {
     const int32_t *dir_node = nullptr;
     const uint8_t *dir_mask = nullptr;
     const int32_t *iptr = nullptr, *ient = nullptr;  // node -> (element << 2 | local node)
+    const uint32_t *islot = nullptr;  // per incidence entry: its row's block slots, see eft_build_graph
     int maxc = 0, rpb = 1;                           // longest matrix row, rows per workgroup
     const uint8_t *fmask = nullptr;                  // [N] bit c set when dof c is free (others: unit rows)
 };
@@ -100,6 +101,7 @@ struct MGLevel {
     int64_t N = 0, E = 0;
     int32_t *conn = nullptr, *epos = nullptr, *inj = nullptr;  // inj: fine-mesh node of each node
     int32_t *iptr = nullptr, *ient = nullptr;
+    uint32_t *islot = nullptr;
     int maxc = 0, rpb = 1;
     double *xyz = nullptr;
     double *va = nullptr, *acc = nullptr, *rho = nullptr, *mu = nullptr, *as = nullptr, *Ba = nullptr;
@@ -183,6 +185,7 @@ struct eft_ctx {
     int32_t *conn = nullptr;
     int32_t *epos = nullptr;        // [E][nn*nn] position of (a,b) in the NS pattern
     int32_t *iptr = nullptr, *ient = nullptr;  // node -> incident (element << 2 | local node)
+    uint32_t *islot = nullptr;      // per incidence entry: its row's block slots (eft_build_graph)
     uint8_t *fmask0 = nullptr;      // [N] bit c set when dof c of the node is free (not Dirichlet)
     int maxc = 0, rpb = 1;          // longest row of the node graph, rows per band-assembly workgroup
     int rpb_ns = 1;                 // rows per momentum/mass assembly workgroup
@@ -326,8 +329,8 @@ bool eft_mg_active(const eft_ctx *ctx, const eft_matrix *A);
 eft_status eft_mg_reserve(eft_ctx *ctx);
 eft_status eft_build_graph(int64_t N, int64_t E, int nn, const int32_t *conn, std::vector<int32_t> &rowptr,
                            std::vector<int32_t> &col, std::vector<int32_t> &diag, std::vector<int32_t> &epos,
-                           std::vector<int32_t> &iptr, std::vector<int32_t> &ient, int &maxc, int &rpb,
-                           int &rpb_ns, std::string &err);
+                           std::vector<int32_t> &iptr, std::vector<int32_t> &ient, std::vector<uint32_t> &islot,
+                           int &maxc, int &rpb, int &rpb_ns, std::string &err);
 eft_status eft_fill(eft_ctx *ctx, double *p, int64_t n, double v);
 eft_status eft_fill32(eft_ctx *ctx, float *p, int64_t n, float v);
 eft_status eft_fill_u8(eft_ctx *ctx, uint8_t *p, int64_t n);

@@ -1,20 +1,23 @@
 // Element assembly of the unified momentum/mass system, eq. (PG_NS).
 //
 // Two kernels:
-//   k_props    per node: generalized-alpha level values (Sec. 2.1.2) and
-//              phase-interpolated rho, mu (Sec. 2.1.1), solid fractions and
-//              B at n+alpha;
-//   k_ns_rows  row-owned assembly: a workgroup owns a set of block rows; each
-//              (row, incident element) pair evaluates the element at its
-//              quadrature points (Galerkin + SUPG/PSPG/LSIC with the tau_m,
-//              tau_c formula, the Newtonian stress, the left-Cauchy-Green
-//              stress mu_L (B - I) and its tangent through dB/dv of eq.
-//              (Bext) / Appendix B) and adds only that row's residual and
-//              blocks into LDS accumulators; the rows are written out whole
-//              (no global atomics), with the unit rows of Dirichlet dofs.
-// The tangent is factored: per element the quadrature sums that multiply each
-// node-pair block are formed once (about 10 scalars per pair), so a 4x4 block
-// costs a few dozen flops instead of a loop over quadrature points.
+//   k_props    per node: generalized-alpha level values (Sec. 2.1.2),
+//              phase-interpolated rho, mu (Sec. 2.1.1) and the mask of the
+//              solids present;
+//   k_ns_rows  row-owned assembly: a workgroup owns a set of consecutive block
+//              rows; each (row, incident element) pair evaluates the element
+//              at its quadrature points (Galerkin + SUPG/PSPG/LSIC with the
+//              tau_m, tau_c formula and the Newtonian stress) and adds only
+//              that row's residual and blocks into LDS accumulators; the
+//              left-Cauchy-Green stress mu_L (B - I) of the solids present on
+//              the element and its tangent through dB/dv (eq. (Bext) /
+//              Appendix B) are queued per (pair, solid) and evaluated after
+//              the fluid pass by all threads; the rows are written out once,
+//              contiguously (no global atomics), with the unit rows of
+//              Dirichlet dofs.
+// The quadrature sums are factored: the sums over the points that do not
+// depend on the row are shared by the row's residual and its blocks, so a
+// 4x4 block costs a few dozen flops.
 #include "dev_common.h"
 #include "eft_internal.h"
 
@@ -102,6 +105,7 @@ struct RowArgs {
     int64_t N;                   // rows (nodes)
     int rpb, maxc;               // rows per workgroup, longest row (LDS layout)
     const int32_t *iptr, *ient;  // node -> incident (element << 2 | local node)
+    const uint32_t *islot;       // per incidence entry: byte k = block slot, in the row, of local node (a + k) mod nn
     const int32_t *conn, *epos, *rowptr;
     const double *xyz, *va, *acc, *vp, *rho, *mu;
     int n_s;
@@ -119,6 +123,127 @@ struct RowArgs {
     const uint8_t *fmask;    // [N] free-dof bits: a Dirichlet dof's row is written as a unit row, residual 0
 };
 
+// Elastic stress mu_L (B - I) of solid sI on the element of one (row,
+// element) pair (residual, added to rl), and its tangent through dB/dv, eq.
+// (Bext), added to the row's blocks in LDS: with F = int alpha mu_L,
+// W_b = int N_b alpha mu_L, M = int alpha mu_L B and D_k = (dB/dx_k) grad N_a,
+// the residual gains (M - F I) grad N_a and block (a, b) gains
+//   alpha kappa (-W_b D_k[i] + dN_a[k] (M grad N_b)_i + delta_ik grad N_a . M grad N_b).
+// nd, dN: the element's nodes and shape gradients with the row node first;
+// sl: the row's block slots of the element's nodes (same order).
+constexpr int EQ_CAP = 2048;   // queued elastic (pair, solid) items per workgroup
+
+template <int D>
+__device__ __forceinline__ void elastic_pair(const RowArgs &a, const int (&nd)[D + 1], const double (&dN)[D + 1][D],
+                                             double w, uint32_t sl, int lr, int sI, bool withJ, double *rl,
+                                             double *accJ)
+{
+    constexpr int NN = D + 1, BS = D + 1, NQ = Rule<D>::NQ, NVv = NV<D>::v, BP = (BS * BS) | 1;
+    constexpr double QA = Rule<D>::QA, QB = Rule<D>::QB, QD = QA - QB;
+    const double(&da)[D] = dN[0];
+    double asn[NN];
+    double Bn[NN][NVv];
+    if (a.as) {
+#pragma unroll
+        for (int b = 0; b < NN; ++b) {
+            asn[b] = a.as[(int64_t)sI * a.N + nd[b]];
+#pragma unroll
+            for (int c = 0; c < NVv; ++c) Bn[b][c] = a.Ba[((int64_t)sI * a.N + nd[b]) * NVv + c];
+        }
+    } else {
+        const int64_t ko = (int64_t)a.solid_ind[sI] * a.N;
+#pragma unroll
+        for (int b = 0; b < NN; ++b) {
+            asn[b] = phase_fraction(a.lphi[ko + nd[b]], a.iphi[ko + nd[b]], a.alpha);
+#pragma unroll
+            for (int c = 0; c < NVv; ++c) {
+                const int64_t o = ((int64_t)sI * a.N + nd[b]) * NVv + c;
+                Bn[b][c] = a.lB[o] + a.alpha * (a.iB[o] - a.lB[o]);
+            }
+        }
+    }
+    const double muL = a.muL[sI];
+    double sa = 0.0, sb[NVv];
+#pragma unroll
+    for (int c = 0; c < NVv; ++c) sb[c] = 0.0;
+#pragma unroll
+    for (int b = 0; b < NN; ++b) {
+        sa += asn[b];
+#pragma unroll
+        for (int c = 0; c < NVv; ++c) sb[c] += Bn[b][c];
+    }
+    // Md = int alpha mu_L (B - I) (B - I formed before the product, as
+    // mu_L may be large and B close to I), M = Md + F I
+    double F = 0.0, Wbs[NN], Mv[NVv];
+#pragma unroll
+    for (int b = 0; b < NN; ++b) Wbs[b] = 0.0;
+#pragma unroll
+    for (int c = 0; c < NVv; ++c) Mv[c] = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double wf = w * (QB * sa + QD * asn[q]) * muL;
+        F += wf;
+#pragma unroll
+        for (int b = 0; b < NN; ++b) Wbs[b] += wf * (b == q ? QA : QB);
+#pragma unroll
+        for (int c = 0; c < NVv; ++c) Mv[c] += wf * (QB * sb[c] + QD * Bn[q][c] - (c < D ? 1.0 : 0.0));
+    }
+    double M2[D][D];
+    vfull<D>(Mv, M2);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        double s2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) s2 += M2[i][j] * da[j];
+        rl[i] += s2;
+    }
+    if (!withJ) return;
+#pragma unroll
+    for (int i = 0; i < D; ++i) M2[i][i] += F;
+    double Dk[D][D];   // Dk[i][k] = ((dB/dx_k) grad N_a)_i
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double gk[NVv];
+#pragma unroll
+        for (int c = 0; c < NVv; ++c) {
+            double s2 = 0.0;
+#pragma unroll
+            for (int b = 0; b < NN; ++b) s2 += dN[b][k] * Bn[b][c];
+            gk[c] = s2;
+        }
+        double gf[D][D];
+        vfull<D>(gk, gf);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double t = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) t += gf[i][j] * da[j];
+            Dk[i][k] = t;
+        }
+    }
+    const double ak = a.alpha * a.kappa;
+#pragma unroll
+    for (int ib = 0; ib < NN; ++ib) {
+        const int slot = (sl >> (8 * ib)) & 0xff;
+        double *blk = accJ + ((int64_t)lr * a.maxc + slot) * BP;
+        double Mb[D], aMb = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double s2 = 0.0;
+#pragma unroll
+            for (int l = 0; l < D; ++l) s2 += M2[i][l] * dN[ib][l];
+            Mb[i] = s2;
+            aMb += da[i] * s2;
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                atomicAdd(blk + i * BS + k,
+                          ak * (-Wbs[ib] * Dk[i][k] + da[k] * Mb[i] + (i == k ? aMb : 0.0)));
+    }
+}
+
 template <int D, typename TJ>
 __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ Jv)
 {
@@ -133,12 +258,27 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
     double *accJ = lds;                                 // [rpb][maxc][BP]
     double *accR = lds + (int64_t)a.rpb * a.maxc * BP;  // [rpb][RP]
     const int nacc = a.rpb * a.maxc * BP + a.rpb * RP;
-    __shared__ int maxinc;
-    if (threadIdx.x == 0) maxinc = 0;
+    // the rows' incidence and block ranges, free-dof bits and, per block of
+    // the workgroup's (contiguous) block range, its row
+    int *istart = reinterpret_cast<int *>(lds + nacc);      // [rpb + 1]
+    int *rstart = istart + (a.rpb + 1);                      // [rpb + 1]
+    uint16_t *blkrow = reinterpret_cast<uint16_t *>(rstart + (a.rpb + 1));   // [rpb * maxc]
+    uint8_t *fml = reinterpret_cast<uint8_t *>(blkrow + a.rpb * a.maxc);     // [rpb]
+    __shared__ int maxinc, eq_n;
+    __shared__ uint32_t eq[EQ_CAP];   // queued (pair << 6 | solid) elastic work
+    if (threadIdx.x == 0) maxinc = eq_n = 0;
     for (int t = threadIdx.x; t < nacc; t += blockDim.x) lds[t] = 0.0;
-    __syncthreads();
     const int nrow = (int)(r1 - r0);
-    if (threadIdx.x < nrow) atomicMax(&maxinc, a.iptr[r0 + threadIdx.x + 1] - a.iptr[r0 + threadIdx.x]);
+    if (threadIdx.x <= nrow) {
+        istart[threadIdx.x] = a.iptr[r0 + threadIdx.x];
+        rstart[threadIdx.x] = a.rowptr[r0 + threadIdx.x];
+    }
+    if (threadIdx.x < nrow) fml[threadIdx.x] = a.fmask[r0 + threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x < nrow) {
+        atomicMax(&maxinc, istart[threadIdx.x + 1] - istart[threadIdx.x]);
+        for (int k = rstart[threadIdx.x]; k < rstart[threadIdx.x + 1]; ++k) blkrow[k - rstart[0]] = threadIdx.x;
+    }
     __syncthreads();
     const double gv[3] = {a.g0, a.g1, a.g2};
     // (row, incident element) pairs are dealt row-interleaved: consecutive
@@ -146,16 +286,21 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
     // hit the same block (all elements of a row add into its diagonal block)
     for (int k = threadIdx.x; k < nrow * maxinc; k += blockDim.x) {
         const int kr = k % nrow;
-        const int ii = a.iptr[r0 + kr] + k / nrow;
-        if (ii >= a.iptr[r0 + kr + 1]) continue;
+        const int ii = istart[kr] + k / nrow;
+        if (ii >= istart[kr + 1]) continue;
         const int32_t ent = a.ient[ii];
+        const uint32_t sl = a.islot[ii];
         const int64_t e = ent >> 2;
         const int la = ent & 3;
+        // the element's nodes rotated so that the row node comes first (local
+        // node b is node (la + b) mod NN of the connectivity): every index
+        // below is then a compile-time constant
         int nd[NN];
         double X[NN][D], v[NN][D], ac[NN][D], p[NN], rh[NN], mu[NN];
 #pragma unroll
+        for (int b = 0; b < NN; ++b) nd[b] = a.conn[e * NN + (la + b < NN ? la + b : la + b - NN)];
+#pragma unroll
         for (int b = 0; b < NN; ++b) {
-            nd[b] = a.conn[e * NN + b];
             const int64_t n = nd[b];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
@@ -167,10 +312,33 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
             rh[b] = a.rho[n];
             mu[b] = a.mu[n];
         }
-        const int64_t row = nd[la];
+        const int64_t row = nd[0];
         const int lr = (int)(row - r0);
         double dN[NN][D], G[D][D];
         const double vol = simplex_geom<D>(X, dN, G);
+        // G = J^-T J^-1 belongs to the reference map with its origin at the
+        // element's first node in the connectivity (it is not invariant under
+        // a relabelling of the nodes): rebuild it as the sum of grad N grad N^T
+        // over the other nodes; the rotation moved that node to local o0
+        {
+            const int o0 = la == 0 ? 0 : NN - la;
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) G[i][j] = 0.0;
+#pragma unroll
+            for (int b = 0; b < NN; ++b) {
+                const double c = b == o0 ? 0.0 : 1.0;
+#pragma unroll
+                for (int i = 0; i < D; ++i)
+#pragma unroll
+                    for (int j = i; j < D; ++j) G[i][j] += c * dN[b][i] * dN[b][j];
+            }
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < i; ++j) G[i][j] = G[j][i];
+        }
         double GG = 0.0, trG = 0.0;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
@@ -195,22 +363,28 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
         }
 #pragma unroll
         for (int i = 0; i < D; ++i) divv += L[i][i];
+        const double(&da)[D] = dN[0];   // grad N of the row node
         const double w = vol * Rule<D>::WF;
-        const double inv4dt2 = 4.0 / (a.dt * a.dt);
-        double rl[BS];
+        const double inv4dt2 = 4.0 / (a.dt * a.dt), rtrG = 1.0 / trG;
+        constexpr double QA = Rule<D>::QA, QB = Rule<D>::QB, QD = QA - QB;
+        // Quadrature sums.  Element-level (the same for every row):
+        //   P = int p, MU = int mu, Tc = int tau_c rho, Tp = int tau_m / rho,
+        //   U = int tau_m v, Q2_b = int tau_m N_b;
+        // row-level, with W_a = rho (N_a + tau_m u_a), u_a = v . grad N_a:
+        //   Cs_b = int W_a N_b, V = int W_a v, Pa = int tau_m u_a and the residual.
+        // The tangent sums of the unfactored form follow from them:
+        //   int W_a (c_t N_b + alpha u_b) = c_t Cs_b + alpha V . grad N_b,
+        //   int tau_m (c_t N_b + alpha u_b) = c_t Q2_b + alpha U . grad N_b.
+        double P = 0.0, MU = 0.0, Tc = 0.0, Tp = 0.0, U[D], Q2s[NN], Cs[NN], V[D], Pa = 0.0, rl[BS];
+#pragma unroll
+        for (int i = 0; i < D; ++i) U[i] = V[i] = 0.0;
+#pragma unroll
+        for (int b = 0; b < NN; ++b) Q2s[b] = Cs[b] = 0.0;
 #pragma unroll
         for (int i = 0; i < BS; ++i) rl[i] = 0.0;
-        // tangent sums per column node b, accumulated over the quadrature
-        // points: A_b = int W_a (c_t N_b + alpha u_b), C_b = int W_a N_b,
-        // Q1_b = int tau_m (c_t N_b + alpha u_b), Q2_b = int tau_m N_b, with
-        // W_a = rho (N_a + tau_m u_a) and u_b = v . grad N_b
-        double As[NN], Cs[NN], Q1s[NN], Q2s[NN];
-#pragma unroll
-        for (int b = 0; b < NN; ++b) As[b] = Cs[b] = Q1s[b] = Q2s[b] = 0.0;
-        double muI = 0.0, Tc = 0.0, Tp = 0.0, Pa = 0.0;
-        // not unrolled: nothing here is indexed by q, and one point's
-        // temporaries at a time keep the register count (and so the
-        // occupancy) in check
+        // not unrolled: one point's temporaries at a time keep the register
+        // count (and so the occupancy) in check; q is uniform, so N_b(q) is a
+        // scalar select
 #pragma unroll 1
         for (int q = 0; q < NQ; ++q) {
             double rq = 0.0, mq = 0.0, pq = 0.0, vq[D], aq[D];
@@ -218,7 +392,7 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
             for (int i = 0; i < D; ++i) vq[i] = aq[i] = 0.0;
 #pragma unroll
             for (int b = 0; b < NN; ++b) {
-                const double Nb = shape_at<D>(q, b);
+                const double Nb = b == q ? QA : QB;
                 rq += Nb * rh[b];
                 mq += Nb * mu[b];
                 pq += Nb * p[b];
@@ -228,7 +402,7 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
                     aq[i] += Nb * ac[b][i];
                 }
             }
-            double Lv[D], vGv = 0.0;
+            double Rm[D], body[D], vGv = 0.0;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 double s = 0.0, t = 0.0;
@@ -237,200 +411,105 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
                     s += L[i][j] * vq[j];
                     t += G[i][j] * vq[j];
                 }
-                Lv[i] = s;
                 vGv += vq[i] * t;
-            }
-            double Rm[D], body[D];
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                body[i] = aq[i] + Lv[i] - gv[i];
+                body[i] = aq[i] + s - gv[i];
                 Rm[i] = rq * body[i] + gp[i];
             }
-            const double nu = mq / rq;
-            const double tau_m = 1.0 / sqrt(inv4dt2 + vGv + a.C_I * nu * nu * GG);
-            const double tau_c = 1.0 / (trG * tau_m);
-            const double Na = shape_at<D>(q, la);
-            double ua = 0.0;
-#pragma unroll
-            for (int j = 0; j < D; ++j) ua += vq[j] * dN[la][j];
-            double gR = 0.0;
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                double sd = -pq * dN[la][i];
-#pragma unroll
-                for (int j = 0; j < D; ++j) sd += mq * (L[i][j] + L[j][i]) * dN[la][j];
-                rl[i] += w * (Na * rq * body[i] + sd + tau_m * ua * Rm[i] + tau_c * rq * dN[la][i] * divv);
-                gR += dN[la][i] * Rm[i];
-            }
-            rl[D] += w * (Na * divv + (tau_m / rq) * gR);
-            const double Wq = w * rq * (Na + tau_m * ua), TMq = w * tau_m;
-#pragma unroll
-            for (int b = 0; b < NN; ++b) {
-                double ub = 0.0;
-#pragma unroll
-                for (int j = 0; j < D; ++j) ub += vq[j] * dN[b][j];
-                const double Nb = shape_at<D>(q, b);
-                const double lin = a.ct * Nb + a.alpha * ub;
-                As[b] += Wq * lin;
-                Cs[b] += Wq * Nb;
-                Q1s[b] += TMq * lin;
-                Q2s[b] += TMq * Nb;
-            }
-            Pa += TMq * ua;
-            muI += w * mq;
+            const double ri = 1.0 / rq, nu = mq * ri;
+            const double sq = sqrt(inv4dt2 + vGv + a.C_I * nu * nu * GG);
+            const double tau_m = 1.0 / sq, tau_c = sq * rtrG, TMq = w * tau_m;
+            P += w * pq;
+            MU += w * mq;
             Tc += w * tau_c * rq;
-            Tp += w * tau_m / rq;
+            Tp += TMq * ri;
+#pragma unroll
+            for (int i = 0; i < D; ++i) U[i] += TMq * vq[i];
+#pragma unroll
+            for (int b = 0; b < NN; ++b) Q2s[b] += TMq * (b == q ? QA : QB);
+            // the row node's share
+            const double Na = q == 0 ? QA : QB;
+            double ua = 0.0, gR = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                ua += vq[j] * da[j];
+                gR += da[j] * Rm[j];
+            }
+            const double tu = tau_m * ua, wNr = w * Na * rq;
+#pragma unroll
+            for (int i = 0; i < D; ++i) rl[i] += wNr * body[i] + w * tu * Rm[i];
+            rl[D] += TMq * ri * gR;
+            const double Wq = w * rq * (Na + tu);
+#pragma unroll
+            for (int b = 0; b < NN; ++b) Cs[b] += Wq * (b == q ? QA : QB);
+#pragma unroll
+            for (int i = 0; i < D; ++i) V[i] += Wq * vq[i];
+            Pa += TMq * ua;
         }
-        // fluid (and pressure) blocks of the row: d(residual of node la)/d(node ib)
+        const double NI = w * (Rule<D>::QA + (NQ - 1) * Rule<D>::QB);   // int N_a
+        // Galerkin pressure / viscous / LSIC terms of the residual, from the element sums
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) s += (L[i][j] + L[j][i]) * da[j];
+            rl[i] += MU * s + (Tc * divv - P) * da[i];
+        }
+        rl[D] += NI * divv;
+        // fluid (and pressure) blocks of the row: d(residual of the row node)/d(local node ib)
         if (Jv != nullptr) {
             const double al = a.alpha;
-            const double NI = w * (Rule<D>::QA + (NQ - 1) * Rule<D>::QB);
             double aL[D];
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 double s = 0.0;
 #pragma unroll
-                for (int j = 0; j < D; ++j) s += dN[la][j] * L[j][k];
+                for (int j = 0; j < D; ++j) s += da[j] * L[j][k];
                 aL[k] = s;
             }
-            const int64_t rbase = a.rowptr[row];
-#pragma unroll 1
-            for (int ib = 0; ib < NN; ++ib) {
-                const double A = As[ib], C = al * Cs[ib], Q1 = Q1s[ib], Q2 = Q2s[ib];
-                double gab = 0.0;
 #pragma unroll
-                for (int j = 0; j < D; ++j) gab += dN[la][j] * dN[ib][j];
-                const int slot = (int)(a.epos[e * NN * NN + la * NN + ib] - rbase);
+            for (int ib = 0; ib < NN; ++ib) {
+                const double(&db)[D] = dN[ib];
+                double gab = 0.0, Vb = 0.0, Ub = 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    gab += da[j] * db[j];
+                    Vb += V[j] * db[j];
+                    Ub += U[j] * db[j];
+                }
+                const double Csb = Cs[ib], Q2 = Q2s[ib];
+                const double A = a.ct * Csb + al * Vb, C = al * Csb, Q1 = a.ct * Q2 + al * Ub;
+                const int slot = (sl >> (8 * ib)) & 0xff;
                 double *blk = accJ + ((int64_t)lr * a.maxc + slot) * BP;
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
 #pragma unroll
                     for (int k = 0; k < D; ++k) {
-                        double val = C * L[i][k] + al * muI * dN[la][k] * dN[ib][i] + al * Tc * dN[la][i] * dN[ib][k];
-                        if (i == k) val += A + al * muI * gab;
+                        double val = C * L[i][k] + al * MU * da[k] * db[i] + al * Tc * da[i] * db[k];
+                        if (i == k) val += A + al * MU * gab;
                         atomicAdd(blk + i * BS + k, val);
                     }
-                    atomicAdd(blk + i * BS + D, -dN[la][i] * NI + Pa * dN[ib][i]);
+                    atomicAdd(blk + i * BS + D, -da[i] * NI + Pa * db[i]);
                 }
 #pragma unroll
                 for (int k = 0; k < D; ++k)
-                    atomicAdd(blk + D * BS + k, al * dN[ib][k] * NI + dN[la][k] * Q1 + al * aL[k] * Q2);
+                    atomicAdd(blk + D * BS + k, al * db[k] * NI + da[k] * Q1 + al * aL[k] * Q2);
                 atomicAdd(blk + D * BS + D, Tp * gab);
             }
         }
-        // elastic stress mu_L (B - I) of every solid present on the element
-        // (residual), and its tangent through dB/dv, eq. (Bext), solid by
-        // solid: with W_b = int N_b alpha mu_L, M = int alpha mu_L B and
-        // D_k = (dB/dx_k) grad N_a, block (a, b) gains
-        //   alpha kappa (-W_b D_k[i] + dN_a[k] (M grad N_b)_i + delta_ik grad N_a . M grad N_b)
-        uint64_t present = 0;
-        if (a.n_s > 0)
+        // elastic stress of the solids present on the element: queued per
+        // (pair, solid) for the dense pass below (a wavefront would otherwise
+        // run the solid body for a few of its lanes), inline when the queue
+        // is full
+        if (a.n_s > 0) {
+            uint64_t present = 0;
 #pragma unroll
             for (int b = 0; b < NN; ++b) present |= a.smask[nd[b]];
-        while (present) {   // the solids present on the element, in increasing order
-            const int sI = __ffsll((unsigned long long)present) - 1;
-            present &= present - 1;
-            double asn[NN];
-            double Bn[NN][NVv];
-            if (a.as) {
-#pragma unroll
-                for (int b = 0; b < NN; ++b) {
-                    asn[b] = a.as[(int64_t)sI * a.N + nd[b]];
-#pragma unroll
-                    for (int c = 0; c < NVv; ++c) Bn[b][c] = a.Ba[((int64_t)sI * a.N + nd[b]) * NVv + c];
-                }
-            } else {
-                const int64_t ko = (int64_t)a.solid_ind[sI] * a.N;
-#pragma unroll
-                for (int b = 0; b < NN; ++b) {
-                    asn[b] = phase_fraction(a.lphi[ko + nd[b]], a.iphi[ko + nd[b]], a.alpha);
-#pragma unroll
-                    for (int c = 0; c < NVv; ++c) {
-                        const int64_t o = ((int64_t)sI * a.N + nd[b]) * NVv + c;
-                        Bn[b][c] = a.lB[o] + a.alpha * (a.iB[o] - a.lB[o]);
-                    }
-                }
-            }
-            const double muL = a.muL[sI];
-            double Wbs[NN], M2[D][D];
-#pragma unroll
-            for (int b = 0; b < NN; ++b) Wbs[b] = 0.0;
-#pragma unroll
-            for (int i = 0; i < D; ++i)
-#pragma unroll
-                for (int j = 0; j < D; ++j) M2[i][j] = 0.0;
-#pragma unroll 1
-            for (int q = 0; q < NQ; ++q) {
-                double aq = 0.0, bq[NVv];
-#pragma unroll
-                for (int c = 0; c < NVv; ++c) bq[c] = 0.0;
-#pragma unroll
-                for (int b = 0; b < NN; ++b) {
-                    const double Nb = shape_at<D>(q, b);
-                    aq += Nb * asn[b];
-#pragma unroll
-                    for (int c = 0; c < NVv; ++c) bq[c] += Nb * Bn[b][c];
-                }
-                double Bq[D][D];
-                vfull<D>(bq, Bq);
-                const double f = aq * muL;
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    double s2 = 0.0;
-#pragma unroll
-                    for (int j = 0; j < D; ++j) s2 += (Bq[i][j] - (i == j ? 1.0 : 0.0)) * dN[la][j];
-                    rl[i] += w * f * s2;
-                }
-#pragma unroll
-                for (int b = 0; b < NN; ++b) Wbs[b] += w * shape_at<D>(q, b) * f;
-#pragma unroll
-                for (int i = 0; i < D; ++i)
-#pragma unroll
-                    for (int j = 0; j < D; ++j) M2[i][j] += w * f * Bq[i][j];
-            }
-            if (Jv == nullptr) continue;
-            double Dk[D][D];   // Dk[i][k] = ((dB/dx_k) grad N_a)_i
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                double gk[NVv];
-#pragma unroll
-                for (int c = 0; c < NVv; ++c) {
-                    double s2 = 0.0;
-#pragma unroll
-                    for (int b = 0; b < NN; ++b) s2 += dN[b][k] * Bn[b][c];
-                    gk[c] = s2;
-                }
-                double gf[D][D];
-                vfull<D>(gk, gf);
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    double t = 0.0;
-#pragma unroll
-                    for (int j = 0; j < D; ++j) t += gf[i][j] * dN[la][j];
-                    Dk[i][k] = t;
-                }
-            }
-            const double ak = a.alpha * a.kappa;
-            const int64_t rbase = a.rowptr[row];
-#pragma unroll
-            for (int ib = 0; ib < NN; ++ib) {
-                const int slot = (int)(a.epos[e * NN * NN + la * NN + ib] - rbase);
-                double *blk = accJ + ((int64_t)lr * a.maxc + slot) * BP;
-                double Mb[D], aMb = 0.0;
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    double s2 = 0.0;
-#pragma unroll
-                    for (int l = 0; l < D; ++l) s2 += M2[i][l] * dN[ib][l];
-                    Mb[i] = s2;
-                    aMb += dN[la][i] * s2;
-                }
-#pragma unroll
-                for (int i = 0; i < D; ++i)
-#pragma unroll
-                    for (int k = 0; k < D; ++k)
-                        atomicAdd(blk + i * BS + k,
-                                  ak * (-Wbs[ib] * Dk[i][k] + dN[la][k] * Mb[i] + (i == k ? aMb : 0.0)));
+            while (present) {   // in increasing solid order
+                const int sI = __ffsll((unsigned long long)present) - 1;
+                present &= present - 1;
+                const int slot = atomicAdd(&eq_n, 1);
+                if (slot < EQ_CAP) eq[slot] = ((uint32_t)k << 6) | (uint32_t)sI;
+                else elastic_pair<D>(a, nd, dN, w, sl, lr, sI, Jv != nullptr, rl, accJ);
             }
         }
         // residual of the row node
@@ -438,21 +517,54 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
         for (int i = 0; i < BS; ++i) atomicAdd(accR + lr * RP + i, rl[i]);
     }
     __syncthreads();
-    for (int64_t r = r0; r < r1; ++r) {
-        const int lr = (int)(r - r0);
-        const int fm = a.fmask[r];
-        if (threadIdx.x < BS) a.R[r * BS + threadIdx.x] = ((fm >> threadIdx.x) & 1) ? accR[lr * RP + threadIdx.x] : 0.0;
-        if (Jv == nullptr) continue;
-        const int64_t kb = a.rowptr[r], len = a.rowptr[r + 1] - kb;
-        for (int t = threadIdx.x; t < len * B2; t += blockDim.x)
-        {
-            const int kk = t / B2, e = t - kk * B2;
-            double v = accJ[((int64_t)lr * a.maxc + kk) * BP + e];
-            if (!((fm >> (e / BS)) & 1)) v = (a.col[kb + kk] == r && e % (BS + 1) == 0) ? 1.0 : 0.0;
-            Jv[kb * B2 + t] = (TJ)v;
-            if (a.J32) a.J32[kb * B2 + t] = (float)v;
-            if (a.J16) a.J16[kb * B2 + t] = to_bf16_rne((float)v);
+    // the queued elastic work, one (pair, solid) per thread
+    const int nq = eq_n < EQ_CAP ? eq_n : EQ_CAP;
+    for (int t = threadIdx.x; t < nq; t += blockDim.x) {
+        const uint32_t item = eq[t];
+        const int k = (int)(item >> 6), sI = (int)(item & 63);
+        const int kr = k % nrow;
+        const int ii = istart[kr] + k / nrow;
+        const int32_t ent = a.ient[ii];
+        const uint32_t sl = a.islot[ii];
+        const int64_t e = ent >> 2;
+        const int la = ent & 3;
+        int nd[NN];
+        double X[NN][D];
+#pragma unroll
+        for (int b = 0; b < NN; ++b) {
+            nd[b] = a.conn[e * NN + (la + b < NN ? la + b : la + b - NN)];
+#pragma unroll
+            for (int i = 0; i < D; ++i) X[b][i] = a.xyz[(int64_t)nd[b] * D + i];
         }
+        double dN[NN][D], G[D][D];
+        const double w = simplex_geom<D>(X, dN, G) * Rule<D>::WF;
+        double rl[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) rl[i] = 0.0;
+        const int lr = (int)(nd[0] - r0);
+        elastic_pair<D>(a, nd, dN, w, sl, lr, sI, Jv != nullptr, rl, accJ);
+#pragma unroll
+        for (int i = 0; i < D; ++i) atomicAdd(accR + lr * RP + i, rl[i]);
+    }
+    __syncthreads();
+    // write-out, flat over the workgroup's rows: R, then the values of its
+    // contiguous block range (coalesced), Dirichlet dofs as unit rows
+    for (int t = threadIdx.x; t < nrow * BS; t += blockDim.x) {
+        const int lr = t / BS, i = t - lr * BS;
+        a.R[r0 * BS + t] = ((fml[lr] >> i) & 1) ? accR[lr * RP + i] : 0.0;
+    }
+    if (Jv == nullptr) return;
+    const int kb0 = rstart[0];
+    const int nval = (rstart[nrow] - kb0) * B2;
+    for (int t = threadIdx.x; t < nval; t += blockDim.x) {
+        const int kk = t / B2, e = t - kk * B2;
+        const int lr = blkrow[kk];
+        double v = accJ[((int64_t)lr * a.maxc + (kk - (rstart[lr] - kb0))) * BP + e];
+        if (!((fml[lr] >> (e / BS)) & 1)) v = (a.col[kb0 + kk] == r0 + lr && e % (BS + 1) == 0) ? 1.0 : 0.0;
+        const int64_t o = (int64_t)kb0 * B2 + t;
+        Jv[o] = (TJ)v;
+        if (a.J32) a.J32[o] = (float)v;
+        if (a.J16) a.J16[o] = to_bf16_rne((float)v);
     }
 }
 
@@ -547,6 +659,7 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
     a.maxc = M.maxc;
     a.iptr = M.iptr;
     a.ient = M.ient;
+    a.islot = M.islot;
     a.conn = M.conn;
     a.epos = M.epos;
     a.rowptr = J ? J->rowptr : nullptr;
@@ -588,11 +701,15 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
         a.rowptr = ctx->J.rowptr;
     }
     const int nb = eft_grid(M.N, M.rpb);
-    const size_t shm = (size_t)M.rpb * ((size_t)M.maxc * ((BS * BS) | 1) + (BS | 1)) * sizeof(double);
+    const size_t shm = (size_t)M.rpb * ((size_t)M.maxc * ((BS * BS) | 1) + (BS | 1)) * sizeof(double) +
+                       (size_t)(M.rpb + 1) * 2 * sizeof(int) + (size_t)M.rpb * M.maxc * sizeof(uint16_t) + M.rpb;
     // kernel-timing hook on the mesh level (not the coarse levels).
     // Algorithmic bytes: J (and its FP32 or BF16 copy when written) and R
-    // written once, the connectivity, every node field the element
-    // evaluation reads and the free-dof bits, once.
+    // written once; read once: the connectivity, the node state the element
+    // evaluation needs (x, v and a at n+alpha, p, rho, mu and the solid mask:
+    // 3d + 4 numbers) and the free-dof bits.  The solid fields of the present
+    // solids are not counted (data-dependent; about 1% of the total on the
+    // floe field).
     const bool fine = M.conn == ctx->conn;
     const int64_t slot = fine ? eft_kt_begin(ctx, EFT_KT_ASSEMBLE) : -1;
     const int d = ctx->dim;
@@ -600,7 +717,7 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
         (J ? (double)J->nnzb * BS * BS * ((J->fp32 ? 4.0 : 8.0) + (a.J32 ? 4.0 : 0.0) + (a.J16 ? 2.0 : 0.0)) : 0.0) +
         (double)M.N * BS * 8.0 +
         (double)M.E * (d + 1) * 4.0 +
-        (double)M.N * 8.0 * (d + BS + d + d + 2 + (double)ctx->n_s * (1 + ctx->nv)) + (double)M.N;
+        (double)M.N * 8.0 * (3 * d + 4) + (double)M.N;
     if (ctx->dim == 2) {
         if (J && J->fp32) hipLaunchKernelGGL((k_ns_rows<2, float>), dim3(nb), dim3(256), shm, ctx->stream, a, J->val32);
         else hipLaunchKernelGGL((k_ns_rows<2, double>), dim3(nb), dim3(256), shm, ctx->stream, a, J ? J->val : nullptr);
@@ -637,6 +754,7 @@ eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_ma
     M.fmask = ctx->fmask0;
     M.iptr = ctx->iptr;
     M.ient = ctx->ient;
+    M.islot = ctx->islot;
     M.maxc = ctx->maxc;
     M.rpb = ctx->rpb_ns;
     // with the multigrid active, the assembly also writes the finest level's

@@ -816,13 +816,16 @@ Dims dims_of(const MGLevel &L) { return Dims{{L.n[0], L.n[1], L.n[2]}}; }
 
 // Node graph of a simplex mesh: sorted columns per row (self included), the
 // diagonal position per row and, per element, the position of each node
-// pair (a, b) in row a.
+// pair (a, b) in row a.  Grouped by node, the incidence entries (element << 2
+// | local node a) and, per entry, the block slots of its row: byte k of
+// islot is the position, within row a, of the column of local node
+// (a + k) mod nn.
 constexpr int64_t NS_PAIRS = 512;   // (row, element) pairs per momentum-assembly workgroup
 
 eft_status eft_build_graph(int64_t N, int64_t E, int nn, const int32_t *conn, std::vector<int32_t> &rowptr,
                            std::vector<int32_t> &col, std::vector<int32_t> &diag, std::vector<int32_t> &epos,
-                           std::vector<int32_t> &iptr, std::vector<int32_t> &ient, int &maxc, int &rpb,
-                           int &rpb_ns, std::string &err)
+                           std::vector<int32_t> &iptr, std::vector<int32_t> &ient, std::vector<uint32_t> &islot,
+                           int &maxc, int &rpb, int &rpb_ns, std::string &err)
 {
     if (E >= (1LL << 29) || (int64_t)E * nn >= 2000000000LL) {
         err = "too many elements for 32-bit incidence entries";
@@ -884,6 +887,22 @@ eft_status eft_build_graph(int64_t N, int64_t E, int nn, const int32_t *conn, st
     }
     maxc = 1;
     for (int64_t p = 0; p < N; ++p) maxc = std::max(maxc, rowptr[p + 1] - rowptr[p]);
+    if (maxc > 255) {
+        err = "a node couples to more than 255 nodes";
+        return EFT_EINVAL;
+    }
+    islot.assign((size_t)E * nn, 0);
+    for (int64_t p = 0; p < N; ++p)
+        for (int64_t t = ioff[p]; t < ioff[p + 1]; ++t) {
+            const int64_t e = ient[t] >> 2;
+            const int a = ient[t] & 3;
+            uint32_t w = 0;
+            for (int k = 0; k < nn; ++k) {
+                const int b = (a + k) % nn;
+                w |= (uint32_t)(epos[(size_t)e * nn * nn + a * nn + b] - rowptr[p]) << (8 * k);
+            }
+            islot[t] = w;
+        }
     // rows per band-assembly workgroup: about two incident elements per
     // thread, and the row accumulators within 40 KB of LDS (a B-system block
     // accumulates 1 + 3 x 3 numbers, 11 doubles with the odd padding; a
@@ -988,11 +1007,13 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
             }
         }
         std::vector<int32_t> rowptr, col, diag, epos, iptr, ient;
+        std::vector<uint32_t> islot;
         int rpb_band = 1;   // (no band systems on the coarse levels)
-        EFT_TRY(eft_build_graph(C.N, C.E, nn, conn.data(), rowptr, col, diag, epos, iptr, ient, C.maxc, rpb_band,
-                                C.rpb, ctx->err));
+        EFT_TRY(eft_build_graph(C.N, C.E, nn, conn.data(), rowptr, col, diag, epos, iptr, ient, islot, C.maxc,
+                                rpb_band, C.rpb, ctx->err));
         EFT_TRY(dput(ctx, &C.iptr, iptr));
         EFT_TRY(dput(ctx, &C.ient, ient));
+        EFT_TRY(dput(ctx, &C.islot, islot));
         EFT_TRY(dput(ctx, &C.conn, conn));
         EFT_TRY(dput(ctx, &C.epos, epos));
         EFT_TRY(dput(ctx, &C.inj, inj32));
@@ -1086,7 +1107,7 @@ void eft_mg_free(eft_ctx *ctx)
         if (l > 0) {
             fr(L.conn); fr(L.epos); fr(L.inj); fr(L.xyz); fr(L.va); fr(L.acc); fr(L.rho); fr(L.mu); fr(L.as);
             fr(L.Ba); fr(L.smask); fr(L.vp); fr(L.R); fr(L.dir_node); fr(L.dir_mask); fr(L.A.rowptr); fr(L.A.col); fr(L.A.diag);
-            fr(L.A.val); fr(L.b); fr(L.iptr); fr(L.ient);
+            fr(L.A.val); fr(L.b); fr(L.iptr); fr(L.ient); fr(L.islot);
         }
         fr(L.fmask); fr(L.Dinv); fr(L.Dinv32); fr(L.x); fr(L.x2); fr(L.r); fr(L.A.val32); fr(L.A.val16);
         fr(L.crow);
@@ -1256,6 +1277,7 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
         M.fmask = C.fmask;
         M.iptr = C.iptr;
         M.ient = C.ient;
+        M.islot = C.islot;
         M.maxc = C.maxc;
         M.rpb = C.rpb;
         // intermediate levels: FP32 values (block inverses) and, with

@@ -182,8 +182,10 @@ def test_kernel_timer_counts(torch_cuda):
     ka = ctx.kernel_time(3)
     E, d = prob.n_elems, prob.dim
     # J in FP64 and, with the multigrid active, its FP32 or BF16 copy for the
-    # finest level written by the same launch; the free-dof bits read once
-    asm_b = nnzb * bs * bs * (8 + vbytes) + n * bs * 8 + E * (d + 1) * 4 + n * 8 * (d + bs + d + d + 2 + 1 * (1 + 6)) + n
+    # finest level written by the same launch, R written; read once: the
+    # connectivity, the node state (x, v, a, p, rho, mu, solid mask: 3d + 4
+    # numbers) and the free-dof bits
+    asm_b = nnzb * bs * bs * (8 + vbytes) + n * bs * 8 + E * (d + 1) * 4 + n * 8 * (3 * d + 4) + n
     assert ka["launches"] == 1 and ka["bytes"] == pytest.approx(asm_b, rel=1e-12)
     ctx.time_kernel()
     ctx.fgmres(-R)
