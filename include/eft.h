@@ -142,6 +142,14 @@ typedef struct {
                                     bands need
                                     more returns EFT_ENOMEM with the state
                                     unchanged; eft_step itself never allocates.   */
+    int32_t graphs;              /* 1: each column of a multigrid-preconditioned
+                                    momentum solve (V-cycle, SpMV, Gram-Schmidt)
+                                    is captured once into a HIP graph and replayed
+                                    (not while kernel timing, pair harvesting or
+                                    the learned preconditioner is on); 0: every
+                                    launch enqueued from the host.  Same kernels,
+                                    same results.  The graphs are kept until the
+                                    parameters or the workspace change.           */
 } eft_params;
 
 /* State at time level n (Sec. 2.1.2): values and rates.  DEVICE arrays. */

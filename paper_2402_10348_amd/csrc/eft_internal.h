@@ -251,6 +251,14 @@ struct eft_ctx {
     double *hscal = nullptr;                     // pinned host scalars
     int32_t nred = 0;
     KrylovWs kw;
+    // HIP graphs of the columns of a multigrid-preconditioned momentum solve,
+    // one per column index, with what they were captured on
+    struct ColGraphs {
+        std::vector<hipGraphExec_t> exec;
+        eft_params par{};
+        std::vector<const void *> key;
+        hipStream_t cap = nullptr;   // the stream they are recorded on (the caller's may be the null stream)
+    } colg;
     // geometric multigrid (structured Kuhn meshes with even cell counts)
     bool structured = false;
     std::vector<MGLevel> mg;

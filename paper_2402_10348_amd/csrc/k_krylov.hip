@@ -14,6 +14,7 @@
 // the normalization of v_{j+1}.  Dot products reduce
 // deterministically: each block writes a partial, a second kernel sums the
 // partials in a fixed order.
+#include <cstring>
 #include <mutex>
 #include <string>
 
@@ -494,6 +495,54 @@ static double spmv_bytes(const eft_matrix *A)
     return (double)A->nnzb * (b2 * vb + 4.0) + (double)(A->n + 1) * 4.0 + 2.0 * A->n * A->bs * 8.0;
 }
 
+// Enqueue column j of a momentum solve as a HIP graph: captured from the
+// column's launches the first time, replayed afterwards.  The cache holds one
+// graph per column index and belongs to the parameters, the Krylov workspace
+// and the matrix arrays it was captured on; any change drops it.
+template <typename F>
+static eft_status column_graph(eft_ctx *ctx, const eft_matrix *A, int j, int m, int64_t nd, F &column)
+{
+    auto &G = ctx->colg;
+    const KrylovWs &K = ctx->kw;
+    const MGLevel &F0 = ctx->mg[0];
+    const std::vector<const void *> key = {K.V, K.Z, K.w, K.part, K.small, K.flag, A->val, A->val32,
+                                           F0.A.val16, F0.A.val32, (const void *)(intptr_t)nd,
+                                           (const void *)(intptr_t)m};
+    if (G.key != key || std::memcmp(&G.par, &ctx->par, sizeof(eft_params)) != 0 || (int)G.exec.size() != m) {
+        for (hipGraphExec_t g : G.exec)
+            if (g) EFT_HIP(hipGraphExecDestroy(g));
+        G.exec.assign(m, nullptr);
+        G.key = key;
+        G.par = ctx->par;
+    }
+    if (!G.exec[j]) {
+        // recorded on the context's own capture stream (the null stream
+        // cannot be captured): the column enqueues on ctx->stream, which
+        // points there while recording; nothing executes until the launch
+        if (!G.cap) EFT_HIP(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        const hipStream_t s0 = ctx->stream;
+        const hipError_t be = hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal);
+        if (be != hipSuccess) EFT_HIP(be);
+        ctx->stream = G.cap;
+        const eft_status st = column(j);
+        const hipError_t e = hipStreamEndCapture(G.cap, &g);
+        ctx->stream = s0;
+        if (st != EFT_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        EFT_HIP(e);
+        hipGraphExec_t x = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        EFT_HIP(ie);
+        G.exec[j] = x;
+    }
+    EFT_HIP(hipGraphLaunch(G.exec[j], ctx->stream));
+    return EFT_OK;
+}
+
 eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, double *x, eft_solve_info *info,
                           double rtol)
 {
@@ -544,6 +593,68 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
     // first residual: r = b
     EFT_HIP(hipMemcpyAsync(K.r, b, sizeof(double) * nd, hipMemcpyDeviceToDevice, ctx->stream));
     double beta = bnorm;
+    // one column j of the Arnoldi process: preconditioner, product and
+    // orthogonalization (every kernel gated by the device flags)
+    auto column = [&](int j) -> eft_status {
+        double *vj = K.V + (int64_t)j * nd, *zj = K.Z + (int64_t)j * nd;
+        ctx->kt.tag = j;
+        if (mg)
+            EFT_TRY(eft_mg_vcycle(ctx, vj, zj, K.flag));
+        else if (learned)
+            EFT_TRY(eft_nn_precond(ctx, K.Dinv, vj, zj, K.flag));
+        else if (A == &ctx->J)
+            EFT_TRY(eft_bj_apply(ctx, bs, n, K.Dinv, vj, zj, K.flag));
+        else   // band systems (w is free until the product below)
+            EFT_TRY(eft_jacobi_apply(ctx, A, K.Dinv, vj, zj, K.w, ctx->par.band_sweeps, ctx->par.band_omega,
+                                     K.flag));
+        const int64_t slot = A == &ctx->J ? eft_kt_begin(ctx, EFT_KT_SPMV) : -1;
+        EFT_TRY(eft_spmv_flag(ctx, A, zj, K.w, K.flag));
+        eft_kt_end(ctx, slot, spmv_bytes(A), EFT_KT_SPMV);
+        if (harvest) EFT_TRY(eft_nn_store_pair(ctx, K.Dinv, K.w, zj, (NS.next + j) % NS.cap_pairs, K.flag));
+        // pass 1: dots with V[0..j] and ||w||^2
+        dim3 g1(nblk, (j + 2 + KC - 1) / KC);
+        hipLaunchKernelGGL(k_mdot, g1, dim3(RB), 0, ctx->stream, K.V, nd, j + 1, 1, K.w, K.part, nblk,
+                           K.flag, 0);
+        hipLaunchKernelGGL(k_sum_parts, dim3(j + 2), dim3(RB), 0, ctx->stream, K.part, nblk, small + L.h(),
+                           K.flag, 0);
+        if (j + 1 <= 32) {
+            // pass 1's update with pass 2's dots (used if pass 2 is taken)
+            const int nv1 = j + 1;
+            if (nv1 <= 8)
+                hipLaunchKernelGGL(k_maxpy_mdot<8>, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, nv1,
+                                   small + L.h(), K.w, K.part, nblk, K.flag);
+            else if (nv1 <= 16)
+                hipLaunchKernelGGL(k_maxpy_mdot<16>, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, nv1,
+                                   small + L.h(), K.w, K.part, nblk, K.flag);
+            else
+                hipLaunchKernelGGL(k_maxpy_mdot<32>, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, nv1,
+                                   small + L.h(), K.w, K.part, nblk, K.flag);
+            hipLaunchKernelGGL(k_close_pass, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, nv1, small, m,
+                               j, 1, K.flag);
+            // the second pass's update (when taken) with the normalization
+            hipLaunchKernelGGL(k_update_normalize, dim3(sg), dim3(RB), 0, ctx->stream, K.V, nd, nv1, K.w,
+                               K.V + (int64_t)(j + 1) * nd, small, m, K.flag);
+        } else {
+            hipLaunchKernelGGL(k_maxpy, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, j + 1, small + L.h(),
+                               -1.0, K.w, K.part, nblk, K.flag, 0);
+            hipLaunchKernelGGL(k_close_pass, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, 0, small, m, j,
+                               1, K.flag);
+            // pass 2's dots (gated)
+            dim3 g2(nblk, (j + 1 + KC - 1) / KC);
+            hipLaunchKernelGGL(k_mdot, g2, dim3(RB), 0, ctx->stream, K.V, nd, j + 1, 0, K.w, K.part, nblk,
+                               K.flag, 1);
+            hipLaunchKernelGGL(k_sum_parts, dim3(j + 1), dim3(RB), 0, ctx->stream, K.part, nblk,
+                               small + L.h2(), K.flag, 1);
+            // pass 2 (gated)
+            hipLaunchKernelGGL(k_maxpy, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, j + 1, small + L.h2(),
+                               -1.0, K.w, K.part, nblk, K.flag, 1);
+            hipLaunchKernelGGL(k_close_pass, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, 0, small, m, j,
+                               2, K.flag);
+            hipLaunchKernelGGL(k_normalize, dim3(sg), dim3(RB), 0, ctx->stream, K.w,
+                               K.V + (int64_t)(j + 1) * nd, nd, small, m, j, K.flag);
+        }
+        return EFT_OK;
+    };
     for (;;) {
         const double rel = beta / bnorm;
         inf.rel_res = rel;
@@ -566,64 +677,13 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
         int j_prev = 0;
         for (int j0 = 0, j1 = 0; j0 < mc; j0 = j1) {
             j1 = std::min(mc, j0 + chunk);
+            // the momentum system's columns as HIP graphs when asked for and
+            // nothing host-side watches the launches
+            const bool graph = ctx->par.graphs && mg && !learned && !harvest && A == &ctx->J && ctx->kt.mask == 0 &&
+                               !ctx->no_alloc;
             for (int j = j0; j < j1; ++j) {
-                double *vj = K.V + (int64_t)j * nd, *zj = K.Z + (int64_t)j * nd;
-                ctx->kt.tag = j;
-                if (mg)
-                    EFT_TRY(eft_mg_vcycle(ctx, vj, zj, K.flag));
-                else if (learned)
-                    EFT_TRY(eft_nn_precond(ctx, K.Dinv, vj, zj, K.flag));
-                else if (A == &ctx->J)
-                    EFT_TRY(eft_bj_apply(ctx, bs, n, K.Dinv, vj, zj, K.flag));
-                else   // band systems (w is free until the product below)
-                    EFT_TRY(eft_jacobi_apply(ctx, A, K.Dinv, vj, zj, K.w, ctx->par.band_sweeps, ctx->par.band_omega,
-                                             K.flag));
-                const int64_t slot = A == &ctx->J ? eft_kt_begin(ctx, EFT_KT_SPMV) : -1;
-                EFT_TRY(eft_spmv_flag(ctx, A, zj, K.w, K.flag));
-                eft_kt_end(ctx, slot, spmv_bytes(A), EFT_KT_SPMV);
-                if (harvest) EFT_TRY(eft_nn_store_pair(ctx, K.Dinv, K.w, zj, (NS.next + j) % NS.cap_pairs, K.flag));
-                // pass 1: dots with V[0..j] and ||w||^2
-                dim3 g1(nblk, (j + 2 + KC - 1) / KC);
-                hipLaunchKernelGGL(k_mdot, g1, dim3(RB), 0, ctx->stream, K.V, nd, j + 1, 1, K.w, K.part, nblk,
-                                   K.flag, 0);
-                hipLaunchKernelGGL(k_sum_parts, dim3(j + 2), dim3(RB), 0, ctx->stream, K.part, nblk, small + L.h(),
-                                   K.flag, 0);
-                if (j + 1 <= 32) {
-                    // pass 1's update with pass 2's dots (used if pass 2 is taken)
-                    const int nv1 = j + 1;
-                    if (nv1 <= 8)
-                        hipLaunchKernelGGL(k_maxpy_mdot<8>, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, nv1,
-                                           small + L.h(), K.w, K.part, nblk, K.flag);
-                    else if (nv1 <= 16)
-                        hipLaunchKernelGGL(k_maxpy_mdot<16>, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, nv1,
-                                           small + L.h(), K.w, K.part, nblk, K.flag);
-                    else
-                        hipLaunchKernelGGL(k_maxpy_mdot<32>, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, nv1,
-                                           small + L.h(), K.w, K.part, nblk, K.flag);
-                    hipLaunchKernelGGL(k_close_pass, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, nv1, small, m,
-                                       j, 1, K.flag);
-                    // the second pass's update (when taken) with the normalization
-                    hipLaunchKernelGGL(k_update_normalize, dim3(sg), dim3(RB), 0, ctx->stream, K.V, nd, nv1, K.w,
-                                       K.V + (int64_t)(j + 1) * nd, small, m, K.flag);
-                } else {
-                    hipLaunchKernelGGL(k_maxpy, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, j + 1, small + L.h(),
-                                       -1.0, K.w, K.part, nblk, K.flag, 0);
-                    hipLaunchKernelGGL(k_close_pass, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, 0, small, m, j,
-                                       1, K.flag);
-                    // pass 2's dots (gated)
-                    dim3 g2(nblk, (j + 1 + KC - 1) / KC);
-                    hipLaunchKernelGGL(k_mdot, g2, dim3(RB), 0, ctx->stream, K.V, nd, j + 1, 0, K.w, K.part, nblk,
-                                       K.flag, 1);
-                    hipLaunchKernelGGL(k_sum_parts, dim3(j + 1), dim3(RB), 0, ctx->stream, K.part, nblk,
-                                       small + L.h2(), K.flag, 1);
-                    // pass 2 (gated)
-                    hipLaunchKernelGGL(k_maxpy, dim3(nblk), dim3(RB), 0, ctx->stream, K.V, nd, j + 1, small + L.h2(),
-                                       -1.0, K.w, K.part, nblk, K.flag, 1);
-                    hipLaunchKernelGGL(k_close_pass, dim3(1), dim3(RB), 0, ctx->stream, K.part, nblk, 0, small, m, j,
-                                       2, K.flag);
-                    hipLaunchKernelGGL(k_normalize, dim3(sg), dim3(RB), 0, ctx->stream, K.w,
-                                       K.V + (int64_t)(j + 1) * nd, nd, small, m, j, K.flag);
-                }
+                if (graph) EFT_TRY(column_graph(ctx, A, j, m, nd, column));
+                else EFT_TRY(column(j));
             }
             EFT_HIP(hipGetLastError());
             ctx->kt.tag = -1;

@@ -171,6 +171,7 @@ class Params:
     mg_galerkin: int = 0       # multigrid coarse operators: 0 rediscretized, 1 Galerkin P^T A P
     nn_maxit: int = 0          # learned preconditioner: iterations before block Jacobi takes over (0: lin_maxit/2)
     band_reserve: float = 0.0  # band storage for all indicators together, in mesh element counts (0: auto)
+    graphs: int = 1           # momentum Krylov columns captured into HIP graphs and replayed
 
 
 @dataclass
