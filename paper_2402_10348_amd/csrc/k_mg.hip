@@ -908,7 +908,8 @@ eft_status eft_build_graph(int64_t N, int64_t E, int nn, const int32_t *conn, st
     // accumulates 1 + 3 x 3 numbers, 11 doubles with the odd padding; a
     // residual row 7)
     const int64_t rowbytes = (int64_t)maxc * 11 * 8 + 7 * 8;
-    rpb = (int)std::max<int64_t>(1, std::min<int64_t>(512 / maxinc, 40960 / rowbytes));
+    // (at most 64: the units stage their rows' metadata in LDS arrays of 64)
+    rpb = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(512 / maxinc, 40960 / rowbytes), 64));
     // the momentum/mass assembly (padded nn x nn blocks): about NS_PAIRS
     // (row, element) pairs per 256-thread workgroup, within 64 KB of LDS (its
     // register count allows two workgroups per compute unit)

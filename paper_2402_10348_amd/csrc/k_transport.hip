@@ -369,6 +369,7 @@ struct TrArgs {
     const int32_t *iptr, *ient;             // global node -> (element << 2 | local node)
     const uint8_t *eflag;                   // [E] 1 for band elements
     const int32_t *conn, *epos, *grow, *gcol;
+    const uint32_t *islot;                  // per incidence entry: its row's block slots (eft_build_graph)
     const int32_t *brow, *bcol;             // band pattern, band-local columns
     const uint8_t *fre;                     // band row is free (else a unit row with residual 0)
     const double *xyz, *va;
@@ -573,41 +574,69 @@ __global__ __launch_bounds__(256) void k_seg_sum2(const double *part, const int3
     }
 }
 
+// Rows of one work unit staged in LDS by the assembly units: per row its
+// first block in the band pattern (kb[nrow] closes the range: the unit's
+// rows are consecutive band rows, so their blocks are contiguous), the first
+// block and the length of its global row, and whether it is solved for.
+struct UnitRows {
+    const int *kb, *gb0, *glen, *fre;
+    int nrow;
+};
+
+// Local row of block k of the unit's block range (the last row starting at
+// or before it; every row has its diagonal block).
+__device__ __forceinline__ int unit_row(const UnitRows &u, int k)
+{
+    int lo = 0, hi = u.nrow - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (u.kb[mid] <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Slot of band block kb (row lr) among the global row's columns: the
+// accumulators are laid out by global row position.
+__device__ __forceinline__ int unit_slot(const TrArgs &a, const UnitRows &u, int lr, int64_t kb)
+{
+    const int32_t col = a.node[a.bcol[kb]];
+    const int32_t *gc = a.gcol + u.gb0[lr];
+    int lo = 0, hi = u.glen[lr] - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (gc[mid] < col) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Rows [r0, r0 + nrow) of a scalar or block band system out of LDS, flat
+// over the unit's residual entries and blocks (one block per thread); rows
+// that keep their value become unit rows with residual 0.
 template <int BS>
-__device__ __forceinline__ void band_rows_out(const TrArgs &a, int64_t r0, int64_t r1, const double *accJ,
+__device__ __forceinline__ void band_rows_out(const TrArgs &a, int64_t r0, const UnitRows &u, const double *accJ,
                                               const double *accR)
 {
     constexpr int B2 = BS * BS, BP = B2 | 1, RP = BS | 1;
-    for (int64_t r = r0; r < r1; ++r) {
-        const int lr = (int)(r - r0);
-        const int64_t kb = a.brow[r], len = a.brow[r + 1] - kb;
-        if (!a.fre[r]) {   // a node that keeps its value: residual 0, unit row
-            if (threadIdx.x < BS) a.R[r * BS + threadIdx.x] = 0.0;
-            for (int t = threadIdx.x; t < len; t += blockDim.x) {
-                double *dst = a.J + (kb + t) * B2;
-                const bool dg = a.bcol[kb + t] == r;
+    for (int t = threadIdx.x; t < u.nrow * BS; t += blockDim.x) {
+        const int lr = t / BS, i = t - lr * BS;
+        a.R[r0 * BS + t] = u.fre[lr] ? accR[lr * RP + i] : 0.0;
+    }
+    const int kb0 = u.kb[0], nblk = u.kb[u.nrow] - kb0;
+    for (int t = threadIdx.x; t < nblk; t += blockDim.x) {
+        const int lr = unit_row(u, kb0 + t);
+        const int64_t kb = kb0 + t;
+        double *dst = a.J + kb * B2;
+        if (!u.fre[lr]) {
+            const bool dg = a.bcol[kb] == r0 + lr;
 #pragma unroll
-                for (int v = 0; v < B2; ++v) dst[v] = (dg && v % (BS + 1) == 0) ? 1.0 : 0.0;
-            }
+            for (int v = 0; v < B2; ++v) dst[v] = (dg && v % (BS + 1) == 0) ? 1.0 : 0.0;
             continue;
         }
-        if (threadIdx.x < BS) a.R[r * BS + threadIdx.x] = accR[lr * RP + threadIdx.x];
-        const int64_t g = a.node[r];
-        const int32_t *gc = a.gcol + a.grow[g];
-        const int glen = a.grow[g + 1] - a.grow[g];
-        for (int t = threadIdx.x; t < len; t += blockDim.x) {
-            const int32_t col = a.node[a.bcol[kb + t]];
-            int lo = 0, hi = glen - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (gc[mid] < col) lo = mid + 1;
-                else hi = mid;
-            }
-            const double *src = accJ + ((int64_t)lr * a.maxc + lo) * BP;
-            double *dst = a.J + (kb + t) * B2;
+        const double *src = accJ + ((int64_t)lr * a.maxc + unit_slot(a, u, lr, kb)) * BP;
 #pragma unroll
-            for (int v = 0; v < B2; ++v) dst[v] = src[v];
-        }
+        for (int v = 0; v < B2; ++v) dst[v] = src[v];
     }
 }
 
@@ -635,58 +664,45 @@ __device__ __forceinline__ double b_block_entry(const double *acc, int c, int cc
     return (c == cc ? acc[0] : 0.0) - s;
 }
 
-// Rows [r0, r1) of the B system out of LDS (blocks expanded from their
-// accumulators, one block per thread).
+// Rows [r0, r0 + nrow) of the B system out of LDS (blocks expanded from
+// their accumulators), flat over the unit's blocks, one block per thread.
 template <int D>
-__device__ __forceinline__ void band_rows_out_b(const TrArgs &a, int64_t r0, int64_t r1, const double *accJ,
+__device__ __forceinline__ void band_rows_out_b(const TrArgs &a, int64_t r0, const UnitRows &u, const double *accJ,
                                                 const double *accR)
 {
     constexpr int NVv = NV<D>::v, B2 = NVv * NVv, BP = BAcc<D>::P, RP = NVv | 1;
-    for (int64_t r = r0; r < r1; ++r) {
-        const int lr = (int)(r - r0);
-        const int64_t kb = a.brow[r], len = a.brow[r + 1] - kb;
-        if (!a.fre[r]) {   // a node that keeps its value: residual 0, unit row
-            if (threadIdx.x < NVv) a.R[r * NVv + threadIdx.x] = 0.0;
-            for (int t = threadIdx.x; t < len; t += blockDim.x) {
-                const bool dg = a.bcol[kb + t] == r;
-                const bool full = a.full_b || !a.Jc;
-                double *dst = full ? a.J + (kb + t) * B2 : a.Jd + r * B2;
-                if (dg || full)
+    for (int t = threadIdx.x; t < u.nrow * NVv; t += blockDim.x) {
+        const int lr = t / NVv, i = t - lr * NVv;
+        a.R[r0 * NVv + t] = u.fre[lr] ? accR[lr * RP + i] : 0.0;
+    }
+    const bool full = a.full_b || !a.Jc;
+    const int kb0 = u.kb[0], nblk = u.kb[u.nrow] - kb0;
+    for (int t = threadIdx.x; t < nblk; t += blockDim.x) {
+        const int lr = unit_row(u, kb0 + t);
+        const int64_t kb = kb0 + t, r = r0 + lr;
+        const bool dg = a.bcol[kb] == r;
+        double *dst = full ? a.J + kb * B2 : a.Jd + r * B2;
+        if (!u.fre[lr]) {   // a node that keeps its value: unit row
+            if (dg || full)
 #pragma unroll
-                    for (int v = 0; v < B2; ++v) dst[v] = (dg && v % (NVv + 1) == 0) ? 1.0 : 0.0;
-                if (a.Jc) {   // compact unit block: s1 = 1, M = 0
-                    double *dc = a.Jc + (kb + t) * BAcc<D>::N;
+                for (int v = 0; v < B2; ++v) dst[v] = (dg && v % (NVv + 1) == 0) ? 1.0 : 0.0;
+            if (a.Jc) {   // compact unit block: s1 = 1, M = 0
+                double *dc = a.Jc + kb * BAcc<D>::N;
 #pragma unroll
-                    for (int v = 0; v < BAcc<D>::N; ++v) dc[v] = (dg && v == 0) ? 1.0 : 0.0;
-                }
+                for (int v = 0; v < BAcc<D>::N; ++v) dc[v] = (dg && v == 0) ? 1.0 : 0.0;
             }
             continue;
         }
-        if (threadIdx.x < NVv) a.R[r * NVv + threadIdx.x] = accR[lr * RP + threadIdx.x];
-        const int64_t g = a.node[r];
-        const int32_t *gc = a.gcol + a.grow[g];
-        const int glen = a.grow[g + 1] - a.grow[g];
-        for (int t = threadIdx.x; t < len; t += blockDim.x) {
-            const int32_t col = a.node[a.bcol[kb + t]];
-            int lo = 0, hi = glen - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (gc[mid] < col) lo = mid + 1;
-                else hi = mid;
-            }
-            const double *src = accJ + ((int64_t)lr * a.maxc + lo) * BP;
-            const bool full = a.full_b || !a.Jc;
-            double *dst = full ? a.J + (kb + t) * B2 : a.Jd + r * B2;
-            if (full || a.bcol[kb + t] == r)   // (the diagonal blocks feed the block inverses)
+        const double *src = accJ + ((int64_t)lr * a.maxc + unit_slot(a, u, lr, kb)) * BP;
+        if (full || dg)   // (the diagonal blocks feed the block inverses)
 #pragma unroll
-                for (int c = 0; c < NVv; ++c)
+            for (int c = 0; c < NVv; ++c)
 #pragma unroll
-                    for (int cc = 0; cc < NVv; ++cc) dst[c * NVv + cc] = b_block_entry<D>(src, c, cc);
-            if (a.Jc) {   // the accumulators themselves: s1, then M
-                double *dc = a.Jc + (kb + t) * BAcc<D>::N;
+                for (int cc = 0; cc < NVv; ++cc) dst[c * NVv + cc] = b_block_entry<D>(src, c, cc);
+        if (a.Jc) {   // the accumulators themselves: s1, then M
+            double *dc = a.Jc + kb * BAcc<D>::N;
 #pragma unroll
-                for (int v = 0; v < BAcc<D>::N; ++v) dc[v] = src[v];
-            }
+            for (int v = 0; v < BAcc<D>::N; ++v) dc[v] = src[v];
         }
     }
 }
@@ -707,19 +723,27 @@ __device__ __forceinline__ void ac_rows_unit(const TrArgs &a, int64_t r0, double
     // per row, staged in LDS (at most 64 rows): first incidence, end of the
     // incidences (the first again for a row that keeps its value, written
     // as a unit row), first block of the row in the global pattern
-    __shared__ int maxinc, s_ip0[64], s_ip1[64], s_gb0[64];
+    // and, for the write-out, the row's first band block, the length of its
+    // global row and whether it is solved for
+    __shared__ int maxinc, s_ip0[64], s_ip1[64], s_gb0[64], s_kb[65], s_glen[64], s_fre[64];
     if (threadIdx.x == 0) maxinc = 0;
     __syncthreads();
     const int nrow = (int)(r1 - r0);
     if (threadIdx.x < nrow) {
         const int64_t gg = a.node[r0 + threadIdx.x];
         const int i0 = a.iptr[gg], i1 = a.iptr[gg + 1];
+        const int fr = a.fre[r0 + threadIdx.x];
         s_ip0[threadIdx.x] = i0;
-        s_ip1[threadIdx.x] = a.fre[r0 + threadIdx.x] ? i1 : i0;
+        s_ip1[threadIdx.x] = fr ? i1 : i0;
         s_gb0[threadIdx.x] = a.grow[gg];
+        s_glen[threadIdx.x] = a.grow[gg + 1] - a.grow[gg];
+        s_fre[threadIdx.x] = fr;
+        s_kb[threadIdx.x] = a.brow[r0 + threadIdx.x];
         atomicMax(&maxinc, i1 - i0);
     }
+    if (threadIdx.x == 0) s_kb[nrow] = a.brow[r1];
     __syncthreads();
+    const UnitRows urows{s_kb, s_gb0, s_glen, s_fre, nrow};
     {
         // pairs dealt row-interleaved: consecutive lanes take different
         // rows, so the LDS atomics of one wavefront rarely hit one block
@@ -730,10 +754,13 @@ __device__ __forceinline__ void ac_rows_unit(const TrArgs &a, int64_t r0, double
             const int32_t ent = a.ient[ii];
             const int64_t e = ent >> 2;
             const int la = ent & 3;
-            // the element's nodes are loaded together with its band flag
+            // the element's nodes (loaded together with its band flag),
+            // rotated so that the row node comes first: local node b is node
+            // (la + b) mod NN of the connectivity, and every index below is a
+            // compile-time constant
             int64_t nid[NN];
 #pragma unroll
-            for (int b = 0; b < NN; ++b) nid[b] = a.conn[e * NN + b];
+            for (int b = 0; b < NN; ++b) nid[b] = a.conn[e * NN + (la + b < NN ? la + b : la + b - NN)];
             if (!a.eflag[e]) continue;
             double X[NN][D], v[NN][D], f[NN], fd[NN];
 #pragma unroll
@@ -751,6 +778,28 @@ __device__ __forceinline__ void ac_rows_unit(const TrArgs &a, int64_t r0, double
             }
             double dN[NN][D], G[D][D];
             const double vol = simplex_geom<D>(X, dN, G);
+            // G belongs to the reference map with its origin at the element's
+            // first node in the connectivity (local o0 after the rotation):
+            // the sum of grad N grad N^T over the other nodes
+            {
+                const int o0 = la == 0 ? 0 : NN - la;
+#pragma unroll
+                for (int i = 0; i < D; ++i)
+#pragma unroll
+                    for (int j = 0; j < D; ++j) G[i][j] = 0.0;
+#pragma unroll
+                for (int b = 0; b < NN; ++b) {
+                    const double c = b == o0 ? 0.0 : 1.0;
+#pragma unroll
+                    for (int i = 0; i < D; ++i)
+#pragma unroll
+                        for (int j = i; j < D; ++j) G[i][j] += c * dN[b][i] * dN[b][j];
+                }
+#pragma unroll
+                for (int i = 0; i < D; ++i)
+#pragma unroll
+                    for (int j = 0; j < i; ++j) G[i][j] = G[j][i];
+            }
             double GG = 0.0;
 #pragma unroll
             for (int i = 0; i < D; ++i)
@@ -766,12 +815,12 @@ __device__ __forceinline__ void ac_rows_unit(const TrArgs &a, int64_t r0, double
             }
             double gga = 0.0, gab[NN];
 #pragma unroll
-            for (int j = 0; j < D; ++j) gga += dN[la][j] * gf[j];
+            for (int j = 0; j < D; ++j) gga += dN[0][j] * gf[j];
 #pragma unroll
             for (int b = 0; b < NN; ++b) {
                 double s = 0.0;
 #pragma unroll
-                for (int j = 0; j < D; ++j) s += dN[la][j] * dN[b][j];
+                for (int j = 0; j < D; ++j) s += dN[0][j] * dN[b][j];
                 gab[b] = s;
             }
             const double w = vol * Rule<D>::WF;
@@ -815,24 +864,24 @@ __device__ __forceinline__ void ac_rows_unit(const TrArgs &a, int64_t r0, double
                     for (int j = 0; j < D; ++j) s += vq[j] * dN[b][j];
                     u[b] = s;
                 }
-                const double Na = shape_at<D>(q, la);
-                re += w * (Na * (fdq + vg) + gamma * (kh * gga + Na * react) + tau * u[la] * Rphi);
+                const double Na = shape_at<D>(q, 0);
+                re += w * (Na * (fdq + vg) + gamma * (kh * gga + Na * react) + tau * u[0] * Rphi);
 #pragma unroll
                 for (int ib = 0; ib < NN; ++ib) {
                     const double Nb = shape_at<D>(q, ib);
                     const double lin = ct * Nb + al * u[ib];
                     K[ib] += w * (Na * lin + al * gamma * (kh * gab[ib] + Na * sh * Nb) +
-                                  tau * u[la] * (lin + al * gamma * sh * Nb));
+                                  tau * u[0] * (lin + al * gamma * sh * Nb));
                 }
             }
             atomicAdd(accR + lr, re);
-            const int64_t gb0 = s_gb0[lr];
+            const uint32_t sl = a.islot[ii];   // byte b: slot of (rotated) local node b
 #pragma unroll
-            for (int ib = 0; ib < NN; ++ib) atomicAdd(accJ + (int64_t)lr * a.maxc + (a.epos[e * NN * NN + la * NN + ib] - gb0), K[ib]);
+            for (int ib = 0; ib < NN; ++ib) atomicAdd(accJ + (int64_t)lr * a.maxc + ((sl >> (8 * ib)) & 0xff), K[ib]);
         }
     }
     __syncthreads();
-    band_rows_out<1>(a, r0, r1, accJ, accR);
+    band_rows_out<1>(a, r0, urows, accJ, accR);
 }
 
 template <int D>
@@ -881,19 +930,27 @@ __device__ __forceinline__ void b_rows_unit(const TrArgs &a, int64_t r0, const d
     // per row, staged in LDS (at most 64 rows): first incidence, end of the
     // incidences (the first again for a row that keeps its value, written
     // as a unit row), first block of the row in the global pattern
-    __shared__ int maxinc, s_ip0[64], s_ip1[64], s_gb0[64];
+    // and, for the write-out, the row's first band block, the length of its
+    // global row and whether it is solved for
+    __shared__ int maxinc, s_ip0[64], s_ip1[64], s_gb0[64], s_kb[65], s_glen[64], s_fre[64];
     if (threadIdx.x == 0) maxinc = 0;
     __syncthreads();
     const int nrow = (int)(r1 - r0);
     if (threadIdx.x < nrow) {
         const int64_t gg = a.node[r0 + threadIdx.x];
         const int i0 = a.iptr[gg], i1 = a.iptr[gg + 1];
+        const int fr = a.fre[r0 + threadIdx.x];
         s_ip0[threadIdx.x] = i0;
-        s_ip1[threadIdx.x] = a.fre[r0 + threadIdx.x] ? i1 : i0;
+        s_ip1[threadIdx.x] = fr ? i1 : i0;
         s_gb0[threadIdx.x] = a.grow[gg];
+        s_glen[threadIdx.x] = a.grow[gg + 1] - a.grow[gg];
+        s_fre[threadIdx.x] = fr;
+        s_kb[threadIdx.x] = a.brow[r0 + threadIdx.x];
         atomicMax(&maxinc, i1 - i0);
     }
+    if (threadIdx.x == 0) s_kb[nrow] = a.brow[r1];
     __syncthreads();
+    const UnitRows urows{s_kb, s_gb0, s_glen, s_fre, nrow};
     {
         // pairs dealt row-interleaved: consecutive lanes take different
         // rows, so the LDS atomics of one wavefront rarely hit one block
@@ -1024,11 +1081,11 @@ __device__ __forceinline__ void b_rows_unit(const TrArgs &a, int64_t r0, const d
             }
 #pragma unroll
             for (int c = 0; c < NVv; ++c) atomicAdd(accR + lr * RP + c, re[c]);
-            const int64_t gb0 = s_gb0[lr];
+            const uint32_t sl = a.islot[ii];   // byte k: slot of local node (la + k) mod NN
 #pragma unroll
             for (int ib = 0; ib < NN; ++ib) {
                 const double s2 = al * S2[ib];
-                double *blk = accJ + ((int64_t)lr * a.maxc + (a.epos[e * NN * NN + la * NN + ib] - gb0)) * BP;
+                double *blk = accJ + ((int64_t)lr * a.maxc + ((sl >> (8 * ((ib - la + NN) % NN))) & 0xff)) * BP;
                 atomicAdd(blk, S1[ib]);
 #pragma unroll
                 for (int i = 0; i < D; ++i)
@@ -1041,7 +1098,7 @@ __device__ __forceinline__ void b_rows_unit(const TrArgs &a, int64_t r0, const d
         }
     }
     __syncthreads();
-    band_rows_out_b<D>(a, r0, r1, accJ, accR);
+    band_rows_out_b<D>(a, r0, urows, accJ, accR);
 }
 
 template <int D>
@@ -1592,6 +1649,7 @@ static TrArgs tr_args(eft_ctx *ctx, const Band &B, const double *lx, const doubl
     a.eflag = B.eflag;
     a.conn = ctx->conn;
     a.epos = ctx->epos;
+    a.islot = ctx->islot;
     a.grow = ctx->J.rowptr;
     a.gcol = ctx->J.col;
     a.brow = B.rowptr;
