@@ -100,7 +100,14 @@ typedef struct {
                                     (point-block Jacobi otherwise, and always for
                                     the band systems); 2 learned preconditioner
                                     (block Jacobi plus the network correction, see
-                                    eft_nn_init) for the momentum/mass block      */
+                                    eft_nn_init) for the momentum/mass block; 3
+                                    block ILU(0) of the momentum/mass matrix in the
+                                    natural row order (factors on the matrix
+                                    pattern, level-scheduled factorization and
+                                    triangular solves; point-block Jacobi for the
+                                    band systems).  The factors' storage (one more
+                                    copy of the matrix values) is reserved by
+                                    eft_create / eft_set_params.                   */
     int32_t precision;           /* 0 FP64; 1 FP32 Jacobian values + FP64 rest     */
     double band_flat;            /* band seed: |phi^n| < 1 - band_flat; a negative
                                     value seeds every cell, so the transport runs
@@ -245,6 +252,15 @@ eft_status eft_matrix_export(eft_ctx *ctx, const eft_matrix *A, int32_t *rowptr,
  * its solves use point-block Jacobi (the multigrid hierarchy is built by the
  * assembly).  For solving other systems of the same pattern, and tests. */
 eft_status eft_matrix_import(eft_ctx *ctx, eft_matrix *A, const double *val);
+
+/* Block ILU(0) factors of the current momentum/mass matrix (test hook,
+ * precond = 3): factors it and copies the factors into DEVICE buffers lu
+ * [nnzb][bs][bs] (the strictly lower blocks hold L, whose diagonal blocks
+ * are the identity and not stored; the others U) and dinv [n][bs][bs] =
+ * U_ii^-1; either may be null.  L U equals the matrix on its pattern
+ * (standard block ILU(0), natural order).  Synchronizes the context stream.
+ * EFT_EINVAL without precond = 3, EFT_EBREAKDOWN on a singular U_ii. */
+eft_status eft_ilu_export(eft_ctx *ctx, double *lu, double *dinv);
 
 /* Multigrid hierarchy of the momentum/mass preconditioner (test hook):
  * level 0 is the mesh itself; level l has cells of 2^l mesh cells.  With

@@ -112,6 +112,7 @@ def _setup(L):
     L.orc_threads.restype = C.c_int
     L.orc_graph_nnz.restype = C.c_int
     L.orc_fgmres.restype = C.c_int
+    L.orc_ilu0.restype = C.c_int
     L.orc_mobility.restype = C.c_double
     L.orc_beta.restype = C.c_double
     L.orc_step.restype = C.c_int
@@ -308,6 +309,28 @@ class Case:
                               restart or self.P.restart, maxit or self.P.lin_maxit,
                               C.c_double(self.P.lin_rtol if rtol is None else rtol), C.byref(its), C.byref(rr))
         return x, dict(status=st, iters=its.value, relres=rr.value)
+
+    def ilu0(self, J):
+        """Block ILU(0) factors of J on the node graph (natural order):
+        (lu [nnz][bs*bs] holding L below and U on and above the diagonal,
+        dinv [N][bs*bs] = U_ii^-1, status 0 or 1 + the first singular row)."""
+        rowptr, col = self.graph()
+        J = _f64(J)
+        bs = int(round((J.size // col.shape[0]) ** 0.5))
+        lu = np.zeros_like(J)
+        dinv = np.zeros((self.N, bs * bs))
+        st = lib().orc_ilu0(bs, self.N, _i(rowptr), _i(col), _d(J), _d(lu), _d(dinv))
+        return lu, dinv, st
+
+    def ilu0_apply(self, lu, dinv, r):
+        """z = (L U)^-1 r with the factors of ilu0."""
+        rowptr, col = self.graph()
+        lu = _f64(lu)
+        bs = int(round((lu.size // col.shape[0]) ** 0.5))
+        r = _f64(r)
+        z = np.zeros_like(r)
+        lib().orc_ilu0_apply(bs, self.N, _i(rowptr), _i(col), _d(lu), _d(_f64(dinv)), _d(r), _d(z))
+        return z
 
     # ---------------------------------------------------------- diagnostics
     def center_of_mass(self, phi):

@@ -20,11 +20,15 @@
  *   - Allen-Cahn semi-discrete form with SUPG            eq. (PPV_AC) and tau_phi
  *   - B transport with recovery term and SUPG            eq. (semiCGT) and tau_B
  *   - partitioned NS -> phi -> B iteration, stop rule    Sec. 2.4 (eqs. LS_NS, LS_AC, LS_MC)
+ *   - the linear solves' plain preconditioners: point-block Jacobi and block
+ *     ILU(0) in the natural order (the textbook definitions: the paper names
+ *     a preconditioned Krylov solve without fixing the preconditioner)
  * Readings of silent or garbled points are marked READING in the comments.
  *
- * Parity pins: see tests/test_oracle_*.py.  Function "orc_band" (the grid-cell
- * transport band) defines a restriction that the paper does not state; its
- * definition is pinned by brute-force checks only.
+ * Parity pins: see tests/test_oracle_*.py (the grid-cell transport band of
+ * orc_band, a restriction the paper does not state, is pinned by the
+ * geometric decay of its truncation with the halo width; ILU(0) by its
+ * defining property, L U = A on the pattern, and by exactness without fill).
  */
 #include <math.h>
 #include <stdint.h>
@@ -880,6 +884,100 @@ done:
     if (relres_out) *relres_out = relres;
     free(LU); free(piv); free(V); free(Z); free(H); free(cs); free(sn); free(gv); free(y); free(r);
     return status;
+}
+
+/* -------------------------------------------------------------- ILU(0) */
+
+/* Inverse of one bs x bs block (LU with partial pivoting, then the unit
+ * columns solved).  Returns 0, or 1 when a pivot is zero. */
+static int block_inverse(int bs, const double *A, double *inv)
+{
+    double LU[64];
+    int piv[8];
+    memcpy(LU, A, sizeof(double) * bs * bs);
+    block_lu(bs, LU, piv);
+    for (int k = 0; k < bs; ++k)
+        if (LU[k * bs + k] == 0.0) return 1;
+    for (int j = 0; j < bs; ++j) {
+        double e[8];
+        for (int i = 0; i < bs; ++i) e[i] = i == j ? 1.0 : 0.0;
+        block_lu_solve(bs, LU, piv, e);
+        for (int i = 0; i < bs; ++i) inv[i * bs + j] = e[i];
+    }
+    return 0;
+}
+
+/* C = A B (bs x bs blocks, row-major) */
+static void block_mul(int bs, const double *A, const double *B, double *C)
+{
+    for (int i = 0; i < bs; ++i)
+        for (int j = 0; j < bs; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < bs; ++k) s += A[i * bs + k] * B[k * bs + j];
+            C[i * bs + j] = s;
+        }
+}
+
+/* Block ILU(0) of a BSR matrix (sorted columns, diagonal present) in the
+ * natural row order: L unit block-lower and U block-upper (with the
+ * diagonal) keep A's pattern, and L U equals A on every block of the
+ * pattern (what L U puts outside it is dropped).  Computed in place in lu
+ * (a copy of A's values), row after row: for the k < i of row i in
+ * increasing order, L_ik = A_ik U_kk^-1, then A_ij -= L_ik U_kj for every
+ * j > k of row i that row k holds.  dinv[i] = U_ii^-1.  Returns 0, or 1 + i
+ * for the first singular U_ii. */
+int orc_ilu0(int bs, int n, const int *rowptr, const int *col, const double *val, double *lu, double *dinv)
+{
+    const size_t b2 = (size_t)bs * bs;
+    memcpy(lu, val, sizeof(double) * b2 * rowptr[n]);
+    double t[64];
+    for (int i = 0; i < n; ++i) {
+        for (int p = rowptr[i]; p < rowptr[i + 1] && col[p] < i; ++p) {
+            const int k = col[p];
+            block_mul(bs, lu + (size_t)p * b2, dinv + (size_t)k * b2, t);
+            memcpy(lu + (size_t)p * b2, t, sizeof(double) * b2);
+            for (int q = p + 1; q < rowptr[i + 1]; ++q) {
+                const int kq = find_col(rowptr, col, k, col[q]);
+                if (kq < 0) continue;
+                double u[64];
+                block_mul(bs, t, lu + (size_t)kq * b2, u);
+                for (size_t v = 0; v < b2; ++v) lu[(size_t)q * b2 + v] -= u[v];
+            }
+        }
+        const int d = find_col(rowptr, col, i, i);
+        if (d < 0 || block_inverse(bs, lu + (size_t)d * b2, dinv + (size_t)i * b2)) return 1 + i;
+    }
+    return 0;
+}
+
+/* z = (L U)^-1 r with the factors of orc_ilu0: L y = r by forward
+ * substitution (unit diagonal), then U z = y backward,
+ * z_i = U_ii^-1 (y_i - sum_{j > i} U_ij z_j). */
+void orc_ilu0_apply(int bs, int n, const int *rowptr, const int *col, const double *lu, const double *dinv,
+                    const double *r, double *z)
+{
+    const size_t b2 = (size_t)bs * bs;
+    double y[8];
+    for (int i = 0; i < n; ++i) {
+        for (int a = 0; a < bs; ++a) y[a] = r[(size_t)i * bs + a];
+        for (int p = rowptr[i]; p < rowptr[i + 1] && col[p] < i; ++p)
+            for (int a = 0; a < bs; ++a)
+                for (int c = 0; c < bs; ++c) y[a] -= lu[(size_t)p * b2 + a * bs + c] * z[(size_t)col[p] * bs + c];
+        for (int a = 0; a < bs; ++a) z[(size_t)i * bs + a] = y[a];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        for (int a = 0; a < bs; ++a) y[a] = z[(size_t)i * bs + a];
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            if (col[p] <= i) continue;
+            for (int a = 0; a < bs; ++a)
+                for (int c = 0; c < bs; ++c) y[a] -= lu[(size_t)p * b2 + a * bs + c] * z[(size_t)col[p] * bs + c];
+        }
+        for (int a = 0; a < bs; ++a) {
+            double s = 0.0;
+            for (int c = 0; c < bs; ++c) s += dinv[(size_t)i * b2 + a * bs + c] * y[c];
+            z[(size_t)i * bs + a] = s;
+        }
+    }
 }
 
 /* ------------------------------------------------------- L2 projection */

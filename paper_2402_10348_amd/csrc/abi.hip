@@ -100,6 +100,7 @@ void free_all(eft_ctx *ctx)
     fr(ctx->red);
     fr(ctx->dscal);
     eft_mg_free(ctx);
+    eft_ilu_free(ctx);
     KrylovWs &K = ctx->kw;
     fr(K.V); fr(K.Z); fr(K.w); fr(K.r); fr(K.Dinv); fr(K.part); fr(K.small); fr(K.flag);
     for (hipGraphExec_t g : ctx->colg.exec)
@@ -120,14 +121,14 @@ eft_status check_params(eft_ctx *ctx, const eft_params *p)
 {
     if (!(p->dt > 0.0) || !(p->eta > 0.0) || p->restart < 1 || p->restart > EFT_MAX_RESTART || p->lin_maxit < 1 ||
         p->band_cell < 1 || p->band_halo < 0 || p->nl_max < 1 || !(p->lin_rtol > 0.0) || p->rho_inf < 0.0 ||
-        p->rho_inf > 1.0 || (p->precision != 0 && p->precision != 1) || (p->precond < 0 || p->precond > 2) ||
+        p->rho_inf > 1.0 || (p->precision != 0 && p->precision != 1) || (p->precond < 0 || p->precond > 3) ||
         p->mg_nu < 1 || p->mg_nu > 16 || !(p->mg_omega > 0.0) || p->mg_omega > 1.5 ||
         (p->mg_bf16 != 0 && p->mg_bf16 != 1) || p->mg_nu_post < 1 || p->mg_nu_post > 16 ||
         (p->mg_smoother != 0 && p->mg_smoother != 1) || p->band_sweeps < 1 || p->band_sweeps > 8 ||
         !(p->band_omega > 0.0 && p->band_omega <= 1.5) || (p->mg_galerkin != 0 && p->mg_galerkin != 1) ||
         (p->graphs != 0 && p->graphs != 1)) {
         ctx->err = "invalid eft_params (dt, eta, lin_rtol > 0; 1 <= restart <= 512; band_cell >= 1; "
-                   "0 <= rho_inf <= 1; precision 0/1; precond 0/1/2; 1 <= mg_nu <= 16; 0 < mg_omega <= 1.5; mg_bf16 0/1; 1 <= mg_nu_post <= 16; mg_smoother 0/1; 1 <= band_sweeps <= 8; 0 < band_omega <= 1.5; mg_galerkin 0/1; graphs 0/1)";
+                   "0 <= rho_inf <= 1; precision 0/1; precond 0/1/2/3; 1 <= mg_nu <= 16; 0 < mg_omega <= 1.5; mg_bf16 0/1; 1 <= mg_nu_post <= 16; mg_smoother 0/1; 1 <= band_sweeps <= 8; 0 < band_omega <= 1.5; mg_galerkin 0/1; graphs 0/1)";
         return EFT_EINVAL;
     }
     return EFT_OK;
@@ -403,6 +404,7 @@ eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *
     if (ctx->structured) {
         EFT_TRY(eft_mg_create(ctx, mesh->grid, dm));
         EFT_TRY(eft_mg_reserve(ctx));
+        EFT_TRY(eft_ilu_reserve(ctx));
     }
     const int mx = std::max(bs, nv);
     EFT_TRY(dalloc(ctx, &ctx->va, N * d));
@@ -573,6 +575,7 @@ eft_status eft_set_params(eft_ctx *ctx, const eft_params *par)
         ctx->mg_valid = false;
     }
     EFT_TRY(eft_mg_reserve(ctx));
+    EFT_TRY(eft_ilu_reserve(ctx));
     if (rebands) EFT_TRY(eft_band_reserve(ctx));
     else if (par->restart > ctx->kw.cap_m) EFT_TRY(eft_krylov_reserve(ctx, ctx->bp.cap_n, ctx->nv, par->restart));
     ctx->bands_valid = false;

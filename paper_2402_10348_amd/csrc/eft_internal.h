@@ -50,6 +50,14 @@ struct KrylovWs {
     int32_t nblk = 0;           // blocks of the reduction kernels
 };
 
+// Block ILU(0) factors of the momentum/mass matrix and their level schedule
+// (rows grouped by the longest chain of lower, resp. upper, dependencies).
+struct IluState {
+    double *lu = nullptr, *dinv = nullptr;      // [nnzb][bs*bs] L below, U on and above the diagonal; [n][bs*bs] U_ii^-1
+    int32_t *lrows = nullptr, *urows = nullptr;  // rows by level (device)
+    std::vector<int32_t> loff, uoff;            // level offsets (host)
+};
+
 // Compact system on the band of one indicator.  Its arrays are slices of
 // the context's band pool (BandPool), reserved at creation.
 struct Band {
@@ -251,6 +259,7 @@ struct eft_ctx {
     double *hscal = nullptr;                     // pinned host scalars
     int32_t nred = 0;
     KrylovWs kw;
+    IluState ilu;
     // HIP graphs of the columns of a multigrid-preconditioned momentum solve,
     // one per column index, with what they were captured on
     struct ColGraphs {
@@ -334,6 +343,10 @@ void eft_mg_free(eft_ctx *ctx);
 // hierarchy belongs to the Jacobian now in A
 bool eft_mg_enabled(const eft_ctx *ctx, const eft_matrix *A);
 bool eft_mg_active(const eft_ctx *ctx, const eft_matrix *A);
+eft_status eft_ilu_reserve(eft_ctx *ctx);
+void eft_ilu_free(eft_ctx *ctx);
+eft_status eft_ilu_setup(eft_ctx *ctx, const eft_matrix *A, int32_t *sing);
+eft_status eft_ilu_apply(eft_ctx *ctx, const double *r, double *z, const int32_t *flag);
 eft_status eft_mg_reserve(eft_ctx *ctx);
 eft_status eft_build_graph(int64_t N, int64_t E, int nn, const int32_t *conn, std::vector<int32_t> &rowptr,
                            std::vector<int32_t> &col, std::vector<int32_t> &diag, std::vector<int32_t> &epos,

@@ -341,16 +341,26 @@ __global__ __launch_bounds__(RB) void k_normalize(const double *__restrict__ w, 
 }
 
 // y = H^-1 g (upper triangular, jj columns)
-__global__ void k_trisolve(double *small, int m, const int32_t *flag)
+// Back substitution H[0..jj)[0..jj) y = g on one wavefront: row by row from
+// the last, the lanes share the dot product of row i with the known part of
+// y (a shuffle tree), y kept in LDS.
+__global__ __launch_bounds__(64) void k_trisolve(double *small, int m, const int32_t *flag)
 {
+    __shared__ double ys[EFT_MAX_RESTART];
     Small L{m};
     const int jj = flag[1];
-    double *H = small + L.H(), *g = small + L.g(), *y = small + L.y();
+    const double *H = small + L.H(), *g = small + L.g();
+    double *y = small + L.y();
+    const int l = threadIdx.x;
     for (int i = jj - 1; i >= 0; --i) {
-        double s = g[i];
-        for (int k = i + 1; k < jj; ++k) s -= H[(int64_t)i * m + k] * y[k];
-        y[i] = s / H[(int64_t)i * m + i];
+        double s = 0.0;
+        for (int k = i + 1 + l; k < jj; k += 64) s += H[(int64_t)i * m + k] * ys[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (l == 0) ys[i] = (g[i] - s) / H[(int64_t)i * m + i];
+        __syncthreads();
     }
+    for (int i = l; i < jj; i += 64) y[i] = ys[i];
 }
 
 // flags of a solve, before its first cycle
@@ -584,7 +594,10 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
     NNState &NS = ctx->net;
     const bool harvest = NS.cap_pairs > 0 && A == &ctx->J;
     hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, ctx->stream, K.flag);
-    if (!mg || harvest) EFT_TRY(eft_bj_setup(ctx, A, K.Dinv, K.flag + 6));
+    // block ILU(0) on the momentum system (point-block Jacobi elsewhere)
+    const bool ilu = ctx->par.precond == 3 && A == &ctx->J;
+    if (ilu) EFT_TRY(eft_ilu_setup(ctx, A, K.flag + 6));
+    if ((!mg && !ilu) || harvest) EFT_TRY(eft_bj_setup(ctx, A, K.Dinv, K.flag + 6));
     const double tol = (rtol > 0.0 ? rtol : ctx->par.lin_rtol) * bnorm;
     int chunk = 8;   // columns enqueued between two reads of the solver state
     int total = 0;
@@ -602,6 +615,8 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
             EFT_TRY(eft_mg_vcycle(ctx, vj, zj, K.flag));
         else if (learned)
             EFT_TRY(eft_nn_precond(ctx, K.Dinv, vj, zj, K.flag));
+        else if (ilu)
+            EFT_TRY(eft_ilu_apply(ctx, vj, zj, K.flag));
         else if (A == &ctx->J)
             EFT_TRY(eft_bj_apply(ctx, bs, n, K.Dinv, vj, zj, K.flag));
         else   // band systems (w is free until the product below)
@@ -697,7 +712,8 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
             eft_kt_void_from(ctx, jdone);
             EFT_TRY(eft_kt_harvest(ctx));
             if (hf[6]) {
-                ctx->err = "singular diagonal block in the point-block Jacobi preconditioner (singular system)";
+                ctx->err = "singular diagonal block in the preconditioner's factorization (point-block Jacobi or "
+                           "ILU(0)): singular system";
                 inf.iters = total + jdone;
                 if (info) *info = inf;
                 return EFT_EBREAKDOWN;
@@ -726,7 +742,7 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
             j_prev = jdone;
         }
         // x += Z y
-        hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(1), 0, ctx->stream, small, m, K.flag);
+        hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(64), 0, ctx->stream, small, m, K.flag);
         hipLaunchKernelGGL(k_maxpy, dim3(nblk), dim3(RB), 0, ctx->stream, K.Z, nd, jdone, small + L.y(), 1.0, x,
                            (double *)nullptr, nblk, (const int32_t *)nullptr, 0);
         EFT_HIP(hipGetLastError());

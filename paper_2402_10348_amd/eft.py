@@ -96,7 +96,7 @@ EXPORTS = ["eft_create", "eft_destroy", "eft_last_error", "eft_set_params", "eft
            "eft_band_system", "eft_transport_solids", "eft_step", "eft_tune", "eft_time_kernel",
            "eft_kernel_time_read", "eft_nn_init", "eft_nn_shape", "eft_nn_params", "eft_nn_harvest", "eft_nn_train",
            "eft_nn_loss_grad", "eft_nn_apply", "eft_center_of_mass", "eft_track_particles", "eft_init_phase",
-           "eft_mg_export"]
+           "eft_mg_export", "eft_ilu_export"]
 
 _lib = None
 
@@ -360,6 +360,14 @@ class Context:
                                          _ptr(val)))
         return rowptr, col, val, nl.value
 
+    def ilu_factors(self):
+        """Block ILU(0) factors of the current momentum matrix (precond = 3):
+        (lu [nnzb][bs*bs], dinv [n][bs*bs]) device tensors."""
+        n, nnz, bs = self.matrix_shape()
+        lu = self.torch.empty((nnz, bs * bs), dtype=self.torch.float64, device=self.dev)
+        dinv = self.torch.empty((n, bs * bs), dtype=self.torch.float64, device=self.dev)
+        self._check(self.L.eft_ilu_export(self.ctx, _ptr(lu), _ptr(dinv)))
+        return lu, dinv
     def spmv(self, x, y=None):
         if y is None:
             y = self.torch.empty_like(x)

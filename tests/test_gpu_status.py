@@ -89,13 +89,14 @@ def test_fast_interface_returns_band_overflow(torch_cuda):
     ctx.close()
 
 
-def test_singular_block_returns_breakdown(torch_cuda):
+@pytest.mark.parametrize("precond", [0, 3])
+def test_singular_block_returns_breakdown(torch_cuda, precond):
     from paper_2402_10348_amd.eft import EftError, EBREAKDOWN
     torch = torch_cuda
     prob = W.cavity_disk_2d(n=8)
-    say("[status] singular diagonal block -> EFT_EBREAKDOWN")
+    say(f"[status] singular diagonal block -> EFT_EBREAKDOWN (precond {precond})")
     lvl, it = W.perturbed_state(prob, seed=5)
-    ctx = ctx_for(prob, precond=0)
+    ctx = ctx_for(prob, precond=precond)
     R = ctx.assemble(ctx.device_state(lvl), ctx.device_state(it))
     rowptr, col, val = ctx.matrix()
     free = int(np.setdiff1d(np.arange(prob.n_nodes), prob.dir_node)[3])
