@@ -42,7 +42,7 @@ typedef enum {
     EFT_EDEVICE = 3,         /* a HIP call failed                                  */
     EFT_ENOTCONV = 4,        /* Krylov solve hit its iteration cap (best iterate
                                 returned, info filled)                             */
-    EFT_EBREAKDOWN = 5,      /* singular system: the point-block Jacobi
+    EFT_EBREAKDOWN = 5,      /* singular system: the point-block Jacobi or ILU(0)
                                 preconditioner met a singular diagonal block, or
                                 FGMRES could make no progress                      */
     EFT_ENAN = 6,            /* NaN/Inf met; fields keep the last good iterate     */
@@ -99,8 +99,9 @@ typedef struct {
                                     is a structured Kuhn box with even cell counts
                                     (point-block Jacobi otherwise, and always for
                                     the band systems); 2 learned preconditioner
-                                    (block Jacobi plus the network correction, see
-                                    eft_nn_init) for the momentum/mass block; 3
+                                    (a network correction of block Jacobi or of the
+                                    V-cycle, see nn_base and eft_nn_init) for the
+                                    momentum/mass block; 3
                                     block ILU(0) of the momentum/mass matrix in the
                                     natural row order (factors on the matrix
                                     pattern, level-scheduled factorization and
@@ -137,8 +138,8 @@ typedef struct {
                                     the fine operator with the V-cycle's transfers */
     int32_t nn_maxit;            /* learned preconditioner: Krylov iterations of
                                     one momentum solve after which the rest of the
-                                    solve uses block Jacobi, its fallback
-                                    (<= 0: lin_maxit / 2)                          */
+                                    solve uses its base (block Jacobi or the
+                                    V-cycle), its fallback (<= 0: lin_maxit / 2)  */
     double band_reserve;         /* band storage reserved at eft_create and
                                     eft_set_params: the bands of all indicators
                                     together may hold this many times the mesh's
@@ -157,6 +158,14 @@ typedef struct {
                                     launch enqueued from the host.  Same kernels,
                                     same results.  The graphs are kept until the
                                     parameters or the workspace change.           */
+    int32_t nn_base;             /* learned preconditioner (precond = 2): the
+                                    vector the network corrects, z = b + s m NN(b/s,
+                                    m): 0 the point-block Jacobi vector D^-1 r; 1
+                                    the multigrid V-cycle's output (structured
+                                    meshes; EFT_EINVAL without a hierarchy).  With
+                                    a zero output layer the preconditioner is
+                                    exactly that base, which is also its fallback.
+                                    Harvested pairs store the base of A z_j.      */
 } eft_params;
 
 /* State at time level n (Sec. 2.1.2): values and rates.  DEVICE arrays. */
@@ -182,13 +191,15 @@ typedef struct {
     int32_t iters;               /* Krylov iterations                              */
     int32_t restarts;            /* completed restart cycles                       */
     int32_t converged;           /* 1 if ||b - A x|| <= lin_rtol ||b||             */
-    int32_t fallback_used;       /* 1: the requested preconditioner gave way to
-                                    point-block Jacobi: multigrid unavailable (mesh
-                                    not a structured Kuhn box, or the matrix not
-                                    assembled by eft_assemble/eft_step), or the
-                                    learned one produced a non-finite value (those
-                                    nodes) or passed nn_maxit iterations (the rest
-                                    of the solve)                                 */
+    int32_t fallback_used;       /* 1: the requested preconditioner gave way to a
+                                    plain one: point-block Jacobi for an
+                                    unavailable multigrid (mesh not a structured
+                                    Kuhn box, or the matrix not assembled by
+                                    eft_assemble/eft_step), or the learned one's
+                                    base (block Jacobi or the V-cycle) where it
+                                    produced a non-finite value (those nodes) or
+                                    after nn_maxit iterations (the rest of the
+                                    solve)                                        */
     double rel_res0;             /* ||b - A x0|| / ||b|| (x0 = 0: 1)               */
     double rel_res;              /* final true relative residual                   */
 } eft_solve_info;
@@ -283,11 +294,13 @@ eft_status eft_spmv(eft_ctx *ctx, const eft_matrix *A, const double *x, double *
 
 /* (b) Solve A x = b with right-preconditioned FGMRES(restart), x0 = 0, the
  * preconditioner chosen by par.precond (point-block Jacobi, the multigrid
- * V-cycle, or the learned one with its block-Jacobi fallback); classical
- * Gram-Schmidt with a conditional second pass, all in FP64.  x is output
- * only.  EFT_ENOTCONV if lin_maxit is reached (x = best iterate);
- * EFT_EBREAKDOWN on a singular diagonal block (point-block Jacobi); EFT_ENAN
- * on a non-finite right-hand side or iterate. */
+ * V-cycle, the learned one with its base as fallback, or block ILU(0));
+ * classical Gram-Schmidt with a conditional second pass, all in FP64.  x is
+ * output only.  EFT_ENOTCONV if lin_maxit is reached (x = best iterate);
+ * EFT_EBREAKDOWN on a singular diagonal block (point-block Jacobi, ILU(0));
+ * EFT_ENAN on a non-finite right-hand side or iterate; EFT_EINVAL for a
+ * learned preconditioner without parameters, or nn_base = 1 without a
+ * multigrid hierarchy. */
 eft_status eft_fgmres(eft_ctx *ctx, const eft_matrix *A, const double *b, double *x, eft_solve_info *info);
 
 /* Allocation-free variant of eft_fgmres, for callers that cannot allocate
@@ -438,19 +451,21 @@ eft_status eft_kernel_time_read(eft_ctx *ctx, int32_t role, eft_kernel_time *out
 
 /* ---- Learned right preconditioner (not in the paper).  FGMRES admits any
  * variable right preconditioner M in eq. (LS_NS), so the network changes the
- * iteration count only, never the converged answer.  With u = D^-1 r (node-
- * block Jacobi), s = sqrt(mean(u^2)) and m the free-dof mask:
+ * iteration count only, never the converged answer.  With the base u = D^-1 r
+ * (node-block Jacobi, nn_base = 0) or u = the multigrid V-cycle applied to r
+ * (nn_base = 1), s = sqrt(mean(u^2)) and m the free-dof mask:
  *   z = u + s (m * NN(u / s, m)),
  * NN = a message-passing network on the matrix graph: input layer 2 bs -> H,
  * L layers h <- relu([h, mean of neighbours' h] W_l + b_l), output H -> bs
  * (H = 64, L = 4).  Parameters: one FP32 vector, W_in [2bs][H], b_in [H],
  * then per layer W_l [2H][H], b_l [H], then W_out [H][bs].  The dense layers
  * run on MFMA with BF16 operands and FP32 accumulation.  Training pairs
- * (u = D^-1 r, e) with A e = r are harvested from the context's own momentum
- * FGMRES solves. */
+ * (u = base of r, e) with A e = r are harvested from the context's own
+ * momentum FGMRES solves.  The parameters do not depend on the mesh size:
+ * a network trained on a small mesh applies to a large one (eft_nn_params). */
 
 /* Allocate (first call) and initialize the parameters from a seed; W_out = 0,
- * so the preconditioner starts as block Jacobi.  Adam moments are reset. */
+ * so the preconditioner starts as its base.  Adam moments are reset. */
 eft_status eft_nn_init(eft_ctx *ctx, uint64_t seed);
 
 /* hidden width, layer count, parameter count (0 before eft_nn_init) and the
@@ -462,9 +477,10 @@ eft_status eft_nn_shape(eft_ctx *ctx, int32_t *hidden, int32_t *layers, int64_t 
 eft_status eft_nn_params(eft_ctx *ctx, float *host, int64_t n, int32_t direction);
 
 /* Keep the last `capacity` training pairs of the momentum FGMRES solves that
- * follow: every Krylov column j gives (D^-1 A z_j, z_j), every converged solve
- * (D^-1 b, x).  0 stops harvesting and frees the ring.  The pairs take
- * 2 capacity N (d+1) FP32 values of device memory. */
+ * follow: every Krylov column j gives (base of A z_j, z_j), every converged
+ * solve (base of b, x), the base after nn_base (with nn_base = 1 one more
+ * V-cycle per column).  0 stops harvesting and frees the ring.  The pairs
+ * take 2 capacity N (d+1) FP32 values of device memory. */
 eft_status eft_nn_harvest(eft_ctx *ctx, int32_t capacity);
 
 /* Train on the harvested pairs: `steps` Adam steps (beta 0.9, 0.999), each on
@@ -479,8 +495,8 @@ eft_status eft_nn_train(eft_ctx *ctx, int32_t steps, int32_t batch, double lr, u
  * receive them.  For tests of the backward pass. */
 eft_status eft_nn_loss_grad(eft_ctx *ctx, const double *u, const double *e, float *grad_host, double *loss);
 
-/* z = u + s (m * NN(u / s, m)) for a DEVICE vector u (already block-Jacobi
- * preconditioned), z DEVICE; both FP64 [N][d+1]. */
+/* z = u + s (m * NN(u / s, m)) for a DEVICE base vector u (already block-
+ * Jacobi or V-cycle preconditioned), z DEVICE; both FP64 [N][d+1]. */
 eft_status eft_nn_apply(eft_ctx *ctx, const double *u, double *z);
 
 #ifdef __cplusplus

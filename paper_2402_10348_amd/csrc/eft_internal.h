@@ -146,7 +146,8 @@ struct NNState {
     float *delta = nullptr;             // [N][bs] network output
     float *part = nullptr;              // split-K and column-sum partials
     int64_t cap_part = 0;
-    double *u = nullptr;                // [N][bs] block-Jacobi vector of the input
+    double *u = nullptr;                // [N][bs] base vector of the input (block Jacobi or V-cycle)
+    int32_t *on = nullptr;              // a device flag that reads 1 (ungated V-cycles of the harvest)
     double *red = nullptr;              // reduction partials; scalars at the end
     double *losses = nullptr;           // [cap_steps] training losses
     int64_t cap_steps = 0;

@@ -578,26 +578,38 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
         if (info) *info = inf;
         return EFT_OK;
     }
-    const bool mg = eft_mg_active(ctx, A);   // hierarchy refreshed by the assembly
+    // the multigrid V-cycle (hierarchy refreshed by the assembly): the
+    // preconditioner with precond = 1, the learned one's base with nn_base = 1
+    const bool mg = eft_mg_active(ctx, A);
     inf.fallback_used = (ctx->par.precond == 1 && A == &ctx->J && !mg) ? 1 : 0;
     // learned preconditioner on the momentum system (block Jacobi elsewhere)
     bool learned = ctx->par.precond == 2 && A == &ctx->J;
+    const bool nn_mg = learned && ctx->par.nn_base == 1;
     if (learned && !ctx->net.ready) {
         ctx->err = "precond = 2 needs eft_nn_init (learned preconditioner parameters)";
         return EFT_EINVAL;
     }
+    if (nn_mg && !mg) {
+        ctx->err = "nn_base = 1 needs the multigrid hierarchy (a structured Kuhn mesh, assembled)";
+        return EFT_EINVAL;
+    }
     const int maxit = std::max(1, ctx->par.lin_maxit);
     // past this many iterations a learned-preconditioned solve continues with
-    // block Jacobi, its fallback (FGMRES admits the change between columns)
+    // its base (block Jacobi or the V-cycle), its fallback (FGMRES admits the
+    // change between columns)
     const int nn_budget = ctx->par.nn_maxit > 0 ? ctx->par.nn_maxit : std::max(1, maxit / 2);
-    // training pairs (u = D^-1 A z_j, z_j) from the momentum solves
+    // training pairs (base of A z_j, z_j) from the momentum solves
     NNState &NS = ctx->net;
     const bool harvest = NS.cap_pairs > 0 && A == &ctx->J;
+    if (harvest && ctx->par.nn_base == 1 && !mg) {
+        ctx->err = "harvesting for nn_base = 1 needs the multigrid hierarchy";
+        return EFT_EINVAL;
+    }
     hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, ctx->stream, K.flag);
     // block ILU(0) on the momentum system (point-block Jacobi elsewhere)
     const bool ilu = ctx->par.precond == 3 && A == &ctx->J;
     if (ilu) EFT_TRY(eft_ilu_setup(ctx, A, K.flag + 6));
-    if ((!mg && !ilu) || harvest) EFT_TRY(eft_bj_setup(ctx, A, K.Dinv, K.flag + 6));
+    if ((!mg && !ilu) || (harvest && ctx->par.nn_base == 0)) EFT_TRY(eft_bj_setup(ctx, A, K.Dinv, K.flag + 6));
     const double tol = (rtol > 0.0 ? rtol : ctx->par.lin_rtol) * bnorm;
     int chunk = 8;   // columns enqueued between two reads of the solver state
     int total = 0;
@@ -611,10 +623,10 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
     auto column = [&](int j) -> eft_status {
         double *vj = K.V + (int64_t)j * nd, *zj = K.Z + (int64_t)j * nd;
         ctx->kt.tag = j;
-        if (mg)
-            EFT_TRY(eft_mg_vcycle(ctx, vj, zj, K.flag));
-        else if (learned)
+        if (learned)
             EFT_TRY(eft_nn_precond(ctx, K.Dinv, vj, zj, K.flag));
+        else if (mg)
+            EFT_TRY(eft_mg_vcycle(ctx, vj, zj, K.flag));
         else if (ilu)
             EFT_TRY(eft_ilu_apply(ctx, vj, zj, K.flag));
         else if (A == &ctx->J)

@@ -1126,7 +1126,10 @@ void eft_mg_free(eft_ctx *ctx)
 
 bool eft_mg_enabled(const eft_ctx *ctx, const eft_matrix *A)
 {
-    return ctx->par.precond == 1 && ctx->mg.size() >= 2 && A == &ctx->J;
+    // the V-cycle preconditions the momentum solves, or is the base the
+    // learned preconditioner corrects
+    return (ctx->par.precond == 1 || (ctx->par.precond == 2 && ctx->par.nn_base == 1)) && ctx->mg.size() >= 2 &&
+           A == &ctx->J;
 }
 
 bool eft_mg_active(const eft_ctx *ctx, const eft_matrix *A)

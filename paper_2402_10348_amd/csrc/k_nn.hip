@@ -3,7 +3,8 @@
 // right preconditioner, so the network changes only the iteration count,
 // never the converged answer.
 //
-//   u = D^-1 r                 node-block Jacobi
+//   u = D^-1 r                 node-block Jacobi (nn_base = 0), or the
+//                              multigrid V-cycle applied to r (nn_base = 1)
 //   s = sqrt(mean(u^2))        global scale (1 when u = 0)
 //   f_i = [u_i / s, m_i]       m = 1 on free dofs, 0 on Dirichlet dofs
 //   h0 = relu(f W_in + b_in)
@@ -11,7 +12,8 @@
 //              (i itself included);   h = relu([h, g] W_l + b_l)
 //   z = u + s (m * (h W_out))
 //
-// With W_out = 0 (its initial value) the map is exactly block Jacobi.  The
+// With W_out = 0 (its initial value) the map is exactly its base (block
+// Jacobi or the V-cycle).  The
 // dense layers are GEMMs [nodes x K] x [K x H] on the matrix cores (MFMA
 // 32x32x8 BF16 operands, FP32 accumulation); activations and parameters are
 // FP32, the input and output vectors FP64.  Training (one pair per
@@ -389,11 +391,14 @@ __global__ void k_store_pair(int64_t n, int bs, const double *Dinv, const double
     if (gated_off(flag)) return;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * bs) return;
-    const int64_t i = t / bs;
-    const int c = (int)(t - i * bs);
-    const double *D = Dinv + i * bs * bs + c * bs;
-    double v = 0.0;
-    for (int q = 0; q < bs; ++q) v += D[q] * r[i * bs + q];
+    double v = r[t];   // the base itself (multigrid base) when Dinv is null
+    if (Dinv) {
+        const int64_t i = t / bs;
+        const int c = (int)(t - i * bs);
+        const double *D = Dinv + i * bs * bs + c * bs;
+        v = 0.0;
+        for (int q = 0; q < bs; ++q) v += D[q] * r[i * bs + q];
+    }
     hu[t] = (float)v;
     he[t] = (float)e[t];
 }
@@ -640,6 +645,11 @@ eft_status eft_nn_alloc(eft_ctx *ctx)
     S.cap_part = ((n + KCHUNK - 1) / KCHUNK) * 2 * H * H + H * 64;
     EFT_TRY(nmal(ctx, &S.part, S.cap_part));
     EFT_TRY(nmal(ctx, &S.u, nd));
+    {
+        const int32_t one[8] = {1, 0, 0, 0, 0, 0, 0, 0};
+        EFT_TRY(nmal(ctx, &S.on, 8));
+        EFT_HIP(hipMemcpy(S.on, one, sizeof(one), hipMemcpyHostToDevice));
+    }
     EFT_TRY(nmal(ctx, &S.red, 16 + 2 * (int64_t)grid_of(nd, NB)));
     hipLaunchKernelGGL(k_fill_f, dim3(grid_of(nd, 256)), dim3(256), 0, ctx->stream, S.mask, nd, 1.0f);
     if (ctx->n_dir > 0)
@@ -658,15 +668,16 @@ void eft_nn_free(eft_ctx *ctx)
         if (p) (void)hipFree(p);
     };
     fr(S.theta); fr(S.grad); fr(S.m1); fr(S.m2); fr(S.mask); fr(S.f); fr(S.pre); fr(S.h); fr(S.g); fr(S.d1);
-    fr(S.d2); fr(S.delta); fr(S.part); fr(S.u); fr(S.red); fr(S.losses); fr(S.hu); fr(S.he);
+    fr(S.d2); fr(S.delta); fr(S.part); fr(S.u); fr(S.on); fr(S.red); fr(S.losses); fr(S.hu); fr(S.he);
     const int H = S.H, L = S.L;
     S = NNState{};
     S.H = H;
     S.L = L;
 }
 
-// z = u + s (m * NN(u / s, m)) with u = D^-1 v; gated by the Krylov flag.
-// A node whose output is not finite takes the block-Jacobi value u instead
+// z = u + s (m * NN(u / s, m)) with the base u = D^-1 v (nn_base = 0) or
+// the multigrid V-cycle applied to v (nn_base = 1); gated by the Krylov
+// flag.  A node whose output is not finite takes the base's value instead
 // (flag[5] = 1 records the fallback; FGMRES admits a preconditioner that
 // changes between columns, so the solve stays valid).
 eft_status eft_nn_precond(eft_ctx *ctx, const double *Dinv, const double *v, double *z, int32_t *flag)
@@ -674,7 +685,13 @@ eft_status eft_nn_precond(eft_ctx *ctx, const double *Dinv, const double *v, dou
     NNState &S = ctx->net;
     const int64_t nd = ctx->N * S.bs;
     const int nblk = grid_of(nd, NB);
-    hipLaunchKernelGGL(k_bj_u, dim3(nblk), dim3(NB), 0, ctx->stream, ctx->N, S.bs, Dinv, v, S.u, S.red + 8, flag);
+    if (ctx->par.nn_base == 1) {
+        EFT_TRY(eft_mg_vcycle(ctx, v, S.u, flag));
+        hipLaunchKernelGGL(k_copy_u, dim3(nblk), dim3(NB), 0, ctx->stream, nd, S.u, S.u, S.red + 8);
+    } else {
+        hipLaunchKernelGGL(k_bj_u, dim3(nblk), dim3(NB), 0, ctx->stream, ctx->N, S.bs, Dinv, v, S.u, S.red + 8,
+                           flag);
+    }
     hipLaunchKernelGGL(k_scale, dim3(1), dim3(NB), 0, ctx->stream, S.red + 8, nblk, nd, S.red, flag);
     forward(ctx, z, flag);
     hipLaunchKernelGGL(k_nn_guard, dim3(grid_of(ctx->N, 256)), dim3(256), 0, ctx->stream, ctx->N, S.bs, S.u, z, flag);
@@ -682,11 +699,20 @@ eft_status eft_nn_precond(eft_ctx *ctx, const double *Dinv, const double *v, dou
     return EFT_OK;
 }
 
+// One training pair (base of r, e): the base D^-1 r (nn_base = 0) or the
+// V-cycle applied to r (nn_base = 1), in FP32 slot `slot` of the pair store.
 eft_status eft_nn_store_pair(eft_ctx *ctx, const double *Dinv, const double *r, const double *e, int64_t slot,
                              const int32_t *flag)
 {
     NNState &S = ctx->net;
     const int64_t nd = ctx->N * S.bs;
+    if (ctx->par.nn_base == 1) {
+        // (the V-cycle's kernels read their gate: an always-active one when
+        // the pair is not gated by a solve's flag)
+        EFT_TRY(eft_mg_vcycle(ctx, r, S.u, flag ? flag : S.on));
+        r = S.u;
+        Dinv = nullptr;
+    }
     hipLaunchKernelGGL(k_store_pair, dim3(grid_of(nd, 256)), dim3(256), 0, ctx->stream, ctx->N, S.bs, Dinv, r, e,
                        S.hu + slot * nd, S.he + slot * nd, flag);
     EFT_HIP(hipGetLastError());

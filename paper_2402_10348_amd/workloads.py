@@ -172,6 +172,7 @@ class Params:
     nn_maxit: int = 0          # learned preconditioner: iterations before block Jacobi takes over (0: lin_maxit/2)
     band_reserve: float = 0.0  # band storage for all indicators together, in mesh element counts (0: auto)
     graphs: int = 1           # momentum Krylov columns captured into HIP graphs and replayed
+    nn_base: int = 0          # learned preconditioner corrects: 0 point-block Jacobi, 1 the multigrid V-cycle
 
 
 @dataclass

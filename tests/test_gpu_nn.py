@@ -146,3 +146,56 @@ def test_training_reduces_krylov_iterations(torch_cuda):
     say(f"  solutions at 1e-12: rel diff {rel(xs[2], xs[0]):.2e}")
     assert rel(xs[2], xs[0]) < 1e-7
     ctx.close()
+
+
+def test_multigrid_base(torch_cuda):
+    """nn_base = 1: with the initial zero output layer the learned
+    preconditioner is the V-cycle itself (the same solve, bit for bit); pairs
+    (V-cycle of A z_j, z_j) are harvested from multigrid steps (the harvest
+    runs one ungated V-cycle per solve besides the gated ones of the columns),
+    training runs on them, and the trained network still reaches the
+    multigrid solution."""
+    torch = torch_cuda
+    prob = W.cavity_sphere_3d(n=16)
+    say(f"[nn] multigrid base sphere3d n=16 N={prob.n_nodes}")
+    ctx, c, rowptr, col, mask, bs = setup(prob, precond=1, nn_base=1, lin_rtol=1e-8, restart=50, lin_maxit=2000)
+    ctx.nn_init(seed=5)
+    lvl, it = W.perturbed_state(prob, seed=33, amp_v=0.05, amp_p=0.01, amp_phi=0.0, amp_B=0.0, amp_rate=0.05)
+    R = ctx.assemble(ctx.device_state(lvl), ctx.device_state(it))
+    b = (-R).contiguous()
+    sol = {}
+    for pc in (1, 2):
+        ctx.set_params(precond=pc)
+        x, si = ctx.fgmres(b)
+        say(f"  untrained precond={pc}: iters={si['iters']} rel_res={si['rel_res']:.2e}")
+        assert si["converged"] == 1 and si["fallback"] == 0
+        sol[pc] = (x.clone(), si["iters"])
+    assert sol[1][1] == sol[2][1] and torch.equal(sol[1][0], sol[2][0])
+    # harvest from multigrid steps, train
+    ctx.set_params(precond=1)
+    ctx.nn_harvest(256)
+    st = ctx.device_state(prob.state_copy())
+    t, k = 0.0, 0
+    for _ in range(3):
+        info = ctx.step(st, t=t, step=k)
+        t, k = info["t"], info["step"]
+    pairs = ctx.nn_shape()["pairs"]
+    say(f"  harvested pairs {pairs}")
+    assert pairs >= 32
+    losses = ctx.nn_train(steps=300, batch=4, lr=1e-3, seed=2)
+    a, l1 = float(np.mean(losses[:20])), float(np.mean(losses[-20:]))
+    # (reported, not asserted: these pairs are the multigrid-preconditioned
+    # Krylov directions, where the V-cycle is least accurate, and a local
+    # network that sees only its output gains little on them)
+    say(f"  loss first {a:.4f} last {l1:.4f}")
+    assert np.all(np.isfinite(losses))
+    ctx.nn_harvest(0)
+    ctx.set_params(precond=2, lin_rtol=1e-12)
+    x2, si = ctx.fgmres(b)
+    say(f"  trained precond=2 at 1e-12: iters={si['iters']} fallback={si['fallback']}")
+    ctx.set_params(precond=1, lin_rtol=1e-12)
+    x1, s1 = ctx.fgmres(b)
+    say(f"  multigrid at 1e-12: iters={s1['iters']}; solutions rel diff {rel(x2.cpu().numpy(), x1.cpu().numpy()):.2e}")
+    assert si["converged"] == 1 and s1["converged"] == 1
+    assert rel(x2.cpu().numpy(), x1.cpu().numpy()) < 1e-7
+    ctx.close()
