@@ -71,7 +71,7 @@ def parse():
     ap.add_argument("--no-learned", dest="learned", action="store_false",
                     help="skip the learned-vs-plain preconditioner comparison")
     ap.add_argument("--learned-n", type=int, default=32)
-    ap.add_argument("--learned-pairs", type=int, default=256)
+    ap.add_argument("--learned-pairs", type=int, default=1024)
     ap.add_argument("--learned-train", type=int, default=400)
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB copied by a plain device copy before the timed steps (HBM counter calibration)")
@@ -269,46 +269,115 @@ def timed_steps(ctx, st, steps, warmup, torch):
     return time.perf_counter() - t0, its
 
 
-def run_learned(args, torch):
-    """Learned vs plain preconditioner at 1e-8 on the n^3 cavity (default
-    32^3, where block Jacobi still converges): the plain FP64 step with
-    point-block Jacobi against the mixed-precision step with the learned
-    preconditioner, trained in this run on pairs harvested from the plain
-    run's own momentum solves (training time reported apart)."""
-    from paper_2402_10348_amd import workloads as W
+def harvest_and_train(args, prob, torch, base):
+    """Pairs (base of A z_j, z_j) harvested from the plain steps of the n^3
+    cavity (multigrid solves for the V-cycle base, point-block Jacobi for
+    the block-Jacobi base) until the ring holds --learned-pairs or 40 steps
+    ran, then --learned-train Adam steps; (parameters, training record)."""
     from paper_2402_10348_amd.eft import Context
-    prob = W.cavity_sphere_3d(n=args.learned_n)
-    common = dict(lin_rtol=1e-8, restart=100, lin_maxit=20000)
-    plain = Context(prob, precond=0, precision=0, **common)
-    plain.nn_init(seed=7)
-    plain.nn_harvest(args.learned_pairs)
-    st = plain.device_state(prob.state_copy())
-    el0, its0 = timed_steps(plain, st, args.steps, args.warmup, torch)
-    torch.cuda.synchronize()
+    pc = 1 if base == 1 else 0
+    ctx = Context(prob, precond=pc, precision=0, nn_base=base, lin_rtol=1e-8, restart=100, lin_maxit=20000)
+    ctx.nn_init(seed=7)
+    ctx.nn_harvest(args.learned_pairs)
+    st = ctx.device_state(prob.state_copy())
+    t_sim, step_no, nsteps = 0.0, 0, 0
     t0 = time.perf_counter()
-    losses = plain.nn_train(steps=args.learned_train, batch=4, lr=2e-3, seed=1)
+    while ctx.nn_shape()["pairs"] < args.learned_pairs and nsteps < 40:
+        info = ctx.step(st, t=t_sim, step=step_no)
+        t_sim, step_no, nsteps = info["t"], info["step"], nsteps + 1
+    torch.cuda.synchronize()
+    t_h = time.perf_counter() - t0
+    pairs = ctx.nn_shape()["pairs"]
+    t0 = time.perf_counter()
+    losses = ctx.nn_train(steps=args.learned_train, batch=4, lr=2e-3, seed=1)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    theta = plain.nn_params()
-    plain.close()
-    learned = Context(prob, precond=2, precision=1, **common)
-    learned.nn_init(seed=7)
-    learned.nn_params(theta)
-    st = learned.device_state(prob.state_copy())
-    el1, its1 = timed_steps(learned, st, args.steps, args.warmup, torch)
-    learned.close()
+    theta = ctx.nn_params()
+    ctx.close()
+    return theta, dict(base="multigrid V-cycle" if base == 1 else "point-block Jacobi", pairs=pairs,
+                       harvest_steps=nsteps, harvest_seconds=round(t_h, 3), adam_steps=args.learned_train,
+                       batch=4, seconds=round(t_train, 3), loss_first=float(losses[:10].mean()),
+                       loss_last=float(losses[-10:].mean()))
 
-    def line(el, its):
-        return dict(steps_per_s=round(args.steps / el, 4), ms_per_step=round(1e3 * el / args.steps, 2),
+
+def run_learned(args, torch):
+    """Learned vs plain preconditioner at 1e-8 per converged step.  The
+    network is local, so it is trained on the --learned-n cavity (pairs from
+    that size's own momentum solves) and its parameters are applied to the
+    128^3 cavity (the configuration of the comparison): there the plain
+    FP64 step with the multigrid V-cycle (the product's preconditioner)
+    against the mixed-precision step with the learned preconditioner on the
+    V-cycle.  At the training size the table adds the plain preconditioners
+    that judge the learned one (point-block Jacobi, ILU(0)) and the learned
+    one on block Jacobi.  The network's forward pass at 128^3 is timed on
+    its own (its dense layers are the MFMA work)."""
+    import numpy as np
+    from paper_2402_10348_amd import workloads as W
+    from paper_2402_10348_amd.eft import Context
+    common = dict(lin_rtol=1e-8, restart=100, lin_maxit=20000)
+
+    def line(el, its, steps, **kw):
+        conv = sum(1 for i in its if i["converged"])
+        return dict(converged_steps_per_s=round(conv / el, 4), ms_per_step=round(1e3 * el / steps, 2),
                     nl_iters_per_step=sum(i["nl_iters"] for i in its) / len(its),
-                    momentum_krylov_iters_per_step=sum(i["lin_iters_block"][0] for i in its) / len(its))
-    return dict(workload=f"3D cavity with elastic sphere, {args.learned_n}^3 x 6 P1 tets, FGMRES(100) to 1e-8",
-                plain=dict(precond="point-block Jacobi", dtype="f64", **line(el0, its0)),
-                learned=dict(precond="learned (block Jacobi + network)", dtype="f64 residual/Krylov, f32 Jacobian",
-                             **line(el1, its1)),
-                training=dict(pairs=args.learned_pairs, adam_steps=args.learned_train, seconds=round(t_train, 3),
-                              loss_first=float(losses[:10].mean()), loss_last=float(losses[-10:].mean())),
-                speedup=round(el0 / el1, 4))
+                    momentum_krylov_iters_per_step=sum(i["lin_iters_block"][0] for i in its) / len(its), **kw)
+
+    small = W.cavity_sphere_3d(n=args.learned_n)
+    log(args, f"[bench] learned: training at {args.learned_n}^3 ...")
+    th_mg, tr_mg = harvest_and_train(args, small, torch, 1)
+    th_bj, tr_bj = harvest_and_train(args, small, torch, 0)
+    table = {}
+    for name, kw, theta in (("plain multigrid (f64)", dict(precond=1, precision=0), None),
+                            ("plain point-block Jacobi (f64)", dict(precond=0, precision=0), None),
+                            ("plain ILU(0) (f64)", dict(precond=3, precision=0), None),
+                            ("learned on multigrid (mixed)", dict(precond=2, nn_base=1, precision=1), th_mg),
+                            ("learned on block Jacobi (mixed)", dict(precond=2, nn_base=0, precision=1), th_bj)):
+        c = Context(small, **common, **kw)
+        if theta is not None:
+            c.nn_init(seed=7)
+            c.nn_params(theta)
+        st = c.device_state(small.state_copy())
+        el, its = timed_steps(c, st, args.steps, args.warmup, torch)
+        c.close()
+        table[name] = line(el, its, args.steps)
+        log(args, f"[bench] learned {args.learned_n}^3 {name}: {table[name]}")
+    big = W.cavity_sphere_3d(n=128)
+    out = {}
+    for name, kw, theta in (("plain", dict(precond=1, precision=0), None),
+                            ("learned", dict(precond=2, nn_base=1, precision=1), th_mg)):
+        c = Context(big, **common, **kw)
+        if theta is not None:
+            c.nn_init(seed=7)
+            c.nn_params(theta)
+        st = c.device_state(big.state_copy())
+        el, its = timed_steps(c, st, args.steps, args.warmup, torch)
+        if theta is not None:
+            # the network's forward pass alone on a base-sized vector
+            u = torch.randn((big.n_nodes, 4), dtype=torch.float64, device="cuda")
+            c.nn_apply(u)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(10):
+                c.nn_apply(u)
+            torch.cuda.synchronize()
+            t_fw = (time.perf_counter() - t0) / 10
+            sh = c.nn_shape()
+            H, L = sh["hidden"], sh["layers"]
+            flop = 2.0 * big.n_nodes * (8 * H + L * 2 * H * H + H * 4)
+        c.close()
+        out[name] = line(el, its, args.steps)
+        log(args, f"[bench] learned 128^3 {name}: {out[name]}")
+    return dict(workload="3D cavity with elastic sphere, 128^3 x 6 P1 tets (2,146,689 nodes), FGMRES(100) to 1e-8",
+                plain=dict(precond="multigrid V-cycle", dtype="f64", **out["plain"]),
+                learned=dict(precond="learned correction of the V-cycle (trained at the small size)",
+                             dtype="f64 residual/Krylov, f32 Jacobian", **out["learned"]),
+                speedup=round(out["learned"]["converged_steps_per_s"] / max(out["plain"]["converged_steps_per_s"], 1e-12), 4),
+                network_forward=dict(seconds=round(t_fw, 6), flop=flop, tflops=round(flop / t_fw / 1e12, 3),
+                                     mfma_peak_tflops=2500.0, frac=round(flop / t_fw / 1e12 / 2500.0, 6),
+                                     note="dense layers on BF16 MFMA with FP32 accumulation; the pass is bound "
+                                          "by the activations' memory traffic, not by the matrix cores"),
+                training_size=dict(workload=f"3D cavity with elastic sphere, {args.learned_n}^3", table=table),
+                training=[tr_mg, tr_bj])
 
 
 def diagnostics(ctx, st, prob):
