@@ -14,8 +14,8 @@
 //
 // With W_out = 0 (its initial value) the map is exactly its base (block
 // Jacobi or the V-cycle).  The
-// dense layers are GEMMs [nodes x K] x [K x H] on the matrix cores (MFMA
-// 32x32x8 BF16 operands, FP32 accumulation); activations and parameters are
+// dense layers are GEMMs [nodes x K] x [K x H] on the matrix cores (gfx950
+// MFMA 32x32x16 BF16 operands, FP32 accumulation); activations and parameters are
 // FP32, the input and output vectors FP64.  Training (one pair per
 // gradient, Adam) runs on the device by the backward kernels below.
 //
@@ -24,7 +24,7 @@
 #include "dev_common.h"
 #include "eft_internal.h"
 
-typedef short eft_bf4 __attribute__((ext_vector_type(4)));
+typedef __bf16 eft_bf8 __attribute__((ext_vector_type(8)));
 typedef float eft_f16v __attribute__((ext_vector_type(16)));
 
 namespace {
@@ -52,13 +52,6 @@ Offs offs_of(const NNState &S)
     return o;
 }
 
-__device__ __forceinline__ short bf16_rne(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
-}
-
 __device__ __forceinline__ bool gated_off(const int32_t *flag) { return flag != nullptr && flag[0] == 0; }
 
 // ------------------------------------------------------------- GEMM ----
@@ -66,10 +59,13 @@ __device__ __forceinline__ bool gated_off(const int32_t *flag) { return flag != 
 // C[z][m][n] = sum over k in split z of A(m, k) B(k, n) (+ bias[n]), with
 // A(m, k) = A1[m a1m + k a1k] for k < K1 and A2[m a2m + (k - K1) a2k]
 // otherwise; B(k, n) = B[k bk + n bn].  A wavefront computes a 32 x 64 tile
-// with two 32x32x8 BF16 MFMA accumulators; a workgroup stacks 4 wavefronts
-// along m.  Lane l supplies A(row l%32, k0 + 4(l/32) + t) and
-// B(k0 + 4(l/32) + t, col l%32), t < 4, and receives C(8(t/4) + 4(l/32) + t%4,
-// l%32) in accumulator slot t (layout checked on the device).
+// with two 32x32x16 BF16 MFMA accumulators (gfx950); a workgroup stacks 4
+// wavefronts along m and shares the B tile: 64 rows of k at a time, staged
+// in LDS as BF16 (rounded once, to nearest even), padded against bank
+// conflicts.  Lane l supplies A(row l%32, k0 + 8(l/32) + t) and
+// B(k0 + 8(l/32) + t, col l%32), t < 8, and receives C(8(t/4) + 4(l/32) + t%4,
+// l%32) in accumulator slot t.  Rows of A with unit k stride are read as
+// two 16-byte vectors per 8 values.
 struct GemmArgs {
     int64_t M, N, K, K1;
     const float *A1, *A2;
@@ -83,38 +79,73 @@ struct GemmArgs {
     const int32_t *flag;
 };
 
+constexpr int GKT = 64;   // k rows of the B tile per LDS stage
+
+// 8 consecutive values of A's row am from k (within one source, unit stride
+// and 16-byte alignment when vec)
+__device__ __forceinline__ void a_row8(const GemmArgs &g, int64_t am, int64_t k, int64_t kend, bool vec,
+                                       eft_bf8 &a)
+{
+    if (am < g.M && vec && k + 8 <= kend && (k + 8 <= g.K1 || k >= g.K1)) {
+        const float *p = k < g.K1 ? g.A1 + am * g.a1m + k : g.A2 + am * g.a2m + (k - g.K1);
+        const float4 x0 = reinterpret_cast<const float4 *>(p)[0], x1 = reinterpret_cast<const float4 *>(p)[1];
+        a[0] = (__bf16)x0.x;
+        a[1] = (__bf16)x0.y;
+        a[2] = (__bf16)x0.z;
+        a[3] = (__bf16)x0.w;
+        a[4] = (__bf16)x1.x;
+        a[5] = (__bf16)x1.y;
+        a[6] = (__bf16)x1.z;
+        a[7] = (__bf16)x1.w;
+        return;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int64_t kk = k + t;
+        float v = 0.0f;
+        if (am < g.M && kk < kend) v = kk < g.K1 ? g.A1[am * g.a1m + kk * g.a1k] : g.A2[am * g.a2m + (kk - g.K1) * g.a2k];
+        a[t] = (__bf16)v;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
 {
     if (gated_off(g.flag)) return;
+    __shared__ __bf16 Bs[GKT][64 + 8];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t m0 = ((int64_t)blockIdx.x * 4 + w) * 32, n0 = (int64_t)blockIdx.y * 64;
     const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
     const int64_t ke = kb + g.kchunk < g.K ? kb + g.kchunk : g.K;
     const int64_t am = m0 + (lane & 31);
-    const int kq = 4 * (lane >> 5);
+    const int kq = 8 * (lane >> 5);
+    // unit k stride with 16-byte aligned rows in both sources
+    const bool vec = g.a1k == 1 && g.a1m % 4 == 0 && (g.K1 >= g.K || (g.a2k == 1 && g.a2m % 4 == 0 && g.K1 % 8 == 0)) &&
+                     (reinterpret_cast<uintptr_t>(g.A1) & 15) == 0 &&
+                     (g.K1 >= g.K || (reinterpret_cast<uintptr_t>(g.A2) & 15) == 0);
     eft_f16v acc0, acc1;
 #pragma unroll
     for (int t = 0; t < 16; ++t) acc0[t] = acc1[t] = 0.0f;
-    // (unrolled: the loads of four k steps are issued before their MFMAs)
-#pragma unroll 4
-    for (int64_t k0 = kb; k0 < ke; k0 += 8) {
-        eft_bf4 a, b0, b1;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int64_t k = k0 + kq + t;
-            float av = 0.0f, bv0 = 0.0f, bv1 = 0.0f;
-            if (k < ke) {
-                if (am < g.M) av = k < g.K1 ? g.A1[am * g.a1m + k * g.a1k] : g.A2[am * g.a2m + (k - g.K1) * g.a2k];
-                const int64_t c0 = n0 + (lane & 31), c1 = c0 + 32;
-                if (c0 < g.N) bv0 = g.B[k * g.bk + c0 * g.bn];
-                if (c1 < g.N) bv1 = g.B[k * g.bk + c1 * g.bn];
-            }
-            a[t] = bf16_rne(av);
-            b0[t] = bf16_rne(bv0);
-            b1[t] = bf16_rne(bv1);
+    for (int64_t kt = kb; kt < ke; kt += GKT) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < GKT * 64; t += 256) {
+            const int r = t >> 6, c = t & 63;
+            const int64_t k = kt + r, col = n0 + c;
+            Bs[r][c] = (__bf16)((k < ke && col < g.N) ? g.B[k * g.bk + col * g.bn] : 0.0f);
         }
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b0, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b1, acc1, 0, 0, 0);
+        __syncthreads();
+        const int64_t kend = kt + GKT < ke ? kt + GKT : ke;
+        for (int64_t k0 = kt; k0 < kend; k0 += 16) {
+            eft_bf8 a, b0, b1;
+            a_row8(g, am, k0 + kq, kend, vec, a);
+            const int r0 = (int)(k0 - kt) + kq;   // < GKT: k0 - kt <= GKT - 16
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                b0[t] = Bs[r0 + t][lane & 31];
+                b1[t] = Bs[r0 + t][32 + (lane & 31)];
+            }
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+        }
     }
     float *C = g.C + (int64_t)blockIdx.z * g.csplit;
 #pragma unroll
