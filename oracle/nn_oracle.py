@@ -19,8 +19,34 @@ A e = r gives the loss  ||m*(z(r) - e)||^2 / ||m*e||^2.
 
 Parameters are one flat vector in the order W_in [F][H], b_in [H], then for
 each layer W_l [2H][H], b_l [H], then W_out [H][bs]  (F = 2 bs).
+
+emulate=True evaluates the same map in the arithmetic of the device kernels
+instead of FP64: the operands of every dense product that runs on the
+matrix cores (the input and hidden layers forward; the weight gradients and
+the hidden layers' input gradients backward) rounded to BF16 (nearest even
+on the FP32 bit pattern), activations, neighbour means and gradients stored
+in FP32, the output layer in FP32 without BF16, the output combination in
+FP64.  The products themselves are summed in FP64 here (FP32 on the
+device), so the two agree to the accumulation rounding, not bit for bit.
 """
 import numpy as np
+
+
+def _f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def _bf16(x):
+    """Round to BF16 (nearest even on the FP32 bit pattern), as float64."""
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _mm(A, B, emulate):
+    """A product on the matrix cores: BF16 operands when emulating."""
+    return _bf16(A) @ _bf16(B) if emulate else A @ B
 
 
 def layout(bs, H, L):
@@ -78,56 +104,60 @@ def mean_agg_T(rowptr, col, y):
     return out
 
 
-def forward(theta, rowptr, col, Dinv, mask, r, bs, H, L, keep=False):
+def forward(theta, rowptr, col, Dinv, mask, r, bs, H, L, keep=False, emulate=False):
     P = unpack(theta, bs, H, L)
     N = rowptr.shape[0] - 1
+    st = _f32 if emulate else (lambda x: x)   # storage of the device's FP32 arrays
     r = np.asarray(r, dtype=np.float64).reshape(N, bs)
     u = np.einsum("nij,nj->ni", Dinv, r)
     s = float(np.sqrt(np.mean(u * u)))
     if s == 0.0:
         s = 1.0
-    f = np.concatenate([u / s, mask], axis=1)
-    pre0 = f @ P["W_in"] + P["b_in"]
+    f = st(np.concatenate([u / s, mask], axis=1))
+    pre0 = st(_mm(f, P["W_in"], emulate) + P["b_in"])
     h = np.maximum(pre0, 0.0)
     cache = dict(f=f, pre=[pre0], h=[h], g=[], u=u, s=s)
     for l in range(L):
-        g = mean_agg(rowptr, col, h)
-        pre = np.concatenate([h, g], axis=1) @ P[f"W_{l + 1}"] + P[f"b_{l + 1}"]
+        g = st(mean_agg(rowptr, col, h))
+        pre = st(_mm(np.concatenate([h, g], axis=1), P[f"W_{l + 1}"], emulate) + P[f"b_{l + 1}"])
         h = np.maximum(pre, 0.0)
         cache["g"].append(g)
         cache["pre"].append(pre)
         cache["h"].append(h)
-    delta = h @ P["W_out"]
+    delta = st(h @ P["W_out"])
     z = u + s * (mask * delta)
     return (z, cache) if keep else z
 
 
-def loss_and_grad(theta, rowptr, col, Dinv, mask, r, e, bs, H, L):
+def loss_and_grad(theta, rowptr, col, Dinv, mask, r, e, bs, H, L, emulate=False):
     """Loss of one pair and its gradient with respect to theta (backward pass
     written out layer by layer)."""
     P = unpack(theta, bs, H, L)
     N = rowptr.shape[0] - 1
+    st = _f32 if emulate else (lambda x: x)
     e = np.asarray(e, dtype=np.float64).reshape(N, bs)
-    z, c = forward(theta, rowptr, col, Dinv, mask, r, bs, H, L, keep=True)
+    if emulate:   # the pair's target is held in FP32
+        e = _f32(e)
+    z, c = forward(theta, rowptr, col, Dinv, mask, r, bs, H, L, keep=True, emulate=emulate)
     E = float(np.sum((mask * e) ** 2))
     if E == 0.0:
         E = 1.0
     res = mask * (z - e)
     loss = float(np.sum(res * res)) / E
     dz = 2.0 * res / E
-    ddelta = c["s"] * mask * dz
+    ddelta = st(c["s"] * mask * dz)
     G = {}
     hL = c["h"][-1]
-    G["W_out"] = hL.T @ ddelta
-    dh = ddelta @ P["W_out"].T
+    G["W_out"] = _mm(hL.T, ddelta, emulate)
+    dh = st(ddelta @ P["W_out"].T)
     for l in range(L - 1, -1, -1):
         dpre = dh * (c["pre"][l + 1] > 0.0)
         X = np.concatenate([c["h"][l], c["g"][l]], axis=1)
-        G[f"W_{l + 1}"] = X.T @ dpre
+        G[f"W_{l + 1}"] = _mm(X.T, dpre, emulate)
         G[f"b_{l + 1}"] = dpre.sum(axis=0)
-        dX = dpre @ P[f"W_{l + 1}"].T
-        dh = dX[:, :H] + mean_agg_T(rowptr, col, dX[:, H:])
+        dX = st(_mm(dpre, P[f"W_{l + 1}"].T, emulate))
+        dh = st(dX[:, :H] + mean_agg_T(rowptr, col, dX[:, H:]))
     dpre0 = dh * (c["pre"][0] > 0.0)
-    G["W_in"] = c["f"].T @ dpre0
+    G["W_in"] = _mm(c["f"].T, dpre0, emulate)
     G["b_in"] = dpre0.sum(axis=0)
     return loss, pack(G, bs, H, L)

@@ -119,3 +119,23 @@ def test_exact_pair_has_zero_loss():
     u = np.einsum("nij,nj->ni", Dinv, r)
     loss, g = NN.loss_and_grad(th, rowptr, col, Dinv, mask, r, u, bs, H, L)
     assert loss == 0.0 and np.all(g == 0.0)
+
+
+def test_device_arithmetic_mode_stays_near_the_definition():
+    """The BF16/FP32 emulation of the reference stays within the BF16
+    rounding (a few 1e-3) of the FP64 definition, and its BF16 rounding is
+    to nearest even on the FP32 bit pattern."""
+    b = NN._bf16(np.array([1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -9, 1.5 * 2.0 ** -20]))
+    assert b[0] == 1.0                      # a tie rounds to the even neighbour
+    assert b[1] == 1.0 + 2.0 ** -6          # a tie rounds to the even neighbour (upwards)
+    assert b[2] == 1.0                      # below half an ulp
+    assert b[3] == 1.5 * 2.0 ** -20         # exactly representable
+    prob, rowptr, col, J, Dinv, mask, bs = small_system("sphere3d")
+    rng = np.random.Generator(np.random.PCG64(4))
+    r = rng.standard_normal((prob.n_nodes, bs))
+    theta = random_theta(bs, 6, out_scale=1.0)
+    z = NN.forward(theta, rowptr, col, Dinv, mask, r, bs, H, L)
+    zm = NN.forward(theta, rowptr, col, Dinv, mask, r, bs, H, L, emulate=True)
+    u = np.einsum("nij,nj->ni", Dinv, r)
+    d = np.abs(zm - z).max() / np.abs(z - u).max()
+    assert 1e-5 < d < 3e-2
