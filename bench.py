@@ -79,6 +79,9 @@ def parse():
     ap.add_argument("--no-variants", dest="variants", action="store_false",
                     help="skip the paper-literal variants and diagnostics (64^3 cavity)")
     ap.add_argument("--graphs", type=int, default=1, help="1: momentum Krylov columns replayed as HIP graphs")
+    ap.add_argument("--mg-lag", type=int, default=1,
+                    help="1: coarse multigrid levels refreshed at the first nonlinear iteration of a step only, "
+                         "0: at every nonlinear iteration")
     ap.add_argument("--kernel-steps", type=int, default=2,
                     help="steps after the timed ones with per-launch HIP-event timing of the roofline kernels")
     ap.add_argument("--quiet", action="store_true")
@@ -156,7 +159,8 @@ def run_steps(args, prob, torch, label, time_kernels=True, **over):
     from paper_2402_10348_amd.eft import Context
     kw = dict(lin_rtol=1e-8, restart=args.restart, lin_maxit=20000, precision=args.precision,
               precond=args.precond, mg_nu=args.mg_nu, mg_omega=args.mg_omega, mg_bf16=args.mg_bf16,
-              mg_nu_post=args.mg_nu_post, mg_smoother=args.mg_smoother, nl_max=20, graphs=args.graphs)
+              mg_nu_post=args.mg_nu_post, mg_smoother=args.mg_smoother, nl_max=20, graphs=args.graphs,
+              mg_lag=args.mg_lag)
     kw.update(band_over(args))
     kw.update(over)
     t0 = time.perf_counter()
@@ -703,6 +707,9 @@ def main():
                    "nl_iters_per_step": head["nl_iters_per_step"],
                    "krylov_iters_per_step_by_block": head["krylov_iters_per_step_by_block"],
                    "transport_ms_per_step": head["transport_ms_per_step"], "tuning": head.get("tuning"),
+                   "preconditioner": {0: "point-block Jacobi", 1: "multigrid V-cycle", 2: "learned",
+                                      3: "block ILU(0)"}[args.precond]
+                   + (" (coarse levels kept within a step)" if args.precond == 1 and args.mg_lag else ""),
                    "parallelism": "1 GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -166,6 +166,14 @@ typedef struct {
                                     a zero output layer the preconditioner is
                                     exactly that base, which is also its fallback.
                                     Harvested pairs store the base of A z_j.      */
+    int32_t mg_lag;              /* multigrid inside eft_step: 0 every assembly
+                                    refreshes the whole hierarchy; 1 the coarse
+                                    levels (Galerkin products or rediscretized
+                                    operators, their block inverses, the coarsest
+                                    inverse) are refreshed at the first nonlinear
+                                    iteration of a step only, the finest level
+                                    (copy of J, block inverses) at every one.  The
+                                    preconditioner changes, the answer does not. */
 } eft_params;
 
 /* State at time level n (Sec. 2.1.2): values and rates.  DEVICE arrays. */

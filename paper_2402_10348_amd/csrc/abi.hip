@@ -126,9 +126,10 @@ eft_status check_params(eft_ctx *ctx, const eft_params *p)
         (p->mg_bf16 != 0 && p->mg_bf16 != 1) || p->mg_nu_post < 1 || p->mg_nu_post > 16 ||
         (p->mg_smoother != 0 && p->mg_smoother != 1) || p->band_sweeps < 1 || p->band_sweeps > 8 ||
         !(p->band_omega > 0.0 && p->band_omega <= 1.5) || (p->mg_galerkin != 0 && p->mg_galerkin != 1) ||
-        (p->graphs != 0 && p->graphs != 1) || (p->nn_base != 0 && p->nn_base != 1)) {
+        (p->graphs != 0 && p->graphs != 1) || (p->nn_base != 0 && p->nn_base != 1) ||
+        (p->mg_lag != 0 && p->mg_lag != 1)) {
         ctx->err = "invalid eft_params (dt, eta, lin_rtol > 0; 1 <= restart <= 512; band_cell >= 1; "
-                   "0 <= rho_inf <= 1; precision 0/1; precond 0/1/2/3; 1 <= mg_nu <= 16; 0 < mg_omega <= 1.5; mg_bf16 0/1; 1 <= mg_nu_post <= 16; mg_smoother 0/1; 1 <= band_sweeps <= 8; 0 < band_omega <= 1.5; mg_galerkin 0/1; graphs 0/1; nn_base 0/1)";
+                   "0 <= rho_inf <= 1; precision 0/1; precond 0/1/2/3; 1 <= mg_nu <= 16; 0 < mg_omega <= 1.5; mg_bf16 0/1; 1 <= mg_nu_post <= 16; mg_smoother 0/1; 1 <= band_sweeps <= 8; 0 < band_omega <= 1.5; mg_galerkin 0/1; graphs 0/1; nn_base 0/1; mg_lag 0/1)";
         return EFT_EINVAL;
     }
     return EFT_OK;
@@ -758,6 +759,11 @@ eft_status eft_step(eft_ctx *ctx, eft_state *st, double dt, eft_step_info *info)
     if (!ctx || !st || !st->vp || !st->vdot) return EFT_EINVAL;
     if ((ctx->n_ind > 0 && (!st->phi || !st->phidot)) || (ctx->n_s > 0 && (!st->B || !st->Bdot))) return EFT_EINVAL;
     if (dt > 0.0) ctx->par.dt = dt;
+    // the nonlinear iteration counter reads 0 again however the step ends
+    struct NlReset {
+        eft_ctx *c;
+        ~NlReset() { c->nl_k = 0; }
+    } nl_reset{ctx};
     const int64_t N = ctx->N;
     const int d = ctx->dim, bs = ctx->bs, nv = ctx->nv;
     const int64_t nvp = N * bs, nphi = N * ctx->n_ind, nB = N * nv * ctx->n_s;
@@ -798,6 +804,7 @@ eft_status eft_step(eft_ctx *ctx, eft_state *st, double dt, eft_step_info *info)
     bool conv = false;
     for (k = 1; k <= nl_lim; ++k) {
         double ta = now_s();
+        ctx->nl_k = k;
         EFT_TRY(eft_props(ctx, &lvl, &it));
         EFT_TRY(eft_ns_kernels(ctx, &it, ctx->R, &ctx->J));
         hipLaunchKernelGGL(k_neg, dim3(sgrid(nvp)), dim3(256), 0, ctx->stream, ctx->R, nvp);

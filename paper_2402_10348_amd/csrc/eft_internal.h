@@ -278,6 +278,7 @@ struct eft_ctx {
     int64_t mg_nd = 0;
     bool mg_f32_fresh = false;   // the finest level's FP32 or BF16 copy was written by the assembly
     bool mg_valid = false;       // the hierarchy belongs to the Jacobian now in J (set by eft_mg_setup)
+    int nl_k = 0;                // nonlinear iteration of the running eft_step (1-based; 0 outside)
     // diagnostics workspace (centre of mass partials, particles)
     double *dg = nullptr;
     int64_t dg_cap = 0;
@@ -337,7 +338,7 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
 
 // k_mg.hip
 eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<uint8_t> &dmask0);
-eft_status eft_mg_setup(eft_ctx *ctx, const double *vp);
+eft_status eft_mg_setup(eft_ctx *ctx, const double *vp, bool coarse = true);
 eft_status eft_mg_vcycle(eft_ctx *ctx, const double *b0, double *z, const int32_t *flag);
 void eft_mg_free(eft_ctx *ctx);
 // the multigrid preconditioner is requested and possible for A / and its

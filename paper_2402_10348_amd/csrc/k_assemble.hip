@@ -764,6 +764,8 @@ eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_ma
     uint16_t *J16 = (mg && ctx->par.mg_bf16 && !J->fp32) ? ctx->mg[0].A.val16 : nullptr;
     EFT_TRY(eft_ns_level(ctx, M, it->vp, R, J, J32, J16));
     ctx->mg_f32_fresh = J32 != nullptr || J16 != nullptr;
-    if (mg) EFT_TRY(eft_mg_setup(ctx, it->vp));
+    // (with mg_lag, inside a step past its first nonlinear iteration, the
+    // coarse levels of the previous iteration are kept)
+    if (mg) EFT_TRY(eft_mg_setup(ctx, it->vp, !(ctx->par.mg_lag && ctx->nl_k > 1 && ctx->mg_valid)));
     return EFT_OK;
 }

@@ -1152,7 +1152,7 @@ eft_status eft_mg_reserve(eft_ctx *ctx)
 
 // Refresh the hierarchy for the current Jacobian: inject node fields,
 // rediscretize the coarse Jacobians, block inverses and the coarsest inverse.
-eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
+eft_status eft_mg_setup(eft_ctx *ctx, const double *vp, bool coarse)
 {
     const int bs = ctx->bs;
     const int64_t L = (int64_t)ctx->mg.size();
@@ -1190,6 +1190,10 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp)
         }
         ctx->mg_f32_fresh = false;
         EFT_TRY(eft_bj_setup32(ctx, &F0.A, F0.Dinv32));
+    }
+    if (!coarse) {   // the coarse levels of the previous refresh are kept
+        ctx->mg_valid = true;
+        return EFT_OK;
     }
     for (int64_t l = 1; l < L && ctx->par.mg_galerkin; ++l) {
         // Galerkin coarse operator from the level above

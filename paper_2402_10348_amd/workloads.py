@@ -173,6 +173,7 @@ class Params:
     band_reserve: float = 0.0  # band storage for all indicators together, in mesh element counts (0: auto)
     graphs: int = 1           # momentum Krylov columns captured into HIP graphs and replayed
     nn_base: int = 0          # learned preconditioner corrects: 0 point-block Jacobi, 1 the multigrid V-cycle
+    mg_lag: int = 0           # 1: coarse multigrid levels refreshed once per time step (first nonlinear iteration)
 
 
 @dataclass

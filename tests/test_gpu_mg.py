@@ -132,3 +132,32 @@ def test_galerkin_multigrid_same_solution(name):
         e = np.linalg.norm(sols[tag][0] - ref) / np.linalg.norm(ref)
         assert e < 1e-8, (tag, e)
     assert sols["galerkin"][1] < sols["bj"][1]
+
+
+def test_lagged_coarse_levels_reach_the_same_step():
+    """mg_lag = 1 keeps the coarse levels of a step's first nonlinear
+    iteration: the preconditioner changes, the converged fields do not
+    (both runs solved tightly)."""
+    import torch
+    from paper_2402_10348_amd.eft import Context
+    prob = W.cavity_sphere_3d(n=16)
+    say("[mg] lagged coarse levels, sphere3d n=16, 3 steps")
+    out = {}
+    for lag in (0, 1):
+        ctx = Context(prob, mg_lag=lag, mg_galerkin=1, lin_rtol=1e-12, nl_rtol=1e-9, nl_max=30)
+        st = ctx.device_state(prob.state_copy())
+        t, k, its = 0.0, 0, []
+        for _ in range(3):
+            info = ctx.step(st, t=t, step=k)
+            t, k = info["t"], info["step"]
+            its.append((info["nl_iters"], info["lin_iters_block"][0], info["converged"]))
+        torch.cuda.synchronize()
+        say(f"  mg_lag={lag}: (nonlinear, momentum Krylov, converged) per step {its}")
+        assert all(c == 1 for _, _, c in its)
+        out[lag] = {n: v.cpu().numpy() for n, v in st.items()}
+        ctx.close()
+    for n in out[0]:
+        a, b = out[0][n], out[1][n]
+        d = float(np.abs(a - b).max()) / max(float(np.abs(a).max()), 1e-300)
+        say(f"  {n}: rel diff {d:.2e}")
+        assert d <= 1e-7, n
