@@ -113,12 +113,15 @@ def make_workload(name):
     return p, f"3D lid-driven cavity with one elastic sphere, {n}^3 x 6 P1 tets"
 
 
-KERNEL_NAME = {1: "k_sweep_blk<4, eft_bf16, float> (finest-level multigrid smoother sweep, BF16 copy of the "
-                  "4x4-block momentum Jacobian, FP32 block inverses, FP64 vectors and arithmetic)",
-               2: "k_spmv_rows<4, double, true> (FP64 SpMV of the 4x4-block momentum Jacobian in FGMRES)",
-               3: "k_ns_rows<3, double> (momentum/mass residual and Jacobian assembly: J, its BF16 copy for the "
-                  "multigrid and R written once, connectivity and node fields read once)"}
-KERNEL_KEY = {1: "k_sweep_blk", 2: "k_spmv_rows", 3: "k_ns_rows"}
+KERNEL_NAME = {1: "k_sweep_blk<4, eft_bf16, float, true> (finest-level multigrid smoother sweep, BF16 copy of the "
+                  "4x4-block momentum Jacobian with its pattern in stencil form (row masks, no column indices), "
+                  "FP32 block inverses, FP64 vectors and arithmetic)",
+               2: "k_spmv_stn<4, true> (FP64 SpMV of the 4x4-block momentum Jacobian in FGMRES, pattern in "
+                  "stencil form)",
+               3: "k_ns_rows<3, double, true> (momentum/mass residual and Jacobian assembly with the node records "
+                  "staged per workgroup: J, its BF16 copy for the multigrid and R written once, connectivity and "
+                  "node fields read once)"}
+KERNEL_KEY = {1: "k_sweep_blk", 2: "k_spmv_stn", 3: "k_ns_rows"}
 # sources each kernel's counter figures were taken on
 KERNEL_SOURCES = {1: ("bsr_rows.h", "k_mg.hip"), 2: ("bsr_rows.h", "k_sparse.hip"),
                   3: ("k_assemble.hip", "dev_common.h")}
@@ -250,7 +253,7 @@ def pair_line(kts, workload):
         traffic = round(ta * a["active"] + ts * s["active"])
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                kernel="k_ns_rows + k_spmv_rows (assembly and FGMRES SpMV of the momentum/mass system, FP64)",
+                kernel="k_ns_rows + k_spmv_stn (assembly and FGMRES SpMV of the momentum/mass system, FP64)",
                 traffic_unit="HBM bytes of all their launches in the kernel-timing steps (rocprofv3 FETCH_SIZE + "
                              "WRITE_SIZE per launch, scaled by a plain copy, times the launches)",
                 algorithmic_bytes=round(byt), seconds=round(sec, 6),

@@ -90,9 +90,9 @@ void free_all(eft_ctx *ctx)
     auto fr = [](void *p) {
         if (p) (void)hipFree(p);
     };
-    fr(ctx->xyz); fr(ctx->conn); fr(ctx->epos); fr(ctx->iptr); fr(ctx->ient); fr(ctx->islot); fr(ctx->cell_of); fr(ctx->dir_node); fr(ctx->dir_mask); fr(ctx->fmask0);
+    fr(ctx->xyz); fr(ctx->conn); fr(ctx->epos); fr(ctx->iptr); fr(ctx->ient); fr(ctx->islot); fr(ctx->wnptr); fr(ctx->wnode); fr(ctx->iloc); fr(ctx->cell_of); fr(ctx->dir_node); fr(ctx->dir_mask); fr(ctx->fmask0);
     fr(ctx->dir_val); fr(ctx->phase_tab); fr(ctx->ind_of_phase);
-    fr(ctx->J.rowptr); fr(ctx->J.col); fr(ctx->J.diag); fr(ctx->J.val); fr(ctx->J.val32);
+    fr(ctx->J.rowptr); fr(ctx->J.col); fr(ctx->J.stn_mask); fr(ctx->J.stn_off); fr(ctx->J.diag); fr(ctx->J.val); fr(ctx->J.val32);
     fr(ctx->va); fr(ctx->acc); fr(ctx->rho); fr(ctx->mu); fr(ctx->smask); fr(ctx->solid_ind_d); fr(ctx->R); fr(ctx->dx);
     fr(ctx->l_vp); fr(ctx->l_vdot); fr(ctx->l_phi); fr(ctx->l_phidot); fr(ctx->l_B); fr(ctx->l_Bdot);
     eft_band_free(ctx);
@@ -373,6 +373,15 @@ eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *
     EFT_TRY(upload(ctx, &ctx->iptr, iptr.data(), N + 1));
     EFT_TRY(upload(ctx, &ctx->ient, ient.data(), E * nn));
     EFT_TRY(upload(ctx, &ctx->islot, islot.data(), E * nn));
+    {
+        std::vector<int32_t> wnptr, wnode;
+        std::vector<uint32_t> iloc;
+        if (eft_ns_stage_build(N, nn, conn, iptr, ient, ctx->rpb_ns, wnptr, wnode, iloc, ctx->maxnl, ctx->maxpw)) {
+            EFT_TRY(upload(ctx, &ctx->wnptr, wnptr.data(), (int64_t)wnptr.size()));
+            EFT_TRY(upload(ctx, &ctx->wnode, wnode.data(), (int64_t)wnode.size()));
+            EFT_TRY(upload(ctx, &ctx->iloc, iloc.data(), (int64_t)iloc.size()));
+        }
+    }
     EFT_TRY(upload(ctx, &ctx->cell_of, cell_of.data(), E));
     ctx->n_dir = mesh->n_dir;
     if (mesh->n_dir > 0) {
@@ -392,6 +401,16 @@ eft_status create_impl(eft_ctx *ctx, const eft_mesh *mesh, const eft_materials *
     ctx->J.nnzb = nnzb;
     EFT_TRY(upload(ctx, &ctx->J.rowptr, rowptr.data(), N + 1));
     EFT_TRY(upload(ctx, &ctx->J.col, col.data(), nnzb));
+    {
+        // the multigrid's narrow-value sweeps read the pattern in stencil
+        // form when it has one (one offset per lane of a row's segment)
+        std::vector<int32_t> soff;
+        std::vector<uint16_t> sm;
+        if (eft_stencil_form(N, rowptr, col, bs == 4 ? 16 : 8, soff, sm)) {
+            EFT_TRY(upload(ctx, &ctx->J.stn_mask, sm.data(), N));
+            EFT_TRY(upload(ctx, &ctx->J.stn_off, soff.data(), (int64_t)soff.size()));
+        }
+    }
     EFT_TRY(upload(ctx, &ctx->J.diag, diag.data(), N));
     EFT_TRY(alloc_jacobian_values(ctx));
     // Dirichlet bits of every node, and the free bits the assembly writes

@@ -268,3 +268,94 @@ __device__ __forceinline__ void bsr_block_dot(int k0, int k1, const int32_t *__r
 #pragma unroll
         for (int i = 0; i < BS; ++i) acc[i] += __shfl_xor(acc[i], s, 64);
 }
+
+// A whole bs x bs block (row-major at p) into v, with the widest loads its
+// alignment allows: a 4x4 BF16 block (32 bytes, 32-byte aligned) is two
+// 16-byte loads.
+template <int BS, typename TV> __device__ __forceinline__ void block_get(const TV *__restrict__ p, double (&v)[BS][BS])
+{
+    if constexpr (BS == 4 && sizeof(TV) == 2) {
+        typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+        const u4 lo = reinterpret_cast<const u4 *>(p)[0], hi = reinterpret_cast<const u4 *>(p)[1];
+        const uint32_t w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            v[t / 2][2 * (t % 2)] = bf16_to_double(w[t] & 0xFFFFu);
+            v[t / 2][2 * (t % 2) + 1] = bf16_to_double(w[t] >> 16);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < BS; ++i) RowLoad<BS, TV, false>::get(p + i * BS, v[i]);
+    }
+}
+
+// The same product for a pattern in stencil form: every column of row r is r
+// + soff[s] for the set bits s of the row's mask m (soff ascending, at most
+// SEG offsets), so lane j of the segment takes stencil slot j: its block is
+// the popcount of the mask below j past the row's first block, its column is
+// row + soff_j.  No column index is read, and the x gather does not wait for
+// one.
+template <int BS, typename TV, int SEG>
+__device__ __forceinline__ void bsr_stencil_dot(int k0, uint32_t m, int64_t row, int soff_j,
+                                                const TV *__restrict__ val, const double *__restrict__ x, int j,
+                                                double (&acc)[BS])
+{
+#pragma unroll
+    for (int i = 0; i < BS; ++i) acc[i] = 0.0;
+    if ((m >> j) & 1u) {
+        const int k = k0 + __popc(m & ((1u << j) - 1u));
+        double v[BS][BS], xx[BS];
+        block_get<BS, TV>(val + (int64_t)k * (BS * BS), v);
+        x_get<BS>(x, row + soff_j, xx);
+#pragma unroll
+        for (int i = 0; i < BS; ++i)
+#pragma unroll
+            for (int e = 0; e < BS; ++e) acc[i] += v[i][e] * xx[e];
+    }
+#pragma unroll
+    for (int s = SEG / 2; s > 0; s >>= 1)
+#pragma unroll
+        for (int i = 0; i < BS; ++i) acc[i] += __shfl_xor(acc[i], s, 64);
+}
+
+// bsr_rows_dot for a pattern in stencil form (wave-uniform rows row[q] with
+// masks m[q]; soff_j = the offset of stencil slot j = lane / bs, 0 past the
+// slots): lane bs*j + r takes scalar row r of the block at slot j, so no
+// column index is read.  MAXS: the slots (at most 64 / bs).
+template <int BS, typename TV, int R, int MAXS>
+__device__ __forceinline__ void bsr_rows_stencil_dot(const int (&k0)[R], const uint32_t (&m)[R],
+                                                     const int64_t (&row)[R], int soff_j,
+                                                     const TV *__restrict__ val, const double *__restrict__ x,
+                                                     int lane, double (&acc)[R])
+{
+    static_assert(MAXS * BS <= 64, "one slot per group of bs lanes");
+    const int j = lane / BS, r = lane - j * BS;
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = 0.0;
+    if (j < MAXS) {
+        double v[R][BS], xv[R][BS];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const bool ok = (m[q] >> j) & 1u;
+            const int k = k0[q] + __popc(m[q] & ((1u << j) - 1u));
+            if (ok) {
+                RowLoad<BS, TV, false>::get(val + (int64_t)k * (BS * BS) + r * BS, v[q]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < BS; ++e) v[q][e] = 0.0;
+            }
+            x_get<BS>(x, ok ? row[q] + soff_j : 0, xv[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+            for (int e = 0; e < BS; ++e) acc[q] += v[q][e] * xv[q][e];
+    }
+#pragma unroll
+    for (int s = 1; s < MAXS; s <<= 1)
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const double o = __shfl_down(acc[q], s * BS, 64);
+            if (j + s < MAXS) acc[q] += o;
+        }
+}

@@ -28,6 +28,10 @@ struct eft_matrix {
     float *val32 = nullptr;
     uint16_t *val16 = nullptr;   // BF16 values (the finest multigrid level's copy)
     const double *bcmp = nullptr;  // B systems: the blocks in compact form (s1, M), see eft_bcmp_*
+    // the pattern in stencil form, or null: every column of row r is r +
+    // stn_off[s] for the set bits s of stn_mask[r] (ascending), see eft_stencil_form
+    uint16_t *stn_mask = nullptr;
+    int32_t *stn_off = nullptr;
     bool fp32 = false;
     bool bf16 = false;
 };
@@ -99,6 +103,10 @@ struct MeshView {
     const uint32_t *islot = nullptr;  // per incidence entry: its row's block slots, see eft_build_graph
     int maxc = 0, rpb = 1;                           // longest matrix row, rows per workgroup
     const uint8_t *fmask = nullptr;                  // [N] bit c set when dof c is free (others: unit rows)
+    // node records staged per assembly workgroup (null: read from the node arrays), see eft_ns_stage_build
+    const int32_t *wnptr = nullptr, *wnode = nullptr;
+    const uint32_t *iloc = nullptr;
+    int maxnl = 0, maxpw = 0;
 };
 
 // One level of the geometric multigrid hierarchy on nested Kuhn meshes.
@@ -198,6 +206,11 @@ struct eft_ctx {
     uint8_t *fmask0 = nullptr;      // [N] bit c set when dof c of the node is free (not Dirichlet)
     int maxc = 0, rpb = 1;          // longest row of the node graph, rows per band-assembly workgroup
     int rpb_ns = 1;                 // rows per momentum/mass assembly workgroup
+    // per assembly workgroup: its nodes (wnode[wnptr[w] .. wnptr[w + 1])) and per
+    // incidence entry the list positions of the element's nodes (null: not staged)
+    int32_t *wnptr = nullptr, *wnode = nullptr;
+    uint32_t *iloc = nullptr;
+    int maxnl = 0, maxpw = 0;
     int32_t *cell_of = nullptr;     // [E] band grid cell of each element
     int64_t n_dir = 0;
     int32_t *dir_node = nullptr;
@@ -335,6 +348,12 @@ eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_ma
 // same launch)
 eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, double *R, eft_matrix *J,
                         float *J32 = nullptr, uint16_t *J16 = nullptr);
+
+bool eft_stencil_form(int64_t n, const std::vector<int32_t> &rowptr, const std::vector<int32_t> &col, int maxs,
+                      std::vector<int32_t> &soff, std::vector<uint16_t> &smask);
+bool eft_ns_stage_build(int64_t N, int nn, const int32_t *conn, const std::vector<int32_t> &iptr,
+                        const std::vector<int32_t> &ient, int rpb, std::vector<int32_t> &wnptr,
+                        std::vector<int32_t> &wnode, std::vector<uint32_t> &iloc, int &maxnl, int &maxpw);
 
 // k_mg.hip
 eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<uint8_t> &dmask0);

@@ -100,7 +100,10 @@ __global__ __launch_bounds__(256) void k_props(PropsArgs a)
 // the row -- the residual of the row node and the blocks coupling it to the
 // element's nodes -- into LDS accumulators.  Each element is thus evaluated
 // once per node (4 times in 3D) instead of scattering 16 blocks with global
-// atomics; the finished rows are written once, contiguously.
+// atomics; the finished rows are written once, contiguously.  When the mesh
+// allows it (at most 256 nodes per workgroup), the records of the nodes the
+// workgroup's elements touch and its incidence words are first staged in LDS,
+// so the pair loop makes no global loads.
 struct RowArgs {
     int64_t N;                   // rows (nodes)
     int rpb, maxc;               // rows per workgroup, longest row (LDS layout)
@@ -121,6 +124,18 @@ struct RowArgs {
     uint16_t *J16;   // optional BF16 copy of the values
     const int32_t *col;      // block columns of the pattern
     const uint8_t *fmask;    // [N] free-dof bits: a Dirichlet dof's row is written as a unit row, residual 0
+    // staged node records (or null): per workgroup its nodes wnode[wnptr[w] ..
+    // wnptr[w + 1]) and per incidence entry the positions of the element's
+    // nodes in that list (byte b: node (a + b) mod nn)
+    const int32_t *wnptr, *wnode;
+    const uint32_t *iloc;
+    int maxnl, maxpw;        // most nodes, most incidence entries of a workgroup
+};
+
+// Staged node record in LDS: x, v and a at n+alpha, p, rho, mu, the solid
+// mask (bits); an odd stride in doubles
+template <int D> struct NodeRec {
+    static constexpr int n = (3 * D + 4) | 1;
 };
 
 // Elastic stress mu_L (B - I) of solid sI on the element of one (row,
@@ -244,7 +259,7 @@ __device__ __forceinline__ void elastic_pair(const RowArgs &a, const int (&nd)[D
     }
 }
 
-template <int D, typename TJ>
+template <int D, typename TJ, bool ST>
 __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ Jv)
 {
     extern __shared__ double lds[];
@@ -264,6 +279,12 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
     int *rstart = istart + (a.rpb + 1);                      // [rpb + 1]
     uint16_t *blkrow = reinterpret_cast<uint16_t *>(rstart + (a.rpb + 1));   // [rpb * maxc]
     uint8_t *fml = reinterpret_cast<uint8_t *>(blkrow + a.rpb * a.maxc);     // [rpb]
+    // staged: the workgroup's node records, node ids and incidence words
+    constexpr int NR = NodeRec<D>::n;
+    double *ndat = lds + nacc + ((2 * (a.rpb + 1) * 4 + a.rpb * a.maxc * 2 + a.rpb + 7) / 8);   // [maxnl][NR]
+    int *nid = reinterpret_cast<int *>(ndat + (ST ? a.maxnl * NR : 0));                     // [maxnl]
+    uint32_t *pw = reinterpret_cast<uint32_t *>(nid + (ST ? a.maxnl : 0));                 // [maxpw][2]
+    uint8_t *pla = reinterpret_cast<uint8_t *>(pw + (ST ? 2 * a.maxpw : 0));              // [maxpw]
     __shared__ int maxinc, eq_n;
     __shared__ uint32_t eq[EQ_CAP];   // queued (pair << 6 | solid) elastic work
     if (threadIdx.x == 0) maxinc = eq_n = 0;
@@ -274,10 +295,37 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
         rstart[threadIdx.x] = a.rowptr[r0 + threadIdx.x];
     }
     if (threadIdx.x < nrow) fml[threadIdx.x] = a.fmask[r0 + threadIdx.x];
+    if constexpr (ST) {
+        // the records of every node the rows' elements touch, read once
+        const int w0 = a.wnptr[blockIdx.x], nl = a.wnptr[blockIdx.x + 1] - w0;
+        for (int t = threadIdx.x; t < nl; t += blockDim.x) {
+            const int64_t n = a.wnode[w0 + t];
+            double *rec = ndat + t * NR;
+            nid[t] = (int)n;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                rec[i] = a.xyz[n * D + i];
+                rec[D + i] = a.va[n * D + i];
+                rec[2 * D + i] = a.acc[n * D + i];
+            }
+            rec[3 * D] = a.vp[n * BS + D];
+            rec[3 * D + 1] = a.rho[n];
+            rec[3 * D + 2] = a.mu[n];
+            rec[3 * D + 3] = __longlong_as_double((long long)a.smask[n]);
+        }
+    }
     __syncthreads();
     if (threadIdx.x < nrow) {
         atomicMax(&maxinc, istart[threadIdx.x + 1] - istart[threadIdx.x]);
         for (int k = rstart[threadIdx.x]; k < rstart[threadIdx.x + 1]; ++k) blkrow[k - rstart[0]] = threadIdx.x;
+    }
+    if constexpr (ST) {
+        const int i0 = istart[0], npw = istart[nrow] - i0;
+        for (int t = threadIdx.x; t < npw; t += blockDim.x) {
+            pw[2 * t] = a.iloc[i0 + t];
+            pw[2 * t + 1] = a.islot[i0 + t];
+            pla[t] = (uint8_t)(a.ient[i0 + t] & 3);
+        }
     }
     __syncthreads();
     const double gv[3] = {a.g0, a.g1, a.g2};
@@ -288,29 +336,49 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
         const int kr = k % nrow;
         const int ii = istart[kr] + k / nrow;
         if (ii >= istart[kr + 1]) continue;
-        const int32_t ent = a.ient[ii];
-        const uint32_t sl = a.islot[ii];
-        const int64_t e = ent >> 2;
-        const int la = ent & 3;
         // the element's nodes rotated so that the row node comes first (local
         // node b is node (la + b) mod NN of the connectivity): every index
         // below is then a compile-time constant
-        int nd[NN];
+        int nd[NN], la;
+        uint32_t sl, lw = 0;
         double X[NN][D], v[NN][D], ac[NN][D], p[NN], rh[NN], mu[NN];
+        uint64_t present = 0;   // solids present on the element
+        if constexpr (ST) {
+            // (the staged path keeps only the positions and reads the other
+            // node values from LDS where it uses them)
+            const int j = ii - istart[0];
+            lw = pw[2 * j];
+            sl = pw[2 * j + 1];
+            la = pla[j];
 #pragma unroll
-        for (int b = 0; b < NN; ++b) nd[b] = a.conn[e * NN + (la + b < NN ? la + b : la + b - NN)];
+            for (int b = 0; b < NN; ++b) {
+                const int lb = (lw >> (8 * b)) & 0xff;
+                const double *rec = ndat + lb * NR;
+                nd[b] = nid[lb];
 #pragma unroll
-        for (int b = 0; b < NN; ++b) {
-            const int64_t n = nd[b];
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                X[b][i] = a.xyz[n * D + i];
-                v[b][i] = a.va[n * D + i];
-                ac[b][i] = a.acc[n * D + i];
+                for (int i = 0; i < D; ++i) X[b][i] = rec[i];
+                present |= (uint64_t)__double_as_longlong(rec[3 * D + 3]);
             }
-            p[b] = a.vp[n * BS + D];
-            rh[b] = a.rho[n];
-            mu[b] = a.mu[n];
+        } else {
+            const int32_t ent = a.ient[ii];
+            sl = a.islot[ii];
+            const int64_t e = ent >> 2;
+            la = ent & 3;
+#pragma unroll
+            for (int b = 0; b < NN; ++b) nd[b] = a.conn[e * NN + (la + b < NN ? la + b : la + b - NN)];
+#pragma unroll
+            for (int b = 0; b < NN; ++b) {
+                const int64_t n = nd[b];
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    X[b][i] = a.xyz[n * D + i];
+                    v[b][i] = a.va[n * D + i];
+                    ac[b][i] = a.acc[n * D + i];
+                }
+                p[b] = a.vp[n * BS + D];
+                rh[b] = a.rho[n];
+                mu[b] = a.mu[n];
+            }
         }
         const int64_t row = nd[0];
         const int lr = (int)(row - r0);
@@ -347,19 +415,48 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
             for (int j = 0; j < D; ++j) GG += G[i][j] * G[i][j];
         }
         double L[D][D], gp[D], divv = 0.0;
+        // staged: the node sums of rho, mu, p, v and a, with which a point
+        // value is QB * sum + (QA - QB) * (value at the point's node)
+        double Srh = 0.0, Smu = 0.0, Sp = 0.0, Sv[D], Sac[D];
+        if constexpr (ST) {
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
+            for (int i = 0; i < D; ++i) {
+                Sv[i] = Sac[i] = gp[i] = 0.0;
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
+                for (int j = 0; j < D; ++j) L[i][j] = 0.0;
+            }
+#pragma unroll
+            for (int b = 0; b < NN; ++b) {
+                const double *rec = ndat + ((lw >> (8 * b)) & 0xff) * NR;
+                const double pb = rec[3 * D];
+                Sp += pb;
+                Srh += rec[3 * D + 1];
+                Smu += rec[3 * D + 2];
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    const double vb = rec[D + i];
+                    Sv[i] += vb;
+                    Sac[i] += rec[2 * D + i];
+                    gp[i] += pb * dN[b][i];
+#pragma unroll
+                    for (int j = 0; j < D; ++j) L[i][j] += vb * dN[b][j];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int b = 0; b < NN; ++b) s += v[b][i] * dN[b][j];
+                    L[i][j] = s;
+                }
                 double s = 0.0;
 #pragma unroll
-                for (int b = 0; b < NN; ++b) s += v[b][i] * dN[b][j];
-                L[i][j] = s;
+                for (int b = 0; b < NN; ++b) s += p[b] * dN[b][i];
+                gp[i] = s;
             }
-            double s = 0.0;
-#pragma unroll
-            for (int b = 0; b < NN; ++b) s += p[b] * dN[b][i];
-            gp[i] = s;
         }
 #pragma unroll
         for (int i = 0; i < D; ++i) divv += L[i][i];
@@ -388,18 +485,30 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
 #pragma unroll 1
         for (int q = 0; q < NQ; ++q) {
             double rq = 0.0, mq = 0.0, pq = 0.0, vq[D], aq[D];
-#pragma unroll
-            for (int i = 0; i < D; ++i) vq[i] = aq[i] = 0.0;
-#pragma unroll
-            for (int b = 0; b < NN; ++b) {
-                const double Nb = b == q ? QA : QB;
-                rq += Nb * rh[b];
-                mq += Nb * mu[b];
-                pq += Nb * p[b];
+            if constexpr (ST) {
+                const double *rec = ndat + ((lw >> (8 * q)) & 0xff) * NR;
+                pq = QB * Sp + QD * rec[3 * D];
+                rq = QB * Srh + QD * rec[3 * D + 1];
+                mq = QB * Smu + QD * rec[3 * D + 2];
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
-                    vq[i] += Nb * v[b][i];
-                    aq[i] += Nb * ac[b][i];
+                    vq[i] = QB * Sv[i] + QD * rec[D + i];
+                    aq[i] = QB * Sac[i] + QD * rec[2 * D + i];
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < D; ++i) vq[i] = aq[i] = 0.0;
+#pragma unroll
+                for (int b = 0; b < NN; ++b) {
+                    const double Nb = b == q ? QA : QB;
+                    rq += Nb * rh[b];
+                    mq += Nb * mu[b];
+                    pq += Nb * p[b];
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        vq[i] += Nb * v[b][i];
+                        aq[i] += Nb * ac[b][i];
+                    }
                 }
             }
             double Rm[D], body[D], vGv = 0.0;
@@ -501,9 +610,10 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
         // run the solid body for a few of its lanes), inline when the queue
         // is full
         if (a.n_s > 0) {
-            uint64_t present = 0;
+            if constexpr (!ST) {
 #pragma unroll
-            for (int b = 0; b < NN; ++b) present |= a.smask[nd[b]];
+                for (int b = 0; b < NN; ++b) present |= a.smask[nd[b]];
+            }
             while (present) {   // in increasing solid order
                 const int sI = __ffsll((unsigned long long)present) - 1;
                 present &= present - 1;
@@ -524,17 +634,31 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
         const int k = (int)(item >> 6), sI = (int)(item & 63);
         const int kr = k % nrow;
         const int ii = istart[kr] + k / nrow;
-        const int32_t ent = a.ient[ii];
-        const uint32_t sl = a.islot[ii];
-        const int64_t e = ent >> 2;
-        const int la = ent & 3;
         int nd[NN];
+        uint32_t sl;
         double X[NN][D];
+        if constexpr (ST) {
+            const int j = ii - istart[0];
+            const uint32_t lw = pw[2 * j];
+            sl = pw[2 * j + 1];
 #pragma unroll
-        for (int b = 0; b < NN; ++b) {
-            nd[b] = a.conn[e * NN + (la + b < NN ? la + b : la + b - NN)];
+            for (int b = 0; b < NN; ++b) {
+                const int lb = (lw >> (8 * b)) & 0xff;
+                nd[b] = nid[lb];
 #pragma unroll
-            for (int i = 0; i < D; ++i) X[b][i] = a.xyz[(int64_t)nd[b] * D + i];
+                for (int i = 0; i < D; ++i) X[b][i] = ndat[lb * NR + i];
+            }
+        } else {
+            const int32_t ent = a.ient[ii];
+            sl = a.islot[ii];
+            const int64_t e = ent >> 2;
+            const int la = ent & 3;
+#pragma unroll
+            for (int b = 0; b < NN; ++b) {
+                nd[b] = a.conn[e * NN + (la + b < NN ? la + b : la + b - NN)];
+#pragma unroll
+                for (int i = 0; i < D; ++i) X[b][i] = a.xyz[(int64_t)nd[b] * D + i];
+            }
         }
         double dN[NN][D], G[D][D];
         const double w = simplex_geom<D>(X, dN, G) * Rule<D>::WF;
@@ -602,6 +726,63 @@ eft_status eft_fill_u8(eft_ctx *ctx, uint8_t *p, int64_t n)
     return EFT_OK;
 }
 
+// ------------------------------------------------------ staged records --
+
+// Node records staged per momentum-assembly workgroup (rows [w rpb, (w + 1)
+// rpb)): the sorted nodes of the elements incident to its rows, and per
+// incidence entry (element e, local node a) the positions in that list of
+// nodes (a + b) mod nn, one byte each.  Returns false, with the outputs
+// cleared, when a workgroup touches more than 256 nodes (the assembly then
+// reads the node fields from the global arrays).
+bool eft_ns_stage_build(int64_t N, int nn, const int32_t *conn, const std::vector<int32_t> &iptr,
+                        const std::vector<int32_t> &ient, int rpb, std::vector<int32_t> &wnptr,
+                        std::vector<int32_t> &wnode, std::vector<uint32_t> &iloc, int &maxnl, int &maxpw)
+{
+    const int64_t nw = (N + rpb - 1) / rpb;
+    wnptr.assign(nw + 1, 0);
+    wnode.clear();
+    iloc.assign(ient.size(), 0);
+    maxnl = maxpw = 0;
+    std::vector<int64_t> seen(N, -1);   // workgroup that last listed the node
+    std::vector<int32_t> pos(N, 0);     // its position in that list
+    std::vector<int32_t> buf;
+    for (int64_t w = 0; w < nw; ++w) {
+        const int64_t r0 = w * rpb, r1 = std::min<int64_t>(N, r0 + rpb);
+        buf.clear();
+        for (int64_t t = iptr[r0]; t < iptr[r1]; ++t) {
+            const int64_t e = ient[t] >> 2;
+            for (int b = 0; b < nn; ++b) {
+                const int32_t n = conn[e * nn + b];
+                if (seen[n] != w) {
+                    seen[n] = w;
+                    buf.push_back(n);
+                }
+            }
+        }
+        if (buf.size() > 256) {
+            wnptr.clear();
+            wnode.clear();
+            iloc.clear();
+            maxnl = maxpw = 0;
+            return false;
+        }
+        std::sort(buf.begin(), buf.end());
+        for (size_t i = 0; i < buf.size(); ++i) pos[buf[i]] = (int32_t)i;
+        for (int64_t t = iptr[r0]; t < iptr[r1]; ++t) {
+            const int64_t e = ient[t] >> 2;
+            const int a = ient[t] & 3;
+            uint32_t word = 0;
+            for (int b = 0; b < nn; ++b) word |= (uint32_t)pos[conn[e * nn + (a + b) % nn]] << (8 * b);
+            iloc[t] = word;
+        }
+        wnode.insert(wnode.end(), buf.begin(), buf.end());
+        wnptr[w + 1] = (int32_t)wnode.size();
+        maxnl = std::max(maxnl, (int)buf.size());
+        maxpw = std::max(maxpw, (int)(iptr[r1] - iptr[r0]));
+    }
+    return true;
+}
+
 // ------------------------------------------------------------- launchers --
 
 eft_status eft_props(eft_ctx *ctx, const eft_state *lvl, const eft_iterate *it)
@@ -665,6 +846,12 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
     a.rowptr = J ? J->rowptr : nullptr;
     a.col = J ? J->col : nullptr;
     a.fmask = M.fmask;
+    a.wnptr = M.wnptr;
+    a.wnode = M.wnode;
+    a.iloc = M.iloc;
+    a.maxnl = M.maxnl;
+    a.maxpw = M.maxpw;
+    const bool st = M.iloc != nullptr;
     if (!M.fmask) {
         ctx->err = "assembly without the free-dof mask";
         return EFT_EINVAL;
@@ -701,8 +888,11 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
         a.rowptr = ctx->J.rowptr;
     }
     const int nb = eft_grid(M.N, M.rpb);
-    const size_t shm = (size_t)M.rpb * ((size_t)M.maxc * ((BS * BS) | 1) + (BS | 1)) * sizeof(double) +
-                       (size_t)(M.rpb + 1) * 2 * sizeof(int) + (size_t)M.rpb * M.maxc * sizeof(uint16_t) + M.rpb;
+    const size_t nrec = ctx->dim == 2 ? NodeRec<2>::n : NodeRec<3>::n;
+    const size_t meta = ((size_t)(M.rpb + 1) * 2 * sizeof(int) + (size_t)M.rpb * M.maxc * sizeof(uint16_t) + M.rpb + 7) /
+                        8 * 8;
+    const size_t shm = (size_t)M.rpb * ((size_t)M.maxc * ((BS * BS) | 1) + (BS | 1)) * sizeof(double) + meta +
+                       (st ? (size_t)M.maxnl * (nrec * sizeof(double) + sizeof(int)) + (size_t)M.maxpw * 9 : 0);
     // kernel-timing hook on the mesh level (not the coarse levels).
     // Algorithmic bytes: J (and its FP32 or BF16 copy when written) and R
     // written once; read once: the connectivity, the node state the element
@@ -718,13 +908,20 @@ eft_status eft_ns_level(eft_ctx *ctx, const MeshView &M, const double *vp, doubl
         (double)M.N * BS * 8.0 +
         (double)M.E * (d + 1) * 4.0 +
         (double)M.N * 8.0 * (3 * d + 4) + (double)M.N;
+#define EFT_NS_LAUNCH(DD, TT, STG, JP) \
+    hipLaunchKernelGGL((k_ns_rows<DD, TT, STG>), dim3(nb), dim3(256), shm, ctx->stream, a, JP)
+    float *j32 = (J && J->fp32) ? J->val32 : nullptr;
+    double *j64 = (J && !J->fp32) ? J->val : nullptr;
     if (ctx->dim == 2) {
-        if (J && J->fp32) hipLaunchKernelGGL((k_ns_rows<2, float>), dim3(nb), dim3(256), shm, ctx->stream, a, J->val32);
-        else hipLaunchKernelGGL((k_ns_rows<2, double>), dim3(nb), dim3(256), shm, ctx->stream, a, J ? J->val : nullptr);
+        if (j32) { if (st) EFT_NS_LAUNCH(2, float, true, j32); else EFT_NS_LAUNCH(2, float, false, j32); }
+        else if (st) EFT_NS_LAUNCH(2, double, true, j64);
+        else EFT_NS_LAUNCH(2, double, false, j64);
     } else {
-        if (J && J->fp32) hipLaunchKernelGGL((k_ns_rows<3, float>), dim3(nb), dim3(256), shm, ctx->stream, a, J->val32);
-        else hipLaunchKernelGGL((k_ns_rows<3, double>), dim3(nb), dim3(256), shm, ctx->stream, a, J ? J->val : nullptr);
+        if (j32) { if (st) EFT_NS_LAUNCH(3, float, true, j32); else EFT_NS_LAUNCH(3, float, false, j32); }
+        else if (st) EFT_NS_LAUNCH(3, double, true, j64);
+        else EFT_NS_LAUNCH(3, double, false, j64);
     }
+#undef EFT_NS_LAUNCH
     EFT_HIP(hipGetLastError());
     eft_kt_end(ctx, slot, abytes, EFT_KT_ASSEMBLE);
     return EFT_OK;
@@ -757,6 +954,11 @@ eft_status eft_ns_kernels(eft_ctx *ctx, const eft_iterate *it, double *R, eft_ma
     M.islot = ctx->islot;
     M.maxc = ctx->maxc;
     M.rpb = ctx->rpb_ns;
+    M.wnptr = ctx->wnptr;
+    M.wnode = ctx->wnode;
+    M.iloc = ctx->iloc;
+    M.maxnl = ctx->maxnl;
+    M.maxpw = ctx->maxpw;
     // with the multigrid active, the assembly also writes the finest level's
     // FP32 copy of the values (no separate conversion pass over J)
     const bool mg = J && eft_mg_enabled(ctx, J);

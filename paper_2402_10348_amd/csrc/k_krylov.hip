@@ -501,8 +501,11 @@ eft_status eft_dot_dev(eft_ctx *ctx, const double *x, const double *y, int64_t n
 // read and y written once.
 static double spmv_bytes(const eft_matrix *A)
 {
+    // (in stencil form the row masks replace the column indices)
     const double vb = A->fp32 ? 4.0 : 8.0, b2 = (double)A->bs * A->bs;
-    return (double)A->nnzb * (b2 * vb + 4.0) + (double)(A->n + 1) * 4.0 + 2.0 * A->n * A->bs * 8.0;
+    const bool stn = A->stn_mask && !A->fp32 && (A->bs == 3 || A->bs == 4);
+    const double cols = stn ? (double)A->n * 2.0 : (double)A->nnzb * 4.0;
+    return (double)A->nnzb * b2 * vb + cols + (double)(A->n + 1) * 4.0 + 2.0 * A->n * A->bs * 8.0;
 }
 
 // Enqueue column j of a momentum solve as a HIP graph: captured from the

@@ -154,9 +154,10 @@ __global__ __launch_bounds__(256) void k_sweep_rows(int64_t n, const int32_t *__
 
 // The same sweep with one block per lane (narrow values, bs 3 or 4): lane j
 // < bs of a row's segment finishes component j of the row.
-template <int BS, typename TV, typename TD>
+template <int BS, typename TV, typename TD, bool STN>
 __device__ __forceinline__ void sweep_blk_rows(int64_t row0, int64_t n, const int32_t *__restrict__ rowptr,
-                                               const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                               const int32_t *__restrict__ col, const uint16_t *__restrict__ smask,
+                                               const int32_t *__restrict__ soff, const TV *__restrict__ val,
                                                const TD *__restrict__ Dinv, double omega,
                                                const double *__restrict__ b, const double *__restrict__ x,
                                                double *__restrict__ xo)
@@ -165,6 +166,12 @@ __device__ __forceinline__ void sweep_blk_rows(int64_t row0, int64_t n, const in
     const int lane = threadIdx.x & 63, q = lane / SEG, j = lane - q * SEG;
     const int64_t row = row0 + q, rr = row < n ? row : row0;   // rr: in bounds, unused past n
     const int jj = j < BS ? j : 0;
+    uint32_t m = 0;
+    int oj = 0;
+    if constexpr (STN) {
+        m = row < n ? smask[rr] : 0u;
+        oj = soff[j];
+    }
     // row data of the update, loaded ahead of the product
     double bb[BS], d[BS];
     x_get<BS>(b, rr, bb);
@@ -173,7 +180,8 @@ __device__ __forceinline__ void sweep_blk_rows(int64_t row0, int64_t n, const in
     int k0, k1;
     seg_extents<RPW>(row0, n, rowptr, q, k0, k1);
     double ax[BS];
-    bsr_block_dot<BS, TV, SEG>(k0, k1, col, val, x, j, ax);
+    if constexpr (STN) bsr_stencil_dot<BS, TV, SEG>(k0, m, rr, oj, val, x, j, ax);
+    else bsr_block_dot<BS, TV, SEG>(k0, k1, col, val, x, j, ax);
     double u = 0.0;
 #pragma unroll
     for (int c = 0; c < BS; ++c) u += d[c] * (bb[c] - ax[c]);
@@ -182,16 +190,19 @@ __device__ __forceinline__ void sweep_blk_rows(int64_t row0, int64_t n, const in
 
 // The same sweep with one block per lane (narrow values, bs 3 or 4): lane j
 // < bs of a row's segment finishes component j of the row.
-template <int BS, typename TV, typename TD>
+// With the pattern in stencil form (smask, soff: see bsr_stencil_dot) no
+// column index is read.
+template <int BS, typename TV, typename TD, bool STN>
 __global__ __launch_bounds__(256) void k_sweep_blk(int64_t n, const int32_t *__restrict__ rowptr,
-                                                   const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                   const int32_t *__restrict__ col, const uint16_t *__restrict__ smask,
+                                                   const int32_t *__restrict__ soff, const TV *__restrict__ val,
                                                    const TD *__restrict__ Dinv, double omega,
                                                    const double *__restrict__ b, const double *__restrict__ x,
                                                    double *__restrict__ xo, const int32_t *flag)
 {
     const int64_t row0 = (xcd_block() * 4 + wave_id()) * BlockSeg<BS>::RPW;
     if (*flag == 0 || row0 >= n) return;
-    sweep_blk_rows<BS, TV, TD>(row0, n, rowptr, col, val, Dinv, omega, b, x, xo);
+    sweep_blk_rows<BS, TV, TD, STN>(row0, n, rowptr, col, smask, soff, val, Dinv, omega, b, x, xo);
 }
 
 // Block Gauss-Seidel on the rows of one colour, in place:
@@ -305,9 +316,10 @@ __global__ __launch_bounds__(256) void k_resid_rows(int64_t n, const int32_t *__
 }
 
 // r = b - A x with one block per lane (narrow values, bs 3 or 4)
-template <int BS, typename TV>
+template <int BS, typename TV, bool STN>
 __device__ __forceinline__ void resid_blk_rows(int64_t row0, int64_t n, const int32_t *__restrict__ rowptr,
-                                               const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                               const int32_t *__restrict__ col, const uint16_t *__restrict__ smask,
+                                               const int32_t *__restrict__ soff, const TV *__restrict__ val,
                                                const double *__restrict__ b, const double *__restrict__ x,
                                                double *__restrict__ r)
 {
@@ -315,10 +327,17 @@ __device__ __forceinline__ void resid_blk_rows(int64_t row0, int64_t n, const in
     const int lane = threadIdx.x & 63, q = lane / SEG, j = lane - q * SEG;
     const int64_t row = row0 + q, rr = row < n ? row : row0;
     const double br = b[rr * BS + (j < BS ? j : 0)];
+    uint32_t m = 0;
+    int oj = 0;
+    if constexpr (STN) {
+        m = row < n ? smask[rr] : 0u;
+        oj = soff[j];
+    }
     int k0, k1;
     seg_extents<RPW>(row0, n, rowptr, q, k0, k1);
     double ax[BS];
-    bsr_block_dot<BS, TV, SEG>(k0, k1, col, val, x, j, ax);
+    if constexpr (STN) bsr_stencil_dot<BS, TV, SEG>(k0, m, rr, oj, val, x, j, ax);
+    else bsr_block_dot<BS, TV, SEG>(k0, k1, col, val, x, j, ax);
     // component j of the row, stored by lane j (unrolled: no dynamically
     // indexed private array)
 #pragma unroll
@@ -326,15 +345,16 @@ __device__ __forceinline__ void resid_blk_rows(int64_t row0, int64_t n, const in
         if (j == c && row < n) r[row * BS + c] = br - ax[c];
 }
 
-template <int BS, typename TV>
+template <int BS, typename TV, bool STN>
 __global__ __launch_bounds__(256) void k_resid_blk(int64_t n, const int32_t *__restrict__ rowptr,
-                                                   const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                   const int32_t *__restrict__ col, const uint16_t *__restrict__ smask,
+                                                   const int32_t *__restrict__ soff, const TV *__restrict__ val,
                                                    const double *__restrict__ b, const double *__restrict__ x,
                                                    double *__restrict__ r, const int32_t *flag)
 {
     const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave_id()) * BlockSeg<BS>::RPW;
     if (*flag == 0 || row0 >= n) return;
-    resid_blk_rows<BS, TV>(row0, n, rowptr, col, val, b, x, r);
+    resid_blk_rows<BS, TV, STN>(row0, n, rowptr, col, smask, soff, val, b, x, r);
 }
 
 // --------------------------------------------------------- transfers ------
@@ -820,6 +840,39 @@ Dims dims_of(const MGLevel &L) { return Dims{{L.n[0], L.n[1], L.n[2]}}; }
 // | local node a) and, per entry, the block slots of its row: byte k of
 // islot is the position, within row a, of the column of local node
 // (a + k) mod nn.
+// Stencil form of a block pattern: when the column offsets c - r of all
+// entries take at most maxs distinct values, soff gets them in ascending order
+// (padded with zeros to maxs) and smask[r] the bits of the offsets row r has.
+// Rows list their columns in ascending order, so block k0[r] + (number of set
+// bits below s) of row r is the one at column r + soff[s].
+bool eft_stencil_form(int64_t n, const std::vector<int32_t> &rowptr, const std::vector<int32_t> &col, int maxs,
+                      std::vector<int32_t> &soff, std::vector<uint16_t> &smask)
+{
+    if (maxs > 16) return false;
+    std::vector<int64_t> offs;
+    for (int64_t r = 0; r < n; ++r)
+        for (int32_t k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+            const int64_t o = (int64_t)col[k] - r;
+            if (std::find(offs.begin(), offs.end(), o) == offs.end()) {
+                if ((int)offs.size() == maxs) return false;
+                offs.push_back(o);
+            }
+        }
+    std::sort(offs.begin(), offs.end());
+    soff.assign(maxs, 0);
+    for (size_t s = 0; s < offs.size(); ++s) soff[s] = (int32_t)offs[s];
+    smask.assign(n, 0);
+    for (int64_t r = 0; r < n; ++r) {
+        uint32_t m = 0;
+        for (int32_t k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+            const int64_t o = (int64_t)col[k] - r;
+            m |= 1u << (int)(std::lower_bound(offs.begin(), offs.end(), o) - offs.begin());
+        }
+        smask[r] = (uint16_t)m;
+    }
+    return true;
+}
+
 constexpr int64_t NS_PAIRS = 512;   // (row, element) pairs per momentum-assembly workgroup
 
 eft_status eft_build_graph(int64_t N, int64_t E, int nn, const int32_t *conn, std::vector<int32_t> &rowptr,
@@ -1029,6 +1082,14 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
         EFT_TRY(dput(ctx, &C.A.rowptr, rowptr));
         EFT_TRY(dput(ctx, &C.A.col, col));
         EFT_TRY(dput(ctx, &C.A.diag, diag));
+        {
+            std::vector<int32_t> so;
+            std::vector<uint16_t> sm;
+            if (eft_stencil_form(C.N, rowptr, col, bs == 4 ? 16 : 8, so, sm)) {
+                EFT_TRY(dput(ctx, &C.A.stn_mask, sm));
+                EFT_TRY(dput(ctx, &C.A.stn_off, so));
+            }
+        }
         EFT_TRY(dmal(ctx, &C.A.val, C.A.nnzb * bs * bs));
         EFT_TRY(dmal(ctx, &C.va, C.N * d));
         EFT_TRY(dmal(ctx, &C.acc, C.N * d));
@@ -1073,6 +1134,8 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
     F0.A.rowptr = ctx->J.rowptr;
     F0.A.col = ctx->J.col;
     F0.A.diag = ctx->J.diag;
+    F0.A.stn_mask = ctx->J.stn_mask;
+    F0.A.stn_off = ctx->J.stn_off;
     F0.A.fp32 = true;   // storage (FP32 or BF16) is chosen and allocated in eft_mg_setup
     // coarsest level: dense inverse over its free dofs
     const MGLevel &Lc = ctx->mg.back();
@@ -1107,7 +1170,7 @@ void eft_mg_free(eft_ctx *ctx)
         MGLevel &L = ctx->mg[l];
         if (l > 0) {
             fr(L.conn); fr(L.epos); fr(L.inj); fr(L.xyz); fr(L.va); fr(L.acc); fr(L.rho); fr(L.mu); fr(L.as);
-            fr(L.Ba); fr(L.smask); fr(L.vp); fr(L.R); fr(L.dir_node); fr(L.dir_mask); fr(L.A.rowptr); fr(L.A.col); fr(L.A.diag);
+            fr(L.Ba); fr(L.smask); fr(L.vp); fr(L.R); fr(L.dir_node); fr(L.dir_mask); fr(L.A.rowptr); fr(L.A.col); fr(L.A.diag); fr(L.A.stn_mask); fr(L.A.stn_off);
             fr(L.A.val); fr(L.b); fr(L.iptr); fr(L.ient); fr(L.islot);
         }
         fr(L.fmask); fr(L.Dinv); fr(L.Dinv32); fr(L.x); fr(L.x2); fr(L.r); fr(L.A.val32); fr(L.A.val16);
@@ -1321,12 +1384,18 @@ void launch_sweep(eft_ctx *ctx, const eft_matrix &A, const TV *val, const TD *Di
 {
     const dim3 t(256);
     if constexpr (sizeof(TV) < 8) {   // narrow values: one block per lane
-        if (A.bs == 3)
-            hipLaunchKernelGGL((k_sweep_blk<3, TV, TD>), dim3(eft_grid(A.n, 4 * BlockSeg<3>::RPW)), t, 0, ctx->stream,
-                               A.n, A.rowptr, A.col, val, Dinv, omega, b, x, xo, flag);
-        else
-            hipLaunchKernelGGL((k_sweep_blk<4, TV, TD>), dim3(eft_grid(A.n, 4 * BlockSeg<4>::RPW)), t, 0, ctx->stream,
-                               A.n, A.rowptr, A.col, val, Dinv, omega, b, x, xo, flag);
+#define EFT_SWEEP_BLK(B_, S_)                                                                                       \
+    hipLaunchKernelGGL((k_sweep_blk<B_, TV, TD, S_>), dim3(eft_grid(A.n, 4 * BlockSeg<B_>::RPW)), t, 0, ctx->stream, \
+                       A.n, A.rowptr, A.col, A.stn_mask, A.stn_off, val, Dinv, omega, b, x, xo, flag)
+        const bool stn = A.stn_mask != nullptr;
+        if (A.bs == 3) {
+            if (stn) EFT_SWEEP_BLK(3, true);
+            else EFT_SWEEP_BLK(3, false);
+        } else {
+            if (stn) EFT_SWEEP_BLK(4, true);
+            else EFT_SWEEP_BLK(4, false);
+        }
+#undef EFT_SWEEP_BLK
         return;
     }
     const dim3 g(eft_grid(A.n, 4 * SWEEP_R));
@@ -1344,12 +1413,18 @@ void launch_resid(eft_ctx *ctx, const eft_matrix &A, const TV *val, const double
 {
     const dim3 t(256);
     if constexpr (sizeof(TV) < 8) {   // narrow values: one block per lane
-        if (A.bs == 3)
-            hipLaunchKernelGGL((k_resid_blk<3, TV>), dim3(eft_grid(A.n, 4 * BlockSeg<3>::RPW)), t, 0, ctx->stream, A.n,
-                               A.rowptr, A.col, val, b, x, r, flag);
-        else
-            hipLaunchKernelGGL((k_resid_blk<4, TV>), dim3(eft_grid(A.n, 4 * BlockSeg<4>::RPW)), t, 0, ctx->stream, A.n,
-                               A.rowptr, A.col, val, b, x, r, flag);
+#define EFT_RESID_BLK(B_, S_)                                                                                      \
+    hipLaunchKernelGGL((k_resid_blk<B_, TV, S_>), dim3(eft_grid(A.n, 4 * BlockSeg<B_>::RPW)), t, 0, ctx->stream, A.n, \
+                       A.rowptr, A.col, A.stn_mask, A.stn_off, val, b, x, r, flag)
+        const bool stn = A.stn_mask != nullptr;
+        if (A.bs == 3) {
+            if (stn) EFT_RESID_BLK(3, true);
+            else EFT_RESID_BLK(3, false);
+        } else {
+            if (stn) EFT_RESID_BLK(4, true);
+            else EFT_RESID_BLK(4, false);
+        }
+#undef EFT_RESID_BLK
         return;
     }
     const dim3 g(eft_grid(A.n, 4 * RESID_R));
@@ -1391,13 +1466,15 @@ void sweep0(eft_ctx *ctx, const MGLevel &L, const double *b, double *x, const in
                            ctx->par.mg_omega, b, x, flag);
 }
 
-// Algorithmic bytes of one sweep: values, column indices and row pointers
-// once, the block inverses, b and x read and x_out written once.
+// Algorithmic bytes of one sweep: values, column indices (or, in stencil
+// form, the row masks) and row pointers once, the block inverses, b and x
+// read and x_out written once.
 double sweep_bytes(const eft_matrix &A)
 {
     const double vb = A.bf16 ? 2.0 : A.fp32 ? 4.0 : 8.0, db = (A.bf16 || A.fp32) ? 4.0 : 8.0;
     const double b2 = (double)A.bs * A.bs;
-    return (double)A.nnzb * (b2 * vb + 4.0) + (double)(A.n + 1) * 4.0 + (double)A.n * (b2 * db + 3.0 * A.bs * 8.0);
+    const double cols = A.stn_mask ? (double)A.n * 2.0 : (double)A.nnzb * 4.0;
+    return (double)A.nnzb * b2 * vb + cols + (double)(A.n + 1) * 4.0 + (double)A.n * (b2 * db + 3.0 * A.bs * 8.0);
 }
 
 // fine-level sweeps carry the kernel-timing hook

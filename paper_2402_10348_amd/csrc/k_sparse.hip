@@ -40,6 +40,34 @@ __global__ __launch_bounds__(256) void k_spmv_rows(int64_t n, const int32_t *__r
         if (lane < BS && row[q] < n) y[row[q] * BS + lane] = acc[q];
 }
 
+// The same product for a pattern in stencil form (FP64 values, bs 3 or 4):
+// the row masks are wave-uniform (scalar loads) and no column index is read.
+template <int BS, bool GATED>
+__global__ __launch_bounds__(256) void k_spmv_stn(int64_t n, const int32_t *__restrict__ rowptr,
+                                                  const uint16_t *__restrict__ smask, const int32_t *__restrict__ soff,
+                                                  const double *__restrict__ val, const double *__restrict__ x,
+                                                  double *__restrict__ y, const int32_t *active)
+{
+    constexpr int MAXS = BS == 4 ? 16 : 8;
+    const int64_t w = (int64_t)blockIdx.x * 4 + wave_id();
+    int64_t row[SPMV_R];
+#pragma unroll
+    for (int q = 0; q < SPMV_R; ++q) row[q] = w * SPMV_R + q;
+    int k0[SPMV_R], k1[SPMV_R];
+    row_extents<SPMV_R>(row, n, rowptr, k0, k1);
+    uint32_t m[SPMV_R];
+#pragma unroll
+    for (int q = 0; q < SPMV_R; ++q) m[q] = row[q] < n ? smask[row[q]] : 0u;
+    if ((GATED && *active == 0) || row[0] >= n) return;
+    const int lane = threadIdx.x & 63, j = lane / BS;
+    const int oj = j < MAXS ? soff[j] : 0;
+    double acc[SPMV_R];
+    bsr_rows_stencil_dot<BS, double, SPMV_R, MAXS>(k0, m, row, oj, val, x, lane, acc);
+#pragma unroll
+    for (int q = 0; q < SPMV_R; ++q)
+        if (lane < BS && row[q] < n) y[row[q] * BS + lane] = acc[q];
+}
+
 // The same product with one block per lane (narrow values, bs 3 or 4).
 template <int BS, typename TV, bool GATED>
 __global__ __launch_bounds__(256) void k_spmv_blk(int64_t n, const int32_t *__restrict__ rowptr,
@@ -153,10 +181,23 @@ eft_status eft_spmv_flag(eft_ctx *ctx, const eft_matrix *A, const double *x, dou
 {
     if (A->n == 0) return EFT_OK;
     if (A->bcmp) return eft_bcmp_spmv(ctx, A, x, y, active);
-    if (A->fp32)
+    if (A->stn_mask && !A->fp32 && (A->bs == 3 || A->bs == 4)) {
+#define EFT_SPMV_STN(B_, G_)                                                                                       \
+    hipLaunchKernelGGL((k_spmv_stn<B_, G_>), dim3(eft_grid(A->n, 4 * SPMV_R)), dim3(256), 0, ctx->stream, A->n, \
+                       A->rowptr, A->stn_mask, A->stn_off, A->val, x, y, active)
+        if (A->bs == 3) {
+            if (active) EFT_SPMV_STN(3, true);
+            else EFT_SPMV_STN(3, false);
+        } else {
+            if (active) EFT_SPMV_STN(4, true);
+            else EFT_SPMV_STN(4, false);
+        }
+#undef EFT_SPMV_STN
+    } else if (A->fp32) {
         spmv_launch<float>(ctx, A->n, A->bs, A->rowptr, A->col, A->val32, x, y, active);
-    else
+    } else {
         spmv_launch<double>(ctx, A->n, A->bs, A->rowptr, A->col, A->val, x, y, active);
+    }
     EFT_HIP(hipGetLastError());
     return EFT_OK;
 }

@@ -78,6 +78,68 @@ def test_assembly_matches_oracle(torch_cuda, name, seed):
     ctx.close()
 
 
+def permuted(prob, seed):
+    """The same problem with its nodes renumbered at random: the rows of an
+    assembly workgroup then touch far more nodes than the staged node records
+    hold, so the assembly reads the node arrays directly (and the mesh is no
+    longer a structured box for the multigrid)."""
+    import copy
+    rng = np.random.Generator(np.random.PCG64(seed))
+    N = prob.n_nodes
+    perm = rng.permutation(N)            # new node k is old node perm[k]
+    inv = np.empty(N, np.int64)
+    inv[perm] = np.arange(N)
+    q = copy.deepcopy(prob)
+    q.xyz = np.ascontiguousarray(prob.xyz[perm])
+    q.conn = inv[prob.conn].astype(prob.conn.dtype)
+    q.dir_node = inv[prob.dir_node].astype(prob.dir_node.dtype)
+    q.vp, q.vdot = prob.vp[perm], prob.vdot[perm]
+    q.phi, q.phidot = prob.phi[:, perm], prob.phidot[:, perm]
+    q.B, q.Bdot = prob.B[:, perm], prob.Bdot[:, perm]
+    return q
+
+
+def most_nodes_per_workgroup(prob):
+    """Largest number of distinct nodes touched by the elements of one
+    assembly workgroup's rows (rows per workgroup as the library picks them)."""
+    conn = prob.conn.astype(np.int64)
+    N, nn = prob.n_nodes, conn.shape[1]
+    maxinc = int(np.bincount(conn.ravel(), minlength=N).max())
+    rows = [set() for _ in range(N)]
+    for e in conn:
+        for a in e:
+            rows[a].update(e.tolist())
+    maxc = max(len(r) for r in rows)
+    rpb = max(1, min(512 // maxinc, 65536 // (maxc * ((nn * nn) | 1) * 8 + (nn | 1) * 8)))
+    worst = 0
+    for r0 in range(0, N, rpb):
+        worst = max(worst, len(set().union(*rows[r0:r0 + rpb])))
+    return worst
+
+
+@pytest.mark.parametrize("name", ["disk2d_32", "sphere3d_10", "falling3d_8"])
+def test_assembly_unstaged_path_matches_oracle(torch_cuda, name):
+    """Node records not staged and no stencil form of the pattern (renumbered
+    mesh): the assembly and the SpMV, which then reads the column indices,
+    still equal the oracle's."""
+    prob = {"disk2d_32": lambda: W.cavity_disk_2d(n=32), "sphere3d_10": lambda: W.cavity_sphere_3d(n=10),
+            "falling3d_8": lambda: W.falling_sphere_3d(n=8)}[name]()
+    q = permuted(prob, seed=4)
+    assert most_nodes_per_workgroup(q) > 256 and most_nodes_per_workgroup(prob) <= 256
+    say(f"[assembly unstaged] case={name} N={q.n_nodes} E={q.n_elems}")
+    lvl, it = W.perturbed_state(q, seed=5)
+    c = O.Case(q)
+    R0, J0 = c.ns_assemble(lvl, it)
+    ctx = ctx_for(q, precond=0)
+    R = ctx.assemble(ctx.device_state(lvl), ctx.device_state(it))
+    _, _, val = ctx.matrix()
+    assert relmax(to_np(R), R0) < 1e-12
+    assert relmax(to_np(val), J0) < 1e-12
+    x = np.random.Generator(np.random.PCG64(6)).standard_normal(R0.shape)
+    assert relmax(to_np(ctx.spmv(ctx.tensor(x))), c.spmv(J0, x)) < 1e-12
+    ctx.close()
+
+
 @pytest.mark.parametrize("name", ["disk2d_32", "sphere3d_6"])
 def test_spmv_and_fgmres_match_oracle(torch_cuda, name):
     torch = torch_cuda
@@ -166,8 +228,10 @@ def test_kernel_timer_counts(torch_cuda):
     n, nnzb, bs = ctx.matrix_shape()
     fine_sweeps = (prob.params.mg_nu - 1) + prob.params.mg_nu_post   # the first pre-sweep is a separate kernel
     vbytes = 2 if prob.params.mg_bf16 else 4   # the finest level's matrix copy (block inverses FP32)
-    sweep_b = nnzb * (bs * bs * vbytes + 4) + (n + 1) * 4 + n * (bs * bs * 4 + 3 * bs * 8)
-    spmv_b = nnzb * (bs * bs * 8 + 4) + (n + 1) * 4 + 2 * n * bs * 8
+    # the Kuhn box's pattern has a stencil form (15 column offsets): both
+    # kernels read a 2-byte mask per row instead of the column indices
+    sweep_b = nnzb * bs * bs * vbytes + 2 * n + (n + 1) * 4 + n * (bs * bs * 4 + 3 * bs * 8)
+    spmv_b = nnzb * bs * bs * 8 + 2 * n + (n + 1) * 4 + 2 * n * bs * 8
     ctx.time_kernel(1, 2, 3)
     x, info = ctx.fgmres(-R)
     assert info["converged"] == 1
