@@ -113,9 +113,9 @@ def make_workload(name):
     return p, f"3D lid-driven cavity with one elastic sphere, {n}^3 x 6 P1 tets"
 
 
-KERNEL_NAME = {1: "k_sweep_blk<4, eft_bf16, float, true> (finest-level multigrid smoother sweep, BF16 copy of the "
-                  "4x4-block momentum Jacobian with its pattern in stencil form (row masks, no column indices), "
-                  "FP32 block inverses, FP64 vectors and arithmetic)",
+KERNEL_NAME = {1: "k_sweep_blk<4, eft_bf16, eft_bf16, true, float, float> (finest-level multigrid smoother sweep: "
+                  "BF16 copy of the 4x4-block momentum Jacobian with its pattern in stencil form (row masks, no "
+                  "column indices), BF16 block inverses, FP32 iterate, FP64 right-hand side and arithmetic)",
                2: "k_spmv_stn<4, true> (FP64 SpMV of the 4x4-block momentum Jacobian in FGMRES, pattern in "
                   "stencil form)",
                3: "k_ns_rows<3, double, true> (momentum/mass residual and Jacobian assembly with the node records "

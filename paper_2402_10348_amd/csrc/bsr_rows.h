@@ -129,11 +129,26 @@ template <int BS, bool NT> struct RowLoad<BS, eft_bf16, NT> {
 };
 
 // bs entries of x under block column c (cached loads: x is re-read by every
-// row that couples to c).
-template <int BS> __device__ __forceinline__ void x_get(const double *__restrict__ x, int64_t c, double (&v)[BS])
+// row that couples to c); x in FP64 or FP32.
+template <int BS, typename TX = double>
+__device__ __forceinline__ void x_get(const TX *__restrict__ x, int64_t c, double (&v)[BS])
 {
-    const double *p = x + c * BS;
-    if constexpr (BS % 2 == 0) {
+    const TX *p = x + c * BS;
+    if constexpr (sizeof(TX) == 4) {
+        if constexpr (BS % 4 == 0) {
+#pragma unroll
+            for (int q = 0; q < BS / 4; ++q) {
+                const eft_f4 t = reinterpret_cast<const eft_f4 *>(p)[q];
+                v[4 * q] = t.x;
+                v[4 * q + 1] = t.y;
+                v[4 * q + 2] = t.z;
+                v[4 * q + 3] = t.w;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < BS; ++q) v[q] = p[q];
+        }
+    } else if constexpr (BS % 2 == 0) {
 #pragma unroll
         for (int q = 0; q < BS / 2; ++q) {
             const eft_d2 t = reinterpret_cast<const eft_d2 *>(p)[q];
@@ -245,9 +260,9 @@ __device__ __forceinline__ void seg_extents(int64_t row0, int64_t n, const int32
         }
 }
 
-template <int BS, typename TV, int SEG>
+template <int BS, typename TV, int SEG, typename TX>
 __device__ __forceinline__ void bsr_block_dot(int k0, int k1, const int32_t *__restrict__ col,
-                                              const TV *__restrict__ val, const double *__restrict__ x, int j,
+                                              const TV *__restrict__ val, const TX *__restrict__ x, int j,
                                               double (&acc)[BS])
 {
 #pragma unroll
@@ -295,9 +310,9 @@ template <int BS, typename TV> __device__ __forceinline__ void block_get(const T
 // the popcount of the mask below j past the row's first block, its column is
 // row + soff_j.  No column index is read, and the x gather does not wait for
 // one.
-template <int BS, typename TV, int SEG>
+template <int BS, typename TV, int SEG, typename TX>
 __device__ __forceinline__ void bsr_stencil_dot(int k0, uint32_t m, int64_t row, int soff_j,
-                                                const TV *__restrict__ val, const double *__restrict__ x, int j,
+                                                const TV *__restrict__ val, const TX *__restrict__ x, int j,
                                                 double (&acc)[BS])
 {
 #pragma unroll

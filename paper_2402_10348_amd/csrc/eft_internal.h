@@ -131,6 +131,8 @@ struct MGLevel {
     double *Dinv = nullptr;          // [N][bs*bs] (levels with FP64 values)
     float *Dinv32 = nullptr;         // [N][bs*bs] (the level with FP32 values)
     double *x = nullptr, *x2 = nullptr, *b = nullptr, *r = nullptr;  // [N*bs]
+    float *xf = nullptr, *xf2 = nullptr, *rf = nullptr;   // [N*bs] the finest level's FP32 iterate and residual
+    uint16_t *Dinv16 = nullptr;      // [N][bs*bs] the finest level's block inverses in BF16 (its FP32-vector cycle)
     int32_t *crow = nullptr;         // rows ordered by parity colour (i%2, j%2, k%2)
     int64_t coff[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // colour c: crow[coff[c] .. coff[c+1])
     int64_t cnnz[8] = {0, 0, 0, 0, 0, 0, 0, 0};     // blocks of the rows of each colour

@@ -503,7 +503,7 @@ static double spmv_bytes(const eft_matrix *A)
 {
     // (in stencil form the row masks replace the column indices)
     const double vb = A->fp32 ? 4.0 : 8.0, b2 = (double)A->bs * A->bs;
-    const bool stn = A->stn_mask && !A->fp32 && (A->bs == 3 || A->bs == 4);
+    const bool stn = A->stn_mask && (A->bs == 3 || A->bs == 4);
     const double cols = stn ? (double)A->n * 2.0 : (double)A->nnzb * 4.0;
     return (double)A->nnzb * b2 * vb + cols + (double)(A->n + 1) * 4.0 + 2.0 * A->n * A->bs * 8.0;
 }

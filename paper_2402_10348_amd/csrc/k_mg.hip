@@ -154,13 +154,13 @@ __global__ __launch_bounds__(256) void k_sweep_rows(int64_t n, const int32_t *__
 
 // The same sweep with one block per lane (narrow values, bs 3 or 4): lane j
 // < bs of a row's segment finishes component j of the row.
-template <int BS, typename TV, typename TD, bool STN>
+template <int BS, typename TV, typename TD, bool STN, typename TX, typename TO>
 __device__ __forceinline__ void sweep_blk_rows(int64_t row0, int64_t n, const int32_t *__restrict__ rowptr,
                                                const int32_t *__restrict__ col, const uint16_t *__restrict__ smask,
                                                const int32_t *__restrict__ soff, const TV *__restrict__ val,
                                                const TD *__restrict__ Dinv, double omega,
-                                               const double *__restrict__ b, const double *__restrict__ x,
-                                               double *__restrict__ xo)
+                                               const double *__restrict__ b, const TX *__restrict__ x,
+                                               TO *__restrict__ xo)
 {
     constexpr int SEG = BlockSeg<BS>::SEG, RPW = BlockSeg<BS>::RPW;
     const int lane = threadIdx.x & 63, q = lane / SEG, j = lane - q * SEG;
@@ -176,7 +176,7 @@ __device__ __forceinline__ void sweep_blk_rows(int64_t row0, int64_t n, const in
     double bb[BS], d[BS];
     x_get<BS>(b, rr, bb);
     RowLoad<BS, TD, false>::get(Dinv + (rr * BS + jj) * BS, d);
-    const double xr = x[rr * BS + jj];
+    const double xr = (double)x[rr * BS + jj];
     int k0, k1;
     seg_extents<RPW>(row0, n, rowptr, q, k0, k1);
     double ax[BS];
@@ -185,24 +185,25 @@ __device__ __forceinline__ void sweep_blk_rows(int64_t row0, int64_t n, const in
     double u = 0.0;
 #pragma unroll
     for (int c = 0; c < BS; ++c) u += d[c] * (bb[c] - ax[c]);
-    if (j < BS && row < n) xo[row * BS + j] = xr + omega * u;
+    if (j < BS && row < n) xo[row * BS + j] = (TO)(xr + omega * u);
 }
 
 // The same sweep with one block per lane (narrow values, bs 3 or 4): lane j
-// < bs of a row's segment finishes component j of the row.
+// < bs of a row's segment finishes component j of the row; x and x_out in
+// FP64 or FP32 (b FP64, arithmetic FP64).
 // With the pattern in stencil form (smask, soff: see bsr_stencil_dot) no
 // column index is read.
-template <int BS, typename TV, typename TD, bool STN>
+template <int BS, typename TV, typename TD, bool STN, typename TX, typename TO>
 __global__ __launch_bounds__(256) void k_sweep_blk(int64_t n, const int32_t *__restrict__ rowptr,
                                                    const int32_t *__restrict__ col, const uint16_t *__restrict__ smask,
                                                    const int32_t *__restrict__ soff, const TV *__restrict__ val,
                                                    const TD *__restrict__ Dinv, double omega,
-                                                   const double *__restrict__ b, const double *__restrict__ x,
-                                                   double *__restrict__ xo, const int32_t *flag)
+                                                   const double *__restrict__ b, const TX *__restrict__ x,
+                                                   TO *__restrict__ xo, const int32_t *flag)
 {
     const int64_t row0 = (xcd_block() * 4 + wave_id()) * BlockSeg<BS>::RPW;
     if (*flag == 0 || row0 >= n) return;
-    sweep_blk_rows<BS, TV, TD, STN>(row0, n, rowptr, col, smask, soff, val, Dinv, omega, b, x, xo);
+    sweep_blk_rows<BS, TV, TD, STN, TX, TO>(row0, n, rowptr, col, smask, soff, val, Dinv, omega, b, x, xo);
 }
 
 // Block Gauss-Seidel on the rows of one colour, in place:
@@ -267,9 +268,9 @@ __global__ __launch_bounds__(256) void k_sweep0(int64_t nd, int bs, const TD *__
 
 // The same with one node per lane (bs 3 or 4): its block inverse and b read
 // as whole rows, several loads in flight per lane.
-template <int BS, typename TD>
+template <int BS, typename TD, typename TO>
 __global__ __launch_bounds__(256) void k_sweep0_nodes(int64_t n, const TD *__restrict__ Dinv, double omega,
-                                                      const double *__restrict__ b, double *__restrict__ x,
+                                                      const double *__restrict__ b, TO *__restrict__ x,
                                                       const int32_t *flag)
 {
     if (*flag == 0) return;
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(256) void k_sweep0_nodes(int64_t n, const TD *__res
         double s = 0.0;
 #pragma unroll
         for (int c = 0; c < BS; ++c) s += d[i][c] * bb[c];
-        x[r * BS + i] = omega * s;
+        x[r * BS + i] = (TO)(omega * s);
     }
 }
 
@@ -316,12 +317,12 @@ __global__ __launch_bounds__(256) void k_resid_rows(int64_t n, const int32_t *__
 }
 
 // r = b - A x with one block per lane (narrow values, bs 3 or 4)
-template <int BS, typename TV, bool STN>
+template <int BS, typename TV, bool STN, typename TX, typename TR>
 __device__ __forceinline__ void resid_blk_rows(int64_t row0, int64_t n, const int32_t *__restrict__ rowptr,
                                                const int32_t *__restrict__ col, const uint16_t *__restrict__ smask,
                                                const int32_t *__restrict__ soff, const TV *__restrict__ val,
-                                               const double *__restrict__ b, const double *__restrict__ x,
-                                               double *__restrict__ r)
+                                               const double *__restrict__ b, const TX *__restrict__ x,
+                                               TR *__restrict__ r)
 {
     constexpr int SEG = BlockSeg<BS>::SEG, RPW = BlockSeg<BS>::RPW;
     const int lane = threadIdx.x & 63, q = lane / SEG, j = lane - q * SEG;
@@ -345,16 +346,16 @@ __device__ __forceinline__ void resid_blk_rows(int64_t row0, int64_t n, const in
         if (j == c && row < n) r[row * BS + c] = br - ax[c];
 }
 
-template <int BS, typename TV, bool STN>
+template <int BS, typename TV, bool STN, typename TX, typename TR>
 __global__ __launch_bounds__(256) void k_resid_blk(int64_t n, const int32_t *__restrict__ rowptr,
                                                    const int32_t *__restrict__ col, const uint16_t *__restrict__ smask,
                                                    const int32_t *__restrict__ soff, const TV *__restrict__ val,
-                                                   const double *__restrict__ b, const double *__restrict__ x,
-                                                   double *__restrict__ r, const int32_t *flag)
+                                                   const double *__restrict__ b, const TX *__restrict__ x,
+                                                   TR *__restrict__ r, const int32_t *flag)
 {
     const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave_id()) * BlockSeg<BS>::RPW;
     if (*flag == 0 || row0 >= n) return;
-    resid_blk_rows<BS, TV, STN>(row0, n, rowptr, col, smask, soff, val, b, x, r);
+    resid_blk_rows<BS, TV, STN, TX, TR>(row0, n, rowptr, col, smask, soff, val, b, x, r);
 }
 
 // --------------------------------------------------------- transfers ------
@@ -364,9 +365,9 @@ __global__ __launch_bounds__(256) void k_resid_blk(int64_t n, const int32_t *__r
 // load is issued unconditionally (index 0 and weight 0 outside the mesh, the
 // Dirichlet mask applied by a select), so the loads of all stencil points are
 // in flight together instead of one round trip per masked branch.
-template <int D>
+template <int D, typename TR>
 __device__ __forceinline__ void restrict_node(const Dims &cd, const Dims &fd, const uint8_t *__restrict__ cmask,
-                                              const uint8_t *__restrict__ fmask, const double *__restrict__ r,
+                                              const uint8_t *__restrict__ fmask, const TR *__restrict__ r,
                                               double *__restrict__ bc, int I)
 {
     constexpr int BS = D + 1;
@@ -386,7 +387,7 @@ __device__ __forceinline__ void restrict_node(const Dims &cd, const Dims &fd, co
         const int m = fmask[f];
 #pragma unroll
         for (int c = 0; c < BS; ++c) {
-            const double v = r[f * BS + c];
+            const double v = (double)r[f * BS + c];
             acc[c] += ((m >> c) & 1) ? w * v : 0.0;
         }
     }
@@ -395,24 +396,24 @@ __device__ __forceinline__ void restrict_node(const Dims &cd, const Dims &fd, co
     for (int c = 0; c < BS; ++c) bc[(int64_t)I * BS + c] = ((mc >> c) & 1) ? acc[c] : 0.0;
 }
 
-template <int D>
+template <int D, typename TR>
 __global__ __launch_bounds__(256) void k_restrict(Dims cd, Dims fd, const uint8_t *__restrict__ cmask,
-                                                  const uint8_t *__restrict__ fmask, const double *__restrict__ r,
+                                                  const uint8_t *__restrict__ fmask, const TR *__restrict__ r,
                                                   double *__restrict__ bc, const int32_t *flag)
 {
     if (*flag == 0) return;
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= (cd.n[0] + 1) * (cd.n[1] + 1) * (cd.n[2] + 1)) return;
-    restrict_node<D>(cd, fd, cmask, fmask, r, bc, I);
+    restrict_node<D, TR>(cd, fd, cmask, fmask, r, bc, I);
 }
 
 // Restriction fused with the coarse level's first sweep from zero: node I
 // gets b[I] and x[I] = omega D_I^-1 b[I] (the arithmetic of k_sweep0 per
 // component), one launch instead of two.
-template <int D, typename TD>
+template <int D, typename TD, typename TR>
 __global__ __launch_bounds__(256) void k_restrict_sweep0(Dims cd, Dims fd, const uint8_t *__restrict__ cmask,
                                                          const uint8_t *__restrict__ fmask,
-                                                         const double *__restrict__ r, double *__restrict__ bc,
+                                                         const TR *__restrict__ r, double *__restrict__ bc,
                                                          const TD *__restrict__ Dinv, double omega,
                                                          double *__restrict__ xc, const int32_t *flag)
 {
@@ -420,7 +421,7 @@ __global__ __launch_bounds__(256) void k_restrict_sweep0(Dims cd, Dims fd, const
     if (*flag == 0) return;
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= (cd.n[0] + 1) * (cd.n[1] + 1) * (cd.n[2] + 1)) return;
-    restrict_node<D>(cd, fd, cmask, fmask, r, bc, I);
+    restrict_node<D, TR>(cd, fd, cmask, fmask, r, bc, I);
     double bb[BS];
 #pragma unroll
     for (int c = 0; c < BS; ++c) bb[c] = bc[(int64_t)I * BS + c];
@@ -435,10 +436,10 @@ __global__ __launch_bounds__(256) void k_restrict_sweep0(Dims cd, Dims fd, const
 }
 
 // x[i] += sum over parents I of i of w(i, I) xc[I] (free dofs only)
-template <int D>
+template <int D, typename TX>
 __device__ __forceinline__ void prolong_node(const Dims &cd, const Dims &fd, const uint8_t *__restrict__ cmask,
                                              const uint8_t *__restrict__ fmask, const double *__restrict__ xc,
-                                             double *__restrict__ x, int f)
+                                             TX *__restrict__ x, int f)
 {
     constexpr int BS = D + 1;
     const int nx = fd.n[0] + 1, ny = fd.n[1] + 1;
@@ -451,21 +452,21 @@ __device__ __forceinline__ void prolong_node(const Dims &cd, const Dims &fd, con
     const double w = mid ? 0.5 : 1.0;   // a node of the coarse mesh takes its own value once
 #pragma unroll
     for (int c = 0; c < BS; ++c) {
-        const double a0 = xc[I0 * BS + c], a1 = xc[I1 * BS + c], xv = x[(int64_t)f * BS + c];
+        const double a0 = xc[I0 * BS + c], a1 = xc[I1 * BS + c], xv = (double)x[(int64_t)f * BS + c];
         const double v = ((m0 >> c) & 1 ? a0 : 0.0) + (mid && ((m1 >> c) & 1) ? a1 : 0.0);
-        x[(int64_t)f * BS + c] = ((m >> c) & 1) ? xv + w * v : xv;
+        x[(int64_t)f * BS + c] = (TX)(((m >> c) & 1) ? xv + w * v : xv);
     }
 }
 
-template <int D>
+template <int D, typename TX>
 __global__ __launch_bounds__(256) void k_prolong(Dims cd, Dims fd, const uint8_t *__restrict__ cmask,
                                                  const uint8_t *__restrict__ fmask, const double *__restrict__ xc,
-                                                 double *__restrict__ x, const int32_t *flag)
+                                                 TX *__restrict__ x, const int32_t *flag)
 {
     if (*flag == 0) return;
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= (fd.n[0] + 1) * (fd.n[1] + 1) * (fd.n[2] + 1)) return;
-    prolong_node<D>(cd, fd, cmask, fmask, xc, x, f);
+    prolong_node<D, TX>(cd, fd, cmask, fmask, xc, x, f);
 }
 
 // ------------------------------------------------ Galerkin coarsening ----
@@ -1136,6 +1137,12 @@ eft_status eft_mg_create(eft_ctx *ctx, const int32_t *grid, const std::vector<ui
     F0.A.diag = ctx->J.diag;
     F0.A.stn_mask = ctx->J.stn_mask;
     F0.A.stn_off = ctx->J.stn_off;
+    if (bs == 3 || bs == 4) {   // FP32 iterate and residual of the finest level's cycle
+        EFT_TRY(dmal(ctx, &F0.xf, F0.A.n * bs));
+        EFT_TRY(dmal(ctx, &F0.xf2, F0.A.n * bs));
+        EFT_TRY(dmal(ctx, &F0.rf, F0.A.n * bs));
+        EFT_TRY(dmal(ctx, &F0.Dinv16, F0.A.n * bs * bs));
+    }
     F0.A.fp32 = true;   // storage (FP32 or BF16) is chosen and allocated in eft_mg_setup
     // coarsest level: dense inverse over its free dofs
     const MGLevel &Lc = ctx->mg.back();
@@ -1174,6 +1181,7 @@ void eft_mg_free(eft_ctx *ctx)
             fr(L.A.val); fr(L.b); fr(L.iptr); fr(L.ient); fr(L.islot);
         }
         fr(L.fmask); fr(L.Dinv); fr(L.Dinv32); fr(L.x); fr(L.x2); fr(L.r); fr(L.A.val32); fr(L.A.val16);
+        fr(L.xf); fr(L.xf2); fr(L.rf); fr(L.Dinv16);
         fr(L.crow);
     }
     ctx->mg.clear();
@@ -1215,6 +1223,18 @@ eft_status eft_mg_reserve(eft_ctx *ctx)
 
 // Refresh the hierarchy for the current Jacobian: inject node fields,
 // rediscretize the coarse Jacobians, block inverses and the coarsest inverse.
+// BF16 copy of the finest level's FP32 block inverses, read by the sweeps of
+// the FP32-vector cycle
+static eft_status dinv_bf16(eft_ctx *ctx, MGLevel &F0)
+{
+    if (!F0.Dinv16) return EFT_OK;
+    const int64_t n = F0.A.n * ctx->bs * ctx->bs;
+    hipLaunchKernelGGL(k_to_bf16<float>, dim3((int)std::min<int64_t>(8192, (n + 255) / 256)), dim3(256), 0,
+                       ctx->stream, F0.Dinv32, F0.Dinv16, n);
+    EFT_HIP(hipGetLastError());
+    return EFT_OK;
+}
+
 eft_status eft_mg_setup(eft_ctx *ctx, const double *vp, bool coarse)
 {
     const int bs = ctx->bs;
@@ -1237,6 +1257,7 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp, bool coarse)
         ctx->mg_f32_fresh = false;
         EFT_HIP(hipGetLastError());
         EFT_TRY(eft_bj_setup32(ctx, &ctx->J, F0.Dinv32));
+        EFT_TRY(dinv_bf16(ctx, F0));
     } else {
         if (!F0.A.val32) {
             ctx->err = "multigrid FP32 copy not reserved";
@@ -1253,6 +1274,7 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp, bool coarse)
         }
         ctx->mg_f32_fresh = false;
         EFT_TRY(eft_bj_setup32(ctx, &F0.A, F0.Dinv32));
+        EFT_TRY(dinv_bf16(ctx, F0));
     }
     if (!coarse) {   // the coarse levels of the previous refresh are kept
         ctx->mg_valid = true;
@@ -1378,15 +1400,15 @@ eft_status eft_mg_setup(eft_ctx *ctx, const double *vp, bool coarse)
 
 namespace {
 
-template <typename TV, typename TD>
+template <typename TV, typename TD, typename TX = double, typename TO = double>
 void launch_sweep(eft_ctx *ctx, const eft_matrix &A, const TV *val, const TD *Dinv, double omega, const double *b,
-                  const double *x, double *xo, const int32_t *flag)
+                  const TX *x, TO *xo, const int32_t *flag)
 {
     const dim3 t(256);
     if constexpr (sizeof(TV) < 8) {   // narrow values: one block per lane
 #define EFT_SWEEP_BLK(B_, S_)                                                                                       \
-    hipLaunchKernelGGL((k_sweep_blk<B_, TV, TD, S_>), dim3(eft_grid(A.n, 4 * BlockSeg<B_>::RPW)), t, 0, ctx->stream, \
-                       A.n, A.rowptr, A.col, A.stn_mask, A.stn_off, val, Dinv, omega, b, x, xo, flag)
+    hipLaunchKernelGGL((k_sweep_blk<B_, TV, TD, S_, TX, TO>), dim3(eft_grid(A.n, 4 * BlockSeg<B_>::RPW)), t, 0,     \
+                       ctx->stream, A.n, A.rowptr, A.col, A.stn_mask, A.stn_off, val, Dinv, omega, b, x, xo, flag)
         const bool stn = A.stn_mask != nullptr;
         if (A.bs == 3) {
             if (stn) EFT_SWEEP_BLK(3, true);
@@ -1397,25 +1419,27 @@ void launch_sweep(eft_ctx *ctx, const eft_matrix &A, const TV *val, const TD *Di
         }
 #undef EFT_SWEEP_BLK
         return;
+    } else {
+        static_assert(sizeof(TX) == 8 && sizeof(TO) == 8, "FP64 values: FP64 vectors");
+        const dim3 g(eft_grid(A.n, 4 * SWEEP_R));
+        if (A.bs == 3)
+            hipLaunchKernelGGL((k_sweep_rows<3, TV, TD>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, Dinv, omega,
+                               b, x, xo, flag);
+        else
+            hipLaunchKernelGGL((k_sweep_rows<4, TV, TD>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, Dinv, omega,
+                               b, x, xo, flag);
     }
-    const dim3 g(eft_grid(A.n, 4 * SWEEP_R));
-    if (A.bs == 3)
-        hipLaunchKernelGGL((k_sweep_rows<3, TV, TD>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, Dinv, omega, b,
-                           x, xo, flag);
-    else
-        hipLaunchKernelGGL((k_sweep_rows<4, TV, TD>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, Dinv, omega, b,
-                           x, xo, flag);
 }
 
-template <typename TV>
-void launch_resid(eft_ctx *ctx, const eft_matrix &A, const TV *val, const double *b, const double *x, double *r,
+template <typename TV, typename TX = double, typename TR = double>
+void launch_resid(eft_ctx *ctx, const eft_matrix &A, const TV *val, const double *b, const TX *x, TR *r,
                   const int32_t *flag)
 {
     const dim3 t(256);
     if constexpr (sizeof(TV) < 8) {   // narrow values: one block per lane
 #define EFT_RESID_BLK(B_, S_)                                                                                      \
-    hipLaunchKernelGGL((k_resid_blk<B_, TV, S_>), dim3(eft_grid(A.n, 4 * BlockSeg<B_>::RPW)), t, 0, ctx->stream, A.n, \
-                       A.rowptr, A.col, A.stn_mask, A.stn_off, val, b, x, r, flag)
+    hipLaunchKernelGGL((k_resid_blk<B_, TV, S_, TX, TR>), dim3(eft_grid(A.n, 4 * BlockSeg<B_>::RPW)), t, 0,        \
+                       ctx->stream, A.n, A.rowptr, A.col, A.stn_mask, A.stn_off, val, b, x, r, flag)
         const bool stn = A.stn_mask != nullptr;
         if (A.bs == 3) {
             if (stn) EFT_RESID_BLK(3, true);
@@ -1426,12 +1450,14 @@ void launch_resid(eft_ctx *ctx, const eft_matrix &A, const TV *val, const double
         }
 #undef EFT_RESID_BLK
         return;
+    } else {
+        static_assert(sizeof(TX) == 8 && sizeof(TR) == 8, "FP64 values: FP64 vectors");
+        const dim3 g(eft_grid(A.n, 4 * RESID_R));
+        if (A.bs == 3)
+            hipLaunchKernelGGL((k_resid_rows<3, TV>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, b, x, r, flag);
+        else
+            hipLaunchKernelGGL((k_resid_rows<4, TV>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, b, x, r, flag);
     }
-    const dim3 g(eft_grid(A.n, 4 * RESID_R));
-    if (A.bs == 3)
-        hipLaunchKernelGGL((k_resid_rows<3, TV>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, b, x, r, flag);
-    else
-        hipLaunchKernelGGL((k_resid_rows<4, TV>), g, t, 0, ctx->stream, A.n, A.rowptr, A.col, val, b, x, r, flag);
 }
 
 // (the momentum/mass system has bs = d + 1, 3 or 4)
@@ -1453,11 +1479,11 @@ void sweep0(eft_ctx *ctx, const MGLevel &L, const double *b, double *x, const in
     const int64_t nd = L.N * ctx->bs;
     const dim3 gn(eft_grid(L.N, 256));
     if ((L.A.fp32 || L.A.bf16) && ctx->bs == 4)
-        hipLaunchKernelGGL((k_sweep0_nodes<4, float>), gn, dim3(256), 0, ctx->stream, L.N, L.Dinv32, ctx->par.mg_omega,
-                           b, x, flag);
+        hipLaunchKernelGGL((k_sweep0_nodes<4, float, double>), gn, dim3(256), 0, ctx->stream, L.N, L.Dinv32,
+                           ctx->par.mg_omega, b, x, flag);
     else if ((L.A.fp32 || L.A.bf16) && ctx->bs == 3)
-        hipLaunchKernelGGL((k_sweep0_nodes<3, float>), gn, dim3(256), 0, ctx->stream, L.N, L.Dinv32, ctx->par.mg_omega,
-                           b, x, flag);
+        hipLaunchKernelGGL((k_sweep0_nodes<3, float, double>), gn, dim3(256), 0, ctx->stream, L.N, L.Dinv32,
+                           ctx->par.mg_omega, b, x, flag);
     else if (L.A.fp32 || L.A.bf16)
         hipLaunchKernelGGL(k_sweep0<float>, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, nd, ctx->bs, L.Dinv32,
                            ctx->par.mg_omega, b, x, flag);
@@ -1469,12 +1495,13 @@ void sweep0(eft_ctx *ctx, const MGLevel &L, const double *b, double *x, const in
 // Algorithmic bytes of one sweep: values, column indices (or, in stencil
 // form, the row masks) and row pointers once, the block inverses, b and x
 // read and x_out written once.
-double sweep_bytes(const eft_matrix &A)
+double sweep_bytes(const eft_matrix &A, double xb = 8.0, double xob = 8.0, double dbo = 0.0)
 {
-    const double vb = A.bf16 ? 2.0 : A.fp32 ? 4.0 : 8.0, db = (A.bf16 || A.fp32) ? 4.0 : 8.0;
+    const double vb = A.bf16 ? 2.0 : A.fp32 ? 4.0 : 8.0, db = dbo > 0.0 ? dbo : (A.bf16 || A.fp32) ? 4.0 : 8.0;
     const double b2 = (double)A.bs * A.bs;
     const double cols = A.stn_mask ? (double)A.n * 2.0 : (double)A.nnzb * 4.0;
-    return (double)A.nnzb * b2 * vb + cols + (double)(A.n + 1) * 4.0 + (double)A.n * (b2 * db + 3.0 * A.bs * 8.0);
+    return (double)A.nnzb * b2 * vb + cols + (double)(A.n + 1) * 4.0 +
+           (double)A.n * (b2 * db + A.bs * (8.0 + xb + xob));
 }
 
 // fine-level sweeps carry the kernel-timing hook
@@ -1523,6 +1550,22 @@ void gs_sweep(eft_ctx *ctx, int l, const MGLevel &L, const double *b, double *x,
             launch_gs<double, double>(ctx, L, c, L.A.val, L.Dinv, b, x, flag);
         eft_kt_end(ctx, slot, bytes, EFT_KT_SMOOTH);
     }
+}
+
+// The finest level with FP32 iterate and residual vectors (b and the
+// output FP64, arithmetic FP64): narrow matrix values, Jacobi smoothing.
+template <typename TX, typename TO>
+void sweep_f(eft_ctx *ctx, const MGLevel &L, const double *b, const TX *x, TO *xo, const int32_t *flag)
+{
+    const double om = ctx->par.mg_omega;
+    const int64_t slot = eft_kt_begin(ctx, EFT_KT_SMOOTH);
+    const eft_bf16 *D16 = reinterpret_cast<const eft_bf16 *>(L.Dinv16);
+    if (L.A.bf16)
+        launch_sweep<eft_bf16, eft_bf16, TX, TO>(ctx, L.A, reinterpret_cast<const eft_bf16 *>(L.A.val16), D16, om, b,
+                                                 x, xo, flag);
+    else
+        launch_sweep<float, eft_bf16, TX, TO>(ctx, L.A, L.A.val32, D16, om, b, x, xo, flag);
+    eft_kt_end(ctx, slot, sweep_bytes(L.A, sizeof(TX), sizeof(TO), 2.0), EFT_KT_SMOOTH);
 }
 
 void resid(eft_ctx *ctx, const eft_matrix &A, const double *b, const double *x, double *r, const int32_t *flag)
@@ -1575,30 +1618,30 @@ double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag, double
     const double om = ctx->par.mg_omega;
     if (!fuse) {
         if (ctx->dim == 2)
-            hipLaunchKernelGGL(k_restrict<2>, gr, tr, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.r, C.b, flag);
+            hipLaunchKernelGGL((k_restrict<2, double>), gr, tr, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.r, C.b, flag);
         else
-            hipLaunchKernelGGL(k_restrict<3>, gr, tr, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.r, C.b, flag);
+            hipLaunchKernelGGL((k_restrict<3, double>), gr, tr, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.r, C.b, flag);
     } else if (ctx->dim == 2) {
         if (c32)
-            hipLaunchKernelGGL((k_restrict_sweep0<2, float>), gr, tr, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.r,
+            hipLaunchKernelGGL((k_restrict_sweep0<2, float, double>), gr, tr, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.r,
                                C.b, C.Dinv32, om, C.x, flag);
         else
-            hipLaunchKernelGGL((k_restrict_sweep0<2, double>), gr, tr, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.r,
+            hipLaunchKernelGGL((k_restrict_sweep0<2, double, double>), gr, tr, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.r,
                                C.b, C.Dinv, om, C.x, flag);
     } else {
         if (c32)
-            hipLaunchKernelGGL((k_restrict_sweep0<3, float>), gr, tr, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.r,
+            hipLaunchKernelGGL((k_restrict_sweep0<3, float, double>), gr, tr, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.r,
                                C.b, C.Dinv32, om, C.x, flag);
         else
-            hipLaunchKernelGGL((k_restrict_sweep0<3, double>), gr, tr, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.r,
+            hipLaunchKernelGGL((k_restrict_sweep0<3, double, double>), gr, tr, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.r,
                                C.b, C.Dinv, om, C.x, flag);
     }
     double *xc = vcycle(ctx, l + 1, C.b, flag, nullptr, fuse);
     if (ctx->dim == 2)
-        hipLaunchKernelGGL(k_prolong<2>, dim3(eft_grid(L.N, 256)), dim3(256), 0, ctx->stream, cd, fd, C.fmask, L.fmask,
+        hipLaunchKernelGGL((k_prolong<2, double>), dim3(eft_grid(L.N, 256)), dim3(256), 0, ctx->stream, cd, fd, C.fmask, L.fmask,
                            xc, cur, flag);
     else
-        hipLaunchKernelGGL(k_prolong<3>, dim3(eft_grid(L.N, 256)), dim3(256), 0, ctx->stream, cd, fd, C.fmask, L.fmask,
+        hipLaunchKernelGGL((k_prolong<3, double>), dim3(eft_grid(L.N, 256)), dim3(256), 0, ctx->stream, cd, fd, C.fmask, L.fmask,
                            xc, cur, flag);
     const int npost = ctx->par.mg_nu_post;
     if (gs) {
@@ -1617,9 +1660,85 @@ double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag, double
 }  // namespace
 
 // z = M^-1 b0 with one V-cycle
+// The finest level's part of the cycle with FP32 iterate and residual
+// vectors and BF16 block inverses (the same steps as vcycle at level 0 with
+// Jacobi smoothing; the last post-sweep writes the FP64 output z).  Halves
+// the vector and inverse bytes of the level's sweeps and their x gathers.
+static bool vcycle0_f32_ok(const eft_ctx *ctx)
+{
+    if (ctx->mg.size() < 2) return false;
+    const MGLevel &L = ctx->mg[0];
+    return L.xf && L.Dinv16 && (L.A.bf16 || L.A.fp32) && (ctx->bs == 3 || ctx->bs == 4) &&
+           ctx->par.mg_smoother == 0;
+}
+
+static void vcycle0_f32(eft_ctx *ctx, const double *b, double *z, const int32_t *flag)
+{
+    MGLevel &L = ctx->mg[0];
+    MGLevel &C = ctx->mg[1];
+    const double om = ctx->par.mg_omega;
+    float *cur = L.xf, *oth = L.xf2;
+    const dim3 gn(eft_grid(L.N, 256)), t(256);
+    const eft_bf16 *D16 = reinterpret_cast<const eft_bf16 *>(L.Dinv16);
+    if (ctx->bs == 4)
+        hipLaunchKernelGGL((k_sweep0_nodes<4, eft_bf16, float>), gn, t, 0, ctx->stream, L.N, D16, om, b, cur, flag);
+    else
+        hipLaunchKernelGGL((k_sweep0_nodes<3, eft_bf16, float>), gn, t, 0, ctx->stream, L.N, D16, om, b, cur, flag);
+    for (int s = 1; s < ctx->par.mg_nu; ++s) {
+        sweep_f<float, float>(ctx, L, b, cur, oth, flag);
+        std::swap(cur, oth);
+    }
+    if (L.A.bf16)
+        launch_resid<eft_bf16, float, float>(ctx, L.A, reinterpret_cast<const eft_bf16 *>(L.A.val16), b, cur, L.rf,
+                                             flag);
+    else
+        launch_resid<float, float, float>(ctx, L.A, L.A.val32, b, cur, L.rf, flag);
+    const Dims fd = dims_of(L), cd = dims_of(C);
+    const bool c_last = ctx->mg.size() == 2;
+    const bool fuse = !(c_last && ctx->mg_inv);
+    const dim3 gr(eft_grid(C.N, 256));
+    const bool c32 = C.A.fp32 || C.A.bf16;
+    if (!fuse) {
+        if (ctx->dim == 2)
+            hipLaunchKernelGGL((k_restrict<2, float>), gr, t, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.rf, C.b, flag);
+        else
+            hipLaunchKernelGGL((k_restrict<3, float>), gr, t, 0, ctx->stream, cd, fd, C.fmask, L.fmask, L.rf, C.b, flag);
+    } else if (ctx->dim == 2) {
+        if (c32)
+            hipLaunchKernelGGL((k_restrict_sweep0<2, float, float>), gr, t, 0, ctx->stream, cd, fd, C.fmask, L.fmask,
+                               L.rf, C.b, C.Dinv32, om, C.x, flag);
+        else
+            hipLaunchKernelGGL((k_restrict_sweep0<2, double, float>), gr, t, 0, ctx->stream, cd, fd, C.fmask, L.fmask,
+                               L.rf, C.b, C.Dinv, om, C.x, flag);
+    } else {
+        if (c32)
+            hipLaunchKernelGGL((k_restrict_sweep0<3, float, float>), gr, t, 0, ctx->stream, cd, fd, C.fmask, L.fmask,
+                               L.rf, C.b, C.Dinv32, om, C.x, flag);
+        else
+            hipLaunchKernelGGL((k_restrict_sweep0<3, double, float>), gr, t, 0, ctx->stream, cd, fd, C.fmask, L.fmask,
+                               L.rf, C.b, C.Dinv, om, C.x, flag);
+    }
+    const double *xc = vcycle(ctx, 1, C.b, flag, nullptr, fuse);
+    if (ctx->dim == 2)
+        hipLaunchKernelGGL((k_prolong<2, float>), gn, t, 0, ctx->stream, cd, fd, C.fmask, L.fmask, xc, cur, flag);
+    else
+        hipLaunchKernelGGL((k_prolong<3, float>), gn, t, 0, ctx->stream, cd, fd, C.fmask, L.fmask, xc, cur, flag);
+    const int npost = ctx->par.mg_nu_post;   // >= 1
+    for (int s = 0; s + 1 < npost; ++s) {
+        sweep_f<float, float>(ctx, L, b, cur, oth, flag);
+        std::swap(cur, oth);
+    }
+    sweep_f<float, double>(ctx, L, b, cur, z, flag);
+}
+
 eft_status eft_mg_vcycle(eft_ctx *ctx, const double *b0, double *z, const int32_t *flag)
 {
     MGLevel &L0 = ctx->mg[0];
+    if (vcycle0_f32_ok(ctx)) {
+        vcycle0_f32(ctx, b0, z, flag);
+        EFT_HIP(hipGetLastError());
+        return EFT_OK;
+    }
     double *x = vcycle(ctx, 0, b0, flag, z);
     EFT_HIP(hipGetLastError());
     if (x != z)

@@ -68,10 +68,12 @@ __global__ __launch_bounds__(256) void k_spmv_stn(int64_t n, const int32_t *__re
         if (lane < BS && row[q] < n) y[row[q] * BS + lane] = acc[q];
 }
 
-// The same product with one block per lane (narrow values, bs 3 or 4).
-template <int BS, typename TV, bool GATED>
+// The same product with one block per lane (narrow values, bs 3 or 4),
+// with the pattern's column indices or (STN) its stencil form.
+template <int BS, typename TV, bool GATED, bool STN>
 __global__ __launch_bounds__(256) void k_spmv_blk(int64_t n, const int32_t *__restrict__ rowptr,
-                                                  const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                  const int32_t *__restrict__ col, const uint16_t *__restrict__ smask,
+                                                  const int32_t *__restrict__ soff, const TV *__restrict__ val,
                                                   const double *__restrict__ x, double *__restrict__ y,
                                                   const int32_t *active)
 {
@@ -79,11 +81,18 @@ __global__ __launch_bounds__(256) void k_spmv_blk(int64_t n, const int32_t *__re
     const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave_id()) * RPW;
     if ((GATED && *active == 0) || row0 >= n) return;
     const int lane = threadIdx.x & 63, q = lane / SEG, j = lane - q * SEG;
+    const int64_t row = row0 + q;
+    uint32_t m = 0;
+    int oj = 0;
+    if constexpr (STN) {
+        m = row < n ? smask[row] : 0u;
+        oj = soff[j];
+    }
     int k0, k1;
     seg_extents<RPW>(row0, n, rowptr, q, k0, k1);
     double acc[BS];
-    bsr_block_dot<BS, TV, SEG>(k0, k1, col, val, x, j, acc);
-    const int64_t row = row0 + q;
+    if constexpr (STN) bsr_stencil_dot<BS, TV, SEG>(k0, m, row < n ? row : row0, oj, val, x, j, acc);
+    else bsr_block_dot<BS, TV, SEG>(k0, k1, col, val, x, j, acc);
 #pragma unroll
     for (int c = 0; c < BS; ++c)
         if (j == c && row < n) y[row * BS + c] = acc[c];
@@ -141,16 +150,21 @@ __global__ __launch_bounds__(256) void k_spmv1(int64_t n, const int32_t *__restr
 
 template <int BS, typename TV>
 static void spmv_rows_launch(eft_ctx *ctx, int64_t n, const int32_t *rowptr, const int32_t *col, const TV *val,
-                             const double *x, double *y, const int32_t *active)
+                             const double *x, double *y, const int32_t *active, const uint16_t *smask = nullptr,
+                             const int32_t *soff = nullptr)
 {
     if constexpr (sizeof(TV) < 8 && BS <= 4) {
         const dim3 g(eft_grid(n, 4 * BlockSeg<BS>::RPW));
-        if (active)
-            hipLaunchKernelGGL((k_spmv_blk<BS, TV, true>), g, dim3(256), 0, ctx->stream, n, rowptr, col, val, x, y,
-                               active);
-        else
-            hipLaunchKernelGGL((k_spmv_blk<BS, TV, false>), g, dim3(256), 0, ctx->stream, n, rowptr, col, val, x, y,
-                               active);
+#define EFT_SPMV_BLK(G_, S_) \
+    hipLaunchKernelGGL((k_spmv_blk<BS, TV, G_, S_>), g, dim3(256), 0, ctx->stream, n, rowptr, col, smask, soff, val, x, y, active)
+        if (smask) {
+            if (active) EFT_SPMV_BLK(true, true);
+            else EFT_SPMV_BLK(false, true);
+        } else {
+            if (active) EFT_SPMV_BLK(true, false);
+            else EFT_SPMV_BLK(false, false);
+        }
+#undef EFT_SPMV_BLK
     } else if (active)
         hipLaunchKernelGGL((k_spmv_rows<BS, TV, true>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream, n,
                            rowptr, col, val, x, y, active);
@@ -193,6 +207,11 @@ eft_status eft_spmv_flag(eft_ctx *ctx, const eft_matrix *A, const double *x, dou
             else EFT_SPMV_STN(4, false);
         }
 #undef EFT_SPMV_STN
+    } else if (A->fp32 && A->stn_mask && (A->bs == 3 || A->bs == 4)) {
+        if (A->bs == 3)
+            spmv_rows_launch<3, float>(ctx, A->n, A->rowptr, A->col, A->val32, x, y, active, A->stn_mask, A->stn_off);
+        else
+            spmv_rows_launch<4, float>(ctx, A->n, A->rowptr, A->col, A->val32, x, y, active, A->stn_mask, A->stn_off);
     } else if (A->fp32) {
         spmv_launch<float>(ctx, A->n, A->bs, A->rowptr, A->col, A->val32, x, y, active);
     } else {

@@ -227,15 +227,18 @@ def test_kernel_timer_counts(torch_cuda):
     R = ctx.assemble(ctx.device_state(lvl), ctx.device_state(it))
     n, nnzb, bs = ctx.matrix_shape()
     fine_sweeps = (prob.params.mg_nu - 1) + prob.params.mg_nu_post   # the first pre-sweep is a separate kernel
-    vbytes = 2 if prob.params.mg_bf16 else 4   # the finest level's matrix copy (block inverses FP32)
+    vbytes = 2 if prob.params.mg_bf16 else 4   # the finest level's matrix copy
     # the Kuhn box's pattern has a stencil form (15 column offsets): both
-    # kernels read a 2-byte mask per row instead of the column indices
-    sweep_b = nnzb * bs * bs * vbytes + 2 * n + (n + 1) * 4 + n * (bs * bs * 4 + 3 * bs * 8)
+    # kernels read a 2-byte mask per row instead of the column indices.  The
+    # finest level's sweeps read BF16 block inverses, b in FP64 and x in FP32
+    # and write FP32, the last one of a cycle FP64 (the preconditioned vector)
+    sweep_base = nnzb * bs * bs * vbytes + 2 * n + (n + 1) * 4 + n * bs * bs * 2
+    per_cycle = (fine_sweeps - 1) * (sweep_base + n * bs * (8 + 4 + 4)) + sweep_base + n * bs * (8 + 4 + 8)
     spmv_b = nnzb * bs * bs * 8 + 2 * n + (n + 1) * 4 + 2 * n * bs * 8
     ctx.time_kernel(1, 2, 3)
     x, info = ctx.fgmres(-R)
     assert info["converged"] == 1
-    for role, per_it, nbytes in ((1, fine_sweeps, sweep_b), (2, 1, spmv_b)):
+    for role, per_it, nbytes in ((1, fine_sweeps, per_cycle / fine_sweeps), (2, 1, spmv_b)):
         kt = ctx.kernel_time(role)
         say(f"  role={role} iters={info['iters']} {kt}")
         assert kt["active"] == info["iters"] * per_it
