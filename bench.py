@@ -223,7 +223,7 @@ def run_steps(args, prob, torch, label, time_kernels=True, **over):
                              transport_s_default=round(tune["band_default_seconds"], 5),
                              transport_s_tuned=round(tune["band_best_seconds"], 5),
                              knobs={k: tune[k] for k in ("mg_nu", "mg_nu_post", "mg_smoother", "mg_omega",
-                                                         "band_sweeps", "band_omega")})
+                                                         "mg_galerkin", "band_sweeps", "band_omega")})
     return out, kts, ctx, st, el
 
 
@@ -650,10 +650,16 @@ def main():
                                                                          ("mg_sweep", 1))}
     mixed = None
     if args.mixed:
-        m, _, c2, s2, _ = run_steps(args, prob, torch, args.workload + " mixed", time_kernels=False, precision=1)
+        # the same steps with FP32 Jacobian values and the FP64 run's tuned
+        # knobs (so that only the precision differs between the two lines)
+        am = argparse.Namespace(**vars(args))
+        am.tune = False
+        knobs = dict((head.get("tuning") or {}).get("knobs") or {})
+        m, _, c2, s2, _ = run_steps(am, prob, torch, args.workload + " mixed", time_kernels=False, precision=1,
+                                    **knobs)
         c2.close()
         del s2
-        mixed = dict(m, dtype="f64 residual/Krylov, f32 Jacobian")
+        mixed = dict(m, dtype="f64 residual/Krylov, f32 Jacobian", knobs=knobs or None)
     secondary = {}
     if args.secondary:
         for name in ("cavity128", "cavity64"):
