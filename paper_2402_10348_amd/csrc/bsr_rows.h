@@ -33,20 +33,6 @@ typedef float eft_f4 __attribute__((ext_vector_type(4)));
 // loads indexed by it, such as the row pointers, go through the scalar unit).
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
-// Workgroup b of a launch runs on XCD b % 8 (round-robin dispatch over the 8
-// XCDs), and every XCD has its own L2.  The row kernels take their rows from
-// xcd_block(): XCD x gets the x-th contiguous share of the row blocks, so
-// rows that gather the same x entries (neighbours in the node order) share
-// one L2 instead of every XCD pulling the whole vector.  A bijection of
-// [0, gridDim.x).
-__device__ __forceinline__ int64_t xcd_block()
-{
-    constexpr int64_t XCD = 8;
-    const int64_t b = blockIdx.x, g = gridDim.x;
-    const int64_t x = b % XCD, local = b / XCD, q = g / XCD, rem = g % XCD;
-    return x * q + (x < rem ? x : rem) + local;
-}
-
 // One load, plain or non-temporal (streamed: not kept in the caches).
 template <bool NT, typename T> __device__ __forceinline__ T ld_hint(const T *p)
 {

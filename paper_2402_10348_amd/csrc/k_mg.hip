@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) void k_sweep_blk(int64_t n, const int32_t *__r
                                                    const double *__restrict__ b, const TX *__restrict__ x,
                                                    TO *__restrict__ xo, const int32_t *flag)
 {
-    const int64_t row0 = (xcd_block() * 4 + wave_id()) * BlockSeg<BS>::RPW;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave_id()) * BlockSeg<BS>::RPW;
     if (*flag == 0 || row0 >= n) return;
     sweep_blk_rows<BS, TV, TD, STN, TX, TO>(row0, n, rowptr, col, smask, soff, val, Dinv, omega, b, x, xo);
 }
