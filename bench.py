@@ -224,7 +224,8 @@ def run_steps(args, prob, torch, label, time_kernels=True, **over):
                              transport_s_default=round(tune["band_default_seconds"], 5),
                              transport_s_tuned=round(tune["band_best_seconds"], 5),
                              knobs={k: tune[k] for k in ("mg_nu", "mg_nu_post", "mg_smoother", "mg_omega",
-                                                         "mg_galerkin", "band_sweeps", "band_omega")})
+                                                         "mg_galerkin", "mg_cnu", "mg_cnu_post", "band_sweeps",
+                                                         "band_omega")})
     return out, kts, ctx, st, el
 
 

@@ -174,6 +174,11 @@ typedef struct {
                                     iteration of a step only, the finest level
                                     (copy of J, block inverses) at every one.  The
                                     preconditioner changes, the answer does not. */
+    int32_t mg_cnu;              /* multigrid coarse levels (all but the finest and
+                                    the coarsest with its dense solve): smoothing
+                                    sweeps before the coarse correction, the first
+                                    from x = 0 (1..32; 0: mg_nu)                   */
+    int32_t mg_cnu_post;         /* ... and after it (1..32; 0: mg_nu_post)         */
 } eft_params;
 
 /* State at time level n (Sec. 2.1.2): values and rates.  DEVICE arrays. */
@@ -411,7 +416,8 @@ eft_status eft_init_phase(eft_ctx *ctx, const eft_surface *surf, double eps, con
 eft_status eft_step(eft_ctx *ctx, eft_state *st, double dt, eft_step_info *info);
 
 /* ---- Autotuner of the solver's run-time knobs (not part of the method).
- * The multigrid sweep counts before/after the coarse correction, its damping,
+ * The multigrid sweep counts before/after the coarse correction (on the
+ * finest level and on the coarse levels), its damping,
  * smoother kind (Jacobi or multicolour Gauss-Seidel) and coarse operators
  * (rediscretized or Galerkin), and the sweeps and
  * damping of the band systems' preconditioner are chosen by measurement: on
@@ -425,7 +431,7 @@ eft_status eft_step(eft_ctx *ctx, eft_state *st, double dt, eft_step_info *info)
  * "key|knobs" lines, the key made of the GPU architecture and the problem's
  * sizes, materials and solver settings; a key found there is applied without
  * a search, a new result is appended.  budget: most momentum candidates
- * timed (<= 0: 64).  info (HOST, may be NULL) receives the outcome. */
+ * timed (<= 0: 80).  info (HOST, may be NULL) receives the outcome. */
 typedef struct {
     int32_t evaluated;           /* solves and transport passes timed              */
     int32_t from_cache;          /* 1: knobs read from the cache file              */
@@ -439,6 +445,7 @@ typedef struct {
     int32_t mg_galerkin;
     int32_t band_sweeps;
     double band_omega;
+    int32_t mg_cnu, mg_cnu_post;
 } eft_tune_info;
 eft_status eft_tune(eft_ctx *ctx, const eft_state *st, const char *cache_path, int32_t budget, eft_tune_info *info);
 

@@ -127,9 +127,10 @@ eft_status check_params(eft_ctx *ctx, const eft_params *p)
         (p->mg_smoother != 0 && p->mg_smoother != 1) || p->band_sweeps < 1 || p->band_sweeps > 8 ||
         !(p->band_omega > 0.0 && p->band_omega <= 1.5) || (p->mg_galerkin != 0 && p->mg_galerkin != 1) ||
         (p->graphs != 0 && p->graphs != 1) || (p->nn_base != 0 && p->nn_base != 1) ||
-        (p->mg_lag != 0 && p->mg_lag != 1)) {
+        (p->mg_lag != 0 && p->mg_lag != 1) || p->mg_cnu < 0 || p->mg_cnu > 32 || p->mg_cnu_post < 0 ||
+        p->mg_cnu_post > 32) {
         ctx->err = "invalid eft_params (dt, eta, lin_rtol > 0; 1 <= restart <= 512; band_cell >= 1; "
-                   "0 <= rho_inf <= 1; precision 0/1; precond 0/1/2/3; 1 <= mg_nu <= 16; 0 < mg_omega <= 1.5; mg_bf16 0/1; 1 <= mg_nu_post <= 16; mg_smoother 0/1; 1 <= band_sweeps <= 8; 0 < band_omega <= 1.5; mg_galerkin 0/1; graphs 0/1; nn_base 0/1; mg_lag 0/1)";
+                   "0 <= rho_inf <= 1; precision 0/1; precond 0/1/2/3; 1 <= mg_nu <= 16; 0 < mg_omega <= 1.5; mg_bf16 0/1; 1 <= mg_nu_post <= 16; mg_smoother 0/1; 1 <= band_sweeps <= 8; 0 < band_omega <= 1.5; mg_galerkin 0/1; graphs 0/1; nn_base 0/1; mg_lag 0/1; 0 <= mg_cnu, mg_cnu_post <= 32)";
         return EFT_EINVAL;
     }
     return EFT_OK;

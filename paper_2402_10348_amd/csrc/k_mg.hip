@@ -1596,7 +1596,9 @@ double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag, double
     const bool gs = ctx->par.mg_smoother == 1 && L.ncolor > 0;
     if (gs && out) cur = out;   // in-place smoothing works on the output directly
     if (!x0_done) sweep0(ctx, L, b, cur, flag);
-    const int nu = last ? 40 : ctx->par.mg_nu;
+    // (levels below the finest may smooth more: the coarse correction sets
+    // the convergence of the cycle)
+    const int nu = last ? 40 : l == 0 || ctx->par.mg_cnu == 0 ? ctx->par.mg_nu : ctx->par.mg_cnu;
     for (int s = 1; s < nu; ++s) {
         if (gs) {
             gs_sweep(ctx, l, L, b, cur, flag, false);
@@ -1643,7 +1645,7 @@ double *vcycle(eft_ctx *ctx, int l, const double *b, const int32_t *flag, double
     else
         hipLaunchKernelGGL((k_prolong<3, double>), dim3(eft_grid(L.N, 256)), dim3(256), 0, ctx->stream, cd, fd, C.fmask, L.fmask,
                            xc, cur, flag);
-    const int npost = ctx->par.mg_nu_post;
+    const int npost = l == 0 || ctx->par.mg_cnu_post == 0 ? ctx->par.mg_nu_post : ctx->par.mg_cnu_post;
     if (gs) {
         for (int s = 0; s < npost; ++s) gs_sweep(ctx, l, L, b, cur, flag, true);
         return cur;

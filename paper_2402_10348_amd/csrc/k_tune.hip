@@ -48,11 +48,13 @@ struct Knobs {
     int mg_galerkin;
     int band_sweeps;
     double band_omega;
+    int mg_cnu, mg_cnu_post;
 };
 
 Knobs knobs_of(const eft_params &p)
 {
-    return Knobs{p.mg_nu, p.mg_nu_post, p.mg_smoother, p.mg_omega, p.mg_galerkin, p.band_sweeps, p.band_omega};
+    return Knobs{p.mg_nu,       p.mg_nu_post, p.mg_smoother, p.mg_omega,   p.mg_galerkin,
+                 p.band_sweeps, p.band_omega, p.mg_cnu,      p.mg_cnu_post};
 }
 
 void set_knobs(eft_params &p, const Knobs &k)
@@ -64,23 +66,28 @@ void set_knobs(eft_params &p, const Knobs &k)
     p.mg_galerkin = k.mg_galerkin;
     p.band_sweeps = k.band_sweeps;
     p.band_omega = k.band_omega;
+    p.mg_cnu = k.mg_cnu;
+    p.mg_cnu_post = k.mg_cnu_post;
 }
 
 std::string knobs_text(const Knobs &k)
 {
     char b[256];
     std::snprintf(b, sizeof b,
-                  "mg_nu=%d mg_nu_post=%d mg_smoother=%d mg_omega=%.6g mg_galerkin=%d band_sweeps=%d band_omega=%.6g",
-                  k.mg_nu, k.mg_nu_post, k.mg_smoother, k.mg_omega, k.mg_galerkin, k.band_sweeps, k.band_omega);
+                  "mg_nu=%d mg_nu_post=%d mg_smoother=%d mg_omega=%.6g mg_galerkin=%d band_sweeps=%d band_omega=%.6g "
+                  "mg_cnu=%d mg_cnu_post=%d",
+                  k.mg_nu, k.mg_nu_post, k.mg_smoother, k.mg_omega, k.mg_galerkin, k.band_sweeps, k.band_omega,
+                  k.mg_cnu, k.mg_cnu_post);
     return b;
 }
 
 bool parse_knobs(const std::string &s, Knobs &k)
 {
     return std::sscanf(s.c_str(),
-                       "mg_nu=%d mg_nu_post=%d mg_smoother=%d mg_omega=%lf mg_galerkin=%d band_sweeps=%d band_omega=%lf",
+                       "mg_nu=%d mg_nu_post=%d mg_smoother=%d mg_omega=%lf mg_galerkin=%d band_sweeps=%d band_omega=%lf "
+                       "mg_cnu=%d mg_cnu_post=%d",
                        &k.mg_nu, &k.mg_nu_post, &k.mg_smoother, &k.mg_omega, &k.mg_galerkin, &k.band_sweeps,
-                       &k.band_omega) == 7;
+                       &k.band_omega, &k.mg_cnu, &k.mg_cnu_post) == 9;
 }
 
 std::string tune_key(eft_ctx *ctx)
@@ -144,12 +151,14 @@ extern "C" eft_status eft_tune(eft_ctx *ctx, const eft_state *st, const char *ca
         inf.mg_smoother = best.mg_smoother;
         inf.mg_omega = best.mg_omega;
         inf.mg_galerkin = best.mg_galerkin;
+        inf.mg_cnu = best.mg_cnu;
+        inf.mg_cnu_post = best.mg_cnu_post;
         inf.band_sweeps = best.band_sweeps;
         inf.band_omega = best.band_omega;
         if (info) *info = inf;
         return EFT_OK;
     }
-    const int cap = budget > 0 ? budget : 64;
+    const int cap = budget > 0 ? budget : 80;
     const int64_t N = ctx->N;
     const int bs = ctx->bs, nv = ctx->nv;
     const int64_t nvp = N * bs, nphi = N * ctx->n_ind, nB = N * nv * ctx->n_s;
@@ -276,10 +285,31 @@ extern "C" eft_status eft_tune(eft_ctx *ctx, const eft_state *st, const char *ca
             k.mg_nu_post = std::max(1, best.mg_nu_post / 2);
             TUNE_TRY(consider(k));
         }
+        // the coarse levels' own sweep counts at the best finest counts (the
+        // coarse correction sets the convergence of the cycle, and a coarse
+        // sweep costs an eighth of a finest one), then the finest counts
+        // again at the best coarse ones
+        for (int c : {4, 6, 8, 12}) {
+            Knobs k = best;
+            k.mg_cnu = c;
+            k.mg_cnu_post = c;
+            TUNE_TRY(consider(k));
+        }
+        if (best.mg_cnu > 0) {
+            const int fine[][2] = {{1, 1}, {1, 2}, {2, 2}, {2, 3}, {2, 4}, {3, 3}};
+            for (const auto &f : fine) {
+                Knobs k = best;
+                if (k.mg_nu == f[0] && k.mg_nu_post == f[1]) continue;
+                k.mg_nu = f[0];
+                k.mg_nu_post = f[1];
+                TUNE_TRY(consider(k));
+            }
+        }
         // confirm against the entry settings with a second timing of both
         if (!(best.mg_nu == entry.mg_nu && best.mg_nu_post == entry.mg_nu_post &&
               best.mg_smoother == entry.mg_smoother && best.mg_omega == entry.mg_omega &&
-              best.mg_galerkin == entry.mg_galerkin)) {
+              best.mg_galerkin == entry.mg_galerkin && best.mg_cnu == entry.mg_cnu &&
+              best.mg_cnu_post == entry.mg_cnu_post)) {
             int i1 = 0, i2 = 0;
             const double t1 = time_solve(best, maxit0, &i1);
             double t2 = t_entry;
@@ -296,6 +326,8 @@ extern "C" eft_status eft_tune(eft_ctx *ctx, const eft_state *st, const char *ca
                 best.mg_smoother = entry.mg_smoother;
                 best.mg_omega = entry.mg_omega;
                 best.mg_galerkin = entry.mg_galerkin;
+                best.mg_cnu = entry.mg_cnu;
+                best.mg_cnu_post = entry.mg_cnu_post;
                 t_best = t2;
                 it_best = i2;
             } else {
@@ -368,6 +400,8 @@ extern "C" eft_status eft_tune(eft_ctx *ctx, const eft_state *st, const char *ca
     inf.mg_smoother = best.mg_smoother;
     inf.mg_omega = best.mg_omega;
     inf.mg_galerkin = best.mg_galerkin;
+    inf.mg_cnu = best.mg_cnu;
+    inf.mg_cnu_post = best.mg_cnu_post;
     inf.band_sweeps = best.band_sweeps;
     inf.band_omega = best.band_omega;
     if (info) *info = inf;

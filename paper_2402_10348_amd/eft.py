@@ -49,7 +49,8 @@ class Params(C.Structure):
                 ("band_sweeps", C.c_int32), ("band_omega", C.c_double), ("mg_galerkin", C.c_int32),
                 ("nn_maxit", C.c_int32),
                 ("band_reserve", C.c_double), ("graphs", C.c_int32),
-                ("nn_base", C.c_int32), ("mg_lag", C.c_int32)]
+                ("nn_base", C.c_int32), ("mg_lag", C.c_int32), ("mg_cnu", C.c_int32),
+                ("mg_cnu_post", C.c_int32)]
 
 
 class State(C.Structure):
@@ -85,7 +86,7 @@ class TuneInfo(C.Structure):
                 ("band_default_seconds", C.c_double), ("band_best_seconds", C.c_double),
                 ("mg_nu", C.c_int32), ("mg_nu_post", C.c_int32), ("mg_smoother", C.c_int32),
                 ("mg_omega", C.c_double), ("mg_galerkin", C.c_int32), ("band_sweeps", C.c_int32),
-                ("band_omega", C.c_double)]
+                ("band_omega", C.c_double), ("mg_cnu", C.c_int32), ("mg_cnu_post", C.c_int32)]
 
 
 class KernelTime(C.Structure):
@@ -137,7 +138,8 @@ def params_struct(p, **over):
                 band_cell=p.band_cell, band_halo=p.band_halo, mg_nu=p.mg_nu, mg_omega=p.mg_omega,
                 mg_bf16=p.mg_bf16, mg_nu_post=p.mg_nu_post, mg_smoother=p.mg_smoother,
                 band_sweeps=p.band_sweeps, band_omega=p.band_omega, mg_galerkin=p.mg_galerkin, nn_maxit=p.nn_maxit, band_reserve=p.band_reserve,
-                graphs=p.graphs, nn_base=p.nn_base, mg_lag=p.mg_lag)
+                graphs=p.graphs, nn_base=p.nn_base, mg_lag=p.mg_lag, mg_cnu=p.mg_cnu,
+                mg_cnu_post=p.mg_cnu_post)
     vals.update(over)
     P = Params()
     for k, v in vals.items():

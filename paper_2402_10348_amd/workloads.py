@@ -174,6 +174,8 @@ class Params:
     graphs: int = 1           # momentum Krylov columns captured into HIP graphs and replayed
     nn_base: int = 0          # learned preconditioner corrects: 0 point-block Jacobi, 1 the multigrid V-cycle
     mg_lag: int = 0           # 1: coarse multigrid levels refreshed once per time step (first nonlinear iteration)
+    mg_cnu: int = 0           # coarse multigrid levels' sweeps before / after the correction (0: as the finest)
+    mg_cnu_post: int = 0
 
 
 @dataclass

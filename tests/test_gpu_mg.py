@@ -3,8 +3,9 @@ coarse level equals P^T A P of the level above, computed here with scipy from
 the exported fine operator and the interpolation of the nested Kuhn meshes
 (weights 1 and 1/2, masked on the Dirichlet dofs of both levels; unit rows
 for the coarse level's Dirichlet dofs), up to the FP32 storage of the
-intermediate levels; and FGMRES preconditioned with it reaches the solution
-of the same system as point-block Jacobi."""
+intermediate levels; and FGMRES preconditioned with it (also with more
+smoothing sweeps on the coarse levels) reaches the solution of the same
+system as point-block Jacobi."""
 import sys
 
 import numpy as np
@@ -119,7 +120,8 @@ def test_galerkin_multigrid_same_solution(name):
     lvl, it = W.perturbed_state(prob, seed=10)
     sols = {}
     for tag, over in (("bj", dict(precond=0)), ("mg", dict(precond=1, mg_galerkin=0)),
-                      ("galerkin", dict(precond=1, mg_galerkin=1))):
+                      ("galerkin", dict(precond=1, mg_galerkin=1)),
+                      ("galerkin_coarse8", dict(precond=1, mg_galerkin=1, mg_cnu=8, mg_cnu_post=8))):
         ctx = Context(prob, lin_rtol=1e-12, restart=200, lin_maxit=40000, **over)
         R = ctx.assemble(ctx.device_state(lvl), ctx.device_state(it))
         x, info = ctx.fgmres(-R)
@@ -128,10 +130,12 @@ def test_galerkin_multigrid_same_solution(name):
         sols[tag] = (to_np(x), info["iters"])
         ctx.close()
     ref = sols["bj"][0]
-    for tag in ("mg", "galerkin"):
+    for tag in ("mg", "galerkin", "galerkin_coarse8"):
         e = np.linalg.norm(sols[tag][0] - ref) / np.linalg.norm(ref)
         assert e < 1e-8, (tag, e)
     assert sols["galerkin"][1] < sols["bj"][1]
+    # more smoothing on the coarse levels strengthens the coarse correction
+    assert sols["galerkin_coarse8"][1] <= sols["galerkin"][1]
 
 
 def test_lagged_coarse_levels_reach_the_same_step():
