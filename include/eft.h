@@ -422,7 +422,9 @@ eft_status eft_step(eft_ctx *ctx, eft_state *st, double dt, eft_step_info *info)
  * (rediscretized or Galerkin), and the sweeps and
  * damping of the band systems' preconditioner are chosen by measurement: on
  * the state st (as the first nonlinear iteration of a step sees it) the
- * momentum/mass system is assembled once and solved once per candidate, and
+ * momentum/mass system is assembled once and solved once per candidate (a
+ * candidate's solve stops at three times the best one's iterations, the entry
+ * settings' at 400; one that does not converge there is not chosen), and
  * one transport pass is timed per band candidate (on copies of phi and B; st
  * is not changed).  None of these knobs changes the converged answer; the
  * definition parameters (band_cell, band_halo, band_flat, eps, eta, dt,
@@ -431,7 +433,7 @@ eft_status eft_step(eft_ctx *ctx, eft_state *st, double dt, eft_step_info *info)
  * "key|knobs" lines, the key made of the GPU architecture and the problem's
  * sizes, materials and solver settings; a key found there is applied without
  * a search, a new result is appended.  budget: most momentum candidates
- * timed (<= 0: 80).  info (HOST, may be NULL) receives the outcome. */
+ * timed (<= 0: 96).  info (HOST, may be NULL) receives the outcome. */
 typedef struct {
     int32_t evaluated;           /* solves and transport passes timed              */
     int32_t from_cache;          /* 1: knobs read from the cache file              */

@@ -158,7 +158,7 @@ extern "C" eft_status eft_tune(eft_ctx *ctx, const eft_state *st, const char *ca
         if (info) *info = inf;
         return EFT_OK;
     }
-    const int cap = budget > 0 ? budget : 80;
+    const int cap = budget > 0 ? budget : 96;
     const int64_t N = ctx->N;
     const int bs = ctx->bs, nv = ctx->nv;
     const int64_t nvp = N * bs, nphi = N * ctx->n_ind, nB = N * nv * ctx->n_s;
@@ -199,6 +199,10 @@ extern "C" eft_status eft_tune(eft_ctx *ctx, const eft_state *st, const char *ca
     hipLaunchKernelGGL(k_negate_copy, dim3(eft_grid(nvp, 256)), dim3(256), 0, ctx->stream, ctx->R, b, nvp);
     TUNE_TRY(hipStreamSynchronize(ctx->stream) == hipSuccess ? EFT_OK : EFT_EDEVICE);
     const int maxit0 = ctx->par.lin_maxit;
+    // the entry settings may be poor (or stall): their solves stop at a
+    // bounded count too, and a solve that does not converge there is no
+    // candidate
+    const int cap_entry = std::min(maxit0, 400);
     int evaluated = 0;
     // one timed momentum solve with the knobs k (iterations capped so that a
     // poor candidate cannot run for long); seconds, or a negative value when
@@ -226,12 +230,12 @@ extern "C" eft_status eft_tune(eft_ctx *ctx, const eft_state *st, const char *ca
     int it_entry = 0, it_best = 0;
     if (eft_mg_active(ctx, &ctx->J)) {
         int itw = 0;
-        (void)time_solve(entry, maxit0, &itw);   // warm-up (first use of the kernels)
+        (void)time_solve(entry, cap_entry, &itw);   // warm-up (first use of the kernels)
         if (stt != EFT_OK) return fail(stt);
-        t_entry = time_solve(entry, maxit0, &it_entry);
+        t_entry = time_solve(entry, cap_entry, &it_entry);
         if (stt != EFT_OK) return fail(stt);
         t_best = t_entry > 0.0 ? t_entry : 1e300;
-        it_best = it_entry;
+        it_best = t_entry > 0.0 ? it_entry : 100;
         auto consider = [&](Knobs k) -> eft_status {
             if (evaluated >= cap) return EFT_OK;
             int its = 0;
@@ -244,8 +248,11 @@ extern "C" eft_status eft_tune(eft_ctx *ctx, const eft_state *st, const char *ca
             }
             return EFT_OK;
         };
-        const int pre[] = {1, 2, 4, 6, 8};
-        const int post[] = {2, 4, 8, 12, 16};
+        // (pre, post) sweep pairs of the grid, each at two dampings: the best
+        // pairs move with the damping, so neither is fixed first
+        const int pairs[][2] = {{1, 2}, {1, 3}, {1, 4}, {2, 2}, {2, 3}, {2, 4}, {3, 3}, {3, 4},
+                                {4, 4}, {4, 6}, {4, 8}, {6, 6}, {8, 8}, {2, 8}, {1, 8}};
+        const double omegas[] = {0.75, 0.85};
         // both kinds of coarse operators; switching rebuilds the hierarchy
         // (the assembly's set-up of the multigrid levels) before the timings
         const int gal0 = entry.mg_galerkin;
@@ -256,14 +263,14 @@ extern "C" eft_status eft_tune(eft_ctx *ctx, const eft_state *st, const char *ca
                 TUNE_TRY(eft_ns_kernels(ctx, &it, ctx->R, &ctx->J));
                 TUNE_TRY(hipStreamSynchronize(ctx->stream) == hipSuccess ? EFT_OK : EFT_EDEVICE);
             }
-            for (int a : pre)
-                for (int c : post) {
-                    if (c < a) continue;
+            for (double om : omegas)
+                for (const auto &pc : pairs) {
                     Knobs k = best;
                     k.mg_galerkin = gal;
                     k.mg_smoother = 0;
-                    k.mg_nu = a;
-                    k.mg_nu_post = c;
+                    k.mg_omega = om;
+                    k.mg_nu = pc[0];
+                    k.mg_nu_post = pc[1];
                     TUNE_TRY(consider(k));
                 }
         }
@@ -272,7 +279,7 @@ extern "C" eft_status eft_tune(eft_ctx *ctx, const eft_state *st, const char *ca
             ctx->par.mg_galerkin = best.mg_galerkin;
             TUNE_TRY(eft_ns_kernels(ctx, &it, ctx->R, &ctx->J));
         }
-        for (double om : {0.65, 0.85}) {
+        for (double om : {0.65, 0.95}) {
             Knobs k = best;
             k.mg_omega = om;
             TUNE_TRY(consider(k));
@@ -311,9 +318,9 @@ extern "C" eft_status eft_tune(eft_ctx *ctx, const eft_state *st, const char *ca
               best.mg_galerkin == entry.mg_galerkin && best.mg_cnu == entry.mg_cnu &&
               best.mg_cnu_post == entry.mg_cnu_post)) {
             int i1 = 0, i2 = 0;
-            const double t1 = time_solve(best, maxit0, &i1);
+            const double t1 = time_solve(best, cap_entry, &i1);
             double t2 = t_entry;
-            if (entry.mg_galerkin == best.mg_galerkin) t2 = time_solve(entry, maxit0, &i2);
+            if (entry.mg_galerkin == best.mg_galerkin) t2 = time_solve(entry, cap_entry, &i2);
             else i2 = it_entry;
             if (stt != EFT_OK) return fail(stt);
             if (!(t1 > 0.0) || (t2 > 0.0 && t2 <= t1)) {
