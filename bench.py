@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--mg-nu-post", type=int, default=3, help="multigrid post-smoothing sweeps")
     ap.add_argument("--mg-smoother", type=int, default=0, help="0 damped block Jacobi, 1 multicolour block Gauss-Seidel")
     ap.add_argument("--mg-omega", type=float, default=0.85,
-                    help="multigrid damping (the tuner's sweep grid runs at it before trying 0.65 and 0.85)")
+                    help="multigrid damping before tuning (the tuner searches 0.65-0.95)")
     ap.add_argument("--mg-bf16", type=int, default=1, help="1: finest multigrid level's matrix copy in BF16, 0: FP32")
     ap.add_argument("--band-sweeps", type=int, default=None,
                     help="damped block-Jacobi sweeps preconditioning the Allen-Cahn and B systems")
