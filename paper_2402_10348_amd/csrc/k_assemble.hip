@@ -259,6 +259,29 @@ __device__ __forceinline__ void elastic_pair(const RowArgs &a, const int (&nd)[D
     }
 }
 
+// 1/x and 1/sqrt(x) for x > 0 from the hardware approximations refined by two
+// Newton steps each (each step roughly doubles the correct bits: from the
+// approximation's about 22 to beyond double precision), instead of the
+// correctly rounded division and square root sequences: the results differ
+// from those by an ulp or two
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-0.5 * x * y, y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-0.5 * x * y, y, 0.5);
+    return fma(y, e, y);
+}
+
 template <int D, typename TJ, bool ST>
 __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ Jv)
 {
@@ -462,7 +485,7 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
         for (int i = 0; i < D; ++i) divv += L[i][i];
         const double(&da)[D] = dN[0];   // grad N of the row node
         const double w = vol * Rule<D>::WF;
-        const double inv4dt2 = 4.0 / (a.dt * a.dt), rtrG = 1.0 / trG;
+        const double inv4dt2 = 4.0 / (a.dt * a.dt), rtrG = rcp_nr(trG);
         constexpr double QA = Rule<D>::QA, QB = Rule<D>::QB, QD = QA - QB;
         // Quadrature sums.  Element-level (the same for every row):
         //   P = int p, MU = int mu, Tc = int tau_c rho, Tp = int tau_m / rho,
@@ -524,9 +547,9 @@ __global__ __launch_bounds__(256, 2) void k_ns_rows(RowArgs a, TJ *__restrict__ 
                 body[i] = aq[i] + s - gv[i];
                 Rm[i] = rq * body[i] + gp[i];
             }
-            const double ri = 1.0 / rq, nu = mq * ri;
-            const double sq = sqrt(inv4dt2 + vGv + a.C_I * nu * nu * GG);
-            const double tau_m = 1.0 / sq, tau_c = sq * rtrG, TMq = w * tau_m;
+            const double ri = rcp_nr(rq), nu = mq * ri;
+            const double Xq = inv4dt2 + vGv + a.C_I * nu * nu * GG;
+            const double tau_m = rsqrt_nr(Xq), sq = Xq * tau_m, tau_c = sq * rtrG, TMq = w * tau_m;
             P += w * pq;
             MU += w * mq;
             Tc += w * tau_c * rq;
