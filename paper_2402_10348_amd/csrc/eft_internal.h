@@ -404,7 +404,6 @@ eft_status eft_krylov_reserve(eft_ctx *ctx, int64_t n, int bs, int m);
 eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, double *x, eft_solve_info *info,
                           double rtol = 0.0);   // rtol <= 0: par.lin_rtol
 eft_status eft_norm2(eft_ctx *ctx, const double *x, int64_t n, double *out_host);
-eft_status eft_dot_dev(eft_ctx *ctx, const double *x, const double *y, int64_t n, double *out_dev);
 // looks up (once per device) the address of the fixed workspace array on the
 // current device and records it in the context
 eft_status eft_scratch_attach(eft_ctx *ctx);

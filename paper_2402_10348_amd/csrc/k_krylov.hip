@@ -403,16 +403,6 @@ __global__ __launch_bounds__(RB) void k_norm_part(const double *__restrict__ x, 
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
-__global__ __launch_bounds__(RB) void k_dot_part(const double *__restrict__ x, const double *__restrict__ y,
-                                                 int64_t nd, double *part, int nblk)
-{
-    __shared__ double lds[RB / 64];
-    double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < nd; i += (int64_t)nblk * RB) acc += x[i] * y[i];
-    acc = block_sum<RB>(acc, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = acc;
-}
-
 int nblk_for(int64_t nd) { return (int)std::max<int64_t>(1, std::min<int64_t>(MAXBLK, (nd + RB - 1) / RB)); }
 int stream_grid(int64_t nd) { return (int)std::max<int64_t>(1, std::min<int64_t>(8192, (nd + RB - 1) / RB)); }
 
@@ -483,16 +473,6 @@ eft_status eft_norm2(eft_ctx *ctx, const double *x, int64_t n, double *out_host)
     double s;
     EFT_TRY(sum_to_host(ctx, ctx->red, nblk, 1, &s));
     *out_host = sqrt(s);
-    return EFT_OK;
-}
-
-eft_status eft_dot_dev(eft_ctx *ctx, const double *x, const double *y, int64_t n, double *out_dev)
-{
-    const int nblk = nblk_for(n);
-    hipLaunchKernelGGL(k_dot_part, dim3(nblk), dim3(RB), 0, ctx->stream, x, y, n, ctx->red, nblk);
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(RB), 0, ctx->stream, ctx->red, nblk, out_dev,
-                       (const int32_t *)nullptr, 0);
-    EFT_HIP(hipGetLastError());
     return EFT_OK;
 }
 

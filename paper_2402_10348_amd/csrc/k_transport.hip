@@ -1130,17 +1130,6 @@ __global__ __launch_bounds__(256) void k_negate(double *x, int64_t n)
     if (i < n) x[i] = -x[i];
 }
 
-// x[node[r]*bs + c] += dx[r*bs + c]
-__global__ __launch_bounds__(256) void k_band_update(int64_t n, int bs, const int32_t *node, const double *dx,
-                                                     double *x)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * bs) return;
-    const int64_t r = t / bs;
-    const int c = (int)(t - r * bs);
-    x[(int64_t)node[r] * bs + c] += dx[t];
-}
-
 // member system of a block-diagonal union: rows shifted by roff, blocks by noff
 __global__ __launch_bounds__(256) void k_union_fill(int64_t n, int64_t nnz, const int32_t *rowptr,
                                                     const int32_t *col, const int32_t *diag, int64_t roff,
@@ -1156,7 +1145,6 @@ __global__ __launch_bounds__(256) void k_union_fill(int64_t n, int64_t nnz, cons
 
 __global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
 
-// v *= 1/sqrt(*nrm2) (unscale: v *= sqrt(*nrm2)); factor 1 when *nrm2 = 0
 // Largest |v|^2 over the band nodes (all bands): per-thread maxima, a
 // wavefront maximum, one atomic maximum per wavefront on the bit pattern
 // (non-negative doubles order like their bits).  *out must start at 0.
@@ -1174,14 +1162,88 @@ __global__ __launch_bounds__(256) void k_band_vmax(int64_t n, const int32_t *nod
     if ((threadIdx.x & 63) == 0 && m > 0.0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
 }
 
-__global__ __launch_bounds__(256) void k_scale_member(int64_t n, double *v, const double *nrm2, int unscale)
+// Batched per-member work of a union solve (all members in one launch): a
+// member's segment is a pointer and a length; the launch's blocks are dealt
+// to the segments in order, chunk elements each (boff: first block of each
+// segment), so every reduction has a fixed partition and order.
+constexpr int SEG_MAX = EFT_MAX_IND;
+struct SegSet {
+    int nseg;
+    int64_t chunk;
+    double *ptr[SEG_MAX];
+    int64_t len[SEG_MAX];
+    int boff[SEG_MAX + 1];
+};
+
+// the block's segment (boff ascending; a wave-uniform search)
+__device__ __forceinline__ int seg_of_block(const SegSet &s, int b)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double s2 = *nrm2;
-    if (!(s2 > 0.0)) return;
-    v[i] = unscale ? v[i] * sqrt(s2) : v[i] / sqrt(s2);
+    int lo = 0, hi = s.nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s.boff[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
+
+// partial sums of squares of the segments, one per block
+__global__ __launch_bounds__(256) void k_seg_sumsq(SegSet s, double *part)
+{
+    __shared__ double lds[4];
+    const int b = blockIdx.x, q = seg_of_block(s, b);
+    const int64_t c0 = (int64_t)(b - s.boff[q]) * s.chunk, c1 = min(c0 + s.chunk, s.len[q]);
+    const double *p = s.ptr[q];
+    double acc = 0.0;
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) acc += p[i] * p[i];
+    acc = block_sum<256>(acc, lds);
+    if (threadIdx.x == 0) part[b] = acc;
+}
+
+// out[q] = the sum of segment q's partials in block order (0 for an empty one)
+__global__ __launch_bounds__(256) void k_seg_total(const double *part, SegSet s, double *out)
+{
+    __shared__ double lds[4];
+    const int q = blockIdx.x;
+    double acc = 0.0;
+    for (int b = s.boff[q] + threadIdx.x; b < s.boff[q + 1]; b += blockDim.x) acc += part[b];
+    acc = block_sum<256>(acc, lds);
+    if (threadIdx.x == 0) out[q] = acc;
+}
+
+// v *= 1/sqrt(nrm2[q]) (unscale: v *= sqrt(nrm2[q])) on every segment; factor
+// 1 when nrm2[q] = 0
+__global__ __launch_bounds__(256) void k_seg_scale(SegSet s, const double *nrm2, int unscale)
+{
+    const int b = blockIdx.x, q = seg_of_block(s, b);
+    const double s2 = nrm2[q];
+    if (!(s2 > 0.0)) return;
+    const double sq = sqrt(s2);
+    const int64_t c0 = (int64_t)(b - s.boff[q]) * s.chunk, c1 = min(c0 + s.chunk, s.len[q]);
+    double *p = s.ptr[q];
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) p[i] = unscale ? p[i] * sq : p[i] / sq;
+}
+
+// x_q[node_q[r] * bs + c] += dx_q[r * bs + c] on every member (segments of dx
+// in rows * bs elements)
+struct UpdSet {
+    const int32_t *node[SEG_MAX];
+    double *x[SEG_MAX];
+};
+__global__ __launch_bounds__(256) void k_seg_band_update(SegSet s, UpdSet u, int bs)
+{
+    const int b = blockIdx.x, q = seg_of_block(s, b);
+    const int64_t c0 = (int64_t)(b - s.boff[q]) * s.chunk, c1 = min(c0 + s.chunk, s.len[q]);
+    const double *dx = s.ptr[q];
+    const int32_t *node = u.node[q];
+    double *x = u.x[q];
+    for (int64_t t = c0 + threadIdx.x; t < c1; t += blockDim.x) {
+        const int64_t r = t / bs;
+        const int c = (int)(t - r * bs);
+        x[(int64_t)node[r] * bs + c] += dx[t];
+    }
+}
+
 
 }  // namespace
 
@@ -1760,6 +1822,35 @@ static eft_status assemble_all(eft_ctx *ctx, const eft_state *lvl, const eft_ite
     return EFT_OK;
 }
 
+// A segment set over the given pointers and lengths, its chunk chosen so that
+// the blocks fit the reduction buffer (at least 16 blocks of 256 per chunk)
+static SegSet seg_set(eft_ctx *ctx, const std::vector<double *> &ptr, const std::vector<int64_t> &len)
+{
+    SegSet s{};
+    s.nseg = (int)ptr.size();
+    int64_t total = 0;
+    for (int64_t l : len) total += l;
+    int64_t chunk = 4096;
+    while ((total + chunk - 1) / chunk + s.nseg > (int64_t)ctx->nred) chunk *= 2;
+    s.chunk = chunk;
+    s.boff[0] = 0;
+    for (int q = 0; q < s.nseg; ++q) {
+        s.ptr[q] = ptr[q];
+        s.len[q] = len[q];
+        s.boff[q + 1] = s.boff[q] + (int)((len[q] + chunk - 1) / chunk);
+    }
+    return s;
+}
+
+// out[q] = ||segment q||^2 for every segment: two launches
+static void seg_sumsq(eft_ctx *ctx, const SegSet &s, double *out)
+{
+    if (s.nseg == 0) return;
+    const int nb = s.boff[s.nseg];
+    if (nb > 0) hipLaunchKernelGGL(k_seg_sumsq, dim3(nb), dim3(256), 0, ctx->stream, s, ctx->red);
+    hipLaunchKernelGGL(k_seg_total, dim3(s.nseg), dim3(256), 0, ctx->stream, ctx->red, s, out);
+}
+
 // Solve the assembled union system (R in bR, matrix in bval) of one kind:
 // rhs = -R; with several members, member k's right-hand side is divided by
 // ||R_k|| (its solution multiplied back afterwards), which weights the
@@ -1776,15 +1867,24 @@ static eft_status union_solve(eft_ctx *ctx, const eft_ctx::BandUnion &U, int bs,
     int members = 0;
     for (int q = 0; q < Q; ++q) members += ctx->band[U.band_of[q]].n > 0 ? 1 : 0;
     const bool scaled = members > 1;
-    if (scaled)
-        for (int q = 0; q < Q; ++q) {
-            const Band &B = ctx->band[U.band_of[q]];
-            if (B.n == 0) continue;
-            double *Rq = ctx->bR + U.roff[q] * bs;
-            EFT_TRY(eft_dot_dev(ctx, Rq, Rq, B.n * bs, ctx->tsc + TS_NRM + q));
-            hipLaunchKernelGGL(k_scale_member, dim3(eft_grid(B.n * bs, 256)), dim3(256), 0, ctx->stream, B.n * bs, Rq,
-                               ctx->tsc + TS_NRM + q, 0);
-        }
+    if (Q > SEG_MAX) {
+        ctx->err = "too many members in a union system";
+        return EFT_EINVAL;
+    }
+    // the members' segments of the union vectors (R, then dx), and the fields
+    std::vector<double *> rptr(Q), dptr(Q);
+    std::vector<int64_t> rlen(Q);
+    for (int q = 0; q < Q; ++q) {
+        rptr[q] = ctx->bR + U.roff[q] * bs;
+        dptr[q] = ctx->bX + U.roff[q] * bs;
+        rlen[q] = ctx->band[U.band_of[q]].n * bs;
+    }
+    const SegSet sR = seg_set(ctx, rptr, rlen), sX = seg_set(ctx, dptr, rlen);
+    if (scaled) {   // all members at once: their squared norms, then the scaling
+        seg_sumsq(ctx, sR, ctx->tsc + TS_NRM);
+        if (sR.boff[Q] > 0)
+            hipLaunchKernelGGL(k_seg_scale, dim3(sR.boff[Q]), dim3(256), 0, ctx->stream, sR, ctx->tsc + TS_NRM, 0);
+    }
     EFT_HIP(hipGetLastError());
     eft_matrix A;
     A.bs = bs;
@@ -1803,20 +1903,20 @@ static eft_status union_solve(eft_ctx *ctx, const eft_ctx::BandUnion &U, int bs,
     const double rtol = ctx->par.lin_rtol / std::sqrt((double)std::max(members, 1));
     eft_status st = eft_fgmres_dev(ctx, &A, ctx->bR, ctx->bX, si, rtol);
     if (st != EFT_OK && st != EFT_ENOTCONV) return st;
-    for (int q = 0; q < Q; ++q) {
-        const Band &B = ctx->band[U.band_of[q]];
-        EFT_TRY(eft_fill(ctx, ctx->tsc + TS_DN + q, 1, 0.0));
-        if (B.n > 0) {
-            double *dx = ctx->bX + U.roff[q] * bs;
-            if (scaled)
-                hipLaunchKernelGGL(k_scale_member, dim3(eft_grid(B.n * bs, 256)), dim3(256), 0, ctx->stream, B.n * bs,
-                                   dx, ctx->tsc + TS_NRM + q, 1);
-            hipLaunchKernelGGL(k_band_update, dim3(eft_grid(B.n * bs, 256)), dim3(256), 0, ctx->stream, B.n, bs,
-                               B.node, dx, x[q]);
-            EFT_TRY(eft_dot_dev(ctx, dx, dx, B.n * bs, ctx->tsc + TS_DN + q));
+    // all members at once: unscale dx, x_q += dx_q on the band nodes, then
+    // ||dx_q||^2 and ||x_q||^2
+    if (sX.boff[Q] > 0) {
+        if (scaled)
+            hipLaunchKernelGGL(k_seg_scale, dim3(sX.boff[Q]), dim3(256), 0, ctx->stream, sX, ctx->tsc + TS_NRM, 1);
+        UpdSet u{};
+        for (int q = 0; q < Q; ++q) {
+            u.node[q] = ctx->band[U.band_of[q]].node;
+            u.x[q] = x[q];
         }
-        EFT_TRY(eft_dot_dev(ctx, x[q], x[q], xlen[q], ctx->tsc + TS_XN + q));
+        hipLaunchKernelGGL(k_seg_band_update, dim3(sX.boff[Q]), dim3(256), 0, ctx->stream, sX, u, bs);
     }
+    seg_sumsq(ctx, sX, ctx->tsc + TS_DN);
+    seg_sumsq(ctx, seg_set(ctx, std::vector<double *>(x.begin(), x.end()), xlen), ctx->tsc + TS_XN);
     EFT_HIP(hipGetLastError());
     EFT_HIP(hipMemcpyAsync(ctx->htsc + TS_DN, ctx->tsc + TS_DN, sizeof(double) * 256, hipMemcpyDeviceToHost,
                            ctx->stream));
