@@ -32,6 +32,11 @@ struct eft_matrix {
     // stn_off[s] for the set bits s of stn_mask[r] (ascending), see eft_stencil_form
     uint16_t *stn_mask = nullptr;
     int32_t *stn_off = nullptr;
+    // band systems: FP32 copies for the Jacobi preconditioner (values or
+    // compact blocks, block inverses), written by the solve's set-up; null:
+    // the preconditioner reads the FP64 arrays
+    float *pc32 = nullptr;
+    float *dinv32 = nullptr;
     bool fp32 = false;
     bool bf16 = false;
 };
@@ -263,6 +268,8 @@ struct eft_ctx {
     double *bval = nullptr;                      // band matrix values [cap_nnz][nv*nv]
     double *bcmp = nullptr;                      // B blocks in compact form [cap_nnz][1 + dim^2]
     double *bdiag = nullptr;                     // B systems: diagonal blocks [cap_n][nv^2] by union row
+    float *bpc32 = nullptr;                      // FP32 copy of bval / bcmp for the Jacobi preconditioner
+    float *bdinv32 = nullptr;                    // FP32 block inverses of the band system [cap_n][nv^2]
     void *hmem = nullptr, *dmem = nullptr;       // member descriptors and unit tables of the batched
                                                  // transport launches (pinned host, device)
     double *tpart = nullptr;                     // partial sums of the batched mobility / beta
@@ -384,7 +391,13 @@ eft_status eft_spmv_dev(eft_ctx *ctx, const eft_matrix *A, const double *x, doub
 // (sing: optional device flag set to 1 when a diagonal block is singular; its
 // inverse is then replaced by the identity)
 eft_status eft_bj_setup(eft_ctx *ctx, const eft_matrix *A, double *Dinv, int32_t *sing = nullptr);
-eft_status eft_bj_setup32(eft_ctx *ctx, const eft_matrix *A, float *Dinv);
+eft_status eft_bj_setup32(eft_ctx *ctx, const eft_matrix *A, float *Dinv, int32_t *sing = nullptr);
+// the Jacobi preconditioner of a band system reads its FP32 copies (values
+// or compact blocks in pc32, block inverses in dinv32)
+inline bool eft_jacobi_narrow(const eft_matrix *A)
+{
+    return A->pc32 && A->dinv32 && (A->bs == 1 || A->bcmp);
+}
 eft_status eft_bj_apply(eft_ctx *ctx, int bs, int64_t n, const double *Dinv, const double *x, double *z,
                         const int32_t *active);
 // z = M v with M = `sweeps` damped point-block Jacobi sweeps from z = 0

@@ -592,7 +592,10 @@ eft_status eft_fgmres_dev(eft_ctx *ctx, const eft_matrix *A, const double *b, do
     // block ILU(0) on the momentum system (point-block Jacobi elsewhere)
     const bool ilu = ctx->par.precond == 3 && A == &ctx->J;
     if (ilu) EFT_TRY(eft_ilu_setup(ctx, A, K.flag + 6));
-    if ((!mg && !ilu) || (harvest && ctx->par.nn_base == 0)) EFT_TRY(eft_bj_setup(ctx, A, K.Dinv, K.flag + 6));
+    if (eft_jacobi_narrow(A))
+        EFT_TRY(eft_bj_setup32(ctx, A, A->dinv32, K.flag + 6));
+    else if ((!mg && !ilu) || (harvest && ctx->par.nn_base == 0))
+        EFT_TRY(eft_bj_setup(ctx, A, K.Dinv, K.flag + 6));
     const double tol = (rtol > 0.0 ? rtol : ctx->par.lin_rtol) * bnorm;
     int chunk = 8;   // columns enqueued between two reads of the solver state
     int total = 0;

@@ -347,7 +347,8 @@ __global__ __launch_bounds__(256) void k_bj_setup_t(int64_t n, const int32_t *__
     if (!ok && sing) *sing = 1;
 }
 
-__global__ __launch_bounds__(256) void k_bj_apply(int64_t nd, int bs, const double *__restrict__ Dinv, double omega,
+template <typename TD>
+__global__ __launch_bounds__(256) void k_bj_apply(int64_t nd, int bs, const TD *__restrict__ Dinv, double omega,
                                                   const double *__restrict__ x, double *__restrict__ z,
                                                   const int32_t *active)
 {
@@ -356,18 +357,20 @@ __global__ __launch_bounds__(256) void k_bj_apply(int64_t nd, int bs, const doub
     if (t >= nd) return;
     const int64_t r = t / bs;
     const int i = (int)(t - r * bs);
-    const double *D = Dinv + r * bs * bs + i * bs;
+    const TD *D = Dinv + r * bs * bs + i * bs;
     const double *xr = x + r * bs;
     double s = 0.0;
-    for (int c = 0; c < bs; ++c) s += D[c] * xr[c];
+    for (int c = 0; c < bs; ++c) s += (double)D[c] * xr[c];
     z[t] = omega * s;
 }
 
-// One damped point-block Jacobi sweep zo = z + omega D^-1 (v - A z) (FP64).
+// One damped point-block Jacobi sweep zo = z + omega D^-1 (v - A z), the
+// arithmetic and vectors FP64, values and inverses FP64 or FP32 copies.
 // bs = 1: 16 lanes per row as the scalar product.
+template <typename TV>
 __global__ __launch_bounds__(256) void k_jsweep1(int64_t n, const int32_t *__restrict__ rowptr,
-                                                 const int32_t *__restrict__ col, const double *__restrict__ val,
-                                                 const double *__restrict__ Dinv, double omega,
+                                                 const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                 const TV *__restrict__ Dinv, double omega,
                                                  const double *__restrict__ v, const double *__restrict__ z,
                                                  double *__restrict__ zo, const int32_t *active)
 {
@@ -377,13 +380,13 @@ __global__ __launch_bounds__(256) void k_jsweep1(int64_t n, const int32_t *__res
     double acc = 0.0;
     if (row < n) {
         const int k0 = rowptr[row], k1 = rowptr[row + 1];
-        for (int k = k0 + sub; k < k1; k += 16) acc += val[k] * z[col[k]];
+        for (int k = k0 + sub; k < k1; k += 16) acc += (double)val[k] * z[col[k]];
     }
     acc += __shfl_xor(acc, 1, 16);
     acc += __shfl_xor(acc, 2, 16);
     acc += __shfl_xor(acc, 4, 16);
     acc += __shfl_xor(acc, 8, 16);
-    if (row < n && sub == 0) zo[row] = z[row] + omega * Dinv[row] * (v[row] - acc);
+    if (row < n && sub == 0) zo[row] = z[row] + omega * (double)Dinv[row] * (v[row] - acc);
 }
 
 // bs in {3, 6}: SPMV_R block rows per wavefront (bsr_rows.h), lanes 0..bs-1
@@ -468,9 +471,9 @@ __device__ __forceinline__ void bcmp_block_apply(const double (&cm)[BCmp<D>::NC]
 
 // (A z) of the segment's block row, one compact block per lane, reduced
 // over the segment (every lane of it holds the row's sums)
-template <int D, int SEG>
+template <int D, int SEG, typename TC = double>
 __device__ __forceinline__ void bcmp_row_dot(int k0, int k1, const int32_t *__restrict__ col,
-                                             const double *__restrict__ cmp, const double *__restrict__ z, int j,
+                                             const TC *__restrict__ cmp, const double *__restrict__ z, int j,
                                              double (&acc)[BCmp<D>::NV])
 {
     constexpr int NV = BCmp<D>::NV, NC = BCmp<D>::NC;
@@ -478,7 +481,7 @@ __device__ __forceinline__ void bcmp_row_dot(int k0, int k1, const int32_t *__re
     for (int c = 0; c < NV; ++c) acc[c] = 0.0;
     for (int k = k0 + j; k < k1; k += SEG) {
         double cm[NC], xv[NV];
-        RowLoad<NC, double, false>::get(cmp + (int64_t)k * NC, cm);
+        RowLoad<NC, TC, false>::get(cmp + (int64_t)k * NC, cm);
         x_get<NV>(z, col[k], xv);
         bcmp_block_apply<D>(cm, xv, acc);
     }
@@ -509,11 +512,12 @@ __global__ __launch_bounds__(256) void k_spmv_bcmp(int64_t n, const int32_t *__r
 }
 
 // damped block-Jacobi sweep zo = z + omega D^-1 (v - A z), lane j < NV of a
-// row's segment finishes component j
-template <int D>
+// row's segment finishes component j (compact blocks and inverses FP64 or
+// FP32 copies, the arithmetic FP64)
+template <int D, typename TC>
 __global__ __launch_bounds__(256) void k_jsweep_bcmp(int64_t n, const int32_t *__restrict__ rowptr,
-                                                     const int32_t *__restrict__ col, const double *__restrict__ cmp,
-                                                     const double *__restrict__ Dinv, double omega,
+                                                     const int32_t *__restrict__ col, const TC *__restrict__ cmp,
+                                                     const TC *__restrict__ Dinv, double omega,
                                                      const double *__restrict__ v, const double *__restrict__ z,
                                                      double *__restrict__ zo, const int32_t *active)
 {
@@ -525,12 +529,12 @@ __global__ __launch_bounds__(256) void k_jsweep_bcmp(int64_t n, const int32_t *_
     const int jj = j < NV ? j : 0;
     double vv[NV], d[NV];
     x_get<NV>(v, rr, vv);
-    RowLoad<NV, double, false>::get(Dinv + (rr * NV + jj) * NV, d);
+    RowLoad<NV, TC, false>::get(Dinv + (rr * NV + jj) * NV, d);
     const double zr = z[rr * NV + jj];
     int k0, k1;
     seg_extents<RPW>(row0, n, rowptr, q, k0, k1);
     double az[NV];
-    bcmp_row_dot<D, SEG>(k0, k1, col, cmp, z, j, az);
+    bcmp_row_dot<D, SEG, TC>(k0, k1, col, cmp, z, j, az);
     double u = 0.0;
 #pragma unroll
     for (int c = 0; c < NV; ++c) u += d[c] * (vv[c] - az[c]);
@@ -572,9 +576,9 @@ eft_status eft_bj_setup(eft_ctx *ctx, const eft_matrix *A, double *Dinv, int32_t
     return bj_setup<double>(ctx, A, Dinv, sing);
 }
 
-eft_status eft_bj_setup32(eft_ctx *ctx, const eft_matrix *A, float *Dinv)
+eft_status eft_bj_setup32(eft_ctx *ctx, const eft_matrix *A, float *Dinv, int32_t *sing)
 {
-    return bj_setup<float>(ctx, A, Dinv, nullptr);
+    return bj_setup<float>(ctx, A, Dinv, sing);
 }
 
 eft_status eft_bj_apply(eft_ctx *ctx, int bs, int64_t n, const double *Dinv, const double *x, double *z,
@@ -582,8 +586,8 @@ eft_status eft_bj_apply(eft_ctx *ctx, int bs, int64_t n, const double *Dinv, con
 {
     const int64_t nd = n * bs;
     if (nd == 0) return EFT_OK;
-    hipLaunchKernelGGL(k_bj_apply, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, nd, bs, Dinv, 1.0, x, z,
-                       active);
+    hipLaunchKernelGGL(k_bj_apply<double>, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, nd, bs, Dinv, 1.0, x,
+                       z, active);
     EFT_HIP(hipGetLastError());
     return EFT_OK;
 }
@@ -599,19 +603,28 @@ eft_status eft_jacobi_apply(eft_ctx *ctx, const eft_matrix *A, const double *Din
         ctx->err = "Jacobi sweeps need FP64 values and bs 1, 3 or 6";
         return EFT_EINVAL;
     }
+    // FP32 copies of the values (or compact blocks) and block inverses
+    const bool narrow = eft_jacobi_narrow(A);
     // sweep s writes z when (sweeps - 1 - s) is even, tmp otherwise, so the
     // last one ends in z
     double *buf[2] = {z, tmp};
     double *cur = buf[(sweeps - 1) & 1];
-    hipLaunchKernelGGL(k_bj_apply, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, nd, bs, Dinv, omega, v, cur,
-                       active);
+    if (narrow)
+        hipLaunchKernelGGL(k_bj_apply<float>, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, nd, bs, A->dinv32,
+                           omega, v, cur, active);
+    else
+        hipLaunchKernelGGL(k_bj_apply<double>, dim3(eft_grid(nd, 256)), dim3(256), 0, ctx->stream, nd, bs, Dinv,
+                           omega, v, cur, active);
     for (int s = 1; s < sweeps; ++s) {
         double *nxt = buf[(sweeps - 1 - s) & 1];
         if (A->bcmp)
             EFT_TRY(eft_bcmp_sweep(ctx, A, Dinv, omega, v, cur, nxt, active));
+        else if (bs == 1 && narrow)
+            hipLaunchKernelGGL(k_jsweep1<float>, dim3(eft_grid(n, 16)), dim3(256), 0, ctx->stream, n, A->rowptr,
+                               A->col, A->pc32, A->dinv32, omega, v, cur, nxt, active);
         else if (bs == 1)
-            hipLaunchKernelGGL(k_jsweep1, dim3(eft_grid(n, 16)), dim3(256), 0, ctx->stream, n, A->rowptr, A->col,
-                               A->val, Dinv, omega, v, cur, nxt, active);
+            hipLaunchKernelGGL(k_jsweep1<double>, dim3(eft_grid(n, 16)), dim3(256), 0, ctx->stream, n, A->rowptr,
+                               A->col, A->val, Dinv, omega, v, cur, nxt, active);
         else if (bs == 3)
             hipLaunchKernelGGL((k_jsweep_rows<3, double>), dim3(eft_grid(n, 4 * SPMV_R)), dim3(256), 0, ctx->stream,
                                n, A->rowptr, A->col, A->val, Dinv, omega, v, cur, nxt, active);
@@ -647,12 +660,21 @@ eft_status eft_bcmp_sweep(eft_ctx *ctx, const eft_matrix *A, const double *Dinv,
 {
     const int64_t n = A->n;
     if (n == 0) return EFT_OK;
-    if (A->bs == 6)
-        hipLaunchKernelGGL(k_jsweep_bcmp<3>, dim3(eft_grid(n, 4 * BlockSeg<6>::RPW)), dim3(256), 0, ctx->stream, n,
-                           A->rowptr, A->col, A->bcmp, Dinv, omega, v, z, zo, active);
+    const bool narrow = eft_jacobi_narrow(A);
+    auto go = [&](auto dc, auto tc, const auto *cmp, const auto *dinv) {
+        constexpr int D = decltype(dc)::value, NV = BCmp<D>::NV;
+        using TC = decltype(tc);
+        hipLaunchKernelGGL((k_jsweep_bcmp<D, TC>), dim3(eft_grid(n, 4 * BlockSeg<NV>::RPW)), dim3(256), 0,
+                           ctx->stream, n, A->rowptr, A->col, cmp, dinv, omega, v, z, zo, active);
+    };
+    if (A->bs == 6 && narrow)
+        go(std::integral_constant<int, 3>{}, 0.0f, A->pc32, A->dinv32);
+    else if (A->bs == 6)
+        go(std::integral_constant<int, 3>{}, 0.0, A->bcmp, Dinv);
+    else if (A->bs == 3 && narrow)
+        go(std::integral_constant<int, 2>{}, 0.0f, A->pc32, A->dinv32);
     else if (A->bs == 3)
-        hipLaunchKernelGGL(k_jsweep_bcmp<2>, dim3(eft_grid(n, 4 * BlockSeg<3>::RPW)), dim3(256), 0, ctx->stream, n,
-                           A->rowptr, A->col, A->bcmp, Dinv, omega, v, z, zo, active);
+        go(std::integral_constant<int, 2>{}, 0.0, A->bcmp, Dinv);
     else {
         ctx->err = "compact B blocks need bs 3 or 6";
         return EFT_EINVAL;

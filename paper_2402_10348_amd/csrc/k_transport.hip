@@ -1130,6 +1130,12 @@ __global__ __launch_bounds__(256) void k_negate(double *x, int64_t n)
     if (i < n) x[i] = -x[i];
 }
 
+__global__ __launch_bounds__(256) void k_narrow_copy(const double *__restrict__ a, float *__restrict__ b, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
 // member system of a block-diagonal union: rows shifted by roff, blocks by noff
 __global__ __launch_bounds__(256) void k_union_fill(int64_t n, int64_t nnz, const int32_t *rowptr,
                                                     const int32_t *col, const int32_t *diag, int64_t roff,
@@ -1335,7 +1341,7 @@ void eft_band_free(eft_ctx *ctx)
         U->rowptr = U->col = U->diag = nullptr;
         U->cap_n = U->cap_nnz = U->n = U->nnz = 0;
     }
-    fr(ctx->bR); fr(ctx->bX); fr(ctx->tnum); fr(ctx->tden); fr(ctx->bval); fr(ctx->bcmp); fr(ctx->bdiag); fr(ctx->iota);
+    fr(ctx->bR); fr(ctx->bX); fr(ctx->tnum); fr(ctx->tden); fr(ctx->bval); fr(ctx->bcmp); fr(ctx->bdiag); fr(ctx->bpc32); fr(ctx->bdinv32); fr(ctx->iota);
     fr(ctx->scan_tmp);
     fr(ctx->dmem);
     fr(ctx->tpart);
@@ -1344,6 +1350,7 @@ void eft_band_free(eft_ctx *ctx)
     ctx->tpart = nullptr;
     ctx->tpart_cap = 0;
     ctx->bR = ctx->bX = ctx->tnum = ctx->tden = ctx->bval = ctx->bcmp = ctx->bdiag = nullptr;
+    ctx->bpc32 = ctx->bdinv32 = nullptr;
     ctx->iota = nullptr;
     ctx->scan_tmp = nullptr;
     ctx->scan_cap = 0;
@@ -1397,6 +1404,8 @@ eft_status eft_band_reserve(eft_ctx *ctx)
     EFT_TRY(tmal(ctx, &ctx->bval, P.cap_nnz));   // Allen-Cahn values (1 x 1 blocks)
     EFT_TRY(tmal(ctx, &ctx->bcmp, P.cap_nnz * (1 + ctx->dim * ctx->dim)));
     EFT_TRY(tmal(ctx, &ctx->bdiag, P.cap_n * nv * nv));
+    EFT_TRY(tmal(ctx, &ctx->bpc32, P.cap_nnz * (1 + ctx->dim * ctx->dim)));
+    EFT_TRY(tmal(ctx, &ctx->bdinv32, P.cap_n * nv * nv));
     EFT_TRY(tmal(ctx, &ctx->iota, P.cap_n));
     const int64_t nb = (std::max(E, N) + TILE - 1) / TILE + 1;
     EFT_TRY(tmal(ctx, &ctx->scan_tmp, nb + 1));
@@ -1900,6 +1909,14 @@ static eft_status union_solve(eft_ctx *ctx, const eft_ctx::BandUnion &U, int bs,
         A.val = ctx->bdiag;
         A.diag = ctx->iota;
     }
+    // the Jacobi preconditioner reads FP32 copies (the products and the
+    // Krylov vectors stay FP64); the solve's set-up writes the inverses
+    const int64_t nc = U.nnz * (bs > 1 ? 1 + ctx->dim * ctx->dim : 1);
+    if (nc > 0)
+        hipLaunchKernelGGL(k_narrow_copy, dim3(eft_grid(nc, 256)), dim3(256), 0, ctx->stream,
+                           bs > 1 ? ctx->bcmp : ctx->bval, ctx->bpc32, nc);
+    A.pc32 = ctx->bpc32;
+    A.dinv32 = ctx->bdinv32;
     const double rtol = ctx->par.lin_rtol / std::sqrt((double)std::max(members, 1));
     eft_status st = eft_fgmres_dev(ctx, &A, ctx->bR, ctx->bX, si, rtol);
     if (st != EFT_OK && st != EFT_ENOTCONV) return st;
