@@ -130,7 +130,10 @@ typedef struct {
     int32_t band_sweeps;         /* preconditioner of the Allen-Cahn and B band
                                     systems: this many damped point-block Jacobi
                                     sweeps from z = 0 (1..8; 1 with band_omega = 1
-                                    is plain point-block Jacobi)                    */
+                                    is plain point-block Jacobi).  The sweeps read
+                                    FP32 copies of the values and block inverses
+                                    (FP64 vectors and arithmetic); the Krylov
+                                    products stay FP64                             */
     double band_omega;           /* damping of those sweeps (0 < omega <= 1.5)      */
     int32_t mg_galerkin;         /* multigrid coarse operators: 0 rediscretized (the
                                     element kernels on node fields injected from
